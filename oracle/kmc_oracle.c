@@ -1,0 +1,317 @@
+/*
+ * Plain CPU oracle for canonical k-mer counting (KMC 2, Deorowicz et al.).
+ *
+ * TEST INFRASTRUCTURE ONLY.  Nothing in the product path may include, link,
+ * load or call this file: only the test suite, the smoke check and the CPU
+ * baseline leg of the benchmark do.  It shares no code with the HIP path.
+ *
+ * What it computes (the plain definition the paper's method reaches exactly):
+ *   the set of pairs (K, c) where K ranges over the canonical k-mers of every
+ *   window of every read that holds only A/C/G/T, and c is the number of such
+ *   windows; a pair is kept iff cutoff_min <= c <= cutoff_max; pairs are
+ *   listed in ascending K.
+ *
+ * Paper passages followed:
+ *   - symbol code A->0 C->1 G->2 T->3, leftmost symbol most significant
+ *     (supplement, database [map] example and .kmc_suf packing example);
+ *   - canonical k-mer = the smaller of the k-mer and its reverse complement
+ *     (Methods, "Minimizers of k-mers");
+ *   - cutoffs: k-mers counted fewer than ci or more than cx times are not
+ *     written (supplement, -ci / -cx options and the min_count / max_count
+ *     header fields);
+ *   - signature of a k-mer = the smallest canonical m-mer that neither starts
+ *     with AAA nor with ACA and has no AA anywhere except at its beginning
+ *     (Methods, "From minimizers to signatures"); a k-mer with no such m-mer
+ *     takes the extra value 4^m (the database map has 4^m + 1 entries).
+ *
+ * Readings where the paper is silent: bytes other than A/C/G/T (either case)
+ * are invalid and exclude every window that holds one; palindromic k-mers
+ * count once per occurrence; counts are exact 32-bit values.
+ *
+ * Keys are held as unsigned __int128 so that one code path serves every k in
+ * [1, 64]; the result is returned in the library's table layout: key_words = 1
+ * (k <= 32) or 2 (hi word first, then lo word).
+ */
+#include <pthread.h>
+#include <stdint.h>
+#include <stdlib.h>
+#include <string.h>
+
+typedef unsigned __int128 u128;
+
+/* A/C/G/T in either case -> 0..3, anything else -> -1. */
+static int sym_code(uint8_t b) {
+  switch (b) {
+    case 'A': case 'a': return 0;
+    case 'C': case 'c': return 1;
+    case 'G': case 'g': return 2;
+    case 'T': case 't': return 3;
+    default: return -1;
+  }
+}
+
+/* Forward value F = sum_t code[t] * 4^(k-1-t) and reverse-complement value
+ * R = sum_t (3 - code[t]) * 4^t of the k symbols at s; returns min(F, R).
+ * The caller guarantees the k symbols are valid. */
+static u128 canonical_at(const uint8_t* s, uint32_t k) {
+  u128 f = 0, r = 0, pw = 1;
+  for (uint32_t t = 0; t < k; ++t) {
+    int c = sym_code(s[t]);
+    f = f * 4 + (u128)c;
+    r = r + (u128)(3 - c) * pw;
+    pw *= 4;
+  }
+  return f < r ? f : r;
+}
+
+/* ---------------------------------------------------------------- count -- */
+
+static int cmp_u128(const void* a, const void* b) {
+  u128 x = *(const u128*)a, y = *(const u128*)b;
+  return (x > y) - (x < y);
+}
+
+typedef struct {
+  u128* keys;      /* this partition's keys */
+  uint64_t n;
+  uint32_t ci, cx;
+  /* results: run-length counted, cutoff-filtered */
+  u128* out_keys;
+  uint32_t* out_counts;
+  uint64_t n_out;
+} part_t;
+
+static void* sort_and_count(void* arg) {
+  part_t* P = (part_t*)arg;
+  qsort(P->keys, P->n, sizeof(u128), cmp_u128);
+  P->out_keys = (u128*)malloc((P->n ? P->n : 1) * sizeof(u128));
+  P->out_counts = (uint32_t*)malloc((P->n ? P->n : 1) * sizeof(uint32_t));
+  uint64_t m = 0;
+  uint64_t i = 0;
+  while (i < P->n) {
+    uint64_t j = i + 1;
+    while (j < P->n && P->keys[j] == P->keys[i]) ++j;
+    uint64_t c = j - i;
+    if (c >= P->ci && c <= P->cx) {
+      P->out_keys[m] = P->keys[i];
+      P->out_counts[m] = (uint32_t)c;
+      ++m;
+    }
+    i = j;
+  }
+  P->n_out = m;
+  return NULL;
+}
+
+typedef struct { part_t* parts; int first, step, count; } job_t;
+
+static void* worker(void* arg) {
+  job_t* J = (job_t*)arg;
+  for (int q = J->first; q < J->count; q += J->step) sort_and_count(&J->parts[q]);
+  return NULL;
+}
+
+/* Number of valid windows: for every maximal run of valid bytes of length L
+ * inside one read, max(0, L - k + 1).  This is the closed form the full count
+ * must sum to when cutoff_min <= 1 and cutoff_max is unbounded. */
+uint64_t kmc_oracle_valid_windows(const uint8_t* seq, const uint64_t* offsets,
+                                  uint64_t n_reads, uint32_t k) {
+  uint64_t total = 0;
+  for (uint64_t r = 0; r < n_reads; ++r) {
+    uint64_t run = 0;
+    for (uint64_t x = offsets[r]; x < offsets[r + 1]; ++x) {
+      if (sym_code(seq[x]) >= 0) {
+        ++run;
+      } else {
+        if (run >= k) total += run - k + 1;
+        run = 0;
+      }
+    }
+    if (run >= k) total += run - k + 1;
+  }
+  return total;
+}
+
+/* Enumerate every canonical k-mer, sort, run-length count, apply cutoffs.
+ * n_threads > 1 partitions the keys by their top 8 bits (so partitions are
+ * key ranges in order) and sorts each partition on its own thread.
+ * Returns 0 on success, -1 on bad arguments, -2 on allocation failure.
+ * *out_keys and *out_counts are malloc'd; release them with kmc_oracle_free. */
+int kmc_oracle_count(const uint8_t* seq, const uint64_t* offsets, uint64_t n_reads,
+                     uint32_t k, uint32_t cutoff_min, uint32_t cutoff_max,
+                     int n_threads, uint64_t* out_n, uint64_t** out_keys,
+                     uint32_t** out_counts) {
+  if (k < 1 || k > 64 || !out_n || !out_keys || !out_counts) return -1;
+  if (cutoff_min > cutoff_max) return -1;
+  if (n_threads < 1) n_threads = 1;
+  uint32_t ci = cutoff_min == 0 ? 1 : cutoff_min;
+
+  uint64_t n_win = kmc_oracle_valid_windows(seq, offsets, n_reads, k);
+  u128* keys = (u128*)malloc((n_win ? n_win : 1) * sizeof(u128));
+  if (!keys) return -2;
+
+  /* Steps 1-2: every window whose k bytes are all valid -> canonical key. */
+  uint64_t n = 0;
+  for (uint64_t r = 0; r < n_reads; ++r) {
+    uint64_t b = offsets[r], e = offsets[r + 1];
+    if (e - b < k) continue;
+    for (uint64_t j = b; j + k <= e; ++j) {
+      int ok = 1;
+      for (uint32_t t = 0; t < k; ++t)
+        if (sym_code(seq[j + t]) < 0) { ok = 0; break; }
+      if (ok) keys[n++] = canonical_at(seq + j, k);
+    }
+  }
+
+  /* Step 3: partition by the top 8 bits of the 2k-bit key (one partition
+   * when single-threaded), then sort and count each partition. */
+  int n_parts = n_threads > 1 ? 256 : 1;
+  uint32_t shift = 2 * k > 8 ? 2 * k - 8 : 0;
+  uint64_t* cnt = (uint64_t*)calloc(n_parts + 1, sizeof(uint64_t));
+  part_t* parts = (part_t*)calloc(n_parts, sizeof(part_t));
+  u128* sorted = n_parts > 1 ? (u128*)malloc((n ? n : 1) * sizeof(u128)) : keys;
+  if (!cnt || !parts || !sorted) return -2;
+  if (n_parts > 1) {
+    for (uint64_t i = 0; i < n; ++i) cnt[(uint32_t)(keys[i] >> shift) + 1]++;
+    for (int q = 0; q < n_parts; ++q) cnt[q + 1] += cnt[q];
+    uint64_t* pos = (uint64_t*)malloc(n_parts * sizeof(uint64_t));
+    memcpy(pos, cnt, n_parts * sizeof(uint64_t));
+    for (uint64_t i = 0; i < n; ++i) sorted[pos[(uint32_t)(keys[i] >> shift)]++] = keys[i];
+    free(pos);
+    free(keys);
+  } else {
+    cnt[1] = n;
+  }
+  for (int q = 0; q < n_parts; ++q) {
+    parts[q].keys = sorted + cnt[q];
+    parts[q].n = cnt[q + 1] - cnt[q];
+    parts[q].ci = ci;
+    parts[q].cx = cutoff_max;
+  }
+  if (n_parts == 1) {
+    sort_and_count(&parts[0]);
+  } else {
+    /* static round-robin of partitions over threads */
+    pthread_t* th = (pthread_t*)malloc(n_threads * sizeof(pthread_t));
+    job_t* jobs = (job_t*)malloc(n_threads * sizeof(job_t));
+    for (int t = 0; t < n_threads; ++t) {
+      jobs[t].parts = parts; jobs[t].first = t; jobs[t].step = n_threads; jobs[t].count = n_parts;
+      pthread_create(&th[t], NULL, worker, &jobs[t]);
+    }
+    for (int t = 0; t < n_threads; ++t) pthread_join(th[t], NULL);
+    free(th);
+    free(jobs);
+  }
+
+  /* Step 4: concatenate the partitions in key order. */
+  uint64_t total = 0;
+  for (int q = 0; q < n_parts; ++q) total += parts[q].n_out;
+  uint32_t kw = k <= 32 ? 1 : 2;
+  uint64_t* ok_keys = (uint64_t*)malloc((total ? total : 1) * kw * sizeof(uint64_t));
+  uint32_t* ok_counts = (uint32_t*)malloc((total ? total : 1) * sizeof(uint32_t));
+  if (!ok_keys || !ok_counts) return -2;
+  uint64_t m = 0;
+  for (int q = 0; q < n_parts; ++q) {
+    for (uint64_t i = 0; i < parts[q].n_out; ++i, ++m) {
+      u128 K = parts[q].out_keys[i];
+      if (kw == 1) {
+        ok_keys[m] = (uint64_t)K;
+      } else {
+        ok_keys[2 * m] = (uint64_t)(K >> 64);
+        ok_keys[2 * m + 1] = (uint64_t)K;
+      }
+      ok_counts[m] = parts[q].out_counts[i];
+    }
+    free(parts[q].out_keys);
+    free(parts[q].out_counts);
+  }
+  free(sorted);
+  free(parts);
+  free(cnt);
+  *out_n = total;
+  *out_keys = ok_keys;
+  *out_counts = ok_counts;
+  return 0;
+}
+
+void kmc_oracle_free(void* p) { free(p); }
+
+/* ------------------------------------------------------------ signature -- */
+
+/* Is the canonical m-mer whose symbols are s[0..m-1] (leftmost first) allowed
+ * as a signature?  Not allowed: it starts with AAA, it starts with ACA, or it
+ * has AA at any offset other than 0 (Methods, "From minimizers to
+ * signatures").  filter == 0 allows every m-mer (plain canonical minimizers,
+ * Methods, "Minimizers of k-mers"). */
+static int mmer_allowed(const int* s, uint32_t m, int filter) {
+  if (!filter) return 1;
+  if (m >= 3 && s[0] == 0 && s[1] == 0 && s[2] == 0) return 0;
+  if (m >= 3 && s[0] == 0 && s[1] == 1 && s[2] == 0) return 0;
+  for (uint32_t i = 1; i + 1 < m; ++i)
+    if (s[i] == 0 && s[i + 1] == 0) return 0;
+  return 1;
+}
+
+/* Signature of the k-mer whose symbols are sym[0..k-1]: the minimum, over
+ * the k-m+1 positions, of the canonical m-mer there, among allowed ones;
+ * 4^m when no m-mer is allowed.  Plain O(k*m) per k-mer. */
+static uint32_t signature_of_symbols(const int* sym, uint32_t k, uint32_t m, int filter) {
+  uint32_t best = 1u << (2 * m); /* 4^m */
+  int can[32];
+  for (uint32_t i = 0; i + m <= k; ++i) {
+    uint32_t f = 0, r = 0, pw = 1;
+    for (uint32_t t = 0; t < m; ++t) {
+      f = f * 4 + (uint32_t)sym[i + t];
+      r = r + (uint32_t)(3 - sym[i + t]) * pw;
+      pw *= 4;
+    }
+    uint32_t c = f < r ? f : r;
+    for (uint32_t t = 0; t < m; ++t) can[t] = (int)((c >> (2 * (m - 1 - t))) & 3);
+    if (mmer_allowed(can, m, filter) && c < best) best = c;
+  }
+  return best;
+}
+
+/* Signature of each packed key (library table layout, key_words words per
+ * key).  Used to check on which bin the GPU path placed each k-mer.
+ * m must be in [1, 15] and m <= k.  Returns 0, or -1 on bad arguments. */
+int kmc_oracle_key_signatures(const uint64_t* keys, uint64_t n, uint32_t key_words,
+                              uint32_t k, uint32_t m, int filter, uint32_t* out) {
+  if (k < 1 || k > 64 || m < 1 || m > 15 || m > k) return -1;
+  if (key_words != (k <= 32 ? 1u : 2u)) return -1;
+  int sym[64];
+  for (uint64_t i = 0; i < n; ++i) {
+    u128 K = key_words == 1 ? (u128)keys[i]
+                            : (((u128)keys[2 * i]) << 64) | (u128)keys[2 * i + 1];
+    for (uint32_t t = 0; t < k; ++t) sym[t] = (int)((K >> (2 * (k - 1 - t))) & 3);
+    out[i] = signature_of_symbols(sym, k, m, filter);
+  }
+  return 0;
+}
+
+/* Signature of the window starting at every byte position of the input:
+ * out[j] = signature of the k bytes at j if they lie in one read and are all
+ * valid, else 0xFFFFFFFF.  out has offsets[n_reads] entries.  The signature
+ * is computed from the window's own symbols (either orientation gives the
+ * same value, since the canonical m-mers of a k-mer and of its reverse
+ * complement coincide). */
+int kmc_oracle_window_signatures(const uint8_t* seq, const uint64_t* offsets,
+                                 uint64_t n_reads, uint32_t k, uint32_t m, int filter,
+                                 uint32_t* out) {
+  if (k < 1 || k > 64 || m < 1 || m > 15 || m > k) return -1;
+  int sym[64];
+  for (uint64_t r = 0; r < n_reads; ++r) {
+    uint64_t b = offsets[r], e = offsets[r + 1];
+    for (uint64_t j = b; j < e; ++j) {
+      out[j] = 0xFFFFFFFFu;
+      if (j + k > e) continue;
+      int ok = 1;
+      for (uint32_t t = 0; t < k; ++t) {
+        sym[t] = sym_code(seq[j + t]);
+        if (sym[t] < 0) { ok = 0; break; }
+      }
+      if (ok) out[j] = signature_of_symbols(sym, k, m, filter);
+    }
+  }
+  return 0;
+}

@@ -1,0 +1,160 @@
+"""Seeded synthetic read sets shaped like the paper's workloads.
+
+This module only makes inputs: random references and reads sampled from them
+(with substitution errors, N bases and random strand).  It computes nothing
+of the counting method and is shared by the tests, the benchmark and the
+smoke check.  All randomness comes from numpy's PCG64 with the stated seed,
+and read sets are returned as the library's CSR form: ``seq`` (uint8 ASCII,
+upper case) and ``offsets`` (uint64, n_reads + 1, offsets[0] = 0).
+
+Workloads (reads ~100-150 bp, ~30-40x coverage, k = 28 / 55 as in the paper's
+experiments; the paper's own datasets are not used, these stand in for them):
+
+- ``uniform``: i.i.d. uniform A/C/G/T reads, no reference, no N.
+- ``genome``: uniform random reference; each read takes a uniform start,
+  a fair-coin strand (reverse complemented if set), then each base is
+  substituted with probability ``err`` by one of the other three uniformly,
+  then set to N with probability ``n_rate`` -- in that order.
+- ``repeat_reference``: a uniform reference with a fraction overwritten by
+  repeat families (unit length U{1000..5000}; half interspersed with 2-10
+  copies, half tandem arrays of 2-20 adjacent copies; each copy diverged by
+  d ~ U[0, 0.10] substitutions).
+"""
+from __future__ import annotations
+
+import hashlib
+
+import numpy as np
+
+GENERATOR_VERSION = 1
+_ASCII = np.frombuffer(b"ACGT", dtype=np.uint8)
+_N = ord("N")
+
+
+def _rng(seed) -> np.random.Generator:
+    if isinstance(seed, (tuple, list)):
+        return np.random.Generator(np.random.PCG64(np.random.SeedSequence(list(seed))))
+    return np.random.Generator(np.random.PCG64(seed))
+
+
+def _substitute(rng, codes: np.ndarray, rate: float) -> None:
+    """In place: each entry replaced with probability rate by another symbol."""
+    if rate <= 0:
+        return
+    hit = rng.random(codes.shape, dtype=np.float32) < rate
+    shift = rng.integers(1, 4, size=int(hit.sum()), dtype=np.uint8)
+    codes[hit] = (codes[hit] + shift) & 3
+
+
+def random_reference(seed, length: int) -> np.ndarray:
+    """Uniform i.i.d. reference as 2-bit codes (uint8 0..3)."""
+    return _rng(seed).integers(0, 4, size=length, dtype=np.uint8)
+
+
+def repeat_reference(seed, length: int, repeat_fraction: float = 0.2) -> np.ndarray:
+    """Uniform reference with repeat_fraction of it overwritten by repeat families."""
+    rng = _rng(seed)
+    ref = rng.integers(0, 4, size=length, dtype=np.uint8)
+    target = int(repeat_fraction * length)
+    written = 0
+    fam = 0
+    while written < target:
+        ulen = int(rng.integers(1000, 5001))
+        unit = rng.integers(0, 4, size=ulen, dtype=np.uint8)
+        tandem = (fam % 2) == 1
+        ncopy = int(rng.integers(2, 21)) if tandem else int(rng.integers(2, 11))
+        if tandem:
+            span = ulen * ncopy
+            if span >= length:
+                ncopy = max(1, length // ulen - 1)
+                span = ulen * ncopy
+            start = int(rng.integers(0, length - span + 1))
+            starts = [start + c * ulen for c in range(ncopy)]
+        else:
+            starts = [int(rng.integers(0, length - ulen + 1)) for _ in range(ncopy)]
+        for s in starts:
+            copy = unit.copy()
+            _substitute(rng, copy, float(rng.uniform(0.0, 0.10)))
+            ref[s:s + ulen] = copy
+            written += ulen
+        fam += 1
+    return ref
+
+
+def sample_reads(seed, ref: np.ndarray, n_reads: int, read_len, err: float,
+                 n_rate: float, chunk: int = 1 << 20):
+    """Reads sampled from ref (2-bit codes).  read_len: int or (lo, hi) inclusive."""
+    rng = _rng(seed)
+    if isinstance(read_len, tuple):
+        lens = rng.integers(read_len[0], read_len[1] + 1, size=n_reads).astype(np.uint64)
+    else:
+        lens = np.full(n_reads, read_len, dtype=np.uint64)
+    offsets = np.zeros(n_reads + 1, dtype=np.uint64)
+    np.cumsum(lens, out=offsets[1:])
+    seq = np.empty(int(offsets[-1]), dtype=np.uint8)
+    L = ref.size
+    for c0 in range(0, n_reads, chunk):
+        c1 = min(n_reads, c0 + chunk)
+        cl = lens[c0:c1].astype(np.int64)
+        maxl = int(cl.max()) if cl.size else 0
+        starts = rng.integers(0, np.maximum(L - cl + 1, 1))
+        strand = rng.random(c1 - c0) < 0.5
+        idx = starts[:, None] + np.arange(maxl)[None, :]
+        np.minimum(idx, L - 1, out=idx)
+        reads = ref[idx]
+        # reverse strand: reverse the read's own bases, complement (code 3 - c)
+        if strand.any():
+            rs = reads[strand]
+            rl = cl[strand]
+            ridx = (rl[:, None] - 1 - np.arange(maxl)[None, :])
+            ridx = np.where(ridx >= 0, ridx, 0)
+            reads[strand] = 3 - np.take_along_axis(rs, ridx, axis=1)
+        _substitute(rng, reads, err)
+        ascii_ = _ASCII[reads]
+        if n_rate > 0:
+            ascii_[rng.random(reads.shape, dtype=np.float32) < n_rate] = _N
+        valid = np.arange(maxl)[None, :] < cl[:, None]
+        seq[int(offsets[c0]):int(offsets[c1])] = ascii_[valid]
+    return seq, offsets
+
+
+def uniform_reads(seed, n_reads: int, read_len: int):
+    rng = _rng(seed)
+    codes = rng.integers(0, 4, size=n_reads * read_len, dtype=np.uint8)
+    offsets = np.arange(n_reads + 1, dtype=np.uint64) * np.uint64(read_len)
+    return _ASCII[codes], offsets
+
+
+def digest(seq: np.ndarray, offsets: np.ndarray) -> str:
+    h = hashlib.sha256()
+    h.update(np.ascontiguousarray(offsets).tobytes())
+    h.update(np.ascontiguousarray(seq).tobytes())
+    return h.hexdigest()
+
+
+# Named workloads: (generator, counting parameters).
+CONFIGS = {
+    "uniform-10k": dict(k=28, p=7, n_bins=512, cutoff_min=1, cutoff_max=10**9),
+    "genome-5M-2Mx100": dict(k=28, p=7, n_bins=512, cutoff_min=2, cutoff_max=10**9),
+    "repeats-50M-30x150-k55": dict(k=55, p=9, n_bins=1024, cutoff_min=2, cutoff_max=10**6),
+}
+
+
+def make(name: str, scale: float = 1.0):
+    """Build a named workload.  scale < 1 shrinks read count and reference
+    (same generator, same shape) for quick tests.  Returns (seq, offsets, params)."""
+    params = dict(CONFIGS[name])
+    if name == "uniform-10k":
+        n = max(1, int(10_000 * scale))
+        seq, off = uniform_reads(1, n, 100)
+    elif name == "genome-5M-2Mx100":
+        ref = random_reference((2, 0), max(1000, int(5_000_000 * scale)))
+        seq, off = sample_reads((2, 1), ref, max(1, int(2_000_000 * scale)), 100,
+                                err=0.01, n_rate=0.0005)
+    elif name == "repeats-50M-30x150-k55":
+        ref = repeat_reference((3, 0), max(20_000, int(50_000_000 * scale)))
+        seq, off = sample_reads((3, 1), ref, max(1, int(10_000_000 * scale)), 150,
+                                err=0.005, n_rate=0.001)
+    else:
+        raise KeyError(name)
+    return seq, off, params

@@ -1,0 +1,277 @@
+"""Pins for the CPU oracle: the paper's worked examples, brute force on tiny
+inputs, closed forms and invariants.  CPU only."""
+from collections import Counter
+
+import numpy as np
+import pytest
+
+from conftest import read_golden
+from oracle import strings as S
+from paper_1407_1507_amd import synth
+
+_BASES = "ACGT"
+
+
+def pack_bytes(s):
+    """Pack per the supplement's .kmc_suf rule: leftmost symbol first, four
+    symbols per byte, the first symbol in the byte's high bits."""
+    out = []
+    for i in range(0, len(s), 4):
+        v = 0
+        for ch in s[i:i + 4]:
+            v = v * 4 + "ACGT".index(ch)
+        out.append(v)
+    return out
+
+
+def key_of(s):
+    """Numeric key of a string: its packed bytes read as one big-endian number."""
+    v = 0
+    for b in pack_bytes(s):
+        v = v * 256 + b
+    return v
+
+
+def to_reads(strs):
+    seq = np.frombuffer("".join(strs).encode(), dtype=np.uint8).copy()
+    off = np.zeros(len(strs) + 1, dtype=np.uint64)
+    off[1:] = np.cumsum([len(s) for s in strs])
+    return seq, off
+
+
+def table_dict(keys, counts, k):
+    if k <= 32:
+        return {int(a): int(c) for a, c in zip(keys, counts)}
+    return {(int(a) << 64) | int(b): int(c) for (a, b), c in zip(keys, counts)}
+
+
+def brute_force(reads, k, ci=1, cx=2**32 - 1):
+    """String-level counter: canonical = min(s, reverse complement) by Python
+    string order, over windows made only of A/C/G/T (either case)."""
+    comp = {"A": "T", "C": "G", "G": "C", "T": "A"}
+    c = Counter()
+    for r in reads:
+        r = r.upper()
+        for j in range(len(r) - k + 1):
+            w = r[j:j + k]
+            if any(ch not in comp for ch in w):
+                continue
+            rc = "".join(comp[ch] for ch in reversed(w))
+            c[min(w, rc)] += 1
+    return {key_of_full(s, k): n for s, n in c.items() if max(ci, 1) <= n <= cx}
+
+
+def key_of_full(s, k):
+    v = 0
+    for ch in s:
+        v = v * 4 + "ACGT".index(ch)
+    return v
+
+
+# ------------------------------------------------------------ paper examples
+
+
+def test_supplement_packing_and_codes():
+    rows = {r[0]: r[1:] for r in read_golden("supp_encoding.txt")}
+    kmer, plen, sig, val = rows["signature"]
+    assert S.signature(kmer, int(plen)) == sig
+    assert S.encode(sig) == int(val)
+    pre, pval = rows["prefix"]
+    assert S.encode(pre) == int(pval)
+    pk, *bytes_ = rows["packed"]
+    assert pack_bytes(pk) == [int(b, 16) for b in bytes_]
+    # the numeric packing used by the oracle is the same big-endian number
+    assert key_of(pk) == key_of_full(pk, len(pk))
+
+
+def test_supplement_signature_in_c(oracle_lib):
+    kmer, plen, sig, val = read_golden("supp_encoding.txt")[0][1:]
+    can = S.canonical(kmer)
+    out = oracle_lib.key_signatures(np.array([key_of_full(can, len(can))], dtype=np.uint64),
+                                    len(kmer), int(plen))
+    assert int(out[0]) == int(val)
+    # AAATG and ACAAA are smaller canonical 5-mers of this k-mer but are excluded
+    assert S.canonical("AAATG") < sig and not S.allowed(S.canonical("AAATG"))
+    assert "ACAAA" < sig and not S.allowed("ACAAA")
+
+
+def test_fig1_superkmers():
+    rows = read_golden("fig1_split.txt")
+    read = rows[0][1]
+    k, m = int(rows[1][1]), int(rows[2][1])
+    sig_rows = [(r[1], r[2]) for r in rows if r[0] == "signature"]
+    min_rows = [(r[1], r[2]) for r in rows if r[0] == "minimizer"]
+    assert S.superkmers(read, k, m, filter=True) == sig_rows
+    assert S.superkmers(read, k, m, filter=False) == min_rows
+    # signatures give fewer super k-mers than minimizers here
+    assert len(sig_rows) < len(min_rows)
+
+
+def test_fig1_window_signatures_in_c(oracle_lib):
+    rows = read_golden("fig1_split.txt")
+    read = rows[0][1]
+    k, m = int(rows[1][1]), int(rows[2][1])
+    seq, off = to_reads([read])
+    for mode, flt in (("signature", True), ("minimizer", False)):
+        expect = []
+        for sk, sig in [(r[1], r[2]) for r in rows if r[0] == mode]:
+            expect += [S.encode(sig)] * (len(sk) - k + 1)
+        got = oracle_lib.window_signatures(seq, off, k, m, filter=flt)
+        assert list(got[:len(read) - k + 1]) == expect
+        assert all(int(x) == 0xFFFFFFFF for x in got[len(read) - k + 1:])
+
+
+def test_fig2_canonical_kmers(oracle_lib):
+    rows = read_golden("fig2_kx_mers.txt")
+    sk = rows[0][1]
+    k, m = int(rows[1][1]), int(rows[2][1])
+    sig = rows[3][1]
+    kx = [r[1] for r in rows if r[0] == "kx"]
+    kmers = []
+    for x in kx:
+        kmers += [x] if len(x) == k else [x[:k], x[1:]]
+    assert len(kmers) == len(sk) - k + 1
+    seq, off = to_reads([sk])
+    keys, counts = oracle_lib.count(seq, off, k, 1)
+    assert sorted(int(a) for a in keys) == sorted(key_of_full(s, k) for s in kmers)
+    assert list(counts) == [1] * len(kmers)
+    sigs = oracle_lib.key_signatures(keys, k, m)
+    assert set(int(s) for s in sigs) == {S.encode(sig)}
+
+
+# -------------------------------------------------------------- brute force
+
+
+def random_reads(rng, n, lo, hi, n_rate=0.0, lower=0.0):
+    out = []
+    for _ in range(n):
+        L = int(rng.integers(lo, hi + 1))
+        s = "".join(rng.choice(list(_BASES), size=L))
+        s = "".join("N" if rng.random() < n_rate else ch for ch in s)
+        s = "".join(ch.lower() if rng.random() < lower else ch for ch in s)
+        out.append(s)
+    return out
+
+
+@pytest.mark.parametrize("k", [1, 4, 5, 15, 31, 32, 33, 55, 63, 64])
+def test_brute_force(oracle_lib, k):
+    rng = np.random.default_rng(100 + k)
+    reads = random_reads(rng, 60, 0, k + 40, n_rate=0.03, lower=0.05)
+    # a low-complexity read so that counts above 1 occur at every k
+    reads.append("ACGT" * 30)
+    reads.append("A" * 90 + "N" + "T" * 70)
+    seq, off = to_reads(reads)
+    for ci, cx in ((1, 2**32 - 1), (2, 2**32 - 1), (1, 1), (2, 5), (0, 3)):
+        keys, counts = oracle_lib.count(seq, off, k, ci, cx)
+        got = table_dict(keys, counts, k)
+        assert got == brute_force(reads, k, ci, cx)
+        flat = [int(a) for a in keys] if k <= 32 else [(int(a) << 64) | int(b) for a, b in keys]
+        assert flat == sorted(flat) and len(set(flat)) == len(flat)
+
+
+@pytest.mark.parametrize("threads", [2, 5])
+def test_threaded_equals_single(oracle_lib, threads):
+    seq, off, _ = synth.make("genome-5M-2Mx100", 0.002)
+    for k in (28, 55):
+        a = oracle_lib.count(seq, off, k, 2, 10**9, threads=1)
+        b = oracle_lib.count(seq, off, k, 2, 10**9, threads=threads)
+        assert np.array_equal(a[0], b[0]) and np.array_equal(a[1], b[1])
+
+
+# ------------------------------------------------------------- closed forms
+
+
+def test_uniform_10k_closed_form(oracle_lib):
+    seq, off, p = synth.make("uniform-10k")
+    keys, counts = oracle_lib.count(seq, off, p["k"], 1, 10**9)
+    # 10,000 reads x (100 - 28 + 1) windows, no N
+    assert int(counts.sum()) == 10_000 * 73 == oracle_lib.valid_windows(seq, off, 28)
+
+
+def test_valid_windows_matches_enumeration(oracle_lib):
+    rng = np.random.default_rng(7)
+    reads = random_reads(rng, 200, 0, 70, n_rate=0.05)
+    seq, off = to_reads(reads)
+    for k in (1, 3, 12, 28):
+        expect = sum(1 for r in reads for j in range(len(r) - k + 1) if "N" not in r[j:j + k])
+        assert oracle_lib.valid_windows(seq, off, k) == expect
+        keys, counts = oracle_lib.count(seq, off, k, 1)
+        assert int(counts.sum()) == expect
+
+
+# --------------------------------------------------------------- invariants
+
+
+def _table(oracle_lib, reads, k, ci=1, cx=2**32 - 1):
+    seq, off = to_reads(reads)
+    return table_dict(*oracle_lib.count(seq, off, k, ci, cx), k)
+
+
+def test_invariants(oracle_lib):
+    rng = np.random.default_rng(11)
+    ref = "".join(rng.choice(list(_BASES), size=400))
+    reads = []
+    for _ in range(150):
+        s = int(rng.integers(0, 300))
+        r = ref[s:s + int(rng.integers(40, 100))]
+        reads.append(S.revcomp(r) if rng.random() < 0.5 else r)
+    reads = [("".join("N" if rng.random() < 0.01 else c for c in r)) for r in reads]
+    for k in (9, 28, 33):
+        base = _table(oracle_lib, reads, k)
+        # reverse-complementing every read leaves the table unchanged
+        rc = [S.revcomp(r.replace("N", "X")).replace("X", "N") for r in reads]
+        assert _table(oracle_lib, rc, k) == base
+        # permuting reads leaves it unchanged
+        perm = [reads[i] for i in rng.permutation(len(reads))]
+        assert _table(oracle_lib, perm, k) == base
+        # additivity: table(A u B) = merge-sum(table(A), table(B))
+        a, b = reads[:70], reads[70:]
+        ta, tb = _table(oracle_lib, a, k), _table(oracle_lib, b, k)
+        merged = Counter(ta)
+        merged.update(tb)
+        assert dict(merged) == base
+        # cutoffs are a filter of the full table
+        for ci, cx in ((2, 10**9), (3, 7), (1, 1)):
+            assert _table(oracle_lib, reads, k, ci, cx) == {
+                key: c for key, c in base.items() if ci <= c <= cx}
+        # an N is the same as a read break
+        split = []
+        for r in reads:
+            split += r.split("N")
+        assert _table(oracle_lib, split, k) == base
+
+
+def test_palindromes_count_once_per_occurrence(oracle_lib):
+    # ACGT is its own reverse complement: 3 occurrences -> count 3
+    got = _table(oracle_lib, ["ACGT", "ACGT", "AACGTT"], 4)
+    assert got[key_of_full("ACGT", 4)] == 3
+
+
+# -------------------------------------------------------------- signatures
+
+
+@pytest.mark.parametrize("k,m", [(8, 4), (15, 4), (28, 7), (55, 9), (64, 12), (21, 5)])
+def test_signature_c_vs_strings(oracle_lib, k, m):
+    rng = np.random.default_rng(k * 100 + m)
+    kmers = ["".join(rng.choice(list(_BASES), size=k)) for _ in range(300)]
+    kmers += ["A" * k, "T" * k, ("AC" * k)[:k], ("ACA" * k)[:k]]
+    cans = [S.canonical(x) for x in kmers]
+    if k <= 32:
+        keys = np.array([key_of_full(c, k) for c in cans], dtype=np.uint64)
+    else:
+        keys = np.array([[key_of_full(c, k) >> 64, key_of_full(c, k) & (2**64 - 1)]
+                         for c in cans], dtype=np.uint64)
+    for flt in (True, False):
+        got = oracle_lib.key_signatures(keys, k, m, filter=flt)
+        for x, g in zip(kmers, got):
+            s = S.signature(x, m, flt)
+            assert int(g) == (4**m if s is None else S.encode(s))
+    # poly-A has no allowed m-mer: sentinel 4^m
+    assert S.signature("A" * k, m) is None
+
+
+def test_signature_is_reverse_complement_invariant():
+    rng = np.random.default_rng(5)
+    for _ in range(200):
+        x = "".join(rng.choice(list(_BASES), size=28))
+        assert S.signature(x, 7) == S.signature(S.revcomp(x), 7)
