@@ -1,0 +1,186 @@
+/*
+ * kmc.h -- C ABI of the MI355X k-mer counting library (libkmc_hip.so).
+ *
+ * The library computes, for a set of DNA reads, every canonical k-mer with its
+ * exact number of occurrences, following the method of KMC 2 (Deorowicz,
+ * Kokot, Grabowski, Debudaj-Grabysz, 2014):
+ *   1. each read is split into super k-mers: maximal runs of consecutive
+ *      k-mers that share one signature (Methods, "From minimizers to
+ *      signatures" and "Sketch of the algorithm", Fig. 1);
+ *   2. the 4^p signatures are merged into n_bins bins from a histogram of a
+ *      small sample of the input (Methods, "Sketch of the algorithm"), and
+ *      every super k-mer is sent to the bin of its signature;
+ *   3. each bin is expanded into canonical k-mers (the smaller of a k-mer and
+ *      its reverse complement, Methods, "Minimizers of k-mers"), radix sorted
+ *      and run-length counted; k-mers counted fewer than cutoff_min or more
+ *      than cutoff_max times are dropped (Methods, "Additional features";
+ *      supplement, -ci / -cx).
+ * Every step runs in hand-written HIP kernels on the GPU; bins live in HBM.
+ *
+ * Symbols: A=0 C=1 G=2 T=3 (either case); a k-mer key packs its symbols with
+ * the leftmost symbol in the most significant bits (supplement, database
+ * format), so numeric order is lexicographic order.  Any other byte (N, IUPAC
+ * codes, ...) is invalid: every window holding one is skipped.
+ *
+ * Conventions for every call:
+ *   - Nothing throws across this ABI; every call returns a kmc_status.
+ *   - On error *out is set to NULL and nothing is leaked; no partial table.
+ *   - Inputs are borrowed for the duration of the call only.
+ *   - One kmc_ctx must not be used by two host threads at the same time.
+ */
+#ifndef KMC_H_
+#define KMC_H_
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum kmc_status {
+  KMC_OK = 0,
+  KMC_ERR_INVALID_ARG = 1,   /* an argument failed validation (see kmc_count) */
+  KMC_ERR_OUT_OF_MEMORY = 2, /* device or host allocation failed */
+  KMC_ERR_DEVICE = 3,        /* a HIP call failed; text via kmc_last_error */
+  KMC_ERR_TOO_LARGE = 4,     /* the job exceeds a size limit of the library */
+  KMC_ERR_BUSY = 5           /* reserved for asynchronous forms */
+} kmc_status;
+
+/* Reads in CSR form.  seq holds n_bases bytes (ASCII); read i is
+ * seq[offsets[i] .. offsets[i+1]).  offsets has n_reads + 1 entries,
+ * offsets[0] == 0, non-decreasing, offsets[n_reads] == n_bases.
+ * on_device = 0: both arrays are host memory; 1: both are device memory of
+ * the context's device (e.g. torch tensors on cuda:0). */
+typedef struct kmc_reads {
+  const uint8_t* seq;
+  const uint64_t* offsets;
+  uint64_t n_reads;
+  uint64_t n_bases;
+  int32_t on_device;
+  int32_t reserved;
+} kmc_reads;
+
+/* Counting parameters.
+ *   k           k-mer length, 4 <= k <= 64 (keys are 1 word for k <= 32,
+ *               2 words for k > 32);
+ *   p           signature length, 4 <= p <= min(k, 12);
+ *   n_bins      number of bins, 1 <= n_bins <= min(4^p + 1, 65535);
+ *   cutoff_min  keep a k-mer only if its count >= cutoff_min (0 acts as 1);
+ *   cutoff_max  keep a k-mer only if its count <= cutoff_max;
+ *               cutoff_min <= cutoff_max;
+ *   flags       KMC_FLAG_* bits. */
+typedef struct kmc_params {
+  uint32_t k;
+  uint32_t p;
+  uint32_t n_bins;
+  uint32_t cutoff_min;
+  uint32_t cutoff_max;
+  uint32_t flags;
+} kmc_params;
+
+/* The returned table stays in device memory (kmc_table.on_device = 1) instead
+ * of being copied to host memory. */
+#define KMC_FLAG_DEVICE_TABLE 0x1u
+/* Plain canonical minimizers instead of signatures (no AAA/ACA/AA filter;
+ * Methods, "Minimizers of k-mers").  Changes only the bins, never the counts. */
+#define KMC_FLAG_PLAIN_MINIMIZERS 0x2u
+
+/* Per-job statistics (measured on the device). */
+typedef struct kmc_stats {
+  uint64_t n_reads;
+  uint64_t n_bases;
+  uint64_t n_kmers;        /* valid windows = sum of counts before cutoffs */
+  uint64_t n_superkmers;   /* records written to the bins */
+  uint64_t n_distinct;     /* distinct canonical k-mers before cutoffs */
+  uint64_t n_out;          /* entries kept after cutoffs */
+  uint64_t sample_kmers;   /* k-mers in the signature histogram sample */
+  uint64_t max_bin_kmers;  /* k-mers in the largest bin */
+  uint64_t n_tiles;        /* sort tiles (sub-bins held in LDS) */
+  uint64_t n_big_tiles;    /* tiles too large for LDS, sorted in HBM */
+  uint64_t bytes_alg;      /* algorithmic HBM bytes of the job (see DESIGN) */
+  double us_map;           /* device time of each phase, microseconds */
+  double us_split;
+  double us_expand;
+  double us_sort;
+  double us_assemble;
+  double us_total;         /* first kernel to last kernel */
+} kmc_stats;
+
+/* Result of a count.  Entries are grouped by bin (bin b holds entries
+ * [bin_offsets[b], bin_offsets[b+1])), the order of the paper's database
+ * (signature, then k-mer; supplement, database format), and ascending by key
+ * inside each bin.  Bins hold disjoint key sets.
+ *   keys        n * key_words uint64; for key_words == 2 each key is stored
+ *               hi word first, then lo word; the hi word holds the top
+ *               2k - 64 bits;
+ *   counts      n exact uint32 counts (no saturation);
+ *   bin_offsets n_bins + 1 uint64 (always host memory);
+ *   sig_to_bin  4^p + 1 uint32: bin of every signature value; the last entry
+ *               is for k-mers with no allowed p-mer (always host memory).
+ * keys/counts are host memory unless on_device = 1.  The table is owned by
+ * the library: release it with kmc_table_free. */
+typedef struct kmc_table {
+  uint32_t k;
+  uint32_t key_words;
+  uint64_t n;
+  uint64_t* keys;
+  uint32_t* counts;
+  uint32_t n_bins;
+  uint32_t p;
+  uint64_t* bin_offsets;
+  uint32_t* sig_to_bin;
+  int32_t on_device;
+  int32_t reserved;
+  kmc_stats stats;
+} kmc_table;
+
+typedef struct kmc_ctx kmc_ctx;
+
+/* Create a context on HIP device `device` (its workspace, cached between
+ * calls, and its default stream).  Returns KMC_ERR_DEVICE if the device is
+ * not usable. */
+kmc_status kmc_ctx_create(int device, kmc_ctx** out);
+/* Destroy a context and free its workspace.  NULL is allowed. */
+void kmc_ctx_destroy(kmc_ctx* ctx);
+/* Text of the last error seen on ctx ("" if none).  Valid until the next
+ * call on ctx. */
+const char* kmc_last_error(const kmc_ctx* ctx);
+
+/* Count the canonical k-mers of `reads` (see the header comment).
+ * Uses a context on device 0 owned by the calling host thread.
+ * Validation (KMC_ERR_INVALID_ARG): see kmc_params; reads != NULL, out !=
+ * NULL, seq/offsets non-NULL when n_reads > 0, offsets well formed.
+ * Reads shorter than k and empty inputs contribute nothing; an empty table
+ * (n = 0) is a valid result. */
+kmc_status kmc_count(const kmc_reads* reads, uint32_t k, uint32_t p, uint32_t n_bins,
+                     uint32_t cutoff_min, uint32_t cutoff_max, kmc_table** out);
+
+/* As kmc_count, on context ctx, with explicit parameters, on HIP stream
+ * `stream` (a hipStream_t; NULL = the context's stream).  The call returns
+ * when the table is complete. */
+kmc_status kmc_count_ex(kmc_ctx* ctx, const kmc_reads* reads, const kmc_params* params,
+                        void* stream, kmc_table** out);
+
+/* Free a table returned by this library.  NULL is allowed. */
+void kmc_table_free(kmc_table* table);
+
+/* Static text for a status code. */
+const char* kmc_status_str(kmc_status status);
+
+/* Audit entry (tests): the signature of the window starting at every byte of
+ * the input, as the GPU's split kernel computes it, into sig_per_window
+ * (host memory, n_bases uint32; 0xFFFFFFFF where no valid k-mer starts), and
+ * 1 in superkmer_start (host memory, n_bases bytes; may be NULL) where the
+ * kernel opens a new super k-mer.  Signature definition: Methods, "From
+ * minimizers to signatures"; super k-mers: Fig. 1.  flags may hold
+ * KMC_FLAG_PLAIN_MINIMIZERS. */
+kmc_status kmc_debug_signatures(kmc_ctx* ctx, const kmc_reads* reads, uint32_t k, uint32_t p,
+                                uint32_t flags, uint32_t* sig_per_window,
+                                uint8_t* superkmer_start);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* KMC_H_ */

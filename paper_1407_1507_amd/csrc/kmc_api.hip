@@ -1,0 +1,584 @@
+// Host runtime of libkmc_hip.so: argument validation, the signature -> bin
+// map, the per-job plan (bin, record, key and tile layout in HBM), the
+// workspace cache and the C ABI declared in include/kmc.h.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cstdio>
+#include <cstdlib>
+#include <cstring>
+#include <new>
+#include <queue>
+#include <string>
+#include <utility>
+#include <vector>
+
+#include "../../include/kmc.h"
+#include "kmc_internal.h"
+
+using namespace kmc;
+
+// --------------------------------------------------------------- context
+
+namespace {
+
+enum BufId {
+  B_SEQ, B_OFF, B_HIST, B_MAP, B_BINCNT, B_CURSOR, B_REC, B_FINE, B_TOF, B_TILES, B_TCUR,
+  B_BASES, B_HTASK, B_ETASK, B_KEYS, B_COUNTS, B_TILEOUT, B_BIG, B_MISC, B_TMP, B_SCANTMP,
+  B_TILEOFF, B_BINOFF, B_OUTK, B_OUTC, B_DBG1, B_DBG2, B_COUNT_
+};
+
+struct DevBuf {
+  void* p = nullptr;
+  size_t cap = 0;
+};
+
+// Misc device words (one small allocation): counters read back by the host.
+struct Misc {
+  unsigned long long sample_kmers;
+  unsigned long long distinct;
+  uint32_t n_big;
+  uint32_t max_big;
+  uint32_t offsets_err;
+  uint32_t pad;
+};
+
+}  // namespace
+
+struct kmc_ctx {
+  int device = 0;
+  hipStream_t stream = nullptr;
+  std::string err;
+  DevBuf buf[B_COUNT_];
+  hipEvent_t ev[8] = {};
+};
+
+namespace {
+
+struct Fail {
+  kmc_status st;
+};
+
+void check(kmc_ctx* c, hipError_t e, const char* what) {
+  if (e != hipSuccess) {
+    c->err = std::string(what) + ": " + hipGetErrorString(e);
+    (void)hipGetLastError();
+    throw Fail{e == hipErrorOutOfMemory ? KMC_ERR_OUT_OF_MEMORY : KMC_ERR_DEVICE};
+  }
+}
+
+template <class T>
+T* ensure(kmc_ctx* c, BufId id, size_t bytes) {
+  DevBuf& b = c->buf[id];
+  if (bytes == 0) bytes = 16;
+  if (b.cap < bytes) {
+    if (b.p) check(c, hipFree(b.p), "hipFree");
+    b.p = nullptr;
+    b.cap = 0;
+    size_t want = bytes + bytes / 8;
+    want = (want + 4095) & ~(size_t)4095;
+    check(c, hipMalloc(&b.p, want), "hipMalloc workspace");
+    b.cap = want;
+  }
+  return static_cast<T*>(b.p);
+}
+
+uint32_t ilog2_ceil(uint64_t x) {
+  uint32_t r = 0;
+  while ((1ull << r) < x) ++r;
+  return r;
+}
+
+// Signature -> bin map (Methods, "Sketch of the algorithm": the least
+// frequent signatures of a sample are merged so that at most n_bins bins
+// remain).  Reading: longest-processing-time packing of the sampled
+// signatures, heaviest first (ties: smaller signature first), each into the
+// currently lightest bin (ties: lowest bin id); signatures absent from the
+// sample go to bin (signature mod n_bins).
+void build_map(const std::vector<uint32_t>& hist, uint32_t n_bins, std::vector<uint32_t>& map) {
+  const uint32_t n_sig = (uint32_t)hist.size();
+  map.assign(n_sig, 0);
+  for (uint32_t s = 0; s < n_sig; ++s) map[s] = s % n_bins;
+  std::vector<std::pair<uint32_t, uint32_t>> seen;
+  for (uint32_t s = 0; s < n_sig; ++s)
+    if (hist[s]) seen.emplace_back(hist[s], s);
+  std::sort(seen.begin(), seen.end(), [](const std::pair<uint32_t, uint32_t>& a,
+                                         const std::pair<uint32_t, uint32_t>& b) {
+    return a.first != b.first ? a.first > b.first : a.second < b.second;
+  });
+  typedef std::pair<uint64_t, uint32_t> LB;  // (load, bin)
+  std::priority_queue<LB, std::vector<LB>, std::greater<LB>> pq;
+  for (uint32_t b = 0; b < n_bins; ++b) pq.emplace(0, b);
+  for (const auto& e : seen) {
+    LB top = pq.top();
+    pq.pop();
+    map[e.second] = top.second;
+    top.first += e.first;
+    pq.push(top);
+  }
+}
+
+kmc_table* new_table() {
+  kmc_table* t = static_cast<kmc_table*>(std::calloc(1, sizeof(kmc_table)));
+  return t;
+}
+
+struct Job {
+  uint32_t k, p, n_bins, ci, cx, kw, flags;
+  uint64_t n_reads, n_bases;
+  const uint8_t* seq;     // device
+  const uint64_t* off;    // device
+  bool aligned4;
+};
+
+ScanCfg scan_cfg(const Job& J) {
+  ScanCfg C;
+  C.k = J.k;
+  C.p = J.p;
+  C.w = J.k - J.p + 1;
+  C.filter = (J.flags & KMC_FLAG_PLAIN_MINIMIZERS) ? 0u : 1u;
+  C.pmask = (uint32_t)((1ull << (2 * J.p)) - 1);
+  C.sent = 1u << (2 * J.p);
+  C.n_bins = J.n_bins;
+  C.aligned4 = J.aligned4 ? 1u : 0u;
+  return C;
+}
+
+kmc_status validate(const kmc_reads* reads, const kmc_params* P) {
+  if (!reads || !P) return KMC_ERR_INVALID_ARG;
+  if (P->k < 4 || P->k > 64) return KMC_ERR_INVALID_ARG;
+  if (P->p < 4 || P->p > 12 || P->p > P->k) return KMC_ERR_INVALID_ARG;
+  const uint64_t n_sig = (1ull << (2 * P->p)) + 1;
+  if (P->n_bins < 1 || P->n_bins > 65535 || P->n_bins > n_sig) return KMC_ERR_INVALID_ARG;
+  if (P->cutoff_min > P->cutoff_max) return KMC_ERR_INVALID_ARG;
+  if (P->flags & ~(KMC_FLAG_DEVICE_TABLE | KMC_FLAG_PLAIN_MINIMIZERS)) return KMC_ERR_INVALID_ARG;
+  if (reads->n_reads > 0 && (!reads->seq && reads->n_bases > 0)) return KMC_ERR_INVALID_ARG;
+  if (reads->n_reads > 0 && !reads->offsets) return KMC_ERR_INVALID_ARG;
+  if (reads->n_reads >= (1ull << 40) || reads->n_bases >= (1ull << 46)) return KMC_ERR_TOO_LARGE;
+  if (!reads->on_device && reads->n_reads > 0) {
+    const uint64_t* o = reads->offsets;
+    if (o[0] != 0 || o[reads->n_reads] != reads->n_bases) return KMC_ERR_INVALID_ARG;
+    for (uint64_t i = 0; i < reads->n_reads; ++i)
+      if (o[i + 1] < o[i]) return KMC_ERR_INVALID_ARG;
+  }
+  return KMC_OK;
+}
+
+// Put the reads on the device (copy host reads into the workspace).
+void stage_reads(kmc_ctx* c, const kmc_reads* R, Job& J) {
+  J.n_reads = R->n_reads;
+  J.n_bases = R->n_bases;
+  if (R->on_device) {
+    J.seq = R->seq;
+    J.off = R->offsets;
+  } else {
+    uint8_t* s = ensure<uint8_t>(c, B_SEQ, R->n_bases + 16);
+    uint64_t* o = ensure<uint64_t>(c, B_OFF, (R->n_reads + 1) * 8);
+    if (R->n_bases)
+      check(c, hipMemcpyAsync(s, R->seq, R->n_bases, hipMemcpyHostToDevice, c->stream), "H2D seq");
+    if (R->offsets)
+      check(c, hipMemcpyAsync(o, R->offsets, (R->n_reads + 1) * 8, hipMemcpyHostToDevice,
+                              c->stream), "H2D offsets");
+    else
+      check(c, hipMemsetAsync(o, 0, 8, c->stream), "memset");
+    J.seq = s;
+    J.off = o;
+  }
+  J.aligned4 = ((uintptr_t)J.seq & 3u) == 0;
+}
+
+float ev_ms(hipEvent_t a, hipEvent_t b) {
+  float ms = 0.f;
+  if (hipEventElapsedTime(&ms, a, b) != hipSuccess) return 0.f;
+  return ms;
+}
+
+void run_count(kmc_ctx* c, const kmc_reads* R, const kmc_params* P, kmc_table* T) {
+  Job J;
+  J.k = P->k;
+  J.p = P->p;
+  J.n_bins = P->n_bins;
+  J.ci = P->cutoff_min == 0 ? 1 : P->cutoff_min;
+  J.cx = P->cutoff_max;
+  J.kw = P->k <= 32 ? 1 : 2;
+  J.flags = P->flags;
+  hipStream_t s = c->stream;
+  const uint32_t n_sig = (1u << (2 * J.p)) + 1;
+  const uint32_t RW = 2 * J.kw;
+
+  T->k = J.k;
+  T->key_words = J.kw;
+  T->n_bins = J.n_bins;
+  T->p = J.p;
+  T->on_device = (J.flags & KMC_FLAG_DEVICE_TABLE) ? 1 : 0;
+  T->bin_offsets = static_cast<uint64_t*>(std::calloc(J.n_bins + 1, sizeof(uint64_t)));
+  T->sig_to_bin = static_cast<uint32_t*>(std::calloc(n_sig, sizeof(uint32_t)));
+  if (!T->bin_offsets || !T->sig_to_bin) throw Fail{KMC_ERR_OUT_OF_MEMORY};
+  kmc_stats& st = T->stats;
+  st.n_reads = R->n_reads;
+  st.n_bases = R->n_bases;
+
+  stage_reads(c, R, J);
+  Misc* misc = ensure<Misc>(c, B_MISC, sizeof(Misc));
+  check(c, hipMemsetAsync(misc, 0, sizeof(Misc), s), "memset");
+  if (R->on_device && J.n_reads > 0)
+    check(c, launch_check_offsets(s, J.off, J.n_reads, J.n_bases, &misc->offsets_err), "check");
+  const ScanCfg C = scan_cfg(J);
+
+  // ---- map: signature histogram of every s-th read (s = N/1e5 in [1,100])
+  check(c, hipEventRecord(c->ev[0], s), "event");
+  uint32_t* hist = ensure<uint32_t>(c, B_HIST, (size_t)n_sig * 4);
+  check(c, hipMemsetAsync(hist, 0, (size_t)n_sig * 4, s), "memset");
+  uint64_t stride = J.n_bases / 100000;
+  stride = stride < 1 ? 1 : (stride > 100 ? 100 : stride);
+  check(c, launch_sig_hist(s, J.seq, J.off, J.n_reads, J.n_bases, stride, C, J.kw, hist,
+                           &misc->sample_kmers), "sig_hist");
+  std::vector<uint32_t> h_hist(n_sig);
+  Misc h_misc;
+  check(c, hipMemcpyAsync(h_hist.data(), hist, (size_t)n_sig * 4, hipMemcpyDeviceToHost, s), "D2H");
+  check(c, hipMemcpyAsync(&h_misc, misc, sizeof(Misc), hipMemcpyDeviceToHost, s), "D2H");
+  check(c, hipStreamSynchronize(s), "sync");
+  if (h_misc.offsets_err) throw Fail{KMC_ERR_INVALID_ARG};
+  st.sample_kmers = h_misc.sample_kmers;
+  std::vector<uint32_t> map;
+  build_map(h_hist, J.n_bins, map);
+  std::memcpy(T->sig_to_bin, map.data(), (size_t)n_sig * 4);
+  uint32_t* d_map = ensure<uint32_t>(c, B_MAP, (size_t)n_sig * 4);
+  check(c, hipMemcpyAsync(d_map, map.data(), (size_t)n_sig * 4, hipMemcpyHostToDevice, s), "H2D map");
+  check(c, hipEventRecord(c->ev[1], s), "event");
+
+  // ---- split: per-bin records / k-mers, then scatter of the records
+  unsigned long long* bincnt = ensure<unsigned long long>(c, B_BINCNT, (size_t)J.n_bins * 16);
+  check(c, hipMemsetAsync(bincnt, 0, (size_t)J.n_bins * 16, s), "memset");
+  check(c, launch_split_count(s, J.seq, J.off, J.n_reads, J.n_bases, C, J.kw, d_map, bincnt,
+                              bincnt + J.n_bins), "split_count");
+  std::vector<uint64_t> h_cnt(2 * (size_t)J.n_bins);
+  check(c, hipMemcpyAsync(h_cnt.data(), bincnt, (size_t)J.n_bins * 16, hipMemcpyDeviceToHost, s), "D2H");
+  check(c, hipStreamSynchronize(s), "sync");
+  const uint64_t* rec_cnt = h_cnt.data();
+  const uint64_t* kmer_cnt = h_cnt.data() + J.n_bins;
+  // bases: [0..n_bins] record base, [n_bins+1..] key base, then tile base
+  std::vector<uint64_t> bases(3 * ((size_t)J.n_bins + 1));
+  uint64_t* rec_base = bases.data();
+  uint64_t* key_base = rec_base + J.n_bins + 1;
+  uint64_t* tile_base = key_base + J.n_bins + 1;
+  uint64_t max_bin = 0;
+  rec_base[0] = key_base[0] = 0;
+  for (uint32_t b = 0; b < J.n_bins; ++b) {
+    rec_base[b + 1] = rec_base[b] + rec_cnt[b];
+    key_base[b + 1] = key_base[b] + kmer_cnt[b];
+    max_bin = std::max<uint64_t>(max_bin, kmer_cnt[b]);
+  }
+  const uint64_t n_rec = rec_base[J.n_bins], n_kmers = key_base[J.n_bins];
+  st.n_kmers = n_kmers;
+  st.n_superkmers = n_rec;
+  st.max_bin_kmers = max_bin;
+  if (max_bin >= (1ull << 32)) {
+    c->err = "a bin holds 2^32 or more k-mers";
+    throw Fail{KMC_ERR_TOO_LARGE};
+  }
+  uint64_t* records = ensure<uint64_t>(c, B_REC, n_rec * RW * 8);
+  unsigned long long* cursor = ensure<unsigned long long>(c, B_CURSOR, (size_t)J.n_bins * 8);
+  check(c, hipMemcpyAsync(cursor, rec_base, (size_t)J.n_bins * 8, hipMemcpyHostToDevice, s), "H2D");
+  check(c, launch_split_scatter(s, J.seq, J.off, J.n_reads, J.n_bases, C, J.kw, d_map, cursor,
+                                records), "split_scatter");
+  check(c, hipEventRecord(c->ev[2], s), "event");
+
+  // ---- expand: fine histogram per bin, tiles, scatter of canonical keys
+  KeyCfg kc;
+  kc.k = J.k;
+  kc.key_words = J.kw;
+  kc.tile_cap = J.kw == 1 ? kTileCap1 : kTileCap2;
+  kc.tile_target = kc.tile_cap / 2;
+  kc.n_bins = J.n_bins;
+  kc.cutoff_min = J.ci;
+  kc.cutoff_max = J.cx;
+  // fine ranges of about tile_target / 4 keys in the largest bin
+  uint32_t fb = ilog2_ceil(max_bin * 4 / kc.tile_target + 1);
+  fb = std::max<uint32_t>(1, std::min<uint32_t>({fb, (uint32_t)kMaxFineBits, 2 * J.k}));
+  kc.fine_bits = fb;
+  uint64_t n_tiles = 0, max_tiles = 0;
+  for (uint32_t b = 0; b < J.n_bins; ++b) {
+    tile_base[b] = n_tiles;
+    const uint64_t nt = kmer_cnt[b] ? (kmer_cnt[b] - 1) / kc.tile_target + 1 : 0;
+    n_tiles += nt;
+    max_tiles = std::max(max_tiles, nt);
+  }
+  tile_base[J.n_bins] = n_tiles;
+  if (max_tiles > (uint64_t)kMaxTilesPerBin) {
+    c->err = "a bin needs more sort tiles than the library supports; use more bins";
+    throw Fail{KMC_ERR_TOO_LARGE};
+  }
+  st.n_tiles = n_tiles;
+  // tasks: fine-histogram tasks of up to 8 * 2^fb records, expansion tasks of 256
+  const uint64_t hrec = std::min<uint64_t>(65536, std::max<uint64_t>(1024, 8ull << fb));
+  std::vector<ExpandTask> htasks, etasks;
+  for (uint32_t b = 0; b < J.n_bins; ++b) {
+    for (uint64_t r = rec_base[b]; r < rec_base[b + 1]; r += hrec)
+      htasks.push_back({r, (uint32_t)std::min<uint64_t>(hrec, rec_base[b + 1] - r), b});
+    for (uint64_t r = rec_base[b]; r < rec_base[b + 1]; r += kExpandThreads)
+      etasks.push_back({r, (uint32_t)std::min<uint64_t>(kExpandThreads, rec_base[b + 1] - r), b});
+  }
+  ExpandTask* d_ht = ensure<ExpandTask>(c, B_HTASK, htasks.size() * sizeof(ExpandTask));
+  ExpandTask* d_et = ensure<ExpandTask>(c, B_ETASK, etasks.size() * sizeof(ExpandTask));
+  uint64_t* d_bases = ensure<uint64_t>(c, B_BASES, bases.size() * 8);
+  if (!htasks.empty())
+    check(c, hipMemcpyAsync(d_ht, htasks.data(), htasks.size() * sizeof(ExpandTask),
+                            hipMemcpyHostToDevice, s), "H2D");
+  if (!etasks.empty())
+    check(c, hipMemcpyAsync(d_et, etasks.data(), etasks.size() * sizeof(ExpandTask),
+                            hipMemcpyHostToDevice, s), "H2D");
+  check(c, hipMemcpyAsync(d_bases, bases.data(), bases.size() * 8, hipMemcpyHostToDevice, s), "H2D");
+  const uint64_t* d_key_base = d_bases + J.n_bins + 1;
+  const uint64_t* d_tile_base = d_bases + 2 * ((size_t)J.n_bins + 1);
+  const size_t nfine = (size_t)J.n_bins << fb;
+  uint32_t* fine = ensure<uint32_t>(c, B_FINE, nfine * 4);
+  check(c, hipMemsetAsync(fine, 0, nfine * 4, s), "memset");
+  check(c, launch_fine_hist(s, kc, d_ht, (uint32_t)htasks.size(), records, fine), "fine_hist");
+  uint16_t* tof = ensure<uint16_t>(c, B_TOF, nfine * 2);
+  Tile* tiles = ensure<Tile>(c, B_TILES, n_tiles * sizeof(Tile));
+  unsigned long long* tcur = ensure<unsigned long long>(c, B_TCUR, n_tiles * 8);
+  if (n_tiles) check(c, hipMemsetAsync(tiles, 0, n_tiles * sizeof(Tile), s), "memset");
+  check(c, launch_plan_tiles(s, kc, fine, d_key_base, d_tile_base, tof, tiles, tcur), "plan");
+  uint64_t* keys = ensure<uint64_t>(c, B_KEYS, n_kmers * J.kw * 8);
+  uint32_t* counts = ensure<uint32_t>(c, B_COUNTS, n_kmers * 4);
+  check(c, launch_expand_scatter(s, kc, d_et, (uint32_t)etasks.size(), records, tof, d_tile_base,
+                                 (uint32_t)max_tiles, tcur, keys), "expand");
+  check(c, hipEventRecord(c->ev[3], s), "event");
+
+  // ---- sort: tiles in LDS, big tiles through HBM
+  uint32_t* tile_out = ensure<uint32_t>(c, B_TILEOUT, n_tiles * 4);
+  uint32_t* big = ensure<uint32_t>(c, B_BIG, n_tiles * 4);
+  check(c, launch_tile_sort(s, kc, tiles, n_tiles, keys, counts, tile_out, big, &misc->n_big,
+                            &misc->distinct), "tile_sort");
+  check(c, hipMemcpyAsync(&h_misc, misc, sizeof(Misc), hipMemcpyDeviceToHost, s), "D2H");
+  check(c, hipStreamSynchronize(s), "sync");
+  st.n_big_tiles = h_misc.n_big;
+  if (h_misc.n_big) {
+    uint64_t* tmp = ensure<uint64_t>(c, B_TMP, (size_t)h_misc.max_big * J.kw * 8);
+    check(c, launch_big_tiles(s, kc, tiles, big, h_misc.n_big, keys, tmp, counts, tile_out,
+                              &misc->distinct), "big_tiles");
+  }
+  check(c, hipEventRecord(c->ev[4], s), "event");
+
+  // ---- assemble: offsets of every tile's output, bin offsets, gather
+  uint64_t* tile_off = ensure<uint64_t>(c, B_TILEOFF, (n_tiles + 1) * 8);
+  uint64_t* scan_tmp = ensure<uint64_t>(c, B_SCANTMP, scan_tmp_words(n_tiles) * 8);
+  check(c, launch_scan_u32(s, tile_out, n_tiles, tile_off, scan_tmp), "scan");
+  uint64_t* bin_off = ensure<uint64_t>(c, B_BINOFF, ((size_t)J.n_bins + 1) * 8);
+  check(c, launch_bin_offsets(s, tile_off, d_tile_base, J.n_bins, bin_off), "bin_offsets");
+  check(c, hipMemcpyAsync(T->bin_offsets, bin_off, ((size_t)J.n_bins + 1) * 8,
+                          hipMemcpyDeviceToHost, s), "D2H");
+  check(c, hipMemcpyAsync(&h_misc, misc, sizeof(Misc), hipMemcpyDeviceToHost, s), "D2H");
+  check(c, hipStreamSynchronize(s), "sync");
+  const uint64_t n_out = T->bin_offsets[J.n_bins];
+  st.n_out = n_out;
+  st.n_distinct = h_misc.distinct;
+  T->n = n_out;
+  uint64_t* out_k;
+  uint32_t* out_c;
+  if (T->on_device) {
+    check(c, hipMalloc(&T->keys, std::max<uint64_t>(1, n_out * J.kw) * 8), "hipMalloc table");
+    check(c, hipMalloc(&T->counts, std::max<uint64_t>(1, n_out) * 4), "hipMalloc table");
+    out_k = T->keys;
+    out_c = T->counts;
+  } else {
+    out_k = ensure<uint64_t>(c, B_OUTK, n_out * J.kw * 8);
+    out_c = ensure<uint32_t>(c, B_OUTC, n_out * 4);
+  }
+  check(c, launch_gather(s, kc, tiles, n_tiles, tile_off, keys, counts, out_k, out_c), "gather");
+  check(c, hipEventRecord(c->ev[5], s), "event");
+  if (!T->on_device) {
+    T->keys = static_cast<uint64_t*>(std::malloc(std::max<uint64_t>(1, n_out * J.kw) * 8));
+    T->counts = static_cast<uint32_t*>(std::malloc(std::max<uint64_t>(1, n_out) * 4));
+    if (!T->keys || !T->counts) throw Fail{KMC_ERR_OUT_OF_MEMORY};
+    if (n_out) {
+      check(c, hipMemcpyAsync(T->keys, out_k, n_out * J.kw * 8, hipMemcpyDeviceToHost, s), "D2H");
+      check(c, hipMemcpyAsync(T->counts, out_c, n_out * 4, hipMemcpyDeviceToHost, s), "D2H");
+    }
+  }
+  check(c, hipStreamSynchronize(s), "sync");
+  st.us_map = 1e3 * ev_ms(c->ev[0], c->ev[1]);
+  st.us_split = 1e3 * ev_ms(c->ev[1], c->ev[2]);
+  st.us_expand = 1e3 * ev_ms(c->ev[2], c->ev[3]);
+  st.us_sort = 1e3 * ev_ms(c->ev[3], c->ev[4]);
+  st.us_assemble = 1e3 * ev_ms(c->ev[4], c->ev[5]);
+  st.us_total = 1e3 * ev_ms(c->ev[0], c->ev[5]);
+  // algorithmic bytes: input once, 2-bit payload of every super k-mer written
+  // and read once (ceil(l/4) + 2 bytes each), keys written and read once,
+  // output written once
+  const uint64_t payload = n_rec * 2 + (n_kmers + n_rec * (J.k - 1)) / 4;
+  st.bytes_alg = J.n_bases + 8 * (J.n_reads + 1) + 2 * payload +
+                 2 * (uint64_t)(8 * J.kw) * n_kmers + (uint64_t)(8 * J.kw + 4) * n_out;
+}
+
+kmc_status guarded(kmc_ctx* c, const kmc_reads* R, const kmc_params* P, kmc_table** out) {
+  kmc_table* T = new_table();
+  if (!T) return KMC_ERR_OUT_OF_MEMORY;
+  try {
+    run_count(c, R, P, T);
+  } catch (const Fail& f) {
+    kmc_table_free(T);
+    (void)hipStreamSynchronize(c->stream);
+    return f.st;
+  } catch (const std::bad_alloc&) {
+    kmc_table_free(T);
+    c->err = "host allocation failed";
+    return KMC_ERR_OUT_OF_MEMORY;
+  }
+  *out = T;
+  return KMC_OK;
+}
+
+thread_local kmc_ctx* t_default_ctx = nullptr;
+
+}  // namespace
+
+// ------------------------------------------------------------------- ABI
+
+extern "C" {
+
+kmc_status kmc_ctx_create(int device, kmc_ctx** out) {
+  if (!out) return KMC_ERR_INVALID_ARG;
+  *out = nullptr;
+  int n = 0;
+  if (hipGetDeviceCount(&n) != hipSuccess || device < 0 || device >= n) {
+    (void)hipGetLastError();
+    return KMC_ERR_DEVICE;
+  }
+  kmc_ctx* c = new (std::nothrow) kmc_ctx();
+  if (!c) return KMC_ERR_OUT_OF_MEMORY;
+  c->device = device;
+  if (hipSetDevice(device) != hipSuccess || hipStreamCreateWithFlags(&c->stream, hipStreamNonBlocking) != hipSuccess) {
+    (void)hipGetLastError();
+    delete c;
+    return KMC_ERR_DEVICE;
+  }
+  for (auto& e : c->ev) {
+    if (hipEventCreate(&e) != hipSuccess) {
+      (void)hipGetLastError();
+      kmc_ctx_destroy(c);
+      return KMC_ERR_DEVICE;
+    }
+  }
+  *out = c;
+  return KMC_OK;
+}
+
+void kmc_ctx_destroy(kmc_ctx* c) {
+  if (!c) return;
+  (void)hipSetDevice(c->device);
+  if (c->stream) (void)hipStreamSynchronize(c->stream);
+  for (auto& b : c->buf)
+    if (b.p) (void)hipFree(b.p);
+  for (auto& e : c->ev)
+    if (e) (void)hipEventDestroy(e);
+  if (c->stream) (void)hipStreamDestroy(c->stream);
+  delete c;
+}
+
+const char* kmc_last_error(const kmc_ctx* c) { return c ? c->err.c_str() : ""; }
+
+const char* kmc_status_str(kmc_status st) {
+  switch (st) {
+    case KMC_OK: return "ok";
+    case KMC_ERR_INVALID_ARG: return "invalid argument";
+    case KMC_ERR_OUT_OF_MEMORY: return "out of memory";
+    case KMC_ERR_DEVICE: return "device error";
+    case KMC_ERR_TOO_LARGE: return "job too large";
+    case KMC_ERR_BUSY: return "busy";
+  }
+  return "unknown status";
+}
+
+kmc_status kmc_count_ex(kmc_ctx* c, const kmc_reads* reads, const kmc_params* params,
+                        void* stream, kmc_table** out) {
+  if (!out) return KMC_ERR_INVALID_ARG;
+  *out = nullptr;
+  if (!c) return KMC_ERR_INVALID_ARG;
+  c->err.clear();
+  kmc_status v = validate(reads, params);
+  if (v != KMC_OK) {
+    c->err = "argument validation failed";
+    return v;
+  }
+  if (hipSetDevice(c->device) != hipSuccess) {
+    (void)hipGetLastError();
+    return KMC_ERR_DEVICE;
+  }
+  hipStream_t saved = c->stream;
+  if (stream) c->stream = static_cast<hipStream_t>(stream);
+  kmc_status st = guarded(c, reads, params, out);
+  c->stream = saved;
+  return st;
+}
+
+kmc_status kmc_count(const kmc_reads* reads, uint32_t k, uint32_t p, uint32_t n_bins,
+                     uint32_t cutoff_min, uint32_t cutoff_max, kmc_table** out) {
+  if (!out) return KMC_ERR_INVALID_ARG;
+  *out = nullptr;
+  kmc_params P{k, p, n_bins, cutoff_min, cutoff_max, 0};
+  kmc_status v = validate(reads, &P);  // before any device work
+  if (v != KMC_OK) return v;
+  if (!t_default_ctx) {
+    kmc_status st = kmc_ctx_create(0, &t_default_ctx);
+    if (st != KMC_OK) return st;
+  }
+  return kmc_count_ex(t_default_ctx, reads, &P, nullptr, out);
+}
+
+void kmc_table_free(kmc_table* t) {
+  if (!t) return;
+  if (t->on_device) {
+    if (t->keys) (void)hipFree(t->keys);
+    if (t->counts) (void)hipFree(t->counts);
+  } else {
+    std::free(t->keys);
+    std::free(t->counts);
+  }
+  std::free(t->bin_offsets);
+  std::free(t->sig_to_bin);
+  std::free(t);
+}
+
+kmc_status kmc_debug_signatures(kmc_ctx* c, const kmc_reads* reads, uint32_t k, uint32_t p,
+                                uint32_t flags, uint32_t* sig_per_window,
+                                uint8_t* superkmer_start) {
+  if (!c || !sig_per_window) return KMC_ERR_INVALID_ARG;
+  kmc_params P{k, p, 1, 1, 1, flags & KMC_FLAG_PLAIN_MINIMIZERS};
+  kmc_status v = validate(reads, &P);
+  if (v != KMC_OK) return v;
+  if (hipSetDevice(c->device) != hipSuccess) {
+    (void)hipGetLastError();
+    return KMC_ERR_DEVICE;
+  }
+  try {
+    Job J;
+    J.k = k;
+    J.p = p;
+    J.n_bins = 1;
+    J.ci = J.cx = 1;
+    J.kw = k <= 32 ? 1 : 2;
+    J.flags = P.flags;
+    stage_reads(c, reads, J);
+    const ScanCfg C = scan_cfg(J);
+    uint32_t* sig = ensure<uint32_t>(c, B_DBG1, J.n_bases * 4);
+    uint8_t* st = ensure<uint8_t>(c, B_DBG2, J.n_bases);
+    check(c, hipMemsetAsync(sig, 0xFF, J.n_bases * 4, c->stream), "memset");
+    check(c, hipMemsetAsync(st, 0, J.n_bases, c->stream), "memset");
+    check(c, launch_debug_sigs(c->stream, J.seq, J.off, J.n_reads, J.n_bases, C, J.kw, sig, st),
+          "debug_sigs");
+    if (J.n_bases) {
+      check(c, hipMemcpyAsync(sig_per_window, sig, J.n_bases * 4, hipMemcpyDeviceToHost, c->stream), "D2H");
+      if (superkmer_start)
+        check(c, hipMemcpyAsync(superkmer_start, st, J.n_bases, hipMemcpyDeviceToHost, c->stream), "D2H");
+    }
+    check(c, hipStreamSynchronize(c->stream), "sync");
+  } catch (const Fail& f) {
+    (void)hipStreamSynchronize(c->stream);
+    return f.st;
+  }
+  return KMC_OK;
+}
+
+}  // extern "C"

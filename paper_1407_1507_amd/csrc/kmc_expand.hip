@@ -1,0 +1,297 @@
+// Sorting phase, first half: per-bin extraction of canonical k-mers from the
+// super k-mer records and their partition into tiles small enough to be
+// sorted inside one workgroup's LDS.
+//
+// Method (KMC 2, Methods, "Sketch of the algorithm"): each bin is read, every
+// k-mer of every super k-mer is extracted in canonical form (the smaller of
+// the k-mer and its reverse complement, "Minimizers of k-mers") and the keys
+// are radix sorted.  Here the most significant digit pass of that radix sort
+// runs through HBM: each bin's keys are split by their top `fine_bits` bits
+// into fine ranges, consecutive fine ranges are grouped into tiles of about
+// `tile_target` keys, and every key is written to its tile.  A tile is thus a
+// contiguous key range of one bin, and tiles of a bin are in key order.
+//
+// Record layout (written by the split kernels): forward key of the first
+// k-mer, then the remaining symbols left aligned with the k-mer count in the
+// low 8 bits.  Keys are rolled forward and reverse-complement at once.
+#include "kmc_device.h"
+#include "kmc_internal.h"
+
+namespace kmc {
+
+namespace {
+
+template <int KW> struct Rec;
+template <> struct Rec<1> {
+  uint64_t F, R, T;
+  uint32_t n;
+  __device__ void load(const uint64_t* r, uint32_t k) {
+    F = r[0];
+    T = r[1];
+    n = (uint32_t)(T & 0xFFu);
+    R = revcomp64(F, k);
+  }
+  __device__ uint64_t key() const { return F < R ? F : R; }
+  __device__ void step(uint32_t k, uint64_t kmask) {
+    const uint32_t c = (uint32_t)(T >> 62);
+    T <<= 2;
+    F = ((F << 2) | c) & kmask;
+    R = (R >> 2) | ((uint64_t)(3u - c) << (2 * k - 2));
+  }
+};
+template <> struct Rec<2> {
+  u128 F, R, T;
+  uint32_t n;
+  __device__ void load(const uint64_t* r, uint32_t k) {
+    F = ((u128)r[0] << 64) | r[1];
+    T = ((u128)r[2] << 64) | r[3];
+    n = (uint32_t)(r[3] & 0xFFu);
+    R = revcomp128(F, k);
+  }
+  __device__ u128 key() const { return F < R ? F : R; }
+  __device__ void step(uint32_t k, u128 kmask) {
+    const uint32_t c = (uint32_t)(T >> 126);
+    T <<= 2;
+    F = ((F << 2) | (u128)c) & kmask;
+    R = (R >> 2) | ((u128)(3u - c) << (2 * k - 2));
+  }
+};
+
+// top `bits` bits of a 2k-bit key
+__device__ __forceinline__ uint32_t top_bits(uint64_t key, uint32_t k, uint32_t bits) {
+  return (uint32_t)(key >> (2 * k - bits));
+}
+__device__ __forceinline__ uint32_t top_bits(u128 key, uint32_t k, uint32_t bits) {
+  return (uint32_t)(key >> (2 * k - bits));
+}
+
+// --------------------------------------------------------------- fine hist
+// One workgroup per task (a run of records of one bin); the task's keys are
+// counted per fine range in LDS, then added to the bin's global histogram.
+template <int KW>
+__global__ void __launch_bounds__(kExpandThreads)
+k_fine_hist(KeyCfg kc, const ExpandTask* __restrict__ tasks, const uint64_t* __restrict__ records,
+            uint32_t* fine_hist) {
+  typedef typename KeyOf<KW>::T K;
+  extern __shared__ uint32_t fh[];
+  const uint32_t nf = 1u << kc.fine_bits;
+  for (uint32_t i = threadIdx.x; i < nf; i += blockDim.x) fh[i] = 0;
+  __syncthreads();
+  const ExpandTask tk = tasks[blockIdx.x];
+  const K kmask = key_mask<K>(kc.k);
+  for (uint32_t r0 = 0; r0 < tk.n_rec; r0 += blockDim.x) {
+    const uint32_t r = r0 + threadIdx.x;
+    if (r < tk.n_rec) {
+      Rec<KW> rec;
+      rec.load(records + (tk.rec_begin + r) * (2 * KW), kc.k);
+      for (uint32_t i = 0;; ++i) {
+        atomicAdd(&fh[top_bits(rec.key(), kc.k, kc.fine_bits)], 1u);
+        if (i + 1 >= rec.n) break;
+        rec.step(kc.k, kmask);
+      }
+    }
+  }
+  __syncthreads();
+  uint32_t* gh = fine_hist + ((uint64_t)tk.bin << kc.fine_bits);
+  for (uint32_t i = threadIdx.x; i < nf; i += blockDim.x)
+    if (fh[i]) atomicAdd(&gh[i], fh[i]);
+}
+
+// -------------------------------------------------------------- plan tiles
+// One workgroup per bin.  Fine range r starting at key s_r (exclusive prefix
+// of the bin's histogram) goes to tile floor(s_r / tile_target); a tile thus
+// holds at most tile_target + (size of its last range) keys.  Tile indices a
+// large range jumps over stay empty (the tile array is zeroed beforehand).
+__global__ void __launch_bounds__(256)
+k_plan_tiles(KeyCfg kc, const uint32_t* __restrict__ fine_hist, const uint64_t* __restrict__ key_base,
+             const uint64_t* __restrict__ tile_base, uint16_t* tile_of_fine, Tile* tiles,
+             unsigned long long* tile_cursor) {
+  extern __shared__ uint32_t lds[];
+  const uint32_t nf = 1u << kc.fine_bits;
+  uint32_t* start = lds;              // nf + 1
+  uint32_t* first = lds + nf + 1;     // max tiles of a bin: first key of each tile
+  uint32_t* tmp = first + kMaxTilesPerBin;
+  const uint32_t b = blockIdx.x;
+  const uint32_t* h = fine_hist + ((uint64_t)b << kc.fine_bits);
+  for (uint32_t i = threadIdx.x; i < nf; i += blockDim.x) start[i] = h[i];
+  __syncthreads();
+  const uint32_t total = block_exclusive_scan(start, nf, tmp);
+  if (threadIdx.x == 0) start[nf] = total;
+  __syncthreads();
+  if (total == 0) return;  // empty bin: no tiles
+  const uint64_t kb = key_base[b], tb = tile_base[b];
+  uint16_t* tof = tile_of_fine + ((uint64_t)b << kc.fine_bits);
+  // empty ranges after the last key start at `total`: clamp them into the
+  // last tile so that t < ceil(total / tile_target) always
+  const uint32_t last = total - 1;
+  for (uint32_t r = threadIdx.x; r < nf; r += blockDim.x) {
+    const uint32_t t = min(start[r], last) / kc.tile_target;
+    tof[r] = (uint16_t)t;
+    if (r == 0 || min(start[r - 1], last) / kc.tile_target != t) first[t] = start[r];
+  }
+  __syncthreads();
+  for (uint32_t r = threadIdx.x; r < nf; r += blockDim.x) {
+    const uint32_t t = min(start[r], last) / kc.tile_target;
+    if (r == nf - 1 || min(start[r + 1], last) / kc.tile_target != t) {
+      const uint32_t end = start[r + 1];
+      Tile T;
+      T.begin = kb + first[t];
+      T.size = end - first[t];
+      T.bin = b;
+      tiles[tb + t] = T;
+      tile_cursor[tb + t] = T.begin;
+    }
+  }
+}
+
+// ---------------------------------------------------------- expand scatter
+// One workgroup per task.  Lane i walks record i's k-mers one per round; keys
+// are staged in LDS, and when the stage could overflow in the next round it is
+// flushed: keys grouped by tile, one atomic reservation per (flush, tile),
+// coalesced writes.
+template <int KW>
+__global__ void __launch_bounds__(kExpandThreads)
+k_expand_scatter(KeyCfg kc, const ExpandTask* __restrict__ tasks,
+                 const uint64_t* __restrict__ records, const uint16_t* __restrict__ tile_of_fine,
+                 const uint64_t* __restrict__ tile_base, uint32_t mt, uint32_t scap,
+                 unsigned long long* tile_cursor, uint64_t* keys) {
+  typedef typename KeyOf<KW>::T K;
+  extern __shared__ __attribute__((aligned(16))) uint64_t lds64[];
+  const uint32_t nf = 1u << kc.fine_bits;
+  // layout: stage K[scap] | delta u64[mt] | cnt u32[mt] | base u32[mt] | tof u16[nf] |
+  //         stile u16[scap] | srank u16[scap] | inv u16[scap] | num, scan tmp
+  K* stage = reinterpret_cast<K*>(lds64);
+  uint64_t* delta = reinterpret_cast<uint64_t*>(stage + scap);
+  uint32_t* cnt = reinterpret_cast<uint32_t*>(delta + mt);
+  uint32_t* base = cnt + mt;
+  uint16_t* tof = reinterpret_cast<uint16_t*>(base + mt);
+  uint16_t* stile = tof + nf;
+  uint16_t* srank = stile + scap;
+  uint16_t* inv = srank + scap;
+  uint32_t* misc = reinterpret_cast<uint32_t*>(inv + scap + (scap & 1));
+  uint32_t* num = misc;
+  uint32_t* tmp = misc + 1;
+
+  const ExpandTask tk = tasks[blockIdx.x];
+  const uint16_t* gt = tile_of_fine + ((uint64_t)tk.bin << kc.fine_bits);
+  for (uint32_t i = threadIdx.x; i < nf; i += blockDim.x) tof[i] = gt[i];
+  for (uint32_t i = threadIdx.x; i < mt; i += blockDim.x) cnt[i] = 0;
+  if (threadIdx.x == 0) *num = 0;
+  const uint64_t tb = tile_base[tk.bin];
+  const K kmask = key_mask<K>(kc.k);
+
+  Rec<KW> rec;
+  const bool active = threadIdx.x < tk.n_rec;
+  rec.n = 0;
+  if (active) rec.load(records + (tk.rec_begin + threadIdx.x) * (2 * KW), kc.k);
+  __syncthreads();
+
+  for (uint32_t round = 0;; ++round) {
+    // flush when the next round might not fit, or when all records are done
+    const uint32_t staged = *num;
+    // any lane still has k-mers?
+    const bool more = __syncthreads_or(active && round < rec.n);
+    if (staged + blockDim.x > scap || !more) {
+      const uint32_t nst = staged;
+      for (uint32_t i = threadIdx.x; i < mt; i += blockDim.x) base[i] = cnt[i];
+      __syncthreads();
+      block_exclusive_scan(base, mt, tmp);
+      for (uint32_t i = threadIdx.x; i < mt; i += blockDim.x) {
+        if (cnt[i]) {
+          const uint64_t g = atomicAdd(&tile_cursor[tb + i], (unsigned long long)cnt[i]);
+          delta[i] = g - base[i];
+        }
+      }
+      for (uint32_t i = threadIdx.x; i < nst; i += blockDim.x)
+        inv[base[stile[i]] + srank[i]] = (uint16_t)i;
+      __syncthreads();
+      for (uint32_t q = threadIdx.x; q < nst; q += blockDim.x) {
+        const uint32_t i = inv[q];
+        const uint64_t g = delta[stile[i]] + q;
+        if (KW == 1) {
+          keys[g] = (uint64_t)stage[i];
+        } else {
+          keys[2 * g] = (uint64_t)((u128)stage[i] >> 64);
+          keys[2 * g + 1] = (uint64_t)stage[i];
+        }
+      }
+      __syncthreads();
+      for (uint32_t i = threadIdx.x; i < mt; i += blockDim.x) cnt[i] = 0;
+      if (threadIdx.x == 0) *num = 0;
+      __syncthreads();
+    }
+    if (!more) break;
+    if (active && round < rec.n) {
+      if (round) rec.step(kc.k, kmask);
+      const K key = rec.key();
+      const uint32_t t = tof[top_bits(key, kc.k, kc.fine_bits)];
+      const uint32_t idx = atomicAdd(num, 1u);
+      srank[idx] = (uint16_t)atomicAdd(&cnt[t], 1u);
+      stile[idx] = (uint16_t)t;
+      stage[idx] = key;
+    }
+    __syncthreads();
+  }
+}
+
+}  // namespace
+
+static size_t expand_lds(uint32_t key_words, uint32_t mt, uint32_t nf, uint32_t scap) {
+  return (size_t)scap * 8 * key_words + (size_t)mt * 16 + (size_t)nf * 2 + (size_t)scap * 6 + 8 +
+         4 + 4 * (kExpandThreads / 64) + 16;
+}
+
+hipError_t launch_fine_hist(hipStream_t s, const KeyCfg& kc, const ExpandTask* tasks,
+                            uint32_t n_tasks, const uint64_t* records, uint32_t* fine_hist) {
+  if (n_tasks == 0) return hipSuccess;
+  const size_t sh = ((size_t)1 << kc.fine_bits) * 4;
+  if (kc.key_words == 1)
+    hipLaunchKernelGGL(k_fine_hist<1>, dim3(n_tasks), dim3(kExpandThreads), sh, s, kc, tasks,
+                       records, fine_hist);
+  else
+    hipLaunchKernelGGL(k_fine_hist<2>, dim3(n_tasks), dim3(kExpandThreads), sh, s, kc, tasks,
+                       records, fine_hist);
+  return hipGetLastError();
+}
+
+hipError_t launch_plan_tiles(hipStream_t s, const KeyCfg& kc, const uint32_t* fine_hist,
+                             const uint64_t* key_base, const uint64_t* tile_base,
+                             uint16_t* tile_of_fine, Tile* tiles,
+                             unsigned long long* tile_cursor) {
+  const uint32_t nf = 1u << kc.fine_bits;
+  const size_t sh = ((size_t)nf + 1 + kMaxTilesPerBin + 8) * 4;
+  hipLaunchKernelGGL(k_plan_tiles, dim3(kc.n_bins), dim3(256), sh, s, kc, fine_hist, key_base,
+                     tile_base, tile_of_fine, tiles, tile_cursor);
+  return hipGetLastError();
+}
+
+hipError_t launch_expand_scatter(hipStream_t s, const KeyCfg& kc, const ExpandTask* tasks,
+                                 uint32_t n_tasks, const uint64_t* records,
+                                 const uint16_t* tile_of_fine, const uint64_t* tile_base,
+                                 uint32_t max_tiles_per_bin,
+                                 unsigned long long* tile_cursor, uint64_t* keys) {
+  if (n_tasks == 0) return hipSuccess;
+  const uint32_t nf = 1u << kc.fine_bits;
+  const uint32_t scap = kc.key_words == 1 ? kExpandStage1 : kExpandStage2;
+  const uint32_t mt = max_tiles_per_bin < 1 ? 1 : max_tiles_per_bin;
+  const size_t sh = expand_lds(kc.key_words, mt, nf, scap);
+  if (kc.key_words == 1) {
+    (void)hipFuncSetAttribute((const void*)k_expand_scatter<1>,
+                        hipFuncAttributeMaxDynamicSharedMemorySize, (int)sh);
+    hipLaunchKernelGGL(k_expand_scatter<1>, dim3(n_tasks), dim3(kExpandThreads), sh, s, kc,
+                       tasks, records, tile_of_fine, tile_base, mt, scap, tile_cursor, keys);
+  } else {
+    (void)hipFuncSetAttribute((const void*)k_expand_scatter<2>,
+                        hipFuncAttributeMaxDynamicSharedMemorySize, (int)sh);
+    hipLaunchKernelGGL(k_expand_scatter<2>, dim3(n_tasks), dim3(kExpandThreads), sh, s, kc,
+                       tasks, records, tile_of_fine, tile_base, mt, scap, tile_cursor, keys);
+  }
+  return hipGetLastError();
+}
+
+size_t expand_scatter_lds_bytes(uint32_t key_words, uint32_t mt, uint32_t fine_bits) {
+  return expand_lds(key_words, mt, 1u << fine_bits,
+                    key_words == 1 ? kExpandStage1 : kExpandStage2);
+}
+
+}  // namespace kmc

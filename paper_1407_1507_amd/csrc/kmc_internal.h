@@ -1,0 +1,142 @@
+// Internal declarations shared by the kernels and the host runtime of
+// libkmc_hip.so.  Not part of the public ABI (include/kmc.h is).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace kmc {
+
+// Sizes of the work units.
+constexpr int kScanThreads = 256;        // one read per thread in the split kernels
+constexpr int kStageCap1 = 2048;         // super k-mer records staged per split WG (1-word keys)
+constexpr int kStageCap2 = 1024;         // same, 2-word keys
+constexpr int kLdsBinsMax = 4096;        // bins counted in LDS; more bins use global atomics
+constexpr int kExpandThreads = 256;      // records per expansion task (one per thread)
+constexpr int kExpandStage1 = 4096;      // keys staged per expansion flush (1-word keys)
+constexpr int kExpandStage2 = 2048;      // same, 2-word keys
+constexpr int kSortThreads = 256;        // threads of a tile-sort workgroup
+constexpr int kTileCap1 = 4096;          // keys of one LDS tile (1-word keys)
+constexpr int kTileCap2 = 2048;          // same, 2-word keys
+constexpr int kMaxFineBits = 12;         // fine ranges per bin: at most 2^12
+constexpr int kMaxTilesPerBin = 4096;
+
+// Parameters of the split (signature scan) kernels.
+struct ScanCfg {
+  uint32_t k, p, w;      // w = k - p + 1: most k-mers in one super k-mer
+  uint32_t filter;       // 1: signatures (AAA/ACA/AA filter), 0: plain minimizers
+  uint32_t pmask;        // 2p low bits
+  uint32_t sent;         // 4^p: signature of a k-mer with no allowed p-mer
+  uint32_t n_bins;
+  uint32_t aligned4;     // seq is 4-byte aligned: fetch whole words
+};
+
+// One expansion task: records [rec_begin, rec_end) of bin `bin`.
+struct ExpandTask {
+  uint64_t rec_begin;
+  uint32_t n_rec;
+  uint32_t bin;
+};
+
+// One sort tile: keys [begin, begin + size) of the key buffer.
+struct Tile {
+  uint64_t begin;
+  uint32_t size;
+  uint32_t bin;
+};
+
+// ---------------------------------------------------------------- launchers
+// All launchers enqueue on `s` and return the launch status.
+
+// Histogram of signatures, weighted by k-mers, over reads r with r % stride == 0.
+hipError_t launch_sig_hist(hipStream_t s, const uint8_t* seq, const uint64_t* offsets,
+                           uint64_t n_reads, uint64_t n_bases, uint64_t stride,
+                           const ScanCfg& cfg, uint32_t key_words, uint32_t* hist,
+                           unsigned long long* sample_kmers);
+
+// Per-bin records and k-mers (atomically added into rec_cnt / kmer_cnt).
+hipError_t launch_split_count(hipStream_t s, const uint8_t* seq, const uint64_t* offsets,
+                              uint64_t n_reads, uint64_t n_bases, const ScanCfg& cfg,
+                              uint32_t key_words, const uint32_t* sig_to_bin,
+                              unsigned long long* rec_cnt, unsigned long long* kmer_cnt);
+
+// Write every super k-mer record into its bin; cursor[b] starts at the bin's
+// first record slot and is advanced atomically.
+hipError_t launch_split_scatter(hipStream_t s, const uint8_t* seq, const uint64_t* offsets,
+                                uint64_t n_reads, uint64_t n_bases, const ScanCfg& cfg,
+                                uint32_t key_words, const uint32_t* sig_to_bin,
+                                unsigned long long* cursor, uint64_t* records);
+
+// Per-window signature and super k-mer starts (audit).
+hipError_t launch_debug_sigs(hipStream_t s, const uint8_t* seq, const uint64_t* offsets,
+                             uint64_t n_reads, uint64_t n_bases, const ScanCfg& cfg,
+                             uint32_t key_words, uint32_t* sig, uint8_t* start);
+
+// Parameters of the expansion / sort kernels.
+struct KeyCfg {
+  uint32_t k;
+  uint32_t key_words;
+  uint32_t fine_bits;   // fine ranges per bin = 2^fine_bits (top bits of the key)
+  uint32_t tile_target; // tiles are planned to hold about this many keys
+  uint32_t tile_cap;    // keys one LDS tile can hold
+  uint32_t n_bins;
+  uint32_t cutoff_min, cutoff_max;
+};
+
+// Fine-range histogram of every bin: fine_hist[bin << fine_bits | range].
+hipError_t launch_fine_hist(hipStream_t s, const KeyCfg& kc, const ExpandTask* tasks,
+                            uint32_t n_tasks, const uint64_t* records, uint32_t* fine_hist);
+
+// Per bin: fine ranges -> tiles.  Writes tile_of_fine (local tile id per
+// range), tiles[tile_base[b] + t] and fills cursors with each tile's start.
+hipError_t launch_plan_tiles(hipStream_t s, const KeyCfg& kc, const uint32_t* fine_hist,
+                             const uint64_t* key_base, const uint64_t* tile_base,
+                             uint16_t* tile_of_fine, Tile* tiles,
+                             unsigned long long* tile_cursor);
+
+// Expand every record into canonical keys and scatter them into their tiles.
+hipError_t launch_expand_scatter(hipStream_t s, const KeyCfg& kc, const ExpandTask* tasks,
+                                 uint32_t n_tasks, const uint64_t* records,
+                                 const uint16_t* tile_of_fine, const uint64_t* tile_base,
+                                 uint32_t max_tiles_per_bin,
+                                 unsigned long long* tile_cursor, uint64_t* keys);
+
+// Sort + count every tile that fits LDS; tiles larger than tile_cap are
+// appended to big_list.  Output of a tile is written over its own keys
+// (out_counts at the same indices); tile_out[t] = entries kept, and
+// distinct[0] += distinct keys.
+// n_big[0] counts the big tiles, n_big[1] receives the largest big tile size.
+hipError_t launch_tile_sort(hipStream_t s, const KeyCfg& kc, const Tile* tiles,
+                            uint64_t n_tiles, uint64_t* keys, uint32_t* out_counts,
+                            uint32_t* tile_out, uint32_t* big_list, uint32_t* n_big,
+                            unsigned long long* distinct);
+
+// Sort + count the big tiles (MSD partition through HBM, tmp has room for the
+// largest big tile).
+hipError_t launch_big_tiles(hipStream_t s, const KeyCfg& kc, const Tile* tiles,
+                            const uint32_t* big_list, uint32_t n_big, uint64_t* keys,
+                            uint64_t* tmp, uint32_t* out_counts, uint32_t* tile_out,
+                            unsigned long long* distinct);
+
+// Exclusive scan of n uint32 into uint64 (out has n + 1 entries: out[n] = total).
+hipError_t launch_scan_u32(hipStream_t s, const uint32_t* in, uint64_t n, uint64_t* out,
+                           uint64_t* block_tmp);
+uint64_t scan_tmp_words(uint64_t n);
+
+// Copy every tile's kept entries to out_keys/out_counts at tile_off[t].
+hipError_t launch_gather(hipStream_t s, const KeyCfg& kc, const Tile* tiles, uint64_t n_tiles,
+                         const uint64_t* tile_off, const uint64_t* keys,
+                         const uint32_t* counts, uint64_t* out_keys, uint32_t* out_counts);
+
+// out[b] = tile_off[tile_base[b]] for b in [0, n_bins] (first output entry of each bin).
+hipError_t launch_bin_offsets(hipStream_t s, const uint64_t* tile_off, const uint64_t* tile_base,
+                              uint32_t n_bins, uint64_t* out);
+
+size_t expand_scatter_lds_bytes(uint32_t key_words, uint32_t mt, uint32_t fine_bits);
+
+// Validate a device offsets array: err[0] |= 1 if offsets[0] != 0, not
+// non-decreasing, or offsets[n_reads] != n_bases.
+hipError_t launch_check_offsets(hipStream_t s, const uint64_t* offsets, uint64_t n_reads,
+                                uint64_t n_bases, uint32_t* err);
+
+}  // namespace kmc

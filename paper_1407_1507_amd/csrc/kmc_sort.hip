@@ -1,0 +1,557 @@
+// Sorting phase, second half: sort every tile of keys in LDS, count runs of
+// equal keys, apply the cutoffs and compact the kept (key, count) pairs; then
+// assemble the per-tile outputs into one table.
+//
+// Method (KMC 2, Methods, "Sketch of the algorithm" and "Additional
+// features"): the extracted k-mers of a bin are radix sorted; equal keys are
+// then adjacent and their run length is the k-mer's count; a k-mer is written
+// only if cutoff_min <= count <= cutoff_max, decided here where the total
+// count is known.
+//
+// Tile sort (one workgroup per tile, keys held in LDS): the keys of a tile
+// share their leading bits; one most-significant-digit counting pass on the
+// next DIG bits (LDS histogram, scan, scatter with atomic slot claims) puts
+// them into 2^DIG buckets of about one distinct key each, which are then
+// finished by insertion sort (a lane per bucket) or, for the rare large
+// bucket, by a workgroup-wide rank sort.  An MSD pass needs no stable
+// ranking, which a 64-wide wave has no cheap primitive for.  Tiles larger
+// than LDS take the same MSD passes through HBM (8-bit digits, recursive)
+// until their pieces fit.
+#include "kmc_device.h"
+#include "kmc_internal.h"
+
+namespace kmc {
+
+namespace {
+
+template <int KW> struct SortCfg;
+template <> struct SortCfg<1> {
+  static constexpr uint32_t CAP = kTileCap1, DIG = 12, ITEMS = kTileCap1 / kSortThreads;
+};
+template <> struct SortCfg<2> {
+  static constexpr uint32_t CAP = kTileCap2, DIG = 11, ITEMS = kTileCap2 / kSortThreads;
+};
+constexpr uint32_t kInsMax = 24;    // buckets up to this size: insertion sort by one lane
+constexpr uint32_t kBigMax = 256;   // large buckets listed per tile (CAP / kInsMax < 256)
+
+__device__ __forceinline__ uint64_t load_key(const uint64_t* p, uint64_t i, uint64_t*) { return p[i]; }
+__device__ __forceinline__ u128 load_key(const uint64_t* p, uint64_t i, u128*) {
+  return ((u128)p[2 * i] << 64) | p[2 * i + 1];
+}
+__device__ __forceinline__ void store_key(uint64_t* p, uint64_t i, uint64_t v) { p[i] = v; }
+__device__ __forceinline__ void store_key(uint64_t* p, uint64_t i, u128 v) {
+  p[2 * i] = (uint64_t)(v >> 64);
+  p[2 * i + 1] = (uint64_t)v;
+}
+
+__device__ __forceinline__ uint64_t wave_and(uint64_t v) {
+  for (int d = 32; d >= 1; d >>= 1) v &= __shfl_xor(v, d, 64);
+  return v;
+}
+__device__ __forceinline__ uint64_t wave_or(uint64_t v) {
+  for (int d = 32; d >= 1; d >>= 1) v |= __shfl_xor(v, d, 64);
+  return v;
+}
+
+// Block-wide AND and OR of per-thread values (identity for threads with no
+// key: all ones / zero).  red needs 4 * (blockDim.x / 64) u64 words.
+template <class K>
+__device__ void block_and_or(K& a, K& o, uint64_t* red) {
+  const uint32_t lane = threadIdx.x & 63u, wid = threadIdx.x >> 6, nw = blockDim.x >> 6;
+  uint64_t a0 = wave_and((uint64_t)a), o0 = wave_or((uint64_t)o);
+  uint64_t a1 = 0, o1 = 0;
+  if (sizeof(K) == 16) {
+    a1 = wave_and((uint64_t)((u128)a >> 64));
+    o1 = wave_or((uint64_t)((u128)o >> 64));
+  }
+  if (lane == 0) {
+    red[wid] = a0;
+    red[nw + wid] = o0;
+    red[2 * nw + wid] = a1;
+    red[3 * nw + wid] = o1;
+  }
+  __syncthreads();
+  a0 = ~0ull; o0 = 0; a1 = ~0ull; o1 = 0;
+  for (uint32_t w = 0; w < nw; ++w) {
+    a0 &= red[w];
+    o0 |= red[nw + w];
+    a1 &= red[2 * nw + w];
+    o1 |= red[3 * nw + w];
+  }
+  __syncthreads();
+  if (sizeof(K) == 16) {
+    a = (K)(((u128)a1 << 64) | a0);
+    o = (K)(((u128)o1 << 64) | o0);
+  } else {
+    a = (K)a0;
+    o = (K)o0;
+  }
+}
+
+__device__ __forceinline__ uint32_t high_bit(uint64_t x) { return 63u - __clzll(x); }
+__device__ __forceinline__ uint32_t high_bit(u128 x) {
+  const uint64_t hi = (uint64_t)(x >> 64);
+  return hi ? 127u - __clzll(hi) : 63u - __clzll((uint64_t)x);
+}
+
+// LDS carve-up of the tile sort.
+template <int KW>
+struct SortShared {
+  typedef typename KeyOf<KW>::T K;
+  K A[SortCfg<KW>::CAP];
+  uint32_t H[(1u << SortCfg<KW>::DIG) > SortCfg<KW>::CAP ? (1u << SortCfg<KW>::DIG) + 1
+                                                          : SortCfg<KW>::CAP + 1];
+  uint64_t red[4 * kSortThreads / 64];
+  uint32_t tmp[kSortThreads / 64];
+  uint32_t big[kBigMax];
+  uint32_t nbig;
+};
+
+// Sort n <= CAP keys from src (global), count runs, apply cutoffs, write the
+// kept pairs to out_keys[0..kept) / out_counts[0..kept).  src and out_keys may
+// be the same memory: every key is read before anything is written.  Returns
+// kept; *distinct receives the number of distinct keys.  All threads call it.
+template <int KW>
+__device__ uint32_t sort_count_emit(const uint64_t* src, uint32_t n, uint64_t* out_keys,
+                                    uint32_t* out_counts, uint32_t ci, uint32_t cx,
+                                    SortShared<KW>& S, uint32_t* distinct) {
+  typedef typename KeyOf<KW>::T K;
+  constexpr uint32_t ITEMS = SortCfg<KW>::ITEMS, DIG = SortCfg<KW>::DIG;
+  const uint32_t tid = threadIdx.x, nt = blockDim.x;
+  K key[ITEMS];
+  K a = ~K(0), o = 0;
+#pragma unroll
+  for (uint32_t m = 0; m < ITEMS; ++m) {
+    const uint32_t i = m * nt + tid;
+    if (i < n) {
+      key[m] = load_key(src, i, (K*)nullptr);
+      a &= key[m];
+      o |= key[m];
+    }
+  }
+  block_and_or<K>(a, o, S.red);
+  const K diff = a ^ o;
+  if (diff == 0) {
+    // every key equal: one run of length n
+    if (tid == 0 && n >= ci && n <= cx) {
+      store_key(out_keys, 0, a);
+      out_counts[0] = n;
+    }
+    *distinct = 1;
+    return (n >= ci && n <= cx) ? 1u : 0u;
+  }
+  const uint32_t hb = high_bit(diff);
+  const uint32_t t = hb + 1 < DIG ? hb + 1 : DIG;
+  const uint32_t shift = hb + 1 - t;
+  const uint32_t nb = 1u << t, dmask = nb - 1;
+
+  // counting pass on the digit below the common prefix
+  for (uint32_t i = tid; i < nb; i += nt) S.H[i] = 0;
+  if (tid == 0) S.nbig = 0;
+  __syncthreads();
+#pragma unroll
+  for (uint32_t m = 0; m < ITEMS; ++m)
+    if (m * nt + tid < n) atomicAdd(&S.H[(uint32_t)(key[m] >> shift) & dmask], 1u);
+  __syncthreads();
+  block_exclusive_scan(S.H, nb, S.tmp);
+#pragma unroll
+  for (uint32_t m = 0; m < ITEMS; ++m)
+    if (m * nt + tid < n) S.A[atomicAdd(&S.H[(uint32_t)(key[m] >> shift) & dmask], 1u)] = key[m];
+  __syncthreads();
+  // H[d] is now the end of bucket d; finish each bucket
+  const uint32_t per = (nb + nt - 1) / nt;
+  for (uint32_t d = tid * per; d < min(nb, (tid + 1) * per); ++d) {
+    const uint32_t s = d ? S.H[d - 1] : 0, e = S.H[d];
+    if (e - s <= 1) continue;
+    if (e - s <= kInsMax) {
+      for (uint32_t i = s + 1; i < e; ++i) {
+        const K x = S.A[i];
+        uint32_t j = i;
+        while (j > s && S.A[j - 1] > x) {
+          S.A[j] = S.A[j - 1];
+          --j;
+        }
+        S.A[j] = x;
+      }
+    } else {
+      S.big[atomicAdd(&S.nbig, 1u)] = d;
+    }
+  }
+  __syncthreads();
+  const uint32_t nbig = S.nbig;
+  for (uint32_t bb = 0; bb < nbig; ++bb) {
+    const uint32_t d = S.big[bb];
+    const uint32_t s = d ? S.H[d - 1] : 0, e = S.H[d];
+    K v[ITEMS];
+    uint32_t rk[ITEMS];
+#pragma unroll
+    for (uint32_t m = 0; m < ITEMS; ++m) {
+      const uint32_t i = s + m * nt + tid;
+      if (i < e) {
+        const K x = S.A[i];
+        uint32_t r = 0;
+        for (uint32_t j = s; j < e; ++j) {
+          const K y = S.A[j];
+          r += (y < x) || (y == x && j < i);
+        }
+        v[m] = x;
+        rk[m] = r;
+      }
+    }
+    __syncthreads();
+#pragma unroll
+    for (uint32_t m = 0; m < ITEMS; ++m)
+      if (s + m * nt + tid < e) S.A[s + rk[m]] = v[m];
+    __syncthreads();
+  }
+  // run heads: positions i with A[i] != A[i-1]; each lane owns a chunk
+  const uint32_t per2 = (n + nt - 1) / nt;
+  const uint32_t b0 = min(n, tid * per2), b1 = min(n, b0 + per2);
+  uint32_t nh = 0;
+  for (uint32_t i = b0; i < b1; ++i) nh += (i == 0 || S.A[i] != S.A[i - 1]);
+  uint32_t H_total;
+  uint32_t h = block_scan_one(nh, S.tmp, H_total);
+  // head positions overwrite the bucket ends (no longer needed)
+  for (uint32_t i = b0; i < b1; ++i)
+    if (i == 0 || S.A[i] != S.A[i - 1]) S.H[h++] = i;
+  if (tid == 0) S.H[H_total] = n;
+  __syncthreads();
+  // counts, cutoffs and compaction of the kept runs
+  const uint32_t per3 = (H_total + nt - 1) / nt;
+  const uint32_t h0 = min(H_total, tid * per3), h1 = min(H_total, h0 + per3);
+  uint32_t nk = 0;
+  for (uint32_t q = h0; q < h1; ++q) {
+    const uint32_t c = S.H[q + 1] - S.H[q];
+    nk += (c >= ci && c <= cx);
+  }
+  uint32_t kept;
+  uint32_t o2 = block_scan_one(nk, S.tmp, kept);
+  for (uint32_t q = h0; q < h1; ++q) {
+    const uint32_t c = S.H[q + 1] - S.H[q];
+    if (c >= ci && c <= cx) {
+      store_key(out_keys, o2, S.A[S.H[q]]);
+      out_counts[o2] = c;
+      ++o2;
+    }
+  }
+  __syncthreads();
+  *distinct = H_total;
+  return kept;
+}
+
+template <int KW>
+__global__ void __launch_bounds__(kSortThreads)
+k_tile_sort(KeyCfg kc, const Tile* __restrict__ tiles, uint64_t* keys, uint32_t* counts,
+            uint32_t* tile_out, uint32_t* big_list, uint32_t* n_big, uint32_t* max_big,
+            unsigned long long* distinct) {
+  __shared__ SortShared<KW> S;
+  const uint64_t t = blockIdx.x;
+  const Tile T = tiles[t];
+  if (T.size == 0) {
+    if (threadIdx.x == 0) tile_out[t] = 0;
+    return;
+  }
+  if (T.size > SortCfg<KW>::CAP) {
+    if (threadIdx.x == 0) {
+      tile_out[t] = 0;
+      big_list[atomicAdd(n_big, 1u)] = (uint32_t)t;
+      atomicMax(max_big, T.size);
+    }
+    return;
+  }
+  uint32_t d;
+  const uint32_t kept = sort_count_emit<KW>(keys + T.begin * KW, T.size, keys + T.begin * KW,
+                                            counts + T.begin, kc.cutoff_min, kc.cutoff_max, S, &d);
+  if (threadIdx.x == 0) {
+    tile_out[t] = kept;
+    atomicAdd(distinct, (unsigned long long)d);
+  }
+}
+
+// ------------------------------------------------------------- big tiles
+// One workgroup per tile larger than LDS.  Depth-first over MSD pieces: a
+// piece that fits LDS is sorted and emitted; a piece whose keys are all equal
+// is one run; any other piece is partitioned on the 8 bits below its common
+// prefix into the other buffer (same offsets) and its children are visited in
+// key order, so the output stays in ascending order.  Output is written over
+// the tile's own keys at a cursor that never passes the piece being read.
+struct Level {
+  uint64_t base;
+  uint32_t next, nchild, buf, pad;
+  uint32_t cs[257];
+};
+template <int KW> struct MaxLevels { static constexpr int N = KW == 1 ? 10 : 18; };
+
+template <int KW>
+__global__ void __launch_bounds__(kSortThreads)
+k_big_tiles(KeyCfg kc, const Tile* __restrict__ tiles, const uint32_t* __restrict__ big_list,
+            uint64_t* keys, uint64_t* tmp, uint32_t* counts, uint32_t* tile_out,
+            unsigned long long* distinct) {
+  typedef typename KeyOf<KW>::T K;
+  __shared__ SortShared<KW> S;
+  __shared__ Level L[MaxLevels<KW>::N];
+  __shared__ uint32_t cur[256];
+  __shared__ unsigned long long outc, dist;
+  const uint32_t tid = threadIdx.x, nt = blockDim.x;
+  const uint32_t t = big_list[blockIdx.x];
+  const Tile T = tiles[t];
+  uint64_t* bufs[2] = {keys + T.begin * KW, tmp};
+  if (tid == 0) {
+    L[0].base = 0;
+    L[0].next = 0;
+    L[0].nchild = 1;
+    L[0].buf = 0;
+    L[0].cs[0] = 0;
+    L[0].cs[1] = T.size;
+    outc = 0;
+    dist = 0;
+  }
+  __syncthreads();
+  int depth = 0;
+  while (depth >= 0) {
+    const uint32_t c = L[depth].next, nch = L[depth].nchild;
+    __syncthreads();
+    if (c == nch) {
+      --depth;
+      continue;
+    }
+    if (tid == 0) L[depth].next = c + 1;
+    const uint64_t off = L[depth].base + L[depth].cs[c];
+    const uint32_t n = L[depth].cs[c + 1] - L[depth].cs[c];
+    const uint32_t buf = L[depth].buf;
+    const uint64_t* src = bufs[buf] + off * KW;
+    __syncthreads();
+    if (n == 0) continue;
+    const unsigned long long oc = outc;
+    if (n <= SortCfg<KW>::CAP) {
+      uint32_t d;
+      const uint32_t kept = sort_count_emit<KW>(src, n, keys + (T.begin + oc) * KW,
+                                                counts + T.begin + oc, kc.cutoff_min,
+                                                kc.cutoff_max, S, &d);
+      if (tid == 0) {
+        outc = oc + kept;
+        dist += d;
+      }
+      __syncthreads();
+      continue;
+    }
+    K a = ~K(0), o = 0;
+    for (uint32_t i = tid; i < n; i += nt) {
+      const K x = load_key(src, i, (K*)nullptr);
+      a &= x;
+      o |= x;
+    }
+    block_and_or<K>(a, o, S.red);
+    const K diff = a ^ o;
+    if (diff == 0) {
+      if (tid == 0) {
+        if (n >= kc.cutoff_min && n <= kc.cutoff_max) {
+          store_key(keys, T.begin + oc, a);
+          counts[T.begin + oc] = n;
+          outc = oc + 1;
+        }
+        dist += 1;
+      }
+      __syncthreads();
+      continue;
+    }
+    const uint32_t hb = high_bit(diff);
+    const uint32_t bits = hb + 1 < 8 ? hb + 1 : 8;
+    const uint32_t shift = hb + 1 - bits;
+    const uint32_t nb = 1u << bits, dmask = nb - 1;
+    for (uint32_t i = tid; i < 256; i += nt) cur[i] = 0;
+    __syncthreads();
+    for (uint32_t i = tid; i < n; i += nt)
+      atomicAdd(&cur[(uint32_t)(load_key(src, i, (K*)nullptr) >> shift) & dmask], 1u);
+    __syncthreads();
+    const uint32_t total = block_exclusive_scan(cur, nb, S.tmp);
+    const int nd = depth + 1;
+    for (uint32_t i = tid; i < nb; i += nt) L[nd].cs[i] = cur[i];
+    if (tid == 0) {
+      L[nd].cs[nb] = total;
+      L[nd].base = off;
+      L[nd].next = 0;
+      L[nd].nchild = nb;
+      L[nd].buf = 1 - buf;
+    }
+    __syncthreads();
+    uint64_t* dst = bufs[1 - buf] + off * KW;
+    for (uint32_t i = tid; i < n; i += nt) {
+      const K x = load_key(src, i, (K*)nullptr);
+      store_key(dst, atomicAdd(&cur[(uint32_t)(x >> shift) & dmask], 1u), x);
+    }
+    __threadfence();
+    __syncthreads();
+    depth = nd;
+  }
+  if (tid == 0) {
+    tile_out[t] = (uint32_t)outc;
+    atomicAdd(distinct, dist);
+  }
+}
+
+// ---------------------------------------------------------------- scans
+constexpr uint32_t kScanChunk = 4096;  // elements per block (256 threads x 16)
+
+__global__ void __launch_bounds__(256)
+k_scan_reduce(const uint32_t* __restrict__ in, uint64_t n, uint64_t* bsum) {
+  __shared__ uint64_t red[4];
+  const uint64_t b0 = (uint64_t)blockIdx.x * kScanChunk;
+  uint64_t s = 0;
+  for (uint32_t i = threadIdx.x; i < kScanChunk; i += 256)
+    if (b0 + i < n) s += in[b0 + i];
+  for (int d = 32; d >= 1; d >>= 1) s += __shfl_xor(s, d, 64);
+  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = s;
+  __syncthreads();
+  if (threadIdx.x == 0) bsum[blockIdx.x] = red[0] + red[1] + red[2] + red[3];
+}
+
+// one workgroup: exclusive scan of bsum[0..nb) in place, total to out[n]
+__global__ void __launch_bounds__(256)
+k_scan_bsum(uint64_t* bsum, uint64_t nb, uint64_t* out, uint64_t n) {
+  __shared__ uint64_t wsum[4];
+  __shared__ uint64_t carry;
+  if (threadIdx.x == 0) carry = 0;
+  __syncthreads();
+  const uint32_t lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+  for (uint64_t c0 = 0; c0 < nb; c0 += 256) {
+    const uint64_t i = c0 + threadIdx.x;
+    const uint64_t v = i < nb ? bsum[i] : 0;
+    uint64_t x = v;
+    for (int d = 1; d < 64; d <<= 1) {
+      uint64_t y = __shfl_up(x, d, 64);
+      if (lane >= (uint32_t)d) x += y;
+    }
+    if (lane == 63) wsum[wid] = x;
+    __syncthreads();
+    uint64_t off = carry;
+    for (uint32_t w = 0; w < wid; ++w) off += wsum[w];
+    if (i < nb) bsum[i] = off + x - v;
+    __syncthreads();
+    if (threadIdx.x == 0) carry += wsum[0] + wsum[1] + wsum[2] + wsum[3];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) out[n] = carry;
+}
+
+__global__ void __launch_bounds__(256)
+k_scan_apply(const uint32_t* __restrict__ in, uint64_t n, const uint64_t* __restrict__ bsum,
+             uint64_t* out) {
+  __shared__ uint64_t wsum[4];
+  const uint64_t b0 = (uint64_t)blockIdx.x * kScanChunk + (uint64_t)threadIdx.x * 16;
+  uint32_t v[16];
+  uint64_t s = 0;
+#pragma unroll
+  for (int q = 0; q < 16; ++q) {
+    v[q] = (b0 + q < n) ? in[b0 + q] : 0u;
+    s += v[q];
+  }
+  const uint32_t lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+  uint64_t x = s;
+  for (int d = 1; d < 64; d <<= 1) {
+    uint64_t y = __shfl_up(x, d, 64);
+    if (lane >= (uint32_t)d) x += y;
+  }
+  if (lane == 63) wsum[wid] = x;
+  __syncthreads();
+  uint64_t run = bsum[blockIdx.x] + x - s;
+  for (uint32_t w = 0; w < wid; ++w) run += wsum[w];
+#pragma unroll
+  for (int q = 0; q < 16; ++q) {
+    if (b0 + q < n) out[b0 + q] = run;
+    run += v[q];
+  }
+}
+
+// ---------------------------------------------------------------- gather
+template <int KW>
+__global__ void __launch_bounds__(256)
+k_gather(const Tile* __restrict__ tiles, const uint64_t* __restrict__ tile_off,
+         const uint64_t* __restrict__ keys, const uint32_t* __restrict__ counts,
+         uint64_t* out_keys, uint32_t* out_counts) {
+  const uint64_t t = blockIdx.x;
+  const uint64_t o = tile_off[t], m = tile_off[t + 1] - o;
+  if (m == 0) return;
+  const uint64_t b = tiles[t].begin;
+  for (uint64_t i = threadIdx.x; i < m * KW; i += blockDim.x) out_keys[o * KW + i] = keys[b * KW + i];
+  for (uint64_t i = threadIdx.x; i < m; i += blockDim.x) out_counts[o + i] = counts[b + i];
+}
+
+}  // namespace
+
+hipError_t launch_tile_sort(hipStream_t s, const KeyCfg& kc, const Tile* tiles,
+                            uint64_t n_tiles, uint64_t* keys, uint32_t* out_counts,
+                            uint32_t* tile_out, uint32_t* big_list, uint32_t* n_big,
+                            unsigned long long* distinct) {
+  if (n_tiles == 0) return hipSuccess;
+  uint32_t* max_big = n_big + 1;
+  if (kc.key_words == 1)
+    hipLaunchKernelGGL(k_tile_sort<1>, dim3((uint32_t)n_tiles), dim3(kSortThreads), 0, s, kc,
+                       tiles, keys, out_counts, tile_out, big_list, n_big, max_big, distinct);
+  else
+    hipLaunchKernelGGL(k_tile_sort<2>, dim3((uint32_t)n_tiles), dim3(kSortThreads), 0, s, kc,
+                       tiles, keys, out_counts, tile_out, big_list, n_big, max_big, distinct);
+  return hipGetLastError();
+}
+
+hipError_t launch_big_tiles(hipStream_t s, const KeyCfg& kc, const Tile* tiles,
+                            const uint32_t* big_list, uint32_t n_big, uint64_t* keys,
+                            uint64_t* tmp, uint32_t* out_counts, uint32_t* tile_out,
+                            unsigned long long* distinct) {
+  if (n_big == 0) return hipSuccess;
+  if (kc.key_words == 1)
+    hipLaunchKernelGGL(k_big_tiles<1>, dim3(n_big), dim3(kSortThreads), 0, s, kc, tiles,
+                       big_list, keys, tmp, out_counts, tile_out, distinct);
+  else
+    hipLaunchKernelGGL(k_big_tiles<2>, dim3(n_big), dim3(kSortThreads), 0, s, kc, tiles,
+                       big_list, keys, tmp, out_counts, tile_out, distinct);
+  return hipGetLastError();
+}
+
+uint64_t scan_tmp_words(uint64_t n) { return (n + kScanChunk - 1) / kScanChunk + 1; }
+
+hipError_t launch_scan_u32(hipStream_t s, const uint32_t* in, uint64_t n, uint64_t* out,
+                           uint64_t* block_tmp) {
+  const uint64_t nb = (n + kScanChunk - 1) / kScanChunk;
+  if (nb == 0) {
+    hipLaunchKernelGGL(k_scan_bsum, dim3(1), dim3(256), 0, s, block_tmp, (uint64_t)0, out, n);
+    return hipGetLastError();
+  }
+  hipLaunchKernelGGL(k_scan_reduce, dim3((uint32_t)nb), dim3(256), 0, s, in, n, block_tmp);
+  hipLaunchKernelGGL(k_scan_bsum, dim3(1), dim3(256), 0, s, block_tmp, nb, out, n);
+  hipLaunchKernelGGL(k_scan_apply, dim3((uint32_t)nb), dim3(256), 0, s, in, n, block_tmp, out);
+  return hipGetLastError();
+}
+
+hipError_t launch_gather(hipStream_t s, const KeyCfg& kc, const Tile* tiles, uint64_t n_tiles,
+                         const uint64_t* tile_off, const uint64_t* keys,
+                         const uint32_t* counts, uint64_t* out_keys, uint32_t* out_counts) {
+  if (n_tiles == 0) return hipSuccess;
+  if (kc.key_words == 1)
+    hipLaunchKernelGGL(k_gather<1>, dim3((uint32_t)n_tiles), dim3(256), 0, s, tiles, tile_off,
+                       keys, counts, out_keys, out_counts);
+  else
+    hipLaunchKernelGGL(k_gather<2>, dim3((uint32_t)n_tiles), dim3(256), 0, s, tiles, tile_off,
+                       keys, counts, out_keys, out_counts);
+  return hipGetLastError();
+}
+
+}  // namespace kmc
+
+namespace kmc {
+namespace {
+__global__ void k_bin_offsets(const uint64_t* __restrict__ tile_off,
+                              const uint64_t* __restrict__ tile_base, uint32_t n_bins,
+                              uint64_t* out) {
+  const uint32_t b = blockIdx.x * blockDim.x + threadIdx.x;
+  if (b <= n_bins) out[b] = tile_off[tile_base[b]];
+}
+}  // namespace
+
+hipError_t launch_bin_offsets(hipStream_t s, const uint64_t* tile_off, const uint64_t* tile_base,
+                              uint32_t n_bins, uint64_t* out) {
+  hipLaunchKernelGGL(k_bin_offsets, dim3((n_bins + 256) / 256), dim3(256), 0, s, tile_off,
+                     tile_base, n_bins, out);
+  return hipGetLastError();
+}
+}  // namespace kmc

@@ -1,0 +1,232 @@
+"""Thin ctypes binding of libkmc_hip.so (include/kmc.h).
+
+Argument marshalling only: every step of the counting path runs in the
+library's HIP kernels.  Inputs are numpy arrays (host memory) or torch tensors
+on a HIP device (device memory); torch is only used for device buffers and
+streams.  The library must have been built (``__graft_entry__.build()``); if
+it is missing this module raises instead of falling back to anything else.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libkmc_hip.so")
+
+KMC_OK = 0
+KMC_ERR_INVALID_ARG = 1
+KMC_ERR_OUT_OF_MEMORY = 2
+KMC_ERR_DEVICE = 3
+KMC_ERR_TOO_LARGE = 4
+KMC_ERR_BUSY = 5
+FLAG_DEVICE_TABLE = 0x1
+FLAG_PLAIN_MINIMIZERS = 0x2
+
+EXPORTS = ["kmc_ctx_create", "kmc_ctx_destroy", "kmc_last_error", "kmc_count", "kmc_count_ex",
+           "kmc_table_free", "kmc_status_str", "kmc_debug_signatures"]
+
+
+class KmcError(RuntimeError):
+    def __init__(self, status: int, msg: str):
+        super().__init__(msg)
+        self.status = status
+
+
+class Reads(ctypes.Structure):
+    _fields_ = [("seq", ctypes.c_void_p), ("offsets", ctypes.c_void_p),
+                ("n_reads", ctypes.c_uint64), ("n_bases", ctypes.c_uint64),
+                ("on_device", ctypes.c_int32), ("reserved", ctypes.c_int32)]
+
+
+class Params(ctypes.Structure):
+    _fields_ = [("k", ctypes.c_uint32), ("p", ctypes.c_uint32), ("n_bins", ctypes.c_uint32),
+                ("cutoff_min", ctypes.c_uint32), ("cutoff_max", ctypes.c_uint32),
+                ("flags", ctypes.c_uint32)]
+
+
+class Stats(ctypes.Structure):
+    _fields_ = [(n, ctypes.c_uint64) for n in (
+        "n_reads", "n_bases", "n_kmers", "n_superkmers", "n_distinct", "n_out", "sample_kmers",
+        "max_bin_kmers", "n_tiles", "n_big_tiles", "bytes_alg")] + [
+        (n, ctypes.c_double) for n in (
+            "us_map", "us_split", "us_expand", "us_sort", "us_assemble", "us_total")]
+
+    def as_dict(self):
+        return {n: getattr(self, n) for n, _ in self._fields_}
+
+
+class Table(ctypes.Structure):
+    _fields_ = [("k", ctypes.c_uint32), ("key_words", ctypes.c_uint32), ("n", ctypes.c_uint64),
+                ("keys", ctypes.POINTER(ctypes.c_uint64)),
+                ("counts", ctypes.POINTER(ctypes.c_uint32)),
+                ("n_bins", ctypes.c_uint32), ("p", ctypes.c_uint32),
+                ("bin_offsets", ctypes.POINTER(ctypes.c_uint64)),
+                ("sig_to_bin", ctypes.POINTER(ctypes.c_uint32)),
+                ("on_device", ctypes.c_int32), ("reserved", ctypes.c_int32),
+                ("stats", Stats)]
+
+
+_lib = None
+
+
+def lib() -> ctypes.CDLL:
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise ImportError(f"{LIB_PATH} is not built; run __graft_entry__.build()")
+        L = ctypes.CDLL(LIB_PATH)
+        vp = ctypes.c_void_p
+        L.kmc_ctx_create.argtypes = [ctypes.c_int, ctypes.POINTER(vp)]
+        L.kmc_ctx_create.restype = ctypes.c_int
+        L.kmc_ctx_destroy.argtypes = [vp]
+        L.kmc_ctx_destroy.restype = None
+        L.kmc_last_error.argtypes = [vp]
+        L.kmc_last_error.restype = ctypes.c_char_p
+        L.kmc_count.argtypes = [ctypes.POINTER(Reads), ctypes.c_uint32, ctypes.c_uint32,
+                                ctypes.c_uint32, ctypes.c_uint32, ctypes.c_uint32,
+                                ctypes.POINTER(ctypes.POINTER(Table))]
+        L.kmc_count.restype = ctypes.c_int
+        L.kmc_count_ex.argtypes = [vp, ctypes.POINTER(Reads), ctypes.POINTER(Params), vp,
+                                   ctypes.POINTER(ctypes.POINTER(Table))]
+        L.kmc_count_ex.restype = ctypes.c_int
+        L.kmc_table_free.argtypes = [ctypes.POINTER(Table)]
+        L.kmc_table_free.restype = None
+        L.kmc_status_str.argtypes = [ctypes.c_int]
+        L.kmc_status_str.restype = ctypes.c_char_p
+        L.kmc_debug_signatures.argtypes = [vp, ctypes.POINTER(Reads), ctypes.c_uint32,
+                                           ctypes.c_uint32, ctypes.c_uint32, vp, vp]
+        L.kmc_debug_signatures.restype = ctypes.c_int
+        _lib = L
+    return _lib
+
+
+def _is_torch(x) -> bool:
+    return type(x).__module__.startswith("torch")
+
+
+def make_reads(seq, offsets):
+    """Reads struct (plus the objects that must stay alive while it is used)."""
+    if _is_torch(seq):
+        if not (seq.is_cuda and offsets.is_cuda):
+            raise ValueError("torch inputs must both live on the GPU")
+        if not (seq.is_contiguous() and offsets.is_contiguous()):
+            raise ValueError("torch inputs must be contiguous")
+        n_reads = offsets.numel() - 1
+        r = Reads(seq.data_ptr(), offsets.data_ptr(), n_reads, seq.numel(), 1, 0)
+        return r, (seq, offsets)
+    seq = np.ascontiguousarray(np.asarray(seq, dtype=np.uint8))
+    offsets = np.ascontiguousarray(np.asarray(offsets, dtype=np.uint64))
+    if offsets.ndim != 1 or offsets.size < 1:
+        raise ValueError("offsets must have n_reads + 1 entries")
+    r = Reads(seq.ctypes.data if seq.size else None, offsets.ctypes.data, offsets.size - 1,
+              seq.size, 0, 0)
+    return r, (seq, offsets)
+
+
+class Result:
+    """A counted table.  Host tables are copied into numpy arrays; device
+    tables keep the library's buffers until free() (or garbage collection)."""
+
+    def __init__(self, ptr):
+        t = ptr.contents
+        self.k = t.k
+        self.key_words = t.key_words
+        self.n = t.n
+        self.p = t.p
+        self.n_bins = t.n_bins
+        self.on_device = bool(t.on_device)
+        self.stats = t.stats.as_dict()
+        self.bin_offsets = np.ctypeslib.as_array(t.bin_offsets, shape=(t.n_bins + 1,)).copy()
+        self.sig_to_bin = np.ctypeslib.as_array(t.sig_to_bin, shape=((1 << (2 * t.p)) + 1,)).copy()
+        self._ptr = ptr
+        if self.on_device:
+            self.keys_ptr = ctypes.cast(t.keys, ctypes.c_void_p).value
+            self.counts_ptr = ctypes.cast(t.counts, ctypes.c_void_p).value
+            self.keys = self.counts = None
+        else:
+            n, kw = t.n, t.key_words
+            if n:
+                keys = np.ctypeslib.as_array(t.keys, shape=(n * kw,)).copy()
+                self.counts = np.ctypeslib.as_array(t.counts, shape=(n,)).copy()
+            else:
+                keys = np.zeros(0, dtype=np.uint64)
+                self.counts = np.zeros(0, dtype=np.uint32)
+            self.keys = keys.reshape(n, 2) if kw == 2 else keys
+            self.free()
+
+    def free(self):
+        if self._ptr is not None:
+            lib().kmc_table_free(self._ptr)
+            self._ptr = None
+
+    def __del__(self):
+        try:
+            self.free()
+        except Exception:
+            pass
+
+
+class Context:
+    def __init__(self, device: int = 0):
+        self._h = ctypes.c_void_p()
+        st = lib().kmc_ctx_create(device, ctypes.byref(self._h))
+        if st != KMC_OK:
+            raise KmcError(st, f"kmc_ctx_create: {lib().kmc_status_str(st).decode()}")
+
+    def close(self):
+        if self._h:
+            lib().kmc_ctx_destroy(self._h)
+            self._h = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def _raise(self, st, what):
+        msg = lib().kmc_last_error(self._h).decode()
+        raise KmcError(st, f"{what}: {lib().kmc_status_str(st).decode()} {msg}".strip())
+
+    def count(self, seq, offsets, k: int, p: int, n_bins: int, cutoff_min: int = 2,
+              cutoff_max: int = 10**9, flags: int = 0, stream=None) -> Result:
+        reads, keep = make_reads(seq, offsets)
+        params = Params(k, p, n_bins, cutoff_min, min(cutoff_max, 2**32 - 1), flags)
+        out = ctypes.POINTER(Table)()
+        sp = None
+        if stream is not None:
+            sp = stream if isinstance(stream, int) else stream.cuda_stream
+        st = lib().kmc_count_ex(self._h, ctypes.byref(reads), ctypes.byref(params), sp,
+                                ctypes.byref(out))
+        del keep
+        if st != KMC_OK:
+            self._raise(st, "kmc_count_ex")
+        return Result(out)
+
+    def debug_signatures(self, seq, offsets, k: int, p: int, flags: int = 0):
+        reads, keep = make_reads(seq, offsets)
+        nb = int(reads.n_bases)
+        sig = np.zeros(max(nb, 1), dtype=np.uint32)
+        start = np.zeros(max(nb, 1), dtype=np.uint8)
+        st = lib().kmc_debug_signatures(self._h, ctypes.byref(reads), k, p, flags,
+                                        sig.ctypes.data, start.ctypes.data)
+        del keep
+        if st != KMC_OK:
+            self._raise(st, "kmc_debug_signatures")
+        return sig[:nb], start[:nb]
+
+
+def count(seq, offsets, k: int, p: int, n_bins: int, cutoff_min: int = 2,
+          cutoff_max: int = 10**9) -> Result:
+    """kmc_count on the calling thread's default context (device 0)."""
+    reads, keep = make_reads(seq, offsets)
+    out = ctypes.POINTER(Table)()
+    st = lib().kmc_count(ctypes.byref(reads), k, p, n_bins, cutoff_min,
+                         min(cutoff_max, 2**32 - 1), ctypes.byref(out))
+    del keep
+    if st != KMC_OK:
+        raise KmcError(st, f"kmc_count: {lib().kmc_status_str(st).decode()}")
+    return Result(out)

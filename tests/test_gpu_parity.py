@@ -1,0 +1,252 @@
+"""GPU parity: the HIP path (through the C ABI) against the CPU oracle.
+
+Integer work, so the bar is bit-exact: the GPU table, put in ascending key
+order, equals the oracle's table entry for entry; the GPU's per-window
+signatures equal the oracle's; every entry lies in the bin its signature maps
+to.  Cases span several tiles and ragged tails, word-boundary k, N bases,
+lowercase, empty and short reads, tiles too large for LDS, and the paper's
+worked examples."""
+import ctypes
+import os
+
+import numpy as np
+import pytest
+
+import oracle
+from conftest import read_golden
+from oracle import strings as S
+from paper_1407_1507_amd import synth
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def kmc():
+    from paper_1407_1507_amd import kmc as m
+    m.lib()
+    return m
+
+
+@pytest.fixture(scope="module")
+def ctx(kmc):
+    c = kmc.Context(0)
+    yield c
+    c.close()
+
+
+def to_reads(strs):
+    seq = np.frombuffer("".join(strs).encode(), dtype=np.uint8).copy()
+    off = np.zeros(len(strs) + 1, dtype=np.uint64)
+    off[1:] = np.cumsum([len(s) for s in strs])
+    return seq, off
+
+
+def ascending(keys, counts):
+    if keys.ndim == 2:
+        order = np.lexsort((keys[:, 1], keys[:, 0]))
+    else:
+        order = np.argsort(keys, kind="stable")
+    return keys[order], counts[order]
+
+
+def check_table(res, seq, off, k, p, ci, cx, flt=True):
+    """Bit-exact against the oracle, plus the bin invariants."""
+    ok_keys, ok_counts = oracle.count(seq, off, k, ci, cx)
+    gk, gc = ascending(res.keys, res.counts)
+    assert res.n == len(ok_counts)
+    assert np.array_equal(gk, ok_keys)
+    assert np.array_equal(gc, ok_counts)
+    # bins: every entry sits in the bin its signature maps to, ascending inside
+    bo = res.bin_offsets
+    assert bo[0] == 0 and bo[-1] == res.n and np.all(bo[1:] >= bo[:-1])
+    if res.n:
+        sig = oracle.key_signatures(res.keys, k, p, filter=flt)
+        bin_of_entry = np.repeat(np.arange(res.n_bins), np.diff(bo).astype(np.int64))
+        assert np.array_equal(res.sig_to_bin[sig], bin_of_entry)
+        for b in range(res.n_bins):
+            seg = res.keys[bo[b]:bo[b + 1]]
+            if len(seg) > 1:
+                if seg.ndim == 2:
+                    assert np.all((seg[1:, 0] > seg[:-1, 0]) |
+                                  ((seg[1:, 0] == seg[:-1, 0]) & (seg[1:, 1] > seg[:-1, 1])))
+                else:
+                    assert np.all(seg[1:] > seg[:-1])
+    if ci <= 1 and cx >= 2**32 - 1:
+        assert int(res.counts.sum()) == oracle.valid_windows(seq, off, k)
+    assert res.stats["n_kmers"] == oracle.valid_windows(seq, off, k)
+
+
+# ---------------------------------------------------------- paper examples
+
+
+def test_fig1_signatures_and_superkmers(ctx):
+    rows = read_golden("fig1_split.txt")
+    read = rows[0][1]
+    k, m = int(rows[1][1]), int(rows[2][1])
+    seq, off = to_reads([read])
+    for mode, flags in (("signature", 0), ("minimizer", 2)):
+        sig, start = ctx.debug_signatures(seq, off, k, m, flags)
+        expect_sig, expect_start = [], []
+        for sk, s in [(r[1], r[2]) for r in rows if r[0] == mode]:
+            n = len(sk) - k + 1
+            expect_sig += [S.encode(s)] * n
+            expect_start += [1] + [0] * (n - 1)
+        n = len(read) - k + 1
+        assert list(sig[:n]) == expect_sig
+        assert list(start[:n]) == expect_start
+        assert all(int(x) == 0xFFFFFFFF for x in sig[n:])
+
+
+def test_fig2_superkmer_counts(ctx):
+    rows = read_golden("fig2_kx_mers.txt")
+    sk, k, m = rows[0][1], int(rows[1][1]), int(rows[2][1])
+    seq, off = to_reads([sk])
+    sig, start = ctx.debug_signatures(seq, off, k, m)
+    assert set(int(x) for x in sig[:len(sk) - k + 1]) == {S.encode(rows[3][1])}
+    res = ctx.count(seq, off, k, m, 4, 1, 2**32 - 1)
+    check_table(res, seq, off, k, m, 1, 2**32 - 1)
+    assert res.n == len(sk) - k + 1
+
+
+def test_supplement_signature(ctx):
+    kmer, plen, sigs, val = read_golden("supp_encoding.txt")[0][1:]
+    seq, off = to_reads([kmer])
+    sig, _ = ctx.debug_signatures(seq, off, len(kmer), int(plen))
+    assert int(sig[0]) == int(val)
+
+
+# ------------------------------------------------------------ random small
+
+
+def random_reads(rng, n, lo, hi, n_rate=0.0, lower=0.0):
+    out = []
+    for _ in range(n):
+        L = int(rng.integers(lo, hi + 1))
+        b = rng.choice(list("ACGT"), size=L)
+        if n_rate:
+            b[rng.random(L) < n_rate] = "N"
+        if lower:
+            idx = rng.random(L) < lower
+            b[idx] = np.char.lower(b[idx])
+        out.append("".join(b))
+    return out
+
+
+@pytest.mark.parametrize("k,p,n_bins", [(4, 4, 3), (5, 4, 16), (15, 4, 7), (21, 5, 64),
+                                        (28, 7, 512), (31, 7, 100), (32, 8, 512), (33, 7, 512),
+                                        (47, 9, 1024), (55, 9, 1024), (63, 12, 4096),
+                                        (64, 11, 2000)])
+def test_random_reads_exact(ctx, k, p, n_bins):
+    rng = np.random.default_rng(1000 + k)
+    reads = random_reads(rng, 700, 0, 260, n_rate=0.01, lower=0.02)
+    reads += ["", "A", "ACGT" * 40, "N" * 50, "A" * 200, "ACACACACAC" * 20]
+    seq, off = to_reads(reads)
+    for ci, cx in ((1, 2**32 - 1), (2, 10**9), (1, 3)):
+        res = ctx.count(seq, off, k, p, n_bins, ci, cx)
+        check_table(res, seq, off, k, p, ci, cx)
+
+
+def test_window_signatures_match_oracle(ctx):
+    rng = np.random.default_rng(77)
+    reads = random_reads(rng, 300, 0, 300, n_rate=0.02, lower=0.01)
+    seq, off = to_reads(reads)
+    for k, p, flt in ((28, 7, True), (28, 7, False), (55, 9, True), (12, 5, True), (64, 12, True)):
+        sig, start = ctx.debug_signatures(seq, off, k, p, 0 if flt else 2)
+        assert np.array_equal(sig, oracle.window_signatures(seq, off, k, p, flt))
+        # a super k-mer starts wherever the signature changes or a valid run starts
+        valid = sig != 0xFFFFFFFF
+        prev_valid = np.concatenate([[False], valid[:-1]])
+        prev_sig = np.concatenate([[0xFFFFFFFF], sig[:-1]])
+        must = valid & (~prev_valid | (sig != prev_sig))
+        assert np.all(start[must] == 1)
+        assert np.all(start[~valid] == 0)
+
+
+# ------------------------------------------------------------- workloads
+
+
+def test_uniform_10k_exact(ctx):
+    seq, off, p = synth.make("uniform-10k")
+    res = ctx.count(seq, off, p["k"], p["p"], p["n_bins"], p["cutoff_min"], p["cutoff_max"])
+    check_table(res, seq, off, p["k"], p["p"], p["cutoff_min"], p["cutoff_max"])
+    assert int(res.counts.sum()) == 730_000
+    assert res.stats["n_tiles"] > 100
+
+
+@pytest.mark.parametrize("scale", [0.01, 0.05])
+def test_genome_exact(ctx, scale):
+    seq, off, p = synth.make("genome-5M-2Mx100", scale)
+    res = ctx.count(seq, off, p["k"], p["p"], p["n_bins"], p["cutoff_min"], p["cutoff_max"])
+    check_table(res, seq, off, p["k"], p["p"], p["cutoff_min"], p["cutoff_max"])
+
+
+def test_repeats_k55_exact(ctx):
+    seq, off, p = synth.make("repeats-50M-30x150-k55", 0.01)
+    res = ctx.count(seq, off, p["k"], p["p"], p["n_bins"], p["cutoff_min"], p["cutoff_max"])
+    check_table(res, seq, off, p["k"], p["p"], p["cutoff_min"], p["cutoff_max"])
+
+
+def test_big_tiles(ctx):
+    # a tiny reference at very high coverage: tiles far beyond LDS capacity,
+    # with many distinct keys (MSD through HBM) and runs of one key
+    ref = synth.random_reference(9, 3000)
+    seq, off = synth.sample_reads(10, ref, 40_000, 100, err=0.002, n_rate=0.0)
+    seq2, off2 = to_reads(["ACGT" * 30] * 3000)
+    seq = np.concatenate([seq, seq2])
+    off = np.concatenate([off, off2[1:] + off[-1]])
+    for k, p, nb in ((28, 7, 4), (55, 9, 4)):
+        res = ctx.count(seq, off, k, p, nb, 1, 2**32 - 1)
+        assert res.stats["n_big_tiles"] > 0
+        check_table(res, seq, off, k, p, 1, 2**32 - 1)
+
+
+def test_plain_minimizers_same_counts(ctx, kmc):
+    seq, off, p = synth.make("genome-5M-2Mx100", 0.01)
+    res = ctx.count(seq, off, 28, 7, 512, 2, 10**9, flags=kmc.FLAG_PLAIN_MINIMIZERS)
+    check_table(res, seq, off, 28, 7, 2, 10**9, flt=False)
+
+
+def test_empty_and_degenerate(ctx):
+    for reads in ([], [""], ["ACG"], ["N" * 100], ["ACGTN" * 20]):
+        seq, off = to_reads(reads)
+        res = ctx.count(seq, off, 28, 7, 512, 1, 2**32 - 1)
+        assert res.n == 0 and res.stats["n_kmers"] == 0
+
+
+def test_deterministic(ctx):
+    seq, off, p = synth.make("genome-5M-2Mx100", 0.02)
+    a = ctx.count(seq, off, 28, 7, 512, 1, 10**9)
+    b = ctx.count(seq, off, 28, 7, 512, 1, 10**9)
+    assert np.array_equal(a.keys, b.keys) and np.array_equal(a.counts, b.counts)
+    assert np.array_equal(a.bin_offsets, b.bin_offsets)
+
+
+def test_device_inputs_and_device_table(ctx, kmc):
+    import torch
+    seq, off, p = synth.make("genome-5M-2Mx100", 0.01)
+    host = ctx.count(seq, off, 28, 7, 512, 2, 10**9)
+    dseq = torch.from_numpy(seq).cuda()
+    doff = torch.from_numpy(off.view(np.int64)).cuda()
+    dev = ctx.count(dseq, doff, 28, 7, 512, 2, 10**9)
+    assert np.array_equal(dev.keys, host.keys) and np.array_equal(dev.counts, host.counts)
+    # table left in device memory, copied back with hipMemcpy
+    t = ctx.count(dseq, doff, 28, 7, 512, 2, 10**9, flags=kmc.FLAG_DEVICE_TABLE)
+    assert t.on_device and t.n == host.n
+    hip = ctypes.CDLL("libamdhip64.so")
+    k = np.zeros(t.n, dtype=np.uint64)
+    c = np.zeros(t.n, dtype=np.uint32)
+    assert hip.hipMemcpy(ctypes.c_void_p(k.ctypes.data), ctypes.c_void_p(t.keys_ptr),
+                         ctypes.c_size_t(k.nbytes), 2) == 0
+    assert hip.hipMemcpy(ctypes.c_void_p(c.ctypes.data), ctypes.c_void_p(t.counts_ptr),
+                         ctypes.c_size_t(c.nbytes), 2) == 0
+    t.free()
+    assert np.array_equal(k, host.keys) and np.array_equal(c, host.counts)
+
+
+def test_bad_device_offsets_rejected(ctx, kmc):
+    import torch
+    seq = torch.zeros(100, dtype=torch.uint8, device="cuda")
+    off = torch.tensor([0, 60, 40, 100], dtype=torch.int64, device="cuda")
+    with pytest.raises(kmc.KmcError) as e:
+        ctx.count(seq, off, 28, 7, 16, 1, 10)
+    assert e.value.status == kmc.KMC_ERR_INVALID_ARG
