@@ -1,0 +1,161 @@
+"""Benchmark: one k-mer counting job per step on one MI355X.
+
+A step is one whole pass of the counting path (signature histogram and map,
+split and scatter of super k-mers into bins, per-bin key expansion, tile sort,
+run-length counting with cutoffs, table assembly) over one synthetic read set
+already resident in HBM; the table is left in HBM.  Prints one JSON line.
+
+  python bench.py [--steps K] [--warmup W] [--workload NAME] [--no-cpu-baseline]
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = ("input bases/sec and k-mers/sec per MI355X; achieved HBM GB/s; "
+          "p50/p99 job latency")
+HBM_PEAK_GBS = 8000.0
+DESCRIPTION = {
+    "genome-5M-2Mx100": ("2,000,000 reads x 100 bp sampled (random strand) from a uniform "
+                         "5 Mbp reference, 1% substitutions, 0.05% N; k=28, p=7, 512 bins, "
+                         "cutoff_min=2, cutoff_max=1e9 (about 40x coverage)"),
+    "uniform-10k": "10,000 i.i.d. uniform reads x 100 bp; k=28, p=7, 512 bins, cutoff_min=1",
+    "repeats-50M-30x150-k55": ("10,000,000 reads x 150 bp from a 50 Mbp reference with 20% "
+                               "repeat families, 0.5% substitutions, 0.1% N; k=55, p=9, "
+                               "1024 bins, cutoff_min=2, cutoff_max=1e6"),
+}
+
+
+def kernel_bytes(name: str, st: dict, k: int) -> int:
+    """Algorithmic HBM bytes of one launch of a kernel (what the method must
+    move through it, not what the implementation happens to move)."""
+    w = 8 if k <= 32 else 16
+    inp = st["n_bases"] + 8 * (st["n_reads"] + 1)
+    payload = 2 * st["n_superkmers"] + (st["n_kmers"] + st["n_superkmers"] * (k - 1)) // 4
+    keys = w * st["n_kmers"]
+    out = (w + 4) * st["n_out"]
+    return {
+        "split": inp + payload,
+        "fine_hist": payload,
+        "expand_scatter": payload + keys,
+        "tile_sort": keys + out,
+        "assemble": 2 * out,
+    }.get(name, 0)
+
+
+def cpu_baseline(seq, off, p, budget_s: float = 15.0):
+    """The oracle, as it stands, on a prefix of the same read set sized to
+    about budget_s of CPU time; all host cores."""
+    import oracle
+    oracle.build(force=False)
+    cores = os.cpu_count() or 1
+    n_reads = off.size - 1
+    # calibrate on 1% of the reads, then run the sized sample once
+    n0 = max(1, n_reads // 100)
+    t = time.perf_counter()
+    oracle.count(seq[: int(off[n0])], off[: n0 + 1], p["k"], p["cutoff_min"], p["cutoff_max"],
+                 threads=cores)
+    dt0 = time.perf_counter() - t
+    n = int(min(n_reads, max(n0, n0 * budget_s / max(dt0, 1e-3))))
+    s, o = seq[: int(off[n])], off[: n + 1]
+    t = time.perf_counter()
+    oracle.count(s, o, p["k"], p["cutoff_min"], p["cutoff_max"], threads=cores)
+    dt = time.perf_counter() - t
+    return {"value": float(o[-1]) / dt, "unit": "bases/s", "cores": cores, "kind": "oracle",
+            "sample": f"first {n} of {n_reads} reads ({int(o[-1])} bases), {dt:.2f} s, "
+                      f"{cores} threads"}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--workload", default="genome-5M-2Mx100")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
+        print("bench.py measures one GPU: the counting path runs on a single MI355X "
+              "(see DESIGN.md for how it would shard); run with --gpus 1", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    from paper_1407_1507_amd import kmc, synth
+
+    seq, off, p = synth.make(args.workload)
+    dseq = torch.from_numpy(seq).to("cuda:0")
+    doff = torch.from_numpy(off.view(np.int64)).to("cuda:0")
+    torch.cuda.synchronize()
+    ctx = kmc.Context(0)
+    run = lambda: ctx.count(dseq, doff, p["k"], p["p"], p["n_bins"], p["cutoff_min"],
+                            p["cutoff_max"], flags=kmc.FLAG_DEVICE_TABLE)
+    for _ in range(args.warmup):
+        run().free()
+    torch.cuda.synchronize()
+    lat, stats, tables = [], [], []
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        s = time.perf_counter()
+        r = run()
+        lat.append(time.perf_counter() - s)
+        stats.append(r.stats)
+        tables.append(r)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    for r in tables:
+        r.free()
+    ms = (t1 - t0) * 1e3 / args.steps
+    st = stats[-1]
+    n_bases, n_kmers = st["n_bases"], st["n_kmers"]
+    # dominant kernel: largest mean device time (HIP events on the library's stream)
+    names = kmc.KERNELS
+    mean_us = {n: float(np.mean([x["us_kernel"][n] for x in stats])) for n in names}
+    dom = max(mean_us, key=mean_us.get)
+    dom_bytes = kernel_bytes(dom, st, p["k"])
+    achieved = dom_bytes / (mean_us[dom] * 1e-6) / 1e9 if mean_us[dom] > 0 else 0.0
+    dev_us = float(np.mean([x["us_total"] for x in stats]))
+    line = {
+        "metric": METRIC,
+        "value": n_bases / (ms * 1e-3),
+        "unit": "bases/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "u64" if p["k"] <= 32 else "u128",
+        "data": "synthetic (seeded generator; stands in for the paper's read sets)",
+        "config": {"workload": f"{args.workload}: {DESCRIPTION.get(args.workload, '')}",
+                   "k": p["k"], "p": p["p"], "n_bins": p["n_bins"],
+                   "cutoff_min": p["cutoff_min"], "cutoff_max": p["cutoff_max"],
+                   "n_reads": int(off.size - 1), "n_bases": int(n_bases)},
+        "kmers_per_s": n_kmers / (ms * 1e-3),
+        "hbm_gbs_alg": st["bytes_alg"] / (ms * 1e-3) / 1e9,
+        "device_ms": dev_us * 1e-3,
+        "latency_ms_p50": float(np.percentile(lat, 50) * 1e3),
+        "latency_ms_p99": float(np.percentile(lat, 99) * 1e3),
+        "kernel_us": {n: round(v, 2) for n, v in mean_us.items()},
+        "job": {key: st[key] for key in ("n_kmers", "n_superkmers", "n_distinct", "n_out",
+                                         "n_tiles", "n_big_tiles", "bytes_alg")},
+        "roofline": {"bound": "hbm", "kernel": dom, "achieved": achieved,
+                     "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS,
+                     "traffic": None},
+    }
+    if not args.no_cpu_baseline:
+        line["cpu_baseline"] = cpu_baseline(seq, off, p)
+    ctx.close()
+    print(json.dumps(line), flush=True)
+
+
+if __name__ == "__main__":
+    main()

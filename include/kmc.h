@@ -86,6 +86,19 @@ typedef struct kmc_params {
  * Methods, "Minimizers of k-mers").  Changes only the bins, never the counts. */
 #define KMC_FLAG_PLAIN_MINIMIZERS 0x2u
 
+/* Kernels timed in kmc_stats.us_kernel. */
+enum {
+  KMC_K_SIG_HIST = 0,   /* signature histogram of the sample */
+  KMC_K_SPLIT = 1,      /* signature scan, super k-mers into bins */
+  KMC_K_FINE_HIST = 2,  /* key histogram per bin (top bits) */
+  KMC_K_PLAN_TILES = 3, /* fine ranges -> sort tiles */
+  KMC_K_EXPAND = 4,     /* canonical keys into tiles */
+  KMC_K_TILE_SORT = 5,  /* LDS sort, run-length count, cutoffs */
+  KMC_K_BIG_TILES = 6,  /* tiles larger than LDS */
+  KMC_K_ASSEMBLE = 7,   /* scan of tile outputs and gather */
+  KMC_N_KERNELS = 8
+};
+
 /* Per-job statistics (measured on the device). */
 typedef struct kmc_stats {
   uint64_t n_reads;
@@ -98,13 +111,15 @@ typedef struct kmc_stats {
   uint64_t max_bin_kmers;  /* k-mers in the largest bin */
   uint64_t n_tiles;        /* sort tiles (sub-bins held in LDS) */
   uint64_t n_big_tiles;    /* tiles too large for LDS, sorted in HBM */
-  uint64_t bytes_alg;      /* algorithmic HBM bytes of the job (see DESIGN) */
+  uint64_t bytes_alg;      /* algorithmic HBM bytes of the job */
+  uint64_t split_passes;   /* 1, or 2 when a bin outgrew its sampled estimate */
   double us_map;           /* device time of each phase, microseconds */
   double us_split;
   double us_expand;
   double us_sort;
   double us_assemble;
   double us_total;         /* first kernel to last kernel */
+  double us_kernel[8];     /* device time of each kernel (KMC_K_*), microseconds */
 } kmc_stats;
 
 /* Result of a count.  Entries are grouped by bin (bin b holds entries

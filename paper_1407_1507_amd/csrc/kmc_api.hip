@@ -36,11 +36,11 @@ struct DevBuf {
 // Misc device words (one small allocation): counters read back by the host.
 struct Misc {
   unsigned long long sample_kmers;
+  unsigned long long sample_bases;
   unsigned long long distinct;
+  unsigned long long big_total;
   uint32_t n_big;
-  uint32_t max_big;
   uint32_t offsets_err;
-  uint32_t pad;
 };
 
 }  // namespace
@@ -50,7 +50,7 @@ struct kmc_ctx {
   hipStream_t stream = nullptr;
   std::string err;
   DevBuf buf[B_COUNT_];
-  hipEvent_t ev[8] = {};
+  hipEvent_t ev[32] = {};  // 0..5 phases, 8 + 2i / 9 + 2i kernel i, 28 / 29 gather
 };
 
 namespace {
@@ -187,6 +187,9 @@ void stage_reads(kmc_ctx* c, const kmc_reads* R, Job& J) {
   J.aligned4 = ((uintptr_t)J.seq & 3u) == 0;
 }
 
+void kbeg(kmc_ctx* c, int i, hipStream_t s) { check(c, hipEventRecord(c->ev[8 + 2 * i], s), "event"); }
+void kend(kmc_ctx* c, int i, hipStream_t s) { check(c, hipEventRecord(c->ev[9 + 2 * i], s), "event"); }
+
 float ev_ms(hipEvent_t a, hipEvent_t b) {
   float ms = 0.f;
   if (hipEventElapsedTime(&ms, a, b) != hipSuccess) return 0.f;
@@ -225,51 +228,86 @@ void run_count(kmc_ctx* c, const kmc_reads* R, const kmc_params* P, kmc_table* T
     check(c, launch_check_offsets(s, J.off, J.n_reads, J.n_bases, &misc->offsets_err), "check");
   const ScanCfg C = scan_cfg(J);
 
-  // ---- map: signature histogram of every s-th read (s = N/1e5 in [1,100])
+  // ---- map: signature histograms of every s-th read (s = N/1e5 in [1,100])
   check(c, hipEventRecord(c->ev[0], s), "event");
-  uint32_t* hist = ensure<uint32_t>(c, B_HIST, (size_t)n_sig * 4);
-  check(c, hipMemsetAsync(hist, 0, (size_t)n_sig * 4, s), "memset");
+  uint32_t* hist = ensure<uint32_t>(c, B_HIST, (size_t)n_sig * 8);
+  check(c, hipMemsetAsync(hist, 0, (size_t)n_sig * 8, s), "memset");
   uint64_t stride = J.n_bases / 100000;
   stride = stride < 1 ? 1 : (stride > 100 ? 100 : stride);
+  kbeg(c, KMC_K_SIG_HIST, s);
   check(c, launch_sig_hist(s, J.seq, J.off, J.n_reads, J.n_bases, stride, C, J.kw, hist,
                            &misc->sample_kmers), "sig_hist");
-  std::vector<uint32_t> h_hist(n_sig);
+  kend(c, KMC_K_SIG_HIST, s);
+  std::vector<uint32_t> h_hist(2 * (size_t)n_sig);
   Misc h_misc;
-  check(c, hipMemcpyAsync(h_hist.data(), hist, (size_t)n_sig * 4, hipMemcpyDeviceToHost, s), "D2H");
+  check(c, hipMemcpyAsync(h_hist.data(), hist, (size_t)n_sig * 8, hipMemcpyDeviceToHost, s), "D2H");
   check(c, hipMemcpyAsync(&h_misc, misc, sizeof(Misc), hipMemcpyDeviceToHost, s), "D2H");
   check(c, hipStreamSynchronize(s), "sync");
   if (h_misc.offsets_err) throw Fail{KMC_ERR_INVALID_ARG};
   st.sample_kmers = h_misc.sample_kmers;
   std::vector<uint32_t> map;
-  build_map(h_hist, J.n_bins, map);
+  {
+    std::vector<uint32_t> hk(h_hist.begin(), h_hist.begin() + n_sig);
+    build_map(hk, J.n_bins, map);
+  }
   std::memcpy(T->sig_to_bin, map.data(), (size_t)n_sig * 4);
   uint32_t* d_map = ensure<uint32_t>(c, B_MAP, (size_t)n_sig * 4);
   check(c, hipMemcpyAsync(d_map, map.data(), (size_t)n_sig * 4, hipMemcpyHostToDevice, s), "H2D map");
   check(c, hipEventRecord(c->ev[1], s), "event");
 
-  // ---- split: per-bin records / k-mers, then scatter of the records
-  unsigned long long* bincnt = ensure<unsigned long long>(c, B_BINCNT, (size_t)J.n_bins * 16);
-  check(c, hipMemsetAsync(bincnt, 0, (size_t)J.n_bins * 16, s), "memset");
-  check(c, launch_split_count(s, J.seq, J.off, J.n_reads, J.n_bases, C, J.kw, d_map, bincnt,
-                              bincnt + J.n_bins), "split_count");
-  std::vector<uint64_t> h_cnt(2 * (size_t)J.n_bins);
-  check(c, hipMemcpyAsync(h_cnt.data(), bincnt, (size_t)J.n_bins * 16, hipMemcpyDeviceToHost, s), "D2H");
-  check(c, hipStreamSynchronize(s), "sync");
-  const uint64_t* rec_cnt = h_cnt.data();
-  const uint64_t* kmer_cnt = h_cnt.data() + J.n_bins;
-  // bases: [0..n_bins] record base, [n_bins+1..] key base, then tile base
+  // ---- split: one pass writing super k-mer records into bin regions sized
+  // from the sample (1.25x the scaled estimate + 256 records); if a bin
+  // overflows, the pass is repeated with the exact sizes its cursor counted
+  std::vector<uint64_t> cap(J.n_bins, 0);
+  {
+    std::vector<double> est(J.n_bins, 0.0);
+    for (uint32_t g = 0; g < n_sig; ++g) est[map[g]] += h_hist[n_sig + g];
+    const double scale = h_misc.sample_bases ? (double)J.n_bases / (double)h_misc.sample_bases : 0.0;
+    for (uint32_t b = 0; b < J.n_bins; ++b) cap[b] = (uint64_t)(est[b] * scale * 1.25) + 256;
+  }
+  // bases: [0..n_bins] record region base, [n_bins+1..] key base, then tile base
   std::vector<uint64_t> bases(3 * ((size_t)J.n_bins + 1));
   uint64_t* rec_base = bases.data();
   uint64_t* key_base = rec_base + J.n_bins + 1;
   uint64_t* tile_base = key_base + J.n_bins + 1;
-  uint64_t max_bin = 0;
-  rec_base[0] = key_base[0] = 0;
+  unsigned long long* bincnt = ensure<unsigned long long>(c, B_BINCNT, (size_t)J.n_bins * 16);
+  unsigned long long* cursor = bincnt;
+  unsigned long long* kmer_dev = bincnt + J.n_bins;
+  uint64_t* d_bases = ensure<uint64_t>(c, B_BASES, bases.size() * 8);
+  std::vector<uint64_t> h_cnt(2 * (size_t)J.n_bins);
+  uint64_t* records = nullptr;
+  for (int pass = 0; pass < 2; ++pass) {
+    rec_base[0] = 0;
+    for (uint32_t b = 0; b < J.n_bins; ++b) rec_base[b + 1] = rec_base[b] + cap[b];
+    records = ensure<uint64_t>(c, B_REC, rec_base[J.n_bins] * RW * 8);
+    check(c, hipMemcpyAsync(d_bases, rec_base, ((size_t)J.n_bins + 1) * 8, hipMemcpyHostToDevice, s), "H2D");
+    check(c, hipMemcpyAsync(cursor, rec_base, (size_t)J.n_bins * 8, hipMemcpyHostToDevice, s), "H2D");
+    check(c, hipMemsetAsync(kmer_dev, 0, (size_t)J.n_bins * 8, s), "memset");
+    kbeg(c, KMC_K_SPLIT, s);
+    check(c, launch_split_scatter(s, J.seq, J.off, J.n_reads, J.n_bases, C, J.kw, d_map, cursor,
+                                  kmer_dev, d_bases, records), "split_scatter");
+    kend(c, KMC_K_SPLIT, s);
+    check(c, hipMemcpyAsync(h_cnt.data(), bincnt, (size_t)J.n_bins * 16, hipMemcpyDeviceToHost, s), "D2H");
+    check(c, hipStreamSynchronize(s), "sync");
+    bool over = false;
+    for (uint32_t b = 0; b < J.n_bins; ++b) {
+      const uint64_t used = h_cnt[b] - rec_base[b];
+      if (used > cap[b]) over = true;
+      cap[b] = used;
+    }
+    st.split_passes = pass + 1;
+    if (!over) break;
+  }
+  std::vector<uint64_t> rec_cnt(cap);
+  const uint64_t* kmer_cnt = h_cnt.data() + J.n_bins;
+  uint64_t max_bin = 0, n_rec = 0;
+  key_base[0] = 0;
   for (uint32_t b = 0; b < J.n_bins; ++b) {
-    rec_base[b + 1] = rec_base[b] + rec_cnt[b];
     key_base[b + 1] = key_base[b] + kmer_cnt[b];
     max_bin = std::max<uint64_t>(max_bin, kmer_cnt[b]);
+    n_rec += rec_cnt[b];
   }
-  const uint64_t n_rec = rec_base[J.n_bins], n_kmers = key_base[J.n_bins];
+  const uint64_t n_kmers = key_base[J.n_bins];
   st.n_kmers = n_kmers;
   st.n_superkmers = n_rec;
   st.max_bin_kmers = max_bin;
@@ -277,11 +315,6 @@ void run_count(kmc_ctx* c, const kmc_reads* R, const kmc_params* P, kmc_table* T
     c->err = "a bin holds 2^32 or more k-mers";
     throw Fail{KMC_ERR_TOO_LARGE};
   }
-  uint64_t* records = ensure<uint64_t>(c, B_REC, n_rec * RW * 8);
-  unsigned long long* cursor = ensure<unsigned long long>(c, B_CURSOR, (size_t)J.n_bins * 8);
-  check(c, hipMemcpyAsync(cursor, rec_base, (size_t)J.n_bins * 8, hipMemcpyHostToDevice, s), "H2D");
-  check(c, launch_split_scatter(s, J.seq, J.off, J.n_reads, J.n_bases, C, J.kw, d_map, cursor,
-                                records), "split_scatter");
   check(c, hipEventRecord(c->ev[2], s), "event");
 
   // ---- expand: fine histogram per bin, tiles, scatter of canonical keys
@@ -314,14 +347,14 @@ void run_count(kmc_ctx* c, const kmc_reads* R, const kmc_params* P, kmc_table* T
   const uint64_t hrec = std::min<uint64_t>(65536, std::max<uint64_t>(1024, 8ull << fb));
   std::vector<ExpandTask> htasks, etasks;
   for (uint32_t b = 0; b < J.n_bins; ++b) {
-    for (uint64_t r = rec_base[b]; r < rec_base[b + 1]; r += hrec)
-      htasks.push_back({r, (uint32_t)std::min<uint64_t>(hrec, rec_base[b + 1] - r), b});
-    for (uint64_t r = rec_base[b]; r < rec_base[b + 1]; r += kExpandThreads)
-      etasks.push_back({r, (uint32_t)std::min<uint64_t>(kExpandThreads, rec_base[b + 1] - r), b});
+    const uint64_t r_end = rec_base[b] + rec_cnt[b];
+    for (uint64_t r = rec_base[b]; r < r_end; r += hrec)
+      htasks.push_back({r, (uint32_t)std::min<uint64_t>(hrec, r_end - r), b});
+    for (uint64_t r = rec_base[b]; r < r_end; r += kExpandThreads)
+      etasks.push_back({r, (uint32_t)std::min<uint64_t>(kExpandThreads, r_end - r), b});
   }
   ExpandTask* d_ht = ensure<ExpandTask>(c, B_HTASK, htasks.size() * sizeof(ExpandTask));
   ExpandTask* d_et = ensure<ExpandTask>(c, B_ETASK, etasks.size() * sizeof(ExpandTask));
-  uint64_t* d_bases = ensure<uint64_t>(c, B_BASES, bases.size() * 8);
   if (!htasks.empty())
     check(c, hipMemcpyAsync(d_ht, htasks.data(), htasks.size() * sizeof(ExpandTask),
                             hipMemcpyHostToDevice, s), "H2D");
@@ -334,39 +367,52 @@ void run_count(kmc_ctx* c, const kmc_reads* R, const kmc_params* P, kmc_table* T
   const size_t nfine = (size_t)J.n_bins << fb;
   uint32_t* fine = ensure<uint32_t>(c, B_FINE, nfine * 4);
   check(c, hipMemsetAsync(fine, 0, nfine * 4, s), "memset");
+  kbeg(c, KMC_K_FINE_HIST, s);
   check(c, launch_fine_hist(s, kc, d_ht, (uint32_t)htasks.size(), records, fine), "fine_hist");
+  kend(c, KMC_K_FINE_HIST, s);
   uint16_t* tof = ensure<uint16_t>(c, B_TOF, nfine * 2);
   Tile* tiles = ensure<Tile>(c, B_TILES, n_tiles * sizeof(Tile));
   unsigned long long* tcur = ensure<unsigned long long>(c, B_TCUR, n_tiles * 8);
   if (n_tiles) check(c, hipMemsetAsync(tiles, 0, n_tiles * sizeof(Tile), s), "memset");
+  kbeg(c, KMC_K_PLAN_TILES, s);
   check(c, launch_plan_tiles(s, kc, fine, d_key_base, d_tile_base, tof, tiles, tcur), "plan");
+  kend(c, KMC_K_PLAN_TILES, s);
   uint64_t* keys = ensure<uint64_t>(c, B_KEYS, n_kmers * J.kw * 8);
   uint32_t* counts = ensure<uint32_t>(c, B_COUNTS, n_kmers * 4);
+  kbeg(c, KMC_K_EXPAND, s);
   check(c, launch_expand_scatter(s, kc, d_et, (uint32_t)etasks.size(), records, tof, d_tile_base,
                                  (uint32_t)max_tiles, tcur, keys), "expand");
+  kend(c, KMC_K_EXPAND, s);
   check(c, hipEventRecord(c->ev[3], s), "event");
 
   // ---- sort: tiles in LDS, big tiles through HBM
   uint32_t* tile_out = ensure<uint32_t>(c, B_TILEOUT, n_tiles * 4);
-  uint32_t* big = ensure<uint32_t>(c, B_BIG, n_tiles * 4);
-  check(c, launch_tile_sort(s, kc, tiles, n_tiles, keys, counts, tile_out, big, &misc->n_big,
-                            &misc->distinct), "tile_sort");
+  uint32_t* big = ensure<uint32_t>(c, B_BIG, n_tiles * 12 + 16);
+  uint64_t* big_off = reinterpret_cast<uint64_t*>(big + ((n_tiles + 1) & ~1ull));
+  kbeg(c, KMC_K_TILE_SORT, s);
+  check(c, launch_tile_sort(s, kc, tiles, n_tiles, keys, counts, tile_out, big, big_off,
+                            &misc->n_big, &misc->big_total, &misc->distinct), "tile_sort");
+  kend(c, KMC_K_TILE_SORT, s);
   check(c, hipMemcpyAsync(&h_misc, misc, sizeof(Misc), hipMemcpyDeviceToHost, s), "D2H");
   check(c, hipStreamSynchronize(s), "sync");
   st.n_big_tiles = h_misc.n_big;
+  kbeg(c, KMC_K_BIG_TILES, s);
   if (h_misc.n_big) {
-    uint64_t* tmp = ensure<uint64_t>(c, B_TMP, (size_t)h_misc.max_big * J.kw * 8);
-    check(c, launch_big_tiles(s, kc, tiles, big, h_misc.n_big, keys, tmp, counts, tile_out,
-                              &misc->distinct), "big_tiles");
+    uint64_t* tmp = ensure<uint64_t>(c, B_TMP, (size_t)h_misc.big_total * J.kw * 8);
+    check(c, launch_big_tiles(s, kc, tiles, big, big_off, h_misc.n_big, keys, tmp, counts,
+                              tile_out, &misc->distinct), "big_tiles");
   }
+  kend(c, KMC_K_BIG_TILES, s);
   check(c, hipEventRecord(c->ev[4], s), "event");
 
   // ---- assemble: offsets of every tile's output, bin offsets, gather
   uint64_t* tile_off = ensure<uint64_t>(c, B_TILEOFF, (n_tiles + 1) * 8);
   uint64_t* scan_tmp = ensure<uint64_t>(c, B_SCANTMP, scan_tmp_words(n_tiles) * 8);
+  kbeg(c, KMC_K_ASSEMBLE, s);
   check(c, launch_scan_u32(s, tile_out, n_tiles, tile_off, scan_tmp), "scan");
   uint64_t* bin_off = ensure<uint64_t>(c, B_BINOFF, ((size_t)J.n_bins + 1) * 8);
   check(c, launch_bin_offsets(s, tile_off, d_tile_base, J.n_bins, bin_off), "bin_offsets");
+  kend(c, KMC_K_ASSEMBLE, s);
   check(c, hipMemcpyAsync(T->bin_offsets, bin_off, ((size_t)J.n_bins + 1) * 8,
                           hipMemcpyDeviceToHost, s), "D2H");
   check(c, hipMemcpyAsync(&h_misc, misc, sizeof(Misc), hipMemcpyDeviceToHost, s), "D2H");
@@ -386,7 +432,9 @@ void run_count(kmc_ctx* c, const kmc_reads* R, const kmc_params* P, kmc_table* T
     out_k = ensure<uint64_t>(c, B_OUTK, n_out * J.kw * 8);
     out_c = ensure<uint32_t>(c, B_OUTC, n_out * 4);
   }
+  check(c, hipEventRecord(c->ev[28], s), "event");
   check(c, launch_gather(s, kc, tiles, n_tiles, tile_off, keys, counts, out_k, out_c), "gather");
+  check(c, hipEventRecord(c->ev[29], s), "event");
   check(c, hipEventRecord(c->ev[5], s), "event");
   if (!T->on_device) {
     T->keys = static_cast<uint64_t*>(std::malloc(std::max<uint64_t>(1, n_out * J.kw) * 8));
@@ -404,6 +452,9 @@ void run_count(kmc_ctx* c, const kmc_reads* R, const kmc_params* P, kmc_table* T
   st.us_sort = 1e3 * ev_ms(c->ev[3], c->ev[4]);
   st.us_assemble = 1e3 * ev_ms(c->ev[4], c->ev[5]);
   st.us_total = 1e3 * ev_ms(c->ev[0], c->ev[5]);
+  for (int i = 0; i < KMC_N_KERNELS; ++i)
+    st.us_kernel[i] = 1e3 * ev_ms(c->ev[8 + 2 * i], c->ev[9 + 2 * i]);
+  st.us_kernel[KMC_K_ASSEMBLE] += 1e3 * ev_ms(c->ev[28], c->ev[29]);
   // algorithmic bytes: input once, 2-bit payload of every super k-mer written
   // and read once (ceil(l/4) + 2 bytes each), keys written and read once,
   // output written once

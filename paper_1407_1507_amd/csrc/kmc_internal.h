@@ -8,10 +8,6 @@
 namespace kmc {
 
 // Sizes of the work units.
-constexpr int kScanThreads = 256;        // one read per thread in the split kernels
-constexpr int kStageCap1 = 2048;         // super k-mer records staged per split WG (1-word keys)
-constexpr int kStageCap2 = 1024;         // same, 2-word keys
-constexpr int kLdsBinsMax = 4096;        // bins counted in LDS; more bins use global atomics
 constexpr int kExpandThreads = 256;      // records per expansion task (one per thread)
 constexpr int kExpandStage1 = 4096;      // keys staged per expansion flush (1-word keys)
 constexpr int kExpandStage2 = 2048;      // same, 2-word keys
@@ -48,24 +44,22 @@ struct Tile {
 // ---------------------------------------------------------------- launchers
 // All launchers enqueue on `s` and return the launch status.
 
-// Histogram of signatures, weighted by k-mers, over reads r with r % stride == 0.
+// Signature histograms of reads r with r % stride == 0: hist[sig] = k-mers,
+// hist[4^p + 1 + sig] = super k-mers; sample[0] += k-mers, sample[1] += bases.
 hipError_t launch_sig_hist(hipStream_t s, const uint8_t* seq, const uint64_t* offsets,
                            uint64_t n_reads, uint64_t n_bases, uint64_t stride,
                            const ScanCfg& cfg, uint32_t key_words, uint32_t* hist,
-                           unsigned long long* sample_kmers);
+                           unsigned long long* sample);
 
-// Per-bin records and k-mers (atomically added into rec_cnt / kmer_cnt).
-hipError_t launch_split_count(hipStream_t s, const uint8_t* seq, const uint64_t* offsets,
-                              uint64_t n_reads, uint64_t n_bases, const ScanCfg& cfg,
-                              uint32_t key_words, const uint32_t* sig_to_bin,
-                              unsigned long long* rec_cnt, unsigned long long* kmer_cnt);
-
-// Write every super k-mer record into its bin; cursor[b] starts at the bin's
-// first record slot and is advanced atomically.
+// Write every super k-mer record into its bin's region [cap_base[b],
+// cap_base[b+1]).  cursor[b] starts at cap_base[b] and counts every record of
+// bin b (records past the region end are counted but not written);
+// kmer_cnt[b] += k-mers of bin b.
 hipError_t launch_split_scatter(hipStream_t s, const uint8_t* seq, const uint64_t* offsets,
                                 uint64_t n_reads, uint64_t n_bases, const ScanCfg& cfg,
                                 uint32_t key_words, const uint32_t* sig_to_bin,
-                                unsigned long long* cursor, uint64_t* records);
+                                unsigned long long* cursor, unsigned long long* kmer_cnt,
+                                const uint64_t* cap_base, uint64_t* records);
 
 // Per-window signature and super k-mer starts (audit).
 hipError_t launch_debug_sigs(hipStream_t s, const uint8_t* seq, const uint64_t* offsets,
@@ -101,22 +95,23 @@ hipError_t launch_expand_scatter(hipStream_t s, const KeyCfg& kc, const ExpandTa
                                  uint32_t max_tiles_per_bin,
                                  unsigned long long* tile_cursor, uint64_t* keys);
 
-// Sort + count every tile that fits LDS; tiles larger than tile_cap are
-// appended to big_list.  Output of a tile is written over its own keys
-// (out_counts at the same indices); tile_out[t] = entries kept, and
-// distinct[0] += distinct keys.
-// n_big[0] counts the big tiles, n_big[1] receives the largest big tile size.
+// Sort + count every tile that fits LDS.  Output of a tile is written over
+// its own keys (out_counts at the same indices); tile_out[t] = entries kept,
+// distinct[0] += distinct keys.  Tiles larger than LDS are appended to
+// big_list (count in n_big[0]) with a private slice of the HBM scratch at
+// big_off (its size summed into big_total).
 hipError_t launch_tile_sort(hipStream_t s, const KeyCfg& kc, const Tile* tiles,
                             uint64_t n_tiles, uint64_t* keys, uint32_t* out_counts,
-                            uint32_t* tile_out, uint32_t* big_list, uint32_t* n_big,
+                            uint32_t* tile_out, uint32_t* big_list, uint64_t* big_off,
+                            uint32_t* n_big, unsigned long long* big_total,
                             unsigned long long* distinct);
 
-// Sort + count the big tiles (MSD partition through HBM, tmp has room for the
-// largest big tile).
+// Sort + count the big tiles: MSD partition through HBM, each tile
+// ping-ponging between its keys and its own slice tmp[big_off[i] ...].
 hipError_t launch_big_tiles(hipStream_t s, const KeyCfg& kc, const Tile* tiles,
-                            const uint32_t* big_list, uint32_t n_big, uint64_t* keys,
-                            uint64_t* tmp, uint32_t* out_counts, uint32_t* tile_out,
-                            unsigned long long* distinct);
+                            const uint32_t* big_list, const uint64_t* big_off, uint32_t n_big,
+                            uint64_t* keys, uint64_t* tmp, uint32_t* out_counts,
+                            uint32_t* tile_out, unsigned long long* distinct);
 
 // Exclusive scan of n uint32 into uint64 (out has n + 1 entries: out[n] = total).
 hipError_t launch_scan_u32(hipStream_t s, const uint32_t* in, uint64_t n, uint64_t* out,

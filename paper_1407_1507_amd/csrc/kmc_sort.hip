@@ -31,7 +31,7 @@ template <> struct SortCfg<1> {
 template <> struct SortCfg<2> {
   static constexpr uint32_t CAP = kTileCap2, DIG = 11, ITEMS = kTileCap2 / kSortThreads;
 };
-constexpr uint32_t kInsMax = 24;    // buckets up to this size: insertion sort by one lane
+constexpr uint32_t kInsMax = 32;    // mixed buckets up to this size: insertion sort by one lane
 constexpr uint32_t kBigMax = 256;   // large buckets listed per tile (CAP / kInsMax < 256)
 
 __device__ __forceinline__ uint64_t load_key(const uint64_t* p, uint64_t i, uint64_t*) { return p[i]; }
@@ -141,7 +141,11 @@ __device__ uint32_t sort_count_emit(const uint64_t* src, uint32_t n, uint64_t* o
     return (n >= ci && n <= cx) ? 1u : 0u;
   }
   const uint32_t hb = high_bit(diff);
-  const uint32_t t = hb + 1 < DIG ? hb + 1 : DIG;
+  // digit width: about two buckets per key, at most DIG bits, at most the
+  // bits below the common prefix
+  uint32_t t = 32u - __clz(n) + 1u;
+  t = t < DIG ? t : DIG;
+  t = t < hb + 1 ? t : hb + 1;
   const uint32_t shift = hb + 1 - t;
   const uint32_t nb = 1u << t, dmask = nb - 1;
 
@@ -163,6 +167,11 @@ __device__ uint32_t sort_count_emit(const uint64_t* src, uint32_t n, uint64_t* o
   for (uint32_t d = tid * per; d < min(nb, (tid + 1) * per); ++d) {
     const uint32_t s = d ? S.H[d - 1] : 0, e = S.H[d];
     if (e - s <= 1) continue;
+    // one key repeated (a k-mer seen many times): already in order
+    const K first = S.A[s];
+    uint32_t i = s + 1;
+    while (i < e && S.A[i] == first) ++i;
+    if (i == e) continue;
     if (e - s <= kInsMax) {
       for (uint32_t i = s + 1; i < e; ++i) {
         const K x = S.A[i];
@@ -242,8 +251,8 @@ __device__ uint32_t sort_count_emit(const uint64_t* src, uint32_t n, uint64_t* o
 template <int KW>
 __global__ void __launch_bounds__(kSortThreads)
 k_tile_sort(KeyCfg kc, const Tile* __restrict__ tiles, uint64_t* keys, uint32_t* counts,
-            uint32_t* tile_out, uint32_t* big_list, uint32_t* n_big, uint32_t* max_big,
-            unsigned long long* distinct) {
+            uint32_t* tile_out, uint32_t* big_list, uint64_t* big_off, uint32_t* n_big,
+            unsigned long long* big_total, unsigned long long* distinct) {
   __shared__ SortShared<KW> S;
   const uint64_t t = blockIdx.x;
   const Tile T = tiles[t];
@@ -254,8 +263,9 @@ k_tile_sort(KeyCfg kc, const Tile* __restrict__ tiles, uint64_t* keys, uint32_t*
   if (T.size > SortCfg<KW>::CAP) {
     if (threadIdx.x == 0) {
       tile_out[t] = 0;
-      big_list[atomicAdd(n_big, 1u)] = (uint32_t)t;
-      atomicMax(max_big, T.size);
+      const uint32_t idx = atomicAdd(n_big, 1u);
+      big_list[idx] = (uint32_t)t;
+      big_off[idx] = atomicAdd(big_total, (unsigned long long)T.size);  // own slice of tmp
     }
     return;
   }
@@ -285,8 +295,8 @@ template <int KW> struct MaxLevels { static constexpr int N = KW == 1 ? 10 : 18;
 template <int KW>
 __global__ void __launch_bounds__(kSortThreads)
 k_big_tiles(KeyCfg kc, const Tile* __restrict__ tiles, const uint32_t* __restrict__ big_list,
-            uint64_t* keys, uint64_t* tmp, uint32_t* counts, uint32_t* tile_out,
-            unsigned long long* distinct) {
+            const uint64_t* __restrict__ big_off, uint64_t* keys, uint64_t* tmp,
+            uint32_t* counts, uint32_t* tile_out, unsigned long long* distinct) {
   typedef typename KeyOf<KW>::T K;
   __shared__ SortShared<KW> S;
   __shared__ Level L[MaxLevels<KW>::N];
@@ -295,7 +305,7 @@ k_big_tiles(KeyCfg kc, const Tile* __restrict__ tiles, const uint32_t* __restric
   const uint32_t tid = threadIdx.x, nt = blockDim.x;
   const uint32_t t = big_list[blockIdx.x];
   const Tile T = tiles[t];
-  uint64_t* bufs[2] = {keys + T.begin * KW, tmp};
+  uint64_t* bufs[2] = {keys + T.begin * KW, tmp + big_off[blockIdx.x] * KW};
   if (tid == 0) {
     L[0].base = 0;
     L[0].next = 0;
@@ -315,9 +325,14 @@ k_big_tiles(KeyCfg kc, const Tile* __restrict__ tiles, const uint32_t* __restric
       --depth;
       continue;
     }
-    if (tid == 0) L[depth].next = c + 1;
+    // consecutive children that fit LDS together are sorted as one piece
+    // (they are adjacent key ranges, adjacent in the buffer)
+    uint32_t c2 = c + 1;
+    if (L[depth].cs[c2] - L[depth].cs[c] <= SortCfg<KW>::CAP)
+      while (c2 < nch && L[depth].cs[c2 + 1] - L[depth].cs[c] <= SortCfg<KW>::CAP) ++c2;
+    if (tid == 0) L[depth].next = c2;
     const uint64_t off = L[depth].base + L[depth].cs[c];
-    const uint32_t n = L[depth].cs[c + 1] - L[depth].cs[c];
+    const uint32_t n = L[depth].cs[c2] - L[depth].cs[c];
     const uint32_t buf = L[depth].buf;
     const uint64_t* src = bufs[buf] + off * KW;
     __syncthreads();
@@ -481,30 +496,32 @@ k_gather(const Tile* __restrict__ tiles, const uint64_t* __restrict__ tile_off,
 
 hipError_t launch_tile_sort(hipStream_t s, const KeyCfg& kc, const Tile* tiles,
                             uint64_t n_tiles, uint64_t* keys, uint32_t* out_counts,
-                            uint32_t* tile_out, uint32_t* big_list, uint32_t* n_big,
+                            uint32_t* tile_out, uint32_t* big_list, uint64_t* big_off,
+                            uint32_t* n_big, unsigned long long* big_total,
                             unsigned long long* distinct) {
   if (n_tiles == 0) return hipSuccess;
-  uint32_t* max_big = n_big + 1;
   if (kc.key_words == 1)
     hipLaunchKernelGGL(k_tile_sort<1>, dim3((uint32_t)n_tiles), dim3(kSortThreads), 0, s, kc,
-                       tiles, keys, out_counts, tile_out, big_list, n_big, max_big, distinct);
+                       tiles, keys, out_counts, tile_out, big_list, big_off, n_big, big_total,
+                       distinct);
   else
     hipLaunchKernelGGL(k_tile_sort<2>, dim3((uint32_t)n_tiles), dim3(kSortThreads), 0, s, kc,
-                       tiles, keys, out_counts, tile_out, big_list, n_big, max_big, distinct);
+                       tiles, keys, out_counts, tile_out, big_list, big_off, n_big, big_total,
+                       distinct);
   return hipGetLastError();
 }
 
 hipError_t launch_big_tiles(hipStream_t s, const KeyCfg& kc, const Tile* tiles,
-                            const uint32_t* big_list, uint32_t n_big, uint64_t* keys,
-                            uint64_t* tmp, uint32_t* out_counts, uint32_t* tile_out,
-                            unsigned long long* distinct) {
+                            const uint32_t* big_list, const uint64_t* big_off, uint32_t n_big,
+                            uint64_t* keys, uint64_t* tmp, uint32_t* out_counts,
+                            uint32_t* tile_out, unsigned long long* distinct) {
   if (n_big == 0) return hipSuccess;
   if (kc.key_words == 1)
     hipLaunchKernelGGL(k_big_tiles<1>, dim3(n_big), dim3(kSortThreads), 0, s, kc, tiles,
-                       big_list, keys, tmp, out_counts, tile_out, distinct);
+                       big_list, big_off, keys, tmp, out_counts, tile_out, distinct);
   else
     hipLaunchKernelGGL(k_big_tiles<2>, dim3(n_big), dim3(kSortThreads), 0, s, kc, tiles,
-                       big_list, keys, tmp, out_counts, tile_out, distinct);
+                       big_list, big_off, keys, tmp, out_counts, tile_out, distinct);
   return hipGetLastError();
 }
 

@@ -44,89 +44,88 @@ struct SeqReader {
   }
 };
 
-__device__ __forceinline__ uint32_t fetch_byte(const uint8_t* seq, uint64_t n, bool a4, uint64_t pos) {
-  if (a4 && (pos | 3ull) < n) {
-    uint32_t w = reinterpret_cast<const uint32_t*>(seq)[pos >> 2];
-    return (w >> ((pos & 3u) << 3)) & 0xFFu;
-  }
-  return seq[pos];
-}
 
-// Scan bytes [x0, x1) of one read.  For every valid k-mer start j the sink
-// sees kmer(j, signature); every super k-mer is passed to
-// sink.superkmer(first k-mer start, number of k-mers, signature, forward key
-// of the first k-mer, tail symbols after the first k-mer).  A super k-mer is
-// also closed after w = k - p + 1 k-mers, so that it never holds more than
-// 2k - p symbols (the count does not depend on where super k-mers are cut).
-template <int KW, class Sink>
+// Scan bytes [x0, x1) of one read.  For every k-mer start j the sink sees
+// kmer(j, signature) (0xFFFFFFFF if the k-mer holds an invalid byte); every
+// super k-mer is passed to sink.superkmer(first k-mer start, number of k-mers,
+// signature, forward key of the first k-mer, tail symbols after the first
+// k-mer).  A super k-mer is also closed after w = k - p + 1 k-mers, so that it
+// never holds more than 2k - p symbols (where super k-mers are cut does not
+// change the counts).
+//
+// Window minimum without data-dependent branches (van Herk / Gil-Werman):
+// p-mer values are grouped in blocks of w; when a block completes its suffix
+// minima are formed in place; the window of k-mer j spans the suffix of one
+// block and the prefix of the next, so its minimum is min(suffix[j],
+// running prefix minimum).  Each lane keeps the current and previous block in
+// its own slice vh[0 .. 2w) of LDS.  A p-mer holding an invalid byte is stored
+// as 0 and a valid one as (value + 1), so a window minimum of 0 flags an
+// invalid k-mer and N bases need no separate branch.
+template <int KW, class VT, class Sink>
 __device__ __forceinline__ void scan_read(const uint8_t* __restrict__ seq, uint64_t n_bases,
-                                          uint64_t x0, uint64_t x1, const ScanCfg& C,
+                                          uint64_t x0, uint64_t x1, const ScanCfg& C, VT* vh,
                                           Sink& sink) {
   typedef typename KeyOf<KW>::T K;
-  const uint32_t k = C.k, p = C.p;
+  const uint32_t k = C.k, p = C.p, w = C.w;
   const K kmask = key_mask<K>(k);
   const uint32_t rcs = 2 * p - 2;
   SeqReader rd(seq, n_bases, C.aligned4 != 0);
-  uint32_t run = 0, fp = 0, rp = 0, minv = 0;
-  uint64_t minpos = 0;
+  uint32_t run = 0, fp = 0, rp = 0;
+  uint32_t in_blk = 0, par = 0, pre = 0;
   uint32_t cur_n = 0, cur_sig = 0;
   uint64_t cur_start = 0;
   K F = 0, curF = 0, tail = 0;
+  const uint64_t xp = x0 + p - 1;  // first byte completing a p-mer
+  const uint64_t xk = x0 + k - 1;  // first byte completing a k-mer
   for (uint64_t x = x0; x < x1; ++x) {
     bool ok;
     const uint32_t c = decode_base(rd.get(x), ok);
-    if (!ok) {
-      if (cur_n) sink.superkmer(cur_start, cur_n, cur_sig, curF, tail);
-      cur_n = 0;
-      run = 0;
-      continue;
-    }
-    ++run;
+    run = ok ? run + 1 : 0;
     fp = ((fp << 2) | c) & C.pmask;
     rp = (rp >> 2) | ((3u - c) << rcs);
     if (Sink::kNeedKeys) F = ((F << 2) | (K)c) & kmask;
-    if (run >= p) {
-      const uint32_t can = min(fp, rp);
-      const uint32_t a = (!C.filter || sig_allowed(can, p)) ? can : C.sent;
-      if (run == p || a <= minv) {  // ties keep the newest position
-        minv = a;
-        minpos = x + 1 - p;
+    if (x < xp) continue;
+    const uint32_t can = min(fp, rp);
+    const uint32_t v =
+        run >= p ? ((!C.filter || sig_allowed(can, p)) ? can : C.sent) + 1u : 0u;
+    pre = in_blk == 0 ? v : min(pre, v);
+    VT* cur = vh + par * w;
+    cur[in_blk] = (VT)v;
+    if (in_blk == w - 1) {
+      uint32_t r = v;
+      for (int i = (int)w - 2; i >= 0; --i) {
+        r = min(r, (uint32_t)cur[i]);
+        cur[i] = (VT)r;
       }
     }
-    if (run < k) continue;
-    const uint64_t j = x + 1 - k;
-    if (minpos < j) {
-      // the minimum left the window: re-scan the p-mers of k-mer j
-      uint32_t f2 = 0, r2 = 0, m = 0xFFFFFFFFu;
-      uint64_t mp = j;
-      for (uint64_t y = j; y <= x; ++y) {
-        bool ok2;
-        const uint32_t c2 = decode_base(fetch_byte(seq, n_bases, C.aligned4 != 0, y), ok2);
-        f2 = ((f2 << 2) | c2) & C.pmask;
-        r2 = (r2 >> 2) | ((3u - c2) << rcs);
-        if (y + 1 >= j + p) {
-          const uint32_t can = min(f2, r2);
-          const uint32_t a = (!C.filter || sig_allowed(can, p)) ? can : C.sent;
-          if (a <= m) {
-            m = a;
-            mp = y + 1 - p;
-          }
+    if (x >= xk) {
+      const uint32_t suf =
+          in_blk == w - 1 ? (uint32_t)cur[0] : (uint32_t)vh[(par ^ 1u) * w + in_blk + 1];
+      const uint32_t m = min(suf, pre);
+      const uint64_t j = x + 1 - k;
+      if (m == 0) {
+        sink.kmer(j, 0xFFFFFFFFu);
+        if (cur_n) sink.superkmer(cur_start, cur_n, cur_sig, curF, tail);
+        cur_n = 0;
+      } else {
+        const uint32_t sig = m - 1;
+        sink.kmer(j, sig);
+        if (cur_n && sig == cur_sig && cur_n < w) {
+          ++cur_n;
+          if (Sink::kNeedKeys) tail = (tail << 2) | (K)c;
+        } else {
+          if (cur_n) sink.superkmer(cur_start, cur_n, cur_sig, curF, tail);
+          cur_start = j;
+          cur_n = 1;
+          cur_sig = sig;
+          curF = F;
+          tail = 0;
         }
       }
-      minv = m;
-      minpos = mp;
     }
-    sink.kmer(j, minv);
-    if (cur_n && minv == cur_sig && cur_n < C.w) {
-      ++cur_n;
-      if (Sink::kNeedKeys) tail = (tail << 2) | (K)c;
-    } else {
-      if (cur_n) sink.superkmer(cur_start, cur_n, cur_sig, curF, tail);
-      cur_start = j;
-      cur_n = 1;
-      cur_sig = minv;
-      curF = F;
-      tail = 0;
+    if (++in_blk == w) {
+      in_blk = 0;
+      par ^= 1u;
     }
   }
   if (cur_n) sink.superkmer(cur_start, cur_n, cur_sig, curF, tail);
@@ -149,145 +148,129 @@ __device__ __forceinline__ void make_record(uint64_t* r, u128 F, u128 tail, uint
   r[3] = (uint64_t)t;
 }
 
+// Lane-private LDS slices for the window buffer: stride 2w + 1 elements.
+template <class VT>
+__device__ __forceinline__ VT* lane_vh(void* lds, uint32_t w) {
+  return reinterpret_cast<VT*>(lds) + threadIdx.x * (2 * w + 1);
+}
+
 // ------------------------------------------------------------ sample hist
 
 template <int KW>
 struct HistSink {
   static constexpr bool kNeedKeys = false;
-  uint32_t* hist;
+  uint32_t* hist_k;   // k-mers per signature
+  uint32_t* hist_r;   // super k-mers per signature
   uint64_t kmers;
   __device__ void kmer(uint64_t, uint32_t) {}
   __device__ void superkmer(uint64_t, uint32_t n, uint32_t sig,
                             typename KeyOf<KW>::T, typename KeyOf<KW>::T) {
-    atomicAdd(&hist[sig], n);
+    atomicAdd(&hist_k[sig], n);
+    atomicAdd(&hist_r[sig], 1u);
     kmers += n;
   }
 };
 
-template <int KW>
-__global__ void __launch_bounds__(kScanThreads)
+template <int KW, class VT>
+__global__ void __launch_bounds__(256)
 k_sig_hist(const uint8_t* __restrict__ seq, const uint64_t* __restrict__ offsets,
            uint64_t n_reads, uint64_t n_bases, uint64_t stride, ScanCfg C, uint32_t* hist,
-           unsigned long long* sample_kmers) {
+           unsigned long long* sample) {
+  extern __shared__ __attribute__((aligned(16))) uint8_t lds8[];
   const uint64_t r = ((uint64_t)blockIdx.x * blockDim.x + threadIdx.x) * stride;
-  HistSink<KW> sink{hist, 0};
-  if (r < n_reads) scan_read<KW>(seq, n_bases, offsets[r], offsets[r + 1], C, sink);
-  if (sink.kmers) atomicAdd(sample_kmers, (unsigned long long)sink.kmers);
-}
-
-// ------------------------------------------------------------ split count
-
-template <int KW, bool LDS>
-struct CountSink {
-  static constexpr bool kNeedKeys = false;
-  const uint32_t* map;
-  uint32_t* lrec;
-  uint32_t* lkmer;
-  unsigned long long* grec;
-  unsigned long long* gkmer;
-  __device__ void kmer(uint64_t, uint32_t) {}
-  __device__ void superkmer(uint64_t, uint32_t n, uint32_t sig,
-                            typename KeyOf<KW>::T, typename KeyOf<KW>::T) {
-    const uint32_t b = map[sig];
-    if (LDS) {
-      atomicAdd(&lrec[b], 1u);
-      atomicAdd(&lkmer[b], n);
-    } else {
-      atomicAdd(&grec[b], 1ull);
-      atomicAdd(&gkmer[b], (unsigned long long)n);
-    }
+  const uint32_t n_sig = C.sent + 1;
+  HistSink<KW> sink{hist, hist + n_sig, 0};
+  uint64_t bases = 0;
+  if (r < n_reads) {
+    bases = offsets[r + 1] - offsets[r];
+    scan_read<KW, VT>(seq, n_bases, offsets[r], offsets[r + 1], C, lane_vh<VT>(lds8, C.w), sink);
   }
-};
-
-template <int KW, bool LDS>
-__global__ void __launch_bounds__(kScanThreads)
-k_split_count(const uint8_t* __restrict__ seq, const uint64_t* __restrict__ offsets,
-              uint64_t n_reads, uint64_t n_bases, ScanCfg C, const uint32_t* __restrict__ map,
-              unsigned long long* rec_cnt, unsigned long long* kmer_cnt) {
-  extern __shared__ uint32_t lds[];
-  uint32_t* lrec = lds;
-  uint32_t* lkmer = lds + (LDS ? C.n_bins : 0);
-  if (LDS) {
-    for (uint32_t i = threadIdx.x; i < C.n_bins; i += blockDim.x) lrec[i] = lkmer[i] = 0;
-    __syncthreads();
-  }
-  const uint64_t r = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  CountSink<KW, LDS> sink{map, lrec, lkmer, rec_cnt, kmer_cnt};
-  if (r < n_reads) scan_read<KW>(seq, n_bases, offsets[r], offsets[r + 1], C, sink);
-  if (LDS) {
-    __syncthreads();
-    for (uint32_t i = threadIdx.x; i < C.n_bins; i += blockDim.x) {
-      if (lrec[i]) {
-        atomicAdd(&rec_cnt[i], (unsigned long long)lrec[i]);
-        atomicAdd(&kmer_cnt[i], (unsigned long long)lkmer[i]);
-      }
-    }
-  }
+  if (sink.kmers) atomicAdd(&sample[0], (unsigned long long)sink.kmers);
+  if (bases) atomicAdd(&sample[1], (unsigned long long)bases);
 }
 
 // ---------------------------------------------------------- split scatter
+// One pass: every super k-mer record goes to its bin's region, whose size was
+// estimated from the sample.  cursor[b] counts every record of bin b; records
+// past the region end are not written (the host then repeats the pass with
+// the exact sizes the cursors report).
 
-template <int KW>
+template <int KW, bool STAGE>
 struct ScatterSink {
   static constexpr bool kNeedKeys = true;
   static constexpr int RW = 2 * KW;  // record words
   const uint32_t* map;
   uint32_t cap;
   uint32_t* lnum;     // staged records
-  uint32_t* lcnt;     // per bin
+  uint32_t* lcnt;     // staged records per bin
+  uint32_t* lkm;      // k-mers per bin
   uint64_t* stage;    // cap * RW
   uint32_t* sbin;     // cap
   uint16_t* srank;    // cap
   unsigned long long* gcursor;
+  unsigned long long* gkmer;
+  const uint64_t* cap_base;  // region of bin b: [cap_base[b], cap_base[b+1])
   uint64_t* records;
   __device__ void kmer(uint64_t, uint32_t) {}
   __device__ void superkmer(uint64_t, uint32_t n, uint32_t sig, typename KeyOf<KW>::T F,
                             typename KeyOf<KW>::T tail) {
     const uint32_t b = map[sig];
-    const uint32_t idx = cap ? atomicAdd(lnum, 1u) : 0u;
     uint64_t rec[RW];
     make_record(rec, F, tail, n);
-    if (idx < cap) {
-      srank[idx] = (uint16_t)atomicAdd(&lcnt[b], 1u);
-      sbin[idx] = b;
+    if (STAGE) {
+      atomicAdd(&lkm[b], n);
+      const uint32_t idx = atomicAdd(lnum, 1u);
+      if (idx < cap) {
+        srank[idx] = (uint16_t)atomicAdd(&lcnt[b], 1u);
+        sbin[idx] = b;
 #pragma unroll
-      for (int q = 0; q < RW; ++q) stage[(uint64_t)idx * RW + q] = rec[q];
+        for (int q = 0; q < RW; ++q) stage[(uint64_t)idx * RW + q] = rec[q];
+        return;
+      }
     } else {
-      // staging full: reserve this one record directly
-      const uint64_t g = atomicAdd(&gcursor[b], 1ull);
+      atomicAdd(&gkmer[b], (unsigned long long)n);
+    }
+    // not staged: claim one slot directly
+    const uint64_t g = atomicAdd(&gcursor[b], 1ull);
+    if (g < cap_base[b + 1]) {
 #pragma unroll
       for (int q = 0; q < RW; ++q) records[g * RW + q] = rec[q];
     }
   }
 };
 
-template <int KW>
-__global__ void __launch_bounds__(kScanThreads)
+template <int KW, class VT>
+__global__ void __launch_bounds__(256)
 k_split_scatter(const uint8_t* __restrict__ seq, const uint64_t* __restrict__ offsets,
                 uint64_t n_reads, uint64_t n_bases, ScanCfg C, const uint32_t* __restrict__ map,
-                unsigned long long* gcursor, uint64_t* records, uint32_t cap) {
+                unsigned long long* gcursor, unsigned long long* gkmer,
+                const uint64_t* __restrict__ cap_base, uint64_t* records, uint32_t cap,
+                uint32_t vh_bytes) {
   constexpr int RW = 2 * KW;
-  extern __shared__ uint64_t lds64[];
-  // layout: stage[cap*RW] u64 | delta[n_bins] u64 | lcnt[n_bins] u32 | lbase[n_bins] u32 |
+  extern __shared__ __attribute__((aligned(16))) uint8_t lds8[];
+  // layout: vh | stage[cap*RW] u64 | delta[n_bins] u64 | lcnt, lbase, lkm [n_bins] u32 |
   //         sbin[cap] u32 | inv[cap] u16 | srank[cap] u16 | lnum, scan tmp
-  uint64_t* stage = lds64;
+  uint64_t* stage = reinterpret_cast<uint64_t*>(lds8 + vh_bytes);
   uint64_t* delta = stage + (uint64_t)cap * RW;
   uint32_t* lcnt = reinterpret_cast<uint32_t*>(delta + C.n_bins);
   uint32_t* lbase = lcnt + C.n_bins;
-  uint32_t* sbin = lbase + C.n_bins;
+  uint32_t* lkm = lbase + C.n_bins;
+  uint32_t* sbin = lkm + C.n_bins;
   uint16_t* inv = reinterpret_cast<uint16_t*>(sbin + cap);
   uint16_t* srank = inv + cap;
   uint32_t* misc = reinterpret_cast<uint32_t*>(srank + cap);
   uint32_t* lnum = misc;
   uint32_t* tmp = misc + 1;
 
-  for (uint32_t i = threadIdx.x; i < C.n_bins; i += blockDim.x) lcnt[i] = 0;
+  for (uint32_t i = threadIdx.x; i < C.n_bins; i += blockDim.x) lcnt[i] = lkm[i] = 0;
   if (threadIdx.x == 0) *lnum = 0;
   __syncthreads();
 
   const uint64_t r = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  ScatterSink<KW> sink{map, cap, lnum, lcnt, stage, sbin, srank, gcursor, records};
-  if (r < n_reads) scan_read<KW>(seq, n_bases, offsets[r], offsets[r + 1], C, sink);
+  ScatterSink<KW, true> sink{map, cap, lnum, lcnt, lkm, stage, sbin, srank,
+                             gcursor, nullptr, cap_base, records};
+  if (r < n_reads)
+    scan_read<KW, VT>(seq, n_bases, offsets[r], offsets[r + 1], C, lane_vh<VT>(lds8, C.w), sink);
   __syncthreads();
 
   const uint32_t nst = min(*lnum, cap);
@@ -300,6 +283,7 @@ k_split_scatter(const uint8_t* __restrict__ seq, const uint64_t* __restrict__ of
       const uint64_t g = atomicAdd(&gcursor[i], (unsigned long long)lcnt[i]);
       delta[i] = g - lbase[i];
     }
+    if (lkm[i]) atomicAdd(&gkmer[i], (unsigned long long)lkm[i]);
   }
   for (uint32_t i = threadIdx.x; i < nst; i += blockDim.x)
     inv[lbase[sbin[i]] + srank[i]] = (uint16_t)i;
@@ -307,23 +291,29 @@ k_split_scatter(const uint8_t* __restrict__ seq, const uint64_t* __restrict__ of
   // write records grouped by bin: consecutive lanes -> consecutive slots
   for (uint32_t q = threadIdx.x; q < nst; q += blockDim.x) {
     const uint32_t i = inv[q];
-    const uint64_t g = delta[sbin[i]] + q;
+    const uint32_t b = sbin[i];
+    const uint64_t g = delta[b] + q;
+    if (g < cap_base[b + 1]) {
 #pragma unroll
-    for (int w = 0; w < RW; ++w) records[g * RW + w] = stage[(uint64_t)i * RW + w];
+      for (int w = 0; w < RW; ++w) records[g * RW + w] = stage[(uint64_t)i * RW + w];
+    }
   }
 }
 
-// Same output without LDS staging (for bin counts whose LDS counters do not
-// fit): one atomic slot claim per record.
-template <int KW>
-__global__ void __launch_bounds__(kScanThreads)
+// Same output without LDS staging (bin counts whose LDS arrays do not fit).
+template <int KW, class VT>
+__global__ void __launch_bounds__(256)
 k_split_scatter_direct(const uint8_t* __restrict__ seq, const uint64_t* __restrict__ offsets,
                        uint64_t n_reads, uint64_t n_bases, ScanCfg C,
                        const uint32_t* __restrict__ map, unsigned long long* gcursor,
+                       unsigned long long* gkmer, const uint64_t* __restrict__ cap_base,
                        uint64_t* records) {
+  extern __shared__ __attribute__((aligned(16))) uint8_t lds8[];
   const uint64_t r = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  ScatterSink<KW> sink{map, 0, nullptr, nullptr, nullptr, nullptr, nullptr, gcursor, records};
-  if (r < n_reads) scan_read<KW>(seq, n_bases, offsets[r], offsets[r + 1], C, sink);
+  ScatterSink<KW, false> sink{map, 0, nullptr, nullptr, nullptr, nullptr, nullptr, nullptr,
+                              gcursor, gkmer, cap_base, records};
+  if (r < n_reads)
+    scan_read<KW, VT>(seq, n_bases, offsets[r], offsets[r + 1], C, lane_vh<VT>(lds8, C.w), sink);
 }
 
 // ------------------------------------------------------------------ debug
@@ -340,13 +330,15 @@ struct DebugSink {
   }
 };
 
-template <int KW>
-__global__ void __launch_bounds__(kScanThreads)
+template <int KW, class VT>
+__global__ void __launch_bounds__(256)
 k_debug_sigs(const uint8_t* __restrict__ seq, const uint64_t* __restrict__ offsets,
              uint64_t n_reads, uint64_t n_bases, ScanCfg C, uint32_t* sig, uint8_t* start) {
+  extern __shared__ __attribute__((aligned(16))) uint8_t lds8[];
   const uint64_t r = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
   DebugSink<KW> sink{sig, start};
-  if (r < n_reads) scan_read<KW>(seq, n_bases, offsets[r], offsets[r + 1], C, sink);
+  if (r < n_reads)
+    scan_read<KW, VT>(seq, n_bases, offsets[r], offsets[r + 1], C, lane_vh<VT>(lds8, C.w), sink);
 }
 
 __global__ void k_check_offsets(const uint64_t* __restrict__ off, uint64_t n_reads,
@@ -366,80 +358,88 @@ uint32_t grid_for(uint64_t n, uint32_t per) { return (uint32_t)((n + per - 1) / 
 
 // --------------------------------------------------------------- launchers
 
+// Window buffers hold u16 when every stored value (4^p + 1 at most) fits.
+static bool small_vt(const ScanCfg& c) { return c.sent + 1u <= 0xFFFFu; }
+static size_t vh_bytes(const ScanCfg& c, uint32_t lanes) {
+  const size_t b = (size_t)lanes * (2 * c.w + 1) * (small_vt(c) ? 2 : 4);
+  return (b + 15) & ~(size_t)15;
+}
+
+#define KMC_SCAN_DISPATCH(KERNEL, grid, lanes, sh, s, ...)                                    \
+  do {                                                                                      \
+    if (key_words == 1) {                                                                   \
+      if (small_vt(cfg)) {                                                                  \
+        (void)hipFuncSetAttribute((const void*)KERNEL<1, uint16_t>,                         \
+                                  hipFuncAttributeMaxDynamicSharedMemorySize, (int)(sh));   \
+        hipLaunchKernelGGL((KERNEL<1, uint16_t>), grid, lanes, sh, s, __VA_ARGS__);         \
+      } else {                                                                              \
+        (void)hipFuncSetAttribute((const void*)KERNEL<1, uint32_t>,                         \
+                                  hipFuncAttributeMaxDynamicSharedMemorySize, (int)(sh));   \
+        hipLaunchKernelGGL((KERNEL<1, uint32_t>), grid, lanes, sh, s, __VA_ARGS__);         \
+      }                                                                                     \
+    } else {                                                                                \
+      if (small_vt(cfg)) {                                                                  \
+        (void)hipFuncSetAttribute((const void*)KERNEL<2, uint16_t>,                         \
+                                  hipFuncAttributeMaxDynamicSharedMemorySize, (int)(sh));   \
+        hipLaunchKernelGGL((KERNEL<2, uint16_t>), grid, lanes, sh, s, __VA_ARGS__);         \
+      } else {                                                                              \
+        (void)hipFuncSetAttribute((const void*)KERNEL<2, uint32_t>,                         \
+                                  hipFuncAttributeMaxDynamicSharedMemorySize, (int)(sh));   \
+        hipLaunchKernelGGL((KERNEL<2, uint32_t>), grid, lanes, sh, s, __VA_ARGS__);         \
+      }                                                                                     \
+    }                                                                                       \
+  } while (0)
+
+// lanes per workgroup for the plain scan kernels: window buffers <= 64 KB
+static uint32_t scan_lanes(const ScanCfg& c) {
+  uint32_t lanes = 256;
+  while (lanes > 64 && vh_bytes(c, lanes) > 64 * 1024) lanes >>= 1;
+  return lanes;
+}
+
 hipError_t launch_sig_hist(hipStream_t s, const uint8_t* seq, const uint64_t* offsets,
                            uint64_t n_reads, uint64_t n_bases, uint64_t stride,
                            const ScanCfg& cfg, uint32_t key_words, uint32_t* hist,
-                           unsigned long long* sample_kmers) {
+                           unsigned long long* sample) {
   const uint64_t n_sample = (n_reads + stride - 1) / stride;
   if (n_sample == 0) return hipSuccess;
-  const uint32_t g = grid_for(n_sample, kScanThreads);
-  if (key_words == 1)
-    hipLaunchKernelGGL(k_sig_hist<1>, dim3(g), dim3(kScanThreads), 0, s, seq, offsets, n_reads,
-                       n_bases, stride, cfg, hist, sample_kmers);
-  else
-    hipLaunchKernelGGL(k_sig_hist<2>, dim3(g), dim3(kScanThreads), 0, s, seq, offsets, n_reads,
-                       n_bases, stride, cfg, hist, sample_kmers);
+  const uint32_t lanes = scan_lanes(cfg);
+  const size_t sh = vh_bytes(cfg, lanes);
+  KMC_SCAN_DISPATCH(k_sig_hist, dim3(grid_for(n_sample, lanes)), dim3(lanes), sh, s, seq,
+                    offsets, n_reads, n_bases, stride, cfg, hist, sample);
   return hipGetLastError();
 }
 
-hipError_t launch_split_count(hipStream_t s, const uint8_t* seq, const uint64_t* offsets,
-                              uint64_t n_reads, uint64_t n_bases, const ScanCfg& cfg,
-                              uint32_t key_words, const uint32_t* sig_to_bin,
-                              unsigned long long* rec_cnt, unsigned long long* kmer_cnt) {
-  if (n_reads == 0) return hipSuccess;
-  const uint32_t g = grid_for(n_reads, kScanThreads);
-  const bool lds = cfg.n_bins <= (uint32_t)kLdsBinsMax;
-  const size_t sh = lds ? 2 * cfg.n_bins * sizeof(uint32_t) : 0;
-  if (key_words == 1) {
-    if (lds)
-      hipLaunchKernelGGL((k_split_count<1, true>), dim3(g), dim3(kScanThreads), sh, s, seq,
-                         offsets, n_reads, n_bases, cfg, sig_to_bin, rec_cnt, kmer_cnt);
-    else
-      hipLaunchKernelGGL((k_split_count<1, false>), dim3(g), dim3(kScanThreads), 0, s, seq,
-                         offsets, n_reads, n_bases, cfg, sig_to_bin, rec_cnt, kmer_cnt);
-  } else {
-    if (lds)
-      hipLaunchKernelGGL((k_split_count<2, true>), dim3(g), dim3(kScanThreads), sh, s, seq,
-                         offsets, n_reads, n_bases, cfg, sig_to_bin, rec_cnt, kmer_cnt);
-    else
-      hipLaunchKernelGGL((k_split_count<2, false>), dim3(g), dim3(kScanThreads), 0, s, seq,
-                         offsets, n_reads, n_bases, cfg, sig_to_bin, rec_cnt, kmer_cnt);
-  }
-  return hipGetLastError();
-}
-
-size_t split_scatter_lds(uint32_t key_words, uint32_t n_bins, uint32_t cap) {
+static size_t split_stage_lds(uint32_t key_words, uint32_t n_bins, uint32_t cap) {
   const uint32_t RW = 2 * key_words;
-  return (size_t)cap * RW * 8 + (size_t)n_bins * 8 + (size_t)n_bins * 8 + (size_t)cap * 4 +
-         (size_t)cap * 4 + 4 + 4 * (kScanThreads / 64) + 16;
+  return (size_t)cap * RW * 8 + (size_t)n_bins * 8 + (size_t)n_bins * 12 + (size_t)cap * 4 +
+         (size_t)cap * 4 + 4 + 4 * 4 + 16;
 }
 
 hipError_t launch_split_scatter(hipStream_t s, const uint8_t* seq, const uint64_t* offsets,
                                 uint64_t n_reads, uint64_t n_bases, const ScanCfg& cfg,
                                 uint32_t key_words, const uint32_t* sig_to_bin,
-                                unsigned long long* cursor, uint64_t* records) {
+                                unsigned long long* cursor, unsigned long long* kmer_cnt,
+                                const uint64_t* cap_base, uint64_t* records) {
   if (n_reads == 0) return hipSuccess;
-  const uint32_t g = grid_for(n_reads, kScanThreads);
-  // staging shrinks when many bins need LDS counters (65535 bins x 16 B = 1 MB
-  // does not fit: then the per-record path is taken for every record)
-  uint32_t cap = key_words == 1 ? kStageCap1 : kStageCap2;
-  while (cap > 256 && split_scatter_lds(key_words, cfg.n_bins, cap) > 64 * 1024) cap >>= 1;
-  if (split_scatter_lds(key_words, cfg.n_bins, cap) > 64 * 1024) {
-    if (key_words == 1)
-      hipLaunchKernelGGL(k_split_scatter_direct<1>, dim3(g), dim3(kScanThreads), 0, s, seq,
-                         offsets, n_reads, n_bases, cfg, sig_to_bin, cursor, records);
-    else
-      hipLaunchKernelGGL(k_split_scatter_direct<2>, dim3(g), dim3(kScanThreads), 0, s, seq,
-                         offsets, n_reads, n_bases, cfg, sig_to_bin, cursor, records);
-    return hipGetLastError();
+  // largest workgroup whose window buffers + staging fit 80 KB (two per CU)
+  const uint32_t per_lane = key_words == 1 ? 8 : 4;  // staged records per lane
+  for (uint32_t lanes = 256; lanes >= 64; lanes >>= 1) {
+    const uint32_t cap = lanes * per_lane;
+    const size_t vb = vh_bytes(cfg, lanes);
+    const size_t sh = vb + split_stage_lds(key_words, cfg.n_bins, cap);
+    if (sh <= 80 * 1024) {
+      KMC_SCAN_DISPATCH(k_split_scatter, dim3(grid_for(n_reads, lanes)), dim3(lanes), sh, s,
+                        seq, offsets, n_reads, n_bases, cfg, sig_to_bin, cursor, kmer_cnt,
+                        cap_base, records, cap, (uint32_t)vb);
+      return hipGetLastError();
+    }
   }
-  const size_t sh = split_scatter_lds(key_words, cfg.n_bins, cap);
-  if (key_words == 1)
-    hipLaunchKernelGGL(k_split_scatter<1>, dim3(g), dim3(kScanThreads), sh, s, seq, offsets,
-                       n_reads, n_bases, cfg, sig_to_bin, cursor, records, cap);
-  else
-    hipLaunchKernelGGL(k_split_scatter<2>, dim3(g), dim3(kScanThreads), sh, s, seq, offsets,
-                       n_reads, n_bases, cfg, sig_to_bin, cursor, records, cap);
+  const uint32_t lanes = scan_lanes(cfg);
+  const size_t sh = vh_bytes(cfg, lanes);
+  KMC_SCAN_DISPATCH(k_split_scatter_direct, dim3(grid_for(n_reads, lanes)), dim3(lanes), sh, s,
+                    seq, offsets, n_reads, n_bases, cfg, sig_to_bin, cursor, kmer_cnt, cap_base,
+                    records);
   return hipGetLastError();
 }
 
@@ -447,13 +447,10 @@ hipError_t launch_debug_sigs(hipStream_t s, const uint8_t* seq, const uint64_t* 
                              uint64_t n_reads, uint64_t n_bases, const ScanCfg& cfg,
                              uint32_t key_words, uint32_t* sig, uint8_t* start) {
   if (n_reads == 0) return hipSuccess;
-  const uint32_t g = grid_for(n_reads, kScanThreads);
-  if (key_words == 1)
-    hipLaunchKernelGGL(k_debug_sigs<1>, dim3(g), dim3(kScanThreads), 0, s, seq, offsets,
-                       n_reads, n_bases, cfg, sig, start);
-  else
-    hipLaunchKernelGGL(k_debug_sigs<2>, dim3(g), dim3(kScanThreads), 0, s, seq, offsets,
-                       n_reads, n_bases, cfg, sig, start);
+  const uint32_t lanes = scan_lanes(cfg);
+  const size_t sh = vh_bytes(cfg, lanes);
+  KMC_SCAN_DISPATCH(k_debug_sigs, dim3(grid_for(n_reads, lanes)), dim3(lanes), sh, s, seq,
+                    offsets, n_reads, n_bases, cfg, sig, start);
   return hipGetLastError();
 }
 

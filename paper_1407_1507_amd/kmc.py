@@ -22,6 +22,9 @@ KMC_ERR_OUT_OF_MEMORY = 2
 KMC_ERR_DEVICE = 3
 KMC_ERR_TOO_LARGE = 4
 KMC_ERR_BUSY = 5
+# device time of each kernel, in the order of kmc_stats.us_kernel
+KERNELS = ["sig_hist", "split", "fine_hist", "plan_tiles", "expand_scatter", "tile_sort",
+           "big_tiles", "assemble"]
 FLAG_DEVICE_TABLE = 0x1
 FLAG_PLAIN_MINIMIZERS = 0x2
 
@@ -50,12 +53,15 @@ class Params(ctypes.Structure):
 class Stats(ctypes.Structure):
     _fields_ = [(n, ctypes.c_uint64) for n in (
         "n_reads", "n_bases", "n_kmers", "n_superkmers", "n_distinct", "n_out", "sample_kmers",
-        "max_bin_kmers", "n_tiles", "n_big_tiles", "bytes_alg")] + [
+        "max_bin_kmers", "n_tiles", "n_big_tiles", "bytes_alg", "split_passes")] + [
         (n, ctypes.c_double) for n in (
-            "us_map", "us_split", "us_expand", "us_sort", "us_assemble", "us_total")]
+            "us_map", "us_split", "us_expand", "us_sort", "us_assemble", "us_total")] + [
+        ("us_kernel", ctypes.c_double * 8)]
 
     def as_dict(self):
-        return {n: getattr(self, n) for n, _ in self._fields_}
+        d = {n: getattr(self, n) for n, _ in self._fields_ if n != "us_kernel"}
+        d["us_kernel"] = dict(zip(KERNELS, list(self.us_kernel)))
+        return d
 
 
 class Table(ctypes.Structure):
@@ -72,9 +78,21 @@ class Table(ctypes.Structure):
 _lib = None
 
 
+def _one_hip_runtime():
+    """torch ships its own HIP runtime with the same soname as the system's.
+    Loading torch first makes the library bind to that already-loaded
+    runtime, so one process never holds two HIP runtimes (the second one to
+    start would find no GPU)."""
+    try:
+        import torch  # noqa: F401
+    except ImportError:
+        pass
+
+
 def lib() -> ctypes.CDLL:
     global _lib
     if _lib is None:
+        _one_hip_runtime()
         if not os.path.exists(LIB_PATH):
             raise ImportError(f"{LIB_PATH} is not built; run __graft_entry__.build()")
         L = ctypes.CDLL(LIB_PATH)
