@@ -37,7 +37,6 @@ struct DevBuf {
 struct Misc {
   unsigned long long sample_kmers;
   unsigned long long sample_bases;
-  unsigned long long distinct;
   unsigned long long big_total;
   uint32_t n_big;
   uint32_t offsets_err;
@@ -386,12 +385,13 @@ void run_count(kmc_ctx* c, const kmc_reads* R, const kmc_params* P, kmc_table* T
   check(c, hipEventRecord(c->ev[3], s), "event");
 
   // ---- sort: tiles in LDS, big tiles through HBM
-  uint32_t* tile_out = ensure<uint32_t>(c, B_TILEOUT, n_tiles * 4);
+  uint32_t* tile_out = ensure<uint32_t>(c, B_TILEOUT, n_tiles * 8 + 8);
+  uint32_t* tile_dist = tile_out + n_tiles + (n_tiles & 1);
   uint32_t* big = ensure<uint32_t>(c, B_BIG, n_tiles * 12 + 16);
   uint64_t* big_off = reinterpret_cast<uint64_t*>(big + ((n_tiles + 1) & ~1ull));
   kbeg(c, KMC_K_TILE_SORT, s);
   check(c, launch_tile_sort(s, kc, tiles, n_tiles, keys, counts, tile_out, big, big_off,
-                            &misc->n_big, &misc->big_total, &misc->distinct), "tile_sort");
+                            &misc->n_big, &misc->big_total, tile_dist), "tile_sort");
   kend(c, KMC_K_TILE_SORT, s);
   check(c, hipMemcpyAsync(&h_misc, misc, sizeof(Misc), hipMemcpyDeviceToHost, s), "D2H");
   check(c, hipStreamSynchronize(s), "sync");
@@ -400,7 +400,7 @@ void run_count(kmc_ctx* c, const kmc_reads* R, const kmc_params* P, kmc_table* T
   if (h_misc.n_big) {
     uint64_t* tmp = ensure<uint64_t>(c, B_TMP, (size_t)h_misc.big_total * J.kw * 8);
     check(c, launch_big_tiles(s, kc, tiles, big, big_off, h_misc.n_big, keys, tmp, counts,
-                              tile_out, &misc->distinct), "big_tiles");
+                              tile_out, tile_dist), "big_tiles");
   }
   kend(c, KMC_K_BIG_TILES, s);
   check(c, hipEventRecord(c->ev[4], s), "event");
@@ -415,11 +415,15 @@ void run_count(kmc_ctx* c, const kmc_reads* R, const kmc_params* P, kmc_table* T
   kend(c, KMC_K_ASSEMBLE, s);
   check(c, hipMemcpyAsync(T->bin_offsets, bin_off, ((size_t)J.n_bins + 1) * 8,
                           hipMemcpyDeviceToHost, s), "D2H");
-  check(c, hipMemcpyAsync(&h_misc, misc, sizeof(Misc), hipMemcpyDeviceToHost, s), "D2H");
+  // distinct keys: sum of the per-tile counts (a scan; its last entry is the total)
+  uint64_t* dist_scan = ensure<uint64_t>(c, B_DBG1, (n_tiles + 1) * 8);
+  check(c, launch_scan_u32(s, tile_dist, n_tiles, dist_scan, scan_tmp), "scan");
+  uint64_t h_distinct = 0;
+  check(c, hipMemcpyAsync(&h_distinct, dist_scan + n_tiles, 8, hipMemcpyDeviceToHost, s), "D2H");
   check(c, hipStreamSynchronize(s), "sync");
   const uint64_t n_out = T->bin_offsets[J.n_bins];
   st.n_out = n_out;
-  st.n_distinct = h_misc.distinct;
+  st.n_distinct = h_distinct;
   T->n = n_out;
   uint64_t* out_k;
   uint32_t* out_c;

@@ -97,21 +97,21 @@ hipError_t launch_expand_scatter(hipStream_t s, const KeyCfg& kc, const ExpandTa
 
 // Sort + count every tile that fits LDS.  Output of a tile is written over
 // its own keys (out_counts at the same indices); tile_out[t] = entries kept,
-// distinct[0] += distinct keys.  Tiles larger than LDS are appended to
+// tile_distinct[t] = distinct keys of tile t.  Tiles larger than LDS are appended to
 // big_list (count in n_big[0]) with a private slice of the HBM scratch at
 // big_off (its size summed into big_total).
 hipError_t launch_tile_sort(hipStream_t s, const KeyCfg& kc, const Tile* tiles,
                             uint64_t n_tiles, uint64_t* keys, uint32_t* out_counts,
                             uint32_t* tile_out, uint32_t* big_list, uint64_t* big_off,
                             uint32_t* n_big, unsigned long long* big_total,
-                            unsigned long long* distinct);
+                            uint32_t* tile_distinct);
 
 // Sort + count the big tiles: MSD partition through HBM, each tile
 // ping-ponging between its keys and its own slice tmp[big_off[i] ...].
 hipError_t launch_big_tiles(hipStream_t s, const KeyCfg& kc, const Tile* tiles,
                             const uint32_t* big_list, const uint64_t* big_off, uint32_t n_big,
                             uint64_t* keys, uint64_t* tmp, uint32_t* out_counts,
-                            uint32_t* tile_out, unsigned long long* distinct);
+                            uint32_t* tile_out, uint32_t* tile_distinct);
 
 // Exclusive scan of n uint32 into uint64 (out has n + 1 entries: out[n] = total).
 hipError_t launch_scan_u32(hipStream_t s, const uint32_t* in, uint64_t n, uint64_t* out,

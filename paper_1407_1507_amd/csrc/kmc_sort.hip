@@ -31,8 +31,8 @@ template <> struct SortCfg<1> {
 template <> struct SortCfg<2> {
   static constexpr uint32_t CAP = kTileCap2, DIG = 11, ITEMS = kTileCap2 / kSortThreads;
 };
-constexpr uint32_t kInsMax = 32;    // mixed buckets up to this size: insertion sort by one lane
-constexpr uint32_t kBigMax = 256;   // large buckets listed per tile (CAP / kInsMax < 256)
+constexpr uint32_t kInsMax = 16;    // mixed buckets up to this size: insertion sort by one lane
+constexpr uint32_t kBigMax = 256;   // larger mixed buckets listed per tile (CAP / (kInsMax + 1) < 256)
 
 __device__ __forceinline__ uint64_t load_key(const uint64_t* p, uint64_t i, uint64_t*) { return p[i]; }
 __device__ __forceinline__ u128 load_key(const uint64_t* p, uint64_t i, u128*) {
@@ -88,6 +88,62 @@ __device__ void block_and_or(K& a, K& o, uint64_t* red) {
   }
 }
 
+// Cross-lane exchange of a key within a wave.
+__device__ __forceinline__ uint64_t shfl_xor_key(uint64_t v, int m) { return __shfl_xor(v, m, 64); }
+__device__ __forceinline__ u128 shfl_xor_key(u128 v, int m) {
+  const uint64_t lo = __shfl_xor((uint64_t)v, m, 64), hi = __shfl_xor((uint64_t)(v >> 64), m, 64);
+  return ((u128)hi << 64) | lo;
+}
+
+// Sort A[s, e) (e - s <= 64 R) with one wave: bitonic network over 64 R
+// slots (slot i = 64 r + lane, padding sorts last as the all-ones key).
+// Distances >= 64 compare two registers of a lane, smaller ones two lanes.
+template <class K, int R>
+__device__ void wave_bitonic(K* A, uint32_t s, uint32_t e) {
+  const uint32_t lane = threadIdx.x & 63u;
+  K v[R];
+#pragma unroll
+  for (int r = 0; r < R; ++r) {
+    const uint32_t i = s + r * 64 + lane;
+    v[r] = i < e ? A[i] : ~K(0);
+  }
+  constexpr uint32_t N = 64u * R;
+#pragma unroll
+  for (uint32_t size = 2; size <= N; size <<= 1) {
+#pragma unroll
+    for (uint32_t j = size >> 1; j > 0; j >>= 1) {
+      if (j >= 64) {
+        const int rj = (int)(j / 64);
+#pragma unroll
+        for (int r = 0; r < R; ++r) {
+          const int q = r ^ rj;
+          if (q > r) {
+            const bool asc = (((uint32_t)r * 64 + lane) & size) == 0;
+            const K a = v[r], b = v[q];
+            const bool sw = asc ? (a > b) : (a < b);
+            v[r] = sw ? b : a;
+            v[q] = sw ? a : b;
+          }
+        }
+      } else {
+        const bool lower = (lane & j) == 0;
+#pragma unroll
+        for (int r = 0; r < R; ++r) {
+          const K o = shfl_xor_key(v[r], (int)j);
+          const bool asc = (((uint32_t)r * 64 + lane) & size) == 0;
+          const K mn = v[r] < o ? v[r] : o, mx = v[r] < o ? o : v[r];
+          v[r] = (asc == lower) ? mn : mx;
+        }
+      }
+    }
+  }
+#pragma unroll
+  for (int r = 0; r < R; ++r) {
+    const uint32_t i = s + r * 64 + lane;
+    if (i < e) A[i] = v[r];
+  }
+}
+
 __device__ __forceinline__ uint32_t high_bit(uint64_t x) { return 63u - __clzll(x); }
 __device__ __forceinline__ uint32_t high_bit(u128 x) {
   const uint64_t hi = (uint64_t)(x >> 64);
@@ -107,10 +163,27 @@ struct SortShared {
   uint32_t nbig;
 };
 
-// Sort n <= CAP keys from src (global), count runs, apply cutoffs, write the
-// kept pairs to out_keys[0..kept) / out_counts[0..kept).  src and out_keys may
-// be the same memory: every key is read before anything is written.  Returns
-// kept; *distinct receives the number of distinct keys.  All threads call it.
+__device__ __forceinline__ uint32_t hash_top(uint64_t x, uint32_t t) {
+  return (uint32_t)((x * 0x9E3779B97F4A7C15ull) >> (64 - t));
+}
+__device__ __forceinline__ uint32_t hash_top(u128 x, uint32_t t) {
+  return hash_top((uint64_t)((uint64_t)x ^ ((uint64_t)(x >> 64) * 0xD6E8FEB86659FD93ull)), t);
+}
+__device__ __forceinline__ uint32_t bit_len(uint32_t x) { return 32u - __clz(x); }
+
+// Count the n <= CAP keys at src (global) and write the kept (key, count)
+// pairs, ascending by key, to out_keys[0..kept) / out_counts[0..kept).  src
+// and out_keys may be the same memory: every key is read before anything is
+// written.  Returns kept; *distinct receives the number of distinct keys.
+// All threads call it.
+//   1. counting pass on a hashed digit: equal keys share a bucket, and buckets
+//      hold about one distinct key each whatever the key distribution;
+//   2. buckets with more than one distinct key are sorted (insertion by a
+//      lane, bitonic by a wave, rank sort by the workgroup above 512);
+//   3. run-length count over the grouped keys, cutoffs;
+//   4. counting pass of the kept keys on the key digit below their common
+//      prefix; each kept key's output slot is its bucket start plus the
+//      number of smaller keys in its bucket.
 template <int KW>
 __device__ uint32_t sort_count_emit(const uint64_t* src, uint32_t n, uint64_t* out_keys,
                                     uint32_t* out_counts, uint32_t ci, uint32_t cx,
@@ -118,133 +191,175 @@ __device__ uint32_t sort_count_emit(const uint64_t* src, uint32_t n, uint64_t* o
   typedef typename KeyOf<KW>::T K;
   constexpr uint32_t ITEMS = SortCfg<KW>::ITEMS, DIG = SortCfg<KW>::DIG;
   const uint32_t tid = threadIdx.x, nt = blockDim.x;
-  K key[ITEMS];
-  K a = ~K(0), o = 0;
-#pragma unroll
-  for (uint32_t m = 0; m < ITEMS; ++m) {
-    const uint32_t i = m * nt + tid;
-    if (i < n) {
-      key[m] = load_key(src, i, (K*)nullptr);
-      a &= key[m];
-      o |= key[m];
-    }
-  }
-  block_and_or<K>(a, o, S.red);
-  const K diff = a ^ o;
-  if (diff == 0) {
-    // every key equal: one run of length n
-    if (tid == 0 && n >= ci && n <= cx) {
-      store_key(out_keys, 0, a);
-      out_counts[0] = n;
-    }
-    *distinct = 1;
-    return (n >= ci && n <= cx) ? 1u : 0u;
-  }
-  const uint32_t hb = high_bit(diff);
-  // digit width: about two buckets per key, at most DIG bits, at most the
-  // bits below the common prefix
-  uint32_t t = 32u - __clz(n) + 1u;
-  t = t < DIG ? t : DIG;
-  t = t < hb + 1 ? t : hb + 1;
-  const uint32_t shift = hb + 1 - t;
-  const uint32_t nb = 1u << t, dmask = nb - 1;
 
-  // counting pass on the digit below the common prefix
-  for (uint32_t i = tid; i < nb; i += nt) S.H[i] = 0;
-  if (tid == 0) S.nbig = 0;
-  __syncthreads();
-#pragma unroll
-  for (uint32_t m = 0; m < ITEMS; ++m)
-    if (m * nt + tid < n) atomicAdd(&S.H[(uint32_t)(key[m] >> shift) & dmask], 1u);
-  __syncthreads();
-  block_exclusive_scan(S.H, nb, S.tmp);
-#pragma unroll
-  for (uint32_t m = 0; m < ITEMS; ++m)
-    if (m * nt + tid < n) S.A[atomicAdd(&S.H[(uint32_t)(key[m] >> shift) & dmask], 1u)] = key[m];
-  __syncthreads();
-  // H[d] is now the end of bucket d; finish each bucket
-  const uint32_t per = (nb + nt - 1) / nt;
-  for (uint32_t d = tid * per; d < min(nb, (tid + 1) * per); ++d) {
-    const uint32_t s = d ? S.H[d - 1] : 0, e = S.H[d];
-    if (e - s <= 1) continue;
-    // one key repeated (a k-mer seen many times): already in order
-    const K first = S.A[s];
-    uint32_t i = s + 1;
-    while (i < e && S.A[i] == first) ++i;
-    if (i == e) continue;
-    if (e - s <= kInsMax) {
-      for (uint32_t i = s + 1; i < e; ++i) {
-        const K x = S.A[i];
-        uint32_t j = i;
-        while (j > s && S.A[j - 1] > x) {
-          S.A[j] = S.A[j - 1];
-          --j;
-        }
-        S.A[j] = x;
-      }
-    } else {
-      S.big[atomicAdd(&S.nbig, 1u)] = d;
-    }
-  }
-  __syncthreads();
-  const uint32_t nbig = S.nbig;
-  for (uint32_t bb = 0; bb < nbig; ++bb) {
-    const uint32_t d = S.big[bb];
-    const uint32_t s = d ? S.H[d - 1] : 0, e = S.H[d];
-    K v[ITEMS];
-    uint32_t rk[ITEMS];
+  // ---- 1. group equal keys
+  {
+    K key[ITEMS];
 #pragma unroll
     for (uint32_t m = 0; m < ITEMS; ++m) {
-      const uint32_t i = s + m * nt + tid;
-      if (i < e) {
-        const K x = S.A[i];
-        uint32_t r = 0;
-        for (uint32_t j = s; j < e; ++j) {
-          const K y = S.A[j];
-          r += (y < x) || (y == x && j < i);
-        }
-        v[m] = x;
-        rk[m] = r;
-      }
+      const uint32_t i = m * nt + tid;
+      if (i < n) key[m] = load_key(src, i, (K*)nullptr);
     }
+    const uint32_t t = min(DIG, bit_len(n) + 1);
+    const uint32_t nb = 1u << t;
+    for (uint32_t i = tid; i < nb; i += nt) S.H[i] = 0;
+    if (tid == 0) S.nbig = 0;
     __syncthreads();
 #pragma unroll
     for (uint32_t m = 0; m < ITEMS; ++m)
-      if (s + m * nt + tid < e) S.A[s + rk[m]] = v[m];
+      if (m * nt + tid < n) atomicAdd(&S.H[hash_top(key[m], t)], 1u);
     __syncthreads();
+    block_exclusive_scan(S.H, nb, S.tmp);
+#pragma unroll
+    for (uint32_t m = 0; m < ITEMS; ++m)
+      if (m * nt + tid < n) S.A[atomicAdd(&S.H[hash_top(key[m], t)], 1u)] = key[m];
+    __syncthreads();
+
+    // ---- 2. S.H[d] is the end of bucket d; sort the mixed buckets
+    const uint32_t per = (nb + nt - 1) / nt;
+    for (uint32_t d = tid * per; d < min(nb, (tid + 1) * per); ++d) {
+      const uint32_t s = d ? S.H[d - 1] : 0, e = S.H[d];
+      if (e - s <= 1) continue;
+      const K first = S.A[s];
+      uint32_t i = s + 1;
+      while (i < e && S.A[i] == first) ++i;
+      if (i == e) continue;  // one key repeated
+      if (e - s <= kInsMax) {
+        for (uint32_t q = s + 1; q < e; ++q) {
+          const K x = S.A[q];
+          uint32_t j = q;
+          while (j > s && S.A[j - 1] > x) {
+            S.A[j] = S.A[j - 1];
+            --j;
+          }
+          S.A[j] = x;
+        }
+      } else {
+        S.big[atomicAdd(&S.nbig, 1u)] = d;
+      }
+    }
+    __syncthreads();
+    const uint32_t nbig = S.nbig;
+    const uint32_t wid = tid >> 6, nw = nt >> 6;
+    for (uint32_t bb = wid; bb < nbig; bb += nw) {
+      const uint32_t d = S.big[bb];
+      const uint32_t s = d ? S.H[d - 1] : 0, e = S.H[d], sz = e - s;
+      if (sz <= 64) wave_bitonic<K, 1>(S.A, s, e);
+      else if (sz <= 128) wave_bitonic<K, 2>(S.A, s, e);
+      else if (sz <= 256) wave_bitonic<K, 4>(S.A, s, e);
+      else if (sz <= 512) wave_bitonic<K, 8>(S.A, s, e);
+    }
+    __syncthreads();
+    for (uint32_t bb = 0; bb < nbig; ++bb) {
+      const uint32_t d = S.big[bb];
+      const uint32_t s = d ? S.H[d - 1] : 0, e = S.H[d];
+      if (e - s <= 512) continue;
+      K v[ITEMS];
+      uint32_t rk[ITEMS];
+#pragma unroll
+      for (uint32_t m = 0; m < ITEMS; ++m) {
+        const uint32_t i = s + m * nt + tid;
+        if (i < e) {
+          const K x = S.A[i];
+          uint32_t r = 0;
+          for (uint32_t j = s; j < e; ++j) {
+            const K y = S.A[j];
+            r += (y < x) || (y == x && j < i);
+          }
+          v[m] = x;
+          rk[m] = r;
+        }
+      }
+      __syncthreads();
+#pragma unroll
+      for (uint32_t m = 0; m < ITEMS; ++m)
+        if (s + m * nt + tid < e) S.A[s + rk[m]] = v[m];
+      __syncthreads();
+    }
   }
-  // run heads: positions i with A[i] != A[i-1]; each lane owns a chunk
+
+  // ---- 3. runs of equal keys: heads, counts, cutoffs
   const uint32_t per2 = (n + nt - 1) / nt;
   const uint32_t b0 = min(n, tid * per2), b1 = min(n, b0 + per2);
   uint32_t nh = 0;
   for (uint32_t i = b0; i < b1; ++i) nh += (i == 0 || S.A[i] != S.A[i - 1]);
   uint32_t H_total;
   uint32_t h = block_scan_one(nh, S.tmp, H_total);
-  // head positions overwrite the bucket ends (no longer needed)
   for (uint32_t i = b0; i < b1; ++i)
     if (i == 0 || S.A[i] != S.A[i - 1]) S.H[h++] = i;
   if (tid == 0) S.H[H_total] = n;
   __syncthreads();
-  // counts, cutoffs and compaction of the kept runs
-  const uint32_t per3 = (H_total + nt - 1) / nt;
+  *distinct = H_total;
+  const uint32_t per3 = (H_total + nt - 1) / nt;  // <= ITEMS
   const uint32_t h0 = min(H_total, tid * per3), h1 = min(H_total, h0 + per3);
+  K sk[ITEMS];
+  uint32_t sc[ITEMS];  // count, 0 = not kept
+  K a = ~K(0), o = 0;
   uint32_t nk = 0;
-  for (uint32_t q = h0; q < h1; ++q) {
-    const uint32_t c = S.H[q + 1] - S.H[q];
-    nk += (c >= ci && c <= cx);
+#pragma unroll
+  for (uint32_t qq = 0; qq < ITEMS; ++qq) {
+    const uint32_t q = h0 + qq;
+    sc[qq] = 0;
+    if (q < h1) {
+      const uint32_t c = S.H[q + 1] - S.H[q];
+      if (c >= ci && c <= cx) {
+        sk[qq] = S.A[S.H[q]];
+        sc[qq] = c;
+        a &= sk[qq];
+        o |= sk[qq];
+        ++nk;
+      }
+    }
   }
   uint32_t kept;
-  uint32_t o2 = block_scan_one(nk, S.tmp, kept);
-  for (uint32_t q = h0; q < h1; ++q) {
-    const uint32_t c = S.H[q + 1] - S.H[q];
-    if (c >= ci && c <= cx) {
-      store_key(out_keys, o2, S.A[S.H[q]]);
-      out_counts[o2] = c;
-      ++o2;
+  (void)block_scan_one(nk, S.tmp, kept);
+  if (kept == 0) return 0;
+  block_and_or<K>(a, o, S.red);
+  const K diff = a ^ o;
+  if (diff == 0) {  // a single kept key
+#pragma unroll
+    for (uint32_t qq = 0; qq < ITEMS; ++qq)
+      if (sc[qq]) {
+        store_key(out_keys, 0, sk[qq]);
+        out_counts[0] = sc[qq];
+      }
+    __syncthreads();
+    return 1;
+  }
+
+  // ---- 4. order the kept keys (distinct) by a key-digit counting pass
+  const uint32_t hb = high_bit(diff);
+  const uint32_t t2 = min(min(DIG, bit_len(kept) + 1), hb + 1);
+  const uint32_t shift = hb + 1 - t2;
+  const uint32_t nb2 = 1u << t2, dmask = nb2 - 1;
+  for (uint32_t i = tid; i < nb2; i += nt) S.H[i] = 0;
+  __syncthreads();
+#pragma unroll
+  for (uint32_t qq = 0; qq < ITEMS; ++qq)
+    if (sc[qq]) atomicAdd(&S.H[(uint32_t)(sk[qq] >> shift) & dmask], 1u);
+  __syncthreads();
+  block_exclusive_scan(S.H, nb2, S.tmp);
+  uint32_t dg[ITEMS];
+#pragma unroll
+  for (uint32_t qq = 0; qq < ITEMS; ++qq) {
+    if (sc[qq]) {
+      dg[qq] = (uint32_t)(sk[qq] >> shift) & dmask;
+      S.A[atomicAdd(&S.H[dg[qq]], 1u)] = sk[qq];
     }
   }
   __syncthreads();
-  *distinct = H_total;
+#pragma unroll
+  for (uint32_t qq = 0; qq < ITEMS; ++qq) {
+    if (sc[qq]) {
+      const uint32_t d = dg[qq];
+      const uint32_t s = d ? S.H[d - 1] : 0, e = S.H[d];
+      uint32_t r = s;
+      for (uint32_t j = s; j < e; ++j) r += S.A[j] < sk[qq];
+      store_key(out_keys, r, sk[qq]);
+      out_counts[r] = sc[qq];
+    }
+  }
+  __syncthreads();
   return kept;
 }
 
@@ -252,17 +367,17 @@ template <int KW>
 __global__ void __launch_bounds__(kSortThreads)
 k_tile_sort(KeyCfg kc, const Tile* __restrict__ tiles, uint64_t* keys, uint32_t* counts,
             uint32_t* tile_out, uint32_t* big_list, uint64_t* big_off, uint32_t* n_big,
-            unsigned long long* big_total, unsigned long long* distinct) {
+            unsigned long long* big_total, uint32_t* tile_distinct) {
   __shared__ SortShared<KW> S;
   const uint64_t t = blockIdx.x;
   const Tile T = tiles[t];
   if (T.size == 0) {
-    if (threadIdx.x == 0) tile_out[t] = 0;
+    if (threadIdx.x == 0) tile_out[t] = tile_distinct[t] = 0;
     return;
   }
   if (T.size > SortCfg<KW>::CAP) {
     if (threadIdx.x == 0) {
-      tile_out[t] = 0;
+      tile_out[t] = tile_distinct[t] = 0;
       const uint32_t idx = atomicAdd(n_big, 1u);
       big_list[idx] = (uint32_t)t;
       big_off[idx] = atomicAdd(big_total, (unsigned long long)T.size);  // own slice of tmp
@@ -274,7 +389,7 @@ k_tile_sort(KeyCfg kc, const Tile* __restrict__ tiles, uint64_t* keys, uint32_t*
                                             counts + T.begin, kc.cutoff_min, kc.cutoff_max, S, &d);
   if (threadIdx.x == 0) {
     tile_out[t] = kept;
-    atomicAdd(distinct, (unsigned long long)d);
+    tile_distinct[t] = d;
   }
 }
 
@@ -296,7 +411,7 @@ template <int KW>
 __global__ void __launch_bounds__(kSortThreads)
 k_big_tiles(KeyCfg kc, const Tile* __restrict__ tiles, const uint32_t* __restrict__ big_list,
             const uint64_t* __restrict__ big_off, uint64_t* keys, uint64_t* tmp,
-            uint32_t* counts, uint32_t* tile_out, unsigned long long* distinct) {
+            uint32_t* counts, uint32_t* tile_out, uint32_t* tile_distinct) {
   typedef typename KeyOf<KW>::T K;
   __shared__ SortShared<KW> S;
   __shared__ Level L[MaxLevels<KW>::N];
@@ -401,7 +516,7 @@ k_big_tiles(KeyCfg kc, const Tile* __restrict__ tiles, const uint32_t* __restric
   }
   if (tid == 0) {
     tile_out[t] = (uint32_t)outc;
-    atomicAdd(distinct, dist);
+    tile_distinct[t] = (uint32_t)dist;
   }
 }
 
@@ -498,30 +613,30 @@ hipError_t launch_tile_sort(hipStream_t s, const KeyCfg& kc, const Tile* tiles,
                             uint64_t n_tiles, uint64_t* keys, uint32_t* out_counts,
                             uint32_t* tile_out, uint32_t* big_list, uint64_t* big_off,
                             uint32_t* n_big, unsigned long long* big_total,
-                            unsigned long long* distinct) {
+                            uint32_t* tile_distinct) {
   if (n_tiles == 0) return hipSuccess;
   if (kc.key_words == 1)
     hipLaunchKernelGGL(k_tile_sort<1>, dim3((uint32_t)n_tiles), dim3(kSortThreads), 0, s, kc,
                        tiles, keys, out_counts, tile_out, big_list, big_off, n_big, big_total,
-                       distinct);
+                       tile_distinct);
   else
     hipLaunchKernelGGL(k_tile_sort<2>, dim3((uint32_t)n_tiles), dim3(kSortThreads), 0, s, kc,
                        tiles, keys, out_counts, tile_out, big_list, big_off, n_big, big_total,
-                       distinct);
+                       tile_distinct);
   return hipGetLastError();
 }
 
 hipError_t launch_big_tiles(hipStream_t s, const KeyCfg& kc, const Tile* tiles,
                             const uint32_t* big_list, const uint64_t* big_off, uint32_t n_big,
                             uint64_t* keys, uint64_t* tmp, uint32_t* out_counts,
-                            uint32_t* tile_out, unsigned long long* distinct) {
+                            uint32_t* tile_out, uint32_t* tile_distinct) {
   if (n_big == 0) return hipSuccess;
   if (kc.key_words == 1)
     hipLaunchKernelGGL(k_big_tiles<1>, dim3(n_big), dim3(kSortThreads), 0, s, kc, tiles,
-                       big_list, big_off, keys, tmp, out_counts, tile_out, distinct);
+                       big_list, big_off, keys, tmp, out_counts, tile_out, tile_distinct);
   else
     hipLaunchKernelGGL(k_big_tiles<2>, dim3(n_big), dim3(kSortThreads), 0, s, kc, tiles,
-                       big_list, big_off, keys, tmp, out_counts, tile_out, distinct);
+                       big_list, big_off, keys, tmp, out_counts, tile_out, tile_distinct);
   return hipGetLastError();
 }
 
