@@ -51,6 +51,49 @@ def kernel_bytes(name: str, st: dict, k: int) -> int:
     }.get(name, 0)
 
 
+KERNEL_SOURCE = {  # the source file of each timed kernel (for staleness of traffic counters)
+    "split": "kmc_split.hip", "sig_hist": "kmc_split.hip", "fine_hist": "kmc_expand.hip",
+    "plan_tiles": "kmc_expand.hip", "expand_scatter": "kmc_expand.hip",
+    "tile_sort": "kmc_sort.hip", "big_tiles": "kmc_sort.hip", "assemble": "kmc_sort.hip",
+}
+
+
+def source_digest(kernel: str) -> str:
+    import hashlib
+    path = os.path.join(ROOT, "paper_1407_1507_amd", "csrc", KERNEL_SOURCE.get(kernel, ""))
+    if not os.path.isfile(path):
+        return ""
+    return hashlib.sha256(open(path, "rb").read()).hexdigest()[:16]
+
+
+def measured_traffic(kernel: str, workload: str):
+    """HBM bytes per launch of `kernel` from the committed rocprofv3 counter
+    summary (FETCH_SIZE + WRITE_SIZE, scaled by the copy-kernel calibration),
+    or None if absent or taken on a different version of the kernel."""
+    path = os.path.join(ROOT, "profiles", "traffic.json")
+    if not os.path.isfile(path):
+        return None
+    try:
+        rec = json.load(open(path)).get(f"{workload}:{kernel}")
+    except (OSError, ValueError):
+        return None
+    if not rec or rec.get("source_sha256_16") != source_digest(kernel):
+        return None
+    return rec.get("bytes_per_launch")
+
+
+def copy_calibration(nbytes: int):
+    """A plain device-to-device copy of nbytes (one kernel), for scaling the
+    FETCH_SIZE / WRITE_SIZE counters."""
+    import torch
+    src = torch.empty(nbytes, dtype=torch.uint8, device="cuda:0").fill_(1)
+    dst = torch.empty_like(src)
+    torch.cuda.synchronize()
+    dst.copy_(src)
+    torch.cuda.synchronize()
+    print(json.dumps({"copy_bytes": nbytes}), flush=True)
+
+
 def cpu_baseline(seq, off, p, budget_s: float = 15.0):
     """The oracle, as it stands, on a prefix of the same read set sized to
     about budget_s of CPU time; all host cores."""
@@ -81,7 +124,12 @@ def main():
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--workload", default="genome-5M-2Mx100")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--copy-calibration", type=int, default=0,
+                    help="only run a device copy of this many bytes (counter calibration)")
     args = ap.parse_args()
+    if args.copy_calibration:
+        copy_calibration(args.copy_calibration)
+        return
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py measures one GPU: the counting path runs on a single MI355X "
               "(see DESIGN.md for how it would shard); run with --gpus 1", file=sys.stderr)
@@ -149,7 +197,8 @@ def main():
                                          "n_tiles", "n_big_tiles", "bytes_alg")},
         "roofline": {"bound": "hbm", "kernel": dom, "achieved": achieved,
                      "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS,
-                     "traffic": None},
+                     "traffic": measured_traffic(dom, args.workload),
+                     "alg_bytes_per_launch": dom_bytes},
     }
     if not args.no_cpu_baseline:
         line["cpu_baseline"] = cpu_baseline(seq, off, p)
