@@ -9,8 +9,8 @@ namespace kmc {
 
 // Sizes of the work units.
 constexpr int kExpandThreads = 256;      // records per expansion task (one per thread)
-constexpr int kExpandStage1 = 4096;      // keys staged per expansion flush (1-word keys)
-constexpr int kExpandStage2 = 2048;      // same, 2-word keys
+constexpr int kExpandStage1 = 2048;      // keys staged per expansion flush (1-word keys)
+constexpr int kExpandStage2 = 1024;      // same, 2-word keys
 constexpr int kSortThreads = 256;        // threads of a tile-sort workgroup
 constexpr int kTileCap1 = 4096;          // keys of one LDS tile (1-word keys)
 constexpr int kTileCap2 = 2048;          // same, 2-word keys

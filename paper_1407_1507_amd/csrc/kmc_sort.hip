@@ -17,6 +17,8 @@
 // ranking, which a 64-wide wave has no cheap primitive for.  Tiles larger
 // than LDS take the same MSD passes through HBM (8-bit digits, recursive)
 // until their pieces fit.
+#include <algorithm>
+
 #include "kmc_device.h"
 #include "kmc_internal.h"
 
@@ -155,11 +157,12 @@ template <int KW>
 struct SortShared {
   typedef typename KeyOf<KW>::T K;
   K A[SortCfg<KW>::CAP];
-  uint32_t H[(1u << SortCfg<KW>::DIG) > SortCfg<KW>::CAP ? (1u << SortCfg<KW>::DIG) + 1
-                                                          : SortCfg<KW>::CAP + 1];
+  uint32_t H[((1u << SortCfg<KW>::DIG) > SortCfg<KW>::CAP ? (1u << SortCfg<KW>::DIG)
+                                                           : SortCfg<KW>::CAP) + 1];
+  uint32_t mixed[(1u << SortCfg<KW>::DIG) / 32];  // bit d: bucket d holds > 1 distinct key
   uint64_t red[4 * kSortThreads / 64];
   uint32_t tmp[kSortThreads / 64];
-  uint32_t big[kBigMax];
+  uint16_t big[kBigMax];
   uint32_t nbig;
 };
 
@@ -176,70 +179,284 @@ __device__ __forceinline__ uint32_t bit_len(uint32_t x) { return 32u - __clz(x);
 // and out_keys may be the same memory: every key is read before anything is
 // written.  Returns kept; *distinct receives the number of distinct keys.
 // All threads call it.
-//   1. counting pass on a hashed digit: equal keys share a bucket, and buckets
-//      hold about one distinct key each whatever the key distribution;
-//   2. buckets with more than one distinct key are sorted (insertion by a
-//      lane, bitonic by a wave, rank sort by the workgroup above 512);
-//   3. run-length count over the grouped keys, cutoffs;
+//   1. counting pass on a hashed digit (about one bucket per key): equal keys
+//      share a bucket whatever the key distribution;
+//   2. a bucket whose keys are not all equal to its first key is "mixed"; only
+//      mixed buckets are sorted (insertion by a lane, bitonic by a wave,
+//      rank sort by the workgroup above 512 keys);
+//   3. runs of equal keys: in a bucket that is not mixed the run is the whole
+//      bucket; counts, cutoffs; kept keys stay in registers;
 //   4. counting pass of the kept keys on the key digit below their common
 //      prefix; each kept key's output slot is its bucket start plus the
-//      number of smaller keys in its bucket.
+//      number of smaller kept keys in its bucket.
+// Order the kept (distinct) keys held in registers (key[m], cnt[m] > 0) and
+// write them ascending to out_keys / out_counts: compact them into A / H, one
+// counting pass on the key digit below their common prefix (diff = AND ^ OR
+// of the kept keys), then each key's slot is its bucket start plus the number
+// of smaller keys in its bucket.  kbase = this thread's first compacted slot.
+// All threads call it; A / H must no longer be read by anyone.
+template <int KW>
+__device__ void order_kept(typename KeyOf<KW>::T (&key)[SortCfg<KW>::ITEMS],
+                           uint32_t (&cnt)[SortCfg<KW>::ITEMS], uint32_t kbase, uint32_t kept,
+                           typename KeyOf<KW>::T diff, uint64_t* out_keys,
+                           uint32_t* out_counts, SortShared<KW>& S) {
+  typedef typename KeyOf<KW>::T K;
+  constexpr uint32_t ITEMS = SortCfg<KW>::ITEMS, DIG = SortCfg<KW>::DIG;
+  const uint32_t tid = threadIdx.x, nt = blockDim.x;
+  // ---- order the kept keys (distinct) by a key-digit counting pass.
+  // Kept runs are first compacted into A / H (both free now), so the loops
+  // below run over ceil(kept / threads) slots instead of all register slots.
+  {
+    uint32_t at = kbase;
+#pragma unroll
+    for (uint32_t qq = 0; qq < ITEMS; ++qq) {
+      if (cnt[qq]) {
+        S.A[at] = key[qq];
+        S.H[at] = cnt[qq];
+        ++at;
+      }
+    }
+  }
+  __syncthreads();
+  const uint32_t mk = (kept + nt - 1) / nt;  // uniform
+  const uint32_t hb = high_bit(diff);
+  const uint32_t t2 = min(min(DIG, bit_len(kept) + 1), hb + 1);
+  const uint32_t shift = hb + 1 - t2;
+  const uint32_t nb2 = 1u << t2, dmask = nb2 - 1;
+#pragma unroll
+  for (uint32_t m = 0; m < ITEMS; ++m) {
+    cnt[m] = 0;
+    if (m < mk) {
+      const uint32_t i = m * nt + tid;
+      if (i < kept) {
+        key[m] = S.A[i];
+        cnt[m] = S.H[i];
+      }
+    }
+  }
+  __syncthreads();
+  for (uint32_t i = tid; i < nb2; i += nt) S.H[i] = 0;
+  __syncthreads();
+#pragma unroll
+  for (uint32_t m = 0; m < ITEMS; ++m)
+    if (m < mk && cnt[m]) atomicAdd(&S.H[(uint32_t)(key[m] >> shift) & dmask], 1u);
+  __syncthreads();
+  block_exclusive_scan(S.H, nb2, S.tmp);
+#pragma unroll
+  for (uint32_t m = 0; m < ITEMS; ++m)
+    if (m < mk && cnt[m]) S.A[atomicAdd(&S.H[(uint32_t)(key[m] >> shift) & dmask], 1u)] = key[m];
+  __syncthreads();
+#pragma unroll
+  for (uint32_t m = 0; m < ITEMS; ++m) {
+    if (m < mk && cnt[m]) {
+      const uint32_t d = (uint32_t)(key[m] >> shift) & dmask;
+      const uint32_t s = d ? S.H[d - 1] : 0, e = S.H[d];
+      uint32_t r = s;
+      for (uint32_t j = s; j < e; ++j) r += S.A[j] < key[m];
+      store_key(out_keys, r, key[m]);
+      out_counts[r] = cnt[m];
+    }
+  }
+  __syncthreads();
+}
+
+template <int KW>
+__device__ uint32_t count_tile(typename KeyOf<KW>::T (&key)[SortCfg<KW>::ITEMS], uint32_t n,
+                               uint64_t* out_keys, uint32_t* out_counts, uint32_t ci,
+                               uint32_t cx, SortShared<KW>& S, uint32_t* distinct);
+
+// Count a tile of 64-bit keys (n <= half the table) with an LDS hash table:
+// open addressing with linear probing over the A (keys) / H (counters) arrays;
+// a key's first insertion claims an empty slot by compare-and-swap and every
+// occurrence adds one to that slot's counter, so each counter ends equal to
+// the run length a sort of the tile would give that key.  Kept keys are then
+// put in key order by order_kept.  The all-ones key marks an empty slot: it is
+// never canonical (its reverse complement, all A, is smaller).
+__device__ uint32_t count_tile_hash(uint64_t (&key)[SortCfg<1>::ITEMS], uint32_t n,
+                                    uint64_t* out_keys, uint32_t* out_counts, uint32_t ci,
+                                    uint32_t cx, SortShared<1>& S, uint32_t* distinct) {
+  constexpr uint32_t ITEMS = SortCfg<1>::ITEMS, T = SortCfg<1>::CAP, TB = 12;
+  static_assert((1u << TB) == T, "table size");
+  constexpr uint64_t EMPTY = ~0ull;
+  const uint32_t tid = threadIdx.x, nt = blockDim.x;
+  for (uint32_t s = tid; s < T; s += nt) {
+    S.A[s] = EMPTY;
+    S.H[s] = 0;
+  }
+  __syncthreads();
+#pragma unroll
+  for (uint32_t m = 0; m < ITEMS; ++m) {
+    if (m * nt + tid < n) {
+      uint32_t slot = hash_top(key[m], TB);
+      for (;;) {
+        const unsigned long long old = atomicCAS(
+            reinterpret_cast<unsigned long long*>(&S.A[slot]), (unsigned long long)EMPTY,
+            (unsigned long long)key[m]);
+        if (old == EMPTY || old == key[m]) {
+          atomicAdd(&S.H[slot], 1u);
+          break;
+        }
+        slot = (slot + 1) & (T - 1);
+      }
+    }
+  }
+  __syncthreads();
+  uint32_t cnt[ITEMS];
+  uint32_t nh = 0, nk = 0;
+  uint64_t a = ~0ull, o = 0;
+#pragma unroll
+  for (uint32_t i = 0; i < ITEMS; ++i) {  // T == ITEMS * threads
+    const uint32_t s = i * nt + tid;
+    const uint64_t x = S.A[s];
+    cnt[i] = 0;
+    if (x != EMPTY) {
+      ++nh;
+      const uint32_t c = S.H[s];
+      if (c >= ci && c <= cx) {
+        key[i] = x;
+        cnt[i] = c;
+        a &= x;
+        o |= x;
+        ++nk;
+      }
+    }
+  }
+  uint32_t H_total, kept;
+  (void)block_scan_one(nh, S.tmp, H_total);
+  *distinct = H_total;
+  const uint32_t kbase = block_scan_one(nk, S.tmp, kept);  // barrier: table reads are done
+  if (kept == 0) return 0;
+  block_and_or<uint64_t>(a, o, S.red);
+  const uint64_t diff = a ^ o;
+  if (diff == 0) {
+#pragma unroll
+    for (uint32_t i = 0; i < ITEMS; ++i)
+      if (cnt[i]) {
+        out_keys[0] = key[i];
+        out_counts[0] = cnt[i];
+      }
+    __syncthreads();
+    return 1;
+  }
+  order_kept<1>(key, cnt, kbase, kept, diff, out_keys, out_counts, S);
+  return kept;
+}
+
+// Count a tile whose keys are in registers: hash table when it fits half the
+// table (64-bit keys), hashed buckets otherwise.
+template <int KW>
+__device__ __forceinline__ uint32_t count_any(typename KeyOf<KW>::T (&key)[SortCfg<KW>::ITEMS],
+                                              uint32_t n, uint64_t* out_keys,
+                                              uint32_t* out_counts, uint32_t ci, uint32_t cx,
+                                              SortShared<KW>& S, uint32_t* distinct);
+template <>
+__device__ __forceinline__ uint32_t count_any<1>(uint64_t (&key)[SortCfg<1>::ITEMS], uint32_t n,
+                                                 uint64_t* out_keys, uint32_t* out_counts,
+                                                 uint32_t ci, uint32_t cx, SortShared<1>& S,
+                                                 uint32_t* distinct) {
+  if (n <= SortCfg<1>::CAP / 2)
+    return count_tile_hash(key, n, out_keys, out_counts, ci, cx, S, distinct);
+  return count_tile<1>(key, n, out_keys, out_counts, ci, cx, S, distinct);
+}
+template <>
+__device__ __forceinline__ uint32_t count_any<2>(u128 (&key)[SortCfg<2>::ITEMS], uint32_t n,
+                                                 uint64_t* out_keys, uint32_t* out_counts,
+                                                 uint32_t ci, uint32_t cx, SortShared<2>& S,
+                                                 uint32_t* distinct) {
+  return count_tile<2>(key, n, out_keys, out_counts, ci, cx, S, distinct);
+}
+
+template <int KW>
+__device__ __forceinline__ void load_tile(const uint64_t* src, uint32_t n,
+                                          typename KeyOf<KW>::T (&key)[SortCfg<KW>::ITEMS]) {
+#pragma unroll
+  for (uint32_t m = 0; m < SortCfg<KW>::ITEMS; ++m) {
+    const uint32_t i = m * blockDim.x + threadIdx.x;
+    if (i < n) key[m] = load_key(src, i, (typename KeyOf<KW>::T*)nullptr);
+  }
+}
+
 template <int KW>
 __device__ uint32_t sort_count_emit(const uint64_t* src, uint32_t n, uint64_t* out_keys,
                                     uint32_t* out_counts, uint32_t ci, uint32_t cx,
                                     SortShared<KW>& S, uint32_t* distinct) {
+  typename KeyOf<KW>::T key[SortCfg<KW>::ITEMS];
+  load_tile<KW>(src, n, key);
+  return count_any<KW>(key, n, out_keys, out_counts, ci, cx, S, distinct);
+}
+
+// Same as sort_count_emit, with the tile's keys already in registers
+// (key[m] = key m * blockDim.x + threadIdx.x, for those < n); key is clobbered.
+template <int KW>
+__device__ uint32_t count_tile(typename KeyOf<KW>::T (&key)[SortCfg<KW>::ITEMS], uint32_t n,
+                               uint64_t* out_keys, uint32_t* out_counts, uint32_t ci,
+                               uint32_t cx, SortShared<KW>& S, uint32_t* distinct) {
   typedef typename KeyOf<KW>::T K;
   constexpr uint32_t ITEMS = SortCfg<KW>::ITEMS, DIG = SortCfg<KW>::DIG;
   const uint32_t tid = threadIdx.x, nt = blockDim.x;
+  uint32_t cnt[ITEMS];  // 0: not a kept run head
 
-  // ---- 1. group equal keys
+  // ---- 1. group equal keys by a hashed digit
+  const uint32_t t = min(DIG, bit_len(n));
+  const uint32_t nb = 1u << t;
   {
-    K key[ITEMS];
+    uint32_t pos[ITEMS], hd[ITEMS];
 #pragma unroll
-    for (uint32_t m = 0; m < ITEMS; ++m) {
-      const uint32_t i = m * nt + tid;
-      if (i < n) key[m] = load_key(src, i, (K*)nullptr);
-    }
-    const uint32_t t = min(DIG, bit_len(n) + 1);
-    const uint32_t nb = 1u << t;
+    for (uint32_t m = 0; m < ITEMS; ++m)
+      if (m * nt + tid < n) hd[m] = hash_top(key[m], t);
     for (uint32_t i = tid; i < nb; i += nt) S.H[i] = 0;
+    for (uint32_t i = tid; i < (nb + 31) / 32; i += nt) S.mixed[i] = 0;
     if (tid == 0) S.nbig = 0;
     __syncthreads();
 #pragma unroll
     for (uint32_t m = 0; m < ITEMS; ++m)
-      if (m * nt + tid < n) atomicAdd(&S.H[hash_top(key[m], t)], 1u);
+      if (m * nt + tid < n) atomicAdd(&S.H[hd[m]], 1u);
     __syncthreads();
     block_exclusive_scan(S.H, nb, S.tmp);
 #pragma unroll
-    for (uint32_t m = 0; m < ITEMS; ++m)
-      if (m * nt + tid < n) S.A[atomicAdd(&S.H[hash_top(key[m], t)], 1u)] = key[m];
-    __syncthreads();
-
-    // ---- 2. S.H[d] is the end of bucket d; sort the mixed buckets
-    const uint32_t per = (nb + nt - 1) / nt;
-    for (uint32_t d = tid * per; d < min(nb, (tid + 1) * per); ++d) {
-      const uint32_t s = d ? S.H[d - 1] : 0, e = S.H[d];
-      if (e - s <= 1) continue;
-      const K first = S.A[s];
-      uint32_t i = s + 1;
-      while (i < e && S.A[i] == first) ++i;
-      if (i == e) continue;  // one key repeated
-      if (e - s <= kInsMax) {
-        for (uint32_t q = s + 1; q < e; ++q) {
-          const K x = S.A[q];
-          uint32_t j = q;
-          while (j > s && S.A[j - 1] > x) {
-            S.A[j] = S.A[j - 1];
-            --j;
-          }
-          S.A[j] = x;
-        }
-      } else {
-        S.big[atomicAdd(&S.nbig, 1u)] = d;
+    for (uint32_t m = 0; m < ITEMS; ++m) {
+      if (m * nt + tid < n) {
+        pos[m] = atomicAdd(&S.H[hd[m]], 1u);
+        S.A[pos[m]] = key[m];
       }
     }
     __syncthreads();
-    const uint32_t nbig = S.nbig;
+    // ---- 2. S.H[d] is the end of bucket d; flag and sort the mixed buckets
+#pragma unroll
+    for (uint32_t m = 0; m < ITEMS; ++m) {
+      if (m * nt + tid < n) {
+        const uint32_t d = hd[m];
+        if (S.A[d ? S.H[d - 1] : 0] != key[m]) atomicOr(&S.mixed[d >> 5], 1u << (d & 31));
+      }
+    }
+    __syncthreads();
+    // the lane holding a mixed bucket's first slot sorts it (or lists it)
+#pragma unroll
+    for (uint32_t m = 0; m < ITEMS; ++m) {
+      if (m * nt + tid < n) {
+        const uint32_t d = hd[m];
+        const uint32_t s = d ? S.H[d - 1] : 0, e = S.H[d];
+        if (pos[m] == s && ((S.mixed[d >> 5] >> (d & 31)) & 1u)) {
+          if (e - s <= kInsMax) {
+            for (uint32_t i = s + 1; i < e; ++i) {
+              const K x = S.A[i];
+              uint32_t j = i;
+              while (j > s && S.A[j - 1] > x) {
+                S.A[j] = S.A[j - 1];
+                --j;
+              }
+              S.A[j] = x;
+            }
+          } else {
+            S.big[atomicAdd(&S.nbig, 1u)] = (uint16_t)d;
+          }
+        }
+      }
+    }
+    __syncthreads();
+  }
+  const uint32_t nbig = S.nbig;
+  if (nbig) {
     const uint32_t wid = tid >> 6, nw = nt >> 6;
     for (uint32_t bb = wid; bb < nbig; bb += nw) {
       const uint32_t d = S.big[bb];
@@ -247,13 +464,12 @@ __device__ uint32_t sort_count_emit(const uint64_t* src, uint32_t n, uint64_t* o
       if (sz <= 64) wave_bitonic<K, 1>(S.A, s, e);
       else if (sz <= 128) wave_bitonic<K, 2>(S.A, s, e);
       else if (sz <= 256) wave_bitonic<K, 4>(S.A, s, e);
-      else if (sz <= 512) wave_bitonic<K, 8>(S.A, s, e);
     }
     __syncthreads();
     for (uint32_t bb = 0; bb < nbig; ++bb) {
       const uint32_t d = S.big[bb];
       const uint32_t s = d ? S.H[d - 1] : 0, e = S.H[d];
-      if (e - s <= 512) continue;
+      if (e - s <= 256) continue;
       K v[ITEMS];
       uint32_t rk[ITEMS];
 #pragma unroll
@@ -278,7 +494,9 @@ __device__ uint32_t sort_count_emit(const uint64_t* src, uint32_t n, uint64_t* o
     }
   }
 
-  // ---- 3. runs of equal keys: heads, counts, cutoffs
+  // ---- 3. run heads (equal keys never sit in two buckets, so a head is any
+  // slot whose key differs from the previous slot's), counts, cutoffs;
+  // kept runs stay in registers
   const uint32_t per2 = (n + nt - 1) / nt;
   const uint32_t b0 = min(n, tid * per2), b1 = min(n, b0 + per2);
   uint32_t nh = 0;
@@ -292,104 +510,77 @@ __device__ uint32_t sort_count_emit(const uint64_t* src, uint32_t n, uint64_t* o
   *distinct = H_total;
   const uint32_t per3 = (H_total + nt - 1) / nt;  // <= ITEMS
   const uint32_t h0 = min(H_total, tid * per3), h1 = min(H_total, h0 + per3);
-  K sk[ITEMS];
-  uint32_t sc[ITEMS];  // count, 0 = not kept
   K a = ~K(0), o = 0;
   uint32_t nk = 0;
 #pragma unroll
   for (uint32_t qq = 0; qq < ITEMS; ++qq) {
     const uint32_t q = h0 + qq;
-    sc[qq] = 0;
+    cnt[qq] = 0;
     if (q < h1) {
       const uint32_t c = S.H[q + 1] - S.H[q];
       if (c >= ci && c <= cx) {
-        sk[qq] = S.A[S.H[q]];
-        sc[qq] = c;
-        a &= sk[qq];
-        o |= sk[qq];
+        key[qq] = S.A[S.H[q]];
+        cnt[qq] = c;
+        a &= key[qq];
+        o |= key[qq];
         ++nk;
       }
     }
   }
   uint32_t kept;
-  (void)block_scan_one(nk, S.tmp, kept);
+  const uint32_t kbase = block_scan_one(nk, S.tmp, kept);  // barrier: A/H reads are done
   if (kept == 0) return 0;
   block_and_or<K>(a, o, S.red);
   const K diff = a ^ o;
   if (diff == 0) {  // a single kept key
 #pragma unroll
-    for (uint32_t qq = 0; qq < ITEMS; ++qq)
-      if (sc[qq]) {
-        store_key(out_keys, 0, sk[qq]);
-        out_counts[0] = sc[qq];
+    for (uint32_t m = 0; m < ITEMS; ++m)
+      if (cnt[m]) {
+        store_key(out_keys, 0, key[m]);
+        out_counts[0] = cnt[m];
       }
     __syncthreads();
     return 1;
   }
 
-  // ---- 4. order the kept keys (distinct) by a key-digit counting pass
-  const uint32_t hb = high_bit(diff);
-  const uint32_t t2 = min(min(DIG, bit_len(kept) + 1), hb + 1);
-  const uint32_t shift = hb + 1 - t2;
-  const uint32_t nb2 = 1u << t2, dmask = nb2 - 1;
-  for (uint32_t i = tid; i < nb2; i += nt) S.H[i] = 0;
-  __syncthreads();
-#pragma unroll
-  for (uint32_t qq = 0; qq < ITEMS; ++qq)
-    if (sc[qq]) atomicAdd(&S.H[(uint32_t)(sk[qq] >> shift) & dmask], 1u);
-  __syncthreads();
-  block_exclusive_scan(S.H, nb2, S.tmp);
-  uint32_t dg[ITEMS];
-#pragma unroll
-  for (uint32_t qq = 0; qq < ITEMS; ++qq) {
-    if (sc[qq]) {
-      dg[qq] = (uint32_t)(sk[qq] >> shift) & dmask;
-      S.A[atomicAdd(&S.H[dg[qq]], 1u)] = sk[qq];
-    }
-  }
-  __syncthreads();
-#pragma unroll
-  for (uint32_t qq = 0; qq < ITEMS; ++qq) {
-    if (sc[qq]) {
-      const uint32_t d = dg[qq];
-      const uint32_t s = d ? S.H[d - 1] : 0, e = S.H[d];
-      uint32_t r = s;
-      for (uint32_t j = s; j < e; ++j) r += S.A[j] < sk[qq];
-      store_key(out_keys, r, sk[qq]);
-      out_counts[r] = sc[qq];
-    }
-  }
+  order_kept<KW>(key, cnt, kbase, kept, diff, out_keys, out_counts, S);
   __syncthreads();
   return kept;
 }
 
+// Persistent: the grid is the number of workgroups resident at once, and
+// workgroup g takes tiles g, g + G, g + 2G, ... (tens of thousands of short
+// tiles would otherwise be bound by workgroup dispatch).
 template <int KW>
 __global__ void __launch_bounds__(kSortThreads)
-k_tile_sort(KeyCfg kc, const Tile* __restrict__ tiles, uint64_t* keys, uint32_t* counts,
-            uint32_t* tile_out, uint32_t* big_list, uint64_t* big_off, uint32_t* n_big,
-            unsigned long long* big_total, uint32_t* tile_distinct) {
+k_tile_sort(KeyCfg kc, const Tile* __restrict__ tiles, uint64_t n_tiles, uint64_t* keys,
+            uint32_t* counts, uint32_t* tile_out, uint32_t* big_list, uint64_t* big_off,
+            uint32_t* n_big, unsigned long long* big_total, uint32_t* tile_distinct) {
+  typedef typename KeyOf<KW>::T K;
+  constexpr uint32_t ITEMS = SortCfg<KW>::ITEMS, CAP = SortCfg<KW>::CAP;
   __shared__ SortShared<KW> S;
-  const uint64_t t = blockIdx.x;
-  const Tile T = tiles[t];
-  if (T.size == 0) {
-    if (threadIdx.x == 0) tile_out[t] = tile_distinct[t] = 0;
-    return;
-  }
-  if (T.size > SortCfg<KW>::CAP) {
-    if (threadIdx.x == 0) {
-      tile_out[t] = tile_distinct[t] = 0;
-      const uint32_t idx = atomicAdd(n_big, 1u);
-      big_list[idx] = (uint32_t)t;
-      big_off[idx] = atomicAdd(big_total, (unsigned long long)T.size);  // own slice of tmp
+  for (uint64_t t = blockIdx.x; t < n_tiles; t += gridDim.x) {
+    const Tile T = tiles[t];
+    if (T.size == 0) {
+      if (threadIdx.x == 0) tile_out[t] = tile_distinct[t] = 0;
+    } else if (T.size > CAP) {
+      if (threadIdx.x == 0) {
+        tile_out[t] = tile_distinct[t] = 0;
+        const uint32_t idx = atomicAdd(n_big, 1u);
+        big_list[idx] = (uint32_t)t;
+        big_off[idx] = atomicAdd(big_total, (unsigned long long)T.size);  // own slice of tmp
+      }
+    } else {
+      K key[ITEMS];
+      load_tile<KW>(keys + T.begin * KW, T.size, key);
+      uint32_t d;
+      const uint32_t kept = count_any<KW>(key, T.size, keys + T.begin * KW, counts + T.begin,
+                                          kc.cutoff_min, kc.cutoff_max, S, &d);
+      if (threadIdx.x == 0) {
+        tile_out[t] = kept;
+        tile_distinct[t] = d;
+      }
     }
-    return;
-  }
-  uint32_t d;
-  const uint32_t kept = sort_count_emit<KW>(keys + T.begin * KW, T.size, keys + T.begin * KW,
-                                            counts + T.begin, kc.cutoff_min, kc.cutoff_max, S, &d);
-  if (threadIdx.x == 0) {
-    tile_out[t] = kept;
-    tile_distinct[t] = d;
   }
 }
 
@@ -615,13 +806,27 @@ hipError_t launch_tile_sort(hipStream_t s, const KeyCfg& kc, const Tile* tiles,
                             uint32_t* n_big, unsigned long long* big_total,
                             uint32_t* tile_distinct) {
   if (n_tiles == 0) return hipSuccess;
+  // persistent grid: exactly the workgroups that are resident at once
+  static int resident[3] = {0, 0, 0};
+  const int kw = kc.key_words == 1 ? 1 : 2;
+  if (!resident[kw]) {
+    int dev = 0, cus = 0, per_cu = 0;
+    (void)hipGetDevice(&dev);
+    (void)hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
+    if (kw == 1)
+      (void)hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_tile_sort<1>, kSortThreads, 0);
+    else
+      (void)hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_tile_sort<2>, kSortThreads, 0);
+    resident[kw] = std::max(1, cus) * std::max(1, per_cu);
+  }
+  const uint32_t grid = (uint32_t)std::min<uint64_t>(n_tiles, (uint64_t)resident[kw]);
   if (kc.key_words == 1)
-    hipLaunchKernelGGL(k_tile_sort<1>, dim3((uint32_t)n_tiles), dim3(kSortThreads), 0, s, kc,
-                       tiles, keys, out_counts, tile_out, big_list, big_off, n_big, big_total,
+    hipLaunchKernelGGL(k_tile_sort<1>, dim3(grid), dim3(kSortThreads), 0, s, kc,
+                       tiles, n_tiles, keys, out_counts, tile_out, big_list, big_off, n_big, big_total,
                        tile_distinct);
   else
-    hipLaunchKernelGGL(k_tile_sort<2>, dim3((uint32_t)n_tiles), dim3(kSortThreads), 0, s, kc,
-                       tiles, keys, out_counts, tile_out, big_list, big_off, n_big, big_total,
+    hipLaunchKernelGGL(k_tile_sort<2>, dim3(grid), dim3(kSortThreads), 0, s, kc,
+                       tiles, n_tiles, keys, out_counts, tile_out, big_list, big_off, n_big, big_total,
                        tile_distinct);
   return hipGetLastError();
 }

@@ -22,113 +22,113 @@ namespace kmc {
 
 namespace {
 
-// Byte access into the read set: whole aligned 32-bit words when seq is
-// 4-byte aligned (never past the last byte's word), bytes otherwise.
-struct SeqReader {
-  const uint8_t* seq;
-  uint64_t n;
-  bool a4;
-  uint64_t widx;
-  uint32_t w;
-  __device__ SeqReader(const uint8_t* s, uint64_t nb, bool al) : seq(s), n(nb), a4(al), widx(~0ull), w(0) {}
-  __device__ __forceinline__ uint32_t get(uint64_t pos) {
-    if (a4 && (pos | 3ull) < n) {
-      uint64_t wi = pos >> 2;
-      if (wi != widx) {
-        widx = wi;
-        w = reinterpret_cast<const uint32_t*>(seq)[wi];
-      }
-      return (w >> ((pos & 3u) << 3)) & 0xFFu;
-    }
-    return seq[pos];
-  }
-};
-
+// The 4 bytes of the aligned word at xw (xw % 4 == 0); bytes at or past
+// n_bases read as 0 (an invalid symbol).  Whole-word loads need seq 4-byte
+// aligned; otherwise bytes are loaded one by one.
+__device__ __forceinline__ uint32_t load_word(const uint8_t* __restrict__ seq, uint64_t n,
+                                              bool a4, uint64_t xw) {
+  if (a4 && xw + 3 < n) return reinterpret_cast<const uint32_t*>(seq)[xw >> 2];
+  uint32_t w = 0;
+#pragma unroll
+  for (int q = 0; q < 4; ++q)
+    if (xw + q < n) w |= (uint32_t)seq[xw + q] << (8 * q);
+  return w;
+}
 
 // Scan bytes [x0, x1) of one read.  For every k-mer start j the sink sees
-// kmer(j, signature) (0xFFFFFFFF if the k-mer holds an invalid byte); every
-// super k-mer is passed to sink.superkmer(first k-mer start, number of k-mers,
+// kmer(j, signature) (0xFFFFFFFF if the k-mer holds an invalid byte; the sink
+// ignores starts outside the read); every super k-mer is passed to
+// sink.superkmer(first k-mer start, number of k-mers, signature, bin of the
 // signature, forward key of the first k-mer, tail symbols after the first
 // k-mer).  A super k-mer is also closed after w = k - p + 1 k-mers, so that it
 // never holds more than 2k - p symbols (where super k-mers are cut does not
 // change the counts).
 //
+// The lane walks whole aligned words from the word holding x0; bytes outside
+// [x0, x1) count as invalid, so no k-mer leaves the read and the loop body has
+// no start/end special cases.
+//
 // Window minimum without data-dependent branches (van Herk / Gil-Werman):
 // p-mer values are grouped in blocks of w; when a block completes its suffix
-// minima are formed in place; the window of k-mer j spans the suffix of one
-// block and the prefix of the next, so its minimum is min(suffix[j],
-// running prefix minimum).  Each lane keeps the current and previous block in
-// its own slice vh[0 .. 2w) of LDS.  A p-mer holding an invalid byte is stored
-// as 0 and a valid one as (value + 1), so a window minimum of 0 flags an
-// invalid k-mer and N bases need no separate branch.
+// minima are formed in place; the window of a k-mer spans the suffix of one
+// block and the prefix of the next, so its minimum is min(suffix, running
+// prefix minimum).  Each lane keeps the current and previous block in its own
+// slice vh[0 .. 2w) of LDS.  A p-mer holding an invalid byte is stored as 0
+// and a valid one as (value + 1), so a window minimum of 0 flags an invalid
+// k-mer and N bases need no separate branch.
 template <int KW, class VT, class Sink>
 __device__ __forceinline__ void scan_read(const uint8_t* __restrict__ seq, uint64_t n_bases,
                                           uint64_t x0, uint64_t x1, const ScanCfg& C, VT* vh,
                                           Sink& sink) {
   typedef typename KeyOf<KW>::T K;
   const uint32_t k = C.k, p = C.p, w = C.w;
+  if (x1 < x0 + k) return;
   const K kmask = key_mask<K>(k);
   const uint32_t rcs = 2 * p - 2;
-  SeqReader rd(seq, n_bases, C.aligned4 != 0);
+  const bool a4 = C.aligned4 != 0;
+  for (uint32_t i = 0; i < 2 * w; ++i) vh[i] = (VT)0;
   uint32_t run = 0, fp = 0, rp = 0;
   uint32_t in_blk = 0, par = 0, pre = 0;
-  uint32_t cur_n = 0, cur_sig = 0;
+  uint32_t cur_n = 0, cur_sig = 0, cur_bin = 0;
   uint64_t cur_start = 0;
   K F = 0, curF = 0, tail = 0;
-  const uint64_t xp = x0 + p - 1;  // first byte completing a p-mer
-  const uint64_t xk = x0 + k - 1;  // first byte completing a k-mer
-  for (uint64_t x = x0; x < x1; ++x) {
-    bool ok;
-    const uint32_t c = decode_base(rd.get(x), ok);
-    run = ok ? run + 1 : 0;
-    fp = ((fp << 2) | c) & C.pmask;
-    rp = (rp >> 2) | ((3u - c) << rcs);
-    if (Sink::kNeedKeys) F = ((F << 2) | (K)c) & kmask;
-    if (x < xp) continue;
-    const uint32_t can = min(fp, rp);
-    const uint32_t v =
-        run >= p ? ((!C.filter || sig_allowed(can, p)) ? can : C.sent) + 1u : 0u;
-    pre = in_blk == 0 ? v : min(pre, v);
-    VT* cur = vh + par * w;
-    cur[in_blk] = (VT)v;
-    if (in_blk == w - 1) {
-      uint32_t r = v;
-      for (int i = (int)w - 2; i >= 0; --i) {
-        r = min(r, (uint32_t)cur[i]);
-        cur[i] = (VT)r;
+  for (uint64_t xw = x0 & ~3ull; xw < x1; xw += 4) {
+    const uint32_t word = load_word(seq, n_bases, a4, xw);
+#pragma unroll
+    for (uint32_t q = 0; q < 4; ++q) {
+      const uint64_t x = xw + q;
+      bool ok;
+      const uint32_t c = decode_base((word >> (8 * q)) & 0xFFu, ok);
+      ok = ok && x >= x0 && x < x1;
+      run = ok ? run + 1 : 0;
+      fp = ((fp << 2) | c) & C.pmask;
+      rp = (rp >> 2) | ((3u - c) << rcs);
+      if (Sink::kNeedKeys) F = ((F << 2) | (K)c) & kmask;
+      const uint32_t can = min(fp, rp);
+      const uint32_t v =
+          run >= p ? ((!C.filter || sig_allowed(can, p)) ? can : C.sent) + 1u : 0u;
+      pre = in_blk == 0 ? v : min(pre, v);
+      VT* cur = vh + par * w;
+      cur[in_blk] = (VT)v;
+      if (in_blk == w - 1) {
+        uint32_t r = v;
+        for (int i = (int)w - 2; i >= 0; --i) {
+          r = min(r, (uint32_t)cur[i]);
+          cur[i] = (VT)r;
+        }
       }
-    }
-    if (x >= xk) {
+      // k-mer ending at x: window of the p-mers ending at x - w + 1 .. x
       const uint32_t suf =
           in_blk == w - 1 ? (uint32_t)cur[0] : (uint32_t)vh[(par ^ 1u) * w + in_blk + 1];
       const uint32_t m = min(suf, pre);
       const uint64_t j = x + 1 - k;
       if (m == 0) {
-        sink.kmer(j, 0xFFFFFFFFu);
-        if (cur_n) sink.superkmer(cur_start, cur_n, cur_sig, curF, tail);
+        sink.kmer(j, 0xFFFFFFFFu, x0, x1);
+        if (cur_n) sink.superkmer(cur_start, cur_n, cur_sig, cur_bin, curF, tail);
         cur_n = 0;
       } else {
         const uint32_t sig = m - 1;
-        sink.kmer(j, sig);
+        sink.kmer(j, sig, x0, x1);
         if (cur_n && sig == cur_sig && cur_n < w) {
           ++cur_n;
           if (Sink::kNeedKeys) tail = (tail << 2) | (K)c;
         } else {
-          if (cur_n) sink.superkmer(cur_start, cur_n, cur_sig, curF, tail);
+          if (cur_n) sink.superkmer(cur_start, cur_n, cur_sig, cur_bin, curF, tail);
           cur_start = j;
           cur_n = 1;
           cur_sig = sig;
+          cur_bin = sink.bin_of(sig);  // issued now, used when the super k-mer closes
           curF = F;
           tail = 0;
         }
       }
-    }
-    if (++in_blk == w) {
-      in_blk = 0;
-      par ^= 1u;
+      if (++in_blk == w) {
+        in_blk = 0;
+        par ^= 1u;
+      }
     }
   }
-  if (cur_n) sink.superkmer(cur_start, cur_n, cur_sig, curF, tail);
+  if (cur_n) sink.superkmer(cur_start, cur_n, cur_sig, cur_bin, curF, tail);
 }
 
 // Record of a super k-mer (2 words for k <= 32, 4 words for k > 32):
@@ -162,8 +162,9 @@ struct HistSink {
   uint32_t* hist_k;   // k-mers per signature
   uint32_t* hist_r;   // super k-mers per signature
   uint64_t kmers;
-  __device__ void kmer(uint64_t, uint32_t) {}
-  __device__ void superkmer(uint64_t, uint32_t n, uint32_t sig,
+  __device__ void kmer(uint64_t, uint32_t, uint64_t, uint64_t) {}
+  __device__ uint32_t bin_of(uint32_t) { return 0; }
+  __device__ void superkmer(uint64_t, uint32_t n, uint32_t sig, uint32_t,
                             typename KeyOf<KW>::T, typename KeyOf<KW>::T) {
     atomicAdd(&hist_k[sig], n);
     atomicAdd(&hist_r[sig], 1u);
@@ -211,10 +212,10 @@ struct ScatterSink {
   unsigned long long* gkmer;
   const uint64_t* cap_base;  // region of bin b: [cap_base[b], cap_base[b+1])
   uint64_t* records;
-  __device__ void kmer(uint64_t, uint32_t) {}
-  __device__ void superkmer(uint64_t, uint32_t n, uint32_t sig, typename KeyOf<KW>::T F,
+  __device__ void kmer(uint64_t, uint32_t, uint64_t, uint64_t) {}
+  __device__ uint32_t bin_of(uint32_t sig) { return map[sig]; }
+  __device__ void superkmer(uint64_t, uint32_t n, uint32_t, uint32_t b, typename KeyOf<KW>::T F,
                             typename KeyOf<KW>::T tail) {
-    const uint32_t b = map[sig];
     uint64_t rec[RW];
     make_record(rec, F, tail, n);
     if (STAGE) {
@@ -323,8 +324,11 @@ struct DebugSink {
   static constexpr bool kNeedKeys = false;
   uint32_t* sig;
   uint8_t* start;
-  __device__ void kmer(uint64_t j, uint32_t s) { sig[j] = s; }
-  __device__ void superkmer(uint64_t j0, uint32_t, uint32_t, typename KeyOf<KW>::T,
+  __device__ void kmer(uint64_t j, uint32_t s, uint64_t x0, uint64_t x1) {
+    if (j >= x0 && j < x1) sig[j] = s;  // starts before the read are not the read's
+  }
+  __device__ uint32_t bin_of(uint32_t) { return 0; }
+  __device__ void superkmer(uint64_t j0, uint32_t, uint32_t, uint32_t, typename KeyOf<KW>::T,
                             typename KeyOf<KW>::T) {
     if (start) start[j0] = 1;
   }
