@@ -120,6 +120,8 @@ typedef struct kmc_stats {
   double us_assemble;
   double us_total;         /* first kernel to last kernel */
   double us_kernel[8];     /* device time of each kernel (KMC_K_*), microseconds */
+  double us_queue;         /* served jobs: submit -> start of work, microseconds */
+  double us_latency;       /* served jobs: submit -> table ready, microseconds */
 } kmc_stats;
 
 /* Result of a count.  Entries are grouped by bin (bin b holds entries
@@ -133,8 +135,9 @@ typedef struct kmc_stats {
  *   bin_offsets n_bins + 1 uint64 (always host memory);
  *   sig_to_bin  4^p + 1 uint32: bin of every signature value; the last entry
  *               is for k-mers with no allowed p-mer (always host memory).
- * keys/counts are host memory unless on_device = 1.  The table is owned by
- * the library: release it with kmc_table_free. */
+ * keys/counts are host memory unless on_device = 1.  reserved = 1 marks a
+ * device table whose keys/counts live in a caller's workspace (kmc_count_ws).
+ * The table is owned by the library: release it with kmc_table_free. */
 typedef struct kmc_table {
   uint32_t k;
   uint32_t key_words;
@@ -182,6 +185,75 @@ void kmc_table_free(kmc_table* table);
 
 /* Static text for a status code. */
 const char* kmc_status_str(kmc_status status);
+
+/* One counting job: reads + parameters.  The reads are borrowed until the
+ * job's table has been returned. */
+typedef struct kmc_job {
+  kmc_reads reads;
+  kmc_params params;
+} kmc_job;
+
+/* Device bytes that kmc_count_ws may use for this job, computed from the sizes
+ * alone (an upper bound: every window a k-mer, every bin at its largest).
+ * Returns KMC_ERR_INVALID_ARG under the same rules as kmc_count. */
+kmc_status kmc_workspace_size(const kmc_reads* reads, const kmc_params* params, size_t* bytes);
+
+/* As kmc_count_ex, with every device buffer of the job carved from
+ * `workspace` (device memory of ctx's device, at least kmc_workspace_size
+ * bytes, 256-byte aligned); the library allocates no device memory of its
+ * own for the job.  With KMC_FLAG_DEVICE_TABLE the table's keys/counts also
+ * live in the workspace: they stay valid until the workspace is reused, and
+ * kmc_table_free releases only the host parts.  Returns KMC_ERR_OUT_OF_MEMORY
+ * if ws_bytes is too small. */
+kmc_status kmc_count_ws(kmc_ctx* ctx, const kmc_reads* reads, const kmc_params* params,
+                        void* stream, void* workspace, size_t ws_bytes, kmc_table** out);
+
+/* Count n_jobs independent jobs (uneven sizes and parameters allowed).
+ * Jobs run concurrently on a pool of worker streams owned by ctx, each with
+ * its own workspace; outs[i] receives job i's table, identical to what
+ * kmc_count_ex returns for that job alone.  On any failure every outs[i] is
+ * NULL, nothing is leaked, and the first failing job's status is returned. */
+kmc_status kmc_batch_count(kmc_ctx* ctx, const kmc_job* jobs, uint32_t n_jobs, kmc_table** outs);
+
+/* Served form: jobs are submitted while others run; a job is admitted when
+ * its footprint (kmc_workspace_size) fits the HBM budget next to the jobs
+ * already admitted (a job larger than the whole budget is admitted alone),
+ * and up to max_active admitted jobs run at once, each on its own stream;
+ * as one finishes the next admissible job starts (continuous batching). */
+typedef struct kmc_server_cfg {
+  uint64_t hbm_budget; /* bytes; 0 = 90% of the device memory free at start */
+  uint32_t max_active; /* 1..16 jobs running at once; 0 = 4 */
+  uint32_t reserved;
+} kmc_server_cfg;
+
+typedef struct kmc_server_stats {
+  uint64_t submitted;
+  uint64_t completed;
+  uint64_t failed;
+  uint64_t admitted_bytes;      /* footprint admitted now */
+  uint64_t peak_admitted_bytes; /* largest admitted footprint so far */
+  uint64_t budget;
+  uint32_t active;              /* jobs running now */
+  uint32_t queued;              /* jobs waiting for admission */
+} kmc_server_stats;
+
+typedef struct kmc_server kmc_server;
+
+/* Start a server on ctx's device (ctx must outlive the server and must not
+ * be used by the caller while the server runs). */
+kmc_status kmc_server_start(kmc_ctx* ctx, const kmc_server_cfg* cfg, kmc_server** out);
+/* Queue a job; *ticket identifies it.  The job's reads stay borrowed until
+ * its table is polled. */
+kmc_status kmc_server_submit(kmc_server* srv, const kmc_job* job, uint64_t* ticket);
+/* Fetch a job's table: KMC_OK with *out set (the ticket is then released),
+ * KMC_ERR_BUSY if it is not done and wait == 0, or the job's failure status.
+ * wait != 0 blocks until the job is done.  stats.us_queue / us_latency give
+ * the job's waiting time and its submit-to-ready latency. */
+kmc_status kmc_server_poll(kmc_server* srv, uint64_t ticket, int32_t wait, kmc_table** out);
+kmc_status kmc_server_stats_get(kmc_server* srv, kmc_server_stats* stats);
+/* Stop accepting jobs, wait for running ones, free unpolled tables and the
+ * server.  NULL is allowed. */
+void kmc_server_stop(kmc_server* srv);
 
 /* Audit entry (tests): the signature of the window starting at every byte of
  * the input, as the GPU's split kernel computes it, into sig_per_window

@@ -44,12 +44,27 @@ struct Misc {
 
 }  // namespace
 
+// Carving of a caller-provided workspace: one region per buffer, sized by
+// upper bounds computed from the job's sizes (kmc_workspace_size).
+struct WsLayout {
+  size_t off[B_COUNT_];
+  size_t size[B_COUNT_];
+  size_t total;
+};
+
 struct kmc_ctx {
   int device = 0;
   hipStream_t stream = nullptr;
   std::string err;
   DevBuf buf[B_COUNT_];
   hipEvent_t ev[32] = {};  // 0..5 phases, 8 + 2i / 9 + 2i kernel i, 28 / 29 gather
+  // workspace mode (kmc_count_ws): buffers come from ws_base + layout
+  uint8_t* ws_base = nullptr;
+  WsLayout ws;
+  bool ws_own_table = false;  // device table allocated apart from the workspace
+  // extension slot (batch worker pool), released with the context
+  void* ext = nullptr;
+  void (*ext_free)(void*) = nullptr;
 };
 
 namespace {
@@ -68,6 +83,13 @@ void check(kmc_ctx* c, hipError_t e, const char* what) {
 
 template <class T>
 T* ensure(kmc_ctx* c, BufId id, size_t bytes) {
+  if (c->ws_base) {
+    if (bytes > c->ws.size[id]) {
+      c->err = "workspace too small for this job";
+      throw Fail{KMC_ERR_OUT_OF_MEMORY};
+    }
+    return reinterpret_cast<T*>(c->ws_base + c->ws.off[id]);
+  }
   DevBuf& b = c->buf[id];
   if (bytes == 0) bytes = 16;
   if (b.cap < bytes) {
@@ -263,6 +285,17 @@ void run_count(kmc_ctx* c, const kmc_reads* R, const kmc_params* P, kmc_table* T
     for (uint32_t g = 0; g < n_sig; ++g) est[map[g]] += h_hist[n_sig + g];
     const double scale = h_misc.sample_bases ? (double)J.n_bases / (double)h_misc.sample_bases : 0.0;
     for (uint32_t b = 0; b < J.n_bins; ++b) cap[b] = (uint64_t)(est[b] * scale * 1.25) + 256;
+    if (c->ws_base) {
+      // keep the regions inside the workspace; a bin that outgrows its share
+      // takes the exact second pass, whose sizes always fit
+      // (less one record per bin: the scaling below rounds each share)
+      const uint64_t room = c->ws.size[B_REC] / (RW * 8) - J.n_bins;
+      uint64_t total = 0;
+      for (uint32_t b = 0; b < J.n_bins; ++b) total += cap[b];
+      if (total > room)
+        for (uint32_t b = 0; b < J.n_bins; ++b)
+          cap[b] = (uint64_t)((double)cap[b] * (double)room / (double)total);
+    }
   }
   // bases: [0..n_bins] record region base, [n_bins+1..] key base, then tile base
   std::vector<uint64_t> bases(3 * ((size_t)J.n_bins + 1));
@@ -427,7 +460,14 @@ void run_count(kmc_ctx* c, const kmc_reads* R, const kmc_params* P, kmc_table* T
   T->n = n_out;
   uint64_t* out_k;
   uint32_t* out_c;
-  if (T->on_device) {
+  if (T->on_device && c->ws_base && !c->ws_own_table) {
+    // the table lives in the caller's workspace; kmc_table_free leaves it
+    T->keys = ensure<uint64_t>(c, B_OUTK, n_out * J.kw * 8);
+    T->counts = ensure<uint32_t>(c, B_OUTC, n_out * 4);
+    T->reserved = 1;
+    out_k = T->keys;
+    out_c = T->counts;
+  } else if (T->on_device) {
     check(c, hipMalloc(&T->keys, std::max<uint64_t>(1, n_out * J.kw) * 8), "hipMalloc table");
     check(c, hipMalloc(&T->counts, std::max<uint64_t>(1, n_out) * 4), "hipMalloc table");
     out_k = T->keys;
@@ -465,6 +505,72 @@ void run_count(kmc_ctx* c, const kmc_reads* R, const kmc_params* P, kmc_table* T
   const uint64_t payload = n_rec * 2 + (n_kmers + n_rec * (J.k - 1)) / 4;
   st.bytes_alg = J.n_bases + 8 * (J.n_reads + 1) + 2 * payload +
                  2 * (uint64_t)(8 * J.kw) * n_kmers + (uint64_t)(8 * J.kw + 4) * n_out;
+}
+
+// Upper bounds of every buffer of one job, from its sizes alone: at most one
+// k-mer per base, one record per k-mer (plus 256 per bin of sampling slack),
+// every tile at most the LDS tile target, every tile possibly too big for LDS.
+WsLayout plan_workspace(const kmc_reads* R, const kmc_params* P) {
+  WsLayout L;
+  const uint64_t N = R->n_bases, NR = R->n_reads, NB = P->n_bins;
+  const uint64_t kw = P->k <= 32 ? 1 : 2, RW = 2 * kw;
+  const uint64_t n_sig = (1ull << (2 * P->p)) + 1;
+  const uint64_t kmax = N;
+  const uint64_t recmax = kmax + 256 * NB;
+  const uint64_t target = (kw == 1 ? kTileCap1 : kTileCap2) / 2;
+  const uint64_t tmax = kmax / target + NB + 1;
+  const uint64_t tasks = recmax / kExpandThreads + NB + 1;
+  uint64_t sz[B_COUNT_] = {};
+  sz[B_SEQ] = R->on_device ? 0 : N + 16;
+  sz[B_OFF] = R->on_device ? 0 : (NR + 1) * 8;
+  sz[B_HIST] = n_sig * 8;
+  sz[B_MAP] = n_sig * 4;
+  sz[B_BINCNT] = NB * 16;
+  sz[B_CURSOR] = NB * 8;
+  sz[B_REC] = recmax * RW * 8;
+  // fine bits as the tile plan picks them, for a bin holding every k-mer
+  const uint32_t fb = std::max<uint32_t>(
+      1, std::min<uint32_t>({ilog2_ceil(kmax * 4 / target + 1), (uint32_t)kMaxFineBits, 2 * P->k}));
+  sz[B_FINE] = (NB << fb) * 4;
+  sz[B_TOF] = (NB << fb) * 2;
+  sz[B_TILES] = tmax * sizeof(Tile);
+  sz[B_TCUR] = tmax * 8;
+  sz[B_BASES] = 3 * (NB + 1) * 8;
+  sz[B_HTASK] = tasks * sizeof(ExpandTask);
+  sz[B_ETASK] = tasks * sizeof(ExpandTask);
+  sz[B_KEYS] = kmax * kw * 8;
+  sz[B_COUNTS] = kmax * 4;
+  sz[B_TILEOUT] = tmax * 8 + 8;
+  sz[B_BIG] = tmax * 12 + 16;
+  sz[B_MISC] = sizeof(Misc);
+  sz[B_TMP] = kmax * kw * 8;
+  sz[B_SCANTMP] = scan_tmp_words(tmax) * 8;
+  sz[B_TILEOFF] = (tmax + 1) * 8;
+  sz[B_BINOFF] = (NB + 1) * 8;
+  sz[B_OUTK] = kmax * kw * 8;
+  sz[B_OUTC] = kmax * 4;
+  sz[B_DBG1] = (tmax + 1) * 8;
+  sz[B_DBG2] = 0;
+  // records are dead once the keys are expanded: the big-tile scratch and,
+  // after it, the assembled table reuse their region
+  auto al = [](uint64_t x) { return (x + 255) & ~(uint64_t)255; };
+  const uint64_t alias_tmp = sz[B_TMP], alias_k = sz[B_OUTK], alias_c = sz[B_OUTC];
+  sz[B_TMP] = sz[B_OUTK] = sz[B_OUTC] = 0;
+  sz[B_REC] = std::max<uint64_t>({sz[B_REC], alias_tmp, al(alias_k) + alias_c});
+  size_t at = 0;
+  for (int i = 0; i < B_COUNT_; ++i) {
+    L.off[i] = at;
+    L.size[i] = (size_t)std::max<uint64_t>(sz[i], 16);
+    at += al(L.size[i]);
+  }
+  L.off[B_TMP] = L.off[B_REC];
+  L.size[B_TMP] = alias_tmp;
+  L.off[B_OUTK] = L.off[B_REC];
+  L.size[B_OUTK] = alias_k;
+  L.off[B_OUTC] = L.off[B_REC] + al(alias_k);
+  L.size[B_OUTC] = alias_c;
+  L.total = at;
+  return L;
 }
 
 kmc_status guarded(kmc_ctx* c, const kmc_reads* R, const kmc_params* P, kmc_table** out) {
@@ -522,6 +628,8 @@ kmc_status kmc_ctx_create(int device, kmc_ctx** out) {
 
 void kmc_ctx_destroy(kmc_ctx* c) {
   if (!c) return;
+  if (c->ext && c->ext_free) c->ext_free(c->ext);
+  c->ext = nullptr;
   (void)hipSetDevice(c->device);
   if (c->stream) (void)hipStreamSynchronize(c->stream);
   for (auto& b : c->buf)
@@ -545,6 +653,27 @@ const char* kmc_status_str(kmc_status st) {
   }
   return "unknown status";
 }
+
+}  // extern "C"
+
+// Extension slot of a context (used by the batch worker pool).
+void** kmc::ctx_ext(kmc_ctx* c, void (*release)(void*)) {
+  if (release) c->ext_free = release;
+  return &c->ext;
+}
+int kmc::ctx_device(const kmc_ctx* c) { return c->device; }
+void kmc::ctx_set_error(kmc_ctx* c, const char* msg) { c->err = msg ? msg : ""; }
+void kmc::ctx_release_buffers(kmc_ctx* c) {
+  (void)hipSetDevice(c->device);
+  if (c->stream) (void)hipStreamSynchronize(c->stream);
+  for (auto& b : c->buf) {
+    if (b.p) (void)hipFree(b.p);
+    b.p = nullptr;
+    b.cap = 0;
+  }
+}
+
+extern "C" {
 
 kmc_status kmc_count_ex(kmc_ctx* c, const kmc_reads* reads, const kmc_params* params,
                         void* stream, kmc_table** out) {
@@ -584,7 +713,9 @@ kmc_status kmc_count(const kmc_reads* reads, uint32_t k, uint32_t p, uint32_t n_
 
 void kmc_table_free(kmc_table* t) {
   if (!t) return;
-  if (t->on_device) {
+  if (t->on_device && t->reserved == 1) {
+    // keys/counts belong to a caller's workspace
+  } else if (t->on_device) {
     if (t->keys) (void)hipFree(t->keys);
     if (t->counts) (void)hipFree(t->counts);
   } else {
@@ -595,6 +726,57 @@ void kmc_table_free(kmc_table* t) {
   std::free(t->sig_to_bin);
   std::free(t);
 }
+
+kmc_status kmc_workspace_size(const kmc_reads* reads, const kmc_params* params, size_t* bytes) {
+  if (!bytes) return KMC_ERR_INVALID_ARG;
+  *bytes = 0;
+  kmc_status v = validate(reads, params);
+  if (v != KMC_OK) return v;
+  *bytes = plan_workspace(reads, params).total;
+  return KMC_OK;
+}
+
+kmc_status kmc_count_ws(kmc_ctx* c, const kmc_reads* reads, const kmc_params* params,
+                        void* stream, void* workspace, size_t ws_bytes, kmc_table** out) {
+  return kmc::count_ws_impl(c, reads, params, stream, workspace, ws_bytes, false, out);
+}
+
+}  // extern "C"
+
+kmc_status kmc::count_ws_impl(kmc_ctx* c, const kmc_reads* reads, const kmc_params* params,
+                              void* stream, void* workspace, size_t ws_bytes, bool own_table,
+                              kmc_table** out) {
+  if (!out) return KMC_ERR_INVALID_ARG;
+  *out = nullptr;
+  if (!c || !workspace || ((uintptr_t)workspace & 255u)) return KMC_ERR_INVALID_ARG;
+  c->err.clear();
+  kmc_status v = validate(reads, params);
+  if (v != KMC_OK) {
+    c->err = "argument validation failed";
+    return v;
+  }
+  const WsLayout L = plan_workspace(reads, params);
+  if (ws_bytes < L.total) {
+    c->err = "workspace smaller than kmc_workspace_size";
+    return KMC_ERR_OUT_OF_MEMORY;
+  }
+  if (hipSetDevice(c->device) != hipSuccess) {
+    (void)hipGetLastError();
+    return KMC_ERR_DEVICE;
+  }
+  hipStream_t saved = c->stream;
+  if (stream) c->stream = static_cast<hipStream_t>(stream);
+  c->ws_base = static_cast<uint8_t*>(workspace);
+  c->ws = L;
+  c->ws_own_table = own_table;
+  kmc_status st = guarded(c, reads, params, out);
+  c->ws_base = nullptr;
+  c->ws_own_table = false;
+  c->stream = saved;
+  return st;
+}
+
+extern "C" {
 
 kmc_status kmc_debug_signatures(kmc_ctx* c, const kmc_reads* reads, uint32_t k, uint32_t p,
                                 uint32_t flags, uint32_t* sig_per_window,

@@ -5,6 +5,8 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include "kmc.h"
+
 namespace kmc {
 
 // Sizes of the work units.
@@ -134,4 +136,20 @@ size_t expand_scatter_lds_bytes(uint32_t key_words, uint32_t mt, uint32_t fine_b
 hipError_t launch_check_offsets(hipStream_t s, const uint64_t* offsets, uint64_t n_reads,
                                 uint64_t n_bases, uint32_t* err);
 
+}  // namespace kmc
+
+struct kmc_ctx;
+namespace kmc {
+// Extension slot of a context: *slot holds an object released by `release`
+// (registered on first use) when the context is destroyed.
+void** ctx_ext(kmc_ctx* c, void (*release)(void*));
+int ctx_device(const kmc_ctx* c);
+void ctx_set_error(kmc_ctx* c, const char* msg);
+// Free the context's cached device buffers (after a one-off large job).
+void ctx_release_buffers(kmc_ctx* c);
+// kmc_count_ws; with own_table a device table is allocated apart from the
+// workspace, so it outlives the workspace's reuse.
+kmc_status count_ws_impl(kmc_ctx* c, const kmc_reads* reads, const kmc_params* params,
+                         void* stream, void* workspace, size_t ws_bytes, bool own_table,
+                         kmc_table** out);
 }  // namespace kmc

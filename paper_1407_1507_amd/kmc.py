@@ -29,7 +29,9 @@ FLAG_DEVICE_TABLE = 0x1
 FLAG_PLAIN_MINIMIZERS = 0x2
 
 EXPORTS = ["kmc_ctx_create", "kmc_ctx_destroy", "kmc_last_error", "kmc_count", "kmc_count_ex",
-           "kmc_table_free", "kmc_status_str", "kmc_debug_signatures"]
+           "kmc_table_free", "kmc_status_str", "kmc_workspace_size", "kmc_count_ws",
+           "kmc_batch_count", "kmc_server_start", "kmc_server_submit", "kmc_server_poll",
+           "kmc_server_stats_get", "kmc_server_stop", "kmc_debug_signatures"]
 
 
 class KmcError(RuntimeError):
@@ -56,7 +58,8 @@ class Stats(ctypes.Structure):
         "max_bin_kmers", "n_tiles", "n_big_tiles", "bytes_alg", "split_passes")] + [
         (n, ctypes.c_double) for n in (
             "us_map", "us_split", "us_expand", "us_sort", "us_assemble", "us_total")] + [
-        ("us_kernel", ctypes.c_double * 8)]
+        ("us_kernel", ctypes.c_double * 8), ("us_queue", ctypes.c_double),
+        ("us_latency", ctypes.c_double)]
 
     def as_dict(self):
         d = {n: getattr(self, n) for n, _ in self._fields_ if n != "us_kernel"}
@@ -73,6 +76,21 @@ class Table(ctypes.Structure):
                 ("sig_to_bin", ctypes.POINTER(ctypes.c_uint32)),
                 ("on_device", ctypes.c_int32), ("reserved", ctypes.c_int32),
                 ("stats", Stats)]
+
+
+class Job(ctypes.Structure):
+    _fields_ = [("reads", Reads), ("params", Params)]
+
+
+class ServerCfg(ctypes.Structure):
+    _fields_ = [("hbm_budget", ctypes.c_uint64), ("max_active", ctypes.c_uint32),
+                ("reserved", ctypes.c_uint32)]
+
+
+class ServerStats(ctypes.Structure):
+    _fields_ = [(n, ctypes.c_uint64) for n in (
+        "submitted", "completed", "failed", "admitted_bytes", "peak_admitted_bytes", "budget")] + [
+        ("active", ctypes.c_uint32), ("queued", ctypes.c_uint32)]
 
 
 _lib = None
@@ -117,6 +135,26 @@ def lib() -> ctypes.CDLL:
         L.kmc_debug_signatures.argtypes = [vp, ctypes.POINTER(Reads), ctypes.c_uint32,
                                            ctypes.c_uint32, ctypes.c_uint32, vp, vp]
         L.kmc_debug_signatures.restype = ctypes.c_int
+        L.kmc_workspace_size.argtypes = [ctypes.POINTER(Reads), ctypes.POINTER(Params),
+                                         ctypes.POINTER(ctypes.c_size_t)]
+        L.kmc_workspace_size.restype = ctypes.c_int
+        L.kmc_count_ws.argtypes = [vp, ctypes.POINTER(Reads), ctypes.POINTER(Params), vp, vp,
+                                   ctypes.c_size_t, ctypes.POINTER(ctypes.POINTER(Table))]
+        L.kmc_count_ws.restype = ctypes.c_int
+        L.kmc_batch_count.argtypes = [vp, ctypes.POINTER(Job), ctypes.c_uint32,
+                                      ctypes.POINTER(ctypes.POINTER(Table))]
+        L.kmc_batch_count.restype = ctypes.c_int
+        L.kmc_server_start.argtypes = [vp, ctypes.POINTER(ServerCfg), ctypes.POINTER(vp)]
+        L.kmc_server_start.restype = ctypes.c_int
+        L.kmc_server_submit.argtypes = [vp, ctypes.POINTER(Job), ctypes.POINTER(ctypes.c_uint64)]
+        L.kmc_server_submit.restype = ctypes.c_int
+        L.kmc_server_poll.argtypes = [vp, ctypes.c_uint64, ctypes.c_int32,
+                                      ctypes.POINTER(ctypes.POINTER(Table))]
+        L.kmc_server_poll.restype = ctypes.c_int
+        L.kmc_server_stats_get.argtypes = [vp, ctypes.POINTER(ServerStats)]
+        L.kmc_server_stats_get.restype = ctypes.c_int
+        L.kmc_server_stop.argtypes = [vp]
+        L.kmc_server_stop.restype = None
         _lib = L
     return _lib
 
@@ -212,7 +250,7 @@ class Context:
     def count(self, seq, offsets, k: int, p: int, n_bins: int, cutoff_min: int = 2,
               cutoff_max: int = 10**9, flags: int = 0, stream=None) -> Result:
         reads, keep = make_reads(seq, offsets)
-        params = Params(k, p, n_bins, cutoff_min, min(cutoff_max, 2**32 - 1), flags)
+        params = make_params(k, p, n_bins, cutoff_min, cutoff_max, flags)
         out = ctypes.POINTER(Table)()
         sp = None
         if stream is not None:
@@ -223,6 +261,53 @@ class Context:
         if st != KMC_OK:
             self._raise(st, "kmc_count_ex")
         return Result(out)
+
+    def workspace_size(self, seq, offsets, k: int, p: int, n_bins: int, cutoff_min: int = 2,
+                       cutoff_max: int = 10**9, flags: int = 0) -> int:
+        reads, keep = make_reads(seq, offsets)
+        params = make_params(k, p, n_bins, cutoff_min, cutoff_max, flags)
+        out = ctypes.c_size_t(0)
+        st = lib().kmc_workspace_size(ctypes.byref(reads), ctypes.byref(params), ctypes.byref(out))
+        del keep
+        if st != KMC_OK:
+            raise KmcError(st, f"kmc_workspace_size: {lib().kmc_status_str(st).decode()}")
+        return out.value
+
+    def count_ws(self, seq, offsets, k: int, p: int, n_bins: int, cutoff_min: int, cutoff_max: int,
+                 workspace, flags: int = 0, stream=None) -> Result:
+        """kmc_count_ws: every device buffer of the job is carved from
+        `workspace` (a contiguous torch uint8 tensor on the context's device)."""
+        reads, keep = make_reads(seq, offsets)
+        params = make_params(k, p, n_bins, cutoff_min, cutoff_max, flags)
+        out = ctypes.POINTER(Table)()
+        sp = None
+        if stream is not None:
+            sp = stream if isinstance(stream, int) else stream.cuda_stream
+        st = lib().kmc_count_ws(self._h, ctypes.byref(reads), ctypes.byref(params), sp,
+                                workspace.data_ptr(), workspace.numel() * workspace.element_size(),
+                                ctypes.byref(out))
+        del keep
+        if st != KMC_OK:
+            self._raise(st, "kmc_count_ws")
+        return Result(out)
+
+    def batch_count(self, jobs) -> list:
+        """kmc_batch_count over jobs = [(seq, offsets, params dict), ...];
+        params keys: k, p, n_bins, cutoff_min, cutoff_max[, flags]."""
+        n = len(jobs)
+        arr = (Job * max(n, 1))()
+        keep = []
+        for i, (seq, off, prm) in enumerate(jobs):
+            r, kp = make_reads(seq, off)
+            keep.append(kp)
+            arr[i].reads = r
+            arr[i].params = make_params(**prm)
+        outs = (ctypes.POINTER(Table) * max(n, 1))()
+        st = lib().kmc_batch_count(self._h, arr, n, outs)
+        del keep
+        if st != KMC_OK:
+            self._raise(st, "kmc_batch_count")
+        return [Result(outs[i]) for i in range(n)]
 
     def debug_signatures(self, seq, offsets, k: int, p: int, flags: int = 0):
         reads, keep = make_reads(seq, offsets)
@@ -235,6 +320,66 @@ class Context:
         if st != KMC_OK:
             self._raise(st, "kmc_debug_signatures")
         return sig[:nb], start[:nb]
+
+
+def make_params(k: int, p: int, n_bins: int, cutoff_min: int = 2, cutoff_max: int = 10**9,
+                flags: int = 0) -> Params:
+    return Params(k, p, n_bins, cutoff_min, min(cutoff_max, 2**32 - 1), flags)
+
+
+class Server:
+    """kmc_server_*: jobs submitted while others run, admitted by their HBM
+    footprint against `hbm_budget` bytes (0 = 90% of free device memory), at
+    most `max_active` at once (0 = 4)."""
+
+    def __init__(self, ctx: Context, hbm_budget: int = 0, max_active: int = 0):
+        self._h = ctypes.c_void_p()
+        self._keep = {}
+        cfg = ServerCfg(hbm_budget, max_active, 0)
+        st = lib().kmc_server_start(ctx._h, ctypes.byref(cfg), ctypes.byref(self._h))
+        if st != KMC_OK:
+            raise KmcError(st, f"kmc_server_start: {lib().kmc_status_str(st).decode()}")
+
+    def submit(self, seq, offsets, k: int, p: int, n_bins: int, cutoff_min: int = 2,
+               cutoff_max: int = 10**9, flags: int = 0) -> int:
+        reads, keep = make_reads(seq, offsets)
+        job = Job(reads, make_params(k, p, n_bins, cutoff_min, cutoff_max, flags))
+        t = ctypes.c_uint64(0)
+        st = lib().kmc_server_submit(self._h, ctypes.byref(job), ctypes.byref(t))
+        if st != KMC_OK:
+            raise KmcError(st, f"kmc_server_submit: {lib().kmc_status_str(st).decode()}")
+        self._keep[t.value] = keep  # the reads stay borrowed until polled
+        return t.value
+
+    def poll(self, ticket: int, wait: bool = True):
+        """The job's Result, or None if it is not done and wait is False."""
+        out = ctypes.POINTER(Table)()
+        st = lib().kmc_server_poll(self._h, ticket, 1 if wait else 0, ctypes.byref(out))
+        if st == KMC_ERR_BUSY and not wait:
+            return None
+        self._keep.pop(ticket, None)
+        if st != KMC_OK:
+            raise KmcError(st, f"kmc_server_poll: {lib().kmc_status_str(st).decode()}")
+        return Result(out)
+
+    def stats(self) -> dict:
+        s = ServerStats()
+        st = lib().kmc_server_stats_get(self._h, ctypes.byref(s))
+        if st != KMC_OK:
+            raise KmcError(st, "kmc_server_stats_get")
+        return {n: getattr(s, n) for n, _ in s._fields_}
+
+    def stop(self):
+        if self._h:
+            lib().kmc_server_stop(self._h)
+            self._h = ctypes.c_void_p()
+            self._keep.clear()
+
+    def __del__(self):
+        try:
+            self.stop()
+        except Exception:
+            pass
 
 
 def count(seq, offsets, k: int, p: int, n_bins: int, cutoff_min: int = 2,

@@ -19,6 +19,8 @@ experiments; the paper's own datasets are not used, these stand in for them):
   repeat families (unit length U{1000..5000}; half interspersed with 2-10
   copies, half tandem arrays of 2-20 adjacent copies; each copy diverged by
   d ~ U[0, 0.10] substitutions).
+- ``batch_job`` / ``served_job``: the uneven jobs of the batched form and the
+  arrivals of the served form.
 """
 from __future__ import annotations
 
@@ -138,6 +140,33 @@ CONFIGS = {
     "genome-5M-2Mx100": dict(k=28, p=7, n_bins=512, cutoff_min=2, cutoff_max=10**9),
     "repeats-50M-30x150-k55": dict(k=55, p=9, n_bins=1024, cutoff_min=2, cutoff_max=10**6),
 }
+
+
+def batch_job(j: int, scale: float = 1.0):
+    """Job j of the batch of uneven jobs: n_reads = floor(10^U(4,6)) (times
+    scale), read lengths U{100..250}, a uniform reference of
+    max(10^4, n_reads * 175 / 30) bases (about 30x), 1% substitutions, no N;
+    k drawn from {21, 25, 31, 47, 55}, p = 7, 512 bins, cutoffs 2..10^9.
+    Seeds (4, j, 0..2).  Returns (seq, offsets, params)."""
+    rng = _rng((4, j, 0))
+    n_reads = max(1, int(10 ** rng.uniform(4, 6) * scale))
+    k = int(rng.choice([21, 25, 31, 47, 55]))
+    ref = random_reference((4, j, 1), max(10_000, int(n_reads * 175 / 30)))
+    seq, off = sample_reads((4, j, 2), ref, n_reads, (100, 250), err=0.01, n_rate=0.0)
+    return seq, off, dict(k=k, p=7, n_bins=512, cutoff_min=2, cutoff_max=10**9)
+
+
+def served_job(i: int, scale: float = 1.0):
+    """Served job i: the repeat-rich generator with a reference whose length
+    is log-uniform in [5, 50] Mbp (times scale), 30x of 150 bp reads, 0.5%
+    substitutions, 0.1% N; k = 55, p = 9, 1024 bins, cutoffs 2..10^6.
+    Seeds (5, i, 0..2).  Returns (seq, offsets, params)."""
+    rng = _rng((5, i, 0))
+    length = max(20_000, int(10 ** rng.uniform(np.log10(5e6), np.log10(5e7)) * scale))
+    ref = repeat_reference((5, i, 1), length)
+    seq, off = sample_reads((5, i, 2), ref, max(1, length * 30 // 150), 150,
+                            err=0.005, n_rate=0.001)
+    return seq, off, dict(CONFIGS["repeats-50M-30x150-k55"])
 
 
 def make(name: str, scale: float = 1.0):

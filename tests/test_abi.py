@@ -52,6 +52,9 @@ int main(void) {
   printf("%zu %zu %zu %zu\\n", sizeof(kmc_reads), sizeof(kmc_params), sizeof(kmc_stats), sizeof(kmc_table));
   printf("%zu %zu %zu %zu\\n", offsetof(kmc_table, keys), offsetof(kmc_table, bin_offsets),
          offsetof(kmc_table, on_device), offsetof(kmc_table, stats));
+  printf("%zu %zu %zu %zu %zu\\n", sizeof(kmc_job), offsetof(kmc_job, params),
+         sizeof(kmc_server_cfg), sizeof(kmc_server_stats), offsetof(kmc_server_stats, active));
+  printf("%zu %zu\\n", offsetof(kmc_stats, us_kernel), offsetof(kmc_stats, us_latency));
   return 0;
 }
 """)
@@ -64,6 +67,11 @@ int main(void) {
                      ctypes.sizeof(kmc.Stats), ctypes.sizeof(kmc.Table)]
     assert offs == [kmc.Table.keys.offset, kmc.Table.bin_offsets.offset,
                     kmc.Table.on_device.offset, kmc.Table.stats.offset]
+    assert [int(x) for x in lines[2].split()] == [
+        ctypes.sizeof(kmc.Job), kmc.Job.params.offset, ctypes.sizeof(kmc.ServerCfg),
+        ctypes.sizeof(kmc.ServerStats), kmc.ServerStats.active.offset]
+    assert [int(x) for x in lines[3].split()] == [kmc.Stats.us_kernel.offset,
+                                                  kmc.Stats.us_latency.offset]
 
 
 def test_status_strings(kmc):
@@ -100,3 +108,45 @@ def test_malformed_offsets_rejected(kmc, off):
     out = ctypes.POINTER(kmc.Table)()
     st = kmc.lib().kmc_count(ctypes.byref(reads), 28, 7, 16, 1, 5, ctypes.byref(out))
     assert st == kmc.KMC_ERR_INVALID_ARG
+
+
+def _ws(kmc, n_reads, length, k, p=7, n_bins=512, ci=1, cx=10):
+    seq = np.full(n_reads * length, ord("A"), dtype=np.uint8)
+    off = np.arange(n_reads + 1, dtype=np.uint64) * length
+    reads, keep = kmc.make_reads(seq, off)
+    params = kmc.Params(k, p, n_bins, ci, cx, 0)
+    out = ctypes.c_size_t(0)
+    st = kmc.lib().kmc_workspace_size(ctypes.byref(reads), ctypes.byref(params), ctypes.byref(out))
+    return st, out.value
+
+
+def test_workspace_size_is_host_only_and_bounded(kmc):
+    # computed from the sizes alone (no device here): grows with the input,
+    # about 2x for 2-word keys, and rejects what kmc_count rejects
+    st, small = _ws(kmc, 100, 100, 28)
+    assert st == kmc.KMC_OK and small > 0
+    st, big = _ws(kmc, 10_000, 100, 28)
+    assert st == kmc.KMC_OK and big > small
+    n = 10_000 * 100
+    assert 16 * n < big < 40 * n
+    st, big2 = _ws(kmc, 10_000, 100, 55, p=9, n_bins=1024)
+    assert st == kmc.KMC_OK and big2 > 1.5 * big
+    assert _ws(kmc, 10, 100, 28, ci=11, cx=10)[0] == kmc.KMC_ERR_INVALID_ARG
+    assert _ws(kmc, 10, 100, 3, p=4)[0] == kmc.KMC_ERR_INVALID_ARG
+    st, empty = _ws(kmc, 0, 100, 28)
+    assert st == kmc.KMC_OK and 0 < empty < small
+
+
+def test_batch_and_server_reject_null_handles(kmc):
+    L = kmc.lib()
+    outs = (ctypes.POINTER(kmc.Table) * 1)()
+    job = kmc.Job()
+    assert L.kmc_batch_count(None, ctypes.byref(job), 1, outs) == kmc.KMC_ERR_INVALID_ARG
+    srv = ctypes.c_void_p()
+    assert L.kmc_server_start(None, None, ctypes.byref(srv)) == kmc.KMC_ERR_INVALID_ARG
+    assert not srv
+    t = ctypes.c_uint64(0)
+    assert L.kmc_server_submit(None, ctypes.byref(job), ctypes.byref(t)) == kmc.KMC_ERR_INVALID_ARG
+    out = ctypes.POINTER(kmc.Table)()
+    assert L.kmc_server_poll(None, 1, 0, ctypes.byref(out)) == kmc.KMC_ERR_INVALID_ARG
+    L.kmc_server_stop(None)
