@@ -117,8 +117,175 @@ def cpu_baseline(seq, off, p, budget_s: float = 15.0):
                       f"{cores} threads"}
 
 
+def _gen(task):
+    from paper_1407_1507_amd import synth
+    kind, i, scale = task
+    return (synth.batch_job if kind == "batch" else synth.served_job)(i, scale)
+
+
+def generate(kind: str, n: int, scale: float):
+    """Jobs 0..n-1 of a generator, built in parallel host processes (before
+    this process touches the GPU)."""
+    from concurrent.futures import ProcessPoolExecutor
+    workers = max(1, min(16, os.cpu_count() or 1, n))
+    with ProcessPoolExecutor(workers) as ex:
+        return list(ex.map(_gen, [(kind, i, scale) for i in range(n)]))
+
+
+def to_device(jobs):
+    import torch
+    out = []
+    for seq, off, p in jobs:
+        out.append((torch.from_numpy(seq).to("cuda:0"),
+                    torch.from_numpy(off.view(np.int64)).to("cuda:0"), p))
+    torch.cuda.synchronize()
+    return out
+
+
+def bench_batch(args):
+    """The batched form: one step = one kmc_batch_count over every job."""
+    jobs = generate("batch", args.batch_jobs, args.batch_scale)
+    import torch
+    from paper_1407_1507_amd import kmc
+    djobs = to_device(jobs)
+    bases = int(sum(int(o[-1]) for _, o, _ in jobs))
+    ctx = kmc.Context(0)
+    prm = [dict(p, flags=kmc.FLAG_DEVICE_TABLE) for _, _, p in djobs]
+    batch = [(s, o, q) for (s, o, _), q in zip(djobs, prm)]
+    for _ in range(args.warmup):
+        for r in ctx.batch_count(batch):
+            r.free()
+    torch.cuda.synchronize()
+    times, kmers = [], 0
+    for _ in range(args.steps):
+        t = time.perf_counter()
+        res = ctx.batch_count(batch)
+        torch.cuda.synchronize()
+        times.append(time.perf_counter() - t)
+        kmers = sum(r.stats["n_kmers"] for r in res)
+        for r in res:
+            r.free()
+    # the same jobs one after another on one stream, for comparison
+    t = time.perf_counter()
+    for s, o, q in batch:
+        ctx.count(s, o, q["k"], q["p"], q["n_bins"], q["cutoff_min"], q["cutoff_max"],
+                  flags=q["flags"]).free()
+    torch.cuda.synchronize()
+    serial = time.perf_counter() - t
+    ctx.close()
+    ms = float(np.mean(times)) * 1e3
+    ks = sorted({p["k"] for _, _, p in jobs})
+    return {
+        "metric": METRIC, "value": bases / (ms * 1e-3), "unit": "bases/s", "n_gpus": 1,
+        "steps": args.steps, "warmup": args.warmup, "ms_per_step": ms,
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "u64/u128",
+        "data": "synthetic (seeded generator)",
+        "config": {"workload": f"batch of {len(jobs)} uneven jobs (scale {args.batch_scale}): "
+                               "n_reads = 10^U(4,6), read length U{100..250}, ~30x uniform "
+                               "references, 1% substitutions, k in {21,25,31,47,55}, p=7, "
+                               "512 bins, cutoffs 2..1e9",
+                   "n_jobs": len(jobs), "n_bases": bases, "k_values": ks},
+        "kmers_per_s": kmers / (ms * 1e-3),
+        "serial_ms": serial * 1e3,
+        "speedup_vs_serial": serial * 1e3 / ms,
+    }
+
+
+def bench_serve(args):
+    """The served form: closed-loop saturation rate, then Poisson arrivals at
+    fractions of it; p50 / p99 of each job's submit-to-ready latency."""
+    import queue
+    import threading
+    pool = generate("serve", args.serve_pool, args.serve_scale)
+    import torch
+    from paper_1407_1507_amd import kmc
+    djobs = to_device(pool)
+    ctx = kmc.Context(0)
+    out = {"metric": METRIC, "unit": "jobs/s", "n_gpus": 1, "higher_is_better": True,
+           "data": "synthetic (seeded generator)", "dtype": "u128",
+           "config": {"workload": f"served jobs: {len(pool)} distinct read sets (scale "
+                                  f"{args.serve_scale}) of the repeat-rich generator, "
+                                  "references log-uniform in [5, 50] Mbp x scale, 30x of "
+                                  "150 bp, k=55, p=9, 1024 bins, cutoffs 2..1e6",
+                      "pool_bases": int(sum(int(o[-1]) for _, o, _ in pool)),
+                      "max_active": args.max_active},
+           "budgets": {}}
+
+    def job(i):
+        s, o, p = djobs[i % len(djobs)]
+        return s, o, p["k"], p["p"], p["n_bins"], p["cutoff_min"], p["cutoff_max"]
+
+    for label, budget in (("full", 0), ("24GB", 24 << 30)):
+        srv = kmc.Server(ctx, hbm_budget=budget, max_active=args.max_active)
+        for i in range(len(djobs)):  # warm every worker stream and shape
+            srv.poll(srv.submit(*job(i))).free()
+        # closed loop: every job queued at once
+        n_sat = max(6 * len(djobs), 64)
+        t = time.perf_counter()
+        tickets = [srv.submit(*job(i)) for i in range(n_sat)]
+        for tk in tickets:
+            srv.poll(tk).free()
+        sat = n_sat / (time.perf_counter() - t)
+        rows = []
+        rng = np.random.default_rng(5)
+        for frac in args.serve_lambdas:
+            lam = frac * sat
+            n = args.serve_arrivals
+            gaps = rng.exponential(1.0 / lam, size=n)
+            tickets = queue.Queue()
+            results = []
+
+            def poller():
+                for _ in range(n):
+                    r = srv.poll(tickets.get())
+                    results.append((r.stats["us_latency"], r.stats["us_queue"],
+                                    r.stats["n_bases"]))
+                    r.free()
+
+            th = threading.Thread(target=poller)
+            th.start()
+            t0 = time.perf_counter()
+            nxt = t0
+            for i in range(n):
+                nxt += gaps[i]
+                d = nxt - time.perf_counter()
+                if d > 0:
+                    time.sleep(d)
+                tickets.put(srv.submit(*job(i)))
+            th.join()
+            span = time.perf_counter() - t0
+            lat = np.array([x[0] for x in results]) * 1e-3
+            q = np.array([x[1] for x in results]) * 1e-3
+            rows.append({"lambda_frac": frac, "lambda_jobs_s": lam, "arrivals": n,
+                         "achieved_jobs_s": n / span,
+                         "bases_per_s": sum(x[2] for x in results) / span,
+                         "latency_ms_p50": float(np.percentile(lat, 50)),
+                         "latency_ms_p99": float(np.percentile(lat, 99)),
+                         "queue_ms_p50": float(np.percentile(q, 50)),
+                         "queue_ms_p99": float(np.percentile(q, 99))})
+            print(f"serve {label} lambda {frac}: {rows[-1]}", file=sys.stderr, flush=True)
+        st = srv.stats()
+        srv.stop()
+        out["budgets"][label] = {"budget_bytes": st["budget"], "saturation_jobs_s": sat,
+                                 "peak_admitted_bytes": st["peak_admitted_bytes"],
+                                 "points": rows}
+    ctx.close()
+    full = out["budgets"]["full"]
+    out["value"] = full["saturation_jobs_s"]
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
+    ap.add_argument("--mode", choices=["single", "batch", "serve"], default="single")
+    ap.add_argument("--batch-jobs", type=int, default=256)
+    ap.add_argument("--batch-scale", type=float, default=1.0)
+    ap.add_argument("--serve-pool", type=int, default=16)
+    ap.add_argument("--serve-scale", type=float, default=0.25)
+    ap.add_argument("--serve-arrivals", type=int, default=200)
+    ap.add_argument("--serve-lambdas", type=float, nargs="+",
+                    default=[0.25, 0.5, 0.7, 0.85, 1.0, 1.2])
+    ap.add_argument("--max-active", type=int, default=4)
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=2)
@@ -134,6 +301,11 @@ def main():
         print("bench.py measures one GPU: the counting path runs on a single MI355X "
               "(see DESIGN.md for how it would shard); run with --gpus 1", file=sys.stderr)
         sys.exit(2)
+
+    if args.mode != "single":
+        line = bench_batch(args) if args.mode == "batch" else bench_serve(args)
+        print(json.dumps(line), flush=True)
+        return
 
     import torch
     from paper_1407_1507_amd import kmc, synth
