@@ -27,11 +27,16 @@ namespace kmc {
 namespace {
 
 template <int KW> struct SortCfg;
+// CAP: keys a workgroup holds; DIRECT: largest tile the tile kernel counts
+// itself (64-bit keys: the LDS hash table at load <= 3/4), larger ones go to
+// the big-tile kernel, whose register budget is its own.
 template <> struct SortCfg<1> {
   static constexpr uint32_t CAP = kTileCap1, DIG = 12, ITEMS = kTileCap1 / kSortThreads;
+  static constexpr uint32_t DIRECT = 3 * kTileCap1 / 4;
 };
 template <> struct SortCfg<2> {
   static constexpr uint32_t CAP = kTileCap2, DIG = 11, ITEMS = kTileCap2 / kSortThreads;
+  static constexpr uint32_t DIRECT = kTileCap2;
 };
 constexpr uint32_t kInsMax = 16;    // mixed buckets up to this size: insertion sort by one lane
 constexpr uint32_t kBigMax = 256;   // larger mixed buckets listed per tile (CAP / (kInsMax + 1) < 256)
@@ -261,7 +266,7 @@ __device__ void order_kept(typename KeyOf<KW>::T (&key)[SortCfg<KW>::ITEMS],
 }
 
 template <int KW>
-__device__ uint32_t count_tile(typename KeyOf<KW>::T (&key)[SortCfg<KW>::ITEMS], uint32_t n,
+__device__ __forceinline__ uint32_t count_tile(typename KeyOf<KW>::T (&key)[SortCfg<KW>::ITEMS], uint32_t n,
                                uint64_t* out_keys, uint32_t* out_counts, uint32_t ci,
                                uint32_t cx, SortShared<KW>& S, uint32_t* distinct);
 
@@ -272,7 +277,7 @@ __device__ uint32_t count_tile(typename KeyOf<KW>::T (&key)[SortCfg<KW>::ITEMS],
 // the run length a sort of the tile would give that key.  Kept keys are then
 // put in key order by order_kept.  The all-ones key marks an empty slot: it is
 // never canonical (its reverse complement, all A, is smaller).
-__device__ uint32_t count_tile_hash(uint64_t (&key)[SortCfg<1>::ITEMS], uint32_t n,
+__device__ __forceinline__ uint32_t count_tile_hash(uint64_t (&key)[SortCfg<1>::ITEMS], uint32_t n,
                                     uint64_t* out_keys, uint32_t* out_counts, uint32_t ci,
                                     uint32_t cx, SortShared<1>& S, uint32_t* distinct) {
   constexpr uint32_t ITEMS = SortCfg<1>::ITEMS, T = SortCfg<1>::CAP, TB = 12;
@@ -354,9 +359,24 @@ __device__ __forceinline__ uint32_t count_any<1>(uint64_t (&key)[SortCfg<1>::ITE
                                                  uint64_t* out_keys, uint32_t* out_counts,
                                                  uint32_t ci, uint32_t cx, SortShared<1>& S,
                                                  uint32_t* distinct) {
-  if (n <= SortCfg<1>::CAP / 2)
+  if (n <= SortCfg<1>::DIRECT)
     return count_tile_hash(key, n, out_keys, out_counts, ci, cx, S, distinct);
   return count_tile<1>(key, n, out_keys, out_counts, ci, cx, S, distinct);
+}
+
+// The tile kernel's counting: only the hash table for 64-bit keys (tiles up
+// to DIRECT keys), so the kernel carries none of the bucket path's registers.
+__device__ __forceinline__ uint32_t count_direct(uint64_t (&key)[SortCfg<1>::ITEMS], uint32_t n,
+                                                 uint64_t* out_keys, uint32_t* out_counts,
+                                                 uint32_t ci, uint32_t cx, SortShared<1>& S,
+                                                 uint32_t* distinct) {
+  return count_tile_hash(key, n, out_keys, out_counts, ci, cx, S, distinct);
+}
+__device__ __forceinline__ uint32_t count_direct(u128 (&key)[SortCfg<2>::ITEMS], uint32_t n,
+                                                 uint64_t* out_keys, uint32_t* out_counts,
+                                                 uint32_t ci, uint32_t cx, SortShared<2>& S,
+                                                 uint32_t* distinct) {
+  return count_tile<2>(key, n, out_keys, out_counts, ci, cx, S, distinct);
 }
 template <>
 __device__ __forceinline__ uint32_t count_any<2>(u128 (&key)[SortCfg<2>::ITEMS], uint32_t n,
@@ -388,7 +408,7 @@ __device__ uint32_t sort_count_emit(const uint64_t* src, uint32_t n, uint64_t* o
 // Same as sort_count_emit, with the tile's keys already in registers
 // (key[m] = key m * blockDim.x + threadIdx.x, for those < n); key is clobbered.
 template <int KW>
-__device__ uint32_t count_tile(typename KeyOf<KW>::T (&key)[SortCfg<KW>::ITEMS], uint32_t n,
+__device__ __forceinline__ uint32_t count_tile(typename KeyOf<KW>::T (&key)[SortCfg<KW>::ITEMS], uint32_t n,
                                uint64_t* out_keys, uint32_t* out_counts, uint32_t ci,
                                uint32_t cx, SortShared<KW>& S, uint32_t* distinct) {
   typedef typename KeyOf<KW>::T K;
@@ -552,7 +572,7 @@ __device__ uint32_t count_tile(typename KeyOf<KW>::T (&key)[SortCfg<KW>::ITEMS],
 // workgroup g takes tiles g, g + G, g + 2G, ... (tens of thousands of short
 // tiles would otherwise be bound by workgroup dispatch).
 template <int KW>
-__global__ void __launch_bounds__(kSortThreads)
+__global__ void __launch_bounds__(kSortThreads, 3)  // 3 waves per SIMD: as many as LDS allows
 k_tile_sort(KeyCfg kc, const Tile* __restrict__ tiles, uint64_t n_tiles, uint64_t* keys,
             uint32_t* counts, uint32_t* tile_out, uint32_t* big_list, uint64_t* big_off,
             uint32_t* n_big, unsigned long long* big_total, uint32_t* tile_distinct) {
@@ -563,7 +583,7 @@ k_tile_sort(KeyCfg kc, const Tile* __restrict__ tiles, uint64_t n_tiles, uint64_
     const Tile T = tiles[t];
     if (T.size == 0) {
       if (threadIdx.x == 0) tile_out[t] = tile_distinct[t] = 0;
-    } else if (T.size > CAP) {
+    } else if (T.size > SortCfg<KW>::DIRECT) {
       if (threadIdx.x == 0) {
         tile_out[t] = tile_distinct[t] = 0;
         const uint32_t idx = atomicAdd(n_big, 1u);
@@ -574,8 +594,8 @@ k_tile_sort(KeyCfg kc, const Tile* __restrict__ tiles, uint64_t n_tiles, uint64_
       K key[ITEMS];
       load_tile<KW>(keys + T.begin * KW, T.size, key);
       uint32_t d;
-      const uint32_t kept = count_any<KW>(key, T.size, keys + T.begin * KW, counts + T.begin,
-                                          kc.cutoff_min, kc.cutoff_max, S, &d);
+      const uint32_t kept = count_direct(key, T.size, keys + T.begin * KW, counts + T.begin,
+                                         kc.cutoff_min, kc.cutoff_max, S, &d);
       if (threadIdx.x == 0) {
         tile_out[t] = kept;
         tile_distinct[t] = d;
