@@ -365,6 +365,8 @@ def main():
         "latency_ms_p50": float(np.percentile(lat, 50) * 1e3),
         "latency_ms_p99": float(np.percentile(lat, 99) * 1e3),
         "kernel_us": {n: round(v, 2) for n, v in mean_us.items()},
+        "phase_us": {n: round(float(np.mean([x["us_" + n] for x in stats])), 2)
+                     for n in ("map", "split", "expand", "sort", "assemble")},
         "job": {key: st[key] for key in ("n_kmers", "n_superkmers", "n_distinct", "n_out",
                                          "n_tiles", "n_big_tiles", "bytes_alg")},
         "roofline": {"bound": "hbm", "kernel": dom, "achieved": achieved,

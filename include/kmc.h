@@ -135,8 +135,10 @@ typedef struct kmc_stats {
  *   bin_offsets n_bins + 1 uint64 (always host memory);
  *   sig_to_bin  4^p + 1 uint32: bin of every signature value; the last entry
  *               is for k-mers with no allowed p-mer (always host memory).
- * keys/counts are host memory unless on_device = 1.  reserved = 1 marks a
- * device table whose keys/counts live in a caller's workspace (kmc_count_ws).
+ * keys/counts are host memory unless on_device = 1.  reserved records how
+ * the library owns keys/counts (1: in a caller's workspace, kmc_count_ws;
+ * 2: a device block that kmc_table_free hands back to the library's pool of
+ * table memory for later tables); callers leave it alone.
  * The table is owned by the library: release it with kmc_table_free. */
 typedef struct kmc_table {
   uint32_t k;

@@ -7,9 +7,11 @@
 #include <cstdio>
 #include <cstdlib>
 #include <cstring>
+#include <mutex>
 #include <new>
 #include <queue>
 #include <string>
+#include <unordered_map>
 #include <utility>
 #include <vector>
 
@@ -40,6 +42,8 @@ struct Misc {
   unsigned long long big_total;
   uint32_t n_big;
   uint32_t offsets_err;
+  uint32_t big_next;  // work counter of the big-tile kernel
+  uint32_t pad;
 };
 
 }  // namespace
@@ -52,11 +56,16 @@ struct WsLayout {
   size_t total;
 };
 
+// Pinned host buffers for the small transfers between the phases (plans,
+// counters, histograms), cached like the device buffers.
+enum HostId { H_HIST, H_CNT, H_BASES, H_MISC, H_BINOFF, H_MAP, H_COUNT_ };
+
 struct kmc_ctx {
   int device = 0;
   hipStream_t stream = nullptr;
   std::string err;
   DevBuf buf[B_COUNT_];
+  DevBuf hbuf[H_COUNT_];  // pinned host memory
   hipEvent_t ev[32] = {};  // 0..5 phases, 8 + 2i / 9 + 2i kernel i, 28 / 29 gather
   // workspace mode (kmc_count_ws): buffers come from ws_base + layout
   uint8_t* ws_base = nullptr;
@@ -79,6 +88,20 @@ void check(kmc_ctx* c, hipError_t e, const char* what) {
     (void)hipGetLastError();
     throw Fail{e == hipErrorOutOfMemory ? KMC_ERR_OUT_OF_MEMORY : KMC_ERR_DEVICE};
   }
+}
+
+template <class T>
+T* ensure_host(kmc_ctx* c, HostId id, size_t bytes) {
+  DevBuf& b = c->hbuf[id];
+  if (b.cap < bytes) {
+    if (b.p) (void)hipHostFree(b.p);
+    b.p = nullptr;
+    b.cap = 0;
+    const size_t want = std::max<size_t>(bytes + bytes / 4, 4096);
+    check(c, hipHostMalloc(&b.p, want, 0), "hipHostMalloc");
+    b.cap = want;
+  }
+  return static_cast<T*>(b.p);
 }
 
 template <class T>
@@ -118,25 +141,133 @@ uint32_t ilog2_ceil(uint64_t x) {
 // sample go to bin (signature mod n_bins).
 void build_map(const std::vector<uint32_t>& hist, uint32_t n_bins, std::vector<uint32_t>& map) {
   const uint32_t n_sig = (uint32_t)hist.size();
-  map.assign(n_sig, 0);
-  for (uint32_t s = 0; s < n_sig; ++s) map[s] = s % n_bins;
-  std::vector<std::pair<uint32_t, uint32_t>> seen;
-  for (uint32_t s = 0; s < n_sig; ++s)
-    if (hist[s]) seen.emplace_back(hist[s], s);
-  std::sort(seen.begin(), seen.end(), [](const std::pair<uint32_t, uint32_t>& a,
-                                         const std::pair<uint32_t, uint32_t>& b) {
-    return a.first != b.first ? a.first > b.first : a.second < b.second;
-  });
-  typedef std::pair<uint64_t, uint32_t> LB;  // (load, bin)
-  std::priority_queue<LB, std::vector<LB>, std::greater<LB>> pq;
-  for (uint32_t b = 0; b < n_bins; ++b) pq.emplace(0, b);
-  for (const auto& e : seen) {
-    LB top = pq.top();
-    pq.pop();
-    map[e.second] = top.second;
-    top.first += e.first;
-    pq.push(top);
+  map.resize(n_sig);
+  std::vector<uint32_t> a, b;
+  a.reserve(n_sig);
+  uint32_t maxc = 0;
+  for (uint32_t s = 0; s < n_sig; ++s) {
+    map[s] = s % n_bins;
+    if (hist[s]) {
+      a.push_back(s);
+      maxc = std::max(maxc, hist[s]);
+    }
   }
+  // seen signatures by descending count, ascending signature among equal
+  // counts: a stable LSD radix sort on the complemented count
+  b.resize(a.size());
+  for (uint32_t shift = 0; shift < 32 && (maxc >> shift); shift += 11) {
+    std::vector<uint32_t> cnt(2049, 0);
+    for (uint32_t s : a) ++cnt[1 + ((~hist[s] >> shift) & 2047u)];
+    for (uint32_t i = 0; i < 2048; ++i) cnt[i + 1] += cnt[i];
+    for (uint32_t s : a) b[cnt[(~hist[s] >> shift) & 2047u]++] = s;
+    a.swap(b);
+  }
+  // each to the lightest bin: binary min-heap of (load << 16 | bin), so equal
+  // loads go to the lowest bin id (n_bins <= 65535)
+  std::vector<uint64_t> heap(n_bins);
+  for (uint32_t i = 0; i < n_bins; ++i) heap[i] = i;
+  for (uint32_t s : a) {
+    uint64_t top = heap[0];
+    map[s] = (uint32_t)(top & 0xFFFFu);
+    top += (uint64_t)hist[s] << 16;
+    uint32_t i = 0;
+    for (;;) {
+      const uint32_t l = 2 * i + 1;
+      if (l >= n_bins) break;
+      const uint32_t m = (l + 1 < n_bins && heap[l + 1] < heap[l]) ? l + 1 : l;
+      if (heap[m] >= top) break;
+      heap[i] = heap[m];
+      i = m;
+    }
+    heap[i] = top;
+  }
+}
+
+// Device tables are recycled: a freed table's memory (keys and counts in one
+// block) goes to a per-process pool and serves a later table of a similar
+// size, so that a stream of jobs does not pay a device allocation (and the
+// synchronisation of a device free) per table.  The pool keeps at most
+// kPoolKeep bytes per device; anything beyond that is freed at once.
+constexpr size_t kPoolKeep = size_t(8) << 30;
+
+struct TablePool {
+  struct Block {
+    int device;
+    size_t bytes;
+    void* p;
+  };
+  std::mutex mu;
+  std::vector<Block> free_blocks;
+  std::unordered_map<void*, Block> live;
+  size_t kept[64] = {};
+};
+
+TablePool& table_pool() {
+  static TablePool* pool = new TablePool;  // never destroyed: tables may outlive everything
+  return *pool;
+}
+
+void* pool_take(int device, size_t bytes) {
+  TablePool& P = table_pool();
+  {
+    std::lock_guard<std::mutex> lk(P.mu);
+    size_t best = SIZE_MAX;
+    for (size_t i = 0; i < P.free_blocks.size(); ++i) {
+      const auto& b = P.free_blocks[i];
+      if (b.device == device && b.bytes >= bytes && b.bytes <= 2 * bytes + (1 << 20) &&
+          (best == SIZE_MAX || b.bytes < P.free_blocks[best].bytes))
+        best = i;
+    }
+    if (best != SIZE_MAX) {
+      TablePool::Block b = P.free_blocks[best];
+      P.free_blocks.erase(P.free_blocks.begin() + best);
+      P.kept[device & 63] -= b.bytes;
+      P.live.emplace(b.p, b);
+      return b.p;
+    }
+  }
+  void* p = nullptr;
+  if (hipMalloc(&p, bytes) != hipSuccess) {
+    (void)hipGetLastError();
+    return nullptr;
+  }
+  std::lock_guard<std::mutex> lk(P.mu);
+  P.live.emplace(p, TablePool::Block{device, bytes, p});
+  return p;
+}
+
+// Returns false if p did not come from the pool.
+bool pool_give(void* p) {
+  TablePool& P = table_pool();
+  TablePool::Block b;
+  std::vector<TablePool::Block> drop;
+  {
+    std::lock_guard<std::mutex> lk(P.mu);
+    auto it = P.live.find(p);
+    if (it == P.live.end()) return false;
+    b = it->second;
+    P.live.erase(it);
+    P.free_blocks.push_back(b);
+    P.kept[b.device & 63] += b.bytes;
+    // over the limit: free the oldest blocks of that device
+    for (size_t i = 0; i < P.free_blocks.size() && P.kept[b.device & 63] > kPoolKeep;) {
+      if (P.free_blocks[i].device == b.device) {
+        P.kept[b.device & 63] -= P.free_blocks[i].bytes;
+        drop.push_back(P.free_blocks[i]);
+        P.free_blocks.erase(P.free_blocks.begin() + i);
+      } else {
+        ++i;
+      }
+    }
+  }
+  for (const auto& d : drop) {
+    int cur = 0;
+    (void)hipGetDevice(&cur);
+    (void)hipSetDevice(d.device);
+    (void)hipFree(d.p);
+    (void)hipSetDevice(cur);
+  }
+  return true;
 }
 
 kmc_table* new_table() {
@@ -149,7 +280,7 @@ struct Job {
   uint64_t n_reads, n_bases;
   const uint8_t* seq;     // device
   const uint64_t* off;    // device
-  bool aligned4;
+  uint32_t seq_align;
 };
 
 ScanCfg scan_cfg(const Job& J) {
@@ -161,7 +292,7 @@ ScanCfg scan_cfg(const Job& J) {
   C.pmask = (uint32_t)((1ull << (2 * J.p)) - 1);
   C.sent = 1u << (2 * J.p);
   C.n_bins = J.n_bins;
-  C.aligned4 = J.aligned4 ? 1u : 0u;
+  C.seq_align = J.seq_align;
   return C;
 }
 
@@ -205,7 +336,7 @@ void stage_reads(kmc_ctx* c, const kmc_reads* R, Job& J) {
     J.seq = s;
     J.off = o;
   }
-  J.aligned4 = ((uintptr_t)J.seq & 3u) == 0;
+  J.seq_align = ((uintptr_t)J.seq & 15u) == 0 ? 16u : ((uintptr_t)J.seq & 3u) == 0 ? 4u : 1u;
 }
 
 void kbeg(kmc_ctx* c, int i, hipStream_t s) { check(c, hipEventRecord(c->ev[8 + 2 * i], s), "event"); }
@@ -259,21 +390,24 @@ void run_count(kmc_ctx* c, const kmc_reads* R, const kmc_params* P, kmc_table* T
   check(c, launch_sig_hist(s, J.seq, J.off, J.n_reads, J.n_bases, stride, C, J.kw, hist,
                            &misc->sample_kmers), "sig_hist");
   kend(c, KMC_K_SIG_HIST, s);
-  std::vector<uint32_t> h_hist(2 * (size_t)n_sig);
-  Misc h_misc;
-  check(c, hipMemcpyAsync(h_hist.data(), hist, (size_t)n_sig * 8, hipMemcpyDeviceToHost, s), "D2H");
-  check(c, hipMemcpyAsync(&h_misc, misc, sizeof(Misc), hipMemcpyDeviceToHost, s), "D2H");
+  uint32_t* h_hist = ensure_host<uint32_t>(c, H_HIST, (size_t)n_sig * 8);
+  Misc* h_misc_p = ensure_host<Misc>(c, H_MISC, sizeof(Misc));
+  check(c, hipMemcpyAsync(h_hist, hist, (size_t)n_sig * 8, hipMemcpyDeviceToHost, s), "D2H");
+  check(c, hipMemcpyAsync(h_misc_p, misc, sizeof(Misc), hipMemcpyDeviceToHost, s), "D2H");
   check(c, hipStreamSynchronize(s), "sync");
+  Misc h_misc = *h_misc_p;
   if (h_misc.offsets_err) throw Fail{KMC_ERR_INVALID_ARG};
   st.sample_kmers = h_misc.sample_kmers;
   std::vector<uint32_t> map;
   {
-    std::vector<uint32_t> hk(h_hist.begin(), h_hist.begin() + n_sig);
+    std::vector<uint32_t> hk(h_hist, h_hist + n_sig);
     build_map(hk, J.n_bins, map);
   }
   std::memcpy(T->sig_to_bin, map.data(), (size_t)n_sig * 4);
+  uint32_t* h_map = ensure_host<uint32_t>(c, H_MAP, (size_t)n_sig * 4);
+  std::memcpy(h_map, map.data(), (size_t)n_sig * 4);
   uint32_t* d_map = ensure<uint32_t>(c, B_MAP, (size_t)n_sig * 4);
-  check(c, hipMemcpyAsync(d_map, map.data(), (size_t)n_sig * 4, hipMemcpyHostToDevice, s), "H2D map");
+  check(c, hipMemcpyAsync(d_map, h_map, (size_t)n_sig * 4, hipMemcpyHostToDevice, s), "H2D map");
   check(c, hipEventRecord(c->ev[1], s), "event");
 
   // ---- split: one pass writing super k-mer records into bin regions sized
@@ -297,16 +431,22 @@ void run_count(kmc_ctx* c, const kmc_reads* R, const kmc_params* P, kmc_table* T
           cap[b] = (uint64_t)((double)cap[b] * (double)room / (double)total);
     }
   }
-  // bases: [0..n_bins] record region base, [n_bins+1..] key base, then tile base
-  std::vector<uint64_t> bases(3 * ((size_t)J.n_bins + 1));
-  uint64_t* rec_base = bases.data();
-  uint64_t* key_base = rec_base + J.n_bins + 1;
-  uint64_t* tile_base = key_base + J.n_bins + 1;
+  // bases, n_bins + 1 entries each: record region base, key base, tile base,
+  // record end, first fine-histogram task, first expansion task (pinned, so
+  // the uploads are asynchronous; written only while the stream is idle)
+  const size_t nb1 = (size_t)J.n_bins + 1, n_bases_words = 6 * nb1;
+  uint64_t* bases = ensure_host<uint64_t>(c, H_BASES, n_bases_words * 8);
+  uint64_t* rec_base = bases;
+  uint64_t* key_base = rec_base + nb1;
+  uint64_t* tile_base = key_base + nb1;
+  uint64_t* rec_end = tile_base + nb1;
+  uint64_t* htask_pre = rec_end + nb1;
+  uint64_t* etask_pre = htask_pre + nb1;
   unsigned long long* bincnt = ensure<unsigned long long>(c, B_BINCNT, (size_t)J.n_bins * 16);
   unsigned long long* cursor = bincnt;
   unsigned long long* kmer_dev = bincnt + J.n_bins;
-  uint64_t* d_bases = ensure<uint64_t>(c, B_BASES, bases.size() * 8);
-  std::vector<uint64_t> h_cnt(2 * (size_t)J.n_bins);
+  uint64_t* d_bases = ensure<uint64_t>(c, B_BASES, n_bases_words * 8);
+  uint64_t* h_cnt = ensure_host<uint64_t>(c, H_CNT, (size_t)J.n_bins * 16);
   uint64_t* records = nullptr;
   for (int pass = 0; pass < 2; ++pass) {
     rec_base[0] = 0;
@@ -319,7 +459,7 @@ void run_count(kmc_ctx* c, const kmc_reads* R, const kmc_params* P, kmc_table* T
     check(c, launch_split_scatter(s, J.seq, J.off, J.n_reads, J.n_bases, C, J.kw, d_map, cursor,
                                   kmer_dev, d_bases, records), "split_scatter");
     kend(c, KMC_K_SPLIT, s);
-    check(c, hipMemcpyAsync(h_cnt.data(), bincnt, (size_t)J.n_bins * 16, hipMemcpyDeviceToHost, s), "D2H");
+    check(c, hipMemcpyAsync(h_cnt, bincnt, (size_t)J.n_bins * 16, hipMemcpyDeviceToHost, s), "D2H");
     check(c, hipStreamSynchronize(s), "sync");
     bool over = false;
     for (uint32_t b = 0; b < J.n_bins; ++b) {
@@ -331,7 +471,7 @@ void run_count(kmc_ctx* c, const kmc_reads* R, const kmc_params* P, kmc_table* T
     if (!over) break;
   }
   std::vector<uint64_t> rec_cnt(cap);
-  const uint64_t* kmer_cnt = h_cnt.data() + J.n_bins;
+  const uint64_t* kmer_cnt = h_cnt + J.n_bins;
   uint64_t max_bin = 0, n_rec = 0;
   key_base[0] = 0;
   for (uint32_t b = 0; b < J.n_bins; ++b) {
@@ -375,32 +515,33 @@ void run_count(kmc_ctx* c, const kmc_reads* R, const kmc_params* P, kmc_table* T
     throw Fail{KMC_ERR_TOO_LARGE};
   }
   st.n_tiles = n_tiles;
-  // tasks: fine-histogram tasks of up to 8 * 2^fb records, expansion tasks of 256
+  // tasks: fine-histogram tasks of up to hrec records, expansion tasks of one
+  // record per lane; only per-bin task offsets go to the device, which lists
+  // every task's bin itself
   const uint64_t hrec = std::min<uint64_t>(65536, std::max<uint64_t>(1024, 8ull << fb));
-  std::vector<ExpandTask> htasks, etasks;
+  htask_pre[0] = etask_pre[0] = 0;
   for (uint32_t b = 0; b < J.n_bins; ++b) {
-    const uint64_t r_end = rec_base[b] + rec_cnt[b];
-    for (uint64_t r = rec_base[b]; r < r_end; r += hrec)
-      htasks.push_back({r, (uint32_t)std::min<uint64_t>(hrec, r_end - r), b});
-    for (uint64_t r = rec_base[b]; r < r_end; r += kExpandThreads)
-      etasks.push_back({r, (uint32_t)std::min<uint64_t>(kExpandThreads, r_end - r), b});
+    rec_end[b] = rec_base[b] + rec_cnt[b];
+    htask_pre[b + 1] = htask_pre[b] + (rec_cnt[b] + hrec - 1) / hrec;
+    etask_pre[b + 1] = etask_pre[b] + (rec_cnt[b] + kExpandThreads - 1) / kExpandThreads;
   }
-  ExpandTask* d_ht = ensure<ExpandTask>(c, B_HTASK, htasks.size() * sizeof(ExpandTask));
-  ExpandTask* d_et = ensure<ExpandTask>(c, B_ETASK, etasks.size() * sizeof(ExpandTask));
-  if (!htasks.empty())
-    check(c, hipMemcpyAsync(d_ht, htasks.data(), htasks.size() * sizeof(ExpandTask),
-                            hipMemcpyHostToDevice, s), "H2D");
-  if (!etasks.empty())
-    check(c, hipMemcpyAsync(d_et, etasks.data(), etasks.size() * sizeof(ExpandTask),
-                            hipMemcpyHostToDevice, s), "H2D");
-  check(c, hipMemcpyAsync(d_bases, bases.data(), bases.size() * 8, hipMemcpyHostToDevice, s), "H2D");
-  const uint64_t* d_key_base = d_bases + J.n_bins + 1;
-  const uint64_t* d_tile_base = d_bases + 2 * ((size_t)J.n_bins + 1);
+  rec_end[J.n_bins] = rec_base[J.n_bins];
+  const uint64_t n_htasks = htask_pre[J.n_bins], n_etasks = etask_pre[J.n_bins];
+  check(c, hipMemcpyAsync(d_bases, bases, n_bases_words * 8, hipMemcpyHostToDevice, s), "H2D");
+  const uint64_t* d_key_base = d_bases + nb1;
+  const uint64_t* d_tile_base = d_bases + 2 * nb1;
+  uint16_t* d_hbin = ensure<uint16_t>(c, B_HTASK, std::max<uint64_t>(1, n_htasks) * 2);
+  uint16_t* d_ebin = ensure<uint16_t>(c, B_ETASK, std::max<uint64_t>(1, n_etasks) * 2);
+  check(c, launch_task_bins(s, J.n_bins, d_bases + 4 * nb1, d_hbin, d_bases + 5 * nb1, d_ebin),
+        "task_bins");
+  const TaskMap hmap{d_hbin, d_bases + 4 * nb1, d_bases, d_bases + 3 * nb1, (uint32_t)hrec};
+  const TaskMap emap{d_ebin, d_bases + 5 * nb1, d_bases, d_bases + 3 * nb1,
+                     (uint32_t)kExpandThreads};
   const size_t nfine = (size_t)J.n_bins << fb;
   uint32_t* fine = ensure<uint32_t>(c, B_FINE, nfine * 4);
   check(c, hipMemsetAsync(fine, 0, nfine * 4, s), "memset");
   kbeg(c, KMC_K_FINE_HIST, s);
-  check(c, launch_fine_hist(s, kc, d_ht, (uint32_t)htasks.size(), records, fine), "fine_hist");
+  check(c, launch_fine_hist(s, kc, hmap, (uint32_t)n_htasks, records, fine), "fine_hist");
   kend(c, KMC_K_FINE_HIST, s);
   uint16_t* tof = ensure<uint16_t>(c, B_TOF, nfine * 2);
   Tile* tiles = ensure<Tile>(c, B_TILES, n_tiles * sizeof(Tile));
@@ -412,7 +553,7 @@ void run_count(kmc_ctx* c, const kmc_reads* R, const kmc_params* P, kmc_table* T
   uint64_t* keys = ensure<uint64_t>(c, B_KEYS, n_kmers * J.kw * 8);
   uint32_t* counts = ensure<uint32_t>(c, B_COUNTS, n_kmers * 4);
   kbeg(c, KMC_K_EXPAND, s);
-  check(c, launch_expand_scatter(s, kc, d_et, (uint32_t)etasks.size(), records, tof, d_tile_base,
+  check(c, launch_expand_scatter(s, kc, emap, (uint32_t)n_etasks, records, tof, d_tile_base,
                                  (uint32_t)max_tiles, tcur, keys), "expand");
   kend(c, KMC_K_EXPAND, s);
   check(c, hipEventRecord(c->ev[3], s), "event");
@@ -426,14 +567,13 @@ void run_count(kmc_ctx* c, const kmc_reads* R, const kmc_params* P, kmc_table* T
   check(c, launch_tile_sort(s, kc, tiles, n_tiles, keys, counts, tile_out, big, big_off,
                             &misc->n_big, &misc->big_total, tile_dist), "tile_sort");
   kend(c, KMC_K_TILE_SORT, s);
-  check(c, hipMemcpyAsync(&h_misc, misc, sizeof(Misc), hipMemcpyDeviceToHost, s), "D2H");
-  check(c, hipStreamSynchronize(s), "sync");
-  st.n_big_tiles = h_misc.n_big;
+  // big tiles: their number stays on the device (no round trip); scratch for
+  // their partition passes is sized for every key
   kbeg(c, KMC_K_BIG_TILES, s);
-  if (h_misc.n_big) {
-    uint64_t* tmp = ensure<uint64_t>(c, B_TMP, (size_t)h_misc.big_total * J.kw * 8);
-    check(c, launch_big_tiles(s, kc, tiles, big, big_off, h_misc.n_big, keys, tmp, counts,
-                              tile_out, tile_dist), "big_tiles");
+  {
+    uint64_t* tmp = ensure<uint64_t>(c, B_TMP, std::max<uint64_t>(1, n_kmers) * J.kw * 8);
+    check(c, launch_big_tiles(s, kc, tiles, big, big_off, &misc->n_big, &misc->big_next, n_tiles,
+                              keys, tmp, counts, tile_out, tile_dist), "big_tiles");
   }
   kend(c, KMC_K_BIG_TILES, s);
   check(c, hipEventRecord(c->ev[4], s), "event");
@@ -446,14 +586,17 @@ void run_count(kmc_ctx* c, const kmc_reads* R, const kmc_params* P, kmc_table* T
   uint64_t* bin_off = ensure<uint64_t>(c, B_BINOFF, ((size_t)J.n_bins + 1) * 8);
   check(c, launch_bin_offsets(s, tile_off, d_tile_base, J.n_bins, bin_off), "bin_offsets");
   kend(c, KMC_K_ASSEMBLE, s);
-  check(c, hipMemcpyAsync(T->bin_offsets, bin_off, ((size_t)J.n_bins + 1) * 8,
-                          hipMemcpyDeviceToHost, s), "D2H");
+  uint64_t* h_binoff = ensure_host<uint64_t>(c, H_BINOFF, (nb1 + 1) * 8);
+  check(c, hipMemcpyAsync(h_binoff, bin_off, nb1 * 8, hipMemcpyDeviceToHost, s), "D2H");
   // distinct keys: sum of the per-tile counts (a scan; its last entry is the total)
   uint64_t* dist_scan = ensure<uint64_t>(c, B_DBG1, (n_tiles + 1) * 8);
   check(c, launch_scan_u32(s, tile_dist, n_tiles, dist_scan, scan_tmp), "scan");
-  uint64_t h_distinct = 0;
-  check(c, hipMemcpyAsync(&h_distinct, dist_scan + n_tiles, 8, hipMemcpyDeviceToHost, s), "D2H");
+  check(c, hipMemcpyAsync(h_binoff + nb1, dist_scan + n_tiles, 8, hipMemcpyDeviceToHost, s), "D2H");
+  check(c, hipMemcpyAsync(h_misc_p, misc, sizeof(Misc), hipMemcpyDeviceToHost, s), "D2H");
   check(c, hipStreamSynchronize(s), "sync");
+  std::memcpy(T->bin_offsets, h_binoff, nb1 * 8);
+  const uint64_t h_distinct = h_binoff[nb1];
+  st.n_big_tiles = h_misc_p->n_big;
   const uint64_t n_out = T->bin_offsets[J.n_bins];
   st.n_out = n_out;
   st.n_distinct = h_distinct;
@@ -468,8 +611,16 @@ void run_count(kmc_ctx* c, const kmc_reads* R, const kmc_params* P, kmc_table* T
     out_k = T->keys;
     out_c = T->counts;
   } else if (T->on_device) {
-    check(c, hipMalloc(&T->keys, std::max<uint64_t>(1, n_out * J.kw) * 8), "hipMalloc table");
-    check(c, hipMalloc(&T->counts, std::max<uint64_t>(1, n_out) * 4), "hipMalloc table");
+    // keys and counts in one pooled block
+    const size_t kb = (std::max<uint64_t>(1, n_out * J.kw) * 8 + 255) & ~(size_t)255;
+    void* blk = pool_take(c->device, kb + std::max<uint64_t>(1, n_out) * 4);
+    if (!blk) {
+      c->err = "device allocation of the table failed";
+      throw Fail{KMC_ERR_OUT_OF_MEMORY};
+    }
+    T->keys = static_cast<uint64_t*>(blk);
+    T->counts = reinterpret_cast<uint32_t*>(static_cast<uint8_t*>(blk) + kb);
+    T->reserved = 2;
     out_k = T->keys;
     out_c = T->counts;
   } else {
@@ -535,7 +686,7 @@ WsLayout plan_workspace(const kmc_reads* R, const kmc_params* P) {
   sz[B_TOF] = (NB << fb) * 2;
   sz[B_TILES] = tmax * sizeof(Tile);
   sz[B_TCUR] = tmax * 8;
-  sz[B_BASES] = 3 * (NB + 1) * 8;
+  sz[B_BASES] = 6 * (NB + 1) * 8;
   sz[B_HTASK] = tasks * sizeof(ExpandTask);
   sz[B_ETASK] = tasks * sizeof(ExpandTask);
   sz[B_KEYS] = kmax * kw * 8;
@@ -634,6 +785,8 @@ void kmc_ctx_destroy(kmc_ctx* c) {
   if (c->stream) (void)hipStreamSynchronize(c->stream);
   for (auto& b : c->buf)
     if (b.p) (void)hipFree(b.p);
+  for (auto& b : c->hbuf)
+    if (b.p) (void)hipHostFree(b.p);
   for (auto& e : c->ev)
     if (e) (void)hipEventDestroy(e);
   if (c->stream) (void)hipStreamDestroy(c->stream);
@@ -715,6 +868,8 @@ void kmc_table_free(kmc_table* t) {
   if (!t) return;
   if (t->on_device && t->reserved == 1) {
     // keys/counts belong to a caller's workspace
+  } else if (t->on_device && t->reserved == 2) {
+    if (t->keys && !pool_give(t->keys)) (void)hipFree(t->keys);
   } else if (t->on_device) {
     if (t->keys) (void)hipFree(t->keys);
     if (t->counts) (void)hipFree(t->counts);

@@ -68,16 +68,23 @@ __device__ __forceinline__ uint32_t top_bits(u128 key, uint32_t k, uint32_t bits
 // --------------------------------------------------------------- fine hist
 // One workgroup per task (a run of records of one bin); the task's keys are
 // counted per fine range in LDS, then added to the bin's global histogram.
+__global__ void __launch_bounds__(256)
+k_task_bins(const uint64_t* __restrict__ pre_a, uint16_t* bin_a, const uint64_t* __restrict__ pre_b,
+            uint16_t* bin_b) {
+  const uint32_t b = blockIdx.x;
+  for (uint64_t t = pre_a[b] + threadIdx.x; t < pre_a[b + 1]; t += blockDim.x) bin_a[t] = (uint16_t)b;
+  for (uint64_t t = pre_b[b] + threadIdx.x; t < pre_b[b + 1]; t += blockDim.x) bin_b[t] = (uint16_t)b;
+}
+
 template <int KW>
 __global__ void __launch_bounds__(kExpandThreads)
-k_fine_hist(KeyCfg kc, const ExpandTask* __restrict__ tasks, const uint64_t* __restrict__ records,
-            uint32_t* fine_hist) {
+k_fine_hist(KeyCfg kc, TaskMap tm, const uint64_t* __restrict__ records, uint32_t* fine_hist) {
   typedef typename KeyOf<KW>::T K;
   extern __shared__ uint32_t fh[];
   const uint32_t nf = 1u << kc.fine_bits;
   for (uint32_t i = threadIdx.x; i < nf; i += blockDim.x) fh[i] = 0;
   __syncthreads();
-  const ExpandTask tk = tasks[blockIdx.x];
+  const ExpandTask tk = tm.get(blockIdx.x);
   const K kmask = key_mask<K>(kc.k);
   for (uint32_t r0 = 0; r0 < tk.n_rec; r0 += blockDim.x) {
     const uint32_t r = r0 + threadIdx.x;
@@ -145,111 +152,94 @@ k_plan_tiles(KeyCfg kc, const uint32_t* __restrict__ fine_hist, const uint64_t* 
 }
 
 // ---------------------------------------------------------- expand scatter
-// One workgroup per task.  Lane i walks record i's k-mers one per round; keys
-// are staged in LDS, and when the stage could overflow in the next round it is
-// flushed: keys grouped by tile, one atomic reservation per (flush, tile),
-// coalesced writes.
+// One workgroup per task (up to blockDim records of one bin, one per lane).
+// Two walks over each record's k-mers: the first counts keys per tile in LDS;
+// after one scan and one global reservation per (task, tile) the second walk
+// writes every key straight to its slot, tile slot = reserved start + rank
+// from an LDS counter.  A task's keys of one tile land in one contiguous
+// range.  No staging and no barrier inside the walks.
 template <int KW>
 __global__ void __launch_bounds__(kExpandThreads)
-k_expand_scatter(KeyCfg kc, const ExpandTask* __restrict__ tasks,
+k_expand_scatter(KeyCfg kc, TaskMap tm,
                  const uint64_t* __restrict__ records, const uint16_t* __restrict__ tile_of_fine,
-                 const uint64_t* __restrict__ tile_base, uint32_t mt, uint32_t scap,
+                 const uint64_t* __restrict__ tile_base, uint32_t mt,
                  unsigned long long* tile_cursor, uint64_t* keys) {
   typedef typename KeyOf<KW>::T K;
   extern __shared__ __attribute__((aligned(16))) uint64_t lds64[];
   const uint32_t nf = 1u << kc.fine_bits;
-  // layout: stage K[scap] | delta u64[mt] | cnt u32[mt] | base u32[mt] | tof u16[nf] |
-  //         stile u16[scap] | srank u16[scap] | inv u16[scap] | num, scan tmp
-  K* stage = reinterpret_cast<K*>(lds64);
-  uint64_t* delta = reinterpret_cast<uint64_t*>(stage + scap);
+  // layout: delta u64[mt] | cnt u32[mt] | tof u16[nf] | scan tmp
+  uint64_t* delta = lds64;
   uint32_t* cnt = reinterpret_cast<uint32_t*>(delta + mt);
-  uint32_t* base = cnt + mt;
-  uint16_t* tof = reinterpret_cast<uint16_t*>(base + mt);
-  uint16_t* stile = tof + nf;
-  uint16_t* srank = stile + scap;
-  uint16_t* inv = srank + scap;
-  uint32_t* misc = reinterpret_cast<uint32_t*>(inv + scap + (scap & 1));
-  uint32_t* num = misc;
-  uint32_t* tmp = misc + 1;
+  uint16_t* tof = reinterpret_cast<uint16_t*>(cnt + mt);
+  uint32_t* tmp = reinterpret_cast<uint32_t*>(tof + nf + (nf & 1));
 
-  const ExpandTask tk = tasks[blockIdx.x];
+  const ExpandTask tk = tm.get(blockIdx.x);
   const uint16_t* gt = tile_of_fine + ((uint64_t)tk.bin << kc.fine_bits);
   for (uint32_t i = threadIdx.x; i < nf; i += blockDim.x) tof[i] = gt[i];
   for (uint32_t i = threadIdx.x; i < mt; i += blockDim.x) cnt[i] = 0;
-  if (threadIdx.x == 0) *num = 0;
   const uint64_t tb = tile_base[tk.bin];
   const K kmask = key_mask<K>(kc.k);
-
-  Rec<KW> rec;
   const bool active = threadIdx.x < tk.n_rec;
-  rec.n = 0;
-  if (active) rec.load(records + (tk.rec_begin + threadIdx.x) * (2 * KW), kc.k);
+  const uint64_t* rp = records + (tk.rec_begin + threadIdx.x) * (2 * KW);
   __syncthreads();
 
-  for (uint32_t round = 0;; ++round) {
-    // flush when the next round might not fit, or when all records are done
-    const uint32_t staged = *num;
-    // any lane still has k-mers?
-    const bool more = __syncthreads_or(active && round < rec.n);
-    if (staged + blockDim.x > scap || !more) {
-      const uint32_t nst = staged;
-      for (uint32_t i = threadIdx.x; i < mt; i += blockDim.x) base[i] = cnt[i];
-      __syncthreads();
-      block_exclusive_scan(base, mt, tmp);
-      for (uint32_t i = threadIdx.x; i < mt; i += blockDim.x) {
-        if (cnt[i]) {
-          const uint64_t g = atomicAdd(&tile_cursor[tb + i], (unsigned long long)cnt[i]);
-          delta[i] = g - base[i];
-        }
-      }
-      for (uint32_t i = threadIdx.x; i < nst; i += blockDim.x)
-        inv[base[stile[i]] + srank[i]] = (uint16_t)i;
-      __syncthreads();
-      for (uint32_t q = threadIdx.x; q < nst; q += blockDim.x) {
-        const uint32_t i = inv[q];
-        const uint64_t g = delta[stile[i]] + q;
-        if (KW == 1) {
-          keys[g] = (uint64_t)stage[i];
-        } else {
-          keys[2 * g] = (uint64_t)((u128)stage[i] >> 64);
-          keys[2 * g + 1] = (uint64_t)stage[i];
-        }
-      }
-      __syncthreads();
-      for (uint32_t i = threadIdx.x; i < mt; i += blockDim.x) cnt[i] = 0;
-      if (threadIdx.x == 0) *num = 0;
-      __syncthreads();
+  if (active) {
+    Rec<KW> rec;
+    rec.load(rp, kc.k);
+    for (uint32_t i = 0;; ++i) {
+      atomicAdd(&cnt[tof[top_bits(rec.key(), kc.k, kc.fine_bits)]], 1u);
+      if (i + 1 >= rec.n) break;
+      rec.step(kc.k, kmask);
     }
-    if (!more) break;
-    if (active && round < rec.n) {
-      if (round) rec.step(kc.k, kmask);
+  }
+  __syncthreads();
+  // reserve each tile's range; cnt then becomes the running slot
+  for (uint32_t i = threadIdx.x; i < mt; i += blockDim.x) {
+    const uint32_t c = cnt[i];
+    if (c) delta[i] = atomicAdd(&tile_cursor[tb + i], (unsigned long long)c);
+    cnt[i] = 0;
+  }
+  __syncthreads();
+  if (active) {
+    Rec<KW> rec;
+    rec.load(rp, kc.k);
+    for (uint32_t i = 0;; ++i) {
       const K key = rec.key();
       const uint32_t t = tof[top_bits(key, kc.k, kc.fine_bits)];
-      const uint32_t idx = atomicAdd(num, 1u);
-      srank[idx] = (uint16_t)atomicAdd(&cnt[t], 1u);
-      stile[idx] = (uint16_t)t;
-      stage[idx] = key;
+      const uint64_t g = delta[t] + atomicAdd(&cnt[t], 1u);
+      if (KW == 1) {
+        keys[g] = (uint64_t)key;
+      } else {
+        keys[2 * g] = (uint64_t)((u128)key >> 64);
+        keys[2 * g + 1] = (uint64_t)key;
+      }
+      if (i + 1 >= rec.n) break;
+      rec.step(kc.k, kmask);
     }
-    __syncthreads();
   }
 }
 
 }  // namespace
 
-static size_t expand_lds(uint32_t key_words, uint32_t mt, uint32_t nf, uint32_t scap) {
-  return (size_t)scap * 8 * key_words + (size_t)mt * 16 + (size_t)nf * 2 + (size_t)scap * 6 + 8 +
-         4 + 4 * (kExpandThreads / 64) + 16;
+static size_t expand_lds(uint32_t mt, uint32_t nf) {
+  return (size_t)mt * 12 + (size_t)nf * 2 + 4 + 16;
 }
 
-hipError_t launch_fine_hist(hipStream_t s, const KeyCfg& kc, const ExpandTask* tasks,
+hipError_t launch_task_bins(hipStream_t s, uint32_t n_bins, const uint64_t* pre_a,
+                            uint16_t* bin_a, const uint64_t* pre_b, uint16_t* bin_b) {
+  hipLaunchKernelGGL(k_task_bins, dim3(n_bins), dim3(256), 0, s, pre_a, bin_a, pre_b, bin_b);
+  return hipGetLastError();
+}
+
+hipError_t launch_fine_hist(hipStream_t s, const KeyCfg& kc, const TaskMap& tm,
                             uint32_t n_tasks, const uint64_t* records, uint32_t* fine_hist) {
   if (n_tasks == 0) return hipSuccess;
   const size_t sh = ((size_t)1 << kc.fine_bits) * 4;
   if (kc.key_words == 1)
-    hipLaunchKernelGGL(k_fine_hist<1>, dim3(n_tasks), dim3(kExpandThreads), sh, s, kc, tasks,
+    hipLaunchKernelGGL(k_fine_hist<1>, dim3(n_tasks), dim3(kExpandThreads), sh, s, kc, tm,
                        records, fine_hist);
   else
-    hipLaunchKernelGGL(k_fine_hist<2>, dim3(n_tasks), dim3(kExpandThreads), sh, s, kc, tasks,
+    hipLaunchKernelGGL(k_fine_hist<2>, dim3(n_tasks), dim3(kExpandThreads), sh, s, kc, tm,
                        records, fine_hist);
   return hipGetLastError();
 }
@@ -265,33 +255,27 @@ hipError_t launch_plan_tiles(hipStream_t s, const KeyCfg& kc, const uint32_t* fi
   return hipGetLastError();
 }
 
-hipError_t launch_expand_scatter(hipStream_t s, const KeyCfg& kc, const ExpandTask* tasks,
+hipError_t launch_expand_scatter(hipStream_t s, const KeyCfg& kc, const TaskMap& tm,
                                  uint32_t n_tasks, const uint64_t* records,
                                  const uint16_t* tile_of_fine, const uint64_t* tile_base,
                                  uint32_t max_tiles_per_bin,
                                  unsigned long long* tile_cursor, uint64_t* keys) {
   if (n_tasks == 0) return hipSuccess;
   const uint32_t nf = 1u << kc.fine_bits;
-  const uint32_t scap = kc.key_words == 1 ? kExpandStage1 : kExpandStage2;
   const uint32_t mt = max_tiles_per_bin < 1 ? 1 : max_tiles_per_bin;
-  const size_t sh = expand_lds(kc.key_words, mt, nf, scap);
+  const size_t sh = expand_lds(mt, nf);
   if (kc.key_words == 1) {
     (void)hipFuncSetAttribute((const void*)k_expand_scatter<1>,
                         hipFuncAttributeMaxDynamicSharedMemorySize, (int)sh);
     hipLaunchKernelGGL(k_expand_scatter<1>, dim3(n_tasks), dim3(kExpandThreads), sh, s, kc,
-                       tasks, records, tile_of_fine, tile_base, mt, scap, tile_cursor, keys);
+                       tm, records, tile_of_fine, tile_base, mt, tile_cursor, keys);
   } else {
     (void)hipFuncSetAttribute((const void*)k_expand_scatter<2>,
                         hipFuncAttributeMaxDynamicSharedMemorySize, (int)sh);
     hipLaunchKernelGGL(k_expand_scatter<2>, dim3(n_tasks), dim3(kExpandThreads), sh, s, kc,
-                       tasks, records, tile_of_fine, tile_base, mt, scap, tile_cursor, keys);
+                       tm, records, tile_of_fine, tile_base, mt, tile_cursor, keys);
   }
   return hipGetLastError();
-}
-
-size_t expand_scatter_lds_bytes(uint32_t key_words, uint32_t mt, uint32_t fine_bits) {
-  return expand_lds(key_words, mt, 1u << fine_bits,
-                    key_words == 1 ? kExpandStage1 : kExpandStage2);
 }
 
 }  // namespace kmc

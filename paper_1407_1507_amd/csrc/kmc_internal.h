@@ -11,8 +11,6 @@ namespace kmc {
 
 // Sizes of the work units.
 constexpr int kExpandThreads = 256;      // records per expansion task (one per thread)
-constexpr int kExpandStage1 = 2048;      // keys staged per expansion flush (1-word keys)
-constexpr int kExpandStage2 = 1024;      // same, 2-word keys
 constexpr int kSortThreads = 256;        // threads of a tile-sort workgroup
 constexpr int kTileCap1 = 4096;          // keys of one LDS tile (1-word keys)
 constexpr int kTileCap2 = 2048;          // same, 2-word keys
@@ -26,7 +24,7 @@ struct ScanCfg {
   uint32_t pmask;        // 2p low bits
   uint32_t sent;         // 4^p: signature of a k-mer with no allowed p-mer
   uint32_t n_bins;
-  uint32_t aligned4;     // seq is 4-byte aligned: fetch whole words
+  uint32_t seq_align;    // alignment of seq (16, 4 or 1): widest loads it allows
 };
 
 // One expansion task: records [rec_begin, rec_end) of bin `bin`.
@@ -34,6 +32,25 @@ struct ExpandTask {
   uint64_t rec_begin;
   uint32_t n_rec;
   uint32_t bin;
+};
+
+// Tasks of a per-record kernel: bin b's records [rec_base[b], rec_end[b]) in
+// runs of `per`, tasks pre[b] .. pre[b+1] - 1; bin[t] is the bin of task t
+// (filled on the device by launch_task_bins).
+struct TaskMap {
+  const uint16_t* bin;
+  const uint64_t* pre;
+  const uint64_t* rec_base;
+  const uint64_t* rec_end;
+  uint32_t per;
+  __device__ __forceinline__ ExpandTask get(uint32_t t) const {
+    ExpandTask k;
+    k.bin = bin[t];
+    k.rec_begin = rec_base[k.bin] + (uint64_t)(t - pre[k.bin]) * per;
+    const uint64_t left = rec_end[k.bin] - k.rec_begin;
+    k.n_rec = left < per ? (uint32_t)left : per;
+    return k;
+  }
 };
 
 // One sort tile: keys [begin, begin + size) of the key buffer.
@@ -79,8 +96,12 @@ struct KeyCfg {
   uint32_t cutoff_min, cutoff_max;
 };
 
+// bin[t] for every task t of two task maps (pre arrays of n_bins + 1).
+hipError_t launch_task_bins(hipStream_t s, uint32_t n_bins, const uint64_t* pre_a,
+                            uint16_t* bin_a, const uint64_t* pre_b, uint16_t* bin_b);
+
 // Fine-range histogram of every bin: fine_hist[bin << fine_bits | range].
-hipError_t launch_fine_hist(hipStream_t s, const KeyCfg& kc, const ExpandTask* tasks,
+hipError_t launch_fine_hist(hipStream_t s, const KeyCfg& kc, const TaskMap& tm,
                             uint32_t n_tasks, const uint64_t* records, uint32_t* fine_hist);
 
 // Per bin: fine ranges -> tiles.  Writes tile_of_fine (local tile id per
@@ -91,7 +112,7 @@ hipError_t launch_plan_tiles(hipStream_t s, const KeyCfg& kc, const uint32_t* fi
                              unsigned long long* tile_cursor);
 
 // Expand every record into canonical keys and scatter them into their tiles.
-hipError_t launch_expand_scatter(hipStream_t s, const KeyCfg& kc, const ExpandTask* tasks,
+hipError_t launch_expand_scatter(hipStream_t s, const KeyCfg& kc, const TaskMap& tm,
                                  uint32_t n_tasks, const uint64_t* records,
                                  const uint16_t* tile_of_fine, const uint64_t* tile_base,
                                  uint32_t max_tiles_per_bin,
@@ -109,9 +130,13 @@ hipError_t launch_tile_sort(hipStream_t s, const KeyCfg& kc, const Tile* tiles,
                             uint32_t* tile_distinct);
 
 // Sort + count the big tiles: MSD partition through HBM, each tile
-// ping-ponging between its keys and its own slice tmp[big_off[i] ...].
+// ping-ponging between its keys and its own slice tmp[big_off[i] ...].  The
+// number of big tiles is read on the device (*n_big, final once the tile
+// kernel has run); workgroups take tiles from the counter *next (zero at
+// launch).  max_big bounds *n_big (the grid never exceeds it).
 hipError_t launch_big_tiles(hipStream_t s, const KeyCfg& kc, const Tile* tiles,
-                            const uint32_t* big_list, const uint64_t* big_off, uint32_t n_big,
+                            const uint32_t* big_list, const uint64_t* big_off,
+                            const uint32_t* n_big, uint32_t* next, uint64_t max_big,
                             uint64_t* keys, uint64_t* tmp, uint32_t* out_counts,
                             uint32_t* tile_out, uint32_t* tile_distinct);
 
@@ -129,7 +154,6 @@ hipError_t launch_gather(hipStream_t s, const KeyCfg& kc, const Tile* tiles, uin
 hipError_t launch_bin_offsets(hipStream_t s, const uint64_t* tile_off, const uint64_t* tile_base,
                               uint32_t n_bins, uint64_t* out);
 
-size_t expand_scatter_lds_bytes(uint32_t key_words, uint32_t mt, uint32_t fine_bits);
 
 // Validate a device offsets array: err[0] |= 1 if offsets[0] != 0, not
 // non-decreasing, or offsets[n_reads] != n_bases.

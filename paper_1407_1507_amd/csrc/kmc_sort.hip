@@ -18,6 +18,7 @@
 // than LDS take the same MSD passes through HBM (8-bit digits, recursive)
 // until their pieces fit.
 #include <algorithm>
+#include <atomic>
 
 #include "kmc_device.h"
 #include "kmc_internal.h"
@@ -270,25 +271,38 @@ __device__ __forceinline__ uint32_t count_tile(typename KeyOf<KW>::T (&key)[Sort
                                uint64_t* out_keys, uint32_t* out_counts, uint32_t ci,
                                uint32_t cx, SortShared<KW>& S, uint32_t* distinct);
 
-// Count a tile of 64-bit keys (n <= half the table) with an LDS hash table:
+// Count a tile of 64-bit keys (n <= 3/4 of the table) with an LDS hash table:
 // open addressing with linear probing over the A (keys) / H (counters) arrays;
 // a key's first insertion claims an empty slot by compare-and-swap and every
 // occurrence adds one to that slot's counter, so each counter ends equal to
-// the run length a sort of the tile would give that key.  Kept keys are then
-// put in key order by order_kept.  The all-ones key marks an empty slot: it is
-// never canonical (its reverse complement, all A, is smaller).
+// the run length a sort of the tile would give that key.  The all-ones key
+// marks an empty slot: it is never canonical (its reverse complement, all A,
+// is smaller).
+//
+// kClean: the table is empty on entry, and is left empty on return (slots
+// are cleared as they are read back, and whatever the ordering step below
+// writes is cleared after it), so a persistent workgroup initialises it once.
+// Kept keys (at most kRankMax of them) are put in key order by a rank sort:
+// each one counts the kept keys smaller than itself; more kept keys take the
+// digit-counting order of order_kept.
+constexpr uint32_t kRankMax = 256;
+
+template <bool kClean>
 __device__ __forceinline__ uint32_t count_tile_hash(uint64_t (&key)[SortCfg<1>::ITEMS], uint32_t n,
-                                    uint64_t* out_keys, uint32_t* out_counts, uint32_t ci,
-                                    uint32_t cx, SortShared<1>& S, uint32_t* distinct) {
+                                                    uint64_t* out_keys, uint32_t* out_counts,
+                                                    uint32_t ci, uint32_t cx, SortShared<1>& S,
+                                                    uint32_t* distinct) {
   constexpr uint32_t ITEMS = SortCfg<1>::ITEMS, T = SortCfg<1>::CAP, TB = 12;
   static_assert((1u << TB) == T, "table size");
   constexpr uint64_t EMPTY = ~0ull;
   const uint32_t tid = threadIdx.x, nt = blockDim.x;
-  for (uint32_t s = tid; s < T; s += nt) {
-    S.A[s] = EMPTY;
-    S.H[s] = 0;
+  if (!kClean) {
+    for (uint32_t s = tid; s < T; s += nt) {
+      S.A[s] = EMPTY;
+      S.H[s] = 0;
+    }
+    __syncthreads();
   }
-  __syncthreads();
 #pragma unroll
   for (uint32_t m = 0; m < ITEMS; ++m) {
     if (m * nt + tid < n) {
@@ -306,6 +320,7 @@ __device__ __forceinline__ uint32_t count_tile_hash(uint64_t (&key)[SortCfg<1>::
     }
   }
   __syncthreads();
+  // read back (and clear) the occupied slots
   uint32_t cnt[ITEMS];
   uint32_t nh = 0, nk = 0;
   uint64_t a = ~0ull, o = 0;
@@ -317,6 +332,8 @@ __device__ __forceinline__ uint32_t count_tile_hash(uint64_t (&key)[SortCfg<1>::
     if (x != EMPTY) {
       ++nh;
       const uint32_t c = S.H[s];
+      S.A[s] = EMPTY;
+      S.H[s] = 0;
       if (c >= ci && c <= cx) {
         key[i] = x;
         cnt[i] = c;
@@ -329,7 +346,7 @@ __device__ __forceinline__ uint32_t count_tile_hash(uint64_t (&key)[SortCfg<1>::
   uint32_t H_total, kept;
   (void)block_scan_one(nh, S.tmp, H_total);
   *distinct = H_total;
-  const uint32_t kbase = block_scan_one(nk, S.tmp, kept);  // barrier: table reads are done
+  const uint32_t kbase = block_scan_one(nk, S.tmp, kept);  // barrier: read-back is done
   if (kept == 0) return 0;
   block_and_or<uint64_t>(a, o, S.red);
   const uint64_t diff = a ^ o;
@@ -343,7 +360,43 @@ __device__ __forceinline__ uint32_t count_tile_hash(uint64_t (&key)[SortCfg<1>::
     __syncthreads();
     return 1;
   }
+  if (kept <= kRankMax) {
+    uint32_t at = kbase;
+#pragma unroll
+    for (uint32_t i = 0; i < ITEMS; ++i) {
+      if (cnt[i]) {
+        S.A[at] = key[i];
+        S.H[at] = cnt[i];
+        ++at;
+      }
+    }
+    __syncthreads();
+    if (tid < kept) {
+      const uint64_t x = S.A[tid];
+      const uint32_t c = S.H[tid];
+      uint32_t r = 0;
+      for (uint32_t j = 0; j < kept; ++j) r += S.A[j] < x;
+      out_keys[r] = x;
+      out_counts[r] = c;
+    }
+    __syncthreads();
+    if (tid < kept) {
+      S.A[tid] = EMPTY;
+      S.H[tid] = 0;
+    }
+    __syncthreads();
+    return kept;
+  }
   order_kept<1>(key, cnt, kbase, kept, diff, out_keys, out_counts, S);
+  if (kClean) {
+    // order_kept used A[0, kept) and H[0, max(kept, buckets)), buckets <= T
+    const uint32_t hb = high_bit(diff);
+    const uint32_t t2 = min(min(SortCfg<1>::DIG, bit_len(kept) + 1), hb + 1);
+    const uint32_t used = max(kept, 1u << t2);
+    for (uint32_t s = tid; s < kept; s += nt) S.A[s] = EMPTY;
+    for (uint32_t s = tid; s < used; s += nt) S.H[s] = 0;
+    __syncthreads();
+  }
   return kept;
 }
 
@@ -360,17 +413,18 @@ __device__ __forceinline__ uint32_t count_any<1>(uint64_t (&key)[SortCfg<1>::ITE
                                                  uint32_t ci, uint32_t cx, SortShared<1>& S,
                                                  uint32_t* distinct) {
   if (n <= SortCfg<1>::DIRECT)
-    return count_tile_hash(key, n, out_keys, out_counts, ci, cx, S, distinct);
+    return count_tile_hash<false>(key, n, out_keys, out_counts, ci, cx, S, distinct);
   return count_tile<1>(key, n, out_keys, out_counts, ci, cx, S, distinct);
 }
 
 // The tile kernel's counting: only the hash table for 64-bit keys (tiles up
-// to DIRECT keys), so the kernel carries none of the bucket path's registers.
+// to DIRECT keys), so the kernel carries none of the bucket path's registers;
+// the kernel keeps the table empty between tiles.
 __device__ __forceinline__ uint32_t count_direct(uint64_t (&key)[SortCfg<1>::ITEMS], uint32_t n,
                                                  uint64_t* out_keys, uint32_t* out_counts,
                                                  uint32_t ci, uint32_t cx, SortShared<1>& S,
                                                  uint32_t* distinct) {
-  return count_tile_hash(key, n, out_keys, out_counts, ci, cx, S, distinct);
+  return count_tile_hash<true>(key, n, out_keys, out_counts, ci, cx, S, distinct);
 }
 __device__ __forceinline__ uint32_t count_direct(u128 (&key)[SortCfg<2>::ITEMS], uint32_t n,
                                                  uint64_t* out_keys, uint32_t* out_counts,
@@ -579,8 +633,17 @@ k_tile_sort(KeyCfg kc, const Tile* __restrict__ tiles, uint64_t n_tiles, uint64_
   typedef typename KeyOf<KW>::T K;
   constexpr uint32_t ITEMS = SortCfg<KW>::ITEMS, CAP = SortCfg<KW>::CAP;
   __shared__ SortShared<KW> S;
+  if (KW == 1) {  // the hash table starts empty; count_direct leaves it empty
+    for (uint32_t i = threadIdx.x; i < CAP; i += blockDim.x) {
+      S.A[i] = ~K(0);
+      S.H[i] = 0;
+    }
+    __syncthreads();
+  }
+  Tile next = tiles[blockIdx.x];
   for (uint64_t t = blockIdx.x; t < n_tiles; t += gridDim.x) {
-    const Tile T = tiles[t];
+    const Tile T = next;
+    if (t + gridDim.x < n_tiles) next = tiles[t + gridDim.x];
     if (T.size == 0) {
       if (threadIdx.x == 0) tile_out[t] = tile_distinct[t] = 0;
     } else if (T.size > SortCfg<KW>::DIRECT) {
@@ -611,6 +674,24 @@ k_tile_sort(KeyCfg kc, const Tile* __restrict__ tiles, uint64_t n_tiles, uint64_
 // prefix into the other buffer (same offsets) and its children are visited in
 // key order, so the output stays in ascending order.  Output is written over
 // the tile's own keys at a cursor that never passes the piece being read.
+// f(x) for every key of src[0..n): each lane keeps U loads in flight (one
+// workgroup walks the whole piece, so latency, not bandwidth, bounds a pass).
+template <class K, int U, class F>
+__device__ __forceinline__ void for_each_key(const uint64_t* src, uint32_t n, F f) {
+  const uint32_t tid = threadIdx.x, nt = blockDim.x;
+  for (uint32_t base = 0; base < n; base += nt * U) {
+    K x[U];
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      const uint32_t i = base + u * nt + tid;
+      if (i < n) x[u] = load_key(src, i, (K*)nullptr);
+    }
+#pragma unroll
+    for (int u = 0; u < U; ++u)
+      if (base + u * nt + tid < n) f(x[u]);
+  }
+}
+
 struct Level {
   uint64_t base;
   uint32_t next, nchild, buf, pad;
@@ -618,20 +699,19 @@ struct Level {
 };
 template <int KW> struct MaxLevels { static constexpr int N = KW == 1 ? 10 : 18; };
 
+// One big tile, by the whole workgroup.
 template <int KW>
-__global__ void __launch_bounds__(kSortThreads)
-k_big_tiles(KeyCfg kc, const Tile* __restrict__ tiles, const uint32_t* __restrict__ big_list,
-            const uint64_t* __restrict__ big_off, uint64_t* keys, uint64_t* tmp,
-            uint32_t* counts, uint32_t* tile_out, uint32_t* tile_distinct) {
+__device__ void big_tile(const KeyCfg& kc, const Tile* __restrict__ tiles, uint32_t t,
+                         uint64_t tmp_off, uint64_t* keys, uint64_t* tmp, uint32_t* counts,
+                         uint32_t* tile_out, uint32_t* tile_distinct) {
   typedef typename KeyOf<KW>::T K;
   __shared__ SortShared<KW> S;
   __shared__ Level L[MaxLevels<KW>::N];
   __shared__ uint32_t cur[256];
   __shared__ unsigned long long outc, dist;
   const uint32_t tid = threadIdx.x, nt = blockDim.x;
-  const uint32_t t = big_list[blockIdx.x];
   const Tile T = tiles[t];
-  uint64_t* bufs[2] = {keys + T.begin * KW, tmp + big_off[blockIdx.x] * KW};
+  uint64_t* bufs[2] = {keys + T.begin * KW, tmp + tmp_off * KW};
   if (tid == 0) {
     L[0].base = 0;
     L[0].next = 0;
@@ -676,12 +756,12 @@ k_big_tiles(KeyCfg kc, const Tile* __restrict__ tiles, const uint32_t* __restric
       __syncthreads();
       continue;
     }
+    constexpr int U = 16 / KW;
     K a = ~K(0), o = 0;
-    for (uint32_t i = tid; i < n; i += nt) {
-      const K x = load_key(src, i, (K*)nullptr);
+    for_each_key<K, U>(src, n, [&](const K& x) {
       a &= x;
       o |= x;
-    }
+    });
     block_and_or<K>(a, o, S.red);
     const K diff = a ^ o;
     if (diff == 0) {
@@ -702,8 +782,9 @@ k_big_tiles(KeyCfg kc, const Tile* __restrict__ tiles, const uint32_t* __restric
     const uint32_t nb = 1u << bits, dmask = nb - 1;
     for (uint32_t i = tid; i < 256; i += nt) cur[i] = 0;
     __syncthreads();
-    for (uint32_t i = tid; i < n; i += nt)
-      atomicAdd(&cur[(uint32_t)(load_key(src, i, (K*)nullptr) >> shift) & dmask], 1u);
+    for_each_key<K, U>(src, n, [&](const K& x) {
+      atomicAdd(&cur[(uint32_t)(x >> shift) & dmask], 1u);
+    });
     __syncthreads();
     const uint32_t total = block_exclusive_scan(cur, nb, S.tmp);
     const int nd = depth + 1;
@@ -717,10 +798,9 @@ k_big_tiles(KeyCfg kc, const Tile* __restrict__ tiles, const uint32_t* __restric
     }
     __syncthreads();
     uint64_t* dst = bufs[1 - buf] + off * KW;
-    for (uint32_t i = tid; i < n; i += nt) {
-      const K x = load_key(src, i, (K*)nullptr);
+    for_each_key<K, U>(src, n, [&](const K& x) {
       store_key(dst, atomicAdd(&cur[(uint32_t)(x >> shift) & dmask], 1u), x);
-    }
+    });
     __threadfence();
     __syncthreads();
     depth = nd;
@@ -728,6 +808,27 @@ k_big_tiles(KeyCfg kc, const Tile* __restrict__ tiles, const uint32_t* __restric
   if (tid == 0) {
     tile_out[t] = (uint32_t)outc;
     tile_distinct[t] = (uint32_t)dist;
+  }
+  __syncthreads();
+}
+
+// Persistent: workgroups take big tiles from a counter until none is left.
+template <int KW>
+__global__ void __launch_bounds__(kSortThreads)
+k_big_tiles(KeyCfg kc, const Tile* __restrict__ tiles, const uint32_t* __restrict__ big_list,
+            const uint64_t* __restrict__ big_off, const uint32_t* n_big, uint32_t* next,
+            uint64_t* keys, uint64_t* tmp, uint32_t* counts, uint32_t* tile_out,
+            uint32_t* tile_distinct) {
+  __shared__ uint32_t item;
+  const uint32_t nb = *n_big;
+  for (;;) {
+    if (threadIdx.x == 0) item = atomicAdd(next, 1u);
+    __syncthreads();
+    const uint32_t it = item;
+    __syncthreads();
+    if (it >= nb) return;
+    big_tile<KW>(kc, tiles, big_list[it], big_off[it], keys, tmp, counts, tile_out,
+                 tile_distinct);
   }
 }
 
@@ -820,6 +921,25 @@ k_gather(const Tile* __restrict__ tiles, const uint64_t* __restrict__ tile_off,
 
 }  // namespace
 
+// Workgroups of kSortThreads that are resident at once on the current
+// device: compute units x blocks per unit (by occupancy), cached per
+// (kernel slot, device).
+static int resident_blocks(const void* kernel, int slot) {
+  constexpr int kSlots = 4, kDevs = 16;
+  static std::atomic<int> cache[kSlots][kDevs];
+  int dev = 0;
+  (void)hipGetDevice(&dev);
+  if (dev < 0 || dev >= kDevs) dev = 0;
+  int v = cache[slot][dev].load(std::memory_order_relaxed);
+  if (v) return v;
+  int cus = 0, per_cu = 0;
+  (void)hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
+  (void)hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kernel, kSortThreads, 0);
+  v = std::max(1, cus) * std::max(1, per_cu);
+  cache[slot][dev].store(v, std::memory_order_relaxed);
+  return v;
+}
+
 hipError_t launch_tile_sort(hipStream_t s, const KeyCfg& kc, const Tile* tiles,
                             uint64_t n_tiles, uint64_t* keys, uint32_t* out_counts,
                             uint32_t* tile_out, uint32_t* big_list, uint64_t* big_off,
@@ -827,19 +947,11 @@ hipError_t launch_tile_sort(hipStream_t s, const KeyCfg& kc, const Tile* tiles,
                             uint32_t* tile_distinct) {
   if (n_tiles == 0) return hipSuccess;
   // persistent grid: exactly the workgroups that are resident at once
-  static int resident[3] = {0, 0, 0};
   const int kw = kc.key_words == 1 ? 1 : 2;
-  if (!resident[kw]) {
-    int dev = 0, cus = 0, per_cu = 0;
-    (void)hipGetDevice(&dev);
-    (void)hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
-    if (kw == 1)
-      (void)hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_tile_sort<1>, kSortThreads, 0);
-    else
-      (void)hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_tile_sort<2>, kSortThreads, 0);
-    resident[kw] = std::max(1, cus) * std::max(1, per_cu);
-  }
-  const uint32_t grid = (uint32_t)std::min<uint64_t>(n_tiles, (uint64_t)resident[kw]);
+  const uint32_t grid = (uint32_t)std::min<uint64_t>(
+      n_tiles, (uint64_t)resident_blocks(kw == 1 ? (const void*)k_tile_sort<1>
+                                                 : (const void*)k_tile_sort<2>,
+                                         kw - 1));
   if (kc.key_words == 1)
     hipLaunchKernelGGL(k_tile_sort<1>, dim3(grid), dim3(kSortThreads), 0, s, kc,
                        tiles, n_tiles, keys, out_counts, tile_out, big_list, big_off, n_big, big_total,
@@ -852,16 +964,24 @@ hipError_t launch_tile_sort(hipStream_t s, const KeyCfg& kc, const Tile* tiles,
 }
 
 hipError_t launch_big_tiles(hipStream_t s, const KeyCfg& kc, const Tile* tiles,
-                            const uint32_t* big_list, const uint64_t* big_off, uint32_t n_big,
+                            const uint32_t* big_list, const uint64_t* big_off,
+                            const uint32_t* n_big, uint32_t* next, uint64_t max_big,
                             uint64_t* keys, uint64_t* tmp, uint32_t* out_counts,
                             uint32_t* tile_out, uint32_t* tile_distinct) {
-  if (n_big == 0) return hipSuccess;
-  if (kc.key_words == 1)
-    hipLaunchKernelGGL(k_big_tiles<1>, dim3(n_big), dim3(kSortThreads), 0, s, kc, tiles,
-                       big_list, big_off, keys, tmp, out_counts, tile_out, tile_distinct);
+  if (max_big == 0) return hipSuccess;
+  const int kw = kc.key_words == 1 ? 1 : 2;
+  const uint32_t grid = (uint32_t)std::min<uint64_t>(
+      max_big, (uint64_t)resident_blocks(kw == 1 ? (const void*)k_big_tiles<1>
+                                                 : (const void*)k_big_tiles<2>,
+                                         1 + kw));
+  if (kw == 1)
+    hipLaunchKernelGGL(k_big_tiles<1>, dim3(grid), dim3(kSortThreads), 0, s, kc, tiles,
+                       big_list, big_off, n_big, next, keys, tmp, out_counts, tile_out,
+                       tile_distinct);
   else
-    hipLaunchKernelGGL(k_big_tiles<2>, dim3(n_big), dim3(kSortThreads), 0, s, kc, tiles,
-                       big_list, big_off, keys, tmp, out_counts, tile_out, tile_distinct);
+    hipLaunchKernelGGL(k_big_tiles<2>, dim3(grid), dim3(kSortThreads), 0, s, kc, tiles,
+                       big_list, big_off, n_big, next, keys, tmp, out_counts, tile_out,
+                       tile_distinct);
   return hipGetLastError();
 }
 

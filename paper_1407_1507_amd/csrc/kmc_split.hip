@@ -35,6 +35,16 @@ __device__ __forceinline__ uint32_t load_word(const uint8_t* __restrict__ seq, u
   return w;
 }
 
+// The 16 bytes at x16 (x16 % 16 == 0), same conventions: one 16-byte load
+// when seq is 16-byte aligned and the chunk lies inside it.
+__device__ __forceinline__ uint4 load_chunk(const uint8_t* __restrict__ seq, uint64_t n,
+                                            uint32_t align, uint64_t x16) {
+  if (align >= 16 && x16 + 15 < n) return reinterpret_cast<const uint4*>(seq)[x16 >> 4];
+  const bool a4 = align >= 4;
+  return make_uint4(load_word(seq, n, a4, x16), load_word(seq, n, a4, x16 + 4),
+                    load_word(seq, n, a4, x16 + 8), load_word(seq, n, a4, x16 + 12));
+}
+
 // Scan bytes [x0, x1) of one read.  For every k-mer start j the sink sees
 // kmer(j, signature) (0xFFFFFFFF if the k-mer holds an invalid byte; the sink
 // ignores starts outside the read); every super k-mer is passed to
@@ -44,7 +54,8 @@ __device__ __forceinline__ uint32_t load_word(const uint8_t* __restrict__ seq, u
 // never holds more than 2k - p symbols (where super k-mers are cut does not
 // change the counts).
 //
-// The lane walks whole aligned words from the word holding x0; bytes outside
+// The lane walks aligned 16-byte chunks from the chunk holding x0, the load
+// of the next chunk in flight while the current one is scanned; bytes outside
 // [x0, x1) count as invalid, so no k-mer leaves the read and the loop body has
 // no start/end special cases.
 //
@@ -65,20 +76,23 @@ __device__ __forceinline__ void scan_read(const uint8_t* __restrict__ seq, uint6
   if (x1 < x0 + k) return;
   const K kmask = key_mask<K>(k);
   const uint32_t rcs = 2 * p - 2;
-  const bool a4 = C.aligned4 != 0;
   for (uint32_t i = 0; i < 2 * w; ++i) vh[i] = (VT)0;
   uint32_t run = 0, fp = 0, rp = 0;
   uint32_t in_blk = 0, par = 0, pre = 0;
   uint32_t cur_n = 0, cur_sig = 0, cur_bin = 0;
   uint64_t cur_start = 0;
   K F = 0, curF = 0, tail = 0;
-  for (uint64_t xw = x0 & ~3ull; xw < x1; xw += 4) {
-    const uint32_t word = load_word(seq, n_bases, a4, xw);
+  uint64_t xc = x0 & ~15ull;
+  uint4 chunk = load_chunk(seq, n_bases, C.seq_align, xc);
+  for (; xc < x1; xc += 16) {
+    const uint4 next =
+        xc + 16 < x1 ? load_chunk(seq, n_bases, C.seq_align, xc + 16) : make_uint4(0, 0, 0, 0);
 #pragma unroll
-    for (uint32_t q = 0; q < 4; ++q) {
-      const uint64_t x = xw + q;
+    for (uint32_t q = 0; q < 16; ++q) {
+      const uint64_t x = xc + q;
+      const uint32_t word = q < 4 ? chunk.x : q < 8 ? chunk.y : q < 12 ? chunk.z : chunk.w;
       bool ok;
-      const uint32_t c = decode_base((word >> (8 * q)) & 0xFFu, ok);
+      const uint32_t c = decode_base((word >> (8 * (q & 3))) & 0xFFu, ok);
       ok = ok && x >= x0 && x < x1;
       run = ok ? run + 1 : 0;
       fp = ((fp << 2) | c) & C.pmask;
@@ -127,6 +141,7 @@ __device__ __forceinline__ void scan_read(const uint8_t* __restrict__ seq, uint6
         par ^= 1u;
       }
     }
+    chunk = next;
   }
   if (cur_n) sink.superkmer(cur_start, cur_n, cur_sig, cur_bin, curF, tail);
 }
@@ -196,21 +211,53 @@ k_sig_hist(const uint8_t* __restrict__ seq, const uint64_t* __restrict__ offsets
 // past the region end are not written (the host then repeats the pass with
 // the exact sizes the cursors report).
 
-template <int KW, bool STAGE>
-struct ScatterSink {
+// Every super k-mer goes to its lane's own queue in LDS (no atomics while the
+// wave scans: emission is divergent, so it must be cheap); a full queue sends
+// the record straight to its bin with a global atomic.
+template <int KW, class VT>
+struct QueueSink {
   static constexpr bool kNeedKeys = true;
   static constexpr int RW = 2 * KW;  // record words
   const uint32_t* map;
-  uint32_t cap;
-  uint32_t* lnum;     // staged records
-  uint32_t* lcnt;     // staged records per bin
-  uint32_t* lkm;      // k-mers per bin
-  uint64_t* stage;    // cap * RW
-  uint32_t* sbin;     // cap
-  uint16_t* srank;    // cap
+  uint64_t* stage;   // this lane's Q slots, RW words each
+  VT* ssig;          // signature of each slot (VT holds every signature)
+  uint32_t q, Q;
   unsigned long long* gcursor;
   unsigned long long* gkmer;
-  const uint64_t* cap_base;  // region of bin b: [cap_base[b], cap_base[b+1])
+  const uint64_t* cap_base;
+  uint64_t* records;
+  __device__ void kmer(uint64_t, uint32_t, uint64_t, uint64_t) {}
+  __device__ uint32_t bin_of(uint32_t) { return 0; }
+  __device__ void superkmer(uint64_t, uint32_t n, uint32_t sig, uint32_t,
+                            typename KeyOf<KW>::T F, typename KeyOf<KW>::T tail) {
+    uint64_t rec[RW];
+    make_record(rec, F, tail, n);
+    if (q < Q) {
+#pragma unroll
+      for (int w = 0; w < RW; ++w) stage[q * RW + w] = rec[w];
+      ssig[q] = (VT)sig;
+      ++q;
+      return;
+    }
+    const uint32_t b = map[sig];
+    atomicAdd(&gkmer[b], (unsigned long long)n);
+    const uint64_t g = atomicAdd(&gcursor[b], 1ull);
+    if (g < cap_base[b + 1]) {
+#pragma unroll
+      for (int w = 0; w < RW; ++w) records[g * RW + w] = rec[w];
+    }
+  }
+};
+
+// Records without a queue (bin counts whose LDS arrays do not fit).
+template <int KW>
+struct DirectSink {
+  static constexpr bool kNeedKeys = true;
+  static constexpr int RW = 2 * KW;
+  const uint32_t* map;
+  unsigned long long* gcursor;
+  unsigned long long* gkmer;
+  const uint64_t* cap_base;
   uint64_t* records;
   __device__ void kmer(uint64_t, uint32_t, uint64_t, uint64_t) {}
   __device__ uint32_t bin_of(uint32_t sig) { return map[sig]; }
@@ -218,81 +265,80 @@ struct ScatterSink {
                             typename KeyOf<KW>::T tail) {
     uint64_t rec[RW];
     make_record(rec, F, tail, n);
-    if (STAGE) {
-      atomicAdd(&lkm[b], n);
-      const uint32_t idx = atomicAdd(lnum, 1u);
-      if (idx < cap) {
-        srank[idx] = (uint16_t)atomicAdd(&lcnt[b], 1u);
-        sbin[idx] = b;
-#pragma unroll
-        for (int q = 0; q < RW; ++q) stage[(uint64_t)idx * RW + q] = rec[q];
-        return;
-      }
-    } else {
-      atomicAdd(&gkmer[b], (unsigned long long)n);
-    }
-    // not staged: claim one slot directly
+    atomicAdd(&gkmer[b], (unsigned long long)n);
     const uint64_t g = atomicAdd(&gcursor[b], 1ull);
     if (g < cap_base[b + 1]) {
 #pragma unroll
-      for (int q = 0; q < RW; ++q) records[g * RW + q] = rec[q];
+      for (int w = 0; w < RW; ++w) records[g * RW + w] = rec[w];
     }
   }
 };
+
+// Queue slots per lane.
+template <int KW> struct SplitQ { static constexpr uint32_t Q = KW == 1 ? 8 : 4; };
 
 template <int KW, class VT>
 __global__ void __launch_bounds__(256)
 k_split_scatter(const uint8_t* __restrict__ seq, const uint64_t* __restrict__ offsets,
                 uint64_t n_reads, uint64_t n_bases, ScanCfg C, const uint32_t* __restrict__ map,
                 unsigned long long* gcursor, unsigned long long* gkmer,
-                const uint64_t* __restrict__ cap_base, uint64_t* records, uint32_t cap,
-                uint32_t vh_bytes) {
+                const uint64_t* __restrict__ cap_base, uint64_t* records, uint32_t vh_bytes) {
   constexpr int RW = 2 * KW;
+  constexpr uint32_t Q = SplitQ<KW>::Q;
   extern __shared__ __attribute__((aligned(16))) uint8_t lds8[];
+  const uint32_t tid = threadIdx.x, nt = blockDim.x, cap = nt * Q;
   // layout: vh | stage[cap*RW] u64 | delta[n_bins] u64 | lcnt, lbase, lkm [n_bins] u32 |
-  //         sbin[cap] u32 | inv[cap] u16 | srank[cap] u16 | lnum, scan tmp
+  //         qn[lanes] u32 | ssig[cap] VT (signature, then bin) | inv[cap] u16 |
+  //         srank[cap] u16 | scan tmp
   uint64_t* stage = reinterpret_cast<uint64_t*>(lds8 + vh_bytes);
   uint64_t* delta = stage + (uint64_t)cap * RW;
   uint32_t* lcnt = reinterpret_cast<uint32_t*>(delta + C.n_bins);
   uint32_t* lbase = lcnt + C.n_bins;
   uint32_t* lkm = lbase + C.n_bins;
-  uint32_t* sbin = lkm + C.n_bins;
-  uint16_t* inv = reinterpret_cast<uint16_t*>(sbin + cap);
+  uint32_t* qn = lkm + C.n_bins;
+  VT* ssig = reinterpret_cast<VT*>(qn + nt);
+  uint16_t* inv = reinterpret_cast<uint16_t*>(ssig + cap);
   uint16_t* srank = inv + cap;
-  uint32_t* misc = reinterpret_cast<uint32_t*>(srank + cap);
-  uint32_t* lnum = misc;
-  uint32_t* tmp = misc + 1;
+  uint32_t* tmp = reinterpret_cast<uint32_t*>(srank + cap);
 
-  for (uint32_t i = threadIdx.x; i < C.n_bins; i += blockDim.x) lcnt[i] = lkm[i] = 0;
-  if (threadIdx.x == 0) *lnum = 0;
-  __syncthreads();
+  for (uint32_t i = tid; i < C.n_bins; i += nt) lcnt[i] = lkm[i] = 0;
 
-  const uint64_t r = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  ScatterSink<KW, true> sink{map, cap, lnum, lcnt, lkm, stage, sbin, srank,
-                             gcursor, nullptr, cap_base, records};
+  const uint64_t r = (uint64_t)blockIdx.x * nt + tid;
+  QueueSink<KW, VT> sink{map, stage + (uint64_t)tid * Q * RW, ssig + tid * Q, 0, Q,
+                     gcursor, gkmer, cap_base, records};
   if (r < n_reads)
     scan_read<KW, VT>(seq, n_bases, offsets[r], offsets[r + 1], C, lane_vh<VT>(lds8, C.w), sink);
+  qn[tid] = sink.q;
   __syncthreads();
 
-  const uint32_t nst = min(*lnum, cap);
-  for (uint32_t i = threadIdx.x; i < C.n_bins; i += blockDim.x) lbase[i] = lcnt[i];
+  // bins of the queued records, their rank inside the bin, k-mers per bin
+  for (uint32_t i = tid; i < cap; i += nt) {
+    if (i % Q < qn[i / Q]) {
+      const uint32_t b = map[ssig[i]];
+      ssig[i] = (VT)b;  // n_bins <= 65535
+      srank[i] = (uint16_t)atomicAdd(&lcnt[b], 1u);
+      atomicAdd(&lkm[b], (uint32_t)(stage[(uint64_t)i * RW + RW - 1] & 0xFFu));
+    }
+  }
   __syncthreads();
-  block_exclusive_scan(lbase, C.n_bins, tmp);
+  for (uint32_t i = tid; i < C.n_bins; i += nt) lbase[i] = lcnt[i];
+  __syncthreads();
+  const uint32_t nst = block_exclusive_scan(lbase, C.n_bins, tmp);
   // one reservation per non-empty bin; delta maps a local slot to its global slot
-  for (uint32_t i = threadIdx.x; i < C.n_bins; i += blockDim.x) {
+  for (uint32_t i = tid; i < C.n_bins; i += nt) {
     if (lcnt[i]) {
       const uint64_t g = atomicAdd(&gcursor[i], (unsigned long long)lcnt[i]);
       delta[i] = g - lbase[i];
     }
     if (lkm[i]) atomicAdd(&gkmer[i], (unsigned long long)lkm[i]);
   }
-  for (uint32_t i = threadIdx.x; i < nst; i += blockDim.x)
-    inv[lbase[sbin[i]] + srank[i]] = (uint16_t)i;
+  for (uint32_t i = tid; i < cap; i += nt)
+    if (i % Q < qn[i / Q]) inv[lbase[ssig[i]] + srank[i]] = (uint16_t)i;
   __syncthreads();
   // write records grouped by bin: consecutive lanes -> consecutive slots
-  for (uint32_t q = threadIdx.x; q < nst; q += blockDim.x) {
+  for (uint32_t q = tid; q < nst; q += nt) {
     const uint32_t i = inv[q];
-    const uint32_t b = sbin[i];
+    const uint32_t b = ssig[i];
     const uint64_t g = delta[b] + q;
     if (g < cap_base[b + 1]) {
 #pragma unroll
@@ -311,8 +357,7 @@ k_split_scatter_direct(const uint8_t* __restrict__ seq, const uint64_t* __restri
                        uint64_t* records) {
   extern __shared__ __attribute__((aligned(16))) uint8_t lds8[];
   const uint64_t r = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  ScatterSink<KW, false> sink{map, 0, nullptr, nullptr, nullptr, nullptr, nullptr, nullptr,
-                              gcursor, gkmer, cap_base, records};
+  DirectSink<KW> sink{map, gcursor, gkmer, cap_base, records};
   if (r < n_reads)
     scan_read<KW, VT>(seq, n_bases, offsets[r], offsets[r + 1], C, lane_vh<VT>(lds8, C.w), sink);
 }
@@ -414,10 +459,11 @@ hipError_t launch_sig_hist(hipStream_t s, const uint8_t* seq, const uint64_t* of
   return hipGetLastError();
 }
 
-static size_t split_stage_lds(uint32_t key_words, uint32_t n_bins, uint32_t cap) {
+static size_t split_stage_lds(const ScanCfg& c, uint32_t key_words, uint32_t lanes) {
   const uint32_t RW = 2 * key_words;
-  return (size_t)cap * RW * 8 + (size_t)n_bins * 8 + (size_t)n_bins * 12 + (size_t)cap * 4 +
-         (size_t)cap * 4 + 4 + 4 * 4 + 16;
+  const size_t cap = (size_t)lanes * (key_words == 1 ? SplitQ<1>::Q : SplitQ<2>::Q);
+  return cap * RW * 8 + (size_t)c.n_bins * 8 + (size_t)c.n_bins * 12 + (size_t)lanes * 4 +
+         cap * (small_vt(c) ? 2 : 4) + cap * 4 + 4 * 4 + 16;
 }
 
 hipError_t launch_split_scatter(hipStream_t s, const uint8_t* seq, const uint64_t* offsets,
@@ -426,16 +472,14 @@ hipError_t launch_split_scatter(hipStream_t s, const uint8_t* seq, const uint64_
                                 unsigned long long* cursor, unsigned long long* kmer_cnt,
                                 const uint64_t* cap_base, uint64_t* records) {
   if (n_reads == 0) return hipSuccess;
-  // largest workgroup whose window buffers + staging fit 80 KB (two per CU)
-  const uint32_t per_lane = key_words == 1 ? 8 : 4;  // staged records per lane
+  // largest workgroup whose window buffers + queues fit 80 KB (two per CU)
   for (uint32_t lanes = 256; lanes >= 64; lanes >>= 1) {
-    const uint32_t cap = lanes * per_lane;
     const size_t vb = vh_bytes(cfg, lanes);
-    const size_t sh = vb + split_stage_lds(key_words, cfg.n_bins, cap);
+    const size_t sh = vb + split_stage_lds(cfg, key_words, lanes);
     if (sh <= 80 * 1024) {
       KMC_SCAN_DISPATCH(k_split_scatter, dim3(grid_for(n_reads, lanes)), dim3(lanes), sh, s,
                         seq, offsets, n_reads, n_bases, cfg, sig_to_bin, cursor, kmer_cnt,
-                        cap_base, records, cap, (uint32_t)vb);
+                        cap_base, records, (uint32_t)vb);
       return hipGetLastError();
     }
   }
