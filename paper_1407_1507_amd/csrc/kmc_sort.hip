@@ -37,7 +37,7 @@ template <> struct SortCfg<1> {
 };
 template <> struct SortCfg<2> {
   static constexpr uint32_t CAP = kTileCap2, DIG = 11, ITEMS = kTileCap2 / kSortThreads;
-  static constexpr uint32_t DIRECT = kTileCap2;
+  static constexpr uint32_t DIRECT = 3 * kTileCap2 / 4;
 };
 constexpr uint32_t kInsMax = 16;    // mixed buckets up to this size: insertion sort by one lane
 constexpr uint32_t kBigMax = 256;   // larger mixed buckets listed per tile (CAP / (kInsMax + 1) < 256)
@@ -205,7 +205,8 @@ template <int KW>
 __device__ void order_kept(typename KeyOf<KW>::T (&key)[SortCfg<KW>::ITEMS],
                            uint32_t (&cnt)[SortCfg<KW>::ITEMS], uint32_t kbase, uint32_t kept,
                            typename KeyOf<KW>::T diff, uint64_t* out_keys,
-                           uint32_t* out_counts, SortShared<KW>& S) {
+                           uint32_t* out_counts, typename KeyOf<KW>::T* A, uint32_t* H,
+                           uint32_t* tmp) {
   typedef typename KeyOf<KW>::T K;
   constexpr uint32_t ITEMS = SortCfg<KW>::ITEMS, DIG = SortCfg<KW>::DIG;
   const uint32_t tid = threadIdx.x, nt = blockDim.x;
@@ -217,8 +218,8 @@ __device__ void order_kept(typename KeyOf<KW>::T (&key)[SortCfg<KW>::ITEMS],
 #pragma unroll
     for (uint32_t qq = 0; qq < ITEMS; ++qq) {
       if (cnt[qq]) {
-        S.A[at] = key[qq];
-        S.H[at] = cnt[qq];
+        A[at] = key[qq];
+        H[at] = cnt[qq];
         ++at;
       }
     }
@@ -235,30 +236,30 @@ __device__ void order_kept(typename KeyOf<KW>::T (&key)[SortCfg<KW>::ITEMS],
     if (m < mk) {
       const uint32_t i = m * nt + tid;
       if (i < kept) {
-        key[m] = S.A[i];
-        cnt[m] = S.H[i];
+        key[m] = A[i];
+        cnt[m] = H[i];
       }
     }
   }
   __syncthreads();
-  for (uint32_t i = tid; i < nb2; i += nt) S.H[i] = 0;
+  for (uint32_t i = tid; i < nb2; i += nt) H[i] = 0;
   __syncthreads();
 #pragma unroll
   for (uint32_t m = 0; m < ITEMS; ++m)
-    if (m < mk && cnt[m]) atomicAdd(&S.H[(uint32_t)(key[m] >> shift) & dmask], 1u);
+    if (m < mk && cnt[m]) atomicAdd(&H[(uint32_t)(key[m] >> shift) & dmask], 1u);
   __syncthreads();
-  block_exclusive_scan(S.H, nb2, S.tmp);
+  block_exclusive_scan(H, nb2, tmp);
 #pragma unroll
   for (uint32_t m = 0; m < ITEMS; ++m)
-    if (m < mk && cnt[m]) S.A[atomicAdd(&S.H[(uint32_t)(key[m] >> shift) & dmask], 1u)] = key[m];
+    if (m < mk && cnt[m]) A[atomicAdd(&H[(uint32_t)(key[m] >> shift) & dmask], 1u)] = key[m];
   __syncthreads();
 #pragma unroll
   for (uint32_t m = 0; m < ITEMS; ++m) {
     if (m < mk && cnt[m]) {
       const uint32_t d = (uint32_t)(key[m] >> shift) & dmask;
-      const uint32_t s = d ? S.H[d - 1] : 0, e = S.H[d];
+      const uint32_t s = d ? H[d - 1] : 0, e = H[d];
       uint32_t r = s;
-      for (uint32_t j = s; j < e; ++j) r += S.A[j] < key[m];
+      for (uint32_t j = s; j < e; ++j) r += A[j] < key[m];
       store_key(out_keys, r, key[m]);
       out_counts[r] = cnt[m];
     }
@@ -387,7 +388,7 @@ __device__ __forceinline__ uint32_t count_tile_hash(uint64_t (&key)[SortCfg<1>::
     __syncthreads();
     return kept;
   }
-  order_kept<1>(key, cnt, kbase, kept, diff, out_keys, out_counts, S);
+  order_kept<1>(key, cnt, kbase, kept, diff, out_keys, out_counts, S.A, S.H, S.tmp);
   if (kClean) {
     // order_kept used A[0, kept) and H[0, max(kept, buckets)), buckets <= T
     const uint32_t hb = high_bit(diff);
@@ -400,8 +401,153 @@ __device__ __forceinline__ uint32_t count_tile_hash(uint64_t (&key)[SortCfg<1>::
   return kept;
 }
 
-// Count a tile whose keys are in registers: hash table when it fits half the
-// table (64-bit keys), hashed buckets otherwise.
+// ------------------------------------------------- 128-bit keys: hash table
+// LDS compare-and-swap is 64 bits wide, so a 128-bit key claims its slot by
+// a 48-bit fingerprint (with a 16-bit count in the same word) and the claimer
+// stores the full key beside it.  After the inserts every key checks the key
+// stored in its slot: if two different keys shared a fingerprint the tile is
+// not counted here (the caller hands it to the exact big-tile path), so the
+// result never depends on the fingerprint.
+constexpr uint32_t kHashSlots2 = 2048, kHashBits2 = 11;
+static_assert((1u << kHashBits2) == kHashSlots2 && kHashSlots2 == kTileCap2, "table size");
+
+struct HashShared2 {
+  uint64_t F[kHashSlots2];  // 0: empty; else fingerprint << 16 | count
+  u128 K[kHashSlots2];      // the key of an occupied slot
+  uint64_t red[4 * kSortThreads / 64];
+  uint32_t tmp[kSortThreads / 64];
+};
+
+__device__ __forceinline__ uint64_t mix128(u128 x) {
+  uint64_t h = (uint64_t)x * 0x9E3779B97F4A7C15ull ^ (uint64_t)(x >> 64) * 0xD6E8FEB86659FD93ull;
+  h ^= h >> 31;
+  h *= 0xBF58476D1CE4E5B9ull;
+  h ^= h >> 29;
+  return h;
+}
+
+constexpr uint32_t kFingerprintClash = 0xFFFFFFFFu;
+
+// Returns the kept count, or kFingerprintClash (nothing written, table
+// empty again).  The table is empty on entry and on return.
+__device__ uint32_t count_tile_hash2(u128 (&key)[SortCfg<2>::ITEMS], uint32_t n,
+                                     uint64_t* out_keys, uint32_t* out_counts, uint32_t ci,
+                                     uint32_t cx, HashShared2& S, uint32_t* distinct) {
+  constexpr uint32_t ITEMS = SortCfg<2>::ITEMS, T = kHashSlots2;
+  static_assert(T == ITEMS * kSortThreads, "one slot per register slot");
+  const uint32_t tid = threadIdx.x, nt = blockDim.x;
+  uint32_t slot_of[ITEMS];
+#pragma unroll
+  for (uint32_t m = 0; m < ITEMS; ++m) {
+    if (m * nt + tid < n) {
+      const uint64_t h = mix128(key[m]);
+      uint32_t slot = (uint32_t)(h >> (64 - kHashBits2));
+      const uint64_t fp = (h & ((1ull << 47) - 1)) | (1ull << 47);  // never 0
+      for (;;) {
+        const unsigned long long old = atomicCAS(
+            reinterpret_cast<unsigned long long*>(&S.F[slot]), 0ull,
+            (unsigned long long)((fp << 16) | 1u));
+        if (old == 0) {
+          S.K[slot] = key[m];
+          break;
+        }
+        if ((old >> 16) == fp) {
+          atomicAdd(reinterpret_cast<unsigned long long*>(&S.F[slot]), 1ull);
+          break;
+        }
+        slot = (slot + 1) & (T - 1);
+      }
+      slot_of[m] = slot;
+    }
+  }
+  __syncthreads();
+  bool clash = false;
+#pragma unroll
+  for (uint32_t m = 0; m < ITEMS; ++m)
+    if (m * nt + tid < n && S.K[slot_of[m]] != key[m]) clash = true;
+  if (__syncthreads_or(clash)) {
+    for (uint32_t i = tid; i < T; i += nt) S.F[i] = 0;
+    __syncthreads();
+    return kFingerprintClash;
+  }
+  // read back (and clear) the occupied slots
+  uint32_t cnt[ITEMS];
+  uint32_t nh = 0, nk = 0;
+  u128 a = ~(u128)0, o = 0;
+#pragma unroll
+  for (uint32_t i = 0; i < ITEMS; ++i) {
+    const uint32_t s = i * nt + tid;
+    const uint64_t w = S.F[s];
+    cnt[i] = 0;
+    if (w) {
+      ++nh;
+      const uint32_t c = (uint32_t)(w & 0xFFFFu);
+      S.F[s] = 0;
+      if (c >= ci && c <= cx) {
+        key[i] = S.K[s];
+        cnt[i] = c;
+        a &= key[i];
+        o |= key[i];
+        ++nk;
+      }
+    }
+  }
+  uint32_t H_total, kept;
+  (void)block_scan_one(nh, S.tmp, H_total);
+  *distinct = H_total;
+  const uint32_t kbase = block_scan_one(nk, S.tmp, kept);  // barrier: read-back is done
+  if (kept == 0) return 0;
+  block_and_or<u128>(a, o, S.red);
+  const u128 diff = a ^ o;
+  if (diff == 0) {
+#pragma unroll
+    for (uint32_t i = 0; i < ITEMS; ++i)
+      if (cnt[i]) {
+        store_key(out_keys, 0, key[i]);
+        out_counts[0] = cnt[i];
+      }
+    __syncthreads();
+    return 1;
+  }
+  // kept keys are ordered in K (free now) with counts in F's words, which
+  // are cleared again afterwards
+  uint32_t* H = reinterpret_cast<uint32_t*>(S.F);
+  uint32_t dirty;
+  if (kept <= kRankMax) {
+    uint32_t at = kbase;
+#pragma unroll
+    for (uint32_t i = 0; i < ITEMS; ++i) {
+      if (cnt[i]) {
+        S.K[at] = key[i];
+        H[at] = cnt[i];
+        ++at;
+      }
+    }
+    __syncthreads();
+    if (tid < kept) {
+      const u128 x = S.K[tid];
+      const uint32_t c = H[tid];
+      uint32_t r = 0;
+      for (uint32_t j = 0; j < kept; ++j) r += S.K[j] < x;
+      store_key(out_keys, r, x);
+      out_counts[r] = c;
+    }
+    __syncthreads();
+    dirty = kept;
+  } else {
+    order_kept<2>(key, cnt, kbase, kept, diff, out_keys, out_counts, S.K, H, S.tmp);
+    const uint32_t hb = high_bit(diff);
+    const uint32_t t2 = min(min(SortCfg<2>::DIG, bit_len(kept) + 1), hb + 1);
+    dirty = max(kept, 1u << t2);
+  }
+  for (uint32_t i = tid; i < (dirty + 1) / 2; i += nt) S.F[i] = 0;
+  __syncthreads();
+  return kept;
+}
+
+// Count a tile whose keys are in registers: the hash table for 64-bit keys
+// (up to CAP keys: the table has CAP slots, so every distinct key finds one),
+// hashed buckets for 128-bit keys.
 template <int KW>
 __device__ __forceinline__ uint32_t count_any(typename KeyOf<KW>::T (&key)[SortCfg<KW>::ITEMS],
                                               uint32_t n, uint64_t* out_keys,
@@ -412,9 +558,7 @@ __device__ __forceinline__ uint32_t count_any<1>(uint64_t (&key)[SortCfg<1>::ITE
                                                  uint64_t* out_keys, uint32_t* out_counts,
                                                  uint32_t ci, uint32_t cx, SortShared<1>& S,
                                                  uint32_t* distinct) {
-  if (n <= SortCfg<1>::DIRECT)
-    return count_tile_hash<false>(key, n, out_keys, out_counts, ci, cx, S, distinct);
-  return count_tile<1>(key, n, out_keys, out_counts, ci, cx, S, distinct);
+  return count_tile_hash<false>(key, n, out_keys, out_counts, ci, cx, S, distinct);
 }
 
 // The tile kernel's counting: only the hash table for 64-bit keys (tiles up
@@ -617,7 +761,7 @@ __device__ __forceinline__ uint32_t count_tile(typename KeyOf<KW>::T (&key)[Sort
     return 1;
   }
 
-  order_kept<KW>(key, cnt, kbase, kept, diff, out_keys, out_counts, S);
+  order_kept<KW>(key, cnt, kbase, kept, diff, out_keys, out_counts, S.A, S.H, S.tmp);
   __syncthreads();
   return kept;
 }
@@ -660,6 +804,44 @@ k_tile_sort(KeyCfg kc, const Tile* __restrict__ tiles, uint64_t n_tiles, uint64_
       const uint32_t kept = count_direct(key, T.size, keys + T.begin * KW, counts + T.begin,
                                          kc.cutoff_min, kc.cutoff_max, S, &d);
       if (threadIdx.x == 0) {
+        tile_out[t] = kept;
+        tile_distinct[t] = d;
+      }
+    }
+  }
+}
+
+// Tiles of 128-bit keys: the fingerprint hash table; tiles above DIRECT keys
+// and tiles whose fingerprints clash go to the big-tile kernel.  Persistent,
+// like k_tile_sort.
+__global__ void __launch_bounds__(kSortThreads, 3)
+k_tile_hash2(KeyCfg kc, const Tile* __restrict__ tiles, uint64_t n_tiles, uint64_t* keys,
+             uint32_t* counts, uint32_t* tile_out, uint32_t* big_list, uint64_t* big_off,
+             uint32_t* n_big, unsigned long long* big_total, uint32_t* tile_distinct) {
+  constexpr uint32_t ITEMS = SortCfg<2>::ITEMS;
+  __shared__ HashShared2 S;
+  for (uint32_t i = threadIdx.x; i < kHashSlots2; i += blockDim.x) S.F[i] = 0;
+  __syncthreads();
+  Tile next = tiles[blockIdx.x];
+  for (uint64_t t = blockIdx.x; t < n_tiles; t += gridDim.x) {
+    const Tile T = next;
+    if (t + gridDim.x < n_tiles) next = tiles[t + gridDim.x];
+    uint32_t kept = kFingerprintClash, d = 0;
+    if (T.size == 0) {
+      kept = 0;
+    } else if (T.size <= SortCfg<2>::DIRECT) {
+      u128 key[ITEMS];
+      load_tile<2>(keys + T.begin * 2, T.size, key);
+      kept = count_tile_hash2(key, T.size, keys + T.begin * 2, counts + T.begin, kc.cutoff_min,
+                              kc.cutoff_max, S, &d);
+    }
+    if (threadIdx.x == 0) {
+      if (kept == kFingerprintClash) {
+        tile_out[t] = tile_distinct[t] = 0;
+        const uint32_t idx = atomicAdd(n_big, 1u);
+        big_list[idx] = (uint32_t)t;
+        big_off[idx] = atomicAdd(big_total, (unsigned long long)T.size);
+      } else {
         tile_out[t] = kept;
         tile_distinct[t] = d;
       }
@@ -950,14 +1132,14 @@ hipError_t launch_tile_sort(hipStream_t s, const KeyCfg& kc, const Tile* tiles,
   const int kw = kc.key_words == 1 ? 1 : 2;
   const uint32_t grid = (uint32_t)std::min<uint64_t>(
       n_tiles, (uint64_t)resident_blocks(kw == 1 ? (const void*)k_tile_sort<1>
-                                                 : (const void*)k_tile_sort<2>,
+                                                 : (const void*)k_tile_hash2,
                                          kw - 1));
   if (kc.key_words == 1)
     hipLaunchKernelGGL(k_tile_sort<1>, dim3(grid), dim3(kSortThreads), 0, s, kc,
                        tiles, n_tiles, keys, out_counts, tile_out, big_list, big_off, n_big, big_total,
                        tile_distinct);
   else
-    hipLaunchKernelGGL(k_tile_sort<2>, dim3(grid), dim3(kSortThreads), 0, s, kc,
+    hipLaunchKernelGGL(k_tile_hash2, dim3(grid), dim3(kSortThreads), 0, s, kc,
                        tiles, n_tiles, keys, out_counts, tile_out, big_list, big_off, n_big, big_total,
                        tile_distinct);
   return hipGetLastError();
