@@ -293,6 +293,7 @@ ScanCfg scan_cfg(const Job& J) {
   C.sent = 1u << (2 * J.p);
   C.n_bins = J.n_bins;
   C.seq_align = J.seq_align;
+  C.L = 31u - (uint32_t)__builtin_clz(C.w);
   return C;
 }
 

@@ -25,6 +25,7 @@ struct ScanCfg {
   uint32_t sent;         // 4^p: signature of a k-mer with no allowed p-mer
   uint32_t n_bins;
   uint32_t seq_align;    // alignment of seq (16, 4 or 1): widest loads it allows
+  uint32_t L;            // floor(log2 w): the wide scan joins two 2^L windows
 };
 
 // One expansion task: records [rec_begin, rec_end) of bin `bin`.
@@ -81,6 +82,17 @@ hipError_t launch_split_scatter(hipStream_t s, const uint8_t* seq, const uint64_
                                 const uint64_t* cap_base, uint64_t* records);
 
 // Per-window signature and super k-mer starts (audit).
+// The split and the debug scan with one position per lane (kmc_scan_wide.hip),
+// for windows whose per-lane buffers do not fit LDS well.
+hipError_t launch_split_wide(hipStream_t s, const uint8_t* seq, const uint64_t* offsets,
+                             uint64_t n_reads, const ScanCfg& cfg, uint32_t key_words,
+                             const uint32_t* sig_to_bin, unsigned long long* cursor,
+                             unsigned long long* kmer_cnt, const uint64_t* cap_base,
+                             uint64_t* records);
+hipError_t launch_debug_wide(hipStream_t s, const uint8_t* seq, const uint64_t* offsets,
+                             uint64_t n_reads, const ScanCfg& cfg, uint32_t key_words,
+                             uint32_t* sig, uint8_t* start);
+
 hipError_t launch_debug_sigs(hipStream_t s, const uint8_t* seq, const uint64_t* offsets,
                              uint64_t n_reads, uint64_t n_bases, const ScanCfg& cfg,
                              uint32_t key_words, uint32_t* sig, uint8_t* start);

@@ -466,12 +466,24 @@ static size_t split_stage_lds(const ScanCfg& c, uint32_t key_words, uint32_t lan
          cap * (small_vt(c) ? 2 : 4) + cap * 4 + 4 * 4 + 16;
 }
 
+static bool lane_scan_fits(const ScanCfg& c, uint32_t key_words) {
+  return small_vt(c) && vh_bytes(c, 256) + split_stage_lds(c, key_words, 256) <= 80 * 1024;
+}
+
+// The lane-per-read scan is used when 256 lanes' window buffers (16-bit
+// values) and record queues fit two workgroups per compute unit; otherwise
+// the scan with one position per lane (the same signatures and records).
+static bool lane_scan_fits(const ScanCfg& c, uint32_t key_words);
+
 hipError_t launch_split_scatter(hipStream_t s, const uint8_t* seq, const uint64_t* offsets,
                                 uint64_t n_reads, uint64_t n_bases, const ScanCfg& cfg,
                                 uint32_t key_words, const uint32_t* sig_to_bin,
                                 unsigned long long* cursor, unsigned long long* kmer_cnt,
                                 const uint64_t* cap_base, uint64_t* records) {
   if (n_reads == 0) return hipSuccess;
+  if (!lane_scan_fits(cfg, key_words))
+    return launch_split_wide(s, seq, offsets, n_reads, cfg, key_words, sig_to_bin, cursor,
+                             kmer_cnt, cap_base, records);
   // largest workgroup whose window buffers + queues fit 80 KB (two per CU)
   for (uint32_t lanes = 256; lanes >= 64; lanes >>= 1) {
     const size_t vb = vh_bytes(cfg, lanes);
@@ -495,6 +507,8 @@ hipError_t launch_debug_sigs(hipStream_t s, const uint8_t* seq, const uint64_t* 
                              uint64_t n_reads, uint64_t n_bases, const ScanCfg& cfg,
                              uint32_t key_words, uint32_t* sig, uint8_t* start) {
   if (n_reads == 0) return hipSuccess;
+  if (!lane_scan_fits(cfg, key_words))
+    return launch_debug_wide(s, seq, offsets, n_reads, cfg, key_words, sig, start);
   const uint32_t lanes = scan_lanes(cfg);
   const size_t sh = vh_bytes(cfg, lanes);
   KMC_SCAN_DISPATCH(k_debug_sigs, dim3(grid_for(n_reads, lanes)), dim3(lanes), sh, s, seq,
