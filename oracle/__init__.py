@@ -66,6 +66,10 @@ def _load():
                                                      ctypes.c_uint32, ctypes.c_int,
                                                      ctypes.c_void_p]
         lib.kmc_oracle_window_signatures.restype = ctypes.c_int
+        lib.kmc_oracle_count_keys.argtypes = [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_uint64,
+                                              ctypes.c_uint32, ctypes.c_void_p, ctypes.c_uint64,
+                                              ctypes.c_uint32, ctypes.c_int, ctypes.c_void_p]
+        lib.kmc_oracle_count_keys.restype = ctypes.c_int
         lib.kmc_oracle_free.argtypes = [ctypes.c_void_p]
         _lib = lib
     return _lib
@@ -103,6 +107,22 @@ def count(seq, offsets, k: int, cutoff_min: int = 1, cutoff_max: int = 2**32 - 1
     if kw == 2:
         keys = keys.reshape(m, 2)
     return keys, counts
+
+
+def count_keys(seq, offsets, k: int, keys, threads: int = 1) -> np.ndarray:
+    """Occurrences (over every valid window, canonical form) of each given key
+    (uint64 [n] or [n, 2]); for sampled checks of tables too large to sort."""
+    seq, offsets = _reads(seq, offsets)
+    keys = np.ascontiguousarray(np.asarray(keys, dtype=np.uint64))
+    kw = 1 if k <= 32 else 2
+    n = keys.shape[0] if keys.ndim > 0 else 0
+    out = np.zeros(max(n, 1), dtype=np.uint64)
+    rc = _load().kmc_oracle_count_keys(seq.ctypes.data, offsets.ctypes.data, offsets.size - 1,
+                                       k, keys.ctypes.data if n else None, n, kw, threads,
+                                       out.ctypes.data)
+    if rc != 0:
+        raise ValueError(f"oracle count_keys failed ({rc})")
+    return out[:n]
 
 
 def valid_windows(seq, offsets, k: int) -> int:

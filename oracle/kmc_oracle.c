@@ -315,3 +315,126 @@ int kmc_oracle_window_signatures(const uint8_t* seq, const uint64_t* offsets,
   }
   return 0;
 }
+
+/* ----------------------------------------------------------- count keys -- */
+
+/* Occurrences of given canonical keys: every valid window of every read is
+ * turned into its canonical key (forward and reverse-complement values rolled
+ * one symbol at a time: F = F*4 + c mod 4^k, R = R/4 + (3-c)*4^(k-1)) and
+ * looked up in an open-addressing table of the query keys.  Used to check
+ * sampled entries of tables too large for a full sort.  keys: n_keys keys of
+ * key_words words (hi word first for 2).  Returns 0, or -1 / -2 as above. */
+typedef struct {
+  const uint8_t* seq;
+  const uint64_t* offsets;
+  uint64_t r0, r1;
+  uint32_t k;
+  const u128* table;
+  const uint32_t* slot_of;
+  uint64_t mask;
+  uint64_t* counts;
+} ck_job_t;
+
+static uint64_t mix_u128(u128 x) {
+  uint64_t h = (uint64_t)x * 0x9E3779B97F4A7C15ull ^ (uint64_t)(x >> 64) * 0xC2B2AE3D27D4EB4Full;
+  h ^= h >> 29;
+  h *= 0xBF58476D1CE4E5B9ull;
+  return h ^ (h >> 32);
+}
+
+static void* count_keys_worker(void* arg) {
+  ck_job_t* J = (ck_job_t*)arg;
+  const uint32_t k = J->k;
+  const u128 kmask = k == 64 ? ~(u128)0 : (((u128)1 << (2 * k)) - 1);
+  const u128 EMPTY = ~(u128)0;
+  for (uint64_t r = J->r0; r < J->r1; ++r) {
+    u128 f = 0, rc = 0;
+    uint64_t run = 0;
+    for (uint64_t x = J->offsets[r]; x < J->offsets[r + 1]; ++x) {
+      const int c = sym_code(J->seq[x]);
+      if (c < 0) {
+        run = 0;
+        continue;
+      }
+      f = ((f << 2) | (u128)c) & kmask;
+      rc = (rc >> 2) | ((u128)(3 - c) << (2 * k - 2));
+      if (++run < k) continue;
+      const u128 key = f < rc ? f : rc;
+      uint64_t s = mix_u128(key) & J->mask;
+      while (J->table[s] != EMPTY) {
+        if (J->table[s] == key) {
+          J->counts[J->slot_of[s]]++;
+          break;
+        }
+        s = (s + 1) & J->mask;
+      }
+    }
+  }
+  return NULL;
+}
+
+int kmc_oracle_count_keys(const uint8_t* seq, const uint64_t* offsets, uint64_t n_reads,
+                          uint32_t k, const uint64_t* keys, uint64_t n_keys,
+                          uint32_t key_words, int n_threads, uint64_t* counts_out) {
+  if (k < 1 || k > 64 || (key_words != 1 && key_words != 2) || !counts_out) return -1;
+  if (n_keys && !keys) return -1;
+  uint64_t cap = 16;
+  while (cap < 2 * n_keys + 16) cap <<= 1;
+  u128* table = (u128*)malloc(cap * sizeof(u128));
+  uint32_t* slot_of = (uint32_t*)malloc(cap * sizeof(uint32_t));
+  if (n_threads < 1) n_threads = 1;
+  if (n_threads > 64) n_threads = 64;
+  uint64_t* part = (uint64_t*)calloc((size_t)n_threads * (n_keys + 1), sizeof(uint64_t));
+  if (!table || !slot_of || !part) {
+    free(table);
+    free(slot_of);
+    free(part);
+    return -2;
+  }
+  for (uint64_t s = 0; s < cap; ++s) table[s] = ~(u128)0;
+  for (uint64_t i = 0; i < n_keys; ++i) {
+    const u128 key = key_words == 1 ? (u128)keys[i]
+                                    : (((u128)keys[2 * i] << 64) | (u128)keys[2 * i + 1]);
+    uint64_t s = mix_u128(key) & (cap - 1);
+    while (table[s] != ~(u128)0 && table[s] != key) s = (s + 1) & (cap - 1);
+    table[s] = key;  /* a repeated query key shares the slot of its first copy */
+    slot_of[s] = (uint32_t)i;
+  }
+  pthread_t th[64];
+  ck_job_t jobs[64];
+  int created[64] = {0};
+  for (int t = 0; t < n_threads; ++t) {
+    jobs[t].seq = seq;
+    jobs[t].offsets = offsets;
+    jobs[t].r0 = n_reads * (uint64_t)t / (uint64_t)n_threads;
+    jobs[t].r1 = n_reads * (uint64_t)(t + 1) / (uint64_t)n_threads;
+    jobs[t].k = k;
+    jobs[t].table = table;
+    jobs[t].slot_of = slot_of;
+    jobs[t].mask = cap - 1;
+    jobs[t].counts = part + (size_t)t * (n_keys + 1);
+    if (n_threads > 1 && pthread_create(&th[t], NULL, count_keys_worker, &jobs[t]) == 0)
+      created[t] = 1;
+    else
+      count_keys_worker(&jobs[t]);
+  }
+  for (int t = 0; t < n_threads; ++t)
+    if (created[t]) pthread_join(th[t], NULL);
+  for (uint64_t i = 0; i < n_keys; ++i) {
+    uint64_t c = 0;
+    for (int t = 0; t < n_threads; ++t) c += part[(size_t)t * (n_keys + 1) + i];
+    counts_out[i] = c;
+  }
+  /* repeated query keys: every copy reports the count */
+  for (uint64_t i = 0; i < n_keys; ++i) {
+    const u128 key = key_words == 1 ? (u128)keys[i]
+                                    : (((u128)keys[2 * i] << 64) | (u128)keys[2 * i + 1]);
+    uint64_t s = mix_u128(key) & (cap - 1);
+    while (table[s] != key) s = (s + 1) & (cap - 1);
+    counts_out[i] = counts_out[slot_of[s]];
+  }
+  free(table);
+  free(slot_of);
+  free(part);
+  return 0;
+}

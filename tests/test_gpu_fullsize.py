@@ -1,0 +1,171 @@
+"""GPU parity at the full sizes of the benchmark workloads, in the launch
+configuration bench.py times (reads resident on the device, table left on the
+device and copied back here).
+
+- genome-5M-2Mx100 (2M reads x 100 bp, k = 28): the whole table equals the
+  oracle's, entry for entry.
+- repeats-50M-30x150-k55 (10M reads x 150 bp, k = 55): too large for the
+  oracle's full sort in a test, so it is checked by properties that hold at
+  any size and on samples the oracle counts one by one: the number of k-mers
+  equals the closed form; sampled table entries carry the oracle's count;
+  sampled windows of the input are in the table exactly when their oracle
+  count passes the cutoffs; sampled keys sit in the bin of their signature;
+  bins are disjoint and ascending.
+"""
+import ctypes
+import os
+
+import numpy as np
+import pytest
+
+import oracle
+from paper_1407_1507_amd import synth
+
+pytestmark = pytest.mark.gpu
+
+THREADS = min(16, os.cpu_count() or 1)
+
+
+@pytest.fixture(scope="module")
+def kmc():
+    from paper_1407_1507_amd import kmc as m
+    m.lib()
+    return m
+
+
+@pytest.fixture(scope="module")
+def ctx(kmc):
+    c = kmc.Context(0)
+    yield c
+    c.close()
+
+
+def run_like_bench(ctx, kmc, seq, off, p):
+    """Device reads, device table (as bench.py), then the table copied back."""
+    import torch
+    dseq = torch.from_numpy(seq).to("cuda:0")
+    doff = torch.from_numpy(off.view(np.int64)).to("cuda:0")
+    t = ctx.count(dseq, doff, p["k"], p["p"], p["n_bins"], p["cutoff_min"], p["cutoff_max"],
+                  flags=kmc.FLAG_DEVICE_TABLE)
+    kw = t.key_words
+    keys = np.zeros(t.n * kw, dtype=np.uint64)
+    counts = np.zeros(t.n, dtype=np.uint32)
+    hip = ctypes.CDLL("libamdhip64.so")
+    if t.n:
+        assert hip.hipMemcpy(ctypes.c_void_p(keys.ctypes.data), ctypes.c_void_p(t.keys_ptr),
+                             ctypes.c_size_t(keys.nbytes), 2) == 0
+        assert hip.hipMemcpy(ctypes.c_void_p(counts.ctypes.data), ctypes.c_void_p(t.counts_ptr),
+                             ctypes.c_size_t(counts.nbytes), 2) == 0
+    stats, bo, s2b = t.stats, t.bin_offsets, t.sig_to_bin
+    t.free()
+    del dseq, doff
+    torch.cuda.empty_cache()
+    return (keys.reshape(-1, 2) if kw == 2 else keys), counts, bo, s2b, stats
+
+
+def check_bins(keys, bo, n):
+    assert bo[0] == 0 and bo[-1] == n and np.all(bo[1:] >= bo[:-1])
+    for b in range(len(bo) - 1):
+        seg = keys[bo[b]:bo[b + 1]]
+        if len(seg) > 1:
+            if seg.ndim == 2:
+                assert np.all((seg[1:, 0] > seg[:-1, 0]) |
+                              ((seg[1:, 0] == seg[:-1, 0]) & (seg[1:, 1] > seg[:-1, 1])))
+            else:
+                assert np.all(seg[1:] > seg[:-1])
+
+
+def ascending(keys):
+    return np.lexsort((keys[:, 1], keys[:, 0])) if keys.ndim == 2 else np.argsort(keys)
+
+
+@pytest.mark.timeout(600)
+def test_genome_full_size_exact(ctx, kmc):
+    seq, off, p = synth.make("genome-5M-2Mx100")
+    keys, counts, bo, s2b, st = run_like_bench(ctx, kmc, seq, off, p)
+    ok_keys, ok_counts = oracle.count(seq, off, p["k"], p["cutoff_min"], p["cutoff_max"],
+                                      threads=THREADS)
+    order = ascending(keys)
+    assert len(counts) == len(ok_counts)
+    assert np.array_equal(keys[order], ok_keys)
+    assert np.array_equal(counts[order], ok_counts)
+    check_bins(keys, bo, len(counts))
+    assert st["n_kmers"] == oracle.valid_windows(seq, off, p["k"])
+    # every entry in the bin of its signature (a sample of the 6M entries)
+    rng = np.random.default_rng(7)
+    idx = rng.choice(len(counts), 20000, replace=False)
+    bin_of = np.searchsorted(bo, idx, side="right") - 1
+    sig = oracle.key_signatures(keys[idx], p["k"], p["p"])
+    assert np.array_equal(s2b[sig], bin_of)
+
+
+def window_keys(seq, off, k, rng, n):
+    """Canonical keys of n random valid windows (Python integers -> words)."""
+    out = []
+    code = {65: 0, 67: 1, 71: 2, 84: 3, 97: 0, 99: 1, 103: 2, 116: 3}
+    n_reads = off.size - 1
+    while len(out) < n:
+        r = int(rng.integers(0, n_reads))
+        a, b = int(off[r]), int(off[r + 1])
+        if b - a < k:
+            continue
+        j = int(rng.integers(a, b - k + 1))
+        w = seq[j:j + k]
+        if not all(int(x) in code for x in w):
+            continue
+        f = 0
+        rc = 0
+        for t, x in enumerate(w):
+            c = code[int(x)]
+            f = f * 4 + c
+            rc += (3 - c) << (2 * t)
+        out.append(min(f, rc))
+    if k <= 32:
+        return np.array(out, dtype=np.uint64)
+    return np.array([[v >> 64, v & (2**64 - 1)] for v in out], dtype=np.uint64)
+
+
+def member(table_keys, order, q):
+    """Index of each query key in the table (or -1)."""
+    s = table_keys[order]
+    if s.ndim == 1:
+        pos = np.minimum(np.searchsorted(s, q), len(s) - 1)
+        return np.where(s[pos] == q, order[pos], -1)
+    hi, lo = np.ascontiguousarray(s[:, 0]), np.ascontiguousarray(s[:, 1])
+    a = np.searchsorted(hi, q[:, 0], side="left")
+    b = np.searchsorted(hi, q[:, 0], side="right")
+    res = np.full(len(q), -1, dtype=np.int64)
+    for i in range(len(q)):
+        j = a[i] + int(np.searchsorted(lo[a[i]:b[i]], q[i, 1]))
+        if j < b[i] and lo[j] == q[i, 1]:
+            res[i] = order[j]
+    return res
+
+
+@pytest.mark.timeout(900)
+def test_repeats_k55_full_size_properties(ctx, kmc):
+    seq, off, p = synth.make("repeats-50M-30x150-k55")
+    k, ci, cx = p["k"], p["cutoff_min"], p["cutoff_max"]
+    keys, counts, bo, s2b, st = run_like_bench(ctx, kmc, seq, off, p)
+    n = len(counts)
+    assert n == st["n_out"] and n > 1_000_000
+    check_bins(keys, bo, n)
+    assert st["n_kmers"] == oracle.valid_windows(seq, off, k)
+    assert np.all((counts >= ci) & (counts <= cx))
+    rng = np.random.default_rng(11)
+    # sampled table entries carry the oracle's count
+    idx = rng.choice(n, 20000, replace=False)
+    got = oracle.count_keys(seq, off, k, keys[idx], threads=THREADS)
+    assert np.array_equal(got, counts[idx].astype(np.uint64))
+    # sampled windows: in the table iff their count passes the cutoffs
+    q = window_keys(seq, off, k, rng, 4000)
+    qc = oracle.count_keys(seq, off, k, q, threads=THREADS)
+    order = ascending(keys)
+    pos = member(keys, order, q)
+    want = (qc >= ci) & (qc <= cx)
+    assert np.array_equal(pos >= 0, want)
+    assert np.array_equal(counts[pos[pos >= 0]].astype(np.uint64), qc[pos >= 0])
+    # sampled keys sit in the bin of their signature
+    bin_of = np.searchsorted(bo, idx[:5000], side="right") - 1
+    sig = oracle.key_signatures(keys[idx[:5000]], k, p["p"])
+    assert np.array_equal(s2b[sig], bin_of)

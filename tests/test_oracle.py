@@ -169,6 +169,31 @@ def test_brute_force(oracle_lib, k):
         assert flat == sorted(flat) and len(set(flat)) == len(flat)
 
 
+@pytest.mark.parametrize("k", [4, 21, 32, 33, 55, 64])
+def test_count_keys_brute_force(oracle_lib, k):
+    # occurrences of chosen keys, against the string-level brute force: keys
+    # present (several counts), keys absent, a repeated query key
+    rng = np.random.default_rng(300 + k)
+    reads = random_reads(rng, 50, 0, k + 40, n_rate=0.03, lower=0.05)
+    reads.append("ACGT" * 30)
+    seq, off = to_reads(reads)
+    full = brute_force(reads, k, 1, 2**32 - 1)
+    present = sorted(full)[:: max(1, len(full) // 40)]
+    absent = []
+    while len(absent) < 10:
+        s = "".join(rng.choice(list(_BASES), size=k))
+        key = key_of_full(s, k)
+        if key not in full:
+            absent.append(key)
+    query = present + absent + present[:3]
+    if k <= 32:
+        arr = np.array(query, dtype=np.uint64)
+    else:
+        arr = np.array([[q >> 64, q & (2**64 - 1)] for q in query], dtype=np.uint64)
+    got = oracle_lib.count_keys(seq, off, k, arr, threads=3)
+    assert [int(c) for c in got] == [full.get(q, 0) for q in query]
+
+
 @pytest.mark.parametrize("threads", [2, 5])
 def test_threaded_equals_single(oracle_lib, threads):
     seq, off, _ = synth.make("genome-5M-2Mx100", 0.002)
