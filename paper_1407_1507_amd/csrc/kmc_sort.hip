@@ -158,7 +158,11 @@ __device__ __forceinline__ uint32_t high_bit(u128 x) {
   return hi ? 127u - __clzll(hi) : 63u - __clzll((uint64_t)x);
 }
 
-// LDS carve-up of the tile sort.
+constexpr uint32_t kRankMax = 256;  // kept keys ordered by a rank sort, at most
+
+// LDS carve-up of the tile sort.  128-bit keys keep the hashed-bucket
+// counting path (mixed buckets, big-bucket list); 64-bit keys only take the
+// hash table and keep a small separate area for the kept keys instead.
 template <int KW>
 struct SortShared {
   typedef typename KeyOf<KW>::T K;
@@ -170,6 +174,15 @@ struct SortShared {
   uint32_t tmp[kSortThreads / 64];
   uint16_t big[kBigMax];
   uint32_t nbig;
+};
+template <>
+struct SortShared<1> {
+  uint64_t A[SortCfg<1>::CAP];      // hash table keys (~0: empty)
+  uint32_t H[SortCfg<1>::CAP + 1];  // hash table counters
+  uint64_t K2[kRankMax];            // kept keys of a tile, in read-back order
+  uint32_t C2[kRankMax];
+  uint64_t red[4 * kSortThreads / 64];
+  uint32_t tmp[kSortThreads / 64];
 };
 
 __device__ __forceinline__ uint32_t hash_top(uint64_t x, uint32_t t) {
@@ -286,8 +299,6 @@ __device__ __forceinline__ uint32_t count_tile(typename KeyOf<KW>::T (&key)[Sort
 // Kept keys (at most kRankMax of them) are put in key order by a rank sort:
 // each one counts the kept keys smaller than itself; more kept keys take the
 // digit-counting order of order_kept.
-constexpr uint32_t kRankMax = 256;
-
 template <bool kClean>
 __device__ __forceinline__ uint32_t count_tile_hash(uint64_t (&key)[SortCfg<1>::ITEMS], uint32_t n,
                                                     uint64_t* out_keys, uint32_t* out_counts,
@@ -344,50 +355,38 @@ __device__ __forceinline__ uint32_t count_tile_hash(uint64_t (&key)[SortCfg<1>::
       }
     }
   }
-  uint32_t H_total, kept;
-  (void)block_scan_one(nh, S.tmp, H_total);
-  *distinct = H_total;
-  const uint32_t kbase = block_scan_one(nk, S.tmp, kept);  // barrier: read-back is done
+  // distinct keys (high half) and kept keys (low half) in one scan; both
+  // are at most CAP, so the halves never carry into each other
+  uint32_t both;
+  const uint32_t pre = block_scan_one((nh << 16) | nk, S.tmp, both);  // read-back is done
+  *distinct = both >> 16;
+  const uint32_t kept = both & 0xFFFFu, kbase = pre & 0xFFFFu;
   if (kept == 0) return 0;
-  block_and_or<uint64_t>(a, o, S.red);
-  const uint64_t diff = a ^ o;
-  if (diff == 0) {
-#pragma unroll
-    for (uint32_t i = 0; i < ITEMS; ++i)
-      if (cnt[i]) {
-        out_keys[0] = key[i];
-        out_counts[0] = cnt[i];
-      }
-    __syncthreads();
-    return 1;
-  }
   if (kept <= kRankMax) {
+    // kept keys to their own small area (the table is already empty again),
+    // then every kept key's output slot is the number of smaller kept keys
     uint32_t at = kbase;
 #pragma unroll
     for (uint32_t i = 0; i < ITEMS; ++i) {
       if (cnt[i]) {
-        S.A[at] = key[i];
-        S.H[at] = cnt[i];
+        S.K2[at] = key[i];
+        S.C2[at] = cnt[i];
         ++at;
       }
     }
     __syncthreads();
     if (tid < kept) {
-      const uint64_t x = S.A[tid];
-      const uint32_t c = S.H[tid];
+      const uint64_t x = S.K2[tid];
       uint32_t r = 0;
-      for (uint32_t j = 0; j < kept; ++j) r += S.A[j] < x;
+      for (uint32_t j = 0; j < kept; ++j) r += S.K2[j] < x;
       out_keys[r] = x;
-      out_counts[r] = c;
+      out_counts[r] = S.C2[tid];
     }
-    __syncthreads();
-    if (tid < kept) {
-      S.A[tid] = EMPTY;
-      S.H[tid] = 0;
-    }
-    __syncthreads();
+    // K2 is written again only after the next tile's barriers
     return kept;
   }
+  block_and_or<uint64_t>(a, o, S.red);
+  const uint64_t diff = a ^ o;  // nonzero: more than one key is kept
   order_kept<1>(key, cnt, kbase, kept, diff, out_keys, out_counts, S.A, S.H, S.tmp);
   if (kClean) {
     // order_kept used A[0, kept) and H[0, max(kept, buckets)), buckets <= T
@@ -414,6 +413,7 @@ static_assert((1u << kHashBits2) == kHashSlots2 && kHashSlots2 == kTileCap2, "ta
 struct HashShared2 {
   uint64_t F[kHashSlots2];  // 0: empty; else fingerprint << 16 | count
   u128 K[kHashSlots2];      // the key of an occupied slot
+  uint32_t C2[kRankMax];    // counts of the kept keys (keys in K[0, kept))
   uint64_t red[4 * kSortThreads / 64];
   uint32_t tmp[kSortThreads / 64];
 };
@@ -492,54 +492,44 @@ __device__ uint32_t count_tile_hash2(u128 (&key)[SortCfg<2>::ITEMS], uint32_t n,
       }
     }
   }
-  uint32_t H_total, kept;
-  (void)block_scan_one(nh, S.tmp, H_total);
-  *distinct = H_total;
-  const uint32_t kbase = block_scan_one(nk, S.tmp, kept);  // barrier: read-back is done
+  // distinct keys (high half) and kept keys (low half) in one scan
+  uint32_t both;
+  const uint32_t pre = block_scan_one((nh << 16) | nk, S.tmp, both);  // read-back is done
+  *distinct = both >> 16;
+  const uint32_t kept = both & 0xFFFFu, kbase = pre & 0xFFFFu;
   if (kept == 0) return 0;
-  block_and_or<u128>(a, o, S.red);
-  const u128 diff = a ^ o;
-  if (diff == 0) {
-#pragma unroll
-    for (uint32_t i = 0; i < ITEMS; ++i)
-      if (cnt[i]) {
-        store_key(out_keys, 0, key[i]);
-        out_counts[0] = cnt[i];
-      }
-    __syncthreads();
-    return 1;
-  }
-  // kept keys are ordered in K (free now) with counts in F's words, which
-  // are cleared again afterwards
-  uint32_t* H = reinterpret_cast<uint32_t*>(S.F);
-  uint32_t dirty;
   if (kept <= kRankMax) {
+    // kept keys into K (free once read back), counts beside; each kept key's
+    // output slot is the number of smaller kept keys
     uint32_t at = kbase;
 #pragma unroll
     for (uint32_t i = 0; i < ITEMS; ++i) {
       if (cnt[i]) {
         S.K[at] = key[i];
-        H[at] = cnt[i];
+        S.C2[at] = cnt[i];
         ++at;
       }
     }
     __syncthreads();
     if (tid < kept) {
       const u128 x = S.K[tid];
-      const uint32_t c = H[tid];
       uint32_t r = 0;
       for (uint32_t j = 0; j < kept; ++j) r += S.K[j] < x;
       store_key(out_keys, r, x);
-      out_counts[r] = c;
+      out_counts[r] = S.C2[tid];
     }
-    __syncthreads();
-    dirty = kept;
-  } else {
-    order_kept<2>(key, cnt, kbase, kept, diff, out_keys, out_counts, S.K, H, S.tmp);
-    const uint32_t hb = high_bit(diff);
-    const uint32_t t2 = min(min(SortCfg<2>::DIG, bit_len(kept) + 1), hb + 1);
-    dirty = max(kept, 1u << t2);
+    __syncthreads();  // the next tile's inserts write K
+    return kept;
   }
+  block_and_or<u128>(a, o, S.red);
+  const u128 diff = a ^ o;  // nonzero: more than one key is kept
+  // kept keys are ordered in K with counts in F's words, which are cleared
+  // again afterwards
+  uint32_t* H = reinterpret_cast<uint32_t*>(S.F);
+  order_kept<2>(key, cnt, kbase, kept, diff, out_keys, out_counts, S.K, H, S.tmp);
+  const uint32_t hb = high_bit(diff);
+  const uint32_t t2 = min(min(SortCfg<2>::DIG, bit_len(kept) + 1), hb + 1);
+  const uint32_t dirty = max(kept, 1u << t2);
   for (uint32_t i = tid; i < (dirty + 1) / 2; i += nt) S.F[i] = 0;
   __syncthreads();
   return kept;
