@@ -495,18 +495,19 @@ void run_count(kmc_ctx* c, const kmc_reads* R, const kmc_params* P, kmc_table* T
   kc.k = J.k;
   kc.key_words = J.kw;
   kc.tile_cap = J.kw == 1 ? kTileCap1 : kTileCap2;
-  kc.tile_target = kc.tile_cap / 2;
+  kc.tile_limit = 3 * kc.tile_cap / 4;  // the largest tile the tile kernels count
   kc.n_bins = J.n_bins;
   kc.cutoff_min = J.ci;
   kc.cutoff_max = J.cx;
-  // fine ranges of about tile_target / 4 keys in the largest bin
-  uint32_t fb = ilog2_ceil(max_bin * 4 / kc.tile_target + 1);
+  // fine ranges of about tile_cap / 8 keys in the largest bin
+  uint32_t fb = ilog2_ceil(max_bin * 8 / kc.tile_cap + 1);
   fb = std::max<uint32_t>(1, std::min<uint32_t>({fb, (uint32_t)kMaxFineBits, 2 * J.k}));
   kc.fine_bits = fb;
   uint64_t n_tiles = 0, max_tiles = 0;
   for (uint32_t b = 0; b < J.n_bins; ++b) {
     tile_base[b] = n_tiles;
-    const uint64_t nt = kmer_cnt[b] ? (kmer_cnt[b] - 1) / kc.tile_target + 1 : 0;
+    // greedy packing: two consecutive tiles hold more than tile_limit keys
+    const uint64_t nt = kmer_cnt[b] ? 2 * ((kmer_cnt[b] - 1) / kc.tile_limit + 1) + 1 : 0;
     n_tiles += nt;
     max_tiles = std::max(max_tiles, nt);
   }
@@ -669,8 +670,8 @@ WsLayout plan_workspace(const kmc_reads* R, const kmc_params* P) {
   const uint64_t n_sig = (1ull << (2 * P->p)) + 1;
   const uint64_t kmax = N;
   const uint64_t recmax = kmax + 256 * NB;
-  const uint64_t target = (kw == 1 ? kTileCap1 : kTileCap2) / 2;
-  const uint64_t tmax = kmax / target + NB + 1;
+  const uint64_t cap = kw == 1 ? kTileCap1 : kTileCap2, limit = 3 * cap / 4;
+  const uint64_t tmax = 2 * (kmax / limit) + 3 * NB + 1;
   const uint64_t tasks = recmax / kExpandThreads + NB + 1;
   uint64_t sz[B_COUNT_] = {};
   sz[B_SEQ] = R->on_device ? 0 : N + 16;
@@ -682,7 +683,7 @@ WsLayout plan_workspace(const kmc_reads* R, const kmc_params* P) {
   sz[B_REC] = recmax * RW * 8;
   // fine bits as the tile plan picks them, for a bin holding every k-mer
   const uint32_t fb = std::max<uint32_t>(
-      1, std::min<uint32_t>({ilog2_ceil(kmax * 4 / target + 1), (uint32_t)kMaxFineBits, 2 * P->k}));
+      1, std::min<uint32_t>({ilog2_ceil(kmax * 8 / cap + 1), (uint32_t)kMaxFineBits, 2 * P->k}));
   sz[B_FINE] = (NB << fb) * 4;
   sz[B_TOF] = (NB << fb) * 2;
   sz[B_TILES] = tmax * sizeof(Tile);

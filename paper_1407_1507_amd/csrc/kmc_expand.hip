@@ -7,8 +7,8 @@
 // the k-mer and its reverse complement, "Minimizers of k-mers") and the keys
 // are radix sorted.  Here the most significant digit pass of that radix sort
 // runs through HBM: each bin's keys are split by their top `fine_bits` bits
-// into fine ranges, consecutive fine ranges are grouped into tiles of about
-// `tile_target` keys, and every key is written to its tile.  A tile is thus a
+// into fine ranges, consecutive fine ranges are packed into tiles of at most
+// `tile_limit` keys, and every key is written to its tile.  A tile is thus a
 // contiguous key range of one bin, and tiles of a bin are in key order.
 //
 // Record layout (written by the split kernels): forward key of the first
@@ -105,49 +105,70 @@ k_fine_hist(KeyCfg kc, TaskMap tm, const uint64_t* __restrict__ records, uint32_
 }
 
 // -------------------------------------------------------------- plan tiles
-// One workgroup per bin.  Fine range r starting at key s_r (exclusive prefix
-// of the bin's histogram) goes to tile floor(s_r / tile_target); a tile thus
-// holds at most tile_target + (size of its last range) keys.  Tile indices a
-// large range jumps over stay empty (the tile array is zeroed beforehand).
+// One workgroup per bin.  Consecutive fine ranges are packed greedily into
+// tiles of at most tile_limit keys: a tile is closed when the next range would
+// take it past the limit (a range larger than the limit is a tile of its own).
+// Two consecutive tiles then hold more than tile_limit keys together, so a bin
+// of T keys needs at most 2 * ceil(T / tile_limit) + 1 tiles; slots beyond
+// the ones used stay empty (the tile array is zeroed beforehand).
+//
+// In parallel: for every range r, nxt[r] = the range that would start the next
+// tile if a tile started at r (a binary search over the prefix sums); one
+// thread then follows the chain from range 0 (one step per tile), and the
+// tiles are written in parallel.
 __global__ void __launch_bounds__(256)
 k_plan_tiles(KeyCfg kc, const uint32_t* __restrict__ fine_hist, const uint64_t* __restrict__ key_base,
              const uint64_t* __restrict__ tile_base, uint16_t* tile_of_fine, Tile* tiles,
              unsigned long long* tile_cursor) {
   extern __shared__ uint32_t lds[];
   const uint32_t nf = 1u << kc.fine_bits;
-  uint32_t* start = lds;              // nf + 1
-  uint32_t* first = lds + nf + 1;     // max tiles of a bin: first key of each tile
-  uint32_t* tmp = first + kMaxTilesPerBin;
-  const uint32_t b = blockIdx.x;
+  uint32_t* start = lds;                                          // nf + 1
+  uint16_t* nxt = reinterpret_cast<uint16_t*>(start + nf + 1);    // nf (+1 spare)
+  uint16_t* chain = nxt + nf + 2;                                 // tile starts, <= nf + 1
+  uint32_t* tmp = reinterpret_cast<uint32_t*>(chain + nf + 2);    // scan tmp, tile count
+  const uint32_t b = blockIdx.x, tid = threadIdx.x, nt = blockDim.x;
   const uint32_t* h = fine_hist + ((uint64_t)b << kc.fine_bits);
-  for (uint32_t i = threadIdx.x; i < nf; i += blockDim.x) start[i] = h[i];
+  for (uint32_t i = tid; i < nf; i += nt) start[i] = h[i];
   __syncthreads();
   const uint32_t total = block_exclusive_scan(start, nf, tmp);
-  if (threadIdx.x == 0) start[nf] = total;
+  if (tid == 0) start[nf] = total;
   __syncthreads();
   if (total == 0) return;  // empty bin: no tiles
-  const uint64_t kb = key_base[b], tb = tile_base[b];
-  uint16_t* tof = tile_of_fine + ((uint64_t)b << kc.fine_bits);
-  // empty ranges after the last key start at `total`: clamp them into the
-  // last tile so that t < ceil(total / tile_target) always
-  const uint32_t last = total - 1;
-  for (uint32_t r = threadIdx.x; r < nf; r += blockDim.x) {
-    const uint32_t t = min(start[r], last) / kc.tile_target;
-    tof[r] = (uint16_t)t;
-    if (r == 0 || min(start[r - 1], last) / kc.tile_target != t) first[t] = start[r];
+  const uint32_t lim = kc.tile_limit;
+  for (uint32_t r = tid; r < nf; r += nt) {
+    const uint32_t s0 = start[r];
+    // q1: the smallest q > r with start[q + 1] > s0 + lim (nf if none)
+    uint32_t lo = r + 1, hi = nf;  // answer in [lo, hi]
+    while (lo < hi) {
+      const uint32_t mid = (lo + hi) >> 1;
+      if (start[mid + 1] > s0 + lim) hi = mid;
+      else lo = mid + 1;
+    }
+    uint32_t q = lo;
+    // a tile still empty at q1 takes range q1 too (a range over the limit)
+    if (q < nf && start[q] == s0) ++q;
+    nxt[r] = (uint16_t)min(q, nf);
   }
   __syncthreads();
-  for (uint32_t r = threadIdx.x; r < nf; r += blockDim.x) {
-    const uint32_t t = min(start[r], last) / kc.tile_target;
-    if (r == nf - 1 || min(start[r + 1], last) / kc.tile_target != t) {
-      const uint32_t end = start[r + 1];
-      Tile T;
-      T.begin = kb + first[t];
-      T.size = end - first[t];
-      T.bin = b;
-      tiles[tb + t] = T;
-      tile_cursor[tb + t] = T.begin;
+  if (tid == 0) {
+    uint32_t c = 0, t = 0;
+    while (c < nf) {
+      chain[t++] = (uint16_t)c;
+      c = nxt[c];
     }
+    chain[t] = (uint16_t)nf;
+    tmp[0] = t;
+  }
+  __syncthreads();
+  const uint32_t n_used = tmp[0];
+  const uint64_t kb = key_base[b], tb = tile_base[b];
+  uint16_t* tof = tile_of_fine + ((uint64_t)b << kc.fine_bits);
+  for (uint32_t t = tid; t < n_used; t += nt) {
+    const uint32_t r0 = chain[t], r1 = chain[t + 1];
+    const uint32_t first = start[r0];
+    tiles[tb + t] = Tile{kb + first, start[r1] - first, b};
+    tile_cursor[tb + t] = kb + first;
+    for (uint32_t r = r0; r < r1; ++r) tof[r] = (uint16_t)t;
   }
 }
 
@@ -249,7 +270,7 @@ hipError_t launch_plan_tiles(hipStream_t s, const KeyCfg& kc, const uint32_t* fi
                              uint16_t* tile_of_fine, Tile* tiles,
                              unsigned long long* tile_cursor) {
   const uint32_t nf = 1u << kc.fine_bits;
-  const size_t sh = ((size_t)nf + 1 + kMaxTilesPerBin + 8) * 4;
+  const size_t sh = ((size_t)nf + 1) * 4 + ((size_t)nf + 2) * 2 * 2 + 16 * 4;
   hipLaunchKernelGGL(k_plan_tiles, dim3(kc.n_bins), dim3(256), sh, s, kc, fine_hist, key_base,
                      tile_base, tile_of_fine, tiles, tile_cursor);
   return hipGetLastError();

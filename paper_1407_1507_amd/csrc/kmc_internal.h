@@ -102,7 +102,7 @@ struct KeyCfg {
   uint32_t k;
   uint32_t key_words;
   uint32_t fine_bits;   // fine ranges per bin = 2^fine_bits (top bits of the key)
-  uint32_t tile_target; // tiles are planned to hold about this many keys
+  uint32_t tile_limit;  // tiles are packed up to this many keys
   uint32_t tile_cap;    // keys one LDS tile can hold
   uint32_t n_bins;
   uint32_t cutoff_min, cutoff_max;
