@@ -65,6 +65,57 @@ __device__ __forceinline__ uint32_t top_bits(u128 key, uint32_t k, uint32_t bits
   return (uint32_t)(key >> (2 * k - bits));
 }
 
+// ------------------------------------------------------------ round staging
+// A super k-mer holds 1 .. w k-mers, so with one record per lane a wavefront
+// runs as long as its longest record.  Each round of up to 256 records is
+// therefore staged in LDS and ranked by k-mer count, longest first (a
+// counting sort on the count byte): slot s of the round is the s-th longest
+// record, and each wavefront walks records of similar length.
+template <int KW>
+struct RoundLds {
+  uint64_t w[kExpandThreads * 2 * KW];  // the round's records, as stored
+  uint32_t hist[64];                     // count buckets, then their offsets
+  uint8_t perm[kExpandThreads];          // slot -> record of the round
+};
+
+// Stage records rp[0 .. nr) (nr <= blockDim.x = kExpandThreads); all threads
+// call it.  On return slot t's record is L.w + L.perm[t] * 2 * KW.
+template <int KW>
+__device__ __forceinline__ void stage_round(const uint64_t* __restrict__ rp, uint32_t nr,
+                                            RoundLds<KW>& L) {
+  const uint32_t t = threadIdx.x;
+  if (t < 64) L.hist[t] = 0;
+  __syncthreads();  // the previous round's slots are done with w and perm
+  uint32_t bucket = 0, rank = 0;
+  if (t < nr) {
+    const uint4* src = reinterpret_cast<const uint4*>(rp + (size_t)t * 2 * KW);
+    uint4* dst = reinterpret_cast<uint4*>(L.w + (size_t)t * 2 * KW);
+    uint4 last;
+#pragma unroll
+    for (int i = 0; i < KW; ++i) {
+      last = src[i];
+      dst[i] = last;
+    }
+    const uint32_t n = last.z & 0xFFu;  // count byte: low byte of the last word
+    bucket = 63u - (n < 63u ? n : 63u);
+    rank = atomicAdd(&L.hist[bucket], 1u);
+  }
+  __syncthreads();
+  if (t < 64) {
+    const uint32_t v = L.hist[t];
+    uint32_t incl = v;
+#pragma unroll
+    for (uint32_t d = 1; d < 64; d <<= 1) {
+      const uint32_t u = __shfl_up(incl, d, 64);
+      if (t >= d) incl += u;
+    }
+    L.hist[t] = incl - v;
+  }
+  __syncthreads();
+  if (t < nr) L.perm[L.hist[bucket] + rank] = (uint8_t)t;
+  __syncthreads();
+}
+
 // --------------------------------------------------------------- fine hist
 // One workgroup per task (a run of records of one bin); the task's keys are
 // counted per fine range in LDS, then added to the bin's global histogram.
@@ -80,17 +131,19 @@ template <int KW>
 __global__ void __launch_bounds__(kExpandThreads)
 k_fine_hist(KeyCfg kc, TaskMap tm, const uint64_t* __restrict__ records, uint32_t* fine_hist) {
   typedef typename KeyOf<KW>::T K;
-  extern __shared__ uint32_t fh[];
+  extern __shared__ __attribute__((aligned(16))) uint64_t lds64[];
+  RoundLds<KW>& L = *reinterpret_cast<RoundLds<KW>*>(lds64);
+  uint32_t* fh = reinterpret_cast<uint32_t*>(&L + 1);
   const uint32_t nf = 1u << kc.fine_bits;
   for (uint32_t i = threadIdx.x; i < nf; i += blockDim.x) fh[i] = 0;
-  __syncthreads();
   const ExpandTask tk = tm.get(blockIdx.x);
   const K kmask = key_mask<K>(kc.k);
-  for (uint32_t r0 = 0; r0 < tk.n_rec; r0 += blockDim.x) {
-    const uint32_t r = r0 + threadIdx.x;
-    if (r < tk.n_rec) {
+  for (uint32_t r0 = 0; r0 < tk.n_rec; r0 += kExpandThreads) {
+    const uint32_t nr = min(tk.n_rec - r0, (uint32_t)kExpandThreads);
+    stage_round<KW>(records + (tk.rec_begin + r0) * (2 * KW), nr, L);
+    if (threadIdx.x < nr) {
       Rec<KW> rec;
-      rec.load(records + (tk.rec_begin + r) * (2 * KW), kc.k);
+      rec.load(L.w + (uint32_t)L.perm[threadIdx.x] * (2 * KW), kc.k);
       for (uint32_t i = 0;; ++i) {
         atomicAdd(&fh[top_bits(rec.key(), kc.k, kc.fine_bits)], 1u);
         if (i + 1 >= rec.n) break;
@@ -188,25 +241,27 @@ k_expand_scatter(KeyCfg kc, TaskMap tm,
   typedef typename KeyOf<KW>::T K;
   extern __shared__ __attribute__((aligned(16))) uint64_t lds64[];
   const uint32_t nf = 1u << kc.fine_bits;
-  // layout: delta u64[mt] | cnt u32[mt] | tof u16[nf] | scan tmp
-  uint64_t* delta = lds64;
+  // layout: round records | delta u64[mt] | cnt u32[mt] | tof u16[nf]
+  RoundLds<KW>& L = *reinterpret_cast<RoundLds<KW>*>(lds64);
+  uint64_t* delta = reinterpret_cast<uint64_t*>(&L + 1);
   uint32_t* cnt = reinterpret_cast<uint32_t*>(delta + mt);
   uint16_t* tof = reinterpret_cast<uint16_t*>(cnt + mt);
-  uint32_t* tmp = reinterpret_cast<uint32_t*>(tof + nf + (nf & 1));
 
-  const ExpandTask tk = tm.get(blockIdx.x);
+  const ExpandTask tk = tm.get(blockIdx.x);  // n_rec <= kExpandThreads: one round
   const uint16_t* gt = tile_of_fine + ((uint64_t)tk.bin << kc.fine_bits);
   for (uint32_t i = threadIdx.x; i < nf; i += blockDim.x) tof[i] = gt[i];
-  for (uint32_t i = threadIdx.x; i < mt; i += blockDim.x) cnt[i] = 0;
   const uint64_t tb = tile_base[tk.bin];
+  const uint32_t nt = (uint32_t)(tile_base[tk.bin + 1] - tb);  // <= mt
+  for (uint32_t i = threadIdx.x; i < nt; i += blockDim.x) cnt[i] = 0;
   const K kmask = key_mask<K>(kc.k);
+  stage_round<KW>(records + tk.rec_begin * (2 * KW), tk.n_rec, L);
   const bool active = threadIdx.x < tk.n_rec;
-  const uint64_t* rp = records + (tk.rec_begin + threadIdx.x) * (2 * KW);
-  __syncthreads();
+  const uint64_t* my = L.w + (uint32_t)L.perm[threadIdx.x] * (2 * KW);
 
+  // walk 1: keys per tile
   if (active) {
     Rec<KW> rec;
-    rec.load(rp, kc.k);
+    rec.load(my, kc.k);
     for (uint32_t i = 0;; ++i) {
       atomicAdd(&cnt[tof[top_bits(rec.key(), kc.k, kc.fine_bits)]], 1u);
       if (i + 1 >= rec.n) break;
@@ -215,15 +270,16 @@ k_expand_scatter(KeyCfg kc, TaskMap tm,
   }
   __syncthreads();
   // reserve each tile's range; cnt then becomes the running slot
-  for (uint32_t i = threadIdx.x; i < mt; i += blockDim.x) {
+  for (uint32_t i = threadIdx.x; i < nt; i += blockDim.x) {
     const uint32_t c = cnt[i];
     if (c) delta[i] = atomicAdd(&tile_cursor[tb + i], (unsigned long long)c);
     cnt[i] = 0;
   }
   __syncthreads();
+  // walk 2: the same keys again, each written to its tile
   if (active) {
     Rec<KW> rec;
-    rec.load(rp, kc.k);
+    rec.load(my, kc.k);
     for (uint32_t i = 0;; ++i) {
       const K key = rec.key();
       const uint32_t t = tof[top_bits(key, kc.k, kc.fine_bits)];
@@ -242,8 +298,11 @@ k_expand_scatter(KeyCfg kc, TaskMap tm,
 
 }  // namespace
 
-static size_t expand_lds(uint32_t mt, uint32_t nf) {
-  return (size_t)mt * 12 + (size_t)nf * 2 + 4 + 16;
+static size_t round_lds(int kw) {
+  return kw == 1 ? sizeof(RoundLds<1>) : sizeof(RoundLds<2>);
+}
+static size_t expand_lds(int kw, uint32_t mt, uint32_t nf) {
+  return round_lds(kw) + (size_t)mt * 12 + (size_t)nf * 2;
 }
 
 hipError_t launch_task_bins(hipStream_t s, uint32_t n_bins, const uint64_t* pre_a,
@@ -255,7 +314,7 @@ hipError_t launch_task_bins(hipStream_t s, uint32_t n_bins, const uint64_t* pre_
 hipError_t launch_fine_hist(hipStream_t s, const KeyCfg& kc, const TaskMap& tm,
                             uint32_t n_tasks, const uint64_t* records, uint32_t* fine_hist) {
   if (n_tasks == 0) return hipSuccess;
-  const size_t sh = ((size_t)1 << kc.fine_bits) * 4;
+  const size_t sh = round_lds(kc.key_words) + ((size_t)1 << kc.fine_bits) * 4;
   if (kc.key_words == 1)
     hipLaunchKernelGGL(k_fine_hist<1>, dim3(n_tasks), dim3(kExpandThreads), sh, s, kc, tm,
                        records, fine_hist);
@@ -284,7 +343,7 @@ hipError_t launch_expand_scatter(hipStream_t s, const KeyCfg& kc, const TaskMap&
   if (n_tasks == 0) return hipSuccess;
   const uint32_t nf = 1u << kc.fine_bits;
   const uint32_t mt = max_tiles_per_bin < 1 ? 1 : max_tiles_per_bin;
-  const size_t sh = expand_lds(mt, nf);
+  const size_t sh = expand_lds(kc.key_words, mt, nf);
   if (kc.key_words == 1) {
     (void)hipFuncSetAttribute((const void*)k_expand_scatter<1>,
                         hipFuncAttributeMaxDynamicSharedMemorySize, (int)sh);

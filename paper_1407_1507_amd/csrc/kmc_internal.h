@@ -10,7 +10,7 @@
 namespace kmc {
 
 // Sizes of the work units.
-constexpr int kExpandThreads = 256;      // records per expansion task (one per thread)
+constexpr int kExpandThreads = 256;      // threads of the expansion kernels: records per round
 constexpr int kSortThreads = 256;        // threads of a tile-sort workgroup
 constexpr int kTileCap1 = 4096;          // keys of one LDS tile (1-word keys)
 constexpr int kTileCap2 = 2048;          // same, 2-word keys
@@ -124,6 +124,7 @@ hipError_t launch_plan_tiles(hipStream_t s, const KeyCfg& kc, const uint32_t* fi
                              unsigned long long* tile_cursor);
 
 // Expand every record into canonical keys and scatter them into their tiles.
+// Tasks hold at most kExpandThreads records.
 hipError_t launch_expand_scatter(hipStream_t s, const KeyCfg& kc, const TaskMap& tm,
                                  uint32_t n_tasks, const uint64_t* records,
                                  const uint16_t* tile_of_fine, const uint64_t* tile_base,
