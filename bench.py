@@ -51,19 +51,30 @@ def kernel_bytes(name: str, st: dict, k: int) -> int:
     }.get(name, 0)
 
 
-KERNEL_SOURCE = {  # the source file of each timed kernel (for staleness of traffic counters)
-    "split": "kmc_split.hip", "sig_hist": "kmc_split.hip", "fine_hist": "kmc_expand.hip",
-    "plan_tiles": "kmc_expand.hip", "expand_scatter": "kmc_expand.hip",
-    "tile_sort": "kmc_sort.hip", "big_tiles": "kmc_sort.hip", "assemble": "kmc_sort.hip",
+# the source files of each timed kernel (for staleness of traffic counters):
+# its own file(s) and the shared device headers
+_SHARED = ("kmc_device.h", "kmc_internal.h")
+KERNEL_SOURCE = {
+    "split": ("kmc_split.hip", "kmc_scan_wide.hip"), "sig_hist": ("kmc_split.hip",),
+    "fine_hist": ("kmc_expand.hip",), "plan_tiles": ("kmc_expand.hip",),
+    "expand_scatter": ("kmc_expand.hip",), "tile_sort": ("kmc_sort.hip",),
+    "big_tiles": ("kmc_sort.hip",), "assemble": ("kmc_sort.hip",),
 }
 
 
 def source_digest(kernel: str) -> str:
+    """First 16 hex digits of the SHA-256 of the kernel's source files."""
     import hashlib
-    path = os.path.join(ROOT, "paper_1407_1507_amd", "csrc", KERNEL_SOURCE.get(kernel, ""))
-    if not os.path.isfile(path):
+    files = KERNEL_SOURCE.get(kernel)
+    if not files:
         return ""
-    return hashlib.sha256(open(path, "rb").read()).hexdigest()[:16]
+    h = hashlib.sha256()
+    for f in files + _SHARED:
+        path = os.path.join(ROOT, "paper_1407_1507_amd", "csrc", f)
+        if not os.path.isfile(path):
+            return ""
+        h.update(open(path, "rb").read())
+    return h.hexdigest()[:16]
 
 
 def measured_traffic(kernel: str, workload: str):
