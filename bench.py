@@ -302,6 +302,8 @@ def main():
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--workload", default="genome-5M-2Mx100")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--order", choices=["bin", "ascending"], default="bin",
+                    help="table order: grouped by bin, or ascending over the whole table")
     ap.add_argument("--copy-calibration", type=int, default=0,
                     help="only run a device copy of this many bytes (counter calibration)")
     args = ap.parse_args()
@@ -326,8 +328,9 @@ def main():
     doff = torch.from_numpy(off.view(np.int64)).to("cuda:0")
     torch.cuda.synchronize()
     ctx = kmc.Context(0)
+    flags = kmc.FLAG_DEVICE_TABLE | (kmc.FLAG_ASCENDING if args.order == "ascending" else 0)
     run = lambda: ctx.count(dseq, doff, p["k"], p["p"], p["n_bins"], p["cutoff_min"],
-                            p["cutoff_max"], flags=kmc.FLAG_DEVICE_TABLE)
+                            p["cutoff_max"], flags=flags)
     for _ in range(args.warmup):
         run().free()
     torch.cuda.synchronize()
@@ -369,7 +372,8 @@ def main():
         "config": {"workload": f"{args.workload}: {DESCRIPTION.get(args.workload, '')}",
                    "k": p["k"], "p": p["p"], "n_bins": p["n_bins"],
                    "cutoff_min": p["cutoff_min"], "cutoff_max": p["cutoff_max"],
-                   "n_reads": int(off.size - 1), "n_bases": int(n_bases)},
+                   "n_reads": int(off.size - 1), "n_bases": int(n_bases),
+                   "order": args.order},
         "kmers_per_s": n_kmers / (ms * 1e-3),
         "hbm_gbs_alg": st["bytes_alg"] / (ms * 1e-3) / 1e9,
         "device_ms": dev_us * 1e-3,

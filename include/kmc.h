@@ -85,6 +85,9 @@ typedef struct kmc_params {
 /* Plain canonical minimizers instead of signatures (no AAA/ACA/AA filter;
  * Methods, "Minimizers of k-mers").  Changes only the bins, never the counts. */
 #define KMC_FLAG_PLAIN_MINIMIZERS 0x2u
+/* Entries in ascending key order over the whole table instead of grouped by
+ * bin (then kmc_table.bin_offsets is NULL).  Same entries either way. */
+#define KMC_FLAG_ASCENDING 0x4u
 
 /* Kernels timed in kmc_stats.us_kernel. */
 enum {
@@ -127,12 +130,15 @@ typedef struct kmc_stats {
 /* Result of a count.  Entries are grouped by bin (bin b holds entries
  * [bin_offsets[b], bin_offsets[b+1])), the order of the paper's database
  * (signature, then k-mer; supplement, database format), and ascending by key
- * inside each bin.  Bins hold disjoint key sets.
+ * inside each bin.  Bins hold disjoint key sets.  With KMC_FLAG_ASCENDING the
+ * entries are in ascending key order over the whole table and bin_offsets is
+ * NULL.
  *   keys        n * key_words uint64; for key_words == 2 each key is stored
  *               hi word first, then lo word; the hi word holds the top
  *               2k - 64 bits;
  *   counts      n exact uint32 counts (no saturation);
- *   bin_offsets n_bins + 1 uint64 (always host memory);
+ *   bin_offsets n_bins + 1 uint64 (always host memory; NULL in ascending
+ *               order);
  *   sig_to_bin  4^p + 1 uint32: bin of every signature value; the last entry
  *               is for k-mers with no allowed p-mer (always host memory).
  * keys/counts are host memory unless on_device = 1.  reserved records how

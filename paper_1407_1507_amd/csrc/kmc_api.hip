@@ -27,7 +27,7 @@ namespace {
 enum BufId {
   B_SEQ, B_OFF, B_HIST, B_MAP, B_BINCNT, B_CURSOR, B_REC, B_FINE, B_TOF, B_TILES, B_TCUR,
   B_BASES, B_HTASK, B_ETASK, B_KEYS, B_COUNTS, B_TILEOUT, B_BIG, B_MISC, B_TMP, B_SCANTMP,
-  B_TILEOFF, B_BINOFF, B_OUTK, B_OUTC, B_DBG1, B_DBG2, B_COUNT_
+  B_TILEOFF, B_BINOFF, B_OUTK, B_OUTC, B_DBG1, B_DBG2, B_ASCSEG, B_ASCK, B_ASCC, B_COUNT_
 };
 
 struct DevBuf {
@@ -304,7 +304,8 @@ kmc_status validate(const kmc_reads* reads, const kmc_params* P) {
   const uint64_t n_sig = (1ull << (2 * P->p)) + 1;
   if (P->n_bins < 1 || P->n_bins > 65535 || P->n_bins > n_sig) return KMC_ERR_INVALID_ARG;
   if (P->cutoff_min > P->cutoff_max) return KMC_ERR_INVALID_ARG;
-  if (P->flags & ~(KMC_FLAG_DEVICE_TABLE | KMC_FLAG_PLAIN_MINIMIZERS)) return KMC_ERR_INVALID_ARG;
+  if (P->flags & ~(KMC_FLAG_DEVICE_TABLE | KMC_FLAG_PLAIN_MINIMIZERS | KMC_FLAG_ASCENDING))
+    return KMC_ERR_INVALID_ARG;
   if (reads->n_reads > 0 && (!reads->seq && reads->n_bases > 0)) return KMC_ERR_INVALID_ARG;
   if (reads->n_reads > 0 && !reads->offsets) return KMC_ERR_INVALID_ARG;
   if (reads->n_reads >= (1ull << 40) || reads->n_bases >= (1ull << 46)) return KMC_ERR_TOO_LARGE;
@@ -631,6 +632,27 @@ void run_count(kmc_ctx* c, const kmc_reads* R, const kmc_params* P, kmc_table* T
   }
   check(c, hipEventRecord(c->ev[28], s), "event");
   check(c, launch_gather(s, kc, tiles, n_tiles, tile_off, keys, counts, out_k, out_c), "gather");
+  if (J.flags & KMC_FLAG_ASCENDING) {
+    // ascending over the whole table: segments by top key bits into a
+    // scratch copy, groups ordered in LDS back into the table
+    std::free(T->bin_offsets);
+    T->bin_offsets = nullptr;
+    if (n_out) {
+      const AscPlan ap = plan_ascending(n_out, J.k, J.kw);
+      const uint64_t nseg = 1ull << ap.seg_bits;
+      auto al = [](uint64_t x) { return (x + 255) & ~(uint64_t)255; };
+      const uint64_t o1 = al(nseg * 4), o2 = o1 + al((nseg + 1) * 8),
+                     o3 = o2 + al(scan_tmp_words(nseg) * 8), o4 = o3 + (ap.n_groups + 1) * 8;
+      uint8_t* sb = ensure<uint8_t>(c, B_ASCSEG, o4);
+      uint64_t* xk = ensure<uint64_t>(c, B_ASCK, n_out * J.kw * 8);
+      uint32_t* xc = ensure<uint32_t>(c, B_ASCC, n_out * 4);
+      check(c, launch_ascending(s, kc, n_out, ap, reinterpret_cast<uint32_t*>(sb),
+                                reinterpret_cast<uint64_t*>(sb + o1),
+                                reinterpret_cast<uint64_t*>(sb + o2),
+                                reinterpret_cast<uint64_t*>(sb + o3), xk, xc, out_k, out_c),
+            "ascending");
+    }
+  }
   check(c, hipEventRecord(c->ev[29], s), "event");
   check(c, hipEventRecord(c->ev[5], s), "event");
   if (!T->on_device) {
@@ -704,12 +726,25 @@ WsLayout plan_workspace(const kmc_reads* R, const kmc_params* P) {
   sz[B_OUTC] = kmax * 4;
   sz[B_DBG1] = (tmax + 1) * 8;
   sz[B_DBG2] = 0;
+  if (P->flags & KMC_FLAG_ASCENDING) {
+    // ascending order: segment counters, offsets, scan scratch, group starts
+    // (the plan for kmax entries has the most segments and groups), and a
+    // scratch copy of the table
+    const AscPlan ap = plan_ascending(kmax, P->k, (uint32_t)kw);
+    const uint64_t nseg = 1ull << ap.seg_bits;
+    sz[B_ASCSEG] = nseg * 4 + (nseg + 1) * 8 + scan_tmp_words(nseg) * 8 + (ap.n_groups + 1) * 8 +
+                   4 * 256;
+    sz[B_ASCK] = kmax * kw * 8;
+    sz[B_ASCC] = kmax * 4;
+  }
   // records are dead once the keys are expanded: the big-tile scratch and,
   // after it, the assembled table reuse their region
   auto al = [](uint64_t x) { return (x + 255) & ~(uint64_t)255; };
   const uint64_t alias_tmp = sz[B_TMP], alias_k = sz[B_OUTK], alias_c = sz[B_OUTC];
-  sz[B_TMP] = sz[B_OUTK] = sz[B_OUTC] = 0;
-  sz[B_REC] = std::max<uint64_t>({sz[B_REC], alias_tmp, al(alias_k) + alias_c});
+  const uint64_t alias_xk = sz[B_ASCK], alias_xc = sz[B_ASCC];
+  sz[B_TMP] = sz[B_OUTK] = sz[B_OUTC] = sz[B_ASCK] = sz[B_ASCC] = 0;
+  sz[B_REC] = std::max<uint64_t>(
+      {sz[B_REC], alias_tmp, al(alias_k) + al(alias_c) + al(alias_xk) + alias_xc});
   size_t at = 0;
   for (int i = 0; i < B_COUNT_; ++i) {
     L.off[i] = at;
@@ -722,6 +757,12 @@ WsLayout plan_workspace(const kmc_reads* R, const kmc_params* P) {
   L.size[B_OUTK] = alias_k;
   L.off[B_OUTC] = L.off[B_REC] + al(alias_k);
   L.size[B_OUTC] = alias_c;
+  // the ascending order's scratch copy follows the table (the big-tile
+  // scratch is dead by then)
+  L.off[B_ASCK] = L.off[B_OUTC] + al(alias_c);
+  L.size[B_ASCK] = alias_xk;
+  L.off[B_ASCC] = L.off[B_ASCK] + al(alias_xk);
+  L.size[B_ASCC] = alias_xc;
   L.total = at;
   return L;
 }

@@ -163,6 +163,28 @@ hipError_t launch_gather(hipStream_t s, const KeyCfg& kc, const Tile* tiles, uin
                          const uint64_t* tile_off, const uint64_t* keys,
                          const uint32_t* counts, uint64_t* out_keys, uint32_t* out_counts);
 
+// Global ascending order of the kept entries (instead of bin-major): entries
+// are partitioned by their top seg_bits key bits into segments, segments are
+// packed into groups starting at the first segment at or above each multiple
+// of `group` entries, and each group is put in order.
+struct AscPlan {
+  uint32_t seg_bits;  // segments: 2^seg_bits (at most kMaxSegBits)
+  uint64_t group;     // group stride in entries (CAP / 2 of the key width)
+  uint64_t n_groups;  // ceil(n_out / group)
+};
+constexpr uint32_t kMaxSegBits = 20;
+// Plan for n_out entries of keys of 2k bits.
+AscPlan plan_ascending(uint64_t n_out, uint32_t k, uint32_t key_words);
+// The bin-major table (table_keys / table_counts, n_out entries) put in
+// ascending order in place.  seg_cnt: u32[2^seg_bits]; seg_start:
+// u64[2^seg_bits + 1]; scan_tmp: scan_tmp_words(2^seg_bits); lo:
+// u64[n_groups + 1]; xk / xc: scratch of n_out entries (not aliasing the
+// table).
+hipError_t launch_ascending(hipStream_t s, const KeyCfg& kc, uint64_t n_out, const AscPlan& ap,
+                            uint32_t* seg_cnt, uint64_t* seg_start, uint64_t* scan_tmp,
+                            uint64_t* lo, uint64_t* xk, uint32_t* xc, uint64_t* table_keys,
+                            uint32_t* table_counts);
+
 // out[b] = tile_off[tile_base[b]] for b in [0, n_bins] (first output entry of each bin).
 hipError_t launch_bin_offsets(hipStream_t s, const uint64_t* tile_off, const uint64_t* tile_base,
                               uint32_t n_bins, uint64_t* out);

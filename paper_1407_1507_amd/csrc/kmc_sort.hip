@@ -1109,6 +1109,169 @@ k_gather(const Tile* __restrict__ tiles, const uint64_t* __restrict__ tile_off,
   for (uint64_t i = threadIdx.x; i < m; i += blockDim.x) out_counts[o + i] = counts[b + i];
 }
 
+// ------------------------------------------------- global ascending order
+// The table in ascending key order over all bins, instead of bin-major: the
+// bin-major table is partitioned by the top bits of its keys (segments) into
+// a scratch copy, consecutive segments are packed into groups of about
+// CAP / 2 entries, and every group is put in order, back into the table, in
+// LDS by the tile sort's ordering of kept keys (the keys are distinct, so
+// nothing is counted).  A group above CAP
+// entries (one segment of more than CAP / 2 keys that share their top bits)
+// is merge sorted through HBM by its workgroup.
+
+// Segment runs of the table in bin order (ascending inside each bin, so
+// entries of a segment are adjacent within a bin): each thread takes
+// kRunChunk consecutive entries and handles each of its runs with one
+// atomic.  kScatter = false: entries per segment into seg_cnt; true: the run
+// is copied to its segment at a slot claimed from the segment's cursor
+// (seg_cnt, zeroed after the scan).
+constexpr uint32_t kRunChunk = 16;
+template <int KW, bool kScatter>
+__global__ void __launch_bounds__(256)
+k_seg_runs(const uint64_t* __restrict__ keys, const uint32_t* __restrict__ counts, uint64_t n,
+           uint32_t shift, uint32_t* seg_cnt, const uint64_t* __restrict__ seg_start,
+           uint64_t* xk, uint32_t* xc) {
+  typedef typename KeyOf<KW>::T K;
+  const uint64_t stride = (uint64_t)gridDim.x * blockDim.x * kRunChunk;
+  for (uint64_t i0 = ((uint64_t)blockIdx.x * blockDim.x + threadIdx.x) * kRunChunk; i0 < n;
+       i0 += stride) {
+    const uint64_t i1 = min(n, i0 + kRunChunk);
+    uint64_t run = i0;
+    uint32_t sg = (uint32_t)(load_key(keys, i0, (K*)nullptr) >> shift);
+    for (uint64_t q = i0 + 1; q <= i1; ++q) {
+      const uint32_t s2 = q < i1 ? (uint32_t)(load_key(keys, q, (K*)nullptr) >> shift) : ~0u;
+      if (s2 == sg) continue;
+      if (!kScatter) {
+        atomicAdd(&seg_cnt[sg], (uint32_t)(q - run));
+      } else {
+        const uint64_t o = seg_start[sg] + atomicAdd(&seg_cnt[sg], (uint32_t)(q - run));
+        for (uint64_t e = run; e < q; ++e) {
+          store_key(xk, o + (e - run), load_key(keys, e, (K*)nullptr));
+          xc[o + (e - run)] = counts[e];
+        }
+      }
+      run = q;
+      sg = s2;
+    }
+  }
+}
+
+// lo[g] = first segment start at or above g * G (lo[n_groups] = total);
+// seg_start holds nseg + 1 entries, the last one the total.
+__global__ void k_group_lo(const uint64_t* __restrict__ seg_start, uint64_t nseg, uint64_t G,
+                           uint64_t n_groups, uint64_t* lo) {
+  const uint64_t s = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (s > nseg) return;
+  const uint64_t st = seg_start[s];
+  // groups g with seg_start[s - 1] < g * G <= seg_start[s]
+  const uint64_t g0 = s == 0 ? 0 : seg_start[s - 1] / G + 1;
+  const uint64_t g1 = s == nseg ? n_groups : st / G;
+  for (uint64_t g = g0; g <= g1; ++g) lo[g] = st;
+}
+
+// Entries [0, n) (n <= CAP, distinct keys) of xk / xc, in key order, to
+// tk / tc.  All threads call it.
+template <int KW>
+__device__ void order_group(const uint64_t* xk, const uint32_t* xc, uint32_t n, uint64_t* tk,
+                            uint32_t* tc, SortShared<KW>& S) {
+  typedef typename KeyOf<KW>::T K;
+  constexpr uint32_t ITEMS = SortCfg<KW>::ITEMS;
+  const uint32_t tid = threadIdx.x, nt = blockDim.x;
+  K key[ITEMS];
+  uint32_t cnt[ITEMS];
+  K a = ~K(0), o = 0;
+  uint32_t mine = 0;
+#pragma unroll
+  for (uint32_t m = 0; m < ITEMS; ++m) {
+    const uint32_t i = m * nt + tid;
+    cnt[m] = 0;
+    if (i < n) {
+      key[m] = load_key(xk, i, (K*)nullptr);
+      cnt[m] = xc[i];  // a kept count is at least 1
+      a &= key[m];
+      o |= key[m];
+      ++mine;
+    }
+  }
+  uint32_t total;
+  const uint32_t kbase = block_scan_one(mine, S.tmp, total);
+  if (n == 1) {
+    if (tid == 0) {
+      store_key(tk, 0, key[0]);
+      tc[0] = cnt[0];
+    }
+    __syncthreads();
+    return;
+  }
+  block_and_or<K>(a, o, S.red);
+  order_kept<KW>(key, cnt, kbase, n, a ^ o, tk, tc, S.A, S.H, S.tmp);
+}
+
+// Number of keys of src[b0, b1) below x (src ascending, distinct keys).
+template <class K>
+__device__ __forceinline__ uint64_t rank_in(const uint64_t* src, uint64_t b0, uint64_t b1,
+                                            const K& x) {
+  while (b0 < b1) {
+    const uint64_t mid = (b0 + b1) / 2;
+    if (load_key(src, mid, (K*)nullptr) < x) b0 = mid + 1;
+    else b1 = mid;
+  }
+  return b0;
+}
+
+template <int KW>
+__global__ void __launch_bounds__(kSortThreads)
+k_group_sort(const uint64_t* __restrict__ lo, uint64_t* xk, uint32_t* xc, uint64_t* tk,
+             uint32_t* tc) {
+  typedef typename KeyOf<KW>::T K;
+  constexpr uint32_t CAP = SortCfg<KW>::CAP;
+  __shared__ SortShared<KW> S;
+  const uint64_t g0 = lo[blockIdx.x], n = lo[blockIdx.x + 1] - g0;
+  if (n == 0) return;
+  xk += g0 * KW;
+  xc += g0;
+  tk += g0 * KW;
+  tc += g0;
+  if (n <= CAP) {
+    order_group<KW>(xk, xc, (uint32_t)n, tk, tc, S);
+    return;
+  }
+  // a group above CAP: chunks of CAP in order into t, then merge rounds
+  // between t and x (a key's place in a merged pair is its place in its run
+  // plus the number of keys of the other run below it)
+  for (uint64_t c0 = 0; c0 < n; c0 += CAP)
+    order_group<KW>(xk + c0 * KW, xc + c0, (uint32_t)min<uint64_t>(CAP, n - c0), tk + c0 * KW,
+                    tc + c0, S);
+  __threadfence();
+  __syncthreads();
+  uint64_t* sk = tk;
+  uint32_t* sc = tc;
+  uint64_t* dk = xk;
+  uint32_t* dc = xc;
+  for (uint64_t w = CAP; w < n; w *= 2) {
+    for (uint64_t i = threadIdx.x; i < n; i += blockDim.x) {
+      const uint64_t p0 = i / (2 * w) * (2 * w), a1 = min(p0 + w, n), b1 = min(p0 + 2 * w, n);
+      const K x = load_key(sk, i, (K*)nullptr);
+      const uint64_t pos = i < a1 ? i + (rank_in(sk, a1, b1, x) - a1)
+                                  : i - w + (rank_in(sk, p0, a1, x) - p0);
+      store_key(dk, pos, x);
+      dc[pos] = sc[i];
+    }
+    __threadfence();
+    __syncthreads();
+    uint64_t* t1 = sk;
+    sk = dk;
+    dk = t1;
+    uint32_t* t2 = sc;
+    sc = dc;
+    dc = t2;
+  }
+  if (sk != tk) {
+    for (uint64_t i = threadIdx.x; i < n * KW; i += blockDim.x) tk[i] = sk[i];
+    for (uint64_t i = threadIdx.x; i < n; i += blockDim.x) tc[i] = sc[i];
+  }
+}
+
 }  // namespace
 
 // Workgroups of kSortThreads that are resident at once on the current
@@ -1200,6 +1363,57 @@ hipError_t launch_gather(hipStream_t s, const KeyCfg& kc, const Tile* tiles, uin
   else
     hipLaunchKernelGGL(k_gather<2>, dim3((uint32_t)n_tiles), dim3(256), 0, s, tiles, tile_off,
                        keys, counts, out_keys, out_counts);
+  return hipGetLastError();
+}
+
+AscPlan plan_ascending(uint64_t n_out, uint32_t k, uint32_t key_words) {
+  AscPlan ap;
+  const uint64_t cap = key_words == 1 ? kTileCap1 : kTileCap2;
+  ap.group = cap / 2;
+  // segments of about cap / 16 entries on average
+  uint32_t b = 1;
+  while (b < kMaxSegBits && ((n_out * 16) >> b) > cap) ++b;
+  ap.seg_bits = std::min<uint32_t>(b, 2 * k);
+  ap.n_groups = (n_out + ap.group - 1) / ap.group;
+  return ap;
+}
+
+hipError_t launch_ascending(hipStream_t s, const KeyCfg& kc, uint64_t n_out, const AscPlan& ap,
+                            uint32_t* seg_cnt, uint64_t* seg_start, uint64_t* scan_tmp,
+                            uint64_t* lo, uint64_t* xk, uint32_t* xc, uint64_t* table_keys,
+                            uint32_t* table_counts) {
+  if (n_out == 0 || ap.n_groups == 0) return hipSuccess;
+  const uint64_t nseg = 1ull << ap.seg_bits;
+  const uint32_t shift = 2 * kc.k - ap.seg_bits;
+  const uint64_t chunks = (n_out + kRunChunk - 1) / kRunChunk;
+  const uint32_t grid = (uint32_t)std::min<uint64_t>((chunks + 255) / 256, 65535);
+  hipError_t e = hipMemsetAsync(seg_cnt, 0, nseg * 4, s);
+  if (e != hipSuccess) return e;
+  const bool one = kc.key_words == 1;
+  if (one)
+    hipLaunchKernelGGL((k_seg_runs<1, false>), dim3(grid), dim3(256), 0, s, table_keys,
+                       table_counts, n_out, shift, seg_cnt, seg_start, xk, xc);
+  else
+    hipLaunchKernelGGL((k_seg_runs<2, false>), dim3(grid), dim3(256), 0, s, table_keys,
+                       table_counts, n_out, shift, seg_cnt, seg_start, xk, xc);
+  if ((e = hipGetLastError()) != hipSuccess) return e;
+  if ((e = launch_scan_u32(s, seg_cnt, nseg, seg_start, scan_tmp)) != hipSuccess) return e;
+  hipLaunchKernelGGL(k_group_lo, dim3((uint32_t)((nseg + 1 + 255) / 256)), dim3(256), 0, s,
+                     seg_start, nseg, ap.group, ap.n_groups, lo);
+  if ((e = hipMemsetAsync(seg_cnt, 0, nseg * 4, s)) != hipSuccess) return e;
+  if (one)
+    hipLaunchKernelGGL((k_seg_runs<1, true>), dim3(grid), dim3(256), 0, s, table_keys,
+                       table_counts, n_out, shift, seg_cnt, seg_start, xk, xc);
+  else
+    hipLaunchKernelGGL((k_seg_runs<2, true>), dim3(grid), dim3(256), 0, s, table_keys,
+                       table_counts, n_out, shift, seg_cnt, seg_start, xk, xc);
+  if ((e = hipGetLastError()) != hipSuccess) return e;
+  if (one)
+    hipLaunchKernelGGL(k_group_sort<1>, dim3((uint32_t)ap.n_groups), dim3(kSortThreads), 0, s,
+                       lo, xk, xc, table_keys, table_counts);
+  else
+    hipLaunchKernelGGL(k_group_sort<2>, dim3((uint32_t)ap.n_groups), dim3(kSortThreads), 0, s,
+                       lo, xk, xc, table_keys, table_counts);
   return hipGetLastError();
 }
 

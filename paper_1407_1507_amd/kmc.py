@@ -27,6 +27,7 @@ KERNELS = ["sig_hist", "split", "fine_hist", "plan_tiles", "expand_scatter", "ti
            "big_tiles", "assemble"]
 FLAG_DEVICE_TABLE = 0x1
 FLAG_PLAIN_MINIMIZERS = 0x2
+FLAG_ASCENDING = 0x4
 
 EXPORTS = ["kmc_ctx_create", "kmc_ctx_destroy", "kmc_last_error", "kmc_count", "kmc_count_ex",
            "kmc_table_free", "kmc_status_str", "kmc_workspace_size", "kmc_count_ws",
@@ -195,7 +196,9 @@ class Result:
         self.n_bins = t.n_bins
         self.on_device = bool(t.on_device)
         self.stats = t.stats.as_dict()
-        self.bin_offsets = np.ctypeslib.as_array(t.bin_offsets, shape=(t.n_bins + 1,)).copy()
+        # None in ascending order (entries not grouped by bin)
+        self.bin_offsets = (np.ctypeslib.as_array(t.bin_offsets, shape=(t.n_bins + 1,)).copy()
+                            if t.bin_offsets else None)
         self.sig_to_bin = np.ctypeslib.as_array(t.sig_to_bin, shape=((1 << (2 * t.p)) + 1,)).copy()
         self._ptr = ptr
         if self.on_device:

@@ -110,11 +110,11 @@ def test_malformed_offsets_rejected(kmc, off):
     assert st == kmc.KMC_ERR_INVALID_ARG
 
 
-def _ws(kmc, n_reads, length, k, p=7, n_bins=512, ci=1, cx=10):
+def _ws(kmc, n_reads, length, k, p=7, n_bins=512, ci=1, cx=10, flags=0):
     seq = np.full(n_reads * length, ord("A"), dtype=np.uint8)
     off = np.arange(n_reads + 1, dtype=np.uint64) * length
     reads, keep = kmc.make_reads(seq, off)
-    params = kmc.Params(k, p, n_bins, ci, cx, 0)
+    params = kmc.Params(k, p, n_bins, ci, cx, flags)
     out = ctypes.c_size_t(0)
     st = kmc.lib().kmc_workspace_size(ctypes.byref(reads), ctypes.byref(params), ctypes.byref(out))
     return st, out.value
@@ -135,6 +135,10 @@ def test_workspace_size_is_host_only_and_bounded(kmc):
     assert _ws(kmc, 10, 100, 3, p=4)[0] == kmc.KMC_ERR_INVALID_ARG
     st, empty = _ws(kmc, 0, 100, 28)
     assert st == kmc.KMC_OK and 0 < empty < small
+    # ascending order adds a scratch copy of the table beside it in the
+    # records' region (24 instead of 16 bytes per window for 1-word keys)
+    st, asc = _ws(kmc, 10_000, 100, 28, flags=kmc.FLAG_ASCENDING)
+    assert st == kmc.KMC_OK and big + 4 * n < asc < big + 12 * n
 
 
 def test_batch_and_server_reject_null_handles(kmc):
