@@ -163,6 +163,46 @@ __device__ __forceinline__ void make_record(uint64_t* r, u128 F, u128 tail, uint
   r[3] = (uint64_t)t;
 }
 
+// Two-bit codes of the 4 bytes of w (bytes known to be bases), the first
+// byte's code in the top two of the 8 bits: the byte -> code map of
+// decode_base on every byte at once, then one multiply gathers the four
+// codes (byte i's code, at bit 8i, lands at bit 30 - 2i; no other partial
+// product reaches bits 24..31).
+__device__ __forceinline__ uint32_t pack4(uint32_t w) {
+  const uint32_t x = (w >> 1) & 0x03030303u;
+  const uint32_t c = x ^ ((x >> 1) & 0x01010101u);
+  return (c * 0x40100401u) >> 24;
+}
+
+// The record of the super k-mer whose first k-mer starts at j0 and which
+// holds n k-mers, rebuilt from the read: the L = k + n - 1 symbols from j0
+// (all valid bases) are read in aligned 16-byte chunks and packed two bits
+// each; the first k go to the forward key, the rest to the tail.
+template <int KW>
+__device__ void record_from_read(const uint8_t* __restrict__ seq, uint64_t n_bases,
+                                 uint32_t align, uint64_t j0, uint32_t n, uint32_t k,
+                                 uint64_t* rec) {
+  typedef typename KeyOf<KW>::T K;
+  const uint64_t j1 = j0 + k + n - 1;
+  K F = 0, T = 0;
+  uint32_t a = 0;  // symbols taken so far
+  for (uint64_t x16 = j0 & ~15ull; x16 < j1; x16 += 16) {
+    const uint4 ch = load_chunk(seq, n_bases, align, x16);
+    // the chunk's 16 codes, first byte's in the top bits
+    const uint32_t P = (pack4(ch.x) << 24) | (pack4(ch.y) << 16) | (pack4(ch.z) << 8) |
+                       pack4(ch.w);
+    const uint32_t sk = x16 < j0 ? (uint32_t)(j0 - x16) : 0u;      // bytes before j0
+    const uint32_t e = x16 + 16 > j1 ? (uint32_t)(j1 - x16) : 16u;  // end byte (exclusive)
+    const uint32_t c = e - sk;                                      // 1 .. 16 symbols
+    const uint64_t v = ((uint64_t)P >> (2 * (16 - e))) & ((1ull << (2 * c)) - 1);
+    const uint32_t toF = a < k ? min(c, k - a) : 0u, toT = c - toF;
+    if (toF) F = (F << (2 * toF)) | (K)(v >> (2 * toT));
+    if (toT) T = (T << (2 * toT)) | (K)(v & ((1ull << (2 * toT)) - 1));
+    a += c;
+  }
+  make_record(rec, F, T, n);
+}
+
 // Lane-private LDS slices for the window buffer: stride 2w + 1 elements.
 template <class VT>
 __device__ __forceinline__ VT* lane_vh(void* lds, uint32_t w) {
@@ -211,41 +251,60 @@ k_sig_hist(const uint8_t* __restrict__ seq, const uint64_t* __restrict__ offsets
 // past the region end are not written (the host then repeats the pass with
 // the exact sizes the cursors report).
 
-// Every super k-mer goes to its lane's own queue in LDS (no atomics while the
-// wave scans: emission is divergent, so it must be cheap); a full queue sends
-// the record straight to its bin with a global atomic.
+// A record that finds its lane's queue full goes straight to its bin: one
+// global reservation.  Out of line: the scan loop calls it for a few reads
+// only, and inlined into every unrolled base step it would bloat the loop.
+template <int KW>
+__device__ __noinline__ void spill_record(const uint8_t* __restrict__ seq, uint64_t n_bases,
+                                          uint32_t align, uint32_t k, uint64_t j0, uint32_t n,
+                                          uint32_t b, unsigned long long* gcursor,
+                                          unsigned long long* gkmer, const uint64_t* cap_base,
+                                          uint64_t* records) {
+  constexpr int RW = 2 * KW;
+  uint64_t rec[RW];
+  record_from_read<KW>(seq, n_bases, align, j0, n, k, rec);
+  atomicAdd(&gkmer[b], (unsigned long long)n);
+  const uint64_t g = atomicAdd(&gcursor[b], 1ull);
+  if (g < cap_base[b + 1]) {
+#pragma unroll
+    for (int w = 0; w < RW; ++w) records[g * RW + w] = rec[w];
+  }
+}
+
+// Every super k-mer goes to its lane's own queue in LDS as (start in the
+// read, k-mer count, signature): no atomics while the wave scans (emission
+// is divergent, so it must be cheap) and no record words in LDS (the records
+// are rebuilt from the read when they are written, which keeps the
+// workgroup's LDS small enough for four workgroups per compute unit).  A
+// full queue sends the record straight to its bin.
 template <int KW, class VT>
-struct QueueSink {
-  static constexpr bool kNeedKeys = true;
-  static constexpr int RW = 2 * KW;  // record words
+struct SlotSink {
+  static constexpr bool kNeedKeys = false;
   const uint32_t* map;
-  uint64_t* stage;   // this lane's Q slots, RW words each
-  VT* ssig;          // signature of each slot (VT holds every signature)
+  uint32_t* sj;      // this lane's Q slots: start of the first k-mer in the read
+  uint8_t* sn;       // k-mers of the super k-mer
+  VT* ssig;          // signature (VT holds every signature)
   uint32_t q, Q;
+  uint64_t x0;       // start of the lane's read
+  const uint8_t* seq;
+  uint64_t n_bases;
+  uint32_t align, k;
   unsigned long long* gcursor;
   unsigned long long* gkmer;
   const uint64_t* cap_base;
   uint64_t* records;
   __device__ void kmer(uint64_t, uint32_t, uint64_t, uint64_t) {}
   __device__ uint32_t bin_of(uint32_t) { return 0; }
-  __device__ void superkmer(uint64_t, uint32_t n, uint32_t sig, uint32_t,
-                            typename KeyOf<KW>::T F, typename KeyOf<KW>::T tail) {
-    uint64_t rec[RW];
-    make_record(rec, F, tail, n);
+  __device__ void superkmer(uint64_t j0, uint32_t n, uint32_t sig, uint32_t,
+                            typename KeyOf<KW>::T, typename KeyOf<KW>::T) {
     if (q < Q) {
-#pragma unroll
-      for (int w = 0; w < RW; ++w) stage[q * RW + w] = rec[w];
+      sj[q] = (uint32_t)(j0 - x0);
+      sn[q] = (uint8_t)n;
       ssig[q] = (VT)sig;
       ++q;
       return;
     }
-    const uint32_t b = map[sig];
-    atomicAdd(&gkmer[b], (unsigned long long)n);
-    const uint64_t g = atomicAdd(&gcursor[b], 1ull);
-    if (g < cap_base[b + 1]) {
-#pragma unroll
-      for (int w = 0; w < RW; ++w) records[g * RW + w] = rec[w];
-    }
+    spill_record<KW>(seq, n_bases, align, k, j0, n, map[sig], gcursor, gkmer, cap_base, records);
   }
 };
 
@@ -275,7 +334,27 @@ struct DirectSink {
 };
 
 // Queue slots per lane.
-template <int KW> struct SplitQ { static constexpr uint32_t Q = KW == 1 ? 8 : 4; };
+template <int KW> struct SplitQ { static constexpr uint32_t Q = 8; };
+
+// LDS of k_split_scatter: region U (the lanes' window buffers during the
+// scan, then the per-bin arrays and the slot order) followed by the queues.
+struct SplitLds {
+  uint32_t u_bytes, sj_off, qn_off, tmp_off, ssig_off, sn_off, total;
+};
+__host__ __device__ inline SplitLds split_lds(uint32_t lanes, uint32_t Q, uint32_t n_bins,
+                                              uint32_t vh_bytes, uint32_t vt_bytes) {
+  SplitLds L;
+  const uint32_t cap = lanes * Q;
+  const uint32_t bins = n_bins * 8 + n_bins * 12 + cap * 4;  // delta | lcnt lbase lkm | inv srank
+  L.u_bytes = ((vh_bytes > bins ? vh_bytes : bins) + 15) & ~15u;
+  L.sj_off = L.u_bytes;
+  L.qn_off = L.sj_off + cap * 4;
+  L.tmp_off = L.qn_off + lanes * 4;
+  L.ssig_off = L.tmp_off + 16;
+  L.sn_off = L.ssig_off + ((cap * vt_bytes + 15) & ~15u);
+  L.total = L.sn_off + ((cap + 15) & ~15u);
+  return L;
+}
 
 template <int KW, class VT>
 __global__ void __launch_bounds__(256)
@@ -287,37 +366,37 @@ k_split_scatter(const uint8_t* __restrict__ seq, const uint64_t* __restrict__ of
   constexpr uint32_t Q = SplitQ<KW>::Q;
   extern __shared__ __attribute__((aligned(16))) uint8_t lds8[];
   const uint32_t tid = threadIdx.x, nt = blockDim.x, cap = nt * Q;
-  // layout: vh | stage[cap*RW] u64 | delta[n_bins] u64 | lcnt, lbase, lkm [n_bins] u32 |
-  //         qn[lanes] u32 | ssig[cap] VT (signature, then bin) | inv[cap] u16 |
-  //         srank[cap] u16 | scan tmp
-  uint64_t* stage = reinterpret_cast<uint64_t*>(lds8 + vh_bytes);
-  uint64_t* delta = stage + (uint64_t)cap * RW;
+  const SplitLds SL = split_lds(nt, Q, C.n_bins, vh_bytes, sizeof(VT));
+  uint32_t* sj = reinterpret_cast<uint32_t*>(lds8 + SL.sj_off);
+  uint32_t* qn = reinterpret_cast<uint32_t*>(lds8 + SL.qn_off);
+  uint32_t* tmp = reinterpret_cast<uint32_t*>(lds8 + SL.tmp_off);
+  VT* ssig = reinterpret_cast<VT*>(lds8 + SL.ssig_off);  // signature, then bin
+  uint8_t* sn = lds8 + SL.sn_off;
+
+  const uint64_t r = (uint64_t)blockIdx.x * nt + tid;
+  const uint64_t x0 = r < n_reads ? offsets[r] : 0;
+  SlotSink<KW, VT> sink{map, sj + tid * Q, sn + tid * Q, ssig + tid * Q, 0, Q, x0, seq,
+                        n_bases, C.seq_align, C.k, gcursor, gkmer, cap_base, records};
+  if (r < n_reads)
+    scan_read<KW, VT>(seq, n_bases, x0, offsets[r + 1], C, lane_vh<VT>(lds8, C.w), sink);
+  qn[tid] = sink.q;
+  __syncthreads();  // the window buffers are dead: region U becomes the bin arrays
+
+  uint64_t* delta = reinterpret_cast<uint64_t*>(lds8);
   uint32_t* lcnt = reinterpret_cast<uint32_t*>(delta + C.n_bins);
   uint32_t* lbase = lcnt + C.n_bins;
   uint32_t* lkm = lbase + C.n_bins;
-  uint32_t* qn = lkm + C.n_bins;
-  VT* ssig = reinterpret_cast<VT*>(qn + nt);
-  uint16_t* inv = reinterpret_cast<uint16_t*>(ssig + cap);
+  uint16_t* inv = reinterpret_cast<uint16_t*>(lkm + C.n_bins);
   uint16_t* srank = inv + cap;
-  uint32_t* tmp = reinterpret_cast<uint32_t*>(srank + cap);
-
   for (uint32_t i = tid; i < C.n_bins; i += nt) lcnt[i] = lkm[i] = 0;
-
-  const uint64_t r = (uint64_t)blockIdx.x * nt + tid;
-  QueueSink<KW, VT> sink{map, stage + (uint64_t)tid * Q * RW, ssig + tid * Q, 0, Q,
-                     gcursor, gkmer, cap_base, records};
-  if (r < n_reads)
-    scan_read<KW, VT>(seq, n_bases, offsets[r], offsets[r + 1], C, lane_vh<VT>(lds8, C.w), sink);
-  qn[tid] = sink.q;
   __syncthreads();
-
   // bins of the queued records, their rank inside the bin, k-mers per bin
   for (uint32_t i = tid; i < cap; i += nt) {
     if (i % Q < qn[i / Q]) {
       const uint32_t b = map[ssig[i]];
       ssig[i] = (VT)b;  // n_bins <= 65535
       srank[i] = (uint16_t)atomicAdd(&lcnt[b], 1u);
-      atomicAdd(&lkm[b], (uint32_t)(stage[(uint64_t)i * RW + RW - 1] & 0xFFu));
+      atomicAdd(&lkm[b], (uint32_t)sn[i]);
     }
   }
   __syncthreads();
@@ -335,14 +414,19 @@ k_split_scatter(const uint8_t* __restrict__ seq, const uint64_t* __restrict__ of
   for (uint32_t i = tid; i < cap; i += nt)
     if (i % Q < qn[i / Q]) inv[lbase[ssig[i]] + srank[i]] = (uint16_t)i;
   __syncthreads();
-  // write records grouped by bin: consecutive lanes -> consecutive slots
+  // records grouped by bin: consecutive lanes -> consecutive slots; each is
+  // rebuilt from its read
+  const uint64_t r0 = (uint64_t)blockIdx.x * nt;
   for (uint32_t q = tid; q < nst; q += nt) {
     const uint32_t i = inv[q];
     const uint32_t b = ssig[i];
     const uint64_t g = delta[b] + q;
     if (g < cap_base[b + 1]) {
+      uint64_t rec[RW];
+      record_from_read<KW>(seq, n_bases, C.seq_align, offsets[r0 + i / Q] + sj[i], sn[i], C.k,
+                           rec);
 #pragma unroll
-      for (int w = 0; w < RW; ++w) records[g * RW + w] = stage[(uint64_t)i * RW + w];
+      for (int w = 0; w < RW; ++w) records[g * RW + w] = rec[w];
     }
   }
 }
@@ -459,20 +543,19 @@ hipError_t launch_sig_hist(hipStream_t s, const uint8_t* seq, const uint64_t* of
   return hipGetLastError();
 }
 
-static size_t split_stage_lds(const ScanCfg& c, uint32_t key_words, uint32_t lanes) {
-  const uint32_t RW = 2 * key_words;
-  const size_t cap = (size_t)lanes * (key_words == 1 ? SplitQ<1>::Q : SplitQ<2>::Q);
-  return cap * RW * 8 + (size_t)c.n_bins * 8 + (size_t)c.n_bins * 12 + (size_t)lanes * 4 +
-         cap * (small_vt(c) ? 2 : 4) + cap * 4 + 4 * 4 + 16;
+static size_t split_lds_bytes(const ScanCfg& c, uint32_t key_words, uint32_t lanes) {
+  const uint32_t Q = key_words == 1 ? SplitQ<1>::Q : SplitQ<2>::Q;
+  return split_lds(lanes, Q, c.n_bins, (uint32_t)vh_bytes(c, lanes), small_vt(c) ? 2 : 4).total;
 }
 
 static bool lane_scan_fits(const ScanCfg& c, uint32_t key_words) {
-  return small_vt(c) && vh_bytes(c, 256) + split_stage_lds(c, key_words, 256) <= 80 * 1024;
+  return small_vt(c) && split_lds_bytes(c, key_words, 256) <= 80 * 1024;
 }
 
 // The lane-per-read scan is used when 256 lanes' window buffers (16-bit
-// values) and record queues fit two workgroups per compute unit; otherwise
-// the scan with one position per lane (the same signatures and records).
+// values) and record queues fit at least two workgroups per compute unit;
+// otherwise the scan with one position per lane (the same signatures and
+// records).
 static bool lane_scan_fits(const ScanCfg& c, uint32_t key_words);
 
 hipError_t launch_split_scatter(hipStream_t s, const uint8_t* seq, const uint64_t* offsets,
@@ -484,10 +567,10 @@ hipError_t launch_split_scatter(hipStream_t s, const uint8_t* seq, const uint64_
   if (!lane_scan_fits(cfg, key_words))
     return launch_split_wide(s, seq, offsets, n_reads, cfg, key_words, sig_to_bin, cursor,
                              kmer_cnt, cap_base, records);
-  // largest workgroup whose window buffers + queues fit 80 KB (two per CU)
+  // largest workgroup whose window buffers + queues fit 80 KB (at least two per CU)
   for (uint32_t lanes = 256; lanes >= 64; lanes >>= 1) {
     const size_t vb = vh_bytes(cfg, lanes);
-    const size_t sh = vb + split_stage_lds(cfg, key_words, lanes);
+    const size_t sh = split_lds_bytes(cfg, key_words, lanes);
     if (sh <= 80 * 1024) {
       KMC_SCAN_DISPATCH(k_split_scatter, dim3(grid_for(n_reads, lanes)), dim3(lanes), sh, s,
                         seq, offsets, n_reads, n_bases, cfg, sig_to_bin, cursor, kmer_cnt,
