@@ -564,8 +564,9 @@ void run_count(kmc_ctx* c, const kmc_reads* R, const kmc_params* P, kmc_table* T
   // ---- sort: tiles in LDS, big tiles through HBM
   uint32_t* tile_out = ensure<uint32_t>(c, B_TILEOUT, n_tiles * 8 + 8);
   uint32_t* tile_dist = tile_out + n_tiles + (n_tiles & 1);
-  uint32_t* big = ensure<uint32_t>(c, B_BIG, n_tiles * 12 + 16);
+  uint32_t* big = ensure<uint32_t>(c, B_BIG, n_tiles * 16 + 16);
   uint64_t* big_off = reinterpret_cast<uint64_t*>(big + ((n_tiles + 1) & ~1ull));
+  uint32_t* big_order = reinterpret_cast<uint32_t*>(big_off + n_tiles);
   kbeg(c, KMC_K_TILE_SORT, s);
   check(c, launch_tile_sort(s, kc, tiles, n_tiles, keys, counts, tile_out, big, big_off,
                             &misc->n_big, &misc->big_total, tile_dist), "tile_sort");
@@ -575,7 +576,8 @@ void run_count(kmc_ctx* c, const kmc_reads* R, const kmc_params* P, kmc_table* T
   kbeg(c, KMC_K_BIG_TILES, s);
   {
     uint64_t* tmp = ensure<uint64_t>(c, B_TMP, std::max<uint64_t>(1, n_kmers) * J.kw * 8);
-    check(c, launch_big_tiles(s, kc, tiles, big, big_off, &misc->n_big, &misc->big_next, n_tiles,
+    check(c, launch_big_tiles(s, kc, tiles, big, big_off, big_order, &misc->n_big,
+                              &misc->big_next, n_tiles,
                               keys, tmp, counts, tile_out, tile_dist), "big_tiles");
   }
   kend(c, KMC_K_BIG_TILES, s);
@@ -716,7 +718,7 @@ WsLayout plan_workspace(const kmc_reads* R, const kmc_params* P) {
   sz[B_KEYS] = kmax * kw * 8;
   sz[B_COUNTS] = kmax * 4;
   sz[B_TILEOUT] = tmax * 8 + 8;
-  sz[B_BIG] = tmax * 12 + 16;
+  sz[B_BIG] = tmax * 16 + 16;
   sz[B_MISC] = sizeof(Misc);
   sz[B_TMP] = kmax * kw * 8;
   sz[B_SCANTMP] = scan_tmp_words(tmax) * 8;

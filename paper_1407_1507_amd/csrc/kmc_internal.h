@@ -148,7 +148,7 @@ hipError_t launch_tile_sort(hipStream_t s, const KeyCfg& kc, const Tile* tiles,
 // kernel has run); workgroups take tiles from the counter *next (zero at
 // launch).  max_big bounds *n_big (the grid never exceeds it).
 hipError_t launch_big_tiles(hipStream_t s, const KeyCfg& kc, const Tile* tiles,
-                            const uint32_t* big_list, const uint64_t* big_off,
+                            const uint32_t* big_list, const uint64_t* big_off, uint32_t* order,
                             const uint32_t* n_big, uint32_t* next, uint64_t max_big,
                             uint64_t* keys, uint64_t* tmp, uint32_t* out_counts,
                             uint32_t* tile_out, uint32_t* tile_distinct);

@@ -1006,9 +1006,9 @@ __device__ void big_tile(const KeyCfg& kc, const Tile* __restrict__ tiles, uint3
 template <int KW>
 __global__ void __launch_bounds__(kSortThreads)
 k_big_tiles(KeyCfg kc, const Tile* __restrict__ tiles, const uint32_t* __restrict__ big_list,
-            const uint64_t* __restrict__ big_off, const uint32_t* n_big, uint32_t* next,
-            uint64_t* keys, uint64_t* tmp, uint32_t* counts, uint32_t* tile_out,
-            uint32_t* tile_distinct) {
+            const uint64_t* __restrict__ big_off, const uint32_t* __restrict__ order,
+            const uint32_t* n_big, uint32_t* next, uint64_t* keys, uint64_t* tmp,
+            uint32_t* counts, uint32_t* tile_out, uint32_t* tile_distinct) {
   __shared__ uint32_t item;
   const uint32_t nb = *n_big;
   for (;;) {
@@ -1017,9 +1017,35 @@ k_big_tiles(KeyCfg kc, const Tile* __restrict__ tiles, const uint32_t* __restric
     const uint32_t it = item;
     __syncthreads();
     if (it >= nb) return;
-    big_tile<KW>(kc, tiles, big_list[it], big_off[it], keys, tmp, counts, tile_out,
+    const uint32_t j = order[it];
+    big_tile<KW>(kc, tiles, big_list[j], big_off[j], keys, tmp, counts, tile_out,
                  tile_distinct);
   }
+}
+
+// The order in which the big-tile workgroups take the big tiles: largest
+// first (a counting sort on the size in quarter octaves), so that the
+// longest tiles start at once and the kernel does not end waiting on one
+// big tile taken last.
+constexpr uint32_t kSizeClasses = 128;
+__device__ __forceinline__ uint32_t size_class(uint32_t size) {
+  const uint32_t l = 31u - __clz(size | 4u);          // floor(log2), at least 2
+  const uint32_t q = (size >> (l - 2)) & 3u;           // next two bits
+  return kSizeClasses - 1u - min(4u * l + q, kSizeClasses - 1u);  // largest -> 0
+}
+__global__ void __launch_bounds__(1024)
+k_order_big(const Tile* __restrict__ tiles, const uint32_t* __restrict__ big_list,
+            const uint32_t* n_big, uint32_t* order) {
+  __shared__ uint32_t cnt[kSizeClasses], tmp[16];
+  const uint32_t nb = *n_big, tid = threadIdx.x;
+  for (uint32_t i = tid; i < kSizeClasses; i += blockDim.x) cnt[i] = 0;
+  __syncthreads();
+  for (uint32_t i = tid; i < nb; i += blockDim.x)
+    atomicAdd(&cnt[size_class(tiles[big_list[i]].size)], 1u);
+  __syncthreads();
+  block_exclusive_scan(cnt, kSizeClasses, tmp);
+  for (uint32_t i = tid; i < nb; i += blockDim.x)
+    order[atomicAdd(&cnt[size_class(tiles[big_list[i]].size)], 1u)] = i;
 }
 
 // ---------------------------------------------------------------- scans
@@ -1317,11 +1343,12 @@ hipError_t launch_tile_sort(hipStream_t s, const KeyCfg& kc, const Tile* tiles,
 }
 
 hipError_t launch_big_tiles(hipStream_t s, const KeyCfg& kc, const Tile* tiles,
-                            const uint32_t* big_list, const uint64_t* big_off,
+                            const uint32_t* big_list, const uint64_t* big_off, uint32_t* order,
                             const uint32_t* n_big, uint32_t* next, uint64_t max_big,
                             uint64_t* keys, uint64_t* tmp, uint32_t* out_counts,
                             uint32_t* tile_out, uint32_t* tile_distinct) {
   if (max_big == 0) return hipSuccess;
+  hipLaunchKernelGGL(k_order_big, dim3(1), dim3(1024), 0, s, tiles, big_list, n_big, order);
   const int kw = kc.key_words == 1 ? 1 : 2;
   const uint32_t grid = (uint32_t)std::min<uint64_t>(
       max_big, (uint64_t)resident_blocks(kw == 1 ? (const void*)k_big_tiles<1>
@@ -1329,11 +1356,11 @@ hipError_t launch_big_tiles(hipStream_t s, const KeyCfg& kc, const Tile* tiles,
                                          1 + kw));
   if (kw == 1)
     hipLaunchKernelGGL(k_big_tiles<1>, dim3(grid), dim3(kSortThreads), 0, s, kc, tiles,
-                       big_list, big_off, n_big, next, keys, tmp, out_counts, tile_out,
+                       big_list, big_off, order, n_big, next, keys, tmp, out_counts, tile_out,
                        tile_distinct);
   else
     hipLaunchKernelGGL(k_big_tiles<2>, dim3(grid), dim3(kSortThreads), 0, s, kc, tiles,
-                       big_list, big_off, n_big, next, keys, tmp, out_counts, tile_out,
+                       big_list, big_off, order, n_big, next, keys, tmp, out_counts, tile_out,
                        tile_distinct);
   return hipGetLastError();
 }
