@@ -121,4 +121,87 @@ __device__ inline uint32_t block_scan_one(uint32_t v, uint32_t* tmp, uint32_t& t
   return off + x - v;
 }
 
+
+// ------------------------------------------------ reads and records
+// The 4 bytes of the aligned word at xw (xw % 4 == 0); bytes at or past
+// n_bases read as 0 (an invalid symbol).  Whole-word loads need seq 4-byte
+// aligned; otherwise bytes are loaded one by one.
+__device__ __forceinline__ uint32_t load_word(const uint8_t* __restrict__ seq, uint64_t n,
+                                              bool a4, uint64_t xw) {
+  if (a4 && xw + 3 < n) return reinterpret_cast<const uint32_t*>(seq)[xw >> 2];
+  uint32_t w = 0;
+#pragma unroll
+  for (int q = 0; q < 4; ++q)
+    if (xw + q < n) w |= (uint32_t)seq[xw + q] << (8 * q);
+  return w;
+}
+
+// The 16 bytes at x16 (x16 % 16 == 0), same conventions: one 16-byte load
+// when seq is 16-byte aligned and the chunk lies inside it.
+__device__ __forceinline__ uint4 load_chunk(const uint8_t* __restrict__ seq, uint64_t n,
+                                            uint32_t align, uint64_t x16) {
+  if (align >= 16 && x16 + 15 < n) return reinterpret_cast<const uint4*>(seq)[x16 >> 4];
+  const bool a4 = align >= 4;
+  return make_uint4(load_word(seq, n, a4, x16), load_word(seq, n, a4, x16 + 4),
+                    load_word(seq, n, a4, x16 + 8), load_word(seq, n, a4, x16 + 12));
+}
+
+// Record of a super k-mer (2 words for k <= 32, 4 words for k > 32):
+//   word group 0: forward key of the first k-mer (hi word first for 2 words);
+//   word group 1: the n-1 symbols after the first k-mer, left aligned (first
+//                 symbol in the top bits), with n in the low 8 bits.
+// At most w - 1 = k - p tail symbols, so 2(k-p) + 8 bits fit one group.
+__device__ __forceinline__ void make_record(uint64_t* r, uint64_t F, uint64_t tail, uint32_t n) {
+  r[0] = F;
+  r[1] = (n > 1 ? (tail << (64 - 2 * (n - 1))) : 0ull) | n;
+}
+__device__ __forceinline__ void make_record(uint64_t* r, u128 F, u128 tail, uint32_t n) {
+  u128 t = (n > 1 ? (tail << (128 - 2 * (n - 1))) : (u128)0) | (u128)n;
+  r[0] = (uint64_t)(F >> 64);
+  r[1] = (uint64_t)F;
+  r[2] = (uint64_t)(t >> 64);
+  r[3] = (uint64_t)t;
+}
+
+// Two-bit codes of the 4 bytes of w (bytes known to be bases), the first
+// byte's code in the top two of the 8 bits: the byte -> code map of
+// decode_base on every byte at once, then one multiply gathers the four
+// codes (byte i's code, at bit 8i, lands at bit 30 - 2i; no other partial
+// product reaches bits 24..31).
+__device__ __forceinline__ uint32_t pack4(uint32_t w) {
+  const uint32_t x = (w >> 1) & 0x03030303u;
+  const uint32_t c = x ^ ((x >> 1) & 0x01010101u);
+  return (c * 0x40100401u) >> 24;
+}
+
+// The record of the super k-mer whose first k-mer starts at j0 and which
+// holds n k-mers, rebuilt from the read: the L = k + n - 1 symbols from j0
+// (all valid bases) are read in aligned 16-byte chunks and packed two bits
+// each; the first k go to the forward key, the rest to the tail.
+template <int KW>
+__device__ void record_from_read(const uint8_t* __restrict__ seq, uint64_t n_bases,
+                                 uint32_t align, uint64_t j0, uint32_t n, uint32_t k,
+                                 uint64_t* rec) {
+  typedef typename KeyOf<KW>::T K;
+  const uint64_t j1 = j0 + k + n - 1;
+  K F = 0, T = 0;
+  uint32_t a = 0;  // symbols taken so far
+  for (uint64_t x16 = j0 & ~15ull; x16 < j1; x16 += 16) {
+    const uint4 ch = load_chunk(seq, n_bases, align, x16);
+    // the chunk's 16 codes, first byte's in the top bits
+    const uint32_t P = (pack4(ch.x) << 24) | (pack4(ch.y) << 16) | (pack4(ch.z) << 8) |
+                       pack4(ch.w);
+    const uint32_t sk = x16 < j0 ? (uint32_t)(j0 - x16) : 0u;      // bytes before j0
+    const uint32_t e = x16 + 16 > j1 ? (uint32_t)(j1 - x16) : 16u;  // end byte (exclusive)
+    const uint32_t c = e - sk;                                      // 1 .. 16 symbols
+    const uint64_t v = ((uint64_t)P >> (2 * (16 - e))) & ((1ull << (2 * c)) - 1);
+    const uint32_t toF = a < k ? min(c, k - a) : 0u, toT = c - toF;
+    if (toF) F = (F << (2 * toF)) | (K)(v >> (2 * toT));
+    if (toT) T = (T << (2 * toT)) | (K)(v & ((1ull << (2 * toT)) - 1));
+    a += c;
+  }
+  make_record(rec, F, T, n);
+}
+
+
 }  // namespace kmc

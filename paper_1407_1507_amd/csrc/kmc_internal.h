@@ -85,7 +85,8 @@ hipError_t launch_split_scatter(hipStream_t s, const uint8_t* seq, const uint64_
 // The split and the debug scan with one position per lane (kmc_scan_wide.hip),
 // for windows whose per-lane buffers do not fit LDS well.
 hipError_t launch_split_wide(hipStream_t s, const uint8_t* seq, const uint64_t* offsets,
-                             uint64_t n_reads, const ScanCfg& cfg, uint32_t key_words,
+                             uint64_t n_reads, uint64_t n_bases, const ScanCfg& cfg,
+                             uint32_t key_words,
                              const uint32_t* sig_to_bin, unsigned long long* cursor,
                              unsigned long long* kmer_cnt, const uint64_t* cap_base,
                              uint64_t* records);

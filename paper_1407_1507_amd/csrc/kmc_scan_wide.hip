@@ -69,23 +69,6 @@ __device__ __forceinline__ u128 ring_codes(const uint32_t* ring, int32_t z, uint
   return len >= 64 ? v : v & (((u128)1 << (2 * len)) - 1);
 }
 
-// Record of a super k-mer (2 words for k <= 32, 4 words for k > 32):
-//   word group 0: forward key of the first k-mer (hi word first for 2 words);
-//   word group 1: the n-1 symbols after the first k-mer, left aligned (first
-//                 symbol in the top bits), with n in the low 8 bits.
-// At most w - 1 = k - p tail symbols, so 2(k-p) + 8 bits fit one group.
-__device__ __forceinline__ void make_record(uint64_t* r, uint64_t F, uint64_t tail, uint32_t n) {
-  r[0] = F;
-  r[1] = (n > 1 ? (tail << (64 - 2 * (n - 1))) : 0ull) | n;
-}
-__device__ __forceinline__ void make_record(uint64_t* r, u128 F, u128 tail, uint32_t n) {
-  u128 t = (n > 1 ? (tail << (128 - 2 * (n - 1))) : (u128)0) | (u128)n;
-  r[0] = (uint64_t)(F >> 64);
-  r[1] = (uint64_t)F;
-  r[2] = (uint64_t)(t >> 64);
-  r[3] = (uint64_t)t;
-}
-
 enum ScanMode { kSplitStaged = 0, kSplitDirect = 1, kDebug = 3 };
 
 struct ScanOut {
@@ -95,17 +78,19 @@ struct ScanOut {
   unsigned long long* gkmer;           // k-mers of every bin
   const uint64_t* cap_base;            // region of bin b: [cap_base[b], cap_base[b+1])
   uint64_t* records;
+  uint64_t n_bases;                    // bytes of seq (records are rebuilt from it)
   uint32_t cap;                        // staged records per workgroup
   // debug
   uint32_t* dsig;
   uint8_t* dstart;
 };
 
-// LDS of the staged split: per-wave rings of packed codes, the staged
-// records, per-bin counters and the record permutation.
+// LDS of the staged split: the staged super k-mers as (first k-mer start,
+// k-mer count, signature) (records are rebuilt from the reads when they are
+// written, so no record words and no code rings are kept), per-bin counters
+// and the record permutation.
 struct StageLayout {
-  uint32_t* ring;       // kScanWaves x 256
-  uint64_t* stage;      // cap x RW
+  uint64_t* start;      // cap: first k-mer start in seq
   uint64_t* delta;      // n_bins
   uint32_t* lcnt;       // n_bins
   uint32_t* lbase;      // n_bins
@@ -114,14 +99,13 @@ struct StageLayout {
   uint16_t* srank;      // cap
   uint16_t* inv;        // cap
   uint32_t* misc;       // [0] staged, [1] iterations, [2..] scan tmp
+  uint8_t* sn;          // cap: k-mers
 };
 
-__device__ __forceinline__ StageLayout stage_layout(uint8_t* lds, uint32_t cap, uint32_t n_bins,
-                                                    int RW) {
+__device__ __forceinline__ StageLayout stage_layout(uint8_t* lds, uint32_t cap, uint32_t n_bins) {
   StageLayout L;
-  L.ring = reinterpret_cast<uint32_t*>(lds);
-  L.stage = reinterpret_cast<uint64_t*>(L.ring + kScanWaves * 256);
-  L.delta = L.stage + (size_t)cap * RW;
+  L.start = reinterpret_cast<uint64_t*>(lds);
+  L.delta = L.start + cap;
   L.lcnt = reinterpret_cast<uint32_t*>(L.delta + n_bins);
   L.lbase = L.lcnt + n_bins;
   L.lkm = L.lbase + n_bins;
@@ -129,6 +113,7 @@ __device__ __forceinline__ StageLayout stage_layout(uint8_t* lds, uint32_t cap, 
   L.srank = reinterpret_cast<uint16_t*>(L.ssig + cap);
   L.inv = L.srank + cap;
   L.misc = reinterpret_cast<uint32_t*>(L.inv + cap);
+  L.sn = reinterpret_cast<uint8_t*>(L.misc + 2 + kScanWaves);
   return L;
 }
 
@@ -136,15 +121,16 @@ __device__ __forceinline__ StageLayout stage_layout(uint8_t* lds, uint32_t cap, 
 // per (flush, bin), consecutive lanes writing consecutive slots of a bin.
 // All threads call it, with the staged records complete.
 template <int KW>
-__device__ void flush_stage(const StageLayout& L, uint32_t n_bins, const ScanOut& O) {
+__device__ void flush_stage(const StageLayout& L, const uint8_t* __restrict__ seq,
+                            const ScanCfg& C, const ScanOut& O) {
   constexpr int RW = 2 * KW;
-  const uint32_t tid = threadIdx.x, nt = blockDim.x;
+  const uint32_t tid = threadIdx.x, nt = blockDim.x, n_bins = C.n_bins;
   const uint32_t nst = L.misc[0];
   for (uint32_t i = tid; i < nst; i += nt) {
     const uint32_t b = O.map[L.ssig[i]];
     L.ssig[i] = b;
     L.srank[i] = (uint16_t)atomicAdd(&L.lcnt[b], 1u);
-    atomicAdd(&L.lkm[b], (uint32_t)(L.stage[(size_t)i * RW + RW - 1] & 0xFFu));
+    atomicAdd(&L.lkm[b], (uint32_t)L.sn[i]);
   }
   __syncthreads();
   for (uint32_t b = tid; b < n_bins; b += nt) L.lbase[b] = L.lcnt[b];
@@ -164,8 +150,10 @@ __device__ void flush_stage(const StageLayout& L, uint32_t n_bins, const ScanOut
     const uint32_t b = L.ssig[i];
     const uint64_t g = L.delta[b] + q;
     if (g < O.cap_base[b + 1]) {
+      uint64_t rec[RW];
+      record_from_read<KW>(seq, O.n_bases, C.seq_align, L.start[i], L.sn[i], C.k, rec);
 #pragma unroll
-      for (int w = 0; w < RW; ++w) O.records[g * RW + w] = L.stage[(size_t)i * RW + w];
+      for (int w = 0; w < RW; ++w) O.records[g * RW + w] = rec[w];
     }
   }
   __syncthreads();
@@ -206,12 +194,11 @@ k_scan(const uint8_t* __restrict__ seq, const uint64_t* __restrict__ offsets, ui
   StageLayout L{};
   uint32_t* ring = nullptr;
   uint32_t iters = n_chunks;
-  if (MODE == kSplitStaged || MODE == kSplitDirect)
-    ring = reinterpret_cast<uint32_t*>(lds8) + wid * 256;
+  if (MODE == kSplitDirect) ring = reinterpret_cast<uint32_t*>(lds8) + wid * 256;
   if (MODE == kSplitStaged) {
     // the workgroup walks its chunks in step, so that staged records can be
     // flushed by all of its threads together
-    L = stage_layout(lds8, O.cap, C.n_bins, RW);
+    L = stage_layout(lds8, O.cap, C.n_bins);
     for (uint32_t b = threadIdx.x; b < C.n_bins; b += blockDim.x) L.lcnt[b] = L.lkm[b] = 0;
     if (threadIdx.x == 0) L.misc[0] = L.misc[1] = 0;
     __syncthreads();
@@ -265,7 +252,7 @@ k_scan(const uint8_t* __restrict__ seq, const uint64_t* __restrict__ offsets, ui
       pf2 = f2;
       pf4 = f4;
       pf8 = f8;
-      if (MODE == kSplitStaged || MODE == kSplitDirect) ring[x & 255] = f16;
+      if (MODE == kSplitDirect) ring[x & 255] = f16;
       const uint32_t fp = f16 & C.pmask;
       const uint32_t can = min(fp, rc_pmer(fp, C.p));
       const uint32_t v =
@@ -312,24 +299,22 @@ k_scan(const uint8_t* __restrict__ seq, const uint64_t* __restrict__ offsets, ui
       if (MODE != kDebug && E) {
         const int32_t y = x - 1;
         const uint32_t n = (uint32_t)(y - s0 + 1);
-        __builtin_amdgcn_wave_barrier();  // the ring entries of this chunk are written
-        uint64_t rec[RW];
-        if (e) {
-          const K F = ring_codes(ring, s0, C.k, (K*)nullptr);
-          const K T = n > 1 ? ring_codes(ring, y, n - 1, (K*)nullptr) : (K)0;
-          make_record(rec, F, T, n);
-        }
         if (MODE == kSplitStaged) {
           uint32_t base = 0;
           if (lane == 0) base = atomicAdd(&L.misc[0], (uint32_t)__popcll(E));
           base = (uint32_t)__builtin_amdgcn_readfirstlane((int)base);
           if (e) {
             const uint32_t idx = base + (uint32_t)__popcll(E & lt);
-#pragma unroll
-            for (int w = 0; w < RW; ++w) L.stage[(size_t)idx * RW + w] = rec[w];
+            L.start[idx] = x_begin + (uint64_t)(s0 - (int32_t)C.k + 1);
+            L.sn[idx] = (uint8_t)n;
             L.ssig[idx] = sigp;
           }
         } else if (e) {
+          __builtin_amdgcn_wave_barrier();  // the ring entries of this chunk are written
+          uint64_t rec[RW];
+          const K F = ring_codes(ring, s0, C.k, (K*)nullptr);
+          const K T = n > 1 ? ring_codes(ring, y, n - 1, (K*)nullptr) : (K)0;
+          make_record(rec, F, T, n);
           const uint32_t b = O.map[sigp];
           atomicAdd(&O.gkmer[b], (unsigned long long)n);
           const uint64_t g = atomicAdd(&O.gcursor[b], 1ull);
@@ -342,12 +327,12 @@ k_scan(const uint8_t* __restrict__ seq, const uint64_t* __restrict__ offsets, ui
     }
     if (MODE == kSplitStaged) {
       __syncthreads();
-      if (L.misc[0] + kScanWaves * 64 > O.cap) flush_stage<KW>(L, C.n_bins, O);
+      if (L.misc[0] + kScanWaves * 64 > O.cap) flush_stage<KW>(L, seq, C, O);
     }
   }
   if (MODE == kSplitStaged) {
     __syncthreads();
-    if (L.misc[0]) flush_stage<KW>(L, C.n_bins, O);
+    if (L.misc[0]) flush_stage<KW>(L, seq, C, O);
   }
 }
 
@@ -375,10 +360,8 @@ hipError_t launch_scan(hipStream_t s, const uint8_t* seq, const uint64_t* offset
   return hipGetLastError();
 }
 
-size_t stage_lds(uint32_t key_words, uint32_t n_bins, uint32_t cap) {
-  const size_t RW = 2 * key_words;
-  return (size_t)kScanWaves * 256 * 4 + cap * RW * 8 + (size_t)n_bins * 20 + (size_t)cap * 8 +
-         (2 + kScanWaves) * 4 + 16;
+size_t stage_lds(uint32_t n_bins, uint32_t cap) {
+  return (size_t)cap * 8 + (size_t)n_bins * 20 + (size_t)cap * 8 + (2 + kScanWaves) * 4 + cap + 16;
 }
 
 }  // namespace
@@ -386,7 +369,8 @@ size_t stage_lds(uint32_t key_words, uint32_t n_bins, uint32_t cap) {
 // --------------------------------------------------------------- launchers
 
 hipError_t launch_split_wide(hipStream_t s, const uint8_t* seq, const uint64_t* offsets,
-                             uint64_t n_reads, const ScanCfg& cfg, uint32_t key_words,
+                             uint64_t n_reads, uint64_t n_bases, const ScanCfg& cfg,
+                             uint32_t key_words,
                              const uint32_t* sig_to_bin, unsigned long long* cursor,
                              unsigned long long* kmer_cnt, const uint64_t* cap_base,
                              uint64_t* records) {
@@ -396,12 +380,13 @@ hipError_t launch_split_wide(hipStream_t s, const uint8_t* seq, const uint64_t* 
   o.gkmer = kmer_cnt;
   o.cap_base = cap_base;
   o.records = records;
-  // the largest stage (records per flush) that keeps four workgroups per
-  // compute unit, else the largest within 64 KB; without room for 512,
-  // records go straight to their bins
-  for (size_t limit : {size_t(40) << 10, size_t(64) << 10}) {
+  o.n_bases = n_bases;
+  // the largest stage (records per flush) that keeps five workgroups per
+  // compute unit, else four, else the largest within 64 KB; without room for
+  // 512, records go straight to their bins
+  for (size_t limit : {size_t(32) << 10, size_t(40) << 10, size_t(64) << 10}) {
     for (uint32_t cap = 2048; cap >= 512; cap >>= 1) {
-      const size_t lds = stage_lds(key_words, cfg.n_bins, cap);
+      const size_t lds = stage_lds(cfg.n_bins, cap);
       if (lds <= limit) {
         o.cap = cap;
         return launch_scan<kSplitStaged>(s, seq, offsets, n_reads, cfg, key_words, 1, lds, o);
