@@ -160,6 +160,31 @@ __device__ __forceinline__ uint32_t high_bit(u128 x) {
 
 constexpr uint32_t kRankMax = 256;  // kept keys ordered by a rank sort, at most
 
+// Output slot of every kept (distinct) 128-bit key of K[0, kept), kept <=
+// kRankMax: the number of smaller kept keys (for 64-bit keys one lane per key
+// measured faster).  K holds the all-ones key (never
+// canonical) from kept up to the next multiple of 8.  Up to four lanes share
+// a key, each counting over a part of K, so that a small set is spread over
+// the whole workgroup; emit(i, key, slot) runs once per key.  All threads
+// call it.
+template <class K, class Emit>
+__device__ __forceinline__ void rank_kept(const K* keys, uint32_t kept, Emit emit) {
+  const uint32_t tid = threadIdx.x;
+  const uint32_t p = kept <= kSortThreads / 4 ? 4u : kept <= kSortThreads / 2 ? 2u : 1u;
+  const uint32_t span = ((kept + 7) & ~7u) / p;  // even
+  const uint32_t i = tid / p, part = tid % p;
+  uint32_t r = 0;
+  K x = 0;
+  if (i < kept) {
+    x = keys[i];
+    for (uint32_t j = part * span, e = j + span; j < e; j += 2)
+      r += (uint32_t)(keys[j] < x) + (uint32_t)(keys[j + 1] < x);
+  }
+  if (p >= 2) r += __shfl_xor(r, 1, 64);  // the lanes of a key are adjacent in a wave
+  if (p >= 4) r += __shfl_xor(r, 2, 64);
+  if (i < kept && part == 0) emit(i, x, r);
+}
+
 // LDS carve-up of the tile sort.  128-bit keys keep the hashed-bucket
 // counting path (mixed buckets, big-bucket list); 64-bit keys only take the
 // hash table and keep a small separate area for the kept keys instead.
@@ -510,14 +535,12 @@ __device__ uint32_t count_tile_hash2(u128 (&key)[SortCfg<2>::ITEMS], uint32_t n,
         ++at;
       }
     }
+    if (tid >= kept && tid < ((kept + 7) & ~7u)) S.K[tid] = ~(u128)0;  // never canonical
     __syncthreads();
-    if (tid < kept) {
-      const u128 x = S.K[tid];
-      uint32_t r = 0;
-      for (uint32_t j = 0; j < kept; ++j) r += S.K[j] < x;
+    rank_kept(S.K, kept, [&](uint32_t i, const u128& x, uint32_t r) {
       store_key(out_keys, r, x);
-      out_counts[r] = S.C2[tid];
-    }
+      out_counts[r] = S.C2[i];
+    });
     __syncthreads();  // the next tile's inserts write K
     return kept;
   }
