@@ -116,6 +116,17 @@ __device__ __forceinline__ void stage_round(const uint64_t* __restrict__ rp, uin
   __syncthreads();
 }
 
+// Workgroups are dealt to the chip's 8 XCDs in turn (workgroup i to XCD
+// i mod 8), each XCD with its own L2.  xcd_task maps workgroup i so that XCD
+// x takes the contiguous tasks [x * per, (x + 1) * per): tasks are ordered by
+// bin and a bin's tiles take keys from that bin's tasks only, so the partial
+// lines that neighbouring tasks write into a tile meet in one L2.  The grid is
+// 8 * per workgroups; indices at or past n_tasks have no task.
+constexpr uint32_t kXcds = 8;
+__device__ __forceinline__ uint32_t xcd_task(uint32_t i, uint32_t per) {
+  return (i % kXcds) * per + i / kXcds;
+}
+
 // --------------------------------------------------------------- fine hist
 // One workgroup per task (a run of records of one bin); the task's keys are
 // counted per fine range in LDS, then added to the bin's global histogram.
@@ -236,7 +247,7 @@ template <int KW>
 __global__ void __launch_bounds__(kExpandThreads)
 k_expand_scatter(KeyCfg kc, TaskMap tm,
                  const uint64_t* __restrict__ records, const uint16_t* __restrict__ tile_of_fine,
-                 const uint64_t* __restrict__ tile_base, uint32_t mt,
+                 const uint64_t* __restrict__ tile_base, uint32_t mt, uint32_t n_tasks,
                  unsigned long long* tile_cursor, uint64_t* keys) {
   typedef typename KeyOf<KW>::T K;
   extern __shared__ __attribute__((aligned(16))) uint64_t lds64[];
@@ -247,7 +258,12 @@ k_expand_scatter(KeyCfg kc, TaskMap tm,
   uint32_t* cnt = reinterpret_cast<uint32_t*>(delta + mt);
   uint16_t* tof = reinterpret_cast<uint16_t*>(cnt + mt);
 
-  const ExpandTask tk = tm.get(blockIdx.x);  // n_rec <= kExpandThreads: one round
+  // 128-bit keys by XCD (the 16-byte scatter otherwise writes back about
+  // twice its bytes); 64-bit keys in launch order, which measured faster
+  const uint32_t task =
+      KW == 2 ? xcd_task(blockIdx.x, (n_tasks + kXcds - 1) / kXcds) : blockIdx.x;
+  if (task >= n_tasks) return;
+  const ExpandTask tk = tm.get(task);  // n_rec <= kExpandThreads: one round
   const uint16_t* gt = tile_of_fine + ((uint64_t)tk.bin << kc.fine_bits);
   for (uint32_t i = threadIdx.x; i < nf; i += blockDim.x) tof[i] = gt[i];
   const uint64_t tb = tile_base[tk.bin];
@@ -344,16 +360,17 @@ hipError_t launch_expand_scatter(hipStream_t s, const KeyCfg& kc, const TaskMap&
   const uint32_t nf = 1u << kc.fine_bits;
   const uint32_t mt = max_tiles_per_bin < 1 ? 1 : max_tiles_per_bin;
   const size_t sh = expand_lds(kc.key_words, mt, nf);
+  const uint32_t grid = kc.key_words == 2 ? (n_tasks + kXcds - 1) / kXcds * kXcds : n_tasks;
   if (kc.key_words == 1) {
     (void)hipFuncSetAttribute((const void*)k_expand_scatter<1>,
                         hipFuncAttributeMaxDynamicSharedMemorySize, (int)sh);
-    hipLaunchKernelGGL(k_expand_scatter<1>, dim3(n_tasks), dim3(kExpandThreads), sh, s, kc,
-                       tm, records, tile_of_fine, tile_base, mt, tile_cursor, keys);
+    hipLaunchKernelGGL(k_expand_scatter<1>, dim3(grid), dim3(kExpandThreads), sh, s, kc,
+                       tm, records, tile_of_fine, tile_base, mt, n_tasks, tile_cursor, keys);
   } else {
     (void)hipFuncSetAttribute((const void*)k_expand_scatter<2>,
                         hipFuncAttributeMaxDynamicSharedMemorySize, (int)sh);
-    hipLaunchKernelGGL(k_expand_scatter<2>, dim3(n_tasks), dim3(kExpandThreads), sh, s, kc,
-                       tm, records, tile_of_fine, tile_base, mt, tile_cursor, keys);
+    hipLaunchKernelGGL(k_expand_scatter<2>, dim3(grid), dim3(kExpandThreads), sh, s, kc,
+                       tm, records, tile_of_fine, tile_base, mt, n_tasks, tile_cursor, keys);
   }
   return hipGetLastError();
 }
