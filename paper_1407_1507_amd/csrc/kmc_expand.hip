@@ -65,6 +65,32 @@ __device__ __forceinline__ uint32_t top_bits(u128 key, uint32_t k, uint32_t bits
   return (uint32_t)(key >> (2 * k - bits));
 }
 
+// The top b bits of a canonical key, min(F, R) >> (2k - b), are min(F >> (2k
+// - b), R >> (2k - b)): a shift keeps the order.  So a walk that needs only
+// those bits keeps the forward key and just the top bits of the reverse
+// complement, which roll on their own: R' = (R >> 2) | (3 - c) << (2k - 2)
+// gives top(R') = (top(R) >> 2) | (3 - c) << (b - 2) (b >= 2).
+template <int KW> struct RecTop {
+  typedef typename KeyOf<KW>::T K;
+  K F, T;
+  uint32_t rt, n;
+  __device__ void load(const uint64_t* r, uint32_t k, uint32_t sh) {
+    Rec<KW> full;
+    full.load(r, k);
+    F = full.F;
+    T = full.T;
+    n = full.n;
+    rt = (uint32_t)(full.R >> sh);
+  }
+  __device__ uint32_t top(uint32_t sh) const { return min((uint32_t)(F >> sh), rt); }
+  __device__ void step(K kmask, uint32_t bits) {
+    const uint32_t c = (uint32_t)(T >> (8 * sizeof(K) - 2));
+    T <<= 2;
+    F = ((F << 2) | (K)c) & kmask;
+    rt = (rt >> 2) | ((3u - c) << (bits - 2));
+  }
+};
+
 // ------------------------------------------------------------ round staging
 // A super k-mer holds 1 .. w k-mers, so with one record per lane a wavefront
 // runs as long as its longest record.  Each round of up to 256 records is
@@ -152,7 +178,17 @@ k_fine_hist(KeyCfg kc, TaskMap tm, const uint64_t* __restrict__ records, uint32_
   for (uint32_t r0 = 0; r0 < tk.n_rec; r0 += kExpandThreads) {
     const uint32_t nr = min(tk.n_rec - r0, (uint32_t)kExpandThreads);
     stage_round<KW>(records + (tk.rec_begin + r0) * (2 * KW), nr, L);
-    if (threadIdx.x < nr) {
+    if (threadIdx.x < nr && kc.fine_bits >= 2) {
+      // only the top fine_bits bits of each key: see RecTop
+      const uint32_t sh = 2 * kc.k - kc.fine_bits;
+      RecTop<KW> rec;
+      rec.load(L.w + (uint32_t)L.perm[threadIdx.x] * (2 * KW), kc.k, sh);
+      for (uint32_t i = 0;; ++i) {
+        atomicAdd(&fh[rec.top(sh)], 1u);
+        if (i + 1 >= rec.n) break;
+        rec.step(kmask, kc.fine_bits);
+      }
+    } else if (threadIdx.x < nr) {
       Rec<KW> rec;
       rec.load(L.w + (uint32_t)L.perm[threadIdx.x] * (2 * KW), kc.k);
       for (uint32_t i = 0;; ++i) {
