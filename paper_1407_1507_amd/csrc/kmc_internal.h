@@ -90,6 +90,11 @@ hipError_t launch_split_wide(hipStream_t s, const uint8_t* seq, const uint64_t* 
                              const uint32_t* sig_to_bin, unsigned long long* cursor,
                              unsigned long long* kmer_cnt, const uint64_t* cap_base,
                              uint64_t* records);
+// Signature histogram of every stride-th read with the position-per-lane
+// scan (one read per wavefront when stride > 1): for long reads.
+hipError_t launch_sig_hist_wide(hipStream_t s, const uint8_t* seq, const uint64_t* offsets,
+                                uint64_t n_reads, uint64_t stride, const ScanCfg& cfg,
+                                uint32_t key_words, uint32_t* hist, unsigned long long* sample);
 hipError_t launch_debug_wide(hipStream_t s, const uint8_t* seq, const uint64_t* offsets,
                              uint64_t n_reads, const ScanCfg& cfg, uint32_t key_words,
                              uint32_t* sig, uint8_t* start);

@@ -69,7 +69,7 @@ __device__ __forceinline__ u128 ring_codes(const uint32_t* ring, int32_t z, uint
   return len >= 64 ? v : v & (((u128)1 << (2 * len)) - 1);
 }
 
-enum ScanMode { kSplitStaged = 0, kSplitDirect = 1, kDebug = 3 };
+enum ScanMode { kSplitStaged = 0, kSplitDirect = 1, kHist = 2, kDebug = 3 };
 
 struct ScanOut {
   // split
@@ -80,6 +80,11 @@ struct ScanOut {
   uint64_t* records;
   uint64_t n_bases;                    // bytes of seq (records are rebuilt from it)
   uint32_t cap;                        // staged records per workgroup
+  // signature histogram of a sample: k-mers per signature, then super
+  // k-mers per signature (n_sig each); sample[0] k-mers, sample[1] bases
+  uint32_t* hist;
+  uint32_t n_sig;
+  unsigned long long* sample;
   // debug
   uint32_t* dsig;
   uint8_t* dstart;
@@ -219,6 +224,7 @@ k_scan(const uint8_t* __restrict__ seq, const uint64_t* __restrict__ offsets, ui
   const uint32_t len = (uint32_t)(x_end - x_begin);
   // the byte of the next chunk is loaded one chunk ahead
   uint32_t bnext = lane < len ? seq[x_begin + lane] : 0u;
+  uint32_t hk = 0;  // sampled k-mers of this lane (histogram mode)
 
   for (uint32_t it = 0; it < iters; ++it) {
     if (it < n_chunks) {
@@ -296,7 +302,13 @@ k_scan(const uint8_t* __restrict__ seq, const uint64_t* __restrict__ offsets, ui
         if (kv) O.dsig[x_begin + (uint32_t)(x - (int32_t)C.k + 1)] = sig;
         if (st) O.dstart[x_begin + (uint32_t)(x - (int32_t)C.k + 1)] = 1;
       }
-      if (MODE != kDebug && E) {
+      if (MODE == kHist && e) {
+        const uint32_t n = (uint32_t)(x - s0);
+        atomicAdd(&O.hist[sigp], n);
+        atomicAdd(&O.hist[O.n_sig + sigp], 1u);
+        hk += n;
+      }
+      if ((MODE == kSplitStaged || MODE == kSplitDirect) && E) {
         const int32_t y = x - 1;
         const uint32_t n = (uint32_t)(y - s0 + 1);
         if (MODE == kSplitStaged) {
@@ -333,6 +345,14 @@ k_scan(const uint8_t* __restrict__ seq, const uint64_t* __restrict__ offsets, ui
   if (MODE == kSplitStaged) {
     __syncthreads();
     if (L.misc[0]) flush_stage<KW>(L, seq, C, O);
+  }
+  if (MODE == kHist) {
+    uint32_t t = hk;
+    for (int d = 32; d >= 1; d >>= 1) t += __shfl_xor(t, d, 64);
+    if (lane == 0 && len) {
+      atomicAdd(&O.sample[0], (unsigned long long)t);
+      atomicAdd(&O.sample[1], (unsigned long long)len);
+    }
   }
 }
 
@@ -395,6 +415,16 @@ hipError_t launch_split_wide(hipStream_t s, const uint8_t* seq, const uint64_t* 
   }
   return launch_scan<kSplitDirect>(s, seq, offsets, n_reads, cfg, key_words, 1,
                                    (size_t)kScanWaves * 256 * 4, o);
+}
+
+hipError_t launch_sig_hist_wide(hipStream_t s, const uint8_t* seq, const uint64_t* offsets,
+                                uint64_t n_reads, uint64_t stride, const ScanCfg& cfg,
+                                uint32_t key_words, uint32_t* hist, unsigned long long* sample) {
+  ScanOut o{};
+  o.hist = hist;
+  o.n_sig = cfg.sent + 1;
+  o.sample = sample;
+  return launch_scan<kHist>(s, seq, offsets, n_reads, cfg, key_words, stride, 0, o);
 }
 
 hipError_t launch_debug_wide(hipStream_t s, const uint8_t* seq, const uint64_t* offsets,

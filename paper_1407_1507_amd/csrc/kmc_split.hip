@@ -411,6 +411,11 @@ uint32_t grid_for(uint64_t n, uint32_t per) { return (uint32_t)((n + per - 1) / 
 
 // --------------------------------------------------------------- launchers
 
+// A lane walks a whole read one base per step, so long reads (a mean above
+// kLongRead bases) take the position-per-lane scan, which walks a read 64
+// bases per step.
+constexpr uint64_t kLongRead = 2048;
+
 // Window buffers hold u16 when every stored value (4^p + 1 at most) fits.
 static bool small_vt(const ScanCfg& c) { return c.sent + 1u <= 0xFFFFu; }
 static size_t vh_bytes(const ScanCfg& c, uint32_t lanes) {
@@ -456,6 +461,9 @@ hipError_t launch_sig_hist(hipStream_t s, const uint8_t* seq, const uint64_t* of
                            unsigned long long* sample) {
   const uint64_t n_sample = (n_reads + stride - 1) / stride;
   if (n_sample == 0) return hipSuccess;
+  if (n_bases > kLongRead * n_reads)
+    return launch_sig_hist_wide(s, seq, offsets, n_reads, stride, cfg, key_words, hist,
+                                sample);
   const uint32_t lanes = scan_lanes(cfg);
   const size_t sh = vh_bytes(cfg, lanes);
   KMC_SCAN_DISPATCH(k_sig_hist, dim3(grid_for(n_sample, lanes)), dim3(lanes), sh, s, seq,
@@ -472,6 +480,11 @@ static bool lane_scan_fits(const ScanCfg& c, uint32_t key_words) {
   return small_vt(c) && split_lds_bytes(c, key_words, 256) <= 80 * 1024;
 }
 
+static bool use_lane_scan(const ScanCfg& c, uint32_t key_words, uint64_t n_reads,
+                          uint64_t n_bases) {
+  return lane_scan_fits(c, key_words) && n_bases <= kLongRead * n_reads;
+}
+
 // The lane-per-read scan is used when 256 lanes' window buffers (16-bit
 // values) and record queues fit at least two workgroups per compute unit;
 // otherwise the scan with one position per lane (the same signatures and
@@ -484,7 +497,7 @@ hipError_t launch_split_scatter(hipStream_t s, const uint8_t* seq, const uint64_
                                 unsigned long long* cursor, unsigned long long* kmer_cnt,
                                 const uint64_t* cap_base, uint64_t* records) {
   if (n_reads == 0) return hipSuccess;
-  if (!lane_scan_fits(cfg, key_words))
+  if (!use_lane_scan(cfg, key_words, n_reads, n_bases))
     return launch_split_wide(s, seq, offsets, n_reads, n_bases, cfg, key_words, sig_to_bin,
                              cursor, kmer_cnt, cap_base, records);
   // largest workgroup whose window buffers + queues fit 80 KB (at least two per CU)
@@ -510,7 +523,7 @@ hipError_t launch_debug_sigs(hipStream_t s, const uint8_t* seq, const uint64_t* 
                              uint64_t n_reads, uint64_t n_bases, const ScanCfg& cfg,
                              uint32_t key_words, uint32_t* sig, uint8_t* start) {
   if (n_reads == 0) return hipSuccess;
-  if (!lane_scan_fits(cfg, key_words))
+  if (!use_lane_scan(cfg, key_words, n_reads, n_bases))
     return launch_debug_wide(s, seq, offsets, n_reads, cfg, key_words, sig, start);
   const uint32_t lanes = scan_lanes(cfg);
   const size_t sh = vh_bytes(cfg, lanes);

@@ -162,6 +162,23 @@ def test_window_signatures_match_oracle(ctx):
         assert np.all(start[~valid] == 0)
 
 
+def test_long_reads(ctx):
+    # a mean read length above 2 kbp takes the position-per-lane scan for every
+    # k (split, sample histogram and the per-window audit); reads of a few
+    # hundred kbp with N runs, beside short reads
+    rng = np.random.default_rng(5)
+    acgt = np.array(list("ACGT"))
+    reads = ["".join(rng.choice(acgt, size=n)) for n in (300_000, 120_000, 50_001)]
+    reads[1] = reads[1][:60_000] + "N" * 40 + reads[1][60_000:]
+    reads += random_reads(rng, 40, 0, 200, n_rate=0.01, lower=0.02)
+    seq, off = to_reads(reads)
+    for k, p, nb in ((28, 7, 512), (21, 5, 64), (33, 7, 256)):
+        res = ctx.count(seq, off, k, p, nb, 1, 2**32 - 1)
+        check_table(res, seq, off, k, p, 1, 2**32 - 1)
+    sig, _ = ctx.debug_signatures(seq, off, 28, 7, 0)
+    assert np.array_equal(sig, oracle.window_signatures(seq, off, 28, 7, True))
+
+
 # ------------------------------------------------------------- workloads
 
 
