@@ -507,16 +507,16 @@ void run_count(kmc_ctx* c, const kmc_reads* R, const kmc_params* P, kmc_table* T
   uint64_t n_tiles = 0, max_tiles = 0;
   for (uint32_t b = 0; b < J.n_bins; ++b) {
     tile_base[b] = n_tiles;
-    // greedy packing: two consecutive tiles hold more than tile_limit keys
-    const uint64_t nt = kmer_cnt[b] ? 2 * ((kmer_cnt[b] - 1) / kc.tile_limit + 1) + 1 : 0;
+    // greedy packing: two consecutive tiles hold more than tile_limit keys;
+    // and a tile holds at least one fine range, so a bin never has more tiles
+    // than fine ranges (a bin whose fine ranges exceed the limit has them as
+    // big tiles, sorted through HBM)
+    uint64_t nt = kmer_cnt[b] ? 2 * ((kmer_cnt[b] - 1) / kc.tile_limit + 1) + 1 : 0;
+    nt = std::min<uint64_t>(nt, 1ull << fb);
     n_tiles += nt;
     max_tiles = std::max(max_tiles, nt);
   }
-  tile_base[J.n_bins] = n_tiles;
-  if (max_tiles > (uint64_t)kMaxTilesPerBin) {
-    c->err = "a bin needs more sort tiles than the library supports; use more bins";
-    throw Fail{KMC_ERR_TOO_LARGE};
-  }
+  tile_base[J.n_bins] = n_tiles;  // max_tiles <= 2^fb <= kMaxTilesPerBin
   st.n_tiles = n_tiles;
   // tasks: fine-histogram tasks of up to hrec records, expansion tasks of one
   // record per lane; only per-bin task offsets go to the device, which lists

@@ -15,7 +15,7 @@ constexpr int kSortThreads = 256;        // threads of a tile-sort workgroup
 constexpr int kTileCap1 = 4096;          // keys of one LDS tile (1-word keys)
 constexpr int kTileCap2 = 2048;          // same, 2-word keys
 constexpr int kMaxFineBits = 12;         // fine ranges per bin: at most 2^12
-constexpr int kMaxTilesPerBin = 4096;
+constexpr int kMaxTilesPerBin = 1 << kMaxFineBits;  // a tile holds >= 1 fine range
 
 // Parameters of the split (signature scan) kernels.
 struct ScanCfg {

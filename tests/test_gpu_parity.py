@@ -162,6 +162,19 @@ def test_window_signatures_match_oracle(ctx):
         assert np.all(start[~valid] == 0)
 
 
+@pytest.mark.parametrize("k,p,n_reads", [(28, 7, 100_000), (40, 7, 60_000)])
+def test_one_huge_bin(ctx, k, p, n_reads):
+    # every k-mer in one bin: more keys than 4096 tiles of the tile limit hold,
+    # so fine ranges above the limit become big tiles (this once returned
+    # KMC_ERR_TOO_LARGE)
+    rng = np.random.default_rng(k)
+    seq = rng.choice(np.frombuffer(b"ACGT", dtype=np.uint8), size=n_reads * 100)
+    off = np.arange(n_reads + 1, dtype=np.uint64) * 100
+    res = ctx.count(seq, off, k, p, 1, 1, 2**32 - 1)
+    assert res.stats["n_big_tiles"] > 0
+    check_table(res, seq, off, k, p, 1, 2**32 - 1)
+
+
 def test_long_reads(ctx):
     # a mean read length above 2 kbp takes the position-per-lane scan for every
     # k (split, sample histogram and the per-window audit); reads of a few
