@@ -332,7 +332,8 @@ __device__ __forceinline__ uint32_t count_tile_hash(uint64_t (&key)[SortCfg<1>::
   constexpr uint32_t ITEMS = SortCfg<1>::ITEMS, T = SortCfg<1>::CAP, TB = 12;
   static_assert((1u << TB) == T, "table size");
   constexpr uint64_t EMPTY = ~0ull;
-  const uint32_t tid = threadIdx.x, nt = blockDim.x;
+  const uint32_t tid = threadIdx.x;
+  constexpr uint32_t nt = kSortThreads;  // every launch of the tile kernels
   if (!kClean) {
     for (uint32_t s = tid; s < T; s += nt) {
       S.A[s] = EMPTY;
@@ -340,44 +341,66 @@ __device__ __forceinline__ uint32_t count_tile_hash(uint64_t (&key)[SortCfg<1>::
     }
     __syncthreads();
   }
+  // A wave has few partners to hide LDS latency behind (the table limits a
+  // compute unit to three workgroups), so the first probes of G keys are
+  // issued before any result is awaited, and the read-back issues all its
+  // loads at once: one LDS round trip per group instead of one per key.
+  constexpr uint32_t G = 4;
 #pragma unroll
-  for (uint32_t m = 0; m < ITEMS; ++m) {
-    if (m * nt + tid < n) {
-      uint32_t slot = hash_top(key[m], TB);
-      for (;;) {
-        const unsigned long long old = atomicCAS(
-            reinterpret_cast<unsigned long long*>(&S.A[slot]), (unsigned long long)EMPTY,
-            (unsigned long long)key[m]);
-        if (old == EMPTY || old == key[m]) {
-          atomicAdd(&S.H[slot], 1u);
-          break;
+  for (uint32_t g = 0; g < ITEMS; g += G) {
+    if (g * nt < n) {  // uniform
+      uint64_t old[G];
+      uint32_t slot[G];
+#pragma unroll
+      for (uint32_t u = 0; u < G; ++u) {
+        slot[u] = hash_top(key[g + u], TB);
+        old[u] = 0;
+        if ((g + u) * nt + tid < n)
+          old[u] = atomicCAS(reinterpret_cast<unsigned long long*>(&S.A[slot[u]]),
+                             (unsigned long long)EMPTY, (unsigned long long)key[g + u]);
+      }
+#pragma unroll
+      for (uint32_t u = 0; u < G; ++u) {
+        if ((g + u) * nt + tid < n) {
+          uint32_t sl = slot[u];
+          uint64_t ov = old[u];
+          while (ov != EMPTY && ov != key[g + u]) {  // linear probing on a clash
+            sl = (sl + 1) & (T - 1);
+            ov = atomicCAS(reinterpret_cast<unsigned long long*>(&S.A[sl]),
+                           (unsigned long long)EMPTY, (unsigned long long)key[g + u]);
+          }
+          atomicAdd(&S.H[sl], 1u);
         }
-        slot = (slot + 1) & (T - 1);
       }
     }
   }
   __syncthreads();
-  // read back (and clear) the occupied slots
+  // read back (and clear) every slot; an empty slot reads count 0 < ci
   uint32_t cnt[ITEMS];
-  uint32_t nh = 0, nk = 0;
-  uint64_t a = ~0ull, o = 0;
 #pragma unroll
   for (uint32_t i = 0; i < ITEMS; ++i) {  // T == ITEMS * threads
     const uint32_t s = i * nt + tid;
-    const uint64_t x = S.A[s];
-    cnt[i] = 0;
-    if (x != EMPTY) {
-      ++nh;
-      const uint32_t c = S.H[s];
-      S.A[s] = EMPTY;
-      S.H[s] = 0;
-      if (c >= ci && c <= cx) {
-        key[i] = x;
-        cnt[i] = c;
-        a &= x;
-        o |= x;
-        ++nk;
-      }
+    key[i] = S.A[s];
+    cnt[i] = S.H[s];
+  }
+#pragma unroll
+  for (uint32_t i = 0; i < ITEMS; ++i) {
+    const uint32_t s = i * nt + tid;
+    S.A[s] = EMPTY;
+    S.H[s] = 0;
+  }
+  uint32_t nh = 0, nk = 0;
+  uint64_t a = ~0ull, o = 0;
+#pragma unroll
+  for (uint32_t i = 0; i < ITEMS; ++i) {
+    const uint32_t c = cnt[i];
+    nh += c != 0;
+    const bool keep = c >= ci && c <= cx;
+    cnt[i] = keep ? c : 0u;
+    if (keep) {
+      a &= key[i];
+      o |= key[i];
+      ++nk;
     }
   }
   // distinct keys (high half) and kept keys (low half) in one scan; both
