@@ -483,29 +483,43 @@ __device__ uint32_t count_tile_hash2(u128 (&key)[SortCfg<2>::ITEMS], uint32_t n,
                                      uint32_t cx, HashShared2& S, uint32_t* distinct) {
   constexpr uint32_t ITEMS = SortCfg<2>::ITEMS, T = kHashSlots2;
   static_assert(T == ITEMS * kSortThreads, "one slot per register slot");
-  const uint32_t tid = threadIdx.x, nt = blockDim.x;
+  const uint32_t tid = threadIdx.x;
+  constexpr uint32_t nt = kSortThreads;  // every launch of the tile kernels
+  // As for 64-bit keys: the first probes of G keys go out before any result
+  // is awaited, and the checks and the read-back issue all their loads at once.
+  constexpr uint32_t G = 4;
   uint32_t slot_of[ITEMS];
 #pragma unroll
-  for (uint32_t m = 0; m < ITEMS; ++m) {
-    if (m * nt + tid < n) {
-      const uint64_t h = mix128(key[m]);
-      uint32_t slot = (uint32_t)(h >> (64 - kHashBits2));
-      const uint64_t fp = (h & ((1ull << 47) - 1)) | (1ull << 47);  // never 0
-      for (;;) {
-        const unsigned long long old = atomicCAS(
-            reinterpret_cast<unsigned long long*>(&S.F[slot]), 0ull,
-            (unsigned long long)((fp << 16) | 1u));
-        if (old == 0) {
-          S.K[slot] = key[m];
-          break;
-        }
-        if ((old >> 16) == fp) {
-          atomicAdd(reinterpret_cast<unsigned long long*>(&S.F[slot]), 1ull);
-          break;
-        }
-        slot = (slot + 1) & (T - 1);
+  for (uint32_t g = 0; g < ITEMS; g += G) {
+    if (g * nt < n) {  // uniform
+      uint64_t old[G], fp[G];
+#pragma unroll
+      for (uint32_t u = 0; u < G; ++u) {
+        const uint64_t h = mix128(key[g + u]);
+        slot_of[g + u] = (uint32_t)(h >> (64 - kHashBits2));
+        fp[u] = (h & ((1ull << 47) - 1)) | (1ull << 47);  // never 0
+        old[u] = 0;
+        if ((g + u) * nt + tid < n)
+          old[u] = atomicCAS(reinterpret_cast<unsigned long long*>(&S.F[slot_of[g + u]]), 0ull,
+                             (unsigned long long)((fp[u] << 16) | 1u));
       }
-      slot_of[m] = slot;
+#pragma unroll
+      for (uint32_t u = 0; u < G; ++u) {
+        if ((g + u) * nt + tid < n) {
+          uint32_t slot = slot_of[g + u];
+          uint64_t ov = old[u];
+          while (ov != 0 && (ov >> 16) != fp[u]) {  // linear probing on a clash
+            slot = (slot + 1) & (T - 1);
+            ov = atomicCAS(reinterpret_cast<unsigned long long*>(&S.F[slot]), 0ull,
+                           (unsigned long long)((fp[u] << 16) | 1u));
+          }
+          if (ov == 0)
+            S.K[slot] = key[g + u];
+          else
+            atomicAdd(reinterpret_cast<unsigned long long*>(&S.F[slot]), 1ull);
+          slot_of[g + u] = slot;
+        }
+      }
     }
   }
   __syncthreads();
@@ -518,26 +532,29 @@ __device__ uint32_t count_tile_hash2(u128 (&key)[SortCfg<2>::ITEMS], uint32_t n,
     __syncthreads();
     return kFingerprintClash;
   }
-  // read back (and clear) the occupied slots
+  // read back (and clear) every slot; an empty slot reads 0
   uint32_t cnt[ITEMS];
-  uint32_t nh = 0, nk = 0;
-  u128 a = ~(u128)0, o = 0;
 #pragma unroll
   for (uint32_t i = 0; i < ITEMS; ++i) {
     const uint32_t s = i * nt + tid;
     const uint64_t w = S.F[s];
-    cnt[i] = 0;
-    if (w) {
-      ++nh;
-      const uint32_t c = (uint32_t)(w & 0xFFFFu);
-      S.F[s] = 0;
-      if (c >= ci && c <= cx) {
-        key[i] = S.K[s];
-        cnt[i] = c;
-        a &= key[i];
-        o |= key[i];
-        ++nk;
-      }
+    key[i] = S.K[s];
+    cnt[i] = (uint32_t)(w & 0xFFFFu);
+  }
+#pragma unroll
+  for (uint32_t i = 0; i < ITEMS; ++i) S.F[i * nt + tid] = 0;
+  uint32_t nh = 0, nk = 0;
+  u128 a = ~(u128)0, o = 0;
+#pragma unroll
+  for (uint32_t i = 0; i < ITEMS; ++i) {
+    const uint32_t c = cnt[i];
+    nh += c != 0;
+    const bool keep = c >= ci && c <= cx;
+    cnt[i] = keep ? c : 0u;
+    if (keep) {
+      a &= key[i];
+      o |= key[i];
+      ++nk;
     }
   }
   // distinct keys (high half) and kept keys (low half) in one scan
