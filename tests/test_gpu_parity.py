@@ -162,17 +162,27 @@ def test_window_signatures_match_oracle(ctx):
         assert np.all(start[~valid] == 0)
 
 
-@pytest.mark.parametrize("k,p,n_reads", [(28, 7, 100_000), (40, 7, 60_000)])
+@pytest.mark.parametrize("k,p,n_reads", [(28, 7, 100_000), (40, 7, 60_000), (28, 7, 200_000)])
 def test_one_huge_bin(ctx, k, p, n_reads):
     # every k-mer in one bin: more keys than 4096 tiles of the tile limit hold,
     # so fine ranges above the limit become big tiles (this once returned
-    # KMC_ERR_TOO_LARGE)
+    # KMC_ERR_TOO_LARGE); at 200 000 reads ranges hold more distinct keys
+    # than the LDS table has slots
     rng = np.random.default_rng(k)
     seq = rng.choice(np.frombuffer(b"ACGT", dtype=np.uint8), size=n_reads * 100)
     off = np.arange(n_reads + 1, dtype=np.uint64) * 100
     res = ctx.count(seq, off, k, p, 1, 1, 2**32 - 1)
     assert res.stats["n_big_tiles"] > 0
     check_table(res, seq, off, k, p, 1, 2**32 - 1)
+
+
+def test_skewed_ranges(ctx):
+    # reads at 40x coverage in 64 bins: the k-mers that begin with their
+    # signature fill fine ranges of several thousand keys (big tiles), about a
+    # quarter of them distinct
+    seq, off, p = synth.make("genome-5M-2Mx100", 0.1)
+    res = ctx.count(seq, off, p["k"], p["p"], 64, p["cutoff_min"], p["cutoff_max"])
+    check_table(res, seq, off, p["k"], p["p"], p["cutoff_min"], p["cutoff_max"])
 
 
 def test_long_reads(ctx):
