@@ -8,15 +8,18 @@
 // only if cutoff_min <= count <= cutoff_max, decided here where the total
 // count is known.
 //
-// Tile sort (one workgroup per tile, keys held in LDS): the keys of a tile
-// share their leading bits; one most-significant-digit counting pass on the
-// next DIG bits (LDS histogram, scan, scatter with atomic slot claims) puts
-// them into 2^DIG buckets of about one distinct key each, which are then
-// finished by insertion sort (a lane per bucket) or, for the rare large
-// bucket, by a workgroup-wide rank sort.  An MSD pass needs no stable
-// ranking, which a 64-wide wave has no cheap primitive for.  Tiles larger
-// than LDS take the same MSD passes through HBM (8-bit digits, recursive)
-// until their pieces fit.
+// Tile counting (a persistent workgroup per compute-unit slot, one tile at
+// a time, the tile's keys in registers): every key goes into an LDS hash
+// table whose per-slot counter ends equal to the run length a sort would
+// give it; the slots are read back, the cutoffs applied, and only the kept
+// keys are put in key order (a rank sort, or a counting pass on the key digit
+// below their common prefix).  64-bit keys claim slots by a 64-bit
+// compare-and-swap; 128-bit keys by a fingerprint, with the full key beside
+// it and a check that no two keys of the tile share one.  Tiles above the
+// tile limit, and 128-bit tiles whose fingerprints clash, take most-
+// significant-digit passes through HBM (8-bit digits) until their pieces
+// fit, and the pieces are counted the same way (128-bit pieces by hashed
+// buckets sorted in LDS).
 #include <algorithm>
 #include <atomic>
 
