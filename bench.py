@@ -31,6 +31,10 @@ DESCRIPTION = {
     "repeats-50M-30x150-k55": ("10,000,000 reads x 150 bp from a 50 Mbp reference with 20% "
                                "repeat families, 0.5% substitutions, 0.1% N; k=55, p=9, "
                                "1024 bins, cutoff_min=2, cutoff_max=1e6"),
+    "large-300M-60Mx150": ("60,000,000 reads x 150 bp (9 Gbases) from a uniform 300 Mbp "
+                           "reference, 0.5% substitutions, 0.1% N; k=28, p=7, 2048 bins, "
+                           "cutoff_min=2, cutoff_max=1e9 (the served form's large job, "
+                           "alone)"),
 }
 
 
@@ -324,6 +328,7 @@ def main():
     from paper_1407_1507_amd import kmc, synth
 
     seq, off, p = synth.make(args.workload)
+    print(f"generated {args.workload}: {seq.size} bases", file=sys.stderr, flush=True)
     dseq = torch.from_numpy(seq).to("cuda:0")
     doff = torch.from_numpy(off.view(np.int64)).to("cuda:0")
     torch.cuda.synchronize()

@@ -21,6 +21,9 @@ experiments; the paper's own datasets are not used, these stand in for them):
   d ~ U[0, 0.10] substitutions).
 - ``batch_job`` / ``served_job``: the uneven jobs of the batched form and the
   arrivals of the served form.
+- ``large-300M-60Mx150``: the served form's large job, 60M reads x 150 bp
+  (9 Gbases) from a uniform 300 Mbp reference, drawn in chunks of 2^20
+  reads, chunk c with seed (500, 1, c).
 """
 from __future__ import annotations
 
@@ -120,6 +123,46 @@ def sample_reads(seed, ref: np.ndarray, n_reads: int, read_len, err: float,
     return seq, offsets
 
 
+_SHARED_REF = None  # reference of the chunked generator, inherited by forked workers
+
+
+def _reads_chunk(task):
+    seed, c, n, read_len, err, n_rate = task
+    return sample_reads((*seed, c), _SHARED_REF, n, read_len, err, n_rate)
+
+
+def sample_reads_chunked(seed, ref: np.ndarray, n_reads: int, read_len: int, err: float,
+                         n_rate: float, chunk: int = 1 << 20, workers: int = 0):
+    """Reads like sample_reads, in chunks of ``chunk`` reads, chunk c drawn
+    with seed (*seed, c) (so the chunks can be drawn by parallel processes);
+    the read set is the chunks in order."""
+    global _SHARED_REF
+    import os
+    workers = workers or min(16, os.cpu_count() or 1)
+    tasks = [(tuple(seed), c, min(chunk, n_reads - c0), read_len, err, n_rate)
+             for c, c0 in enumerate(range(0, n_reads, chunk))]
+    _SHARED_REF = ref
+    try:
+        if workers > 1 and len(tasks) > 1:
+            import multiprocessing as mp
+            with mp.get_context("fork").Pool(min(workers, len(tasks))) as pool:
+                parts = pool.map(_reads_chunk, tasks, chunksize=1)
+        else:
+            parts = [_reads_chunk(t) for t in tasks]
+    finally:
+        _SHARED_REF = None
+    offsets = np.zeros(n_reads + 1, dtype=np.uint64)
+    seq = np.empty(sum(int(pt[1][-1]) for pt in parts), dtype=np.uint8)
+    r = b = 0
+    for ps, po in parts:
+        m = po.size - 1
+        offsets[r + 1:r + m + 1] = po[1:] + np.uint64(b)
+        seq[b:b + ps.size] = ps
+        r += m
+        b += ps.size
+    return seq, offsets
+
+
 def uniform_reads(seed, n_reads: int, read_len: int):
     rng = _rng(seed)
     codes = rng.integers(0, 4, size=n_reads * read_len, dtype=np.uint8)
@@ -139,6 +182,9 @@ CONFIGS = {
     "uniform-10k": dict(k=28, p=7, n_bins=512, cutoff_min=1, cutoff_max=10**9),
     "genome-5M-2Mx100": dict(k=28, p=7, n_bins=512, cutoff_min=2, cutoff_max=10**9),
     "repeats-50M-30x150-k55": dict(k=55, p=9, n_bins=1024, cutoff_min=2, cutoff_max=10**6),
+    # the served form's large job; 2048 bins keep bins near 3.5M keys, which
+    # 2^12 fine ranges split into LDS tiles (512 bins would leave 14M)
+    "large-300M-60Mx150": dict(k=28, p=7, n_bins=2048, cutoff_min=2, cutoff_max=10**9),
 }
 
 
@@ -184,6 +230,10 @@ def make(name: str, scale: float = 1.0):
         ref = repeat_reference((3, 0), max(20_000, int(50_000_000 * scale)))
         seq, off = sample_reads((3, 1), ref, max(1, int(10_000_000 * scale)), 150,
                                 err=0.005, n_rate=0.001)
+    elif name == "large-300M-60Mx150":
+        ref = random_reference((500, 0), max(1000, int(300_000_000 * scale)))
+        seq, off = sample_reads_chunked((500, 1), ref, max(1, int(60_000_000 * scale)), 150,
+                                        err=0.005, n_rate=0.001)
     else:
         raise KeyError(name)
     return seq, off, params
