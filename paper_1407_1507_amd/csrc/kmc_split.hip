@@ -131,18 +131,31 @@ __device__ __forceinline__ VT* lane_vh(void* lds, uint32_t w) {
 
 // ------------------------------------------------------------ sample hist
 
+// Signatures below kLdsSig are counted in the workgroup's LDS first: the
+// smallest canonical m-mers are the most frequent minimizers, and their
+// global counters would otherwise take most of the sample's atomics on a few
+// addresses.
+constexpr uint32_t kLdsSig = 4096;
+
 template <int KW>
 struct HistSink {
   static constexpr bool kNeedKeys = false;
   uint32_t* hist_k;   // k-mers per signature
   uint32_t* hist_r;   // super k-mers per signature
+  uint32_t* lds_k;    // the same for signatures below kLdsSig, in LDS
+  uint32_t* lds_r;
   uint64_t kmers;
   __device__ void kmer(uint64_t, uint32_t, uint64_t, uint64_t) {}
   __device__ uint32_t bin_of(uint32_t) { return 0; }
   __device__ void superkmer(uint64_t, uint32_t n, uint32_t sig, uint32_t,
                             typename KeyOf<KW>::T, typename KeyOf<KW>::T) {
-    atomicAdd(&hist_k[sig], n);
-    atomicAdd(&hist_r[sig], 1u);
+    if (sig < kLdsSig) {
+      atomicAdd(&lds_k[sig], n);
+      atomicAdd(&lds_r[sig], 1u);
+    } else {
+      atomicAdd(&hist_k[sig], n);
+      atomicAdd(&hist_r[sig], 1u);
+    }
     kmers += n;
   }
 };
@@ -155,7 +168,13 @@ k_sig_hist(const uint8_t* __restrict__ seq, const uint64_t* __restrict__ offsets
   extern __shared__ __attribute__((aligned(16))) uint8_t lds8[];
   const uint64_t r = ((uint64_t)blockIdx.x * blockDim.x + threadIdx.x) * stride;
   const uint32_t n_sig = C.sent + 1;
-  HistSink<KW> sink{hist, hist + n_sig, 0};
+  const uint32_t nl = min(n_sig, kLdsSig);
+  const size_t vb = ((size_t)blockDim.x * (2 * C.w + 1) * sizeof(VT) + 15) & ~(size_t)15;
+  uint32_t* lk = reinterpret_cast<uint32_t*>(lds8 + vb);  // after the window buffers
+  uint32_t* lr = lk + nl;
+  for (uint32_t i = threadIdx.x; i < 2 * nl; i += blockDim.x) lk[i] = 0;
+  __syncthreads();
+  HistSink<KW> sink{hist, hist + n_sig, lk, lr, 0};
   uint64_t bases = 0;
   if (r < n_reads) {
     bases = offsets[r + 1] - offsets[r];
@@ -163,6 +182,13 @@ k_sig_hist(const uint8_t* __restrict__ seq, const uint64_t* __restrict__ offsets
   }
   if (sink.kmers) atomicAdd(&sample[0], (unsigned long long)sink.kmers);
   if (bases) atomicAdd(&sample[1], (unsigned long long)bases);
+  __syncthreads();
+  for (uint32_t i = threadIdx.x; i < nl; i += blockDim.x) {
+    if (lr[i]) {
+      atomicAdd(&hist[i], lk[i]);
+      atomicAdd(&hist[n_sig + i], lr[i]);
+    }
+  }
 }
 
 // ---------------------------------------------------------- split scatter
@@ -465,7 +491,7 @@ hipError_t launch_sig_hist(hipStream_t s, const uint8_t* seq, const uint64_t* of
     return launch_sig_hist_wide(s, seq, offsets, n_reads, stride, cfg, key_words, hist,
                                 sample);
   const uint32_t lanes = scan_lanes(cfg);
-  const size_t sh = vh_bytes(cfg, lanes);
+  const size_t sh = vh_bytes(cfg, lanes) + 2 * std::min<size_t>(cfg.sent + 1, kLdsSig) * 4;
   KMC_SCAN_DISPATCH(k_sig_hist, dim3(grid_for(n_sample, lanes)), dim3(lanes), sh, s, seq,
                     offsets, n_reads, n_bases, stride, cfg, hist, sample);
   return hipGetLastError();
