@@ -534,12 +534,15 @@ void run_count(kmc_ctx* c, const kmc_reads* R, const kmc_params* P, kmc_table* T
   const uint64_t* d_key_base = d_bases + nb1;
   const uint64_t* d_tile_base = d_bases + 2 * nb1;
   uint16_t* d_hbin = ensure<uint16_t>(c, B_HTASK, std::max<uint64_t>(1, n_htasks) * 2);
-  uint16_t* d_ebin = ensure<uint16_t>(c, B_ETASK, std::max<uint64_t>(1, n_etasks) * 2);
-  check(c, launch_task_bins(s, J.n_bins, d_bases + 4 * nb1, d_hbin, d_bases + 5 * nb1, d_ebin),
+  ExpandTask* d_etask =
+      ensure<ExpandTask>(c, B_ETASK, std::max<uint64_t>(1, n_etasks) * sizeof(ExpandTask));
+  check(c, launch_task_bins(s, J.n_bins, d_bases + 4 * nb1, d_hbin, d_bases + 5 * nb1, d_bases,
+                            d_bases + 3 * nb1, (uint32_t)kExpandThreads, d_etask),
         "task_bins");
-  const TaskMap hmap{d_hbin, d_bases + 4 * nb1, d_bases, d_bases + 3 * nb1, (uint32_t)hrec};
-  const TaskMap emap{d_ebin, d_bases + 5 * nb1, d_bases, d_bases + 3 * nb1,
-                     (uint32_t)kExpandThreads};
+  const TaskMap hmap{d_hbin, d_bases + 4 * nb1, d_bases, d_bases + 3 * nb1, (uint32_t)hrec,
+                     nullptr};
+  const TaskMap emap{nullptr, d_bases + 5 * nb1, d_bases, d_bases + 3 * nb1,
+                     (uint32_t)kExpandThreads, d_etask};
   const size_t nfine = (size_t)J.n_bins << fb;
   uint32_t* fine = ensure<uint32_t>(c, B_FINE, nfine * 4);
   check(c, hipMemsetAsync(fine, 0, nfine * 4, s), "memset");

@@ -158,10 +158,18 @@ __device__ __forceinline__ uint32_t xcd_task(uint32_t i, uint32_t per) {
 // counted per fine range in LDS, then added to the bin's global histogram.
 __global__ void __launch_bounds__(256)
 k_task_bins(const uint64_t* __restrict__ pre_a, uint16_t* bin_a, const uint64_t* __restrict__ pre_b,
-            uint16_t* bin_b) {
+            const uint64_t* __restrict__ rec_base, const uint64_t* __restrict__ rec_end,
+            uint32_t per_b, ExpandTask* desc_b) {
   const uint32_t b = blockIdx.x;
   for (uint64_t t = pre_a[b] + threadIdx.x; t < pre_a[b + 1]; t += blockDim.x) bin_a[t] = (uint16_t)b;
-  for (uint64_t t = pre_b[b] + threadIdx.x; t < pre_b[b + 1]; t += blockDim.x) bin_b[t] = (uint16_t)b;
+  for (uint64_t t = pre_b[b] + threadIdx.x; t < pre_b[b + 1]; t += blockDim.x) {
+    ExpandTask k;
+    k.bin = b;
+    k.rec_begin = rec_base[b] + (t - pre_b[b]) * per_b;
+    const uint64_t left = rec_end[b] - k.rec_begin;
+    k.n_rec = left < per_b ? (uint32_t)left : per_b;
+    desc_b[t] = k;
+  }
 }
 
 template <int KW>
@@ -358,8 +366,10 @@ static size_t expand_lds(int kw, uint32_t mt, uint32_t nf) {
 }
 
 hipError_t launch_task_bins(hipStream_t s, uint32_t n_bins, const uint64_t* pre_a,
-                            uint16_t* bin_a, const uint64_t* pre_b, uint16_t* bin_b) {
-  hipLaunchKernelGGL(k_task_bins, dim3(n_bins), dim3(256), 0, s, pre_a, bin_a, pre_b, bin_b);
+                            uint16_t* bin_a, const uint64_t* pre_b, const uint64_t* rec_base,
+                            const uint64_t* rec_end, uint32_t per_b, ExpandTask* desc_b) {
+  hipLaunchKernelGGL(k_task_bins, dim3(n_bins), dim3(256), 0, s, pre_a, bin_a, pre_b, rec_base,
+                     rec_end, per_b, desc_b);
   return hipGetLastError();
 }
 

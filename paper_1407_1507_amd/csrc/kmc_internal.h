@@ -37,14 +37,17 @@ struct ExpandTask {
 
 // Tasks of a per-record kernel: bin b's records [rec_base[b], rec_end[b]) in
 // runs of `per`, tasks pre[b] .. pre[b+1] - 1; bin[t] is the bin of task t
-// (filled on the device by launch_task_bins).
+// (filled on the device by launch_task_bins), or, when desc is set, desc[t]
+// is task t whole (one load instead of two dependent ones).
 struct TaskMap {
   const uint16_t* bin;
   const uint64_t* pre;
   const uint64_t* rec_base;
   const uint64_t* rec_end;
   uint32_t per;
+  const ExpandTask* desc;
   __device__ __forceinline__ ExpandTask get(uint32_t t) const {
+    if (desc) return desc[t];
     ExpandTask k;
     k.bin = bin[t];
     k.rec_begin = rec_base[k.bin] + (uint64_t)(t - pre[k.bin]) * per;
@@ -116,7 +119,8 @@ struct KeyCfg {
 
 // bin[t] for every task t of two task maps (pre arrays of n_bins + 1).
 hipError_t launch_task_bins(hipStream_t s, uint32_t n_bins, const uint64_t* pre_a,
-                            uint16_t* bin_a, const uint64_t* pre_b, uint16_t* bin_b);
+                            uint16_t* bin_a, const uint64_t* pre_b, const uint64_t* rec_base,
+                            const uint64_t* rec_end, uint32_t per_b, ExpandTask* desc_b);
 
 // Fine-range histogram of every bin: fine_hist[bin << fine_bits | range].
 hipError_t launch_fine_hist(hipStream_t s, const KeyCfg& kc, const TaskMap& tm,
