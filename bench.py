@@ -339,18 +339,18 @@ def main():
     for _ in range(args.warmup):
         run().free()
     torch.cuda.synchronize()
-    lat, stats, tables = [], [], []
+    # each step's table is freed once the call returns: its block goes back to
+    # the library's pool and holds the next step's table, as in a stream of jobs
+    lat, stats = [], []
     t0 = time.perf_counter()
     for _ in range(args.steps):
         s = time.perf_counter()
         r = run()
         lat.append(time.perf_counter() - s)
         stats.append(r.stats)
-        tables.append(r)
+        r.free()
     torch.cuda.synchronize()
     t1 = time.perf_counter()
-    for r in tables:
-        r.free()
     ms = (t1 - t0) * 1e3 / args.steps
     st = stats[-1]
     n_bases, n_kmers = st["n_bases"], st["n_kmers"]
