@@ -145,8 +145,9 @@ void build_map(const std::vector<uint32_t>& hist, uint32_t n_bins, std::vector<u
   std::vector<uint32_t> a, b;
   a.reserve(n_sig);
   uint32_t maxc = 0;
-  for (uint32_t s = 0; s < n_sig; ++s) {
-    map[s] = s % n_bins;
+  for (uint32_t s = 0, m = 0; s < n_sig; ++s) {
+    map[s] = m;  // s % n_bins, without a division per signature
+    if (++m == n_bins) m = 0;
     if (hist[s]) {
       a.push_back(s);
       maxc = std::max(maxc, hist[s]);
@@ -162,24 +163,23 @@ void build_map(const std::vector<uint32_t>& hist, uint32_t n_bins, std::vector<u
     for (uint32_t s : a) b[cnt[(~hist[s] >> shift) & 2047u]++] = s;
     a.swap(b);
   }
-  // each to the lightest bin: binary min-heap of (load << 16 | bin), so equal
-  // loads go to the lowest bin id (n_bins <= 65535)
-  std::vector<uint64_t> heap(n_bins);
-  for (uint32_t i = 0; i < n_bins; ++i) heap[i] = i;
+  // each to the lightest bin: the minimum of (load << 16 | bin) over the bins,
+  // so equal loads go to the lowest bin id (n_bins <= 65535), kept by a
+  // tournament tree (leaves = bins, each node the minimum of its children):
+  // an update recomputes one path with branch-free minima, where a heap's
+  // sift-down mispredicts a branch per level
+  uint32_t nl = 1;
+  while (nl < n_bins) nl <<= 1;
+  std::vector<uint64_t> tree(2 * nl, ~0ull);
+  for (uint32_t b = 0; b < n_bins; ++b) tree[nl + b] = b;
+  for (uint32_t i = nl - 1; i >= 1; --i) tree[i] = std::min(tree[2 * i], tree[2 * i + 1]);
   for (uint32_t s : a) {
-    uint64_t top = heap[0];
-    map[s] = (uint32_t)(top & 0xFFFFu);
-    top += (uint64_t)hist[s] << 16;
-    uint32_t i = 0;
-    for (;;) {
-      const uint32_t l = 2 * i + 1;
-      if (l >= n_bins) break;
-      const uint32_t m = (l + 1 < n_bins && heap[l + 1] < heap[l]) ? l + 1 : l;
-      if (heap[m] >= top) break;
-      heap[i] = heap[m];
-      i = m;
-    }
-    heap[i] = top;
+    const uint64_t top = tree[1];
+    const uint32_t bin = (uint32_t)(top & 0xFFFFu);
+    map[s] = bin;
+    uint32_t i = nl + bin;
+    tree[i] = top + ((uint64_t)hist[s] << 16);
+    for (i >>= 1; i >= 1; i >>= 1) tree[i] = std::min(tree[2 * i], tree[2 * i + 1]);
   }
 }
 
