@@ -172,7 +172,7 @@ __device__ void flush_stage(const StageLayout& L, const uint8_t* __restrict__ se
 // bytes x - k + 1 .. x.  A super k-mer is emitted in the chunk that sees the
 // position after its last k-mer.
 template <int KW, int MODE>
-__global__ void __launch_bounds__(kScanWaves * 64)
+__global__ void __launch_bounds__(kScanWaves * 64, 5)  // five workgroups per compute unit, as the LDS allows
 k_scan(const uint8_t* __restrict__ seq, const uint64_t* __restrict__ offsets, uint64_t n_reads,
        ScanCfg C, uint32_t rpw, uint64_t stride, ScanOut O) {
   typedef typename KeyOf<KW>::T K;
