@@ -40,8 +40,11 @@ namespace {
 // p-mer values are grouped in blocks of w; when a block completes its suffix
 // minima are formed in place; the window of a k-mer spans the suffix of one
 // block and the prefix of the next, so its minimum is min(suffix, running
-// prefix minimum).  Each lane keeps the current and previous block in its own
-// slice vh[0 .. 2w) of LDS.  A p-mer holding an invalid byte is stored as 0
+// prefix minimum).  Each lane keeps one block in its own slice vh[0 .. w) of
+// LDS: at offset j of a block it first reads the previous block's suffix
+// minimum at j + 1 and then stores its own value at j, which the previous
+// block no longer needs, so the suffix minima become the next block's
+// prefix in place.  A p-mer holding an invalid byte is stored as 0
 // and a valid one as (value + 1), so a window minimum of 0 flags an invalid
 // k-mer and N bases need no separate branch.
 template <int KW, class VT, class Sink>
@@ -53,9 +56,9 @@ __device__ __forceinline__ void scan_read(const uint8_t* __restrict__ seq, uint6
   if (x1 < x0 + k) return;
   const K kmask = key_mask<K>(k);
   const uint32_t rcs = 2 * p - 2;
-  for (uint32_t i = 0; i < 2 * w; ++i) vh[i] = (VT)0;
+  for (uint32_t i = 0; i < w; ++i) vh[i] = (VT)0;
   uint32_t run = 0, fp = 0, rp = 0;
-  uint32_t in_blk = 0, par = 0, pre = 0;
+  uint32_t in_blk = 0, pre = 0;
   uint32_t cur_n = 0, cur_sig = 0, cur_bin = 0;
   uint64_t cur_start = 0;
   K F = 0, curF = 0, tail = 0;
@@ -79,18 +82,21 @@ __device__ __forceinline__ void scan_read(const uint8_t* __restrict__ seq, uint6
       const uint32_t v =
           run >= p ? ((!C.filter || sig_allowed(can, p)) ? can : C.sent) + 1u : 0u;
       pre = in_blk == 0 ? v : min(pre, v);
-      VT* cur = vh + par * w;
-      cur[in_blk] = (VT)v;
+      uint32_t suf;
       if (in_blk == w - 1) {
+        // the block is complete: its suffix minima in place; the window of
+        // this k-mer is the whole block
+        vh[in_blk] = (VT)v;
         uint32_t r = v;
         for (int i = (int)w - 2; i >= 0; --i) {
-          r = min(r, (uint32_t)cur[i]);
-          cur[i] = (VT)r;
+          r = min(r, (uint32_t)vh[i]);
+          vh[i] = (VT)r;
         }
+        suf = r;
+      } else {
+        suf = (uint32_t)vh[in_blk + 1];  // previous block's suffix minimum
+        vh[in_blk] = (VT)v;
       }
-      // k-mer ending at x: window of the p-mers ending at x - w + 1 .. x
-      const uint32_t suf =
-          in_blk == w - 1 ? (uint32_t)cur[0] : (uint32_t)vh[(par ^ 1u) * w + in_blk + 1];
       const uint32_t m = min(suf, pre);
       const uint64_t j = x + 1 - k;
       if (m == 0) {
@@ -115,7 +121,6 @@ __device__ __forceinline__ void scan_read(const uint8_t* __restrict__ seq, uint6
       }
       if (++in_blk == w) {
         in_blk = 0;
-        par ^= 1u;
       }
     }
     chunk = next;
@@ -126,7 +131,7 @@ __device__ __forceinline__ void scan_read(const uint8_t* __restrict__ seq, uint6
 // Lane-private LDS slices for the window buffer: stride 2w + 1 elements.
 template <class VT>
 __device__ __forceinline__ VT* lane_vh(void* lds, uint32_t w) {
-  return reinterpret_cast<VT*>(lds) + threadIdx.x * (2 * w + 1);
+  return reinterpret_cast<VT*>(lds) + threadIdx.x * (w + 1);
 }
 
 // ------------------------------------------------------------ sample hist
@@ -169,7 +174,7 @@ k_sig_hist(const uint8_t* __restrict__ seq, const uint64_t* __restrict__ offsets
   const uint64_t r = ((uint64_t)blockIdx.x * blockDim.x + threadIdx.x) * stride;
   const uint32_t n_sig = C.sent + 1;
   const uint32_t nl = min(n_sig, kLdsSig);
-  const size_t vb = ((size_t)blockDim.x * (2 * C.w + 1) * sizeof(VT) + 15) & ~(size_t)15;
+  const size_t vb = ((size_t)blockDim.x * (C.w + 1) * sizeof(VT) + 15) & ~(size_t)15;
   uint32_t* lk = reinterpret_cast<uint32_t*>(lds8 + vb);  // after the window buffers
   uint32_t* lr = lk + nl;
   for (uint32_t i = threadIdx.x; i < 2 * nl; i += blockDim.x) lk[i] = 0;
@@ -221,7 +226,7 @@ __device__ __noinline__ void spill_record(const uint8_t* __restrict__ seq, uint6
 // read, k-mer count, signature): no atomics while the wave scans (emission
 // is divergent, so it must be cheap) and no record words in LDS (the records
 // are rebuilt from the read when they are written, which keeps the
-// workgroup's LDS small enough for four workgroups per compute unit).  A
+// workgroup's LDS small enough for five workgroups per compute unit).  A
 // full queue sends the record straight to its bin.
 template <int KW, class VT>
 struct SlotSink {
@@ -291,7 +296,7 @@ __host__ __device__ inline SplitLds split_lds(uint32_t lanes, uint32_t Q, uint32
                                               uint32_t vh_bytes, uint32_t vt_bytes) {
   SplitLds L;
   const uint32_t cap = lanes * Q;
-  const uint32_t bins = n_bins * 8 + n_bins * 12 + cap * 4;  // delta | lcnt lbase lkm | inv srank
+  const uint32_t bins = n_bins * 4 + n_bins * 12 + cap * 4;  // delta | lcnt lbase lkm | inv srank
   L.u_bytes = ((vh_bytes > bins ? vh_bytes : bins) + 15) & ~15u;
   L.sj_off = L.u_bytes;
   L.qn_off = L.sj_off + cap * 4;
@@ -328,7 +333,9 @@ k_split_scatter(const uint8_t* __restrict__ seq, const uint64_t* __restrict__ of
   qn[tid] = sink.q;
   __syncthreads();  // the window buffers are dead: region U becomes the bin arrays
 
-  uint64_t* delta = reinterpret_cast<uint64_t*>(lds8);
+  // delta[b]: global slot of local slot q is cap_base[b] + delta[b] + q (32
+  // bits: a bin's region holds fewer than 2^31 records)
+  int32_t* delta = reinterpret_cast<int32_t*>(lds8);
   uint32_t* lcnt = reinterpret_cast<uint32_t*>(delta + C.n_bins);
   uint32_t* lbase = lcnt + C.n_bins;
   uint32_t* lkm = lbase + C.n_bins;
@@ -353,7 +360,7 @@ k_split_scatter(const uint8_t* __restrict__ seq, const uint64_t* __restrict__ of
   for (uint32_t i = tid; i < C.n_bins; i += nt) {
     if (lcnt[i]) {
       const uint64_t g = atomicAdd(&gcursor[i], (unsigned long long)lcnt[i]);
-      delta[i] = g - lbase[i];
+      delta[i] = (int32_t)((int64_t)(g - cap_base[i]) - (int64_t)lbase[i]);
     }
     if (lkm[i]) atomicAdd(&gkmer[i], (unsigned long long)lkm[i]);
   }
@@ -366,7 +373,7 @@ k_split_scatter(const uint8_t* __restrict__ seq, const uint64_t* __restrict__ of
   for (uint32_t q = tid; q < nst; q += nt) {
     const uint32_t i = inv[q];
     const uint32_t b = ssig[i];
-    const uint64_t g = delta[b] + q;
+    const uint64_t g = (uint64_t)((int64_t)cap_base[b] + delta[b] + (int64_t)q);
     if (g < cap_base[b + 1]) {
       uint64_t rec[RW];
       record_from_read<KW>(seq, n_bases, C.seq_align, offsets[r0 + i / Q] + sj[i], sn[i], C.k,
@@ -445,7 +452,7 @@ constexpr uint64_t kLongRead = 2048;
 // Window buffers hold u16 when every stored value (4^p + 1 at most) fits.
 static bool small_vt(const ScanCfg& c) { return c.sent + 1u <= 0xFFFFu; }
 static size_t vh_bytes(const ScanCfg& c, uint32_t lanes) {
-  const size_t b = (size_t)lanes * (2 * c.w + 1) * (small_vt(c) ? 2 : 4);
+  const size_t b = (size_t)lanes * (c.w + 1) * (small_vt(c) ? 2 : 4);
   return (b + 15) & ~(size_t)15;
 }
 
