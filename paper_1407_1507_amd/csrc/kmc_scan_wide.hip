@@ -1,6 +1,6 @@
 // Split for long windows: the signature scan with one position per lane.
 //
-// The lane-per-read scan (kmc_split.hip) keeps two blocks of w = k - p + 1
+// The lane-per-read scan (kmc_split.hip) keeps a block of w = k - p + 1
 // window values per lane in LDS.  With p > 7 the values need 32 bits and with
 // large k the window is long (w = 47 at k = 55, p = 9), so those buffers
 // leave room for only a few wavefronts per compute unit.  This scan needs no

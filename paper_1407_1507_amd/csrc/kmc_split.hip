@@ -128,7 +128,7 @@ __device__ __forceinline__ void scan_read(const uint8_t* __restrict__ seq, uint6
   if (cur_n) sink.superkmer(cur_start, cur_n, cur_sig, cur_bin, curF, tail);
 }
 
-// Lane-private LDS slices for the window buffer: stride 2w + 1 elements.
+// Lane-private LDS slices for the window buffer: stride w + 1 elements.
 template <class VT>
 __device__ __forceinline__ VT* lane_vh(void* lds, uint32_t w) {
   return reinterpret_cast<VT*>(lds) + threadIdx.x * (w + 1);
