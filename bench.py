@@ -46,11 +46,15 @@ def kernel_bytes(name: str, st: dict, k: int) -> int:
     payload = 2 * st["n_superkmers"] + (st["n_kmers"] + st["n_superkmers"] * (k - 1)) // 4
     keys = w * st["n_kmers"]
     out = (w + 4) * st["n_out"]
+    # the tile kernel reads the keys of the LDS tiles and writes their entries;
+    # the big-tile kernel those of the tiles counted through HBM
+    big_keys, big_out = w * st["n_big_keys"], (w + 4) * st["n_big_out"]
     return {
         "split": inp + payload,
         "fine_hist": payload,
         "expand_scatter": payload + keys,
-        "tile_sort": keys + out,
+        "tile_sort": keys - big_keys + out - big_out,
+        "big_tiles": big_keys + big_out,
         "assemble": 2 * out,
     }.get(name, 0)
 

@@ -88,6 +88,13 @@ typedef struct kmc_params {
 /* Entries in ascending key order over the whole table instead of grouped by
  * bin (then kmc_table.bin_offsets is NULL).  Same entries either way. */
 #define KMC_FLAG_ASCENDING 0x4u
+/* Test only.  Tiles of 128-bit keys (k > 32) are counted in an LDS hash table
+ * whose slots are claimed by a 47-bit fingerprint of the key; a tile where two
+ * different keys share a fingerprint is detected and counted by the exact
+ * partition path for tiles too large for LDS instead.  This flag narrows the
+ * fingerprint to 2 bits, so almost every tile with several distinct keys takes
+ * that path: the table is the same, and tests use the flag to drive it. */
+#define KMC_FLAG_TEST_NARROW_FINGERPRINT 0x100u
 
 /* Kernels timed in kmc_stats.us_kernel. */
 enum {
@@ -116,6 +123,8 @@ typedef struct kmc_stats {
   uint64_t n_big_tiles;    /* tiles too large for LDS, sorted in HBM */
   uint64_t bytes_alg;      /* algorithmic HBM bytes of the job */
   uint64_t split_passes;   /* 1, or 2 when a bin outgrew its sampled estimate */
+  uint64_t n_big_keys;     /* k-mers of the tiles counted through HBM (n_big_tiles) */
+  uint64_t n_big_out;      /* entries of the table those tiles kept */
   double us_map;           /* device time of each phase, microseconds */
   double us_split;
   double us_expand;

@@ -86,6 +86,14 @@ static void* sort_and_count(void* arg) {
   qsort(P->keys, P->n, sizeof(u128), cmp_u128);
   P->out_keys = (u128*)malloc((P->n ? P->n : 1) * sizeof(u128));
   P->out_counts = (uint32_t*)malloc((P->n ? P->n : 1) * sizeof(uint32_t));
+  P->n_out = 0;
+  if (!P->out_keys || !P->out_counts) {  /* the caller sees the NULL and fails */
+    free(P->out_keys);
+    free(P->out_counts);
+    P->out_keys = NULL;
+    P->out_counts = NULL;
+    return NULL;
+  }
   uint64_t m = 0;
   uint64_t i = 0;
   while (i < P->n) {
@@ -111,13 +119,29 @@ static void* worker(void* arg) {
   return NULL;
 }
 
-/* Number of valid windows: for every maximal run of valid bytes of length L
- * inside one read, max(0, L - k + 1).  This is the closed form the full count
- * must sum to when cutoff_min <= 1 and cutoff_max is unbounded. */
-uint64_t kmc_oracle_valid_windows(const uint8_t* seq, const uint64_t* offsets,
-                                  uint64_t n_reads, uint32_t k) {
+/* Run fn(args + i * size) for i in [0, n) on n threads (inline where a
+ * thread cannot be created). */
+static void run_threads(void* (*fn)(void*), void* args, size_t size, int n) {
+  pthread_t th[256];
+  int created[256] = {0};
+  if (n > 256) n = 256;
+  for (int t = 0; t < n; ++t) {
+    void* a = (char*)args + (size_t)t * size;
+    if (n > 1 && pthread_create(&th[t], NULL, fn, a) == 0)
+      created[t] = 1;
+    else
+      fn(a);
+  }
+  for (int t = 0; t < n; ++t)
+    if (created[t]) pthread_join(th[t], NULL);
+}
+
+/* Number of valid windows of reads [r0, r1): for every maximal run of valid
+ * bytes of length L inside one read, max(0, L - k + 1). */
+static uint64_t valid_windows_range(const uint8_t* seq, const uint64_t* offsets,
+                                    uint64_t r0, uint64_t r1, uint32_t k) {
   uint64_t total = 0;
-  for (uint64_t r = 0; r < n_reads; ++r) {
+  for (uint64_t r = r0; r < r1; ++r) {
     uint64_t run = 0;
     for (uint64_t x = offsets[r]; x < offsets[r + 1]; ++x) {
       if (sym_code(seq[x]) >= 0) {
@@ -132,11 +156,73 @@ uint64_t kmc_oracle_valid_windows(const uint8_t* seq, const uint64_t* offsets,
   return total;
 }
 
+/* Number of valid windows of the whole input.  This is the closed form the
+ * full count must sum to when cutoff_min <= 1 and cutoff_max is unbounded. */
+uint64_t kmc_oracle_valid_windows(const uint8_t* seq, const uint64_t* offsets,
+                                  uint64_t n_reads, uint32_t k) {
+  return valid_windows_range(seq, offsets, 0, n_reads, k);
+}
+
+/* One thread's share of the enumeration: reads [r0, r1). */
+typedef struct {
+  const uint8_t* seq;
+  const uint64_t* offsets;
+  uint64_t r0, r1;
+  uint32_t k, shift;
+  int n_parts;
+  uint64_t n_win;   /* valid windows of the share */
+  u128* keys;       /* the share's keys go to keys[0 .. n_win) */
+  uint64_t* hist;   /* keys of the share per partition (n_parts) */
+  uint64_t* pos;    /* next slot of each partition in `sorted` */
+  u128* sorted;
+} enum_t;
+
+static void* enum_count(void* arg) {
+  enum_t* E = (enum_t*)arg;
+  E->n_win = valid_windows_range(E->seq, E->offsets, E->r0, E->r1, E->k);
+  return NULL;
+}
+
+/* Steps 1-2 on the share: every window whose k bytes are all valid ->
+ * canonical key; and the partition histogram of the keys. */
+static void* enum_keys(void* arg) {
+  enum_t* E = (enum_t*)arg;
+  const uint32_t k = E->k;
+  uint64_t n = 0;
+  for (uint64_t r = E->r0; r < E->r1; ++r) {
+    uint64_t b = E->offsets[r], e = E->offsets[r + 1];
+    if (e - b < k) continue;
+    for (uint64_t j = b; j + k <= e; ++j) {
+      int ok = 1;
+      for (uint32_t t = 0; t < k; ++t)
+        if (sym_code(E->seq[j + t]) < 0) { ok = 0; break; }
+      if (ok) {
+        const u128 K = canonical_at(E->seq + j, k);
+        E->keys[n++] = K;
+        if (E->n_parts > 1) E->hist[(uint32_t)(K >> E->shift)]++;
+      }
+    }
+  }
+  return NULL;
+}
+
+/* The share's keys to their partitions. */
+static void* enum_scatter(void* arg) {
+  enum_t* E = (enum_t*)arg;
+  for (uint64_t i = 0; i < E->n_win; ++i) {
+    const u128 K = E->keys[i];
+    E->sorted[E->pos[(uint32_t)(K >> E->shift)]++] = K;
+  }
+  return NULL;
+}
+
 /* Enumerate every canonical k-mer, sort, run-length count, apply cutoffs.
- * n_threads > 1 partitions the keys by their top 8 bits (so partitions are
- * key ranges in order) and sorts each partition on its own thread.
- * Returns 0 on success, -1 on bad arguments, -2 on allocation failure.
- * *out_keys and *out_counts are malloc'd; release them with kmc_oracle_free. */
+ * n_threads > 1 splits the reads into n_threads consecutive shares that are
+ * enumerated in parallel, partitions the keys by their top 8 bits (so
+ * partitions are key ranges in order) and sorts each partition on its own
+ * thread.  Returns 0 on success, -1 on bad arguments, -2 on allocation
+ * failure (nothing allocated is left behind).  *out_keys and *out_counts are
+ * malloc'd; release them with kmc_oracle_free. */
 int kmc_oracle_count(const uint8_t* seq, const uint64_t* offsets, uint64_t n_reads,
                      uint32_t k, uint32_t cutoff_min, uint32_t cutoff_max,
                      int n_threads, uint64_t* out_n, uint64_t** out_keys,
@@ -144,42 +230,74 @@ int kmc_oracle_count(const uint8_t* seq, const uint64_t* offsets, uint64_t n_rea
   if (k < 1 || k > 64 || !out_n || !out_keys || !out_counts) return -1;
   if (cutoff_min > cutoff_max) return -1;
   if (n_threads < 1) n_threads = 1;
-  uint32_t ci = cutoff_min == 0 ? 1 : cutoff_min;
-
-  uint64_t n_win = kmc_oracle_valid_windows(seq, offsets, n_reads, k);
-  u128* keys = (u128*)malloc((n_win ? n_win : 1) * sizeof(u128));
-  if (!keys) return -2;
-
-  /* Steps 1-2: every window whose k bytes are all valid -> canonical key. */
+  if (n_threads > 256) n_threads = 256;
+  const uint32_t ci = cutoff_min == 0 ? 1 : cutoff_min;
+  const int n_parts = n_threads > 1 ? 256 : 1;
+  const uint32_t shift = 2 * k > 8 ? 2 * k - 8 : 0;
+  int rc = -2;
   uint64_t n = 0;
-  for (uint64_t r = 0; r < n_reads; ++r) {
-    uint64_t b = offsets[r], e = offsets[r + 1];
-    if (e - b < k) continue;
-    for (uint64_t j = b; j + k <= e; ++j) {
-      int ok = 1;
-      for (uint32_t t = 0; t < k; ++t)
-        if (sym_code(seq[j + t]) < 0) { ok = 0; break; }
-      if (ok) keys[n++] = canonical_at(seq + j, k);
+
+  enum_t* E = (enum_t*)calloc(n_threads, sizeof(enum_t));
+  uint64_t* hist = (uint64_t*)calloc((size_t)n_threads * n_parts * 2, sizeof(uint64_t));
+  uint64_t* cnt = (uint64_t*)calloc(n_parts + 1, sizeof(uint64_t));
+  part_t* parts = (part_t*)calloc(n_parts, sizeof(part_t));
+  job_t* jobs = (job_t*)calloc(n_threads, sizeof(job_t));
+  u128* keys = NULL;
+  u128* sorted = NULL;
+  uint64_t* ok_keys = NULL;
+  uint32_t* ok_counts = NULL;
+  if (!E || !hist || !cnt || !parts || !jobs) goto done;
+
+  /* Steps 1-2: the windows of each share, then every share's keys in place
+   * (shares in read order, so single- and multi-threaded runs enumerate the
+   * same sequence of keys). */
+  for (int t = 0; t < n_threads; ++t) {
+    E[t].seq = seq;
+    E[t].offsets = offsets;
+    E[t].r0 = n_reads * (uint64_t)t / (uint64_t)n_threads;
+    E[t].r1 = n_reads * (uint64_t)(t + 1) / (uint64_t)n_threads;
+    E[t].k = k;
+    E[t].shift = shift;
+    E[t].n_parts = n_parts;
+    E[t].hist = hist + (size_t)t * n_parts;
+    E[t].pos = hist + (size_t)(n_threads + t) * n_parts;
+  }
+  run_threads(enum_count, E, sizeof(enum_t), n_threads);
+  for (int t = 0; t < n_threads; ++t) n += E[t].n_win;
+  keys = (u128*)malloc((n ? n : 1) * sizeof(u128));
+  if (!keys) goto done;
+  {
+    uint64_t before = 0;
+    for (int t = 0; t < n_threads; ++t) {
+      E[t].keys = keys + before;
+      before += E[t].n_win;
     }
   }
+  run_threads(enum_keys, E, sizeof(enum_t), n_threads);
 
   /* Step 3: partition by the top 8 bits of the 2k-bit key (one partition
    * when single-threaded), then sort and count each partition. */
-  int n_parts = n_threads > 1 ? 256 : 1;
-  uint32_t shift = 2 * k > 8 ? 2 * k - 8 : 0;
-  uint64_t* cnt = (uint64_t*)calloc(n_parts + 1, sizeof(uint64_t));
-  part_t* parts = (part_t*)calloc(n_parts, sizeof(part_t));
-  u128* sorted = n_parts > 1 ? (u128*)malloc((n ? n : 1) * sizeof(u128)) : keys;
-  if (!cnt || !parts || !sorted) return -2;
   if (n_parts > 1) {
-    for (uint64_t i = 0; i < n; ++i) cnt[(uint32_t)(keys[i] >> shift) + 1]++;
+    sorted = (u128*)malloc((n ? n : 1) * sizeof(u128));
+    if (!sorted) goto done;
+    for (int q = 0; q < n_parts; ++q)
+      for (int t = 0; t < n_threads; ++t) cnt[q + 1] += E[t].hist[q];
     for (int q = 0; q < n_parts; ++q) cnt[q + 1] += cnt[q];
-    uint64_t* pos = (uint64_t*)malloc(n_parts * sizeof(uint64_t));
-    memcpy(pos, cnt, n_parts * sizeof(uint64_t));
-    for (uint64_t i = 0; i < n; ++i) sorted[pos[(uint32_t)(keys[i] >> shift)]++] = keys[i];
-    free(pos);
+    /* share t's keys of partition q follow those of shares 0 .. t-1 */
+    for (int q = 0; q < n_parts; ++q) {
+      uint64_t at = cnt[q];
+      for (int t = 0; t < n_threads; ++t) {
+        E[t].pos[q] = at;
+        at += E[t].hist[q];
+      }
+    }
+    for (int t = 0; t < n_threads; ++t) E[t].sorted = sorted;
+    run_threads(enum_scatter, E, sizeof(enum_t), n_threads);
     free(keys);
+    keys = NULL;
   } else {
+    sorted = keys;
+    keys = NULL;
     cnt[1] = n;
   }
   for (int q = 0; q < n_parts; ++q) {
@@ -188,50 +306,61 @@ int kmc_oracle_count(const uint8_t* seq, const uint64_t* offsets, uint64_t n_rea
     parts[q].ci = ci;
     parts[q].cx = cutoff_max;
   }
-  if (n_parts == 1) {
-    sort_and_count(&parts[0]);
-  } else {
-    /* static round-robin of partitions over threads */
-    pthread_t* th = (pthread_t*)malloc(n_threads * sizeof(pthread_t));
-    job_t* jobs = (job_t*)malloc(n_threads * sizeof(job_t));
-    for (int t = 0; t < n_threads; ++t) {
-      jobs[t].parts = parts; jobs[t].first = t; jobs[t].step = n_threads; jobs[t].count = n_parts;
-      pthread_create(&th[t], NULL, worker, &jobs[t]);
-    }
-    for (int t = 0; t < n_threads; ++t) pthread_join(th[t], NULL);
-    free(th);
-    free(jobs);
+  /* static round-robin of partitions over threads */
+  for (int t = 0; t < n_threads; ++t) {
+    jobs[t].parts = parts;
+    jobs[t].first = t;
+    jobs[t].step = n_threads;
+    jobs[t].count = n_parts;
   }
+  run_threads(worker, jobs, sizeof(job_t), n_parts > 1 ? n_threads : 1);
+  for (int q = 0; q < n_parts; ++q)
+    if (!parts[q].out_keys || !parts[q].out_counts) goto done;
 
   /* Step 4: concatenate the partitions in key order. */
-  uint64_t total = 0;
-  for (int q = 0; q < n_parts; ++q) total += parts[q].n_out;
-  uint32_t kw = k <= 32 ? 1 : 2;
-  uint64_t* ok_keys = (uint64_t*)malloc((total ? total : 1) * kw * sizeof(uint64_t));
-  uint32_t* ok_counts = (uint32_t*)malloc((total ? total : 1) * sizeof(uint32_t));
-  if (!ok_keys || !ok_counts) return -2;
-  uint64_t m = 0;
-  for (int q = 0; q < n_parts; ++q) {
-    for (uint64_t i = 0; i < parts[q].n_out; ++i, ++m) {
-      u128 K = parts[q].out_keys[i];
-      if (kw == 1) {
-        ok_keys[m] = (uint64_t)K;
-      } else {
-        ok_keys[2 * m] = (uint64_t)(K >> 64);
-        ok_keys[2 * m + 1] = (uint64_t)K;
+  {
+    uint64_t total = 0;
+    for (int q = 0; q < n_parts; ++q) total += parts[q].n_out;
+    const uint32_t kw = k <= 32 ? 1 : 2;
+    ok_keys = (uint64_t*)malloc((total ? total : 1) * kw * sizeof(uint64_t));
+    ok_counts = (uint32_t*)malloc((total ? total : 1) * sizeof(uint32_t));
+    if (!ok_keys || !ok_counts) goto done;
+    uint64_t m = 0;
+    for (int q = 0; q < n_parts; ++q) {
+      for (uint64_t i = 0; i < parts[q].n_out; ++i, ++m) {
+        const u128 K = parts[q].out_keys[i];
+        if (kw == 1) {
+          ok_keys[m] = (uint64_t)K;
+        } else {
+          ok_keys[2 * m] = (uint64_t)(K >> 64);
+          ok_keys[2 * m + 1] = (uint64_t)K;
+        }
+        ok_counts[m] = parts[q].out_counts[i];
       }
-      ok_counts[m] = parts[q].out_counts[i];
     }
-    free(parts[q].out_keys);
-    free(parts[q].out_counts);
+    *out_n = total;
+    *out_keys = ok_keys;
+    *out_counts = ok_counts;
+    ok_keys = NULL;
+    ok_counts = NULL;
+    rc = 0;
   }
+done:
+  if (parts)
+    for (int q = 0; q < n_parts; ++q) {
+      free(parts[q].out_keys);
+      free(parts[q].out_counts);
+    }
+  free(ok_keys);
+  free(ok_counts);
+  free(keys);
   free(sorted);
   free(parts);
+  free(jobs);
   free(cnt);
-  *out_n = total;
-  *out_keys = ok_keys;
-  *out_counts = ok_counts;
-  return 0;
+  free(hist);
+  free(E);
+  return rc;
 }
 
 void kmc_oracle_free(void* p) { free(p); }

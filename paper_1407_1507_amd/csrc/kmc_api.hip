@@ -44,6 +44,7 @@ struct Misc {
   uint32_t offsets_err;
   uint32_t big_next;  // work counter of the big-tile kernel
   uint32_t pad;
+  unsigned long long big_out;  // entries kept by the big tiles
 };
 
 }  // namespace
@@ -304,7 +305,8 @@ kmc_status validate(const kmc_reads* reads, const kmc_params* P) {
   const uint64_t n_sig = (1ull << (2 * P->p)) + 1;
   if (P->n_bins < 1 || P->n_bins > 65535 || P->n_bins > n_sig) return KMC_ERR_INVALID_ARG;
   if (P->cutoff_min > P->cutoff_max) return KMC_ERR_INVALID_ARG;
-  if (P->flags & ~(KMC_FLAG_DEVICE_TABLE | KMC_FLAG_PLAIN_MINIMIZERS | KMC_FLAG_ASCENDING))
+  if (P->flags & ~(KMC_FLAG_DEVICE_TABLE | KMC_FLAG_PLAIN_MINIMIZERS | KMC_FLAG_ASCENDING |
+                   KMC_FLAG_TEST_NARROW_FINGERPRINT))
     return KMC_ERR_INVALID_ARG;
   if (reads->n_reads > 0 && (!reads->seq && reads->n_bases > 0)) return KMC_ERR_INVALID_ARG;
   if (reads->n_reads > 0 && !reads->offsets) return KMC_ERR_INVALID_ARG;
@@ -420,7 +422,8 @@ void run_count(kmc_ctx* c, const kmc_reads* R, const kmc_params* P, kmc_table* T
     std::vector<double> est(J.n_bins, 0.0);
     for (uint32_t g = 0; g < n_sig; ++g) est[map[g]] += h_hist[n_sig + g];
     const double scale = h_misc.sample_bases ? (double)J.n_bases / (double)h_misc.sample_bases : 0.0;
-    for (uint32_t b = 0; b < J.n_bins; ++b) cap[b] = (uint64_t)(est[b] * scale * 1.25) + 256;
+    for (uint32_t b = 0; b < J.n_bins; ++b)
+      cap[b] = std::min<uint64_t>((uint64_t)(est[b] * scale * 1.25) + 256, kMaxBinRecords);
     if (c->ws_base) {
       // keep the regions inside the workspace; a bin that outgrows its share
       // takes the exact second pass, whose sizes always fit
@@ -468,6 +471,10 @@ void run_count(kmc_ctx* c, const kmc_reads* R, const kmc_params* P, kmc_table* T
       const uint64_t used = h_cnt[b] - rec_base[b];
       if (used > cap[b]) over = true;
       cap[b] = used;
+      if (used > kMaxBinRecords) {
+        c->err = "a bin holds more super k-mers than a bin's region may address";
+        throw Fail{KMC_ERR_TOO_LARGE};
+      }
     }
     st.split_passes = pass + 1;
     if (!over) break;
@@ -500,6 +507,7 @@ void run_count(kmc_ctx* c, const kmc_reads* R, const kmc_params* P, kmc_table* T
   kc.n_bins = J.n_bins;
   kc.cutoff_min = J.ci;
   kc.cutoff_max = J.cx;
+  kc.fp_bits = (J.flags & KMC_FLAG_TEST_NARROW_FINGERPRINT) ? 2u : 47u;
   // fine ranges of about tile_cap / 8 keys in the largest bin
   uint32_t fb = ilog2_ceil(max_bin * 8 / kc.tile_cap + 1);
   fb = std::max<uint32_t>(1, std::min<uint32_t>({fb, (uint32_t)kMaxFineBits, 2 * J.k}));
@@ -581,7 +589,8 @@ void run_count(kmc_ctx* c, const kmc_reads* R, const kmc_params* P, kmc_table* T
     uint64_t* tmp = ensure<uint64_t>(c, B_TMP, std::max<uint64_t>(1, n_kmers) * J.kw * 8);
     check(c, launch_big_tiles(s, kc, tiles, big, big_off, big_order, &misc->n_big,
                               &misc->big_next, n_tiles,
-                              keys, tmp, counts, tile_out, tile_dist), "big_tiles");
+                              keys, tmp, counts, tile_out, tile_dist, &misc->big_out),
+          "big_tiles");
   }
   kend(c, KMC_K_BIG_TILES, s);
   check(c, hipEventRecord(c->ev[4], s), "event");
@@ -605,6 +614,8 @@ void run_count(kmc_ctx* c, const kmc_reads* R, const kmc_params* P, kmc_table* T
   std::memcpy(T->bin_offsets, h_binoff, nb1 * 8);
   const uint64_t h_distinct = h_binoff[nb1];
   st.n_big_tiles = h_misc_p->n_big;
+  st.n_big_keys = h_misc_p->big_total;
+  st.n_big_out = h_misc_p->big_out;
   const uint64_t n_out = T->bin_offsets[J.n_bins];
   st.n_out = n_out;
   st.n_distinct = h_distinct;

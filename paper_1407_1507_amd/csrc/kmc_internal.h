@@ -16,6 +16,10 @@ constexpr int kTileCap1 = 4096;          // keys of one LDS tile (1-word keys)
 constexpr int kTileCap2 = 2048;          // same, 2-word keys
 constexpr int kMaxFineBits = 12;         // fine ranges per bin: at most 2^12
 constexpr int kMaxTilesPerBin = 1 << kMaxFineBits;  // a tile holds >= 1 fine range
+// Most super k-mer records one bin's region may hold: the lane scan addresses a
+// workgroup's slots in a bin by 32-bit offsets (kMaxBinRecords plus a
+// workgroup's slot count stays below 2^31).
+constexpr uint64_t kMaxBinRecords = (1ull << 31) - (1ull << 20);
 
 // Parameters of the split (signature scan) kernels.
 struct ScanCfg {
@@ -115,6 +119,7 @@ struct KeyCfg {
   uint32_t tile_cap;    // keys one LDS tile can hold
   uint32_t n_bins;
   uint32_t cutoff_min, cutoff_max;
+  uint32_t fp_bits;     // fingerprint bits of 128-bit hash-table claims (47; fewer in tests)
 };
 
 // bin[t] for every task t of two task maps (pre arrays of n_bins + 1).
@@ -156,12 +161,14 @@ hipError_t launch_tile_sort(hipStream_t s, const KeyCfg& kc, const Tile* tiles,
 // ping-ponging between its keys and its own slice tmp[big_off[i] ...].  The
 // number of big tiles is read on the device (*n_big, final once the tile
 // kernel has run); workgroups take tiles from the counter *next (zero at
-// launch).  max_big bounds *n_big (the grid never exceeds it).
+// launch).  max_big bounds *n_big (the grid never exceeds it).  *big_out
+// accumulates the entries the big tiles keep.
 hipError_t launch_big_tiles(hipStream_t s, const KeyCfg& kc, const Tile* tiles,
                             const uint32_t* big_list, const uint64_t* big_off, uint32_t* order,
                             const uint32_t* n_big, uint32_t* next, uint64_t max_big,
                             uint64_t* keys, uint64_t* tmp, uint32_t* out_counts,
-                            uint32_t* tile_out, uint32_t* tile_distinct);
+                            uint32_t* tile_out, uint32_t* tile_distinct,
+                            unsigned long long* big_out);
 
 // Exclusive scan of n uint32 into uint64 (out has n + 1 entries: out[n] = total).
 hipError_t launch_scan_u32(hipStream_t s, const uint32_t* in, uint64_t n, uint64_t* out,

@@ -221,21 +221,6 @@ __device__ __forceinline__ uint32_t hash_top(u128 x, uint32_t t) {
 }
 __device__ __forceinline__ uint32_t bit_len(uint32_t x) { return 32u - __clz(x); }
 
-// Count the n <= CAP keys at src (global) and write the kept (key, count)
-// pairs, ascending by key, to out_keys[0..kept) / out_counts[0..kept).  src
-// and out_keys may be the same memory: every key is read before anything is
-// written.  Returns kept; *distinct receives the number of distinct keys.
-// All threads call it.
-//   1. counting pass on a hashed digit (about one bucket per key): equal keys
-//      share a bucket whatever the key distribution;
-//   2. a bucket whose keys are not all equal to its first key is "mixed"; only
-//      mixed buckets are sorted (insertion by a lane, bitonic by a wave,
-//      rank sort by the workgroup above 512 keys);
-//   3. runs of equal keys: in a bucket that is not mixed the run is the whole
-//      bucket; counts, cutoffs; kept keys stay in registers;
-//   4. counting pass of the kept keys on the key digit below their common
-//      prefix; each kept key's output slot is its bucket start plus the
-//      number of smaller kept keys in its bucket.
 // Order the kept (distinct) keys held in registers (key[m], cnt[m] > 0) and
 // write them ascending to out_keys / out_counts: compact them into A / H, one
 // counting pass on the key digit below their common prefix (diff = AND ^ OR
@@ -328,6 +313,12 @@ __device__ __forceinline__ uint32_t count_tile(typename KeyOf<KW>::T (&key)[Sort
 // each one counts the kept keys smaller than itself; more kept keys take the
 // digit-counting order of order_kept.
 template <bool kClean>
+__device__ __forceinline__ uint32_t hash_finish(uint64_t (&key)[SortCfg<1>::ITEMS],
+                                                uint64_t* out_keys, uint32_t* out_counts,
+                                                uint32_t ci, uint32_t cx, SortShared<1>& S,
+                                                uint32_t* distinct);
+
+template <bool kClean>
 __device__ __forceinline__ uint32_t count_tile_hash(uint64_t (&key)[SortCfg<1>::ITEMS], uint32_t n,
                                                     uint64_t* out_keys, uint32_t* out_counts,
                                                     uint32_t ci, uint32_t cx, SortShared<1>& S,
@@ -378,6 +369,21 @@ __device__ __forceinline__ uint32_t count_tile_hash(uint64_t (&key)[SortCfg<1>::
     }
   }
   __syncthreads();
+  return hash_finish<kClean>(key, out_keys, out_counts, ci, cx, S, distinct);
+}
+
+// The second half of count_tile_hash, once every key is in the table: read
+// back (and clear) every slot, apply the cutoffs and write the kept keys in
+// key order.  key is scratch.  All threads call it.
+template <bool kClean>
+__device__ __forceinline__ uint32_t hash_finish(uint64_t (&key)[SortCfg<1>::ITEMS],
+                                                uint64_t* out_keys, uint32_t* out_counts,
+                                                uint32_t ci, uint32_t cx, SortShared<1>& S,
+                                                uint32_t* distinct) {
+  constexpr uint32_t ITEMS = SortCfg<1>::ITEMS, T = SortCfg<1>::CAP;
+  constexpr uint64_t EMPTY = ~0ull;
+  const uint32_t tid = threadIdx.x;
+  constexpr uint32_t nt = kSortThreads;
   // read back (and clear) every slot; an empty slot reads count 0 < ci
   uint32_t cnt[ITEMS];
 #pragma unroll
@@ -481,9 +487,12 @@ constexpr uint32_t kFingerprintClash = 0xFFFFFFFFu;
 
 // Returns the kept count, or kFingerprintClash (nothing written, table
 // empty again).  The table is empty on entry and on return.
+// fp_mask keeps the fingerprint's low bits (47 in use; fewer only to let tests
+// force clashes).
 __device__ uint32_t count_tile_hash2(u128 (&key)[SortCfg<2>::ITEMS], uint32_t n,
                                      uint64_t* out_keys, uint32_t* out_counts, uint32_t ci,
-                                     uint32_t cx, HashShared2& S, uint32_t* distinct) {
+                                     uint32_t cx, uint64_t fp_mask, HashShared2& S,
+                                     uint32_t* distinct) {
   constexpr uint32_t ITEMS = SortCfg<2>::ITEMS, T = kHashSlots2;
   static_assert(T == ITEMS * kSortThreads, "one slot per register slot");
   const uint32_t tid = threadIdx.x;
@@ -500,7 +509,7 @@ __device__ uint32_t count_tile_hash2(u128 (&key)[SortCfg<2>::ITEMS], uint32_t n,
       for (uint32_t u = 0; u < G; ++u) {
         const uint64_t h = mix128(key[g + u]);
         slot_of[g + u] = (uint32_t)(h >> (64 - kHashBits2));
-        fp[u] = (h & ((1ull << 47) - 1)) | (1ull << 47);  // never 0
+        fp[u] = (h & fp_mask) | (1ull << 47);  // never 0
         old[u] = 0;
         if ((g + u) * nt + tid < n)
           old[u] = atomicCAS(reinterpret_cast<unsigned long long*>(&S.F[slot_of[g + u]]), 0ull,
@@ -673,6 +682,17 @@ __device__ uint32_t sort_count_emit(const uint64_t* src, uint32_t n, uint64_t* o
 
 // Same as sort_count_emit, with the tile's keys already in registers
 // (key[m] = key m * blockDim.x + threadIdx.x, for those < n); key is clobbered.
+// Used for the pieces of 128-bit big tiles (64-bit keys always take the hash
+// table).  Steps:
+//   1. counting pass on a hashed digit (about one bucket per key): equal keys
+//      share a bucket whatever the key distribution;
+//   2. a bucket whose keys are not all equal to its first key is "mixed"; only
+//      mixed buckets are sorted (insertion by a lane, bitonic by a wave,
+//      rank sort by the workgroup above 256 keys);
+//   3. runs of equal keys: in a bucket that is not mixed the run is the whole
+//      bucket; counts, cutoffs; kept keys stay in registers;
+//   4. the kept keys are put in key order by order_kept.
+// Returns the kept count; *distinct receives the number of distinct keys.
 template <int KW>
 __device__ __forceinline__ uint32_t count_tile(typename KeyOf<KW>::T (&key)[SortCfg<KW>::ITEMS], uint32_t n,
                                uint64_t* out_keys, uint32_t* out_counts, uint32_t ci,
@@ -906,7 +926,7 @@ k_tile_hash2(KeyCfg kc, const Tile* __restrict__ tiles, uint64_t n_tiles, uint64
       kept = 0;
     } else if (direct) {
       kept = count_tile_hash2(key, T.size, keys + T.begin * 2, counts + T.begin, kc.cutoff_min,
-                              kc.cutoff_max, S, &d);
+                              kc.cutoff_max, (1ull << kc.fp_bits) - 1, S, &d);
     }
     if (threadIdx.x == 0) {
       if (kept == kFingerprintClash) {
@@ -921,6 +941,93 @@ k_tile_hash2(KeyCfg kc, const Tile* __restrict__ tiles, uint64_t n_tiles, uint64
     }
     keep_loaded(touched);
   }
+}
+
+// ------------------------------------------------------ streamed big tiles
+// A tile too large for registers often holds few distinct keys (at 30-40x
+// coverage a key occurs tens of times): its keys are then streamed through
+// the LDS hash table in chunks of kStreamChunk, each key read once, and the
+// table is read back as for a small tile.  The distinct keys claimed so far
+// are checked after every chunk: once more than DIRECT are claimed the attempt
+// stops (the table emptied, false returned) and the caller partitions the
+// tile instead.  A chunk holds T - DIRECT keys, so the table never fills and
+// every probe ends.
+constexpr uint32_t kStreamItems = 4;
+constexpr uint32_t kStreamChunk = kStreamItems * kSortThreads;
+static_assert(SortCfg<1>::CAP - SortCfg<1>::DIRECT >= kStreamChunk, "a chunk never fills the table");
+
+__device__ bool stream_count_hash(const uint64_t* src, uint64_t n, uint64_t* out_keys,
+                                  uint32_t* out_counts, uint32_t ci, uint32_t cx,
+                                  SortShared<1>& S, uint32_t* claims, uint32_t* distinct,
+                                  uint32_t* kept) {
+  constexpr uint32_t T = SortCfg<1>::CAP, TB = 12, U = kStreamItems;
+  constexpr uint64_t EMPTY = ~0ull;
+  const uint32_t tid = threadIdx.x;
+  constexpr uint32_t nt = kSortThreads;
+  for (uint32_t s = tid; s < T; s += nt) {
+    S.A[s] = EMPTY;
+    S.H[s] = 0;
+  }
+  if (tid == 0) *claims = 0;
+  uint64_t cur[U];
+#pragma unroll
+  for (uint32_t u = 0; u < U; ++u) {
+    const uint64_t i = (uint64_t)u * nt + tid;
+    cur[u] = i < n ? src[i] : EMPTY;
+  }
+  __syncthreads();
+  bool ok = true;
+  for (uint64_t base = 0; base < n; base += kStreamChunk) {
+    // the next chunk's loads go out before this chunk's inserts
+    uint64_t nxt[U];
+#pragma unroll
+    for (uint32_t u = 0; u < U; ++u) {
+      const uint64_t i = base + kStreamChunk + (uint64_t)u * nt + tid;
+      nxt[u] = i < n ? src[i] : EMPTY;
+    }
+    uint64_t old[U];
+    uint32_t slot[U];
+#pragma unroll
+    for (uint32_t u = 0; u < U; ++u) {
+      slot[u] = hash_top(cur[u], TB);
+      old[u] = 0;
+      if (cur[u] != EMPTY)
+        old[u] = atomicCAS(reinterpret_cast<unsigned long long*>(&S.A[slot[u]]),
+                           (unsigned long long)EMPTY, (unsigned long long)cur[u]);
+    }
+    uint32_t mine = 0;
+#pragma unroll
+    for (uint32_t u = 0; u < U; ++u) {
+      if (cur[u] != EMPTY) {
+        uint32_t sl = slot[u];
+        uint64_t ov = old[u];
+        while (ov != EMPTY && ov != cur[u]) {  // linear probing on a clash
+          sl = (sl + 1) & (T - 1);
+          ov = atomicCAS(reinterpret_cast<unsigned long long*>(&S.A[sl]),
+                         (unsigned long long)EMPTY, (unsigned long long)cur[u]);
+        }
+        mine += ov == EMPTY;  // this key claimed its slot
+        atomicAdd(&S.H[sl], 1u);
+      }
+    }
+    // claims of the wave, one atomic per wave
+    uint32_t w = mine;
+    for (int d = 32; d >= 1; d >>= 1) w += __shfl_xor(w, d, 64);
+    if ((tid & 63u) == 0 && w) atomicAdd(claims, w);
+    __syncthreads();
+    const uint32_t c = *claims;  // the same for every thread: read between two barriers
+    __syncthreads();             // before the next chunk adds to it
+    if (c > SortCfg<1>::DIRECT) {
+      ok = false;
+      break;
+    }
+#pragma unroll
+    for (uint32_t u = 0; u < U; ++u) cur[u] = nxt[u];
+  }
+  if (!ok) return false;
+  uint64_t key[SortCfg<1>::ITEMS];
+  *kept = hash_finish<false>(key, out_keys, out_counts, ci, cx, S, distinct);
+  return true;
 }
 
 // ------------------------------------------------------------- big tiles
@@ -959,7 +1066,8 @@ template <int KW> struct MaxLevels { static constexpr int N = KW == 1 ? 10 : 18;
 template <int KW>
 __device__ void big_tile(const KeyCfg& kc, const Tile* __restrict__ tiles, uint32_t t,
                          uint64_t tmp_off, uint64_t* keys, uint64_t* tmp, uint32_t* counts,
-                         uint32_t* tile_out, uint32_t* tile_distinct) {
+                         uint32_t* tile_out, uint32_t* tile_distinct,
+                         unsigned long long* big_out) {
   typedef typename KeyOf<KW>::T K;
   __shared__ SortShared<KW> S;
   __shared__ Level L[MaxLevels<KW>::N];
@@ -967,6 +1075,21 @@ __device__ void big_tile(const KeyCfg& kc, const Tile* __restrict__ tiles, uint3
   __shared__ unsigned long long outc, dist;
   const uint32_t tid = threadIdx.x, nt = blockDim.x;
   const Tile T = tiles[t];
+  if constexpr (KW == 1) {
+    // few distinct keys: one streamed pass through the hash table
+    __shared__ uint32_t claims;
+    uint32_t d, kept;
+    if (stream_count_hash(keys + T.begin, T.size, keys + T.begin, counts + T.begin,
+                          kc.cutoff_min, kc.cutoff_max, S, &claims, &d, &kept)) {
+      if (tid == 0) {
+        tile_out[t] = kept;
+        tile_distinct[t] = d;
+        atomicAdd(big_out, (unsigned long long)kept);
+      }
+      __syncthreads();
+      return;
+    }
+  }
   uint64_t* bufs[2] = {keys + T.begin * KW, tmp + tmp_off * KW};
   if (tid == 0) {
     L[0].base = 0;
@@ -1064,6 +1187,7 @@ __device__ void big_tile(const KeyCfg& kc, const Tile* __restrict__ tiles, uint3
   if (tid == 0) {
     tile_out[t] = (uint32_t)outc;
     tile_distinct[t] = (uint32_t)dist;
+    atomicAdd(big_out, outc);
   }
   __syncthreads();
 }
@@ -1074,7 +1198,8 @@ __global__ void __launch_bounds__(kSortThreads)
 k_big_tiles(KeyCfg kc, const Tile* __restrict__ tiles, const uint32_t* __restrict__ big_list,
             const uint64_t* __restrict__ big_off, const uint32_t* __restrict__ order,
             const uint32_t* n_big, uint32_t* next, uint64_t* keys, uint64_t* tmp,
-            uint32_t* counts, uint32_t* tile_out, uint32_t* tile_distinct) {
+            uint32_t* counts, uint32_t* tile_out, uint32_t* tile_distinct,
+            unsigned long long* big_out) {
   __shared__ uint32_t item;
   const uint32_t nb = *n_big;
   for (;;) {
@@ -1085,7 +1210,7 @@ k_big_tiles(KeyCfg kc, const Tile* __restrict__ tiles, const uint32_t* __restric
     if (it >= nb) return;
     const uint32_t j = order[it];
     big_tile<KW>(kc, tiles, big_list[j], big_off[j], keys, tmp, counts, tile_out,
-                 tile_distinct);
+                 tile_distinct, big_out);
   }
 }
 
@@ -1412,7 +1537,8 @@ hipError_t launch_big_tiles(hipStream_t s, const KeyCfg& kc, const Tile* tiles,
                             const uint32_t* big_list, const uint64_t* big_off, uint32_t* order,
                             const uint32_t* n_big, uint32_t* next, uint64_t max_big,
                             uint64_t* keys, uint64_t* tmp, uint32_t* out_counts,
-                            uint32_t* tile_out, uint32_t* tile_distinct) {
+                            uint32_t* tile_out, uint32_t* tile_distinct,
+                            unsigned long long* big_out) {
   if (max_big == 0) return hipSuccess;
   hipLaunchKernelGGL(k_order_big, dim3(1), dim3(1024), 0, s, tiles, big_list, n_big, order);
   const int kw = kc.key_words == 1 ? 1 : 2;
@@ -1423,11 +1549,11 @@ hipError_t launch_big_tiles(hipStream_t s, const KeyCfg& kc, const Tile* tiles,
   if (kw == 1)
     hipLaunchKernelGGL(k_big_tiles<1>, dim3(grid), dim3(kSortThreads), 0, s, kc, tiles,
                        big_list, big_off, order, n_big, next, keys, tmp, out_counts, tile_out,
-                       tile_distinct);
+                       tile_distinct, big_out);
   else
     hipLaunchKernelGGL(k_big_tiles<2>, dim3(grid), dim3(kSortThreads), 0, s, kc, tiles,
                        big_list, big_off, order, n_big, next, keys, tmp, out_counts, tile_out,
-                       tile_distinct);
+                       tile_distinct, big_out);
   return hipGetLastError();
 }
 

@@ -10,11 +10,13 @@
 // sample of the input.
 //
 // GPU mapping: one read per lane.  A lane walks its read once; per base it
-// updates the rolling forward / reverse-complement p-mer, the canonical
-// p-mer, and the running minimum over the current k-mer's p-mers (the
-// minimum is re-scanned from the read only when its position leaves the
-// window).  Records are staged per workgroup in LDS, grouped by bin, and
-// written with one atomic reservation per (workgroup, bin).
+// updates the rolling forward / reverse-complement p-mer and the canonical
+// p-mer, and takes the window minimum over the current k-mer's p-mers by van
+// Herk / Gil-Werman blocks kept in a lane-private LDS slice (no window is
+// re-scanned).  Finished super k-mers are queued per lane in LDS as (start,
+// k-mer count, signature), grouped by bin at the end of the workgroup, and
+// each record is rebuilt from the read as it is written, with one atomic
+// reservation per (workgroup, bin).
 #include "kmc_device.h"
 #include "kmc_internal.h"
 
@@ -286,6 +288,10 @@ struct DirectSink {
 
 // Queue slots per lane.
 template <int KW> struct SplitQ { static constexpr uint32_t Q = 8; };
+// A bin's slot offsets (region offset + a workgroup's slots) fit 31 bits.
+static_assert(kMaxBinRecords + 256ull * SplitQ<1>::Q < (1ull << 31) &&
+                  kMaxBinRecords + 256ull * SplitQ<2>::Q < (1ull << 31),
+              "32-bit slot offsets of the lane scan");
 
 // LDS of k_split_scatter: region U (the lanes' window buffers during the
 // scan, then the per-bin arrays and the slot order) followed by the queues.
@@ -333,8 +339,11 @@ k_split_scatter(const uint8_t* __restrict__ seq, const uint64_t* __restrict__ of
   qn[tid] = sink.q;
   __syncthreads();  // the window buffers are dead: region U becomes the bin arrays
 
-  // delta[b]: global slot of local slot q is cap_base[b] + delta[b] + q (32
-  // bits: a bin's region holds fewer than 2^31 records)
+  // delta[b]: global slot of local slot q is cap_base[b] + delta[b] + q, in
+  // 32 bits.  The host keeps every region below kMaxBinRecords records, so a
+  // reservation starting further into the bin than that lies wholly past the
+  // region's end: its offset is clamped to kMaxBinRecords, which still lands
+  // every slot past the end (not written; the cursor has counted them).
   int32_t* delta = reinterpret_cast<int32_t*>(lds8);
   uint32_t* lcnt = reinterpret_cast<uint32_t*>(delta + C.n_bins);
   uint32_t* lbase = lcnt + C.n_bins;
@@ -360,7 +369,8 @@ k_split_scatter(const uint8_t* __restrict__ seq, const uint64_t* __restrict__ of
   for (uint32_t i = tid; i < C.n_bins; i += nt) {
     if (lcnt[i]) {
       const uint64_t g = atomicAdd(&gcursor[i], (unsigned long long)lcnt[i]);
-      delta[i] = (int32_t)((int64_t)(g - cap_base[i]) - (int64_t)lbase[i]);
+      const uint64_t rel = min(g - cap_base[i], (uint64_t)kMaxBinRecords);
+      delta[i] = (int32_t)((int64_t)rel - (int64_t)lbase[i]);
     }
     if (lkm[i]) atomicAdd(&gkmer[i], (unsigned long long)lkm[i]);
   }

@@ -28,6 +28,7 @@ KERNELS = ["sig_hist", "split", "fine_hist", "plan_tiles", "expand_scatter", "ti
 FLAG_DEVICE_TABLE = 0x1
 FLAG_PLAIN_MINIMIZERS = 0x2
 FLAG_ASCENDING = 0x4
+FLAG_TEST_NARROW_FINGERPRINT = 0x100  # test only: drives the exact path of 128-bit tiles
 
 EXPORTS = ["kmc_ctx_create", "kmc_ctx_destroy", "kmc_last_error", "kmc_count", "kmc_count_ex",
            "kmc_table_free", "kmc_status_str", "kmc_workspace_size", "kmc_count_ws",
@@ -56,7 +57,8 @@ class Params(ctypes.Structure):
 class Stats(ctypes.Structure):
     _fields_ = [(n, ctypes.c_uint64) for n in (
         "n_reads", "n_bases", "n_kmers", "n_superkmers", "n_distinct", "n_out", "sample_kmers",
-        "max_bin_kmers", "n_tiles", "n_big_tiles", "bytes_alg", "split_passes")] + [
+        "max_bin_kmers", "n_tiles", "n_big_tiles", "bytes_alg", "split_passes", "n_big_keys",
+        "n_big_out")] + [
         (n, ctypes.c_double) for n in (
             "us_map", "us_split", "us_expand", "us_sort", "us_assemble", "us_total")] + [
         ("us_kernel", ctypes.c_double * 8), ("us_queue", ctypes.c_double),

@@ -4,17 +4,17 @@ device and copied back here).
 
 - genome-5M-2Mx100 (2M reads x 100 bp, k = 28): the whole table equals the
   oracle's, entry for entry.
+- repeats-50M-30x150-k55 (10M reads x 150 bp, k = 55): the whole table equals
+  the oracle's, entry for entry (the oracle enumerates and sorts on 16 host
+  threads).
 - large-300M-60Mx150 (the served form's large job, 60M reads x 150 bp, 9
   Gbases, k = 28, 2048 bins): exact at 2% scale (same generator and
-  parameters); at full size (about three minutes, run with KMC_LARGE_TEST=1)
-  the same properties and samples as the k = 55 workload below.
-- repeats-50M-30x150-k55 (10M reads x 150 bp, k = 55): too large for the
-  oracle's full sort in a test, so it is checked by properties that hold at
-  any size and on samples the oracle counts one by one: the number of k-mers
-  equals the closed form; sampled table entries carry the oracle's count;
-  sampled windows of the input are in the table exactly when their oracle
-  count passes the cutoffs; sampled keys sit in the bin of their signature;
-  bins are disjoint and ascending.
+  parameters); at full size (7.2e9 k-mers, beyond a full oracle sort in a
+  test) by properties that hold at any size and on samples the oracle counts
+  one by one: the number of k-mers equals the closed form; sampled table
+  entries carry the oracle's count; sampled windows of the input are in the
+  table exactly when their oracle count passes the cutoffs; sampled keys sit
+  in the bin of their signature; bins are disjoint and ascending.
 """
 import ctypes
 import os
@@ -146,32 +146,30 @@ def member(table_keys, order, q):
     return res
 
 
-@pytest.mark.timeout(900)
-def test_repeats_k55_full_size_properties(ctx, kmc):
+@pytest.mark.timeout(1200)
+def test_repeats_k55_full_size_exact(ctx, kmc):
+    step = lambda m: print(f"[repeats k=55] {m}", flush=True)  # progress of a long test
     seq, off, p = synth.make("repeats-50M-30x150-k55")
+    step(f"generated {seq.size} bases")
     k, ci, cx = p["k"], p["cutoff_min"], p["cutoff_max"]
     keys, counts, bo, s2b, st = run_like_bench(ctx, kmc, seq, off, p)
     n = len(counts)
+    step(f"counted: {n} entries")
     assert n == st["n_out"] and n > 1_000_000
     check_bins(keys, bo, n)
-    assert st["n_kmers"] == oracle.valid_windows(seq, off, k)
-    assert np.all((counts >= ci) & (counts <= cx))
-    rng = np.random.default_rng(11)
-    # sampled table entries carry the oracle's count
-    idx = rng.choice(n, 20000, replace=False)
-    got = oracle.count_keys(seq, off, k, keys[idx], threads=THREADS)
-    assert np.array_equal(got, counts[idx].astype(np.uint64))
-    # sampled windows: in the table iff their count passes the cutoffs
-    q = window_keys(seq, off, k, rng, 4000)
-    qc = oracle.count_keys(seq, off, k, q, threads=THREADS)
+    ok_keys, ok_counts = oracle.count(seq, off, k, ci, cx, threads=THREADS)
+    step(f"oracle: {len(ok_counts)} entries")
     order = ascending(keys)
-    pos = member(keys, order, q)
-    want = (qc >= ci) & (qc <= cx)
-    assert np.array_equal(pos >= 0, want)
-    assert np.array_equal(counts[pos[pos >= 0]].astype(np.uint64), qc[pos >= 0])
-    # sampled keys sit in the bin of their signature
-    bin_of = np.searchsorted(bo, idx[:5000], side="right") - 1
-    sig = oracle.key_signatures(keys[idx[:5000]], k, p["p"])
+    assert n == len(ok_counts)
+    assert np.array_equal(keys[order], ok_keys)
+    assert np.array_equal(counts[order], ok_counts)
+    del ok_keys, ok_counts
+    assert st["n_kmers"] == oracle.valid_windows(seq, off, k)
+    # every entry in the bin of its signature (a sample of the entries)
+    rng = np.random.default_rng(11)
+    idx = rng.choice(n, 20000, replace=False)
+    bin_of = np.searchsorted(bo, idx, side="right") - 1
+    sig = oracle.key_signatures(keys[idx], k, p["p"])
     assert np.array_equal(s2b[sig], bin_of)
 
 
@@ -188,8 +186,6 @@ def test_large_job_scaled_exact(ctx, kmc):
 
 
 @pytest.mark.timeout(1200)
-@pytest.mark.skipif(os.environ.get("KMC_LARGE_TEST") != "1",
-                    reason="9 Gbases (about three minutes); run with KMC_LARGE_TEST=1")
 def test_large_job_full_size_properties(ctx, kmc):
     step = lambda m: print(f"[large job] {m}", flush=True)  # progress of a long test
     seq, off, p = synth.make("large-300M-60Mx150")

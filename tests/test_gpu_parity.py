@@ -290,3 +290,47 @@ def test_bad_device_offsets_rejected(ctx, kmc):
     with pytest.raises(kmc.KmcError) as e:
         ctx.count(seq, off, 28, 7, 16, 1, 10)
     assert e.value.status == kmc.KMC_ERR_INVALID_ARG
+
+
+# ------------------------------------------------ forced fallbacks (exact)
+
+
+def hot_unsampled_reads(n_reads, stride, seed):
+    """Random reads, except that every read whose index is not a multiple of
+    `stride` (the sample histogram scans reads 0, stride, 2 stride, ...) is a
+    copy of one read: its signatures are hot in the input and absent from the
+    sample, so their bins outgrow the regions sized from the sample."""
+    rng = np.random.default_rng(seed)
+    acgt = np.frombuffer(b"ACGT", dtype=np.uint8)
+    seq = rng.choice(acgt, size=n_reads * 100).reshape(n_reads, 100)
+    hot = rng.choice(acgt, size=100)
+    mask = (np.arange(n_reads) % stride) != 0
+    seq[mask] = hot
+    off = np.arange(n_reads + 1, dtype=np.uint64) * 100
+    return seq.reshape(-1).copy(), off
+
+
+@pytest.mark.parametrize("k,p,n_bins", [(28, 7, 512), (55, 9, 1024), (33, 7, 64)])
+def test_split_second_pass(ctx, k, p, n_bins):
+    # 20 000 reads x 100 bp: the sample takes every 20th read (stride =
+    # bases / 1e5); the other 19 000 are one read repeated
+    seq, off = hot_unsampled_reads(20_000, 20, k)
+    res = ctx.count(seq, off, k, p, n_bins, 1, 2**32 - 1)
+    assert res.stats["split_passes"] == 2
+    check_table(res, seq, off, k, p, 1, 2**32 - 1)
+
+
+@pytest.mark.parametrize("k", [33, 47, 55, 64])
+def test_fingerprint_clash_fallback(ctx, kmc, k):
+    # 128-bit tiles are counted by fingerprint; a tile where two keys share
+    # one goes to the exact partition path.  With the fingerprint narrowed to
+    # 2 bits nearly every tile clashes: the table must not change.
+    seq, off, p = synth.make("repeats-50M-30x150-k55", 0.004)
+    pk = 9 if k >= 47 else 7
+    base = ctx.count(seq, off, k, pk, 256, 2, 10**6)
+    res = ctx.count(seq, off, k, pk, 256, 2, 10**6, flags=kmc.FLAG_TEST_NARROW_FINGERPRINT)
+    print(k, {x: (base.stats[x], res.stats[x]) for x in ("n_tiles", "n_big_tiles", "n_big_keys")})
+    assert res.stats["n_big_tiles"] >= max(1000, 10 * base.stats["n_big_tiles"])
+    assert res.stats["n_big_keys"] > base.stats["n_big_keys"]
+    check_table(res, seq, off, k, pk, 2, 10**6)
+    assert np.array_equal(res.keys, base.keys) and np.array_equal(res.counts, base.counts)
