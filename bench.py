@@ -23,6 +23,8 @@ sys.path.insert(0, ROOT)
 METRIC = ("input bases/sec and k-mers/sec per MI355X; achieved HBM GB/s; "
           "p50/p99 job latency")
 HBM_PEAK_GBS = 8000.0
+DEFAULT_WORKLOAD = "repeats-50M-30x150-k55"
+ALSO = ["genome-5M-2Mx100"]
 DESCRIPTION = {
     "genome-5M-2Mx100": ("2,000,000 reads x 100 bp sampled (random strand) from a uniform "
                          "5 Mbp reference, 1% substitutions, 0.05% N; k=28, p=7, 512 bins, "
@@ -113,27 +115,75 @@ def copy_calibration(nbytes: int):
     print(json.dumps({"copy_bytes": nbytes}), flush=True)
 
 
-def cpu_baseline(seq, off, p, budget_s: float = 15.0):
-    """The oracle, as it stands, on a prefix of the same read set sized to
-    about budget_s of CPU time; all host cores."""
+def host_cpu() -> str:
+    """The host CPU's model name and logical core count."""
+    model = ""
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    return f"{model or 'unknown CPU'}, {os.cpu_count()} logical cores"
+
+
+def _oracle_rate(seq, off, p, threads: int, budget_s: float):
+    """Bases/s of the oracle on a prefix of the reads sized to about budget_s."""
     import oracle
-    oracle.build(force=False)
-    cores = os.cpu_count() or 1
     n_reads = off.size - 1
-    # calibrate on 1% of the reads, then run the sized sample once
-    n0 = max(1, n_reads // 100)
+    # calibrate on a small prefix, then run the sized sample once
+    n0 = max(1, min(n_reads, 20_000 if threads == 1 else n_reads // 100))
     t = time.perf_counter()
     oracle.count(seq[: int(off[n0])], off[: n0 + 1], p["k"], p["cutoff_min"], p["cutoff_max"],
-                 threads=cores)
+                 threads=threads)
     dt0 = time.perf_counter() - t
     n = int(min(n_reads, max(n0, n0 * budget_s / max(dt0, 1e-3))))
     s, o = seq[: int(off[n])], off[: n + 1]
     t = time.perf_counter()
-    oracle.count(s, o, p["k"], p["cutoff_min"], p["cutoff_max"], threads=cores)
+    oracle.count(s, o, p["k"], p["cutoff_min"], p["cutoff_max"], threads=threads)
     dt = time.perf_counter() - t
-    return {"value": float(o[-1]) / dt, "unit": "bases/s", "cores": cores, "kind": "oracle",
-            "sample": f"first {n} of {n_reads} reads ({int(o[-1])} bases), {dt:.2f} s, "
-                      f"{cores} threads"}
+    return float(o[-1]) / dt, n, int(o[-1]), dt
+
+
+def cpu_baseline(seq, off, p, budget_s: float = 15.0):
+    """The oracle, as it stands, on a prefix of the same read set sized to
+    about budget_s of CPU time on all host cores, and on one thread (a smaller
+    prefix, about budget_s / 3)."""
+    import oracle
+    oracle.build(force=False)
+    cores = os.cpu_count() or 1
+    n_reads = off.size - 1
+    v, n, b, dt = _oracle_rate(seq, off, p, cores, budget_s)
+    v1, n1, b1, dt1 = _oracle_rate(seq, off, p, 1, budget_s / 3)
+    return {"value": v, "unit": "bases/s", "cores": cores, "kind": "oracle",
+            "sample": f"first {n} of {n_reads} reads ({b} bases), {dt:.2f} s, "
+                      f"{cores} threads",
+            "host": host_cpu(),
+            "one_thread": {"value": v1, "unit": "bases/s", "cores": 1,
+                           "sample": f"first {n1} of {n_reads} reads ({b1} bases), "
+                                     f"{dt1:.2f} s, 1 thread"}}
+
+
+def copy_peak(nbytes: int = 2 << 30, reps: int = 10) -> float:
+    """Measured HBM rate of a plain device-to-device copy (GB/s, read + write
+    bytes), beside the nominal peak."""
+    import torch
+    src = torch.empty(nbytes, dtype=torch.uint8, device="cuda:0").fill_(1)
+    dst = torch.empty_like(src)
+    dst.copy_(src)
+    a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    a.record()
+    for _ in range(reps):
+        dst.copy_(src)
+    b.record()
+    torch.cuda.synchronize()
+    ms = a.elapsed_time(b) / reps
+    del src, dst
+    torch.cuda.empty_cache()
+    return 2 * nbytes / (ms * 1e-3) / 1e9
 
 
 def _gen(task):
@@ -294,9 +344,43 @@ def bench_serve(args):
     return out
 
 
+def bench_table6(args):
+    """Super k-mers per read and the largest bin, signatures against plain
+    canonical minimizers (the shape of the paper's Table 6), on the 2M-read
+    genome-like read set, k = 28 and 55, m = 7, 512 bins."""
+    import torch
+    from paper_1407_1507_amd import kmc, synth
+    seq, off, p = synth.make("genome-5M-2Mx100", args.table6_scale)
+    dseq = torch.from_numpy(seq).to("cuda:0")
+    doff = torch.from_numpy(off.view(np.int64)).to("cuda:0")
+    ctx = kmc.Context(0)
+    n_reads = int(off.size - 1)
+    rows = []
+    for k in (28, 55):
+        for label, flags in (("signatures", 0), ("minimizers", kmc.FLAG_PLAIN_MINIMIZERS)):
+            r = ctx.count(dseq, doff, k, 7, 512, 2, 10**9, flags=flags | kmc.FLAG_DEVICE_TABLE)
+            st = r.stats
+            r.free()
+            rows.append({"k": k, "m": 7, "kind": label,
+                         "superkmers_per_read": st["n_superkmers"] / n_reads,
+                         "largest_bin_kmers": st["max_bin_kmers"],
+                         "largest_bin_frac": st["max_bin_kmers"] / max(1, st["n_kmers"]),
+                         "n_kmers": st["n_kmers"]})
+            print(json.dumps(rows[-1]), file=sys.stderr, flush=True)
+    ctx.close()
+    return {"metric": "super k-mers per read and largest bin (Table 6 shape)",
+            "value": None, "unit": "super k-mers per read", "n_gpus": 1,
+            "data": "synthetic (seeded generator)",
+            "config": {"workload": f"genome-5M-2Mx100 at scale {args.table6_scale}: "
+                                   f"{n_reads} reads x 100 bp, 512 bins",
+                       "n_reads": n_reads},
+            "rows": rows}
+
+
 def main():
     ap = argparse.ArgumentParser()
-    ap.add_argument("--mode", choices=["single", "batch", "serve"], default="single")
+    ap.add_argument("--mode", choices=["single", "batch", "serve", "table6"], default="single")
+    ap.add_argument("--table6-scale", type=float, default=1.0)
     ap.add_argument("--batch-jobs", type=int, default=256)
     ap.add_argument("--batch-scale", type=float, default=1.0)
     ap.add_argument("--serve-pool", type=int, default=16)
@@ -308,7 +392,9 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=2)
-    ap.add_argument("--workload", default="genome-5M-2Mx100")
+    ap.add_argument("--workload", default=DEFAULT_WORKLOAD)
+    ap.add_argument("--also", nargs="*", default=ALSO,
+                    help="other workloads measured with a few steps each (extra keys)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--order", choices=["bin", "ascending"], default="bin",
                     help="table order: grouped by bin, or ascending over the whole table")
@@ -324,30 +410,58 @@ def main():
         sys.exit(2)
 
     if args.mode != "single":
-        line = bench_batch(args) if args.mode == "batch" else bench_serve(args)
+        line = {"batch": bench_batch, "serve": bench_serve,
+                "table6": bench_table6}[args.mode](args)
         print(json.dumps(line), flush=True)
         return
 
     import torch
+
+    line, data = bench_single(args.workload, args.steps, args.warmup, args.order)
+    line["roofline"]["copy_peak_gbs"] = copy_peak()
+    line["roofline"]["frac_vs_copy"] = line["roofline"]["achieved"] / line["roofline"]["copy_peak_gbs"]
+    line["job_roofline"]["frac_vs_copy"] = (line["job_roofline"]["achieved"] /
+                                            line["roofline"]["copy_peak_gbs"])
+    # the other single-job workloads, a few steps each (not the headline value)
+    also = {}
+    for w in args.also:
+        if w == args.workload:
+            continue
+        other, _ = bench_single(w, max(3, min(args.steps, 5)), 1, args.order)
+        also[w] = {key: other[key] for key in ("value", "unit", "ms_per_step", "kmers_per_s",
+                                               "device_ms", "hbm_gbs_alg", "job_roofline",
+                                               "roofline", "kernel_us", "job", "config")}
+    if also:
+        line["also"] = also
+    if not args.no_cpu_baseline:
+        seq, off, p = data
+        line["cpu_baseline"] = cpu_baseline(seq, off, p)
+    print(json.dumps(line), flush=True)
+
+
+def bench_single(workload: str, steps: int, warmup: int, order: str):
+    """One job per step on one read set resident in HBM; returns the bench
+    line (without the CPU baseline) and the read set."""
+    import torch
     from paper_1407_1507_amd import kmc, synth
 
-    seq, off, p = synth.make(args.workload)
-    print(f"generated {args.workload}: {seq.size} bases", file=sys.stderr, flush=True)
+    seq, off, p = synth.make(workload)
+    print(f"generated {workload}: {seq.size} bases", file=sys.stderr, flush=True)
     dseq = torch.from_numpy(seq).to("cuda:0")
     doff = torch.from_numpy(off.view(np.int64)).to("cuda:0")
     torch.cuda.synchronize()
     ctx = kmc.Context(0)
-    flags = kmc.FLAG_DEVICE_TABLE | (kmc.FLAG_ASCENDING if args.order == "ascending" else 0)
+    flags = kmc.FLAG_DEVICE_TABLE | (kmc.FLAG_ASCENDING if order == "ascending" else 0)
     run = lambda: ctx.count(dseq, doff, p["k"], p["p"], p["n_bins"], p["cutoff_min"],
                             p["cutoff_max"], flags=flags)
-    for _ in range(args.warmup):
+    for _ in range(warmup):
         run().free()
     torch.cuda.synchronize()
     # each step's table is freed once the call returns: its block goes back to
     # the library's pool and holds the next step's table, as in a stream of jobs
     lat, stats = [], []
     t0 = time.perf_counter()
-    for _ in range(args.steps):
+    for _ in range(steps):
         s = time.perf_counter()
         r = run()
         lat.append(time.perf_counter() - s)
@@ -355,7 +469,7 @@ def main():
         r.free()
     torch.cuda.synchronize()
     t1 = time.perf_counter()
-    ms = (t1 - t0) * 1e3 / args.steps
+    ms = (t1 - t0) * 1e3 / steps
     st = stats[-1]
     n_bases, n_kmers = st["n_bases"], st["n_kmers"]
     # dominant kernel: largest mean device time (HIP events on the library's stream)
@@ -365,24 +479,25 @@ def main():
     dom_bytes = kernel_bytes(dom, st, p["k"])
     achieved = dom_bytes / (mean_us[dom] * 1e-6) / 1e9 if mean_us[dom] > 0 else 0.0
     dev_us = float(np.mean([x["us_total"] for x in stats]))
+    job_gbs = st["bytes_alg"] / (dev_us * 1e-6) / 1e9 if dev_us > 0 else 0.0
     line = {
         "metric": METRIC,
         "value": n_bases / (ms * 1e-3),
         "unit": "bases/s",
         "n_gpus": 1,
-        "steps": args.steps,
-        "warmup": args.warmup,
+        "steps": steps,
+        "warmup": warmup,
         "ms_per_step": ms,
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
         "dtype": "u64" if p["k"] <= 32 else "u128",
         "data": "synthetic (seeded generator; stands in for the paper's read sets)",
-        "config": {"workload": f"{args.workload}: {DESCRIPTION.get(args.workload, '')}",
+        "config": {"workload": f"{workload}: {DESCRIPTION.get(workload, '')}",
                    "k": p["k"], "p": p["p"], "n_bins": p["n_bins"],
                    "cutoff_min": p["cutoff_min"], "cutoff_max": p["cutoff_max"],
                    "n_reads": int(off.size - 1), "n_bases": int(n_bases),
-                   "order": args.order},
+                   "order": order},
         "kmers_per_s": n_kmers / (ms * 1e-3),
         "hbm_gbs_alg": st["bytes_alg"] / (ms * 1e-3) / 1e9,
         "device_ms": dev_us * 1e-3,
@@ -392,16 +507,20 @@ def main():
         "phase_us": {n: round(float(np.mean([x["us_" + n] for x in stats])), 2)
                      for n in ("map", "split", "expand", "sort", "assemble")},
         "job": {key: st[key] for key in ("n_kmers", "n_superkmers", "n_distinct", "n_out",
-                                         "n_tiles", "n_big_tiles", "bytes_alg")},
+                                         "n_tiles", "n_big_tiles", "n_big_keys", "bytes_alg",
+                                         "max_bin_kmers")},
         "roofline": {"bound": "hbm", "kernel": dom, "achieved": achieved,
                      "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS,
-                     "traffic": measured_traffic(dom, args.workload),
+                     "traffic": measured_traffic(dom, workload),
                      "alg_bytes_per_launch": dom_bytes},
+        # the whole job: algorithmic bytes over device time (first kernel to last)
+        "job_roofline": {"achieved": job_gbs, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                         "frac": job_gbs / HBM_PEAK_GBS},
     }
-    if not args.no_cpu_baseline:
-        line["cpu_baseline"] = cpu_baseline(seq, off, p)
     ctx.close()
-    print(json.dumps(line), flush=True)
+    del dseq, doff
+    torch.cuda.empty_cache()
+    return line, (seq, off, p)
 
 
 if __name__ == "__main__":

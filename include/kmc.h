@@ -69,7 +69,10 @@ typedef struct kmc_reads {
  *   cutoff_min  keep a k-mer only if its count >= cutoff_min (0 acts as 1);
  *   cutoff_max  keep a k-mer only if its count <= cutoff_max;
  *               cutoff_min <= cutoff_max;
- *   flags       KMC_FLAG_* bits. */
+ *   flags       KMC_FLAG_* bits;
+ *   counter_max stored counts saturate at this value (0 = exact counts);
+ *               the cutoffs apply to the exact counts (supplement, -cs:
+ *               the maximal value of a counter). */
 typedef struct kmc_params {
   uint32_t k;
   uint32_t p;
@@ -77,6 +80,7 @@ typedef struct kmc_params {
   uint32_t cutoff_min;
   uint32_t cutoff_max;
   uint32_t flags;
+  uint32_t counter_max;
 } kmc_params;
 
 /* The returned table stays in device memory (kmc_table.on_device = 1) instead
@@ -88,6 +92,11 @@ typedef struct kmc_params {
 /* Entries in ascending key order over the whole table instead of grouped by
  * bin (then kmc_table.bin_offsets is NULL).  Same entries either way. */
 #define KMC_FLAG_ASCENDING 0x4u
+/* Count k-mers as read instead of in canonical form (supplement, -b: turn
+ * off the canonical form): a k-mer and its reverse complement are counted
+ * as two keys.  Bins are unchanged (the signature of a k-mer and of its
+ * reverse complement are the same). */
+#define KMC_FLAG_NON_CANONICAL 0x8u
 /* Test only.  Tiles of 128-bit keys (k > 32) are counted in an LDS hash table
  * whose slots are claimed by a 47-bit fingerprint of the key; a tile where two
  * different keys share a fingerprint is detected and counted by the exact

@@ -51,7 +51,8 @@ def _load():
         u32p = ctypes.POINTER(ctypes.c_uint32)
         lib.kmc_oracle_count.argtypes = [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_uint64,
                                          ctypes.c_uint32, ctypes.c_uint32, ctypes.c_uint32,
-                                         ctypes.c_int, ctypes.POINTER(ctypes.c_uint64),
+                                         ctypes.c_int, ctypes.c_int,
+                                         ctypes.POINTER(ctypes.c_uint64),
                                          ctypes.POINTER(u64p), ctypes.POINTER(u32p)]
         lib.kmc_oracle_count.restype = ctypes.c_int
         lib.kmc_oracle_valid_windows.argtypes = [ctypes.c_void_p, ctypes.c_void_p,
@@ -86,15 +87,18 @@ def _reads(seq, offsets):
 
 
 def count(seq, offsets, k: int, cutoff_min: int = 1, cutoff_max: int = 2**32 - 1,
-          threads: int = 1):
-    """Return (keys, counts): keys is uint64 [n] (k <= 32) or [n, 2] (hi, lo)."""
+          threads: int = 1, canonical: bool = True, counter_max: int = 0):
+    """Return (keys, counts): keys is uint64 [n] (k <= 32) or [n, 2] (hi, lo).
+    canonical=False counts k-mers as read (supplement, -b); counter_max > 0
+    stores min(count, counter_max), the cutoffs applying to the exact count
+    (supplement, -cs)."""
     seq, offsets = _reads(seq, offsets)
     lib = _load()
     n = ctypes.c_uint64(0)
     kp = ctypes.POINTER(ctypes.c_uint64)()
     cp = ctypes.POINTER(ctypes.c_uint32)()
     rc = lib.kmc_oracle_count(seq.ctypes.data, offsets.ctypes.data, offsets.size - 1, k,
-                              cutoff_min, cutoff_max, threads, ctypes.byref(n),
+                              cutoff_min, cutoff_max, int(canonical), threads, ctypes.byref(n),
                               ctypes.byref(kp), ctypes.byref(cp))
     if rc != 0:
         raise ValueError(f"oracle count failed ({rc})")
@@ -106,6 +110,8 @@ def count(seq, offsets, k: int, cutoff_min: int = 1, cutoff_max: int = 2**32 - 1
     lib.kmc_oracle_free(ctypes.cast(cp, ctypes.c_void_p))
     if kw == 2:
         keys = keys.reshape(m, 2)
+    if counter_max:
+        counts = np.minimum(counts, np.uint32(counter_max))
     return keys, counts
 
 

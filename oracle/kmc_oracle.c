@@ -51,9 +51,11 @@ static int sym_code(uint8_t b) {
 }
 
 /* Forward value F = sum_t code[t] * 4^(k-1-t) and reverse-complement value
- * R = sum_t (3 - code[t]) * 4^t of the k symbols at s; returns min(F, R).
- * The caller guarantees the k symbols are valid. */
-static u128 canonical_at(const uint8_t* s, uint32_t k) {
+ * R = sum_t (3 - code[t]) * 4^t of the k symbols at s; returns min(F, R), or
+ * F alone when canonical is 0 (the supplement's -b option: k-mers counted as
+ * read, not in canonical form).  The caller guarantees the k symbols are
+ * valid. */
+static u128 key_at(const uint8_t* s, uint32_t k, int canonical) {
   u128 f = 0, r = 0, pw = 1;
   for (uint32_t t = 0; t < k; ++t) {
     int c = sym_code(s[t]);
@@ -61,6 +63,7 @@ static u128 canonical_at(const uint8_t* s, uint32_t k) {
     r = r + (u128)(3 - c) * pw;
     pw *= 4;
   }
+  if (!canonical) return f;
   return f < r ? f : r;
 }
 
@@ -169,6 +172,7 @@ typedef struct {
   const uint64_t* offsets;
   uint64_t r0, r1;
   uint32_t k, shift;
+  int canonical;
   int n_parts;
   uint64_t n_win;   /* valid windows of the share */
   u128* keys;       /* the share's keys go to keys[0 .. n_win) */
@@ -197,7 +201,7 @@ static void* enum_keys(void* arg) {
       for (uint32_t t = 0; t < k; ++t)
         if (sym_code(E->seq[j + t]) < 0) { ok = 0; break; }
       if (ok) {
-        const u128 K = canonical_at(E->seq + j, k);
+        const u128 K = key_at(E->seq + j, k, E->canonical);
         E->keys[n++] = K;
         if (E->n_parts > 1) E->hist[(uint32_t)(K >> E->shift)]++;
       }
@@ -224,7 +228,7 @@ static void* enum_scatter(void* arg) {
  * failure (nothing allocated is left behind).  *out_keys and *out_counts are
  * malloc'd; release them with kmc_oracle_free. */
 int kmc_oracle_count(const uint8_t* seq, const uint64_t* offsets, uint64_t n_reads,
-                     uint32_t k, uint32_t cutoff_min, uint32_t cutoff_max,
+                     uint32_t k, uint32_t cutoff_min, uint32_t cutoff_max, int canonical,
                      int n_threads, uint64_t* out_n, uint64_t** out_keys,
                      uint32_t** out_counts) {
   if (k < 1 || k > 64 || !out_n || !out_keys || !out_counts) return -1;
@@ -257,6 +261,7 @@ int kmc_oracle_count(const uint8_t* seq, const uint64_t* offsets, uint64_t n_rea
     E[t].r0 = n_reads * (uint64_t)t / (uint64_t)n_threads;
     E[t].r1 = n_reads * (uint64_t)(t + 1) / (uint64_t)n_threads;
     E[t].k = k;
+    E[t].canonical = canonical;
     E[t].shift = shift;
     E[t].n_parts = n_parts;
     E[t].hist = hist + (size_t)t * n_parts;

@@ -277,7 +277,7 @@ kmc_table* new_table() {
 }
 
 struct Job {
-  uint32_t k, p, n_bins, ci, cx, kw, flags;
+  uint32_t k, p, n_bins, ci, cx, kw, flags, cmax;
   uint64_t n_reads, n_bases;
   const uint8_t* seq;     // device
   const uint64_t* off;    // device
@@ -306,7 +306,7 @@ kmc_status validate(const kmc_reads* reads, const kmc_params* P) {
   if (P->n_bins < 1 || P->n_bins > 65535 || P->n_bins > n_sig) return KMC_ERR_INVALID_ARG;
   if (P->cutoff_min > P->cutoff_max) return KMC_ERR_INVALID_ARG;
   if (P->flags & ~(KMC_FLAG_DEVICE_TABLE | KMC_FLAG_PLAIN_MINIMIZERS | KMC_FLAG_ASCENDING |
-                   KMC_FLAG_TEST_NARROW_FINGERPRINT))
+                   KMC_FLAG_NON_CANONICAL | KMC_FLAG_TEST_NARROW_FINGERPRINT))
     return KMC_ERR_INVALID_ARG;
   if (reads->n_reads > 0 && (!reads->seq && reads->n_bases > 0)) return KMC_ERR_INVALID_ARG;
   if (reads->n_reads > 0 && !reads->offsets) return KMC_ERR_INVALID_ARG;
@@ -359,6 +359,7 @@ void run_count(kmc_ctx* c, const kmc_reads* R, const kmc_params* P, kmc_table* T
   J.n_bins = P->n_bins;
   J.ci = P->cutoff_min == 0 ? 1 : P->cutoff_min;
   J.cx = P->cutoff_max;
+  J.cmax = P->counter_max == 0 ? 0xFFFFFFFFu : P->counter_max;
   J.kw = P->k <= 32 ? 1 : 2;
   J.flags = P->flags;
   hipStream_t s = c->stream;
@@ -508,6 +509,8 @@ void run_count(kmc_ctx* c, const kmc_reads* R, const kmc_params* P, kmc_table* T
   kc.cutoff_min = J.ci;
   kc.cutoff_max = J.cx;
   kc.fp_bits = (J.flags & KMC_FLAG_TEST_NARROW_FINGERPRINT) ? 2u : 47u;
+  kc.canonical = (J.flags & KMC_FLAG_NON_CANONICAL) ? 0u : 1u;
+  kc.counter_max = J.cmax;
   // fine ranges of about tile_cap / 8 keys in the largest bin
   uint32_t fb = ilog2_ceil(max_bin * 8 / kc.tile_cap + 1);
   fb = std::max<uint32_t>(1, std::min<uint32_t>({fb, (uint32_t)kMaxFineBits, 2 * J.k}));

@@ -25,13 +25,15 @@ template <int KW> struct Rec;
 template <> struct Rec<1> {
   uint64_t F, R, T;
   uint32_t n;
-  __device__ void load(const uint64_t* r, uint32_t k) {
+  bool canon;  // canonical keys; else the forward k-mer itself
+  __device__ void load(const uint64_t* r, uint32_t k, bool canonical = true) {
     F = r[0];
     T = r[1];
     n = (uint32_t)(T & 0xFFu);
     R = revcomp64(F, k);
+    canon = canonical;
   }
-  __device__ uint64_t key() const { return F < R ? F : R; }
+  __device__ uint64_t key() const { return canon && R < F ? R : F; }
   __device__ void step(uint32_t k, uint64_t kmask) {
     const uint32_t c = (uint32_t)(T >> 62);
     T <<= 2;
@@ -42,13 +44,15 @@ template <> struct Rec<1> {
 template <> struct Rec<2> {
   u128 F, R, T;
   uint32_t n;
-  __device__ void load(const uint64_t* r, uint32_t k) {
+  bool canon;
+  __device__ void load(const uint64_t* r, uint32_t k, bool canonical = true) {
     F = ((u128)r[0] << 64) | r[1];
     T = ((u128)r[2] << 64) | r[3];
     n = (uint32_t)(r[3] & 0xFFu);
     R = revcomp128(F, k);
+    canon = canonical;
   }
-  __device__ u128 key() const { return F < R ? F : R; }
+  __device__ u128 key() const { return canon && R < F ? R : F; }
   __device__ void step(uint32_t k, u128 kmask) {
     const uint32_t c = (uint32_t)(T >> 126);
     T <<= 2;
@@ -74,15 +78,20 @@ template <int KW> struct RecTop {
   typedef typename KeyOf<KW>::T K;
   K F, T;
   uint32_t rt, n;
-  __device__ void load(const uint64_t* r, uint32_t k, uint32_t sh) {
+  bool canon;
+  __device__ void load(const uint64_t* r, uint32_t k, uint32_t sh, bool canonical) {
     Rec<KW> full;
     full.load(r, k);
     F = full.F;
     T = full.T;
     n = full.n;
     rt = (uint32_t)(full.R >> sh);
+    canon = canonical;
   }
-  __device__ uint32_t top(uint32_t sh) const { return min((uint32_t)(F >> sh), rt); }
+  __device__ uint32_t top(uint32_t sh) const {
+    const uint32_t f = (uint32_t)(F >> sh);
+    return canon ? min(f, rt) : f;
+  }
   __device__ void step(K kmask, uint32_t bits) {
     const uint32_t c = (uint32_t)(T >> (8 * sizeof(K) - 2));
     T <<= 2;
@@ -190,7 +199,7 @@ k_fine_hist(KeyCfg kc, TaskMap tm, const uint64_t* __restrict__ records, uint32_
       // only the top fine_bits bits of each key: see RecTop
       const uint32_t sh = 2 * kc.k - kc.fine_bits;
       RecTop<KW> rec;
-      rec.load(L.w + (uint32_t)L.perm[threadIdx.x] * (2 * KW), kc.k, sh);
+      rec.load(L.w + (uint32_t)L.perm[threadIdx.x] * (2 * KW), kc.k, sh, kc.canonical != 0);
       for (uint32_t i = 0;; ++i) {
         atomicAdd(&fh[rec.top(sh)], 1u);
         if (i + 1 >= rec.n) break;
@@ -198,7 +207,7 @@ k_fine_hist(KeyCfg kc, TaskMap tm, const uint64_t* __restrict__ records, uint32_
       }
     } else if (threadIdx.x < nr) {
       Rec<KW> rec;
-      rec.load(L.w + (uint32_t)L.perm[threadIdx.x] * (2 * KW), kc.k);
+      rec.load(L.w + (uint32_t)L.perm[threadIdx.x] * (2 * KW), kc.k, kc.canonical != 0);
       for (uint32_t i = 0;; ++i) {
         atomicAdd(&fh[top_bits(rec.key(), kc.k, kc.fine_bits)], 1u);
         if (i + 1 >= rec.n) break;
@@ -321,7 +330,7 @@ k_expand_scatter(KeyCfg kc, TaskMap tm,
   // walk 1: keys per tile
   if (active) {
     Rec<KW> rec;
-    rec.load(my, kc.k);
+    rec.load(my, kc.k, kc.canonical != 0);
     for (uint32_t i = 0;; ++i) {
       atomicAdd(&cnt[tof[top_bits(rec.key(), kc.k, kc.fine_bits)]], 1u);
       if (i + 1 >= rec.n) break;
@@ -339,7 +348,7 @@ k_expand_scatter(KeyCfg kc, TaskMap tm,
   // walk 2: the same keys again, each written to its tile
   if (active) {
     Rec<KW> rec;
-    rec.load(my, kc.k);
+    rec.load(my, kc.k, kc.canonical != 0);
     for (uint32_t i = 0;; ++i) {
       const K key = rec.key();
       const uint32_t t = tof[top_bits(key, kc.k, kc.fine_bits)];

@@ -120,6 +120,8 @@ struct KeyCfg {
   uint32_t n_bins;
   uint32_t cutoff_min, cutoff_max;
   uint32_t fp_bits;     // fingerprint bits of 128-bit hash-table claims (47; fewer in tests)
+  uint32_t canonical;   // 1: keys are canonical k-mers; 0: forward k-mers as read
+  uint32_t counter_max; // stored counts saturate here (0xFFFFFFFF: exact)
 };
 
 // bin[t] for every task t of two task maps (pre arrays of n_bins + 1).

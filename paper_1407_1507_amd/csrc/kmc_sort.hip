@@ -1313,17 +1313,19 @@ k_scan_apply(const uint32_t* __restrict__ in, uint64_t n, const uint64_t* __rest
 }
 
 // ---------------------------------------------------------------- gather
+// Counts are stored saturated at cmax (counter saturation; the cutoffs were
+// applied to the exact counts before).
 template <int KW>
 __global__ void __launch_bounds__(256)
 k_gather(const Tile* __restrict__ tiles, const uint64_t* __restrict__ tile_off,
          const uint64_t* __restrict__ keys, const uint32_t* __restrict__ counts,
-         uint64_t* out_keys, uint32_t* out_counts) {
+         uint64_t* out_keys, uint32_t* out_counts, uint32_t cmax) {
   const uint64_t t = blockIdx.x;
   const uint64_t o = tile_off[t], m = tile_off[t + 1] - o;
   if (m == 0) return;
   const uint64_t b = tiles[t].begin;
   for (uint64_t i = threadIdx.x; i < m * KW; i += blockDim.x) out_keys[o * KW + i] = keys[b * KW + i];
-  for (uint64_t i = threadIdx.x; i < m; i += blockDim.x) out_counts[o + i] = counts[b + i];
+  for (uint64_t i = threadIdx.x; i < m; i += blockDim.x) out_counts[o + i] = min(counts[b + i], cmax);
 }
 
 // ------------------------------------------------- global ascending order
@@ -1578,10 +1580,10 @@ hipError_t launch_gather(hipStream_t s, const KeyCfg& kc, const Tile* tiles, uin
   if (n_tiles == 0) return hipSuccess;
   if (kc.key_words == 1)
     hipLaunchKernelGGL(k_gather<1>, dim3((uint32_t)n_tiles), dim3(256), 0, s, tiles, tile_off,
-                       keys, counts, out_keys, out_counts);
+                       keys, counts, out_keys, out_counts, kc.counter_max);
   else
     hipLaunchKernelGGL(k_gather<2>, dim3((uint32_t)n_tiles), dim3(256), 0, s, tiles, tile_off,
-                       keys, counts, out_keys, out_counts);
+                       keys, counts, out_keys, out_counts, kc.counter_max);
   return hipGetLastError();
 }
 

@@ -28,6 +28,7 @@ KERNELS = ["sig_hist", "split", "fine_hist", "plan_tiles", "expand_scatter", "ti
 FLAG_DEVICE_TABLE = 0x1
 FLAG_PLAIN_MINIMIZERS = 0x2
 FLAG_ASCENDING = 0x4
+FLAG_NON_CANONICAL = 0x8
 FLAG_TEST_NARROW_FINGERPRINT = 0x100  # test only: drives the exact path of 128-bit tiles
 
 EXPORTS = ["kmc_ctx_create", "kmc_ctx_destroy", "kmc_last_error", "kmc_count", "kmc_count_ex",
@@ -51,7 +52,7 @@ class Reads(ctypes.Structure):
 class Params(ctypes.Structure):
     _fields_ = [("k", ctypes.c_uint32), ("p", ctypes.c_uint32), ("n_bins", ctypes.c_uint32),
                 ("cutoff_min", ctypes.c_uint32), ("cutoff_max", ctypes.c_uint32),
-                ("flags", ctypes.c_uint32)]
+                ("flags", ctypes.c_uint32), ("counter_max", ctypes.c_uint32)]
 
 
 class Stats(ctypes.Structure):
@@ -253,9 +254,10 @@ class Context:
         raise KmcError(st, f"{what}: {lib().kmc_status_str(st).decode()} {msg}".strip())
 
     def count(self, seq, offsets, k: int, p: int, n_bins: int, cutoff_min: int = 2,
-              cutoff_max: int = 10**9, flags: int = 0, stream=None) -> Result:
+              cutoff_max: int = 10**9, flags: int = 0, stream=None,
+              counter_max: int = 0) -> Result:
         reads, keep = make_reads(seq, offsets)
-        params = make_params(k, p, n_bins, cutoff_min, cutoff_max, flags)
+        params = make_params(k, p, n_bins, cutoff_min, cutoff_max, flags, counter_max)
         out = ctypes.POINTER(Table)()
         sp = None
         if stream is not None:
@@ -328,8 +330,8 @@ class Context:
 
 
 def make_params(k: int, p: int, n_bins: int, cutoff_min: int = 2, cutoff_max: int = 10**9,
-                flags: int = 0) -> Params:
-    return Params(k, p, n_bins, cutoff_min, min(cutoff_max, 2**32 - 1), flags)
+                flags: int = 0, counter_max: int = 0) -> Params:
+    return Params(k, p, n_bins, cutoff_min, min(cutoff_max, 2**32 - 1), flags, counter_max)
 
 
 class Server:

@@ -49,9 +49,9 @@ def ascending(keys, counts):
     return keys[order], counts[order]
 
 
-def check_table(res, seq, off, k, p, ci, cx, flt=True):
+def check_table(res, seq, off, k, p, ci, cx, flt=True, canonical=True, cs=0):
     """Bit-exact against the oracle, plus the bin invariants."""
-    ok_keys, ok_counts = oracle.count(seq, off, k, ci, cx)
+    ok_keys, ok_counts = oracle.count(seq, off, k, ci, cx, canonical=canonical, counter_max=cs)
     gk, gc = ascending(res.keys, res.counts)
     assert res.n == len(ok_counts)
     assert np.array_equal(gk, ok_keys)
@@ -71,7 +71,7 @@ def check_table(res, seq, off, k, p, ci, cx, flt=True):
                                   ((seg[1:, 0] == seg[:-1, 0]) & (seg[1:, 1] > seg[:-1, 1])))
                 else:
                     assert np.all(seg[1:] > seg[:-1])
-    if ci <= 1 and cx >= 2**32 - 1:
+    if ci <= 1 and cx >= 2**32 - 1 and not cs:
         assert int(res.counts.sum()) == oracle.valid_windows(seq, off, k)
     assert res.stats["n_kmers"] == oracle.valid_windows(seq, off, k)
 
@@ -244,6 +244,64 @@ def test_plain_minimizers_same_counts(ctx, kmc):
     seq, off, p = synth.make("genome-5M-2Mx100", 0.01)
     res = ctx.count(seq, off, 28, 7, 512, 2, 10**9, flags=kmc.FLAG_PLAIN_MINIMIZERS)
     check_table(res, seq, off, 28, 7, 2, 10**9, flt=False)
+
+
+@pytest.mark.parametrize("k,p,n_bins", [(15, 5, 64), (28, 7, 512), (33, 7, 256), (55, 9, 1024)])
+def test_non_canonical(ctx, kmc, k, p, n_bins):
+    # k-mers as read (supplement, -b): random reads with N and lowercase, and
+    # the genome workload at 1%; both scans (p <= 7 lane scan, p = 9 position
+    # scan)
+    rng = np.random.default_rng(900 + k)
+    seq, off = to_reads(random_reads(rng, 3000, 0, 160, n_rate=0.01, lower=0.02))
+    res = ctx.count(seq, off, k, p, n_bins, 1, 2**32 - 1, flags=kmc.FLAG_NON_CANONICAL)
+    check_table(res, seq, off, k, p, 1, 2**32 - 1, canonical=False)
+    seq, off, _ = synth.make("genome-5M-2Mx100", 0.01)
+    res = ctx.count(seq, off, k, p, n_bins, 2, 10**9, flags=kmc.FLAG_NON_CANONICAL)
+    check_table(res, seq, off, k, p, 2, 10**9, canonical=False)
+
+
+def test_non_canonical_big_tiles(ctx, kmc):
+    # tiles beyond LDS (partitioned through HBM) in the as-read mode
+    ref = synth.random_reference(9, 3000)
+    seq, off = synth.sample_reads(10, ref, 40_000, 100, err=0.002, n_rate=0.0)
+    for k, p, nb in ((28, 7, 4), (55, 9, 4)):
+        res = ctx.count(seq, off, k, p, nb, 1, 2**32 - 1, flags=kmc.FLAG_NON_CANONICAL)
+        assert res.stats["n_big_tiles"] > 0
+        check_table(res, seq, off, k, p, 1, 2**32 - 1, canonical=False)
+
+
+@pytest.mark.parametrize("ci,cx,cs", [(1, 2**32 - 1, 1), (2, 10**9, 3), (1, 6, 5), (2, 10**9, 255)])
+def test_counter_saturation(ctx, kmc, ci, cx, cs):
+    # counters clipped at cs (supplement, -cs), cutoffs on the exact counts;
+    # both key widths and the ascending order
+    for name, sc in (("genome-5M-2Mx100", 0.01), ("repeats-50M-30x150-k55", 0.003)):
+        seq, off, p = synth.make(name, sc)
+        res = ctx.count(seq, off, p["k"], p["p"], p["n_bins"], ci, cx, counter_max=cs)
+        check_table(res, seq, off, p["k"], p["p"], ci, cx, cs=cs)
+        asc = ctx.count(seq, off, p["k"], p["p"], p["n_bins"], ci, cx, counter_max=cs,
+                        flags=kmc.FLAG_ASCENDING)
+        ok_keys, ok_counts = oracle.count(seq, off, p["k"], ci, cx, counter_max=cs)
+        assert np.array_equal(asc.keys, ok_keys) and np.array_equal(asc.counts, ok_counts)
+
+
+def test_table6_shape(ctx, kmc):
+    # Table 6's shape on 100 bp genome-like reads at m = 7: signatures give
+    # fewer super k-mers per read than plain canonical minimizers, at k = 28
+    # and k = 55, about 6.7 per read at k = 28 (the paper's 6.728 on G.
+    # gallus); the same k-mers are counted either way
+    seq, off, _ = synth.make("genome-5M-2Mx100", 0.05)
+    n_reads = off.size - 1
+    for k in (28, 55):
+        per = {}
+        for flags in (0, kmc.FLAG_PLAIN_MINIMIZERS):
+            r = ctx.count(seq, off, k, 7, 512, 2, 10**9, flags=flags)
+            per[flags] = (r.stats["n_superkmers"] / n_reads, r.stats["n_kmers"])
+        assert per[0][1] == per[kmc.FLAG_PLAIN_MINIMIZERS][1]
+        assert per[0][0] < per[kmc.FLAG_PLAIN_MINIMIZERS][0]
+        if k == 28:
+            assert 5.5 < per[0][0] < 8.0
+        else:
+            assert 2.0 < per[0][0] < 3.5
 
 
 def test_empty_and_degenerate(ctx):

@@ -45,9 +45,11 @@ def table_dict(keys, counts, k):
     return {(int(a) << 64) | int(b): int(c) for (a, b), c in zip(keys, counts)}
 
 
-def brute_force(reads, k, ci=1, cx=2**32 - 1):
+def brute_force(reads, k, ci=1, cx=2**32 - 1, canonical=True, cs=0):
     """String-level counter: canonical = min(s, reverse complement) by Python
-    string order, over windows made only of A/C/G/T (either case)."""
+    string order (or the window as read when canonical is False), over windows
+    made only of A/C/G/T (either case); counts kept by the cutoffs, then
+    clipped at cs when cs > 0."""
     comp = {"A": "T", "C": "G", "G": "C", "T": "A"}
     c = Counter()
     for r in reads:
@@ -57,8 +59,9 @@ def brute_force(reads, k, ci=1, cx=2**32 - 1):
             if any(ch not in comp for ch in w):
                 continue
             rc = "".join(comp[ch] for ch in reversed(w))
-            c[min(w, rc)] += 1
-    return {key_of_full(s, k): n for s, n in c.items() if max(ci, 1) <= n <= cx}
+            c[min(w, rc) if canonical else w] += 1
+    return {key_of_full(s, k): (min(n, cs) if cs else n) for s, n in c.items()
+            if max(ci, 1) <= n <= cx}
 
 
 def key_of_full(s, k):
@@ -167,6 +170,44 @@ def test_brute_force(oracle_lib, k):
         assert got == brute_force(reads, k, ci, cx)
         flat = [int(a) for a in keys] if k <= 32 else [(int(a) << 64) | int(b) for a, b in keys]
         assert flat == sorted(flat) and len(set(flat)) == len(flat)
+
+
+@pytest.mark.parametrize("k", [4, 15, 32, 33, 64])
+def test_non_canonical_and_saturation_brute_force(oracle_lib, k):
+    # k-mers as read (supplement, -b) and saturated counters (-cs), with the
+    # cutoffs applied to the exact counts before the counters are clipped
+    rng = np.random.default_rng(200 + k)
+    reads = random_reads(rng, 60, 0, k + 40, n_rate=0.03, lower=0.05)
+    reads.append("ACGT" * 30)
+    reads.append("A" * 90 + "N" + "T" * 70)
+    seq, off = to_reads(reads)
+    for ci, cx, cs in ((1, 2**32 - 1, 0), (2, 2**32 - 1, 0), (1, 2**32 - 1, 3), (1, 6, 5)):
+        for canonical in (False, True):
+            keys, counts = oracle_lib.count(seq, off, k, ci, cx, canonical=canonical,
+                                            counter_max=cs)
+            got = table_dict(keys, counts, k)
+            assert got == brute_force(reads, k, ci, cx, canonical=canonical, cs=cs)
+
+
+def test_non_canonical_folds_into_canonical(oracle_lib):
+    # count of a canonical key = as-read count of the key + as-read count of
+    # its reverse complement (once for a palindrome): ties the two modes
+    rng = np.random.default_rng(17)
+    reads = random_reads(rng, 300, 20, 120, n_rate=0.01)
+    reads.append("ACGT" * 20)
+    seq, off = to_reads(reads)
+    for k in (12, 28, 40):
+        can = table_dict(*oracle_lib.count(seq, off, k), k)
+        raw = table_dict(*oracle_lib.count(seq, off, k, canonical=False), k)
+        mask = (1 << (2 * k)) - 1
+        folded = Counter()
+        for key, c in raw.items():
+            rc = 0
+            for t in range(k):
+                rc = rc * 4 + (3 - ((key >> (2 * t)) & 3))
+            folded[min(key, rc & mask)] += c
+        assert dict(folded) == can
+        assert sum(raw.values()) == sum(can.values())
 
 
 @pytest.mark.parametrize("k", [4, 21, 32, 33, 55, 64])
