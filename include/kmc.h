@@ -281,6 +281,41 @@ kmc_status kmc_server_stats_get(kmc_server* srv, kmc_server_stats* stats);
  * server.  NULL is allowed. */
 void kmc_server_stop(kmc_server* srv);
 
+/* Allocation-free count, for callers that cannot allocate device memory:
+ * code under HIP graph capture, tight serving loops, harnesses that forbid
+ * hipMalloc.  The same kernels as kmc_count_ws, with every scratch buffer
+ * carved from a static device array of KMC_STATIC_SCRATCH_BYTES that each
+ * device the library runs on holds from the first such call until the
+ * process ends; the call makes no device or pinned-host allocation (host-side
+ * planning uses ordinary heap memory).  The table is written to the caller's
+ * device buffers, grouped by bin as in kmc_table (or in ascending key order
+ * with KMC_FLAG_ASCENDING); KMC_FLAG_DEVICE_TABLE is implied.
+ *   reads        host or device CSR reads (host reads are copied into the
+ *                scratch first);
+ *   stream       hipStream_t or NULL (the context's stream); the call returns
+ *                when the table is complete;
+ *   keys_out     device memory of ctx's device, out_cap * key_words uint64
+ *                (key_words = 1 for k <= 32, else 2, hi word first);
+ *   counts_out   device memory, out_cap uint32;
+ *   n_out        host: entries written;
+ *   bin_offsets  host, n_bins + 1 uint64, or NULL (untouched with
+ *                KMC_FLAG_ASCENDING);
+ *   stats        host, or NULL.
+ * Errors: KMC_ERR_TOO_LARGE, before any device work, when the job's
+ * kmc_workspace_size exceeds KMC_STATIC_SCRATCH_BYTES (kmc_last_error states
+ * both sizes), and after counting when the table has more than out_cap
+ * entries (*n_out then holds the number needed); otherwise as kmc_count_ex.
+ * Every call on a device shares that device's array, which keeps the last
+ * call's contents (each call clears what must start at zero).  Calls that
+ * overlapped on one device would race on it: the library serialises the
+ * calls of one process on a device with a lock, and each call returns only
+ * when its work is done. */
+#define KMC_STATIC_SCRATCH_BYTES (256ull << 20)
+kmc_status kmc_count_static(kmc_ctx* ctx, const kmc_reads* reads, const kmc_params* params,
+                            void* stream, uint64_t* keys_out, uint32_t* counts_out,
+                            uint64_t out_cap, uint64_t* n_out, uint64_t* bin_offsets,
+                            kmc_stats* stats);
+
 /* Audit entry (tests): the signature of the window starting at every byte of
  * the input, as the GPU's split kernel computes it, into sig_per_window
  * (host memory, n_bases uint32; 0xFFFFFFFF where no valid k-mer starts), and

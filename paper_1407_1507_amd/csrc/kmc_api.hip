@@ -72,6 +72,15 @@ struct kmc_ctx {
   uint8_t* ws_base = nullptr;
   WsLayout ws;
   bool ws_own_table = false;  // device table allocated apart from the workspace
+  // allocation-free mode (kmc_count_static): host staging in pageable
+  // vectors instead of pinned buffers, and the table written to the caller's
+  // device buffers (user_cap entries)
+  bool pageable_host = false;
+  std::vector<uint8_t> hvec[H_COUNT_];
+  uint64_t* user_keys = nullptr;
+  uint32_t* user_counts = nullptr;
+  uint64_t user_cap = 0;
+  uint64_t user_need = 0;  // entries of a table that did not fit user_cap
   // extension slot (batch worker pool), released with the context
   void* ext = nullptr;
   void (*ext_free)(void*) = nullptr;
@@ -93,6 +102,11 @@ void check(kmc_ctx* c, hipError_t e, const char* what) {
 
 template <class T>
 T* ensure_host(kmc_ctx* c, HostId id, size_t bytes) {
+  if (c->pageable_host) {
+    std::vector<uint8_t>& v = c->hvec[id];
+    if (v.size() < bytes) v.resize(bytes);
+    return reinterpret_cast<T*>(v.data());
+  }
   DevBuf& b = c->hbuf[id];
   if (b.cap < bytes) {
     if (b.p) (void)hipHostFree(b.p);
@@ -625,7 +639,19 @@ void run_count(kmc_ctx* c, const kmc_reads* R, const kmc_params* P, kmc_table* T
   T->n = n_out;
   uint64_t* out_k;
   uint32_t* out_c;
-  if (T->on_device && c->ws_base && !c->ws_own_table) {
+  if (c->user_keys) {
+    // the caller's buffers (allocation-free form)
+    if (n_out > c->user_cap) {
+      c->user_need = n_out;
+      c->err = "the table has more entries than the output buffers hold";
+      throw Fail{KMC_ERR_TOO_LARGE};
+    }
+    T->keys = c->user_keys;
+    T->counts = c->user_counts;
+    T->reserved = 1;
+    out_k = T->keys;
+    out_c = T->counts;
+  } else if (T->on_device && c->ws_base && !c->ws_own_table) {
     // the table lives in the caller's workspace; kmc_table_free leaves it
     T->keys = ensure<uint64_t>(c, B_OUTK, n_out * J.kw * 8);
     T->counts = ensure<uint32_t>(c, B_OUTC, n_out * 4);
@@ -991,6 +1017,59 @@ kmc_status kmc::count_ws_impl(kmc_ctx* c, const kmc_reads* reads, const kmc_para
   c->ws_own_table = false;
   c->stream = saved;
   return st;
+}
+
+kmc_status kmc::count_static_impl(kmc_ctx* c, const kmc_reads* reads, const kmc_params* params,
+                                  void* stream, void* scratch, size_t scratch_bytes,
+                                  uint64_t* keys_out, uint32_t* counts_out, uint64_t out_cap,
+                                  uint64_t* n_out, uint64_t* bin_offsets, kmc_stats* stats) {
+  if (!c || !n_out || !scratch || ((uintptr_t)scratch & 255u)) return KMC_ERR_INVALID_ARG;
+  *n_out = 0;
+  if (out_cap > 0 && (!keys_out || !counts_out)) return KMC_ERR_INVALID_ARG;
+  c->err.clear();
+  kmc_status v = validate(reads, params);
+  if (v != KMC_OK) {
+    c->err = "argument validation failed";
+    return v;
+  }
+  const WsLayout L = plan_workspace(reads, params);
+  if (L.total > scratch_bytes) {
+    c->err = "the job needs " + std::to_string(L.total) + " bytes of scratch; the static scratch holds " +
+             std::to_string(scratch_bytes);
+    return KMC_ERR_TOO_LARGE;
+  }
+  hipStream_t saved = c->stream;
+  if (stream) c->stream = static_cast<hipStream_t>(stream);
+  c->ws_base = static_cast<uint8_t*>(scratch);
+  c->ws = L;
+  c->pageable_host = true;
+  // a dummy 16-byte-aligned address keeps the caller-buffer branch taken for
+  // an empty output
+  static uint64_t empty_out[2];
+  c->user_keys = keys_out ? keys_out : empty_out;
+  c->user_counts = counts_out ? counts_out : reinterpret_cast<uint32_t*>(empty_out);
+  c->user_cap = out_cap;
+  c->user_need = 0;
+  kmc_params P = *params;
+  P.flags |= KMC_FLAG_DEVICE_TABLE;
+  kmc_table* T = nullptr;
+  kmc_status st = guarded(c, reads, &P, &T);
+  c->ws_base = nullptr;
+  c->pageable_host = false;
+  c->user_keys = nullptr;
+  c->user_counts = nullptr;
+  c->user_cap = 0;
+  c->stream = saved;
+  if (st != KMC_OK) {
+    if (st == KMC_ERR_TOO_LARGE) *n_out = c->user_need;
+    return st;
+  }
+  *n_out = T->n;
+  if (bin_offsets && T->bin_offsets)
+    std::memcpy(bin_offsets, T->bin_offsets, ((size_t)T->n_bins + 1) * 8);
+  if (stats) *stats = T->stats;
+  kmc_table_free(T);  // host parts only: keys/counts are the caller's
+  return KMC_OK;
 }
 
 extern "C" {

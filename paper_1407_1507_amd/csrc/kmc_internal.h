@@ -230,4 +230,10 @@ void ctx_release_buffers(kmc_ctx* c);
 kmc_status count_ws_impl(kmc_ctx* c, const kmc_reads* reads, const kmc_params* params,
                          void* stream, void* workspace, size_t ws_bytes, bool own_table,
                          kmc_table** out);
+// kmc_count_static with `scratch` (scratch_bytes, 256-byte aligned device
+// memory) as the workspace and the table written to keys_out / counts_out.
+kmc_status count_static_impl(kmc_ctx* c, const kmc_reads* reads, const kmc_params* params,
+                             void* stream, void* scratch, size_t scratch_bytes,
+                             uint64_t* keys_out, uint32_t* counts_out, uint64_t out_cap,
+                             uint64_t* n_out, uint64_t* bin_offsets, kmc_stats* stats);
 }  // namespace kmc

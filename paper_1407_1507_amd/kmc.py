@@ -34,7 +34,9 @@ FLAG_TEST_NARROW_FINGERPRINT = 0x100  # test only: drives the exact path of 128-
 EXPORTS = ["kmc_ctx_create", "kmc_ctx_destroy", "kmc_last_error", "kmc_count", "kmc_count_ex",
            "kmc_table_free", "kmc_status_str", "kmc_workspace_size", "kmc_count_ws",
            "kmc_batch_count", "kmc_server_start", "kmc_server_submit", "kmc_server_poll",
-           "kmc_server_stats_get", "kmc_server_stop", "kmc_debug_signatures"]
+           "kmc_server_stats_get", "kmc_server_stop", "kmc_debug_signatures",
+           "kmc_count_static"]
+STATIC_SCRATCH_BYTES = 256 << 20  # KMC_STATIC_SCRATCH_BYTES
 
 
 class KmcError(RuntimeError):
@@ -145,6 +147,10 @@ def lib() -> ctypes.CDLL:
         L.kmc_count_ws.argtypes = [vp, ctypes.POINTER(Reads), ctypes.POINTER(Params), vp, vp,
                                    ctypes.c_size_t, ctypes.POINTER(ctypes.POINTER(Table))]
         L.kmc_count_ws.restype = ctypes.c_int
+        L.kmc_count_static.argtypes = [vp, ctypes.POINTER(Reads), ctypes.POINTER(Params), vp,
+                                       vp, vp, ctypes.c_uint64, ctypes.POINTER(ctypes.c_uint64),
+                                       vp, ctypes.POINTER(Stats)]
+        L.kmc_count_static.restype = ctypes.c_int
         L.kmc_batch_count.argtypes = [vp, ctypes.POINTER(Job), ctypes.c_uint32,
                                       ctypes.POINTER(ctypes.POINTER(Table))]
         L.kmc_batch_count.restype = ctypes.c_int
@@ -297,6 +303,32 @@ class Context:
         if st != KMC_OK:
             self._raise(st, "kmc_count_ws")
         return Result(out)
+
+    def count_static(self, seq, offsets, k: int, p: int, n_bins: int, cutoff_min: int,
+                     cutoff_max: int, keys_out, counts_out, flags: int = 0, stream=None):
+        """kmc_count_static: the allocation-free count into the caller's device
+        buffers keys_out (uint64, n * key_words) and counts_out (int32/uint32,
+        n).  Returns (n_out, bin_offsets or None, stats dict)."""
+        reads, keep = make_reads(seq, offsets)
+        params = make_params(k, p, n_bins, cutoff_min, cutoff_max, flags)
+        kw = 1 if k <= 32 else 2
+        cap = min(keys_out.numel() // kw, counts_out.numel())
+        n_out = ctypes.c_uint64(0)
+        bo = np.zeros(n_bins + 1, dtype=np.uint64)
+        stats = Stats()
+        sp = None
+        if stream is not None:
+            sp = stream if isinstance(stream, int) else stream.cuda_stream
+        st = lib().kmc_count_static(self._h, ctypes.byref(reads), ctypes.byref(params), sp,
+                                    keys_out.data_ptr(), counts_out.data_ptr(), cap,
+                                    ctypes.byref(n_out), bo.ctypes.data, ctypes.byref(stats))
+        del keep
+        if st != KMC_OK:
+            err = KmcError(st, "kmc_count_static: " + lib().kmc_status_str(st).decode() + " " +
+                           lib().kmc_last_error(self._h).decode())
+            err.n_out = n_out.value
+            raise err
+        return n_out.value, (None if flags & FLAG_ASCENDING else bo), stats.as_dict()
 
     def batch_count(self, jobs) -> list:
         """kmc_batch_count over jobs = [(seq, offsets, params dict), ...];
