@@ -520,7 +520,7 @@ static size_t split_lds_bytes(const ScanCfg& c, uint32_t key_words, uint32_t lan
 }
 
 static bool lane_scan_fits(const ScanCfg& c, uint32_t key_words) {
-  return small_vt(c) && split_lds_bytes(c, key_words, 256) <= 80 * 1024;
+  return split_lds_bytes(c, key_words, 256) <= 80 * 1024;
 }
 
 static bool use_lane_scan(const ScanCfg& c, uint32_t key_words, uint64_t n_reads,
@@ -529,9 +529,9 @@ static bool use_lane_scan(const ScanCfg& c, uint32_t key_words, uint64_t n_reads
 }
 
 // The lane-per-read scan is used when 256 lanes' window buffers (16-bit
-// values) and record queues fit at least two workgroups per compute unit;
-// otherwise the scan with one position per lane (the same signatures and
-// records).
+// values for p <= 7, 32-bit above) and record queues fit at least two
+// workgroups per compute unit; otherwise the scan with one position per lane
+// (the same signatures and records).
 static bool lane_scan_fits(const ScanCfg& c, uint32_t key_words);
 
 hipError_t launch_split_scatter(hipStream_t s, const uint8_t* seq, const uint64_t* offsets,

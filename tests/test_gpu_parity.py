@@ -198,8 +198,9 @@ def test_long_reads(ctx):
     for k, p, nb in ((28, 7, 512), (21, 5, 64), (33, 7, 256)):
         res = ctx.count(seq, off, k, p, nb, 1, 2**32 - 1)
         check_table(res, seq, off, k, p, 1, 2**32 - 1)
-    sig, _ = ctx.debug_signatures(seq, off, 28, 7, 0)
-    assert np.array_equal(sig, oracle.window_signatures(seq, off, 28, 7, True))
+    for k, p in ((28, 7), (55, 9)):
+        sig, _ = ctx.debug_signatures(seq, off, k, p, 0)
+        assert np.array_equal(sig, oracle.window_signatures(seq, off, k, p, True))
 
 
 # ------------------------------------------------------------- workloads
@@ -246,11 +247,12 @@ def test_plain_minimizers_same_counts(ctx, kmc):
     check_table(res, seq, off, 28, 7, 2, 10**9, flt=False)
 
 
-@pytest.mark.parametrize("k,p,n_bins", [(15, 5, 64), (28, 7, 512), (33, 7, 256), (55, 9, 1024)])
+@pytest.mark.parametrize("k,p,n_bins", [(15, 5, 64), (28, 7, 512), (33, 7, 256), (55, 9, 1024),
+                                        (55, 9, 8192)])
 def test_non_canonical(ctx, kmc, k, p, n_bins):
     # k-mers as read (supplement, -b): random reads with N and lowercase, and
-    # the genome workload at 1%; both scans (p <= 7 lane scan, p = 9 position
-    # scan)
+    # the genome workload at 1%; both scans (8192 bins do not fit the lane
+    # scan's LDS and take the position-per-lane scan)
     rng = np.random.default_rng(900 + k)
     seq, off = to_reads(random_reads(rng, 3000, 0, 160, n_rate=0.01, lower=0.02))
     res = ctx.count(seq, off, k, p, n_bins, 1, 2**32 - 1, flags=kmc.FLAG_NON_CANONICAL)
@@ -368,8 +370,9 @@ def hot_unsampled_reads(n_reads, stride, seed):
     return seq.reshape(-1).copy(), off
 
 
-@pytest.mark.parametrize("k,p,n_bins", [(28, 7, 512), (55, 9, 1024), (33, 7, 64)])
+@pytest.mark.parametrize("k,p,n_bins", [(28, 7, 512), (55, 9, 1024), (33, 7, 64), (55, 9, 8192)])
 def test_split_second_pass(ctx, k, p, n_bins):
+    # both scans: 8192 bins take the position-per-lane scan
     # 20 000 reads x 100 bp: the sample takes every 20th read (stride =
     # bases / 1e5); the other 19 000 are one read repeated
     seq, off = hot_unsampled_reads(20_000, 20, k)
