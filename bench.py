@@ -221,26 +221,35 @@ def bench_batch(args):
     ctx = kmc.Context(0)
     prm = [dict(p, flags=kmc.FLAG_DEVICE_TABLE) for _, _, p in djobs]
     batch = [(s, o, q) for (s, o, _), q in zip(djobs, prm)]
-    for _ in range(args.warmup):
-        for r in ctx.batch_count(batch):
-            r.free()
-    torch.cuda.synchronize()
-    times, kmers = [], 0
-    for _ in range(args.steps):
-        t = time.perf_counter()
-        res = ctx.batch_count(batch)
+
+    def timed_batches():
+        for _ in range(args.warmup):
+            for r in ctx.batch_count(batch):
+                r.free()
         torch.cuda.synchronize()
-        times.append(time.perf_counter() - t)
-        kmers = sum(r.stats["n_kmers"] for r in res)
-        for r in res:
-            r.free()
-    # the same jobs one after another on one stream, for comparison
-    t = time.perf_counter()
-    for s, o, q in batch:
-        ctx.count(s, o, q["k"], q["p"], q["n_bins"], q["cutoff_min"], q["cutoff_max"],
-                  flags=q["flags"]).free()
-    torch.cuda.synchronize()
-    serial = time.perf_counter() - t
+        times, kmers = [], 0
+        for _ in range(args.steps):
+            t = time.perf_counter()
+            res = ctx.batch_count(batch)
+            torch.cuda.synchronize()
+            times.append(time.perf_counter() - t)
+            kmers = sum(r.stats["n_kmers"] for r in res)
+            for r in res:
+                r.free()
+        return times, kmers
+
+    times, kmers = timed_batches()
+    # the plain per-job launch: the same jobs one after another on one
+    # stream, on a context with the default knobs (a warm pass, then timed)
+    plain = kmc.Context(0)
+    for rep in range(2):
+        t = time.perf_counter()
+        for s, o, q in batch:
+            plain.count(s, o, q["k"], q["p"], q["n_bins"], q["cutoff_min"], q["cutoff_max"],
+                        flags=q["flags"]).free()
+        torch.cuda.synchronize()
+        serial = time.perf_counter() - t
+    plain.close()
     ctx.close()
     ms = float(np.mean(times)) * 1e3
     ks = sorted({p["k"] for _, _, p in jobs})
@@ -288,13 +297,15 @@ def bench_serve(args):
         srv = kmc.Server(ctx, hbm_budget=budget, max_active=args.max_active)
         for i in range(len(djobs)):  # warm every worker stream and shape
             srv.poll(srv.submit(*job(i))).free()
-        # closed loop: every job queued at once
+        # closed loop: every job queued at once (once to warm the table
+        # pools with as many tables alive as the loop keeps, then timed)
         n_sat = max(6 * len(djobs), 64)
-        t = time.perf_counter()
-        tickets = [srv.submit(*job(i)) for i in range(n_sat)]
-        for tk in tickets:
-            srv.poll(tk).free()
-        sat = n_sat / (time.perf_counter() - t)
+        for rep in range(2):
+            t = time.perf_counter()
+            tickets = [srv.submit(*job(i)) for i in range(n_sat)]
+            for tk in tickets:
+                srv.poll(tk).free()
+            sat = n_sat / (time.perf_counter() - t)
         rows = []
         rng = np.random.default_rng(5)
         for frac in args.serve_lambdas:
@@ -338,10 +349,108 @@ def bench_serve(args):
         out["budgets"][label] = {"budget_bytes": st["budget"], "saturation_jobs_s": sat,
                                  "peak_admitted_bytes": st["peak_admitted_bytes"],
                                  "points": rows}
+    # the plain per-job launch on the same pool: one host thread counts the
+    # jobs one after another (kmc_count_ex), at the same arrival rates
+    n_sat = max(6 * len(djobs), 64)
+    for rep in range(2):
+        t = time.perf_counter()
+        for i in range(n_sat):
+            ctx.count(*job(i)).free()
+        plain_sat = n_sat / (time.perf_counter() - t)
+    rows = []
+    rng = np.random.default_rng(5)
+    sat = out["budgets"]["full"]["saturation_jobs_s"]
+    for frac in args.serve_lambdas:
+        lam = frac * sat
+        n = args.serve_arrivals
+        gaps = rng.exponential(1.0 / lam, size=n)
+        arrive = np.cumsum(gaps)
+        lat, bases = [], 0
+        t0 = time.perf_counter()
+        for i in range(n):
+            d = t0 + arrive[i] - time.perf_counter()
+            if d > 0:
+                time.sleep(d)
+            r = ctx.count(*job(i))
+            done = time.perf_counter()
+            lat.append((done - (t0 + arrive[i])) * 1e3)
+            bases += r.stats["n_bases"]
+            r.free()
+        span = time.perf_counter() - t0
+        rows.append({"lambda_frac": frac, "lambda_jobs_s": lam, "arrivals": n,
+                     "achieved_jobs_s": n / span, "bases_per_s": bases / span,
+                     "latency_ms_p50": float(np.percentile(lat, 50)),
+                     "latency_ms_p99": float(np.percentile(lat, 99))})
+        print(f"plain lambda {frac}: {rows[-1]}", file=sys.stderr, flush=True)
+    out["plain"] = {"saturation_jobs_s": plain_sat, "points": rows,
+                    "served_over_plain_saturation": sat / plain_sat}
+    if args.serve_large:
+        out["large_in_mix"] = serve_large_mix(ctx, kmc, djobs, job, sat, args)
     ctx.close()
     full = out["budgets"]["full"]
     out["value"] = full["saturation_jobs_s"]
     return out
+
+
+def serve_large_mix(ctx, kmc, djobs, job, sat, args):
+    """The served form's large job (60M reads x 150 bp, 9 Gbases, k = 28)
+    submitted first, beside Poisson arrivals of the pool's jobs at half the
+    saturation rate, for each budget; the large job's table must equal its
+    table counted alone."""
+    import queue
+    import threading
+    import torch
+    from paper_1407_1507_amd import synth
+    seq, off, p = synth.make("large-300M-60Mx150")
+    dl = (torch.from_numpy(seq).to("cuda:0"), torch.from_numpy(off.view(np.int64)).to("cuda:0"))
+    del seq, off
+    largs = (dl[0], dl[1], p["k"], p["p"], p["n_bins"], p["cutoff_min"], p["cutoff_max"])
+    alone = ctx.count(*largs, flags=kmc.FLAG_DEVICE_TABLE)
+    ref = (alone.n, alone.stats["n_kmers"], alone.stats["us_total"])
+    alone.free()
+    res = {"large_job": {"n_bases": int(dl[0].numel()), "alone_device_ms": ref[2] * 1e-3}}
+    for label, budget in (("full", 0), ("24GB", 24 << 30)):
+        srv = kmc.Server(ctx, hbm_budget=budget, max_active=args.max_active)
+        n = args.serve_arrivals
+        rng = np.random.default_rng(9)
+        gaps = rng.exponential(1.0 / (0.5 * sat), size=n)
+        tickets = queue.Queue()
+        lat = []
+
+        def poller():
+            for _ in range(n):
+                r = srv.poll(tickets.get())
+                lat.append(r.stats["us_latency"] * 1e-3)
+                r.free()
+
+        th = threading.Thread(target=poller)
+        th.start()
+        t0 = time.perf_counter()
+        big = srv.submit(*largs)
+        nxt = t0
+        for i in range(n):
+            nxt += gaps[i]
+            d = nxt - time.perf_counter()
+            if d > 0:
+                time.sleep(d)
+            tickets.put(srv.submit(*job(i)))
+        r = srv.poll(big)
+        big_ms = r.stats["us_latency"] * 1e-3
+        same = r.n == ref[0] and r.stats["n_kmers"] == ref[1]
+        groups, spilled = r.stats["n_groups"], r.stats["records_spilled"]
+        r.free()
+        th.join()
+        span = time.perf_counter() - t0
+        st = srv.stats()
+        srv.stop()
+        res[label] = {"budget_bytes": st["budget"], "large_latency_ms": big_ms,
+                      "large_n_groups": groups, "large_records_spilled": spilled,
+                      "large_table_as_alone": same, "small_jobs": n,
+                      "small_latency_ms_p50": float(np.percentile(lat, 50)),
+                      "small_latency_ms_p99": float(np.percentile(lat, 99)),
+                      "span_s": span}
+        print(f"large in mix {label}: {res[label]}", file=sys.stderr, flush=True)
+    return res
 
 
 def bench_table6(args):
@@ -377,9 +486,107 @@ def bench_table6(args):
             "rows": rows}
 
 
+def fastq_bytes(seq, off, read_len: int) -> np.ndarray:
+    """FASTQ text of equal-length reads ("@r<i>" headers, constant quality),
+    built with array operations."""
+    n = off.size - 1
+    head = np.frombuffer(b"@r\n", dtype=np.uint8)
+    mid = np.frombuffer(b"\n+\n", dtype=np.uint8)
+    rec = np.empty((n, 3 + read_len + 3 + read_len + 1), dtype=np.uint8)
+    rec[:, :3] = head
+    rec[:, 3:3 + read_len] = seq.reshape(n, read_len)
+    rec[:, 3 + read_len:6 + read_len] = mid
+    rec[:, 6 + read_len:6 + 2 * read_len] = ord("I")
+    rec[:, -1] = ord("\n")
+    return rec.reshape(-1)
+
+
+def bench_parse(args):
+    """Device parsing of FASTQ text (kmc_parse): the 2M-read genome workload
+    as FASTQ (one read per record), text resident in HBM."""
+    import torch
+    from paper_1407_1507_amd import kmc, synth
+    seq, off, p = synth.make("genome-5M-2Mx100")
+    text = fastq_bytes(seq, off, 100)
+    dtext = torch.from_numpy(text).to("cuda:0")
+    ctx = kmc.Context(0)
+    for _ in range(args.warmup):
+        kmc.Parsed(ctx, dtext, kmc.FORMAT_FASTQ).free()
+    torch.cuda.synchronize()
+    times = []
+    for _ in range(args.steps):
+        t = time.perf_counter()
+        pr = kmc.Parsed(ctx, dtext, kmc.FORMAT_FASTQ)
+        times.append(time.perf_counter() - t)
+        assert pr.n_reads == off.size - 1 and pr.n_bases == seq.size
+        pr.free()
+    ms = float(np.median(times)) * 1e3
+    ctx.close()
+    return {"metric": "FASTQ bytes parsed per second on the device", "value": text.size / (ms * 1e-3),
+            "unit": "bytes/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+            "ms_per_step": ms, "higher_is_better": True, "data": "synthetic (seeded generator)",
+            "dtype": "u8",
+            "config": {"workload": "genome-5M-2Mx100 as FASTQ (2,000,000 records of 100 bp)",
+                       "text_bytes": int(text.size)},
+            "bases_per_s": seq.size / (ms * 1e-3),
+            "hbm_gbs_alg": (text.size + seq.size + 8 * off.size) / (ms * 1e-3) / 1e9}
+
+
+def bench_query(args):
+    """Batched device lookups (kmc_db_query) in the KMC 2 database of the
+    genome workload's table: half the queries present (in either
+    orientation), half random k-mers."""
+    import torch
+    from paper_1407_1507_amd import kmc, synth
+    seq, off, p = synth.make("genome-5M-2Mx100")
+    ctx = kmc.Context(0)
+    dseq = torch.from_numpy(seq).to("cuda:0")
+    doff = torch.from_numpy(off.view(np.int64)).to("cuda:0")
+    res = ctx.count(dseq, doff, p["k"], p["p"], p["n_bins"], p["cutoff_min"], p["cutoff_max"],
+                    flags=kmc.FLAG_DEVICE_TABLE)
+    t = time.perf_counter()
+    db = kmc.Db.build(ctx, res, 4, 4)
+    build_ms = (time.perf_counter() - t) * 1e3
+    keys = torch.zeros(res.n, dtype=torch.int64, device="cuda:0")
+    counts = torch.zeros(res.n, dtype=torch.int32, device="cuda:0")
+    db.decode(keys, counts)
+    n_q = args.query_n
+    g = torch.Generator(device="cuda:0").manual_seed(7)
+    present = keys[torch.randint(0, res.n, (n_q // 2,), device="cuda:0", generator=g)]
+    rnd = torch.randint(0, 2**56, (n_q - n_q // 2,), device="cuda:0", generator=g,
+                        dtype=torch.int64)
+    q = torch.cat([present, rnd])
+    out = torch.zeros(n_q, dtype=torch.int32, device="cuda:0")
+    for _ in range(args.warmup):
+        db.query(q, out)
+    torch.cuda.synchronize()
+    times = []
+    for _ in range(args.steps):
+        t = time.perf_counter()
+        db.query(q, out)
+        times.append(time.perf_counter() - t)
+    hit = float((out[: n_q // 2] > 0).float().mean())
+    ms = float(np.median(times)) * 1e3
+    info = db.info
+    db.free()
+    res.free()
+    ctx.close()
+    return {"metric": "k-mer lookups per second in the device database", "value": n_q / (ms * 1e-3),
+            "unit": "lookups/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+            "ms_per_step": ms, "higher_is_better": True, "data": "synthetic (seeded generator)",
+            "dtype": "u64",
+            "config": {"workload": f"genome-5M-2Mx100 table ({info['total_kmers']} k-mers, "
+                                   "k=28, lut_prefix_length 4, 4-byte counters), "
+                                   f"{n_q} queries, half present",
+                       "queries": n_q},
+            "present_hit_rate": hit, "db_build_ms": build_ms}
+
+
 def main():
     ap = argparse.ArgumentParser()
-    ap.add_argument("--mode", choices=["single", "batch", "serve", "table6"], default="single")
+    ap.add_argument("--mode", choices=["single", "batch", "serve", "table6", "parse", "query"],
+                    default="single")
+    ap.add_argument("--query-n", type=int, default=50_000_000)
     ap.add_argument("--table6-scale", type=float, default=1.0)
     ap.add_argument("--batch-jobs", type=int, default=256)
     ap.add_argument("--batch-scale", type=float, default=1.0)
@@ -389,6 +596,8 @@ def main():
     ap.add_argument("--serve-lambdas", type=float, nargs="+",
                     default=[0.25, 0.5, 0.7, 0.85, 1.0, 1.2])
     ap.add_argument("--max-active", type=int, default=4)
+    ap.add_argument("--serve-large", action="store_true",
+                    help="serve mode: also the 9-Gbase large job beside the arrivals")
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=2)
@@ -411,7 +620,8 @@ def main():
 
     if args.mode != "single":
         line = {"batch": bench_batch, "serve": bench_serve,
-                "table6": bench_table6}[args.mode](args)
+                "table6": bench_table6, "parse": bench_parse,
+                "query": bench_query}[args.mode](args)
         print(json.dumps(line), flush=True)
         return
 

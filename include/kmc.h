@@ -134,6 +134,10 @@ typedef struct kmc_stats {
   uint64_t split_passes;   /* 1, or 2 when a bin outgrew its sampled estimate */
   uint64_t n_big_keys;     /* k-mers of the tiles counted through HBM (n_big_tiles) */
   uint64_t n_big_out;      /* entries of the table those tiles kept */
+  uint64_t n_groups;       /* bin groups of the sorting phase (1 unless a
+                              memory budget splits the job) */
+  uint64_t records_spilled; /* 1 if the super k-mer records went to pinned
+                               host memory (memory budget) */
   double us_map;           /* device time of each phase, microseconds */
   double us_split;
   double us_expand;
@@ -161,8 +165,9 @@ typedef struct kmc_stats {
  *               is for k-mers with no allowed p-mer (always host memory).
  * keys/counts are host memory unless on_device = 1.  reserved records how
  * the library owns keys/counts (1: in a caller's workspace, kmc_count_ws;
- * 2: a device block that kmc_table_free hands back to the library's pool of
- * table memory for later tables); callers leave it alone.
+ * 2: a device block, 3: a pinned host block, that kmc_table_free hands back
+ * to the library's pool of table memory for later tables); callers leave it
+ * alone.
  * The table is owned by the library: release it with kmc_table_free. */
 typedef struct kmc_table {
   uint32_t k;
@@ -190,6 +195,19 @@ void kmc_ctx_destroy(kmc_ctx* ctx);
 /* Text of the last error seen on ctx ("" if none).  Valid until the next
  * call on ctx. */
 const char* kmc_last_error(const kmc_ctx* ctx);
+/* Memory budget of ctx's jobs (kmc_count / kmc_count_ex): the device bytes
+ * their buffers may take (the caller's reads and the returned device table
+ * aside); 0 = no bound (the default).  A job above it still runs, the way
+ * the paper's disk-based design keeps RAM bounded (bins on disk, one bin
+ * group sorted at a time; Methods, "Sketch of the algorithm"; Additional
+ * features, RAM-only mode): its bins are expanded, counted and assembled in
+ * groups whose keys fit the budget, and when the super k-mer records take
+ * more than half of it they go to pinned host memory and each group's
+ * records are copied back to the device.  Same table.  KMC_ERR_TOO_LARGE if
+ * one bin's keys exceed the budget.  With KMC_FLAG_ASCENDING the whole table
+ * is ordered on the device.  Not used by kmc_count_ws / kmc_count_static
+ * (their workspace is the bound). */
+kmc_status kmc_ctx_set_budget(kmc_ctx* ctx, uint64_t device_bytes);
 
 /* Count the canonical k-mers of `reads` (see the header comment).
  * Uses a context on device 0 owned by the calling host thread.
@@ -243,9 +261,13 @@ kmc_status kmc_batch_count(kmc_ctx* ctx, const kmc_job* jobs, uint32_t n_jobs, k
 
 /* Served form: jobs are submitted while others run; a job is admitted when
  * its footprint (kmc_workspace_size) fits the HBM budget next to the jobs
- * already admitted (a job larger than the whole budget is admitted alone),
- * and up to max_active admitted jobs run at once, each on its own stream;
- * as one finishes the next admissible job starts (continuous batching). */
+ * already admitted, and up to max_active admitted jobs run at once, each on
+ * its own stream; as one finishes the next admissible job starts (continuous
+ * batching).  A job larger than the whole budget runs alone, within the
+ * budget: the reserved arena is released while it runs and the job's
+ * buffers are bounded by the budget as under kmc_ctx_set_budget (bin
+ * groups, records in pinned host memory); its device table, if requested,
+ * is allocated beside the budget. */
 typedef struct kmc_server_cfg {
   uint64_t hbm_budget; /* bytes; 0 = 90% of the device memory free at start */
   uint32_t max_active; /* 1..16 jobs running at once; 0 = 4 */
@@ -315,6 +337,99 @@ kmc_status kmc_count_static(kmc_ctx* ctx, const kmc_reads* reads, const kmc_para
                             void* stream, uint64_t* keys_out, uint32_t* counts_out,
                             uint64_t out_cap, uint64_t* n_out, uint64_t* bin_offsets,
                             kmc_stats* stats);
+
+/* ------------------------------------------------------------ database
+ * The KMC 2 database (supplement, "Database format" and "API"): the table of
+ * a count in the layout of the .kmc_pre / .kmc_suf files, held in device
+ * memory, written to and read from those files, and queried in batches on
+ * the device.
+ *   map       uint32[4^p + 1]: the prefix array of each signature value (the
+ *             table's sig_to_bin);
+ *   prefixes  n_bins arrays of 4^lut_prefix_length uint64 and a guard:
+ *             entry x of array b = index of the first record of bin b whose
+ *             k-mer starts with the lut-symbol prefix x; the guard = the
+ *             number of records;
+ *   records   per table entry (bin by bin, keys ascending inside a bin): the
+ *             k - lut_prefix_length symbols after the prefix, four per byte,
+ *             leftmost symbol first in the high bits, then the count on
+ *             counter_size bytes, least significant byte first (counts above
+ *             the field's range are stored as its largest value).
+ * .kmc_pre = "KMCP", prefixes, map, header, header size (uint32), "KMCP";
+ * .kmc_suf = "KMCS", records, "KMCS"; integers least significant byte first.
+ * The header's unused tmp[0] holds `flags` (0 for the paper's canonical,
+ * signature-binned database). */
+typedef struct kmc_db_info {
+  uint32_t kmer_length;
+  uint32_t mode;              /* 0: occurrence counters */
+  uint32_t counter_size;      /* bytes per counter, 1..4 */
+  uint32_t lut_prefix_length; /* symbols cut off as the prefix; 4 | (k - it) */
+  uint32_t signature_length;  /* p */
+  uint32_t min_count;         /* the count's cutoffs */
+  uint32_t max_count;
+  uint32_t flags;             /* KMC_FLAG_NON_CANONICAL / KMC_FLAG_PLAIN_MINIMIZERS */
+  uint64_t total_kmers;       /* records */
+} kmc_db_info;
+
+typedef struct kmc_db kmc_db;
+
+/* Build a database from a bin-major table (host or device; not one counted
+ * with KMC_FLAG_ASCENDING) and the parameters it was counted with, on ctx's
+ * device.  KMC_ERR_INVALID_ARG if the parameters do not match the table,
+ * 4 does not divide k - lut_prefix_len, counter_size is not 1..4, or
+ * n_bins * 4^lut_prefix_len exceeds 2^28. */
+kmc_status kmc_db_build(kmc_ctx* ctx, const kmc_table* table, const kmc_params* params,
+                        uint32_t lut_prefix_len, uint32_t counter_size, kmc_db** out);
+/* Header fields of a database. */
+kmc_status kmc_db_info_get(const kmc_db* db, kmc_db_info* info);
+/* Write <path_prefix>.kmc_pre and <path_prefix>.kmc_suf. */
+kmc_status kmc_db_write(const kmc_db* db, const char* path_prefix);
+/* Read <path_prefix>.kmc_pre / .kmc_suf into device memory of ctx's device
+ * (markers, header position, sizes and prefix arrays checked:
+ * KMC_ERR_INVALID_ARG on a malformed file). */
+kmc_status kmc_db_open(kmc_ctx* ctx, const char* path_prefix, kmc_db** out);
+/* Batched random-access lookup (the API's CheckKmer): kmers = n packed k-mers
+ * as read (device memory, key_words per k-mer, hi word first), counts = n
+ * uint32 (device memory).  A k-mer is put in canonical form first when the
+ * database is canonical; counts[i] = its stored count, or 0 if it is absent
+ * or its count lies outside [min_count, max_count] (SetMinCount /
+ * SetMaxCount).  On `stream` (NULL = the null stream); returns when done. */
+kmc_status kmc_db_query(const kmc_db* db, const uint64_t* kmers, uint64_t n, uint32_t min_count,
+                        uint32_t max_count, uint32_t* counts, void* stream);
+/* Every record back as (key, count) in database order (the API's listing):
+ * keys = total_kmers * key_words uint64, counts = total_kmers uint32, both
+ * device memory. */
+kmc_status kmc_db_decode(const kmc_db* db, uint64_t* keys, uint32_t* counts, void* stream);
+/* Free a database.  NULL is allowed. */
+void kmc_db_free(kmc_db* db);
+
+/* -------------------------------------------------------------- parsing
+ * FASTQ, FASTA and multi-FASTA text (uncompressed) parsed on the device into
+ * CSR reads (the input of the distribution phase, which reads FASTQ / FASTA:
+ * Methods, "Sketch of the algorithm"; Additional features).  Lines end with
+ * '\n'; a '\r' before it is dropped; the last line may lack the '\n';
+ * trailing empty lines are ignored.
+ *   FASTQ: records of four lines ('@' header, sequence, '+' line, quality of
+ *          the sequence's length); each sequence line is one read.  Wrapped
+ *          (multi-line) FASTQ records are not supported.
+ *   FASTA: a line starting with '>' opens a record; its read is the
+ *          following lines joined without line breaks, up to the next header
+ *          (a whole genome record is one long read).
+ * Read bytes are copied unchanged (bytes other than A/C/G/T are invalid
+ * symbols for the count, as in any read). */
+#define KMC_FORMAT_AUTO 0u  /* from the first byte that is not white space */
+#define KMC_FORMAT_FASTQ 1u
+#define KMC_FORMAT_FASTA 2u
+typedef struct kmc_parsed kmc_parsed;
+/* Parse n_bytes of text (host memory, or device memory of ctx's device when
+ * on_device != 0) on ctx's device.  *reads receives device CSR reads
+ * (on_device = 1) owned by *out until kmc_parsed_free.  KMC_ERR_INVALID_ARG
+ * for an unknown format, a FASTQ record with a bad '@' or '+' line or a
+ * quality line of another length, FASTQ text that ends inside a record, or
+ * FASTA sequence before the first header (kmc_last_error names the line). */
+kmc_status kmc_parse(kmc_ctx* ctx, const uint8_t* text, uint64_t n_bytes, int32_t on_device,
+                     uint32_t format, kmc_reads* reads, kmc_parsed** out);
+/* Free parsed reads.  NULL is allowed. */
+void kmc_parsed_free(kmc_parsed* parsed);
 
 /* Audit entry (tests): the signature of the window starting at every byte of
  * the input, as the GPU's split kernel computes it, into sig_per_window

@@ -12,7 +12,8 @@ CSRC = os.path.join(HERE, "csrc")
 OUT = os.path.join(HERE, "libkmc_hip.so")
 BUILD = os.path.join(ROOT, "_build")
 SOURCES = ["kmc_split.hip", "kmc_expand.hip", "kmc_sort.hip", "kmc_api.hip", "kmc_serve.hip",
-           "kmc_scan_wide.hip", "kmc_static.hip"]
+           "kmc_scan_wide.hip", "kmc_static.hip", "kmc_db.hip",
+           "kmc_parse.hip"]
 ARCH = os.environ.get("KMC_OFFLOAD_ARCH", "gfx950")
 FLAGS = ["-O3", "-std=c++17", "-fPIC", f"--offload-arch={ARCH}",
          "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",

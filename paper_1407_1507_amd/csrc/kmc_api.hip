@@ -27,7 +27,8 @@ namespace {
 enum BufId {
   B_SEQ, B_OFF, B_HIST, B_MAP, B_BINCNT, B_CURSOR, B_REC, B_FINE, B_TOF, B_TILES, B_TCUR,
   B_BASES, B_HTASK, B_ETASK, B_KEYS, B_COUNTS, B_TILEOUT, B_BIG, B_MISC, B_TMP, B_SCANTMP,
-  B_TILEOFF, B_BINOFF, B_OUTK, B_OUTC, B_DBG1, B_DBG2, B_ASCSEG, B_ASCK, B_ASCC, B_COUNT_
+  B_TILEOFF, B_BINOFF, B_OUTK, B_OUTC, B_DBG1, B_DBG2, B_ASCSEG, B_ASCK, B_ASCC, B_STAGE,
+  B_AUX0, B_COUNT_ = B_AUX0 + kmc::kCtxAuxBuffers
 };
 
 struct DevBuf {
@@ -75,6 +76,10 @@ struct kmc_ctx {
   // allocation-free mode (kmc_count_static): host staging in pageable
   // vectors instead of pinned buffers, and the table written to the caller's
   // device buffers (user_cap entries)
+  // memory budget (kmc_ctx_set_budget): device bytes a job's buffers may
+  // take, 0 = unbounded; records beyond it spill to pinned host memory
+  uint64_t budget = 0;
+  DevBuf spill;            // pinned host records (device-accessible)
   bool pageable_host = false;
   std::vector<uint8_t> hvec[H_COUNT_];
   uint64_t* user_keys = nullptr;
@@ -142,6 +147,29 @@ T* ensure(kmc_ctx* c, BufId id, size_t bytes) {
   return static_cast<T*>(b.p);
 }
 
+// Device-accessible pinned host memory for records that do not fit the
+// budget, cached like the device buffers.
+template <class T = uint64_t>
+T* ensure_spill(kmc_ctx* c, size_t bytes) {
+  DevBuf& b = c->spill;
+  if (b.cap < bytes) {
+    if (b.p) (void)hipHostFree(b.p);
+    b.p = nullptr;
+    b.cap = 0;
+    const size_t want = std::max<size_t>(bytes, 4096);
+    check(c, hipHostMalloc(&b.p, want, hipHostMallocMapped), "hipHostMalloc records");
+    b.cap = want;
+  }
+  void* d = nullptr;
+  check(c, hipHostGetDevicePointer(&d, b.p, 0), "hipHostGetDevicePointer");
+  return static_cast<T*>(d);
+}
+
+// Device bytes per k-mer of one bin group in the sorting phase: keys, their
+// counters, the big-tile scratch, the group's gathered entries, and room for
+// its records when they are staged from host memory.
+uint64_t key_bytes_per_kmer(uint32_t kw) { return 3 * 8 * (uint64_t)kw + 8 + 16; }
+
 uint32_t ilog2_ceil(uint64_t x) {
   uint32_t r = 0;
   while ((1ull << r) < x) ++r;
@@ -202,8 +230,14 @@ void build_map(const std::vector<uint32_t>& hist, uint32_t n_bins, std::vector<u
 // block) goes to a per-process pool and serves a later table of a similar
 // size, so that a stream of jobs does not pay a device allocation (and the
 // synchronisation of a device free) per table.  The pool keeps at most
-// kPoolKeep bytes per device; anything beyond that is freed at once.
+// kPoolKeep bytes per device; anything beyond that is freed at once.  Host
+// tables come from the same pool's pinned host blocks (pseudo-device
+// kHostPool): the table is copied straight into them at full bus rate, and a
+// recycled block has no pages to fault in; tables above kPinnedMax bytes go
+// to ordinary memory.
 constexpr size_t kPoolKeep = size_t(8) << 30;
+constexpr int kHostPool = 64;
+constexpr size_t kPinnedMax = size_t(4) << 30;
 
 struct TablePool {
   struct Block {
@@ -214,7 +248,7 @@ struct TablePool {
   std::mutex mu;
   std::vector<Block> free_blocks;
   std::unordered_map<void*, Block> live;
-  size_t kept[64] = {};
+  size_t kept[65] = {};  // per device, then the host blocks
 };
 
 TablePool& table_pool() {
@@ -236,13 +270,14 @@ void* pool_take(int device, size_t bytes) {
     if (best != SIZE_MAX) {
       TablePool::Block b = P.free_blocks[best];
       P.free_blocks.erase(P.free_blocks.begin() + best);
-      P.kept[device & 63] -= b.bytes;
+      P.kept[device == kHostPool ? 64 : device & 63] -= b.bytes;
       P.live.emplace(b.p, b);
       return b.p;
     }
   }
   void* p = nullptr;
-  if (hipMalloc(&p, bytes) != hipSuccess) {
+  const hipError_t e = device == kHostPool ? hipHostMalloc(&p, bytes, 0) : hipMalloc(&p, bytes);
+  if (e != hipSuccess) {
     (void)hipGetLastError();
     return nullptr;
   }
@@ -263,11 +298,12 @@ bool pool_give(void* p) {
     b = it->second;
     P.live.erase(it);
     P.free_blocks.push_back(b);
-    P.kept[b.device & 63] += b.bytes;
+    const int ki = b.device == kHostPool ? 64 : b.device & 63;
+    P.kept[ki] += b.bytes;
     // over the limit: free the oldest blocks of that device
-    for (size_t i = 0; i < P.free_blocks.size() && P.kept[b.device & 63] > kPoolKeep;) {
+    for (size_t i = 0; i < P.free_blocks.size() && P.kept[ki] > kPoolKeep;) {
       if (P.free_blocks[i].device == b.device) {
-        P.kept[b.device & 63] -= P.free_blocks[i].bytes;
+        P.kept[ki] -= P.free_blocks[i].bytes;
         drop.push_back(P.free_blocks[i]);
         P.free_blocks.erase(P.free_blocks.begin() + i);
       } else {
@@ -276,6 +312,10 @@ bool pool_give(void* p) {
     }
   }
   for (const auto& d : drop) {
+    if (d.device == kHostPool) {
+      (void)hipHostFree(d.p);
+      continue;
+    }
     int cur = 0;
     (void)hipGetDevice(&cur);
     (void)hipSetDevice(d.device);
@@ -283,6 +323,24 @@ bool pool_give(void* p) {
     (void)hipSetDevice(cur);
   }
   return true;
+}
+
+// Host memory of a host table's keys and counts: one pinned block from the
+// pool (reserved = 3) up to kPinnedMax bytes, else ordinary memory.
+void host_table(kmc_table* T, uint64_t n, uint32_t kw) {
+  const size_t kb = (std::max<uint64_t>(1, n * kw) * 8 + 255) & ~(size_t)255;
+  const size_t total = kb + std::max<uint64_t>(1, n) * 4;
+  void* blk = total <= kPinnedMax ? pool_take(kHostPool, total) : nullptr;
+  if (blk) {
+    T->keys = static_cast<uint64_t*>(blk);
+    T->counts = reinterpret_cast<uint32_t*>(static_cast<uint8_t*>(blk) + kb);
+    T->reserved = 3;
+    return;
+  }
+  T->keys = static_cast<uint64_t*>(std::malloc(std::max<uint64_t>(1, n * kw) * 8));
+  T->counts = static_cast<uint32_t*>(std::malloc(std::max<uint64_t>(1, n) * 4));
+  T->reserved = 0;
+  if (!T->keys || !T->counts) throw Fail{KMC_ERR_OUT_OF_MEMORY};
 }
 
 kmc_table* new_table() {
@@ -455,23 +513,23 @@ void run_count(kmc_ctx* c, const kmc_reads* R, const kmc_params* P, kmc_table* T
   // record end, first fine-histogram task, first expansion task (pinned, so
   // the uploads are asynchronous; written only while the stream is idle)
   const size_t nb1 = (size_t)J.n_bins + 1, n_bases_words = 6 * nb1;
-  uint64_t* bases = ensure_host<uint64_t>(c, H_BASES, n_bases_words * 8);
-  uint64_t* rec_base = bases;
-  uint64_t* key_base = rec_base + nb1;
-  uint64_t* tile_base = key_base + nb1;
-  uint64_t* rec_end = tile_base + nb1;
-  uint64_t* htask_pre = rec_end + nb1;
-  uint64_t* etask_pre = htask_pre + nb1;
+  uint64_t* rec_base = ensure_host<uint64_t>(c, H_BASES, n_bases_words * 8);
   unsigned long long* bincnt = ensure<unsigned long long>(c, B_BINCNT, (size_t)J.n_bins * 16);
   unsigned long long* cursor = bincnt;
   unsigned long long* kmer_dev = bincnt + J.n_bins;
   uint64_t* d_bases = ensure<uint64_t>(c, B_BASES, n_bases_words * 8);
   uint64_t* h_cnt = ensure_host<uint64_t>(c, H_CNT, (size_t)J.n_bins * 16);
   uint64_t* records = nullptr;
+  bool rec_on_host = false;
   for (int pass = 0; pass < 2; ++pass) {
     rec_base[0] = 0;
     for (uint32_t b = 0; b < J.n_bins; ++b) rec_base[b + 1] = rec_base[b] + cap[b];
-    records = ensure<uint64_t>(c, B_REC, rec_base[J.n_bins] * RW * 8);
+    // under a memory budget the records stay on the device while they take
+    // at most half of it; beyond that they go to pinned host memory (the
+    // split writes them over the bus, each bin group is staged back)
+    const uint64_t rec_bytes = rec_base[J.n_bins] * RW * 8;
+    rec_on_host = c->budget && !c->ws_base && rec_bytes > c->budget / 2;
+    records = rec_on_host ? ensure_spill(c, rec_bytes) : ensure<uint64_t>(c, B_REC, rec_bytes);
     check(c, hipMemcpyAsync(d_bases, rec_base, ((size_t)J.n_bins + 1) * 8, hipMemcpyHostToDevice, s), "H2D");
     check(c, hipMemcpyAsync(cursor, rec_base, (size_t)J.n_bins * 8, hipMemcpyHostToDevice, s), "H2D");
     check(c, hipMemsetAsync(kmer_dev, 0, (size_t)J.n_bins * 8, s), "memset");
@@ -497,13 +555,14 @@ void run_count(kmc_ctx* c, const kmc_reads* R, const kmc_params* P, kmc_table* T
   std::vector<uint64_t> rec_cnt(cap);
   const uint64_t* kmer_cnt = h_cnt + J.n_bins;
   uint64_t max_bin = 0, n_rec = 0;
-  key_base[0] = 0;
+  std::vector<uint64_t> g_rec_base(rec_base, rec_base + nb1), g_key_base(nb1, 0);
   for (uint32_t b = 0; b < J.n_bins; ++b) {
-    key_base[b + 1] = key_base[b] + kmer_cnt[b];
+    g_key_base[b + 1] = g_key_base[b] + kmer_cnt[b];
     max_bin = std::max<uint64_t>(max_bin, kmer_cnt[b]);
     n_rec += rec_cnt[b];
   }
-  const uint64_t n_kmers = key_base[J.n_bins];
+  std::vector<uint64_t> g_kmers(kmer_cnt, kmer_cnt + J.n_bins);
+  const uint64_t n_kmers = g_key_base[J.n_bins];
   st.n_kmers = n_kmers;
   st.n_superkmers = n_rec;
   st.max_bin_kmers = max_bin;
@@ -513,13 +572,11 @@ void run_count(kmc_ctx* c, const kmc_reads* R, const kmc_params* P, kmc_table* T
   }
   check(c, hipEventRecord(c->ev[2], s), "event");
 
-  // ---- expand: fine histogram per bin, tiles, scatter of canonical keys
   KeyCfg kc;
   kc.k = J.k;
   kc.key_words = J.kw;
   kc.tile_cap = J.kw == 1 ? kTileCap1 : kTileCap2;
   kc.tile_limit = 3 * kc.tile_cap / 4;  // the largest tile the tile kernels count
-  kc.n_bins = J.n_bins;
   kc.cutoff_min = J.ci;
   kc.cutoff_max = J.cx;
   kc.fp_bits = (J.flags & KMC_FLAG_TEST_NARROW_FINGERPRINT) ? 2u : 47u;
@@ -529,118 +586,237 @@ void run_count(kmc_ctx* c, const kmc_reads* R, const kmc_params* P, kmc_table* T
   uint32_t fb = ilog2_ceil(max_bin * 8 / kc.tile_cap + 1);
   fb = std::max<uint32_t>(1, std::min<uint32_t>({fb, (uint32_t)kMaxFineBits, 2 * J.k}));
   kc.fine_bits = fb;
-  uint64_t n_tiles = 0, max_tiles = 0;
-  for (uint32_t b = 0; b < J.n_bins; ++b) {
-    tile_base[b] = n_tiles;
-    // greedy packing: two consecutive tiles hold more than tile_limit keys;
-    // and a tile holds at least one fine range, so a bin never has more tiles
-    // than fine ranges (a bin whose fine ranges exceed the limit has them as
-    // big tiles, sorted through HBM)
-    uint64_t nt = kmer_cnt[b] ? 2 * ((kmer_cnt[b] - 1) / kc.tile_limit + 1) + 1 : 0;
-    nt = std::min<uint64_t>(nt, 1ull << fb);
-    n_tiles += nt;
-    max_tiles = std::max(max_tiles, nt);
-  }
-  tile_base[J.n_bins] = n_tiles;  // max_tiles <= 2^fb <= kMaxTilesPerBin
-  st.n_tiles = n_tiles;
-  // tasks: fine-histogram tasks of up to hrec records, expansion tasks of one
-  // record per lane; only per-bin task offsets go to the device, which lists
-  // every task's bin itself
-  const uint64_t hrec = std::min<uint64_t>(65536, std::max<uint64_t>(1024, 8ull << fb));
-  htask_pre[0] = etask_pre[0] = 0;
-  for (uint32_t b = 0; b < J.n_bins; ++b) {
-    rec_end[b] = rec_base[b] + rec_cnt[b];
-    htask_pre[b + 1] = htask_pre[b] + (rec_cnt[b] + hrec - 1) / hrec;
-    etask_pre[b + 1] = etask_pre[b] + (rec_cnt[b] + kExpandThreads - 1) / kExpandThreads;
-  }
-  rec_end[J.n_bins] = rec_base[J.n_bins];
-  const uint64_t n_htasks = htask_pre[J.n_bins], n_etasks = etask_pre[J.n_bins];
-  check(c, hipMemcpyAsync(d_bases, bases, n_bases_words * 8, hipMemcpyHostToDevice, s), "H2D");
-  const uint64_t* d_key_base = d_bases + nb1;
-  const uint64_t* d_tile_base = d_bases + 2 * nb1;
-  uint16_t* d_hbin = ensure<uint16_t>(c, B_HTASK, std::max<uint64_t>(1, n_htasks) * 2);
-  ExpandTask* d_etask =
-      ensure<ExpandTask>(c, B_ETASK, std::max<uint64_t>(1, n_etasks) * sizeof(ExpandTask));
-  check(c, launch_task_bins(s, J.n_bins, d_bases + 4 * nb1, d_hbin, d_bases + 5 * nb1, d_bases,
-                            d_bases + 3 * nb1, (uint32_t)kExpandThreads, d_etask),
-        "task_bins");
-  const TaskMap hmap{d_hbin, d_bases + 4 * nb1, d_bases, d_bases + 3 * nb1, (uint32_t)hrec,
-                     nullptr};
-  const TaskMap emap{nullptr, d_bases + 5 * nb1, d_bases, d_bases + 3 * nb1,
-                     (uint32_t)kExpandThreads, d_etask};
-  const size_t nfine = (size_t)J.n_bins << fb;
-  uint32_t* fine = ensure<uint32_t>(c, B_FINE, nfine * 4);
-  check(c, hipMemsetAsync(fine, 0, nfine * 4, s), "memset");
-  kbeg(c, KMC_K_FINE_HIST, s);
-  check(c, launch_fine_hist(s, kc, hmap, (uint32_t)n_htasks, records, fine), "fine_hist");
-  kend(c, KMC_K_FINE_HIST, s);
-  uint16_t* tof = ensure<uint16_t>(c, B_TOF, nfine * 2);
-  Tile* tiles = ensure<Tile>(c, B_TILES, n_tiles * sizeof(Tile));
-  unsigned long long* tcur = ensure<unsigned long long>(c, B_TCUR, n_tiles * 8);
-  if (n_tiles) check(c, hipMemsetAsync(tiles, 0, n_tiles * sizeof(Tile), s), "memset");
-  kbeg(c, KMC_K_PLAN_TILES, s);
-  check(c, launch_plan_tiles(s, kc, fine, d_key_base, d_tile_base, tof, tiles, tcur), "plan");
-  kend(c, KMC_K_PLAN_TILES, s);
-  uint64_t* keys = ensure<uint64_t>(c, B_KEYS, n_kmers * J.kw * 8);
-  uint32_t* counts = ensure<uint32_t>(c, B_COUNTS, n_kmers * 4);
-  kbeg(c, KMC_K_EXPAND, s);
-  check(c, launch_expand_scatter(s, kc, emap, (uint32_t)n_etasks, records, tof, d_tile_base,
-                                 (uint32_t)max_tiles, tcur, keys), "expand");
-  kend(c, KMC_K_EXPAND, s);
-  check(c, hipEventRecord(c->ev[3], s), "event");
 
-  // ---- sort: tiles in LDS, big tiles through HBM
-  uint32_t* tile_out = ensure<uint32_t>(c, B_TILEOUT, n_tiles * 8 + 8);
-  uint32_t* tile_dist = tile_out + n_tiles + (n_tiles & 1);
-  uint32_t* big = ensure<uint32_t>(c, B_BIG, n_tiles * 16 + 16);
-  uint64_t* big_off = reinterpret_cast<uint64_t*>(big + ((n_tiles + 1) & ~1ull));
-  uint32_t* big_order = reinterpret_cast<uint32_t*>(big_off + n_tiles);
-  kbeg(c, KMC_K_TILE_SORT, s);
-  check(c, launch_tile_sort(s, kc, tiles, n_tiles, keys, counts, tile_out, big, big_off,
-                            &misc->n_big, &misc->big_total, tile_dist), "tile_sort");
-  kend(c, KMC_K_TILE_SORT, s);
-  // big tiles: their number stays on the device (no round trip); scratch for
-  // their partition passes is sized for every key
-  kbeg(c, KMC_K_BIG_TILES, s);
-  {
-    uint64_t* tmp = ensure<uint64_t>(c, B_TMP, std::max<uint64_t>(1, n_kmers) * J.kw * 8);
-    check(c, launch_big_tiles(s, kc, tiles, big, big_off, big_order, &misc->n_big,
-                              &misc->big_next, n_tiles,
-                              keys, tmp, counts, tile_out, tile_dist, &misc->big_out),
-          "big_tiles");
+  // ---- groups of bins for the sorting phase.  Without a memory budget (or
+  // when the job fits it) one group holds every bin.  Under a budget the bins
+  // are taken in order into groups whose k-mers fit the key buffers the
+  // budget leaves room for; each group is expanded, counted and assembled on
+  // its own, its entries appended to the table (bins hold disjoint key sets,
+  // so the table is the same).
+  std::vector<std::pair<uint32_t, uint32_t>> groups;
+  const uint64_t per_kmer = key_bytes_per_kmer(J.kw);
+  uint64_t key_cap = ~0ull;
+  if (c->budget && !c->ws_base) {
+    // the records (unless spilled), host reads copied to the device, the
+    // fine histograms, and a fixed allowance for the per-tile and per-task
+    // arrays, scans and counters
+    const uint64_t rec_dev = rec_on_host ? 0 : g_rec_base[J.n_bins] * RW * 8;
+    const uint64_t fixed = (R->on_device ? 0 : J.n_bases + 8 * (J.n_reads + 1)) +
+                           ((uint64_t)J.n_bins << fb) * 6 + (16ull << 20);
+    const uint64_t room = c->budget > rec_dev + fixed ? c->budget - rec_dev - fixed : 0;
+    key_cap = room / per_kmer;
+    if (max_bin > key_cap) {
+      c->err = "a bin's k-mers do not fit the memory budget";
+      throw Fail{KMC_ERR_TOO_LARGE};
+    }
   }
-  kend(c, KMC_K_BIG_TILES, s);
-  check(c, hipEventRecord(c->ev[4], s), "event");
+  if (n_kmers <= key_cap) {
+    groups.emplace_back(0u, J.n_bins);
+  } else {
+    uint32_t b0 = 0;
+    uint64_t acc = 0;
+    for (uint32_t b = 0; b < J.n_bins; ++b) {
+      if (acc + g_kmers[b] > key_cap) {
+        groups.emplace_back(b0, b);
+        b0 = b;
+        acc = 0;
+      }
+      acc += g_kmers[b];
+    }
+    groups.emplace_back(b0, J.n_bins);
+  }
+  const bool grouped = groups.size() > 1 || rec_on_host;
+  st.n_groups = groups.size();
+  st.records_spilled = rec_on_host ? 1 : 0;
+  // a grouped job collects its entries in host memory (pinned staging), and
+  // builds the requested table from them at the end
+  std::vector<uint64_t> acc_keys;
+  std::vector<uint32_t> acc_counts;
+  double acc_us[KMC_N_KERNELS] = {}, acc_phase[3] = {};
+  uint64_t n_out_total = 0, n_distinct = 0, n_tiles_all = 0;
+  uint64_t big_tiles = 0, big_keys = 0, big_out = 0;
+  uint64_t* out_k = nullptr;
+  uint32_t* out_c = nullptr;
 
-  // ---- assemble: offsets of every tile's output, bin offsets, gather
-  uint64_t* tile_off = ensure<uint64_t>(c, B_TILEOFF, (n_tiles + 1) * 8);
-  uint64_t* scan_tmp = ensure<uint64_t>(c, B_SCANTMP, scan_tmp_words(n_tiles) * 8);
-  kbeg(c, KMC_K_ASSEMBLE, s);
-  check(c, launch_scan_u32(s, tile_out, n_tiles, tile_off, scan_tmp), "scan");
-  uint64_t* bin_off = ensure<uint64_t>(c, B_BINOFF, ((size_t)J.n_bins + 1) * 8);
-  check(c, launch_bin_offsets(s, tile_off, d_tile_base, J.n_bins, bin_off), "bin_offsets");
-  kend(c, KMC_K_ASSEMBLE, s);
-  uint64_t* h_binoff = ensure_host<uint64_t>(c, H_BINOFF, (nb1 + 1) * 8);
-  check(c, hipMemcpyAsync(h_binoff, bin_off, nb1 * 8, hipMemcpyDeviceToHost, s), "D2H");
-  // distinct keys: sum of the per-tile counts (a scan; its last entry is the total)
-  uint64_t* dist_scan = ensure<uint64_t>(c, B_DBG1, (n_tiles + 1) * 8);
-  check(c, launch_scan_u32(s, tile_dist, n_tiles, dist_scan, scan_tmp), "scan");
-  check(c, hipMemcpyAsync(h_binoff + nb1, dist_scan + n_tiles, 8, hipMemcpyDeviceToHost, s), "D2H");
-  check(c, hipMemcpyAsync(h_misc_p, misc, sizeof(Misc), hipMemcpyDeviceToHost, s), "D2H");
-  check(c, hipStreamSynchronize(s), "sync");
-  std::memcpy(T->bin_offsets, h_binoff, nb1 * 8);
-  const uint64_t h_distinct = h_binoff[nb1];
-  st.n_big_tiles = h_misc_p->n_big;
-  st.n_big_keys = h_misc_p->big_total;
-  st.n_big_out = h_misc_p->big_out;
-  const uint64_t n_out = T->bin_offsets[J.n_bins];
+  for (size_t gi = 0; gi < groups.size(); ++gi) {
+    const uint32_t b0 = groups[gi].first, b1 = groups[gi].second, nbg = b1 - b0;
+    const size_t gb1 = (size_t)nbg + 1;
+    kc.n_bins = nbg;
+    if (gi > 0) check(c, hipMemsetAsync(misc, 0, sizeof(Misc), s), "memset");
+    // the group's bases, relative to its first bin
+    uint64_t* bases = ensure_host<uint64_t>(c, H_BASES, 6 * gb1 * 8);
+    uint64_t* rb = bases;
+    uint64_t* key_base = rb + gb1;
+    uint64_t* tile_base = key_base + gb1;
+    uint64_t* rec_end = tile_base + gb1;
+    uint64_t* htask_pre = rec_end + gb1;
+    uint64_t* etask_pre = htask_pre + gb1;
+    uint64_t gmax = 0;
+    for (uint32_t i = 0; i <= nbg; ++i) {
+      rb[i] = g_rec_base[b0 + i] - g_rec_base[b0];
+      key_base[i] = g_key_base[b0 + i] - g_key_base[b0];
+    }
+    uint64_t n_tiles = 0, max_tiles = 0;
+    for (uint32_t i = 0; i < nbg; ++i) {
+      const uint64_t km = g_kmers[b0 + i];
+      gmax = std::max(gmax, km);
+      tile_base[i] = n_tiles;
+      // greedy packing: two consecutive tiles hold more than tile_limit keys;
+      // and a tile holds at least one fine range, so a bin never has more
+      // tiles than fine ranges (a bin whose fine ranges exceed the limit has
+      // them as big tiles, sorted through HBM)
+      uint64_t nt = km ? 2 * ((km - 1) / kc.tile_limit + 1) + 1 : 0;
+      nt = std::min<uint64_t>(nt, 1ull << fb);
+      n_tiles += nt;
+      max_tiles = std::max(max_tiles, nt);
+    }
+    tile_base[nbg] = n_tiles;  // max_tiles <= 2^fb <= kMaxTilesPerBin
+    n_tiles_all += n_tiles;
+    const uint64_t gk = key_base[nbg];
+    // tasks: fine-histogram tasks of up to hrec records, expansion tasks of
+    // one record per lane; only per-bin task offsets go to the device, which
+    // lists every task's bin itself
+    const uint64_t hrec = std::min<uint64_t>(65536, std::max<uint64_t>(1024, 8ull << fb));
+    const uint64_t eper = expand_task_records(J.kw);
+    htask_pre[0] = etask_pre[0] = 0;
+    for (uint32_t i = 0; i < nbg; ++i) {
+      const uint64_t rc = rec_cnt[b0 + i];
+      rec_end[i] = rb[i] + rc;
+      htask_pre[i + 1] = htask_pre[i] + (rc + hrec - 1) / hrec;
+      etask_pre[i + 1] = etask_pre[i] + (rc + eper - 1) / eper;
+    }
+    rec_end[nbg] = rb[nbg];
+    const uint64_t n_htasks = htask_pre[nbg], n_etasks = etask_pre[nbg];
+    check(c, hipMemcpyAsync(d_bases, bases, 6 * gb1 * 8, hipMemcpyHostToDevice, s), "H2D");
+    // the group's records: in place on the device, or staged from host memory
+    const uint64_t* grec = records + g_rec_base[b0] * RW;
+    if (rec_on_host) {
+      const uint64_t words = rb[nbg] * RW;
+      uint64_t* stage = ensure<uint64_t>(c, B_STAGE, std::max<uint64_t>(1, words) * 8);
+      if (words)
+        check(c, hipMemcpyAsync(stage, grec, words * 8, hipMemcpyDefault, s), "H2D records");
+      grec = stage;
+    }
+    const uint64_t* d_key_base = d_bases + gb1;
+    const uint64_t* d_tile_base = d_bases + 2 * gb1;
+    uint16_t* d_hbin = ensure<uint16_t>(c, B_HTASK, std::max<uint64_t>(1, n_htasks) * 2);
+    ExpandTask* d_etask =
+        ensure<ExpandTask>(c, B_ETASK, std::max<uint64_t>(1, n_etasks) * sizeof(ExpandTask));
+    check(c, launch_task_bins(s, nbg, d_bases + 4 * gb1, d_hbin, d_bases + 5 * gb1, d_bases,
+                              d_bases + 3 * gb1, (uint32_t)eper, d_etask),
+          "task_bins");
+    const TaskMap hmap{d_hbin, d_bases + 4 * gb1, d_bases, d_bases + 3 * gb1, (uint32_t)hrec,
+                       nullptr};
+    const TaskMap emap{nullptr, d_bases + 5 * gb1, d_bases, d_bases + 3 * gb1,
+                       (uint32_t)eper, d_etask};
+    const size_t nfine = (size_t)nbg << fb;
+    uint32_t* fine = ensure<uint32_t>(c, B_FINE, nfine * 4);
+    check(c, hipMemsetAsync(fine, 0, nfine * 4, s), "memset");
+    kbeg(c, KMC_K_FINE_HIST, s);
+    check(c, launch_fine_hist(s, kc, hmap, (uint32_t)n_htasks, grec, fine), "fine_hist");
+    kend(c, KMC_K_FINE_HIST, s);
+    uint16_t* tof = ensure<uint16_t>(c, B_TOF, nfine * 2);
+    Tile* tiles = ensure<Tile>(c, B_TILES, n_tiles * sizeof(Tile));
+    unsigned long long* tcur = ensure<unsigned long long>(c, B_TCUR, n_tiles * 8);
+    if (n_tiles) check(c, hipMemsetAsync(tiles, 0, n_tiles * sizeof(Tile), s), "memset");
+    kbeg(c, KMC_K_PLAN_TILES, s);
+    check(c, launch_plan_tiles(s, kc, fine, d_key_base, d_tile_base, tof, tiles, tcur), "plan");
+    kend(c, KMC_K_PLAN_TILES, s);
+    uint64_t* keys = ensure<uint64_t>(c, B_KEYS, gk * J.kw * 8);
+    uint32_t* counts = ensure<uint32_t>(c, B_COUNTS, gk * 4);
+    kbeg(c, KMC_K_EXPAND, s);
+    check(c, launch_expand_scatter(s, kc, emap, (uint32_t)n_etasks, grec, tof, d_tile_base,
+                                   (uint32_t)max_tiles, tcur, keys), "expand");
+    kend(c, KMC_K_EXPAND, s);
+    check(c, hipEventRecord(c->ev[3], s), "event");
+
+    // ---- sort: tiles in LDS, big tiles through HBM
+    uint32_t* tile_out = ensure<uint32_t>(c, B_TILEOUT, n_tiles * 8 + 8);
+    uint32_t* tile_dist = tile_out + n_tiles + (n_tiles & 1);
+    uint32_t* big = ensure<uint32_t>(c, B_BIG, n_tiles * 16 + 16);
+    uint64_t* big_off = reinterpret_cast<uint64_t*>(big + ((n_tiles + 1) & ~1ull));
+    uint32_t* big_order = reinterpret_cast<uint32_t*>(big_off + n_tiles);
+    kbeg(c, KMC_K_TILE_SORT, s);
+    check(c, launch_tile_sort(s, kc, tiles, n_tiles, keys, counts, tile_out, big, big_off,
+                              &misc->n_big, &misc->big_total, tile_dist), "tile_sort");
+    kend(c, KMC_K_TILE_SORT, s);
+    // big tiles: their number stays on the device (no round trip); scratch
+    // for their partition passes is sized for every key of the group
+    kbeg(c, KMC_K_BIG_TILES, s);
+    {
+      uint64_t* tmp = ensure<uint64_t>(c, B_TMP, std::max<uint64_t>(1, gk) * J.kw * 8);
+      check(c, launch_big_tiles(s, kc, tiles, big, big_off, big_order, &misc->n_big,
+                                &misc->big_next, n_tiles, keys, tmp, counts, tile_out, tile_dist,
+                                &misc->big_out),
+            "big_tiles");
+    }
+    kend(c, KMC_K_BIG_TILES, s);
+    check(c, hipEventRecord(c->ev[4], s), "event");
+
+    // ---- assemble: offsets of every tile's output, bin offsets, gather
+    uint64_t* tile_off = ensure<uint64_t>(c, B_TILEOFF, (n_tiles + 1) * 8);
+    uint64_t* scan_tmp = ensure<uint64_t>(c, B_SCANTMP, scan_tmp_words(n_tiles) * 8);
+    kbeg(c, KMC_K_ASSEMBLE, s);
+    check(c, launch_scan_u32(s, tile_out, n_tiles, tile_off, scan_tmp), "scan");
+    uint64_t* bin_off = ensure<uint64_t>(c, B_BINOFF, gb1 * 8);
+    check(c, launch_bin_offsets(s, tile_off, d_tile_base, nbg, bin_off), "bin_offsets");
+    kend(c, KMC_K_ASSEMBLE, s);
+    uint64_t* h_binoff = ensure_host<uint64_t>(c, H_BINOFF, (gb1 + 1) * 8);
+    check(c, hipMemcpyAsync(h_binoff, bin_off, gb1 * 8, hipMemcpyDeviceToHost, s), "D2H");
+    // distinct keys: sum of the per-tile counts (a scan; its last entry is the total)
+    uint64_t* dist_scan = ensure<uint64_t>(c, B_DBG1, (n_tiles + 1) * 8);
+    check(c, launch_scan_u32(s, tile_dist, n_tiles, dist_scan, scan_tmp), "scan");
+    check(c, hipMemcpyAsync(h_binoff + gb1, dist_scan + n_tiles, 8, hipMemcpyDeviceToHost, s),
+          "D2H");
+    check(c, hipMemcpyAsync(h_misc_p, misc, sizeof(Misc), hipMemcpyDeviceToHost, s), "D2H");
+    check(c, hipStreamSynchronize(s), "sync");
+    const uint64_t g_out = h_binoff[nbg];
+    for (uint32_t i = 0; i <= nbg; ++i) T->bin_offsets[b0 + i] = n_out_total + h_binoff[i];
+    n_distinct += h_binoff[gb1];
+    big_tiles += h_misc_p->n_big;
+    big_keys += h_misc_p->big_total;
+    big_out += h_misc_p->big_out;
+    if (!grouped) {
+      // one group: the table is gathered straight into its final place
+      n_out_total = g_out;
+      break;
+    }
+    // a group of a grouped job: gathered into a staging block, appended to
+    // the entries kept in host memory
+    uint64_t* gk_out = ensure<uint64_t>(c, B_OUTK, std::max<uint64_t>(1, g_out) * J.kw * 8);
+    uint32_t* gc_out = ensure<uint32_t>(c, B_OUTC, std::max<uint64_t>(1, g_out) * 4);
+    check(c, hipEventRecord(c->ev[28], s), "event");
+    check(c, launch_gather(s, kc, tiles, n_tiles, tile_off, keys, counts, gk_out, gc_out),
+          "gather");
+    check(c, hipEventRecord(c->ev[29], s), "event");
+    acc_keys.resize((n_out_total + g_out) * J.kw);
+    acc_counts.resize(n_out_total + g_out);
+    if (g_out) {
+      check(c, hipMemcpyAsync(acc_keys.data() + n_out_total * J.kw, gk_out, g_out * J.kw * 8,
+                              hipMemcpyDeviceToHost, s), "D2H");
+      check(c, hipMemcpyAsync(acc_counts.data() + n_out_total, gc_out, g_out * 4,
+                              hipMemcpyDeviceToHost, s), "D2H");
+    }
+    check(c, hipStreamSynchronize(s), "sync");
+    n_out_total += g_out;
+    for (int i = KMC_K_FINE_HIST; i < KMC_N_KERNELS; ++i)
+      acc_us[i] += 1e3 * ev_ms(c->ev[8 + 2 * i], c->ev[9 + 2 * i]);
+    acc_us[KMC_K_ASSEMBLE] += 1e3 * ev_ms(c->ev[28], c->ev[29]);
+    acc_phase[0] += 1e3 * ev_ms(gi == 0 ? c->ev[2] : c->ev[8 + 2 * KMC_K_FINE_HIST], c->ev[3]);
+    acc_phase[1] += 1e3 * ev_ms(c->ev[3], c->ev[4]);
+    acc_phase[2] += 1e3 * ev_ms(c->ev[4], c->ev[29]);
+  }
+  st.n_tiles = n_tiles_all;
+  st.n_big_tiles = big_tiles;
+  st.n_big_keys = big_keys;
+  st.n_big_out = big_out;
+  const uint64_t n_out = n_out_total;
   st.n_out = n_out;
-  st.n_distinct = h_distinct;
+  st.n_distinct = n_distinct;
   T->n = n_out;
-  uint64_t* out_k;
-  uint32_t* out_c;
+  // the table's keys and counts: the caller's buffers (allocation-free form),
+  // the caller's workspace, a pooled device block, or host memory
   if (c->user_keys) {
-    // the caller's buffers (allocation-free form)
     if (n_out > c->user_cap) {
       c->user_need = n_out;
       c->err = "the table has more entries than the output buffers hold";
@@ -658,7 +834,7 @@ void run_count(kmc_ctx* c, const kmc_reads* R, const kmc_params* P, kmc_table* T
     T->reserved = 1;
     out_k = T->keys;
     out_c = T->counts;
-  } else if (T->on_device) {
+  } else if (T->on_device || (grouped && (J.flags & KMC_FLAG_ASCENDING))) {
     // keys and counts in one pooled block
     const size_t kb = (std::max<uint64_t>(1, n_out * J.kw) * 8 + 255) & ~(size_t)255;
     void* blk = pool_take(c->device, kb + std::max<uint64_t>(1, n_out) * 4);
@@ -669,15 +845,33 @@ void run_count(kmc_ctx* c, const kmc_reads* R, const kmc_params* P, kmc_table* T
     T->keys = static_cast<uint64_t*>(blk);
     T->counts = reinterpret_cast<uint32_t*>(static_cast<uint8_t*>(blk) + kb);
     T->reserved = 2;
+    T->on_device = 1;
     out_k = T->keys;
     out_c = T->counts;
-  } else {
+  } else if (!grouped) {
     out_k = ensure<uint64_t>(c, B_OUTK, n_out * J.kw * 8);
     out_c = ensure<uint32_t>(c, B_OUTC, n_out * 4);
   }
-  check(c, hipEventRecord(c->ev[28], s), "event");
-  check(c, launch_gather(s, kc, tiles, n_tiles, tile_off, keys, counts, out_k, out_c), "gather");
-  if (J.flags & KMC_FLAG_ASCENDING) {
+  if (!grouped) {
+    // the last (only) group's tiles are still in place: gather them
+    check(c, hipEventRecord(c->ev[28], s), "event");
+    const uint64_t n_tiles = n_tiles_all;
+    check(c, launch_gather(s, kc, ensure<Tile>(c, B_TILES, n_tiles * sizeof(Tile)), n_tiles,
+                           ensure<uint64_t>(c, B_TILEOFF, (n_tiles + 1) * 8),
+                           ensure<uint64_t>(c, B_KEYS, n_kmers * J.kw * 8),
+                           ensure<uint32_t>(c, B_COUNTS, n_kmers * 4), out_k, out_c),
+          "gather");
+  } else if (out_k && n_out) {
+    // a grouped job's entries into the device table
+    check(c, hipEventRecord(c->ev[28], s), "event");
+    check(c, hipMemcpyAsync(out_k, acc_keys.data(), n_out * J.kw * 8, hipMemcpyHostToDevice, s),
+          "H2D table");
+    check(c, hipMemcpyAsync(out_c, acc_counts.data(), n_out * 4, hipMemcpyHostToDevice, s),
+          "H2D table");
+  } else {
+    check(c, hipEventRecord(c->ev[28], s), "event");
+  }
+  if ((J.flags & KMC_FLAG_ASCENDING) && out_k) {
     // ascending over the whole table: segments by top key bits into a
     // scratch copy, groups ordered in LDS back into the table
     std::free(T->bin_offsets);
@@ -700,25 +894,54 @@ void run_count(kmc_ctx* c, const kmc_reads* R, const kmc_params* P, kmc_table* T
   }
   check(c, hipEventRecord(c->ev[29], s), "event");
   check(c, hipEventRecord(c->ev[5], s), "event");
-  if (!T->on_device) {
-    T->keys = static_cast<uint64_t*>(std::malloc(std::max<uint64_t>(1, n_out * J.kw) * 8));
-    T->counts = static_cast<uint32_t*>(std::malloc(std::max<uint64_t>(1, n_out) * 4));
-    if (!T->keys || !T->counts) throw Fail{KMC_ERR_OUT_OF_MEMORY};
+  const bool want_host = !(J.flags & KMC_FLAG_DEVICE_TABLE) && !c->user_keys;
+  if (want_host && grouped && !(J.flags & KMC_FLAG_ASCENDING)) {
+    // a grouped job's host table: the entries collected in host memory
+    T->on_device = 0;
+    host_table(T, n_out, J.kw);
     if (n_out) {
-      check(c, hipMemcpyAsync(T->keys, out_k, n_out * J.kw * 8, hipMemcpyDeviceToHost, s), "D2H");
-      check(c, hipMemcpyAsync(T->counts, out_c, n_out * 4, hipMemcpyDeviceToHost, s), "D2H");
+      std::memcpy(T->keys, acc_keys.data(), n_out * J.kw * 8);
+      std::memcpy(T->counts, acc_counts.data(), n_out * 4);
     }
+  } else if (want_host) {
+    // a host table copied out of the device table (or the staging buffers)
+    uint64_t* dk = out_k;
+    uint32_t* dc = out_c;
+    void* pooled = T->reserved == 2 ? T->keys : nullptr;
+    T->on_device = 0;
+    T->reserved = 0;
+    T->keys = nullptr;
+    T->counts = nullptr;
+    try {
+      host_table(T, n_out, J.kw);
+    } catch (const Fail&) {
+      if (pooled) pool_give(pooled);
+      throw;
+    }
+    if (n_out) {
+      check(c, hipMemcpyAsync(T->keys, dk, n_out * J.kw * 8, hipMemcpyDeviceToHost, s), "D2H");
+      check(c, hipMemcpyAsync(T->counts, dc, n_out * 4, hipMemcpyDeviceToHost, s), "D2H");
+    }
+    check(c, hipStreamSynchronize(s), "sync");
+    if (pooled) pool_give(pooled);
   }
   check(c, hipStreamSynchronize(s), "sync");
   st.us_map = 1e3 * ev_ms(c->ev[0], c->ev[1]);
   st.us_split = 1e3 * ev_ms(c->ev[1], c->ev[2]);
-  st.us_expand = 1e3 * ev_ms(c->ev[2], c->ev[3]);
-  st.us_sort = 1e3 * ev_ms(c->ev[3], c->ev[4]);
-  st.us_assemble = 1e3 * ev_ms(c->ev[4], c->ev[5]);
   st.us_total = 1e3 * ev_ms(c->ev[0], c->ev[5]);
   for (int i = 0; i < KMC_N_KERNELS; ++i)
     st.us_kernel[i] = 1e3 * ev_ms(c->ev[8 + 2 * i], c->ev[9 + 2 * i]);
-  st.us_kernel[KMC_K_ASSEMBLE] += 1e3 * ev_ms(c->ev[28], c->ev[29]);
+  if (!grouped) {
+    st.us_expand = 1e3 * ev_ms(c->ev[2], c->ev[3]);
+    st.us_sort = 1e3 * ev_ms(c->ev[3], c->ev[4]);
+    st.us_assemble = 1e3 * ev_ms(c->ev[4], c->ev[5]);
+    st.us_kernel[KMC_K_ASSEMBLE] += 1e3 * ev_ms(c->ev[28], c->ev[29]);
+  } else {
+    for (int i = KMC_K_FINE_HIST; i < KMC_N_KERNELS; ++i) st.us_kernel[i] = acc_us[i];
+    st.us_expand = acc_phase[0];
+    st.us_sort = acc_phase[1];
+    st.us_assemble = acc_phase[2];
+  }
   // algorithmic bytes: input once, 2-bit payload of every super k-mer written
   // and read once (ceil(l/4) + 2 bytes each), keys written and read once,
   // output written once
@@ -875,6 +1098,7 @@ void kmc_ctx_destroy(kmc_ctx* c) {
     if (b.p) (void)hipFree(b.p);
   for (auto& b : c->hbuf)
     if (b.p) (void)hipHostFree(b.p);
+  if (c->spill.p) (void)hipHostFree(c->spill.p);
   for (auto& e : c->ev)
     if (e) (void)hipEventDestroy(e);
   if (c->stream) (void)hipStreamDestroy(c->stream);
@@ -882,6 +1106,12 @@ void kmc_ctx_destroy(kmc_ctx* c) {
 }
 
 const char* kmc_last_error(const kmc_ctx* c) { return c ? c->err.c_str() : ""; }
+
+kmc_status kmc_ctx_set_budget(kmc_ctx* c, uint64_t device_bytes) {
+  if (!c) return KMC_ERR_INVALID_ARG;
+  c->budget = device_bytes;
+  return KMC_OK;
+}
 
 const char* kmc_status_str(kmc_status st) {
   switch (st) {
@@ -903,6 +1133,7 @@ void** kmc::ctx_ext(kmc_ctx* c, void (*release)(void*)) {
   return &c->ext;
 }
 int kmc::ctx_device(const kmc_ctx* c) { return c->device; }
+hipStream_t kmc::ctx_stream(const kmc_ctx* c) { return c->stream; }
 void kmc::ctx_set_error(kmc_ctx* c, const char* msg) { c->err = msg ? msg : ""; }
 void kmc::ctx_release_buffers(kmc_ctx* c) {
   (void)hipSetDevice(c->device);
@@ -912,6 +1143,23 @@ void kmc::ctx_release_buffers(kmc_ctx* c) {
     b.p = nullptr;
     b.cap = 0;
   }
+  if (c->spill.p) (void)hipHostFree(c->spill.p);
+  c->spill.p = nullptr;
+  c->spill.cap = 0;
+}
+void kmc::ctx_set_budget(kmc_ctx* c, uint64_t bytes) { c->budget = bytes; }
+void* kmc::ctx_aux_buffer(kmc_ctx* c, int slot, size_t bytes) {
+  if (slot < 0 || slot >= kCtxAuxBuffers) return nullptr;
+  uint8_t* saved = c->ws_base;
+  c->ws_base = nullptr;  // always the context's own cached buffers
+  void* p = nullptr;
+  try {
+    p = ensure<uint8_t>(c, static_cast<BufId>(B_AUX0 + slot), bytes);
+  } catch (const Fail&) {
+    p = nullptr;
+  }
+  c->ws_base = saved;
+  return p;
 }
 
 extern "C" {
@@ -961,6 +1209,8 @@ void kmc_table_free(kmc_table* t) {
   } else if (t->on_device) {
     if (t->keys) (void)hipFree(t->keys);
     if (t->counts) (void)hipFree(t->counts);
+  } else if (t->reserved == 3) {
+    if (t->keys) pool_give(t->keys);  // pinned host block, back to the pool
   } else {
     std::free(t->keys);
     std::free(t->counts);

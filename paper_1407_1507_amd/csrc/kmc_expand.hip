@@ -290,12 +290,13 @@ k_plan_tiles(KeyCfg kc, const uint32_t* __restrict__ fine_hist, const uint64_t* 
 }
 
 // ---------------------------------------------------------- expand scatter
-// One workgroup per task (up to blockDim records of one bin, one per lane).
-// Two walks over each record's k-mers: the first counts keys per tile in LDS;
-// after one scan and one global reservation per (task, tile) the second walk
-// writes every key straight to its slot, tile slot = reserved start + rank
-// from an LDS counter.  A task's keys of one tile land in one contiguous
-// range.  No staging and no barrier inside the walks.
+// One workgroup per task (a run of records of one bin, staged a round of
+// blockDim records at a time, one per lane).  Two walks over each record's
+// k-mers: the first counts keys per tile in LDS; after one global
+// reservation per (task, tile) the second walk writes every key straight to
+// its slot, tile slot = reserved start + rank from an LDS counter.  A task's
+// keys of one tile land in one contiguous range.  No barrier inside the
+// walks.
 template <int KW>
 __global__ void __launch_bounds__(kExpandThreads)
 k_expand_scatter(KeyCfg kc, TaskMap tm,
@@ -316,39 +317,28 @@ k_expand_scatter(KeyCfg kc, TaskMap tm,
   const uint32_t task =
       KW == 2 ? xcd_task(blockIdx.x, (n_tasks + kXcds - 1) / kXcds) : blockIdx.x;
   if (task >= n_tasks) return;
-  const ExpandTask tk = tm.get(task);  // n_rec <= kExpandThreads: one round
+  const ExpandTask tk = tm.get(task);
   const uint16_t* gt = tile_of_fine + ((uint64_t)tk.bin << kc.fine_bits);
   for (uint32_t i = threadIdx.x; i < nf; i += blockDim.x) tof[i] = gt[i];
   const uint64_t tb = tile_base[tk.bin];
   const uint32_t nt = (uint32_t)(tile_base[tk.bin + 1] - tb);  // <= mt
   for (uint32_t i = threadIdx.x; i < nt; i += blockDim.x) cnt[i] = 0;
   const K kmask = key_mask<K>(kc.k);
-  stage_round<KW>(records + tk.rec_begin * (2 * KW), tk.n_rec, L);
-  const bool active = threadIdx.x < tk.n_rec;
-  const uint64_t* my = L.w + (uint32_t)L.perm[threadIdx.x] * (2 * KW);
-
-  // walk 1: keys per tile
-  if (active) {
+  const bool canon = kc.canonical != 0;
+  // walk 1 over the slot's staged record: keys per tile
+  auto count_walk = [&](const uint64_t* my) {
     Rec<KW> rec;
-    rec.load(my, kc.k, kc.canonical != 0);
+    rec.load(my, kc.k, canon);
     for (uint32_t i = 0;; ++i) {
       atomicAdd(&cnt[tof[top_bits(rec.key(), kc.k, kc.fine_bits)]], 1u);
       if (i + 1 >= rec.n) break;
       rec.step(kc.k, kmask);
     }
-  }
-  __syncthreads();
-  // reserve each tile's range; cnt then becomes the running slot
-  for (uint32_t i = threadIdx.x; i < nt; i += blockDim.x) {
-    const uint32_t c = cnt[i];
-    if (c) delta[i] = atomicAdd(&tile_cursor[tb + i], (unsigned long long)c);
-    cnt[i] = 0;
-  }
-  __syncthreads();
+  };
   // walk 2: the same keys again, each written to its tile
-  if (active) {
+  auto write_walk = [&](const uint64_t* my) {
     Rec<KW> rec;
-    rec.load(my, kc.k, kc.canonical != 0);
+    rec.load(my, kc.k, canon);
     for (uint32_t i = 0;; ++i) {
       const K key = rec.key();
       const uint32_t t = tof[top_bits(key, kc.k, kc.fine_bits)];
@@ -362,6 +352,42 @@ k_expand_scatter(KeyCfg kc, TaskMap tm,
       if (i + 1 >= rec.n) break;
       rec.step(kc.k, kmask);
     }
+  };
+  // reserve each tile's range; cnt then becomes the running slot
+  auto reserve = [&]() {
+    for (uint32_t i = threadIdx.x; i < nt; i += blockDim.x) {
+      const uint32_t c = cnt[i];
+      if (c) delta[i] = atomicAdd(&tile_cursor[tb + i], (unsigned long long)c);
+      cnt[i] = 0;
+    }
+  };
+  const uint64_t* base = records + tk.rec_begin * (2 * KW);
+  if (tk.n_rec <= kExpandThreads) {
+    // one round: staged once, walked twice
+    stage_round<KW>(base, tk.n_rec, L);
+    const uint64_t* my = L.w + (uint32_t)L.perm[threadIdx.x] * (2 * KW);
+    if (threadIdx.x < tk.n_rec) count_walk(my);
+    __syncthreads();
+    reserve();
+    __syncthreads();
+    if (threadIdx.x < tk.n_rec) write_walk(my);
+    return;
+  }
+  // several rounds (longer runs of keys per tile): every round staged for
+  // the counting walk, one reservation per tile, then staged again for the
+  // writing walk
+  for (uint32_t r0 = 0; r0 < tk.n_rec; r0 += kExpandThreads) {
+    const uint32_t nr = min(tk.n_rec - r0, (uint32_t)kExpandThreads);
+    stage_round<KW>(base + (uint64_t)r0 * (2 * KW), nr, L);
+    if (threadIdx.x < nr) count_walk(L.w + (uint32_t)L.perm[threadIdx.x] * (2 * KW));
+  }
+  __syncthreads();
+  reserve();
+  __syncthreads();
+  for (uint32_t r0 = 0; r0 < tk.n_rec; r0 += kExpandThreads) {
+    const uint32_t nr = min(tk.n_rec - r0, (uint32_t)kExpandThreads);
+    stage_round<KW>(base + (uint64_t)r0 * (2 * KW), nr, L);
+    if (threadIdx.x < nr) write_walk(L.w + (uint32_t)L.perm[threadIdx.x] * (2 * KW));
   }
 }
 

@@ -11,6 +11,14 @@ namespace kmc {
 
 // Sizes of the work units.
 constexpr int kExpandThreads = 256;      // threads of the expansion kernels: records per round
+// Records per expansion task, by key width (a multiple of kExpandThreads):
+// more records per task give longer runs of keys per (task, tile), so fewer
+// partially written lines.
+constexpr uint32_t kExpandTask1 = 256;
+constexpr uint32_t kExpandTask2 = 256;
+inline uint32_t expand_task_records(uint32_t key_words) {
+  return key_words == 1 ? kExpandTask1 : kExpandTask2;
+}
 constexpr int kSortThreads = 256;        // threads of a tile-sort workgroup
 constexpr int kTileCap1 = 4096;          // keys of one LDS tile (1-word keys)
 constexpr int kTileCap2 = 2048;          // same, 2-word keys
@@ -141,7 +149,7 @@ hipError_t launch_plan_tiles(hipStream_t s, const KeyCfg& kc, const uint32_t* fi
                              unsigned long long* tile_cursor);
 
 // Expand every record into canonical keys and scatter them into their tiles.
-// Tasks hold at most kExpandThreads records.
+// Tasks hold at most expand_task_records(key_words) records.
 hipError_t launch_expand_scatter(hipStream_t s, const KeyCfg& kc, const TaskMap& tm,
                                  uint32_t n_tasks, const uint64_t* records,
                                  const uint16_t* tile_of_fine, const uint64_t* tile_base,
@@ -222,9 +230,16 @@ namespace kmc {
 // (registered on first use) when the context is destroyed.
 void** ctx_ext(kmc_ctx* c, void (*release)(void*));
 int ctx_device(const kmc_ctx* c);
+hipStream_t ctx_stream(const kmc_ctx* c);
 void ctx_set_error(kmc_ctx* c, const char* msg);
 // Free the context's cached device buffers (after a one-off large job).
 void ctx_release_buffers(kmc_ctx* c);
+// Device buffer `slot` of the context's cache (grown to `bytes` as needed and
+// kept for later calls; freed with the context), or nullptr on failure.
+constexpr int kCtxAuxBuffers = 12;
+void* ctx_aux_buffer(kmc_ctx* c, int slot, size_t bytes);
+// Set the context's memory budget (as kmc_ctx_set_budget).
+void ctx_set_budget(kmc_ctx* c, uint64_t bytes);
 // kmc_count_ws; with own_table a device table is allocated apart from the
 // workspace, so it outlives the workspace's reuse.
 kmc_status count_ws_impl(kmc_ctx* c, const kmc_reads* reads, const kmc_params* params,

@@ -56,7 +56,7 @@ struct SrvJob {
   uint64_t ticket = 0;
   kmc_job job{};
   size_t footprint = 0;
-  bool oversize = false;  // larger than the whole budget: runs alone
+  bool oversize = false;  // larger than the whole budget: runs alone, bounded by it
   uint32_t bypassed = 0;
   int state = 0;  // 0 queued, 1 running, 2 done
   kmc_status st = KMC_OK;
@@ -156,10 +156,23 @@ void serve(kmc_server* s, kmc_ctx* w) {
     kmc_table* t = nullptr;
     kmc_status st;
     if (j->oversize) {
-      // sized by what the job really needs, not by the upper bound, then
-      // handed back so the arena's neighbours get the memory again
+      // alone, inside the budget: the arena is handed back for the job's
+      // duration (no other job runs), and the job's own buffers are bounded
+      // by the budget (bin groups, records spilled to pinned host memory);
+      // then the arena is reserved again
+      (void)hipSetDevice(s->device);
+      if (s->arena) (void)hipFree(s->arena);
+      s->arena = nullptr;
+      kmc::ctx_set_budget(w, s->budget);
       st = kmc_count_ex(w, &j->job.reads, &j->job.params, nullptr, &t);
+      kmc::ctx_set_budget(w, 0);
       kmc::ctx_release_buffers(w);
+      if (hipMalloc(&s->arena, s->budget) != hipSuccess) {
+        (void)hipGetLastError();
+        s->arena = nullptr;  // later jobs fail with KMC_ERR_OUT_OF_MEMORY
+      }
+    } else if (!s->arena) {
+      st = KMC_ERR_OUT_OF_MEMORY;
     } else {
       st = kmc::count_ws_impl(w, &j->job.reads, &j->job.params, nullptr, s->arena + j->ws_off,
                               j->footprint, true, &t);

@@ -130,10 +130,19 @@ __device__ __forceinline__ void scan_read(const uint8_t* __restrict__ seq, uint6
   if (cur_n) sink.superkmer(cur_start, cur_n, cur_sig, cur_bin, curF, tail);
 }
 
-// Lane-private LDS slices for the window buffer: stride w + 1 elements.
+// Lane-private LDS slices for the window buffer.  The slices of a wave's 64
+// lanes are read and written at the same offset j together, so their stride
+// decides the bank conflicts: an odd number of 32-bit words (32-bit values),
+// or 2 mod 4 16-bit values (an odd number of words), puts the 64 lanes in 64
+// different banks.  (A stride of w + 1 = 48 words at w = 47 put all 64 lanes
+// in four banks.)
+__host__ __device__ __forceinline__ uint32_t vh_stride(uint32_t w, uint32_t vt_bytes) {
+  const uint32_t s = w + 1;
+  return vt_bytes == 4 ? (s | 1u) : s + ((2u - s) & 3u);
+}
 template <class VT>
 __device__ __forceinline__ VT* lane_vh(void* lds, uint32_t w) {
-  return reinterpret_cast<VT*>(lds) + threadIdx.x * (w + 1);
+  return reinterpret_cast<VT*>(lds) + threadIdx.x * vh_stride(w, sizeof(VT));
 }
 
 // ------------------------------------------------------------ sample hist
@@ -176,7 +185,8 @@ k_sig_hist(const uint8_t* __restrict__ seq, const uint64_t* __restrict__ offsets
   const uint64_t r = ((uint64_t)blockIdx.x * blockDim.x + threadIdx.x) * stride;
   const uint32_t n_sig = C.sent + 1;
   const uint32_t nl = min(n_sig, kLdsSig);
-  const size_t vb = ((size_t)blockDim.x * (C.w + 1) * sizeof(VT) + 15) & ~(size_t)15;
+  const size_t vb =
+      ((size_t)blockDim.x * vh_stride(C.w, sizeof(VT)) * sizeof(VT) + 15) & ~(size_t)15;
   uint32_t* lk = reinterpret_cast<uint32_t*>(lds8 + vb);  // after the window buffers
   uint32_t* lr = lk + nl;
   for (uint32_t i = threadIdx.x; i < 2 * nl; i += blockDim.x) lk[i] = 0;
@@ -462,7 +472,8 @@ constexpr uint64_t kLongRead = 2048;
 // Window buffers hold u16 when every stored value (4^p + 1 at most) fits.
 static bool small_vt(const ScanCfg& c) { return c.sent + 1u <= 0xFFFFu; }
 static size_t vh_bytes(const ScanCfg& c, uint32_t lanes) {
-  const size_t b = (size_t)lanes * (c.w + 1) * (small_vt(c) ? 2 : 4);
+  const uint32_t vt = small_vt(c) ? 2 : 4;
+  const size_t b = (size_t)lanes * vh_stride(c.w, vt) * vt;
   return (b + 15) & ~(size_t)15;
 }
 

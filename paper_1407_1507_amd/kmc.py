@@ -31,11 +31,13 @@ FLAG_ASCENDING = 0x4
 FLAG_NON_CANONICAL = 0x8
 FLAG_TEST_NARROW_FINGERPRINT = 0x100  # test only: drives the exact path of 128-bit tiles
 
-EXPORTS = ["kmc_ctx_create", "kmc_ctx_destroy", "kmc_last_error", "kmc_count", "kmc_count_ex",
+EXPORTS = ["kmc_ctx_create", "kmc_ctx_destroy", "kmc_last_error", "kmc_ctx_set_budget", "kmc_count", "kmc_count_ex",
            "kmc_table_free", "kmc_status_str", "kmc_workspace_size", "kmc_count_ws",
            "kmc_batch_count", "kmc_server_start", "kmc_server_submit", "kmc_server_poll",
            "kmc_server_stats_get", "kmc_server_stop", "kmc_debug_signatures",
-           "kmc_count_static"]
+           "kmc_count_static", "kmc_db_build", "kmc_db_info_get", "kmc_db_write", "kmc_db_open",
+           "kmc_db_query", "kmc_db_decode", "kmc_db_free", "kmc_parse", "kmc_parsed_free"]
+FORMAT_AUTO, FORMAT_FASTQ, FORMAT_FASTA = 0, 1, 2
 STATIC_SCRATCH_BYTES = 256 << 20  # KMC_STATIC_SCRATCH_BYTES
 
 
@@ -61,7 +63,7 @@ class Stats(ctypes.Structure):
     _fields_ = [(n, ctypes.c_uint64) for n in (
         "n_reads", "n_bases", "n_kmers", "n_superkmers", "n_distinct", "n_out", "sample_kmers",
         "max_bin_kmers", "n_tiles", "n_big_tiles", "bytes_alg", "split_passes", "n_big_keys",
-        "n_big_out")] + [
+        "n_big_out", "n_groups", "records_spilled")] + [
         (n, ctypes.c_double) for n in (
             "us_map", "us_split", "us_expand", "us_sort", "us_assemble", "us_total")] + [
         ("us_kernel", ctypes.c_double * 8), ("us_queue", ctypes.c_double),
@@ -82,6 +84,12 @@ class Table(ctypes.Structure):
                 ("sig_to_bin", ctypes.POINTER(ctypes.c_uint32)),
                 ("on_device", ctypes.c_int32), ("reserved", ctypes.c_int32),
                 ("stats", Stats)]
+
+
+class DbInfo(ctypes.Structure):
+    _fields_ = [(n, ctypes.c_uint32) for n in (
+        "kmer_length", "mode", "counter_size", "lut_prefix_length", "signature_length",
+        "min_count", "max_count", "flags")] + [("total_kmers", ctypes.c_uint64)]
 
 
 class Job(ctypes.Structure):
@@ -125,6 +133,8 @@ def lib() -> ctypes.CDLL:
         L.kmc_ctx_create.restype = ctypes.c_int
         L.kmc_ctx_destroy.argtypes = [vp]
         L.kmc_ctx_destroy.restype = None
+        L.kmc_ctx_set_budget.argtypes = [vp, ctypes.c_uint64]
+        L.kmc_ctx_set_budget.restype = ctypes.c_int
         L.kmc_last_error.argtypes = [vp]
         L.kmc_last_error.restype = ctypes.c_char_p
         L.kmc_count.argtypes = [ctypes.POINTER(Reads), ctypes.c_uint32, ctypes.c_uint32,
@@ -151,6 +161,27 @@ def lib() -> ctypes.CDLL:
                                        vp, vp, ctypes.c_uint64, ctypes.POINTER(ctypes.c_uint64),
                                        vp, ctypes.POINTER(Stats)]
         L.kmc_count_static.restype = ctypes.c_int
+        L.kmc_db_build.argtypes = [vp, ctypes.POINTER(Table), ctypes.POINTER(Params),
+                                   ctypes.c_uint32, ctypes.c_uint32, ctypes.POINTER(vp)]
+        L.kmc_db_build.restype = ctypes.c_int
+        L.kmc_db_info_get.argtypes = [vp, ctypes.POINTER(DbInfo)]
+        L.kmc_db_info_get.restype = ctypes.c_int
+        L.kmc_db_write.argtypes = [vp, ctypes.c_char_p]
+        L.kmc_db_write.restype = ctypes.c_int
+        L.kmc_db_open.argtypes = [vp, ctypes.c_char_p, ctypes.POINTER(vp)]
+        L.kmc_db_open.restype = ctypes.c_int
+        L.kmc_db_query.argtypes = [vp, vp, ctypes.c_uint64, ctypes.c_uint32, ctypes.c_uint32,
+                                   vp, vp]
+        L.kmc_db_query.restype = ctypes.c_int
+        L.kmc_db_decode.argtypes = [vp, vp, vp, vp]
+        L.kmc_db_decode.restype = ctypes.c_int
+        L.kmc_db_free.argtypes = [vp]
+        L.kmc_db_free.restype = None
+        L.kmc_parse.argtypes = [vp, vp, ctypes.c_uint64, ctypes.c_int32, ctypes.c_uint32,
+                                ctypes.POINTER(Reads), ctypes.POINTER(vp)]
+        L.kmc_parse.restype = ctypes.c_int
+        L.kmc_parsed_free.argtypes = [vp]
+        L.kmc_parsed_free.restype = None
         L.kmc_batch_count.argtypes = [vp, ctypes.POINTER(Job), ctypes.c_uint32,
                                       ctypes.POINTER(ctypes.POINTER(Table))]
         L.kmc_batch_count.restype = ctypes.c_int
@@ -175,6 +206,8 @@ def _is_torch(x) -> bool:
 
 def make_reads(seq, offsets):
     """Reads struct (plus the objects that must stay alive while it is used)."""
+    if isinstance(seq, Parsed):
+        return seq.reads, (seq,)
     if _is_torch(seq):
         if not (seq.is_cuda and offsets.is_cuda):
             raise ValueError("torch inputs must both live on the GPU")
@@ -196,7 +229,7 @@ class Result:
     """A counted table.  Host tables are copied into numpy arrays; device
     tables keep the library's buffers until free() (or garbage collection)."""
 
-    def __init__(self, ptr):
+    def __init__(self, ptr, keep: bool = False):
         t = ptr.contents
         self.k = t.k
         self.key_words = t.key_words
@@ -223,7 +256,8 @@ class Result:
                 keys = np.zeros(0, dtype=np.uint64)
                 self.counts = np.zeros(0, dtype=np.uint32)
             self.keys = keys.reshape(n, 2) if kw == 2 else keys
-            self.free()
+            if not keep:  # keep: the library's table stays until free() (kmc_db_build reads it)
+                self.free()
 
     def free(self):
         if self._ptr is not None:
@@ -244,6 +278,12 @@ class Context:
         if st != KMC_OK:
             raise KmcError(st, f"kmc_ctx_create: {lib().kmc_status_str(st).decode()}")
 
+    def set_budget(self, device_bytes: int):
+        """kmc_ctx_set_budget: device bytes a job's buffers may take (0 = no bound)."""
+        st = lib().kmc_ctx_set_budget(self._h, device_bytes)
+        if st != KMC_OK:
+            raise KmcError(st, "kmc_ctx_set_budget")
+
     def close(self):
         if self._h:
             lib().kmc_ctx_destroy(self._h)
@@ -261,7 +301,7 @@ class Context:
 
     def count(self, seq, offsets, k: int, p: int, n_bins: int, cutoff_min: int = 2,
               cutoff_max: int = 10**9, flags: int = 0, stream=None,
-              counter_max: int = 0) -> Result:
+              counter_max: int = 0, keep_table: bool = False) -> Result:
         reads, keep = make_reads(seq, offsets)
         params = make_params(k, p, n_bins, cutoff_min, cutoff_max, flags, counter_max)
         out = ctypes.POINTER(Table)()
@@ -273,7 +313,9 @@ class Context:
         del keep
         if st != KMC_OK:
             self._raise(st, "kmc_count_ex")
-        return Result(out)
+        res = Result(out, keep=keep_table)
+        res.params = params
+        return res
 
     def workspace_size(self, seq, offsets, k: int, p: int, n_bins: int, cutoff_min: int = 2,
                        cutoff_max: int = 10**9, flags: int = 0) -> int:
@@ -359,6 +401,123 @@ class Context:
         if st != KMC_OK:
             self._raise(st, "kmc_debug_signatures")
         return sig[:nb], start[:nb]
+
+
+class Parsed:
+    """Reads parsed on the device from FASTQ / FASTA text (kmc_parse); pass it
+    as `seq` (offsets None) to Context.count."""
+
+    def __init__(self, ctx: "Context", text, fmt: int = FORMAT_AUTO):
+        self._h = ctypes.c_void_p()
+        self.reads = Reads()
+        if _is_torch(text):
+            ptr, n, on_dev = text.data_ptr(), text.numel(), 1
+            keep = text
+        else:
+            keep = np.frombuffer(bytes(text), dtype=np.uint8) if not isinstance(
+                text, np.ndarray) else np.ascontiguousarray(text, dtype=np.uint8)
+            ptr, n, on_dev = (keep.ctypes.data if keep.size else None), keep.size, 0
+        st = lib().kmc_parse(ctx._h, ptr, n, on_dev, fmt, ctypes.byref(self.reads),
+                             ctypes.byref(self._h))
+        del keep
+        if st != KMC_OK:
+            ctx._raise(st, "kmc_parse")
+        self.n_reads = self.reads.n_reads
+        self.n_bases = self.reads.n_bases
+
+    def to_host(self):
+        """(seq, offsets) copied to numpy arrays."""
+        hip = ctypes.CDLL("libamdhip64.so")
+        seq = np.zeros(self.n_bases, dtype=np.uint8)
+        off = np.zeros(self.n_reads + 1, dtype=np.uint64)
+        if self.n_bases:
+            assert hip.hipMemcpy(ctypes.c_void_p(seq.ctypes.data), ctypes.c_void_p(self.reads.seq),
+                                 ctypes.c_size_t(seq.nbytes), 2) == 0
+        assert hip.hipMemcpy(ctypes.c_void_p(off.ctypes.data), ctypes.c_void_p(self.reads.offsets),
+                             ctypes.c_size_t(off.nbytes), 2) == 0
+        return seq, off
+
+    def free(self):
+        if self._h:
+            lib().kmc_parsed_free(self._h)
+            self._h = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.free()
+        except Exception:
+            pass
+
+
+class Db:
+    """A KMC 2 database in device memory (kmc_db_*): built from a counted
+    table (Result of Context.count with keep_table=True or a device table),
+    or opened from .kmc_pre / .kmc_suf files."""
+
+    def __init__(self, handle: ctypes.c_void_p):
+        self._h = handle
+        info = DbInfo()
+        st = lib().kmc_db_info_get(self._h, ctypes.byref(info))
+        if st != KMC_OK:
+            raise KmcError(st, "kmc_db_info_get")
+        self.info = {n: getattr(info, n) for n, _ in info._fields_}
+        self.key_words = 1 if info.kmer_length <= 32 else 2
+
+    @classmethod
+    def build(cls, ctx: "Context", table: "Result", lut_prefix_len: int, counter_size: int = 4):
+        if table._ptr is None:
+            raise ValueError("the table was freed; count with keep_table=True")
+        h = ctypes.c_void_p()
+        st = lib().kmc_db_build(ctx._h, table._ptr, ctypes.byref(table.params), lut_prefix_len,
+                                counter_size, ctypes.byref(h))
+        if st != KMC_OK:
+            ctx._raise(st, "kmc_db_build")
+        return cls(h)
+
+    @classmethod
+    def open(cls, ctx: "Context", path_prefix: str):
+        h = ctypes.c_void_p()
+        st = lib().kmc_db_open(ctx._h, path_prefix.encode(), ctypes.byref(h))
+        if st != KMC_OK:
+            ctx._raise(st, "kmc_db_open")
+        return cls(h)
+
+    def write(self, path_prefix: str):
+        st = lib().kmc_db_write(self._h, path_prefix.encode())
+        if st != KMC_OK:
+            raise KmcError(st, f"kmc_db_write: {lib().kmc_status_str(st).decode()}")
+
+    def query(self, kmers, counts_out, min_count: int = 0, max_count: int = 2**32 - 1,
+              stream=None):
+        """kmers: torch uint64/int64 tensor on the device (n * key_words);
+        counts_out: torch int32 tensor of n entries on the device."""
+        n = kmers.numel() // self.key_words
+        sp = None
+        if stream is not None:
+            sp = stream if isinstance(stream, int) else stream.cuda_stream
+        st = lib().kmc_db_query(self._h, kmers.data_ptr(), n, min_count, max_count,
+                                counts_out.data_ptr(), sp)
+        if st != KMC_OK:
+            raise KmcError(st, f"kmc_db_query: {lib().kmc_status_str(st).decode()}")
+
+    def decode(self, keys_out, counts_out, stream=None):
+        sp = None
+        if stream is not None:
+            sp = stream if isinstance(stream, int) else stream.cuda_stream
+        st = lib().kmc_db_decode(self._h, keys_out.data_ptr(), counts_out.data_ptr(), sp)
+        if st != KMC_OK:
+            raise KmcError(st, f"kmc_db_decode: {lib().kmc_status_str(st).decode()}")
+
+    def free(self):
+        if self._h:
+            lib().kmc_db_free(self._h)
+            self._h = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.free()
+        except Exception:
+            pass
 
 
 def make_params(k: int, p: int, n_bins: int, cutoff_min: int = 2, cutoff_max: int = 10**9,
