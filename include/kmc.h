@@ -209,6 +209,27 @@ const char* kmc_last_error(const kmc_ctx* ctx);
  * (their workspace is the bound). */
 kmc_status kmc_ctx_set_budget(kmc_ctx* ctx, uint64_t device_bytes);
 
+/* Knobs of the counting path.  None changes the table (entries, counts,
+ * bins and order); they trade work between kernels:
+ *   tile_fill       sort tiles are packed up to tile_fill quarters of the
+ *                   LDS tile (2 or 3; 0 = 3);
+ *   fine_bits_bias  added to the number of key bits (fine ranges per bin)
+ *                   the plan picks for the first digit, -2..2 (then clamped
+ *                   to 1..12);
+ *   expand_task     super k-mer records per expansion task: 256, 512 or
+ *                   1024 (0 = the default for the key width).
+ * Jobs counted in a caller's workspace (kmc_count_ws, kmc_count_static, the
+ * served form) use the defaults. */
+typedef struct kmc_knobs {
+  uint32_t tile_fill;
+  int32_t fine_bits_bias;
+  uint32_t expand_task;
+} kmc_knobs;
+
+/* Knobs for every later job of ctx (NULL: back to the defaults, or to the
+ * knobs kmc_autotune chose).  KMC_ERR_INVALID_ARG for a value out of range. */
+kmc_status kmc_ctx_set_knobs(kmc_ctx* ctx, const kmc_knobs* knobs);
+
 /* Count the canonical k-mers of `reads` (see the header comment).
  * Uses a context on device 0 owned by the calling host thread.
  * Validation (KMC_ERR_INVALID_ARG): see kmc_params; reads != NULL, out !=
@@ -258,6 +279,32 @@ kmc_status kmc_count_ws(kmc_ctx* ctx, const kmc_reads* reads, const kmc_params* 
  * kmc_count_ex returns for that job alone.  On any failure every outs[i] is
  * NULL, nothing is leaked, and the first failing job's status is returned. */
 kmc_status kmc_batch_count(kmc_ctx* ctx, const kmc_job* jobs, uint32_t n_jobs, kmc_table** outs);
+
+/* Autotuner.  For each class of the given jobs (key width, and the power of
+ * two of its input bases) the largest job of the class is counted alone with
+ * every candidate knob set (kmc_knobs: tile packing 2/4 or 3/4, first-digit
+ * bits -1..+1, 256 / 512 / 1024 records per expansion task; twelve sets),
+ * and the fastest device time is kept as the class's knobs for later jobs of
+ * ctx (kmc_count_ex and kmc_batch_count; a kmc_ctx_set_knobs override
+ * wins).  Then the classes' samples run as one batch with 2, 4 and 8 worker
+ * streams, and the fastest count becomes ctx's batch pool size.  No knob
+ * changes a table.  report may be NULL. */
+#define KMC_TUNE_MAX_CLASSES 32
+typedef struct kmc_tune_class {
+  uint32_t key_words;
+  uint32_t reserved;
+  uint64_t sample_bases;
+  kmc_knobs knobs;
+  uint32_t pad;
+  double us;           /* device time of the sample with the chosen knobs */
+} kmc_tune_class;
+typedef struct kmc_tune_report {
+  uint32_t n_classes;
+  uint32_t batch_workers;
+  kmc_tune_class classes[KMC_TUNE_MAX_CLASSES];
+} kmc_tune_report;
+kmc_status kmc_autotune(kmc_ctx* ctx, const kmc_job* jobs, uint32_t n_jobs,
+                        kmc_tune_report* report);
 
 /* Served form: jobs are submitted while others run; a job is admitted when
  * its footprint (kmc_workspace_size) fits the HBM budget next to the jobs

@@ -7,6 +7,7 @@
 #include <cstdio>
 #include <cstdlib>
 #include <cstring>
+#include <map>
 #include <mutex>
 #include <new>
 #include <queue>
@@ -79,6 +80,12 @@ struct kmc_ctx {
   // memory budget (kmc_ctx_set_budget): device bytes a job's buffers may
   // take, 0 = unbounded; records beyond it spill to pinned host memory
   uint64_t budget = 0;
+  // knobs of the counting path (never change the table): an override for
+  // every job, else the tuned knobs of the job's class (kmc_autotune)
+  bool has_knobs = false;
+  kmc_knobs knobs{};
+  std::map<uint32_t, kmc_knobs> tuned;
+  uint32_t batch_workers = 0;  // 0 = the default pool size
   DevBuf spill;            // pinned host records (device-accessible)
   bool pageable_host = false;
   std::vector<uint8_t> hvec[H_COUNT_];
@@ -424,6 +431,23 @@ float ev_ms(hipEvent_t a, hipEvent_t b) {
   return ms;
 }
 
+// The class of a job for tuned knobs: key width and log2 of its bases.
+uint32_t job_class(uint32_t kw, uint64_t n_bases) {
+  uint32_t l = 0;
+  while (l < 63 && (2ull << l) <= n_bases) ++l;
+  return (kw - 1) * 64 + l;
+}
+
+// The knobs a job runs with (a workspace job always takes the defaults,
+// which its workspace bounds assume).
+kmc_knobs job_knobs(const kmc_ctx* c, uint32_t kw, uint64_t n_bases) {
+  kmc_knobs k{0, 0, 0};
+  if (c->ws_base) return k;
+  if (c->has_knobs) return c->knobs;
+  auto it = c->tuned.find(job_class(kw, n_bases));
+  return it == c->tuned.end() ? k : it->second;
+}
+
 void run_count(kmc_ctx* c, const kmc_reads* R, const kmc_params* P, kmc_table* T) {
   Job J;
   J.k = P->k;
@@ -576,7 +600,10 @@ void run_count(kmc_ctx* c, const kmc_reads* R, const kmc_params* P, kmc_table* T
   kc.k = J.k;
   kc.key_words = J.kw;
   kc.tile_cap = J.kw == 1 ? kTileCap1 : kTileCap2;
-  kc.tile_limit = 3 * kc.tile_cap / 4;  // the largest tile the tile kernels count
+  const kmc_knobs kn = job_knobs(c, J.kw, J.n_bases);
+  // the largest tile the tile kernels count is 3/4 of the table; knobs may
+  // pack tiles to 2/4
+  kc.tile_limit = (kn.tile_fill == 2 ? 2u : 3u) * kc.tile_cap / 4;
   kc.cutoff_min = J.ci;
   kc.cutoff_max = J.cx;
   kc.fp_bits = (J.flags & KMC_FLAG_TEST_NARROW_FINGERPRINT) ? 2u : 47u;
@@ -584,6 +611,7 @@ void run_count(kmc_ctx* c, const kmc_reads* R, const kmc_params* P, kmc_table* T
   kc.counter_max = J.cmax;
   // fine ranges of about tile_cap / 8 keys in the largest bin
   uint32_t fb = ilog2_ceil(max_bin * 8 / kc.tile_cap + 1);
+  fb = (uint32_t)std::max<int32_t>(1, (int32_t)fb + std::max(-2, std::min(2, kn.fine_bits_bias)));
   fb = std::max<uint32_t>(1, std::min<uint32_t>({fb, (uint32_t)kMaxFineBits, 2 * J.k}));
   kc.fine_bits = fb;
 
@@ -677,7 +705,7 @@ void run_count(kmc_ctx* c, const kmc_reads* R, const kmc_params* P, kmc_table* T
     // one record per lane; only per-bin task offsets go to the device, which
     // lists every task's bin itself
     const uint64_t hrec = std::min<uint64_t>(65536, std::max<uint64_t>(1024, 8ull << fb));
-    const uint64_t eper = expand_task_records(J.kw);
+    const uint64_t eper = kn.expand_task ? kn.expand_task : expand_task_records(J.kw);
     htask_pre[0] = etask_pre[0] = 0;
     for (uint32_t i = 0; i < nbg; ++i) {
       const uint64_t rc = rec_cnt[b0 + i];
@@ -1113,6 +1141,22 @@ kmc_status kmc_ctx_set_budget(kmc_ctx* c, uint64_t device_bytes) {
   return KMC_OK;
 }
 
+kmc_status kmc_ctx_set_knobs(kmc_ctx* c, const kmc_knobs* knobs) {
+  if (!c) return KMC_ERR_INVALID_ARG;
+  if (!knobs) {
+    c->has_knobs = false;
+    return KMC_OK;
+  }
+  if ((knobs->tile_fill != 0 && knobs->tile_fill != 2 && knobs->tile_fill != 3) ||
+      knobs->fine_bits_bias < -2 || knobs->fine_bits_bias > 2 ||
+      (knobs->expand_task != 0 && knobs->expand_task != 256 && knobs->expand_task != 512 &&
+       knobs->expand_task != 1024))
+    return KMC_ERR_INVALID_ARG;
+  c->knobs = *knobs;
+  c->has_knobs = true;
+  return KMC_OK;
+}
+
 const char* kmc_status_str(kmc_status st) {
   switch (st) {
     case KMC_OK: return "ok";
@@ -1148,6 +1192,26 @@ void kmc::ctx_release_buffers(kmc_ctx* c) {
   c->spill.cap = 0;
 }
 void kmc::ctx_set_budget(kmc_ctx* c, uint64_t bytes) { c->budget = bytes; }
+void kmc::ctx_copy_tuning(kmc_ctx* dst, const kmc_ctx* src) {
+  dst->has_knobs = src->has_knobs;
+  dst->knobs = src->knobs;
+  dst->tuned = src->tuned;
+}
+void kmc::ctx_set_tuned(kmc_ctx* c, uint32_t key_words, uint64_t n_bases, const kmc_knobs& k) {
+  c->tuned[job_class(key_words, n_bases)] = k;
+}
+uint32_t kmc::ctx_batch_workers(const kmc_ctx* c) { return c->batch_workers; }
+void kmc::ctx_set_batch_workers(kmc_ctx* c, uint32_t n) { c->batch_workers = n; }
+bool kmc::ctx_override_knobs(kmc_ctx* c, const kmc_knobs* k) {
+  const bool had = c->has_knobs;
+  if (k) {
+    c->knobs = *k;
+    c->has_knobs = true;
+  } else {
+    c->has_knobs = false;
+  }
+  return had;
+}
 void* kmc::ctx_aux_buffer(kmc_ctx* c, int slot, size_t bytes) {
   if (slot < 0 || slot >= kCtxAuxBuffers) return nullptr;
   uint8_t* saved = c->ws_base;

@@ -240,6 +240,14 @@ constexpr int kCtxAuxBuffers = 12;
 void* ctx_aux_buffer(kmc_ctx* c, int slot, size_t bytes);
 // Set the context's memory budget (as kmc_ctx_set_budget).
 void ctx_set_budget(kmc_ctx* c, uint64_t bytes);
+// Knobs: copy src's override and tuned knobs into dst; tuned knobs of the
+// class of (key_words, n_bases); the batch pool's worker count (0 = default);
+// override (k non-null) or clear it, returning whether one was set.
+void ctx_copy_tuning(kmc_ctx* dst, const kmc_ctx* src);
+void ctx_set_tuned(kmc_ctx* c, uint32_t key_words, uint64_t n_bases, const kmc_knobs& k);
+uint32_t ctx_batch_workers(const kmc_ctx* c);
+void ctx_set_batch_workers(kmc_ctx* c, uint32_t n);
+bool ctx_override_knobs(kmc_ctx* c, const kmc_knobs* k);
 // kmc_count_ws; with own_table a device table is allocated apart from the
 // workspace, so it outlives the workspace's reuse.
 kmc_status count_ws_impl(kmc_ctx* c, const kmc_reads* reads, const kmc_params* params,

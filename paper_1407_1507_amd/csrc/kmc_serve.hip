@@ -232,7 +232,8 @@ kmc_status kmc_batch_count(kmc_ctx* ctx, const kmc_job* jobs, uint32_t n_jobs, k
     if (!pool) return KMC_ERR_OUT_OF_MEMORY;
     *slot = pool;
   }
-  const uint32_t n_workers = std::min(n_jobs, kBatchWorkers);
+  const uint32_t want = kmc::ctx_batch_workers(ctx) ? kmc::ctx_batch_workers(ctx) : kBatchWorkers;
+  const uint32_t n_workers = std::min(n_jobs, std::min(want, kMaxActive));
   while (pool->workers.size() < n_workers) {
     kmc_ctx* w = nullptr;
     kmc_status st = kmc_ctx_create(kmc::ctx_device(ctx), &w);
@@ -242,6 +243,8 @@ kmc_status kmc_batch_count(kmc_ctx* ctx, const kmc_job* jobs, uint32_t n_jobs, k
     }
     pool->workers.push_back(w);
   }
+  // the workers count with the caller's knobs (override or tuned)
+  for (uint32_t t = 0; t < n_workers; ++t) kmc::ctx_copy_tuning(pool->workers[t], ctx);
   std::atomic<uint32_t> next{0};
   std::atomic<bool> failed{false};
   std::vector<kmc_status> status(n_jobs, KMC_OK);
@@ -281,6 +284,102 @@ kmc_status kmc_batch_count(kmc_ctx* ctx, const kmc_job* jobs, uint32_t n_jobs, k
     outs[j] = nullptr;
   }
   return first;
+}
+
+// Candidate knobs of kmc_autotune: tile packing, first-digit bits, records
+// per expansion task.
+static const kmc_knobs kCandidates[] = {
+    {3, 0, 0},  {2, 0, 0},  {3, -1, 0}, {3, 1, 0},  {3, 0, 512}, {3, 0, 1024},
+    {2, 1, 0},  {2, 0, 512}, {3, 1, 512}, {2, -1, 0}, {3, -1, 512}, {2, 1, 512}};
+static const uint32_t kWorkerCandidates[] = {2, 4, 8};
+
+kmc_status kmc_autotune(kmc_ctx* ctx, const kmc_job* jobs, uint32_t n_jobs,
+                        kmc_tune_report* report) {
+  if (!ctx || (n_jobs && !jobs)) return KMC_ERR_INVALID_ARG;
+  if (report) *report = kmc_tune_report{};
+  // one sample per class: the largest job of each (key width, log2 bases)
+  std::map<uint32_t, uint32_t> sample;
+  for (uint32_t i = 0; i < n_jobs; ++i) {
+    const uint32_t kw = jobs[i].params.k <= 32 ? 1 : 2;
+    uint32_t l = 0;
+    while (l < 63 && (2ull << l) <= jobs[i].reads.n_bases) ++l;
+    const uint32_t cls = (kw - 1) * 64 + l;
+    auto it = sample.find(cls);
+    if (it == sample.end() || jobs[i].reads.n_bases > jobs[it->second].reads.n_bases)
+      sample[cls] = i;
+  }
+  (void)kmc::ctx_override_knobs(ctx, nullptr);  // tuning replaces any override
+  uint32_t n_cls = 0;
+  for (const auto& kv : sample) {
+    const kmc_job& J = jobs[kv.second];
+    kmc_params P = J.params;
+    P.flags |= KMC_FLAG_DEVICE_TABLE;
+    double best_us = 1e300;
+    kmc_knobs best = kCandidates[0];
+    for (const kmc_knobs& cand : kCandidates) {
+      kmc::ctx_override_knobs(ctx, &cand);
+      double us = 0;
+      for (int rep = 0; rep < 2; ++rep) {  // the first run sizes the cached buffers
+        kmc_table* t = nullptr;
+        const kmc_status st = kmc_count_ex(ctx, &J.reads, &P, nullptr, &t);
+        if (st != KMC_OK) {
+          kmc::ctx_override_knobs(ctx, nullptr);
+          return st;
+        }
+        us = t->stats.us_total;
+        kmc_table_free(t);
+      }
+      if (us < best_us) {
+        best_us = us;
+        best = cand;
+      }
+    }
+    kmc::ctx_override_knobs(ctx, nullptr);
+    kmc::ctx_set_tuned(ctx, J.params.k <= 32 ? 1 : 2, J.reads.n_bases, best);
+    if (report && n_cls < KMC_TUNE_MAX_CLASSES) {
+      kmc_tune_class& c = report->classes[n_cls];
+      c.key_words = J.params.k <= 32 ? 1 : 2;
+      c.sample_bases = J.reads.n_bases;
+      c.knobs = best;
+      c.us = best_us;
+    }
+    ++n_cls;
+  }
+  if (report) report->n_classes = std::min<uint32_t>(n_cls, KMC_TUNE_MAX_CLASSES);
+  // batch streams: the sample jobs as one batch with 2, 4 and 8 workers
+  if (n_jobs > 1) {
+    std::vector<kmc_job> sj;
+    for (const auto& kv : sample) {
+      kmc_job j = jobs[kv.second];
+      j.params.flags |= KMC_FLAG_DEVICE_TABLE;
+      sj.push_back(j);
+    }
+    while (sj.size() < 16) sj.push_back(sj[sj.size() % sample.size()]);
+    std::vector<kmc_table*> outs(sj.size(), nullptr);
+    double best_s = 1e300;
+    uint32_t best_w = kBatchWorkers;
+    for (uint32_t w : kWorkerCandidates) {
+      kmc::ctx_set_batch_workers(ctx, w);
+      double dt = 0;
+      for (int rep = 0; rep < 2; ++rep) {
+        const double t0 = now_us();
+        const kmc_status st = kmc_batch_count(ctx, sj.data(), (uint32_t)sj.size(), outs.data());
+        dt = now_us() - t0;
+        for (auto*& t : outs) {
+          kmc_table_free(t);
+          t = nullptr;
+        }
+        if (st != KMC_OK) return st;
+      }
+      if (dt < best_s) {
+        best_s = dt;
+        best_w = w;
+      }
+    }
+    kmc::ctx_set_batch_workers(ctx, best_w);
+    if (report) report->batch_workers = best_w;
+  }
+  return KMC_OK;
 }
 
 kmc_status kmc_server_start(kmc_ctx* ctx, const kmc_server_cfg* cfg, kmc_server** out) {

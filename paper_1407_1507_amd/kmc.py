@@ -36,7 +36,8 @@ EXPORTS = ["kmc_ctx_create", "kmc_ctx_destroy", "kmc_last_error", "kmc_ctx_set_b
            "kmc_batch_count", "kmc_server_start", "kmc_server_submit", "kmc_server_poll",
            "kmc_server_stats_get", "kmc_server_stop", "kmc_debug_signatures",
            "kmc_count_static", "kmc_db_build", "kmc_db_info_get", "kmc_db_write", "kmc_db_open",
-           "kmc_db_query", "kmc_db_decode", "kmc_db_free", "kmc_parse", "kmc_parsed_free"]
+           "kmc_db_query", "kmc_db_decode", "kmc_db_free", "kmc_parse", "kmc_parsed_free",
+           "kmc_ctx_set_knobs", "kmc_autotune"]
 FORMAT_AUTO, FORMAT_FASTQ, FORMAT_FASTA = 0, 1, 2
 STATIC_SCRATCH_BYTES = 256 << 20  # KMC_STATIC_SCRATCH_BYTES
 
@@ -90,6 +91,27 @@ class DbInfo(ctypes.Structure):
     _fields_ = [(n, ctypes.c_uint32) for n in (
         "kmer_length", "mode", "counter_size", "lut_prefix_length", "signature_length",
         "min_count", "max_count", "flags")] + [("total_kmers", ctypes.c_uint64)]
+
+
+class Knobs(ctypes.Structure):
+    _fields_ = [("tile_fill", ctypes.c_uint32), ("fine_bits_bias", ctypes.c_int32),
+                ("expand_task", ctypes.c_uint32)]
+
+
+class TuneClass(ctypes.Structure):
+    _fields_ = [("key_words", ctypes.c_uint32), ("reserved", ctypes.c_uint32),
+                ("sample_bases", ctypes.c_uint64), ("knobs", Knobs), ("pad", ctypes.c_uint32),
+                ("us", ctypes.c_double)]
+
+
+class TuneReport(ctypes.Structure):
+    _fields_ = [("n_classes", ctypes.c_uint32), ("batch_workers", ctypes.c_uint32),
+                ("classes", TuneClass * 32)]
+
+
+# the autotuner's candidate knob sets (tile_fill, fine_bits_bias, expand_task)
+KNOB_CANDIDATES = [(3, 0, 0), (2, 0, 0), (3, -1, 0), (3, 1, 0), (3, 0, 512), (3, 0, 1024),
+                   (2, 1, 0), (2, 0, 512), (3, 1, 512), (2, -1, 0), (3, -1, 512), (2, 1, 512)]
 
 
 class Job(ctypes.Structure):
@@ -182,6 +204,11 @@ def lib() -> ctypes.CDLL:
         L.kmc_parse.restype = ctypes.c_int
         L.kmc_parsed_free.argtypes = [vp]
         L.kmc_parsed_free.restype = None
+        L.kmc_ctx_set_knobs.argtypes = [vp, ctypes.POINTER(Knobs)]
+        L.kmc_ctx_set_knobs.restype = ctypes.c_int
+        L.kmc_autotune.argtypes = [vp, ctypes.POINTER(Job), ctypes.c_uint32,
+                                   ctypes.POINTER(TuneReport)]
+        L.kmc_autotune.restype = ctypes.c_int
         L.kmc_batch_count.argtypes = [vp, ctypes.POINTER(Job), ctypes.c_uint32,
                                       ctypes.POINTER(ctypes.POINTER(Table))]
         L.kmc_batch_count.restype = ctypes.c_int
@@ -283,6 +310,34 @@ class Context:
         st = lib().kmc_ctx_set_budget(self._h, device_bytes)
         if st != KMC_OK:
             raise KmcError(st, "kmc_ctx_set_budget")
+
+    def set_knobs(self, knobs=None):
+        """kmc_ctx_set_knobs: (tile_fill, fine_bits_bias, expand_task), or None."""
+        k = Knobs(*knobs) if knobs is not None else None
+        st = lib().kmc_ctx_set_knobs(self._h, ctypes.byref(k) if k is not None else None)
+        if st != KMC_OK:
+            raise KmcError(st, "kmc_ctx_set_knobs")
+
+    def autotune(self, jobs) -> dict:
+        """kmc_autotune over jobs = [(seq, offsets, params dict), ...]."""
+        n = len(jobs)
+        arr = (Job * max(n, 1))()
+        keep = []
+        for i, (seq, off, prm) in enumerate(jobs):
+            r, kp = make_reads(seq, off)
+            keep.append(kp)
+            arr[i].reads = r
+            arr[i].params = make_params(**prm)
+        rep = TuneReport()
+        st = lib().kmc_autotune(self._h, arr, n, ctypes.byref(rep))
+        del keep
+        if st != KMC_OK:
+            self._raise(st, "kmc_autotune")
+        return {"batch_workers": rep.batch_workers,
+                "classes": [{"key_words": c.key_words, "sample_bases": c.sample_bases,
+                             "knobs": (c.knobs.tile_fill, c.knobs.fine_bits_bias,
+                                       c.knobs.expand_task), "us": c.us}
+                            for c in rep.classes[:rep.n_classes]]}
 
     def close(self):
         if self._h:

@@ -55,6 +55,8 @@ int main(void) {
   printf("%zu %zu %zu %zu %zu\\n", sizeof(kmc_job), offsetof(kmc_job, params),
          sizeof(kmc_server_cfg), sizeof(kmc_server_stats), offsetof(kmc_server_stats, active));
   printf("%zu %zu\\n", offsetof(kmc_stats, us_kernel), offsetof(kmc_stats, us_latency));
+  printf("%zu %zu %zu %zu %zu\\n", sizeof(kmc_knobs), sizeof(kmc_tune_class),
+         sizeof(kmc_tune_report), offsetof(kmc_tune_class, us), sizeof(kmc_db_info));
   return 0;
 }
 """)
@@ -72,6 +74,9 @@ int main(void) {
         ctypes.sizeof(kmc.ServerStats), kmc.ServerStats.active.offset]
     assert [int(x) for x in lines[3].split()] == [kmc.Stats.us_kernel.offset,
                                                   kmc.Stats.us_latency.offset]
+    assert [int(x) for x in lines[4].split()] == [
+        ctypes.sizeof(kmc.Knobs), ctypes.sizeof(kmc.TuneClass), ctypes.sizeof(kmc.TuneReport),
+        kmc.TuneClass.us.offset, ctypes.sizeof(kmc.DbInfo)]
 
 
 def test_status_strings(kmc):
