@@ -286,8 +286,9 @@ kmc_status kmc_batch_count(kmc_ctx* ctx, const kmc_job* jobs, uint32_t n_jobs, k
  * bits -1..+1, 256 / 512 / 1024 records per expansion task; twelve sets),
  * and the fastest device time is kept as the class's knobs for later jobs of
  * ctx (kmc_count_ex and kmc_batch_count; a kmc_ctx_set_knobs override
- * wins).  Then the classes' samples run as one batch with 2, 4 and 8 worker
- * streams, and the fastest count becomes ctx's batch pool size.  No knob
+ * wins).  Then up to 64 of the jobs (spread over the list) run as one batch
+ * with 2, 4 and 8 worker streams, and the fastest count becomes ctx's batch
+ * pool size.  No knob
  * changes a table.  report may be NULL. */
 #define KMC_TUNE_MAX_CLASSES 32
 typedef struct kmc_tune_class {

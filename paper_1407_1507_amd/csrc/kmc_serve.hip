@@ -346,25 +346,26 @@ kmc_status kmc_autotune(kmc_ctx* ctx, const kmc_job* jobs, uint32_t n_jobs,
     ++n_cls;
   }
   if (report) report->n_classes = std::min<uint32_t>(n_cls, KMC_TUNE_MAX_CLASSES);
-  // batch streams: the sample jobs as one batch with 2, 4 and 8 workers
+  // batch streams: up to 64 of the jobs (every n_jobs/64-th, so the mix of
+  // sizes is the batch's) as one batch with 2, 4 and 8 workers
   if (n_jobs > 1) {
     std::vector<kmc_job> sj;
-    for (const auto& kv : sample) {
-      kmc_job j = jobs[kv.second];
+    const uint32_t step = n_jobs > 64 ? n_jobs / 64 : 1;
+    for (uint32_t i = 0; i < n_jobs && sj.size() < 64; i += step) {
+      kmc_job j = jobs[i];
       j.params.flags |= KMC_FLAG_DEVICE_TABLE;
       sj.push_back(j);
     }
-    while (sj.size() < 16) sj.push_back(sj[sj.size() % sample.size()]);
     std::vector<kmc_table*> outs(sj.size(), nullptr);
     double best_s = 1e300;
     uint32_t best_w = kBatchWorkers;
     for (uint32_t w : kWorkerCandidates) {
       kmc::ctx_set_batch_workers(ctx, w);
-      double dt = 0;
-      for (int rep = 0; rep < 2; ++rep) {
+      double dt = 1e300;
+      for (int rep = 0; rep < 3; ++rep) {  // the first run sizes the workers' buffers
         const double t0 = now_us();
         const kmc_status st = kmc_batch_count(ctx, sj.data(), (uint32_t)sj.size(), outs.data());
-        dt = now_us() - t0;
+        if (rep > 0) dt = std::min(dt, now_us() - t0);
         for (auto*& t : outs) {
           kmc_table_free(t);
           t = nullptr;

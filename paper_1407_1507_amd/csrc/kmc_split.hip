@@ -147,10 +147,11 @@ __device__ __forceinline__ VT* lane_vh(void* lds, uint32_t w) {
 
 // ------------------------------------------------------------ sample hist
 
-// Signatures below kLdsSig are counted in the workgroup's LDS first: the
-// smallest canonical m-mers are the most frequent minimizers, and their
-// global counters would otherwise take most of the sample's atomics on a few
-// addresses.
+// Signatures below kLdsSig (fewer when the window buffers leave less room
+// for two workgroups per compute unit) are counted in the workgroup's LDS
+// first: the smallest canonical m-mers are the most frequent minimizers, and
+// their global counters would otherwise take most of the sample's atomics on
+// a few addresses.
 constexpr uint32_t kLdsSig = 4096;
 
 template <int KW>
@@ -160,12 +161,13 @@ struct HistSink {
   uint32_t* hist_r;   // super k-mers per signature
   uint32_t* lds_k;    // the same for signatures below kLdsSig, in LDS
   uint32_t* lds_r;
+  uint32_t nl;        // signatures counted in LDS
   uint64_t kmers;
   __device__ void kmer(uint64_t, uint32_t, uint64_t, uint64_t) {}
   __device__ uint32_t bin_of(uint32_t) { return 0; }
   __device__ void superkmer(uint64_t, uint32_t n, uint32_t sig, uint32_t,
                             typename KeyOf<KW>::T, typename KeyOf<KW>::T) {
-    if (sig < kLdsSig) {
+    if (sig < nl) {
       atomicAdd(&lds_k[sig], n);
       atomicAdd(&lds_r[sig], 1u);
     } else {
@@ -180,18 +182,17 @@ template <int KW, class VT>
 __global__ void __launch_bounds__(256)
 k_sig_hist(const uint8_t* __restrict__ seq, const uint64_t* __restrict__ offsets,
            uint64_t n_reads, uint64_t n_bases, uint64_t stride, ScanCfg C, uint32_t* hist,
-           unsigned long long* sample) {
+           unsigned long long* sample, uint32_t nl) {
   extern __shared__ __attribute__((aligned(16))) uint8_t lds8[];
   const uint64_t r = ((uint64_t)blockIdx.x * blockDim.x + threadIdx.x) * stride;
   const uint32_t n_sig = C.sent + 1;
-  const uint32_t nl = min(n_sig, kLdsSig);
   const size_t vb =
       ((size_t)blockDim.x * vh_stride(C.w, sizeof(VT)) * sizeof(VT) + 15) & ~(size_t)15;
   uint32_t* lk = reinterpret_cast<uint32_t*>(lds8 + vb);  // after the window buffers
   uint32_t* lr = lk + nl;
   for (uint32_t i = threadIdx.x; i < 2 * nl; i += blockDim.x) lk[i] = 0;
   __syncthreads();
-  HistSink<KW> sink{hist, hist + n_sig, lk, lr, 0};
+  HistSink<KW> sink{hist, hist + n_sig, lk, lr, nl, 0};
   uint64_t bases = 0;
   if (r < n_reads) {
     bases = offsets[r + 1] - offsets[r];
@@ -468,6 +469,13 @@ uint32_t grid_for(uint64_t n, uint32_t per) { return (uint32_t)((n + per - 1) / 
 // kLongRead bases) take the position-per-lane scan, which walks a read 64
 // bases per step.
 constexpr uint64_t kLongRead = 2048;
+// A lane walks its read one base per step, so the lane scan fills the chip
+// only with many reads: a job of fewer reads (or a sample histogram of fewer
+// sampled reads) takes the position-per-lane scan, whose wavefronts share
+// the positions of a few reads (measured: 35K reads, 235 -> 93 us; 770K
+// reads of 175 bp at k = 55 still favour the lane scan, 747 vs 917 us).
+constexpr uint64_t kLaneScanMinReads = 1ull << 18;
+constexpr uint64_t kLaneHistMinSample = 4096;
 
 // Window buffers hold u16 when every stored value (4^p + 1 at most) fits.
 static bool small_vt(const ScanCfg& c) { return c.sent + 1u <= 0xFFFFu; }
@@ -515,13 +523,19 @@ hipError_t launch_sig_hist(hipStream_t s, const uint8_t* seq, const uint64_t* of
                            unsigned long long* sample) {
   const uint64_t n_sample = (n_reads + stride - 1) / stride;
   if (n_sample == 0) return hipSuccess;
-  if (n_bases > kLongRead * n_reads)
+  if (n_bases > kLongRead * n_reads || n_sample < kLaneHistMinSample)
     return launch_sig_hist_wide(s, seq, offsets, n_reads, stride, cfg, key_words, hist,
                                 sample);
   const uint32_t lanes = scan_lanes(cfg);
-  const size_t sh = vh_bytes(cfg, lanes) + 2 * std::min<size_t>(cfg.sent + 1, kLdsSig) * 4;
+  const size_t vb = vh_bytes(cfg, lanes);
+  // LDS-counted signatures: up to kLdsSig, fewer if that keeps the
+  // workgroup within 80 KB (two per compute unit)
+  uint32_t nl = std::min<uint32_t>(cfg.sent + 1, kLdsSig);
+  if (vb + (size_t)nl * 8 > 80 * 1024)
+    nl = vb < 80 * 1024 - 8 * 256 ? (uint32_t)((80 * 1024 - vb) / 8) : 256u;
+  const size_t sh = vb + (size_t)nl * 8;
   KMC_SCAN_DISPATCH(k_sig_hist, dim3(grid_for(n_sample, lanes)), dim3(lanes), sh, s, seq,
-                    offsets, n_reads, n_bases, stride, cfg, hist, sample);
+                    offsets, n_reads, n_bases, stride, cfg, hist, sample, nl);
   return hipGetLastError();
 }
 
@@ -534,9 +548,23 @@ static bool lane_scan_fits(const ScanCfg& c, uint32_t key_words) {
   return split_lds_bytes(c, key_words, 256) <= 80 * 1024;
 }
 
+// A super k-mer holds about w / 2 k-mers (Table 6: 6.7 per 100 bp read at
+// k = 28, m = 7), so a read of mean length L gives about 2 (L - k + 1) / w + 1
+// of them.  The lane scan queues SplitQ of them per lane in LDS and sends the
+// rest one by one to global memory, so reads expected to overflow the queue
+// (long reads for their k: 911K reads of 175 bp at k = 21, 4.2 ms against
+// 1.1 ms) take the position-per-lane scan.
+static bool lane_queue_fits(const ScanCfg& c, uint32_t key_words, uint64_t n_reads,
+                            uint64_t n_bases) {
+  const uint64_t L = n_reads ? n_bases / n_reads : 0;
+  const uint64_t Q = key_words == 1 ? SplitQ<1>::Q : SplitQ<2>::Q;
+  return L < c.k || 2 * (L - c.k + 1) + c.w <= Q * c.w;
+}
+
 static bool use_lane_scan(const ScanCfg& c, uint32_t key_words, uint64_t n_reads,
                           uint64_t n_bases) {
-  return lane_scan_fits(c, key_words) && n_bases <= kLongRead * n_reads;
+  return lane_scan_fits(c, key_words) && n_bases <= kLongRead * n_reads &&
+         n_reads >= kLaneScanMinReads && lane_queue_fits(c, key_words, n_reads, n_bases);
 }
 
 // The lane-per-read scan is used when 256 lanes' window buffers (16-bit

@@ -241,6 +241,30 @@ def test_big_tiles(ctx):
         check_table(res, seq, off, k, p, 1, 2**32 - 1)
 
 
+@pytest.mark.parametrize("name,scale", [("genome-5M-2Mx100", 0.15),
+                                        ("repeats-50M-30x150-k55", 0.03)])
+def test_lane_scan_workloads(ctx, name, scale):
+    # 300 000 reads: enough for the lane-per-read scan (smaller jobs take the
+    # position-per-lane scan)
+    seq, off, p = synth.make(name, scale)
+    res = ctx.count(seq, off, p["k"], p["p"], p["n_bins"], p["cutoff_min"], p["cutoff_max"])
+    check_table(res, seq, off, p["k"], p["p"], p["cutoff_min"], p["cutoff_max"])
+
+
+def test_lane_scan_queue_overflow(ctx):
+    # 300 000 reads, one in ten of 600 bp: the mean length keeps the lane
+    # scan, and the long reads overflow their lane's queue of super k-mers
+    # (the rest go to their bins one by one)
+    ref = synth.random_reference(32, 2_000_000)
+    seq, off = synth.sample_reads(33, ref, 300_000, 100, err=0.01, n_rate=0.001)
+    lseq, loff = synth.sample_reads(34, ref, 30_000, 600, err=0.01, n_rate=0.001)
+    seq = np.concatenate([seq[: int(off[270_000])], lseq])
+    off = np.concatenate([off[:270_001], loff[1:] + off[270_000]])
+    assert off.size == 300_001
+    res = ctx.count(seq, off, 55, 9, 1024, 1, 2**32 - 1)
+    check_table(res, seq, off, 55, 9, 1, 2**32 - 1)
+
+
 def test_plain_minimizers_same_counts(ctx, kmc):
     seq, off, p = synth.make("genome-5M-2Mx100", 0.01)
     res = ctx.count(seq, off, 28, 7, 512, 2, 10**9, flags=kmc.FLAG_PLAIN_MINIMIZERS)
