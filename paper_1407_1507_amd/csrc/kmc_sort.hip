@@ -659,18 +659,6 @@ __device__ __forceinline__ void load_tile(const uint64_t* src, uint32_t n,
   }
 }
 
-// One word of every 128-byte line of a tile's keys (a tile of at most 256
-// lines), loaded so that the lines are in the L2 when the tile itself is
-// loaded: a persistent workgroup of 128-bit tiles touches its next tile
-// while it counts the current one (for 64-bit tiles it measured no faster).
-// The caller hands the value to keep_loaded once the current tile is done,
-// which keeps the load and awaits it only there.
-__device__ __forceinline__ uint32_t touch_tile(const uint64_t* src, uint64_t words) {
-  const uint64_t i = (uint64_t)threadIdx.x * 16;
-  return i < words ? *reinterpret_cast<const uint32_t*>(src + i) : 0u;
-}
-__device__ __forceinline__ void keep_loaded(uint32_t v) { asm volatile("" ::"v"(v)); }
-
 template <int KW>
 __device__ uint32_t sort_count_emit(const uint64_t* src, uint32_t n, uint64_t* out_keys,
                                     uint32_t* out_counts, uint32_t ci, uint32_t cx,
@@ -872,10 +860,21 @@ k_tile_sort(KeyCfg kc, const Tile* __restrict__ tiles, uint64_t n_tiles, uint64_
     }
     __syncthreads();
   }
+  // the next tile's keys are loaded into registers while the current tile
+  // is counted (double buffering hides the load latency behind the LDS work)
+  auto direct = [](const Tile& x) { return x.size != 0 && x.size <= SortCfg<KW>::DIRECT; };
   Tile next = tiles[blockIdx.x];
+  K nkey[ITEMS];
+  if (direct(next)) load_tile<KW>(keys + next.begin * KW, next.size, nkey);
   for (uint64_t t = blockIdx.x; t < n_tiles; t += gridDim.x) {
     const Tile T = next;
-    if (t + gridDim.x < n_tiles) next = tiles[t + gridDim.x];
+    K key[ITEMS];
+#pragma unroll
+    for (uint32_t m = 0; m < ITEMS; ++m) key[m] = nkey[m];
+    if (t + gridDim.x < n_tiles) {
+      next = tiles[t + gridDim.x];
+      if (direct(next)) load_tile<KW>(keys + next.begin * KW, next.size, nkey);
+    }
     if (T.size == 0) {
       if (threadIdx.x == 0) tile_out[t] = tile_distinct[t] = 0;
     } else if (T.size > SortCfg<KW>::DIRECT) {
@@ -886,8 +885,6 @@ k_tile_sort(KeyCfg kc, const Tile* __restrict__ tiles, uint64_t n_tiles, uint64_
         big_off[idx] = atomicAdd(big_total, (unsigned long long)T.size);  // own slice of tmp
       }
     } else {
-      K key[ITEMS];
-      load_tile<KW>(keys + T.begin * KW, T.size, key);
       uint32_t d;
       const uint32_t kept = count_direct(key, T.size, keys + T.begin * KW, counts + T.begin,
                                          kc.cutoff_min, kc.cutoff_max, S, &d);
@@ -910,18 +907,24 @@ k_tile_hash2(KeyCfg kc, const Tile* __restrict__ tiles, uint64_t n_tiles, uint64
   __shared__ HashShared2 S;
   for (uint32_t i = threadIdx.x; i < kHashSlots2; i += blockDim.x) S.F[i] = 0;
   __syncthreads();
+  // the next tile's keys are loaded into registers while the current tile
+  // is counted (double buffering)
   Tile next = tiles[blockIdx.x];
+  u128 nkey[ITEMS];
+  if (next.size != 0 && next.size <= SortCfg<2>::DIRECT)
+    load_tile<2>(keys + next.begin * 2, next.size, nkey);
   for (uint64_t t = blockIdx.x; t < n_tiles; t += gridDim.x) {
     const Tile T = next;
-    const bool more = t + gridDim.x < n_tiles;
-    if (more) next = tiles[t + gridDim.x];
     uint32_t kept = kFingerprintClash, d = 0;
     const bool direct = T.size != 0 && T.size <= SortCfg<2>::DIRECT;
     u128 key[ITEMS];
-    if (direct) load_tile<2>(keys + T.begin * 2, T.size, key);
-    uint32_t touched = 0;
-    if (more && next.size != 0 && next.size <= SortCfg<2>::DIRECT)
-      touched = touch_tile(keys + next.begin * 2, (uint64_t)next.size * 2);
+#pragma unroll
+    for (uint32_t m = 0; m < ITEMS; ++m) key[m] = nkey[m];
+    if (t + gridDim.x < n_tiles) {
+      next = tiles[t + gridDim.x];
+      if (next.size != 0 && next.size <= SortCfg<2>::DIRECT)
+        load_tile<2>(keys + next.begin * 2, next.size, nkey);
+    }
     if (T.size == 0) {
       kept = 0;
     } else if (direct) {
@@ -939,7 +942,6 @@ k_tile_hash2(KeyCfg kc, const Tile* __restrict__ tiles, uint64_t n_tiles, uint64
         tile_distinct[t] = d;
       }
     }
-    keep_loaded(touched);
   }
 }
 
