@@ -4,6 +4,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <cmath>
 #include <cstdio>
 #include <cstdlib>
 #include <cstring>
@@ -512,15 +513,19 @@ void run_count(kmc_ctx* c, const kmc_reads* R, const kmc_params* P, kmc_table* T
   check(c, hipEventRecord(c->ev[1], s), "event");
 
   // ---- split: one pass writing super k-mer records into bin regions sized
-  // from the sample (1.25x the scaled estimate + 256 records); if a bin
-  // overflows, the pass is repeated with the exact sizes its cursor counted
+  // from the sample; if a bin overflows, the pass is repeated with the exact
+  // sizes its cursor counted. A bin whose sample holds n records gets
+  // scale * (1.15 n + 8 sqrt(n)) + 256: the relative error of a sampled count
+  // shrinks as 1/sqrt(n), so small bins need the wider margin (reads of a
+  // repeat family arrive together, which widens the spread beyond Poisson)
   std::vector<uint64_t> cap(J.n_bins, 0);
   {
     std::vector<double> est(J.n_bins, 0.0);
     for (uint32_t g = 0; g < n_sig; ++g) est[map[g]] += h_hist[n_sig + g];
     const double scale = h_misc.sample_bases ? (double)J.n_bases / (double)h_misc.sample_bases : 0.0;
     for (uint32_t b = 0; b < J.n_bins; ++b)
-      cap[b] = std::min<uint64_t>((uint64_t)(est[b] * scale * 1.25) + 256, kMaxBinRecords);
+      cap[b] = std::min<uint64_t>((uint64_t)((1.15 * est[b] + 8.0 * std::sqrt(est[b])) * scale) + 256,
+                                  kMaxBinRecords);
     if (c->ws_base) {
       // keep the regions inside the workspace; a bin that outgrows its share
       // takes the exact second pass, whose sizes always fit
