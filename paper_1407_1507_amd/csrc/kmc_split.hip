@@ -297,11 +297,12 @@ struct DirectSink {
   }
 };
 
-// Queue slots per lane.
-template <int KW> struct SplitQ { static constexpr uint32_t Q = 8; };
+// Queue slots per lane: 2^3, or 2^4 for reads that give more super k-mers
+// than 8 on average (a slot is 7 bytes of LDS: records are rebuilt from the
+// read at write-out).
+constexpr uint32_t kSplitQBitsMin = 3, kSplitQBitsMax = 4;
 // A bin's slot offsets (region offset + a workgroup's slots) fit 31 bits.
-static_assert(kMaxBinRecords + 256ull * SplitQ<1>::Q < (1ull << 31) &&
-                  kMaxBinRecords + 256ull * SplitQ<2>::Q < (1ull << 31),
+static_assert(kMaxBinRecords + (256ull << kSplitQBitsMax) < (1ull << 31),
               "32-bit slot offsets of the lane scan");
 
 // LDS of k_split_scatter: region U (the lanes' window buffers during the
@@ -329,9 +330,10 @@ __global__ void __launch_bounds__(256)
 k_split_scatter(const uint8_t* __restrict__ seq, const uint64_t* __restrict__ offsets,
                 uint64_t n_reads, uint64_t n_bases, ScanCfg C, const uint32_t* __restrict__ map,
                 unsigned long long* gcursor, unsigned long long* gkmer,
-                const uint64_t* __restrict__ cap_base, uint64_t* records, uint32_t vh_bytes) {
+                const uint64_t* __restrict__ cap_base, uint64_t* records, uint32_t vh_bytes,
+                uint32_t qb) {
   constexpr int RW = 2 * KW;
-  constexpr uint32_t Q = SplitQ<KW>::Q;
+  const uint32_t Q = 1u << qb;
   extern __shared__ __attribute__((aligned(16))) uint8_t lds8[];
   const uint32_t tid = threadIdx.x, nt = blockDim.x, cap = nt * Q;
   const SplitLds SL = split_lds(nt, Q, C.n_bins, vh_bytes, sizeof(VT));
@@ -365,7 +367,7 @@ k_split_scatter(const uint8_t* __restrict__ seq, const uint64_t* __restrict__ of
   __syncthreads();
   // bins of the queued records, their rank inside the bin, k-mers per bin
   for (uint32_t i = tid; i < cap; i += nt) {
-    if (i % Q < qn[i / Q]) {
+    if ((i & (Q - 1)) < qn[i >> qb]) {
       const uint32_t b = map[ssig[i]];
       ssig[i] = (VT)b;  // n_bins <= 65535
       srank[i] = (uint16_t)atomicAdd(&lcnt[b], 1u);
@@ -386,7 +388,7 @@ k_split_scatter(const uint8_t* __restrict__ seq, const uint64_t* __restrict__ of
     if (lkm[i]) atomicAdd(&gkmer[i], (unsigned long long)lkm[i]);
   }
   for (uint32_t i = tid; i < cap; i += nt)
-    if (i % Q < qn[i / Q]) inv[lbase[ssig[i]] + srank[i]] = (uint16_t)i;
+    if ((i & (Q - 1)) < qn[i >> qb]) inv[lbase[ssig[i]] + srank[i]] = (uint16_t)i;
   __syncthreads();
   // records grouped by bin: consecutive lanes -> consecutive slots; each is
   // rebuilt from its read
@@ -397,8 +399,8 @@ k_split_scatter(const uint8_t* __restrict__ seq, const uint64_t* __restrict__ of
     const uint64_t g = (uint64_t)((int64_t)cap_base[b] + delta[b] + (int64_t)q);
     if (g < cap_base[b + 1]) {
       uint64_t rec[RW];
-      record_from_read<KW>(seq, n_bases, C.seq_align, offsets[r0 + i / Q] + sj[i], sn[i], C.k,
-                           rec);
+      record_from_read<KW>(seq, n_bases, C.seq_align, offsets[r0 + (i >> qb)] + sj[i], sn[i],
+                           C.k, rec);
 #pragma unroll
       for (int w = 0; w < RW; ++w) records[g * RW + w] = rec[w];
     }
@@ -539,39 +541,35 @@ hipError_t launch_sig_hist(hipStream_t s, const uint8_t* seq, const uint64_t* of
   return hipGetLastError();
 }
 
-static size_t split_lds_bytes(const ScanCfg& c, uint32_t key_words, uint32_t lanes) {
-  const uint32_t Q = key_words == 1 ? SplitQ<1>::Q : SplitQ<2>::Q;
-  return split_lds(lanes, Q, c.n_bins, (uint32_t)vh_bytes(c, lanes), small_vt(c) ? 2 : 4).total;
-}
-
-static bool lane_scan_fits(const ScanCfg& c, uint32_t key_words) {
-  return split_lds_bytes(c, key_words, 256) <= 80 * 1024;
+static size_t split_lds_bytes(const ScanCfg& c, uint32_t lanes, uint32_t qb) {
+  return split_lds(lanes, 1u << qb, c.n_bins, (uint32_t)vh_bytes(c, lanes), small_vt(c) ? 2 : 4)
+      .total;
 }
 
 // A super k-mer holds about w / 2 k-mers (Table 6: 6.7 per 100 bp read at
 // k = 28, m = 7), so a read of mean length L gives about 2 (L - k + 1) / w + 1
-// of them.  The lane scan queues SplitQ of them per lane in LDS and sends the
-// rest one by one to global memory, so reads expected to overflow the queue
-// (long reads for their k: 911K reads of 175 bp at k = 21, 4.2 ms against
-// 1.1 ms) take the position-per-lane scan.
-static bool lane_queue_fits(const ScanCfg& c, uint32_t key_words, uint64_t n_reads,
-                            uint64_t n_bases) {
+// of them.  The lane scan queues 2^qb of them per lane in LDS and sends the
+// rest one by one to global memory: the queue is the shortest that holds the
+// expected count, and reads expected to overflow the longest queue (long
+// reads for their k: 911K reads of 175 bp at k = 21, 4.2 ms against 1.1 ms
+// with 8 slots) take the position-per-lane scan.  Returns 0 when none fits.
+static uint32_t lane_queue_bits(const ScanCfg& c, uint64_t n_reads, uint64_t n_bases) {
   const uint64_t L = n_reads ? n_bases / n_reads : 0;
-  const uint64_t Q = key_words == 1 ? SplitQ<1>::Q : SplitQ<2>::Q;
-  return L < c.k || 2 * (L - c.k + 1) + c.w <= Q * c.w;
-}
-
-static bool use_lane_scan(const ScanCfg& c, uint32_t key_words, uint64_t n_reads,
-                          uint64_t n_bases) {
-  return lane_scan_fits(c, key_words) && n_bases <= kLongRead * n_reads &&
-         n_reads >= kLaneScanMinReads && lane_queue_fits(c, key_words, n_reads, n_bases);
+  for (uint32_t qb = kSplitQBitsMin; qb <= kSplitQBitsMax; ++qb)
+    if (L < c.k || 2 * (L - c.k + 1) + c.w <= ((uint64_t)c.w << qb)) return qb;
+  return 0;
 }
 
 // The lane-per-read scan is used when 256 lanes' window buffers (16-bit
 // values for p <= 7, 32-bit above) and record queues fit at least two
 // workgroups per compute unit; otherwise the scan with one position per lane
-// (the same signatures and records).
-static bool lane_scan_fits(const ScanCfg& c, uint32_t key_words);
+// (the same signatures and records).  Returns the queue bits, 0 for the
+// position-per-lane scan.
+static uint32_t lane_scan_bits(const ScanCfg& c, uint64_t n_reads, uint64_t n_bases) {
+  if (n_bases > kLongRead * n_reads || n_reads < kLaneScanMinReads) return 0;
+  const uint32_t qb = lane_queue_bits(c, n_reads, n_bases);
+  return qb && split_lds_bytes(c, 256, qb) <= 80 * 1024 ? qb : 0;
+}
 
 hipError_t launch_split_scatter(hipStream_t s, const uint8_t* seq, const uint64_t* offsets,
                                 uint64_t n_reads, uint64_t n_bases, const ScanCfg& cfg,
@@ -579,17 +577,18 @@ hipError_t launch_split_scatter(hipStream_t s, const uint8_t* seq, const uint64_
                                 unsigned long long* cursor, unsigned long long* kmer_cnt,
                                 const uint64_t* cap_base, uint64_t* records) {
   if (n_reads == 0) return hipSuccess;
-  if (!use_lane_scan(cfg, key_words, n_reads, n_bases))
+  const uint32_t qb = lane_scan_bits(cfg, n_reads, n_bases);
+  if (qb == 0)
     return launch_split_wide(s, seq, offsets, n_reads, n_bases, cfg, key_words, sig_to_bin,
                              cursor, kmer_cnt, cap_base, records);
   // largest workgroup whose window buffers + queues fit 80 KB (at least two per CU)
   for (uint32_t lanes = 256; lanes >= 64; lanes >>= 1) {
     const size_t vb = vh_bytes(cfg, lanes);
-    const size_t sh = split_lds_bytes(cfg, key_words, lanes);
+    const size_t sh = split_lds_bytes(cfg, lanes, qb);
     if (sh <= 80 * 1024) {
       KMC_SCAN_DISPATCH(k_split_scatter, dim3(grid_for(n_reads, lanes)), dim3(lanes), sh, s,
                         seq, offsets, n_reads, n_bases, cfg, sig_to_bin, cursor, kmer_cnt,
-                        cap_base, records, (uint32_t)vb);
+                        cap_base, records, (uint32_t)vb, qb);
       return hipGetLastError();
     }
   }
@@ -605,7 +604,7 @@ hipError_t launch_debug_sigs(hipStream_t s, const uint8_t* seq, const uint64_t* 
                              uint64_t n_reads, uint64_t n_bases, const ScanCfg& cfg,
                              uint32_t key_words, uint32_t* sig, uint8_t* start) {
   if (n_reads == 0) return hipSuccess;
-  if (!use_lane_scan(cfg, key_words, n_reads, n_bases))
+  if (lane_scan_bits(cfg, n_reads, n_bases) == 0)
     return launch_debug_wide(s, seq, offsets, n_reads, cfg, key_words, sig, start);
   const uint32_t lanes = scan_lanes(cfg);
   const size_t sh = vh_bytes(cfg, lanes);

@@ -265,6 +265,20 @@ def test_lane_scan_queue_overflow(ctx):
     check_table(res, seq, off, 55, 9, 1, 2**32 - 1)
 
 
+def test_lane_scan_long_queue_overflow(ctx):
+    # 300 000 reads at k = 28, one in twenty of 600 bp, the rest 150 bp: the
+    # mean length (172.5) needs the 16-slot queue per lane (about 14 super
+    # k-mers per read), and the long reads (about 53 each) overflow it
+    ref = synth.random_reference(35, 4_000_000)
+    seq, off = synth.sample_reads(36, ref, 300_000, 150, err=0.01, n_rate=0.001)
+    lseq, loff = synth.sample_reads(37, ref, 15_000, 600, err=0.01, n_rate=0.001)
+    seq = np.concatenate([seq[: int(off[285_000])], lseq])
+    off = np.concatenate([off[:285_001], loff[1:] + off[285_000]])
+    assert off.size == 300_001
+    res = ctx.count(seq, off, 28, 7, 2048, 1, 2**32 - 1)
+    check_table(res, seq, off, 28, 7, 1, 2**32 - 1)
+
+
 def test_plain_minimizers_same_counts(ctx, kmc):
     seq, off, p = synth.make("genome-5M-2Mx100", 0.01)
     res = ctx.count(seq, off, 28, 7, 512, 2, 10**9, flags=kmc.FLAG_PLAIN_MINIMIZERS)
