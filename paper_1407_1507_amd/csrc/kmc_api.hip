@@ -46,8 +46,10 @@ struct Misc {
   uint32_t n_big;
   uint32_t offsets_err;
   uint32_t big_next;  // work counter of the big-tile kernel
-  uint32_t pad;
+  uint32_t n_fail;    // big tiles left to the partition path (64-bit keys)
   unsigned long long big_out;  // entries kept by the big tiles
+  uint32_t fail_next;  // work counter of the partition path
+  uint32_t pad;
 };
 
 }  // namespace
@@ -619,6 +621,16 @@ void run_count(kmc_ctx* c, const kmc_reads* R, const kmc_params* P, kmc_table* T
   fb = (uint32_t)std::max<int32_t>(1, (int32_t)fb + std::max(-2, std::min(2, kn.fine_bits_bias)));
   fb = std::max<uint32_t>(1, std::min<uint32_t>({fb, (uint32_t)kMaxFineBits, 2 * J.k}));
   kc.fine_bits = fb;
+  // big tiles of 64-bit keys take the streamed pass as a kernel of its own
+  // when bins whose mean fine range exceeds half the tile limit hold an
+  // eighth of the k-mers: most of their fine ranges are then big tiles, most
+  // with few distinct keys.  Otherwise the big tiles are few (fine ranges
+  // that hold the k-mers starting with the bin's signature), and one kernel
+  // that streams or partitions each of them ends sooner.
+  uint64_t heavy = 0;
+  for (uint32_t b = 0; b < J.n_bins; ++b)
+    if (g_kmers[b] > ((uint64_t)kc.tile_limit / 2 << fb)) heavy += g_kmers[b];
+  const bool stream_big = heavy * 8 > n_kmers;
 
   // ---- groups of bins for the sorting phase.  Without a memory budget (or
   // when the job fits it) one group holds every bin.  Under a budget the bins
@@ -766,9 +778,10 @@ void run_count(kmc_ctx* c, const kmc_reads* R, const kmc_params* P, kmc_table* T
     // ---- sort: tiles in LDS, big tiles through HBM
     uint32_t* tile_out = ensure<uint32_t>(c, B_TILEOUT, n_tiles * 8 + 8);
     uint32_t* tile_dist = tile_out + n_tiles + (n_tiles & 1);
-    uint32_t* big = ensure<uint32_t>(c, B_BIG, n_tiles * 16 + 16);
+    uint32_t* big = ensure<uint32_t>(c, B_BIG, n_tiles * 20 + 16);
     uint64_t* big_off = reinterpret_cast<uint64_t*>(big + ((n_tiles + 1) & ~1ull));
     uint32_t* big_order = reinterpret_cast<uint32_t*>(big_off + n_tiles);
+    uint32_t* big_fail = big_order + n_tiles;
     kbeg(c, KMC_K_TILE_SORT, s);
     check(c, launch_tile_sort(s, kc, tiles, n_tiles, keys, counts, tile_out, big, big_off,
                               &misc->n_big, &misc->big_total, tile_dist), "tile_sort");
@@ -778,8 +791,9 @@ void run_count(kmc_ctx* c, const kmc_reads* R, const kmc_params* P, kmc_table* T
     kbeg(c, KMC_K_BIG_TILES, s);
     {
       uint64_t* tmp = ensure<uint64_t>(c, B_TMP, std::max<uint64_t>(1, gk) * J.kw * 8);
-      check(c, launch_big_tiles(s, kc, tiles, big, big_off, big_order, &misc->n_big,
-                                &misc->big_next, n_tiles, keys, tmp, counts, tile_out, tile_dist,
+      check(c, launch_big_tiles(s, kc, tiles, big, big_off, big_order, big_fail, &misc->n_big,
+                                &misc->big_next, &misc->n_fail, &misc->fail_next, n_tiles,
+                                stream_big, keys, tmp, counts, tile_out, tile_dist,
                                 &misc->big_out),
             "big_tiles");
     }
@@ -1017,7 +1031,7 @@ WsLayout plan_workspace(const kmc_reads* R, const kmc_params* P) {
   sz[B_KEYS] = kmax * kw * 8;
   sz[B_COUNTS] = kmax * 4;
   sz[B_TILEOUT] = tmax * 8 + 8;
-  sz[B_BIG] = tmax * 16 + 16;
+  sz[B_BIG] = tmax * 20 + 16;
   sz[B_MISC] = sizeof(Misc);
   sz[B_TMP] = kmax * kw * 8;
   sz[B_SCANTMP] = scan_tmp_words(tmax) * 8;

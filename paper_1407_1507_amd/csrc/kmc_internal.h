@@ -168,14 +168,21 @@ hipError_t launch_tile_sort(hipStream_t s, const KeyCfg& kc, const Tile* tiles,
                             uint32_t* tile_distinct);
 
 // Sort + count the big tiles: MSD partition through HBM, each tile
-// ping-ponging between its keys and its own slice tmp[big_off[i] ...].  The
-// number of big tiles is read on the device (*n_big, final once the tile
-// kernel has run); workgroups take tiles from the counter *next (zero at
-// launch).  max_big bounds *n_big (the grid never exceeds it).  *big_out
-// accumulates the entries the big tiles keep.
+// ping-ponging between its keys and its own slice tmp[big_off[i] ...]; for
+// 64-bit keys each big tile is first streamed through the LDS hash table and
+// partitioned only if it has too many distinct keys; with stream_first that
+// pass is a kernel of its own (more workgroups per compute unit) that lists
+// the failures in fail_list for the partition kernel.  The number of big tiles is read on the device (*n_big, final
+// once the tile kernel has run); workgroups take tiles from the counters
+// *next and *fail_next, and the failures are counted in *n_fail (all three
+// zero at launch).  order and fail_list hold max_big entries; max_big bounds
+// *n_big (the grids never exceed it).  *big_out accumulates the entries the
+// big tiles keep.
 hipError_t launch_big_tiles(hipStream_t s, const KeyCfg& kc, const Tile* tiles,
                             const uint32_t* big_list, const uint64_t* big_off, uint32_t* order,
-                            const uint32_t* n_big, uint32_t* next, uint64_t max_big,
+                            uint32_t* fail_list, const uint32_t* n_big, uint32_t* next,
+                            uint32_t* n_fail, uint32_t* fail_next, uint64_t max_big,
+                            bool stream_first,
                             uint64_t* keys, uint64_t* tmp, uint32_t* out_counts,
                             uint32_t* tile_out, uint32_t* tile_distinct,
                             unsigned long long* big_out);

@@ -1064,8 +1064,10 @@ struct Level {
 };
 template <int KW> struct MaxLevels { static constexpr int N = KW == 1 ? 10 : 18; };
 
-// One big tile, by the whole workgroup.
-template <int KW>
+// One big tile, by the whole workgroup.  kStream (64-bit keys): the tile is
+// first streamed through the LDS hash table, and partitioned only if it holds
+// too many distinct keys.
+template <int KW, bool kStream>
 __device__ void big_tile(const KeyCfg& kc, const Tile* __restrict__ tiles, uint32_t t,
                          uint64_t tmp_off, uint64_t* keys, uint64_t* tmp, uint32_t* counts,
                          uint32_t* tile_out, uint32_t* tile_distinct,
@@ -1077,8 +1079,7 @@ __device__ void big_tile(const KeyCfg& kc, const Tile* __restrict__ tiles, uint3
   __shared__ unsigned long long outc, dist;
   const uint32_t tid = threadIdx.x, nt = blockDim.x;
   const Tile T = tiles[t];
-  if constexpr (KW == 1) {
-    // few distinct keys: one streamed pass through the hash table
+  if constexpr (KW == 1 && kStream) {
     __shared__ uint32_t claims;
     uint32_t d, kept;
     if (stream_count_hash(keys + T.begin, T.size, keys + T.begin, counts + T.begin,
@@ -1194,15 +1195,42 @@ __device__ void big_tile(const KeyCfg& kc, const Tile* __restrict__ tiles, uint3
   __syncthreads();
 }
 
-// Persistent: workgroups take big tiles from a counter until none is left.
-template <int KW>
+// Persistent: workgroups take big tiles from a counter until none is left;
+// item it of the work is big tile list[it] (an index into big_list /
+// big_off), for it < *n_items.
+template <int KW, bool kStream>
 __global__ void __launch_bounds__(kSortThreads)
 k_big_tiles(KeyCfg kc, const Tile* __restrict__ tiles, const uint32_t* __restrict__ big_list,
-            const uint64_t* __restrict__ big_off, const uint32_t* __restrict__ order,
-            const uint32_t* n_big, uint32_t* next, uint64_t* keys, uint64_t* tmp,
+            const uint64_t* __restrict__ big_off, const uint32_t* __restrict__ list,
+            const uint32_t* n_items, uint32_t* next, uint64_t* keys, uint64_t* tmp,
             uint32_t* counts, uint32_t* tile_out, uint32_t* tile_distinct,
             unsigned long long* big_out) {
   __shared__ uint32_t item;
+  const uint32_t nb = *n_items;
+  for (;;) {
+    if (threadIdx.x == 0) item = atomicAdd(next, 1u);
+    __syncthreads();
+    const uint32_t it = item;
+    __syncthreads();
+    if (it >= nb) return;
+    const uint32_t j = list[it];
+    big_tile<KW, kStream>(kc, tiles, big_list[j], big_off[j], keys, tmp, counts, tile_out,
+                          tile_distinct, big_out);
+  }
+}
+
+// Big tiles of 64-bit keys, first pass: each is streamed through the LDS
+// hash table (stream_count_hash); those with more distinct keys than the
+// table takes are listed in fail_list for k_big_tiles.  A kernel of its own,
+// so that its registers allow two workgroups per compute unit (the kernel
+// that does both allows one).
+__global__ void __launch_bounds__(kSortThreads)
+k_big_stream(KeyCfg kc, const Tile* __restrict__ tiles, const uint32_t* __restrict__ big_list,
+             const uint32_t* __restrict__ order, const uint32_t* n_big, uint32_t* next,
+             uint64_t* keys, uint32_t* counts, uint32_t* tile_out, uint32_t* tile_distinct,
+             unsigned long long* big_out, uint32_t* fail_list, uint32_t* n_fail) {
+  __shared__ SortShared<1> S;
+  __shared__ uint32_t item, claims;
   const uint32_t nb = *n_big;
   for (;;) {
     if (threadIdx.x == 0) item = atomicAdd(next, 1u);
@@ -1210,9 +1238,21 @@ k_big_tiles(KeyCfg kc, const Tile* __restrict__ tiles, const uint32_t* __restric
     const uint32_t it = item;
     __syncthreads();
     if (it >= nb) return;
-    const uint32_t j = order[it];
-    big_tile<KW>(kc, tiles, big_list[j], big_off[j], keys, tmp, counts, tile_out,
-                 tile_distinct, big_out);
+    const uint32_t j = order[it], t = big_list[j];
+    const Tile T = tiles[t];
+    uint32_t d, kept;
+    const bool ok = stream_count_hash(keys + T.begin, T.size, keys + T.begin, counts + T.begin,
+                                      kc.cutoff_min, kc.cutoff_max, S, &claims, &d, &kept);
+    if (threadIdx.x == 0) {
+      if (ok) {
+        tile_out[t] = kept;
+        tile_distinct[t] = d;
+        atomicAdd(big_out, (unsigned long long)kept);
+      } else {
+        fail_list[atomicAdd(n_fail, 1u)] = j;
+      }
+    }
+    __syncthreads();  // the table is set up again for the next tile
   }
 }
 
@@ -1499,7 +1539,7 @@ k_group_sort(const uint64_t* __restrict__ lo, uint64_t* xk, uint32_t* xc, uint64
 // device: compute units x blocks per unit (by occupancy), cached per
 // (kernel slot, device).
 static int resident_blocks(const void* kernel, int slot) {
-  constexpr int kSlots = 4, kDevs = 16;
+  constexpr int kSlots = 6, kDevs = 16;
   static std::atomic<int> cache[kSlots][kDevs];
   int dev = 0;
   (void)hipGetDevice(&dev);
@@ -1539,25 +1579,37 @@ hipError_t launch_tile_sort(hipStream_t s, const KeyCfg& kc, const Tile* tiles,
 
 hipError_t launch_big_tiles(hipStream_t s, const KeyCfg& kc, const Tile* tiles,
                             const uint32_t* big_list, const uint64_t* big_off, uint32_t* order,
-                            const uint32_t* n_big, uint32_t* next, uint64_t max_big,
-                            uint64_t* keys, uint64_t* tmp, uint32_t* out_counts,
-                            uint32_t* tile_out, uint32_t* tile_distinct,
+                            uint32_t* fail_list, const uint32_t* n_big, uint32_t* next,
+                            uint32_t* n_fail, uint32_t* fail_next, uint64_t max_big,
+                            bool stream_first, uint64_t* keys, uint64_t* tmp,
+                            uint32_t* out_counts, uint32_t* tile_out, uint32_t* tile_distinct,
                             unsigned long long* big_out) {
   if (max_big == 0) return hipSuccess;
   hipLaunchKernelGGL(k_order_big, dim3(1), dim3(1024), 0, s, tiles, big_list, n_big, order);
-  const int kw = kc.key_words == 1 ? 1 : 2;
-  const uint32_t grid = (uint32_t)std::min<uint64_t>(
-      max_big, (uint64_t)resident_blocks(kw == 1 ? (const void*)k_big_tiles<1>
-                                                 : (const void*)k_big_tiles<2>,
-                                         1 + kw));
-  if (kw == 1)
-    hipLaunchKernelGGL(k_big_tiles<1>, dim3(grid), dim3(kSortThreads), 0, s, kc, tiles,
+  if (kc.key_words == 1 && !stream_first) {
+    const uint32_t grid = (uint32_t)std::min<uint64_t>(
+        max_big, (uint64_t)resident_blocks((const void*)k_big_tiles<1, true>, 5));
+    hipLaunchKernelGGL((k_big_tiles<1, true>), dim3(grid), dim3(kSortThreads), 0, s, kc, tiles,
                        big_list, big_off, order, n_big, next, keys, tmp, out_counts, tile_out,
                        tile_distinct, big_out);
-  else
-    hipLaunchKernelGGL(k_big_tiles<2>, dim3(grid), dim3(kSortThreads), 0, s, kc, tiles,
+  } else if (kc.key_words == 1) {
+    const uint32_t gs = (uint32_t)std::min<uint64_t>(
+        max_big, (uint64_t)resident_blocks((const void*)k_big_stream, 4));
+    hipLaunchKernelGGL(k_big_stream, dim3(gs), dim3(kSortThreads), 0, s, kc, tiles, big_list,
+                       order, n_big, next, keys, out_counts, tile_out, tile_distinct, big_out,
+                       fail_list, n_fail);
+    const uint32_t grid = (uint32_t)std::min<uint64_t>(
+        max_big, (uint64_t)resident_blocks((const void*)k_big_tiles<1, false>, 2));
+    hipLaunchKernelGGL((k_big_tiles<1, false>), dim3(grid), dim3(kSortThreads), 0, s, kc, tiles,
+                       big_list, big_off, fail_list, n_fail, fail_next, keys, tmp, out_counts,
+                       tile_out, tile_distinct, big_out);
+  } else {
+    const uint32_t grid = (uint32_t)std::min<uint64_t>(
+        max_big, (uint64_t)resident_blocks((const void*)k_big_tiles<2, false>, 3));
+    hipLaunchKernelGGL((k_big_tiles<2, false>), dim3(grid), dim3(kSortThreads), 0, s, kc, tiles,
                        big_list, big_off, order, n_big, next, keys, tmp, out_counts, tile_out,
                        tile_distinct, big_out);
+  }
   return hipGetLastError();
 }
 
