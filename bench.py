@@ -617,6 +617,10 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--order", choices=["bin", "ascending"], default="bin",
                     help="table order: grouped by bin, or ascending over the whole table")
+    ap.add_argument("--input-cache", default="",
+                    help="folder holding the generated read sets (made on first use)")
+    ap.add_argument("--generate-only", action="store_true",
+                    help="with --input-cache: only write the read sets")
     ap.add_argument("--copy-calibration", type=int, default=0,
                     help="only run a device copy of this many bytes (counter calibration)")
     args = ap.parse_args()
@@ -637,7 +641,12 @@ def main():
 
     import torch
 
-    line, data = bench_single(args.workload, args.steps, args.warmup, args.order)
+    if args.input_cache and args.generate_only:
+        for w in [args.workload] + list(args.also):
+            load_workload(w, args.input_cache)
+        return
+    line, data = bench_single(args.workload, args.steps, args.warmup, args.order,
+                              args.input_cache)
     line["roofline"]["copy_peak_gbs"] = copy_peak()
     line["roofline"]["frac_vs_copy"] = line["roofline"]["achieved"] / line["roofline"]["copy_peak_gbs"]
     line["job_roofline"]["frac_vs_copy"] = (line["job_roofline"]["achieved"] /
@@ -647,7 +656,7 @@ def main():
     for w in args.also:
         if w == args.workload:
             continue
-        other, _ = bench_single(w, max(3, min(args.steps, 5)), 1, args.order)
+        other, _ = bench_single(w, max(3, min(args.steps, 5)), 1, args.order, args.input_cache)
         also[w] = {key: other[key] for key in ("value", "unit", "ms_per_step", "kmers_per_s",
                                                "device_ms", "hbm_gbs_alg", "job_roofline",
                                                "roofline", "kernel_us", "job", "config")}
@@ -659,13 +668,31 @@ def main():
     print(json.dumps(line), flush=True)
 
 
-def bench_single(workload: str, steps: int, warmup: int, order: str):
+def load_workload(workload: str, cache: str = ""):
+    """The named synthetic read set; with a cache folder, taken from (or saved
+    to) <cache>/<workload>.seq.npy and .off.npy, so that a profiler run need
+    not generate it (the large set's parallel generator under a counter
+    profiler profiles every worker process)."""
+    from paper_1407_1507_amd import synth
+
+    fs, fo = (os.path.join(cache, f"{workload}.{x}.npy") for x in ("seq", "off"))
+    if cache and os.path.exists(fs) and os.path.exists(fo):
+        return np.load(fs), np.load(fo), dict(synth.CONFIGS[workload])
+    seq, off, p = synth.make(workload)
+    if cache:
+        os.makedirs(cache, exist_ok=True)
+        np.save(fs, seq)
+        np.save(fo, off)
+    return seq, off, p
+
+
+def bench_single(workload: str, steps: int, warmup: int, order: str, input_cache: str = ""):
     """One job per step on one read set resident in HBM; returns the bench
     line (without the CPU baseline) and the read set."""
     import torch
     from paper_1407_1507_amd import kmc, synth
 
-    seq, off, p = synth.make(workload)
+    seq, off, p = load_workload(workload, input_cache)
     print(f"generated {workload}: {seq.size} bases", file=sys.stderr, flush=True)
     dseq = torch.from_numpy(seq).to("cuda:0")
     doff = torch.from_numpy(off.view(np.int64)).to("cuda:0")

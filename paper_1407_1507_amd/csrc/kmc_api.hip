@@ -771,7 +771,7 @@ void run_count(kmc_ctx* c, const kmc_reads* R, const kmc_params* P, kmc_table* T
     uint32_t* counts = ensure<uint32_t>(c, B_COUNTS, gk * 4);
     kbeg(c, KMC_K_EXPAND, s);
     check(c, launch_expand_scatter(s, kc, emap, (uint32_t)n_etasks, grec, tof, d_tile_base,
-                                   (uint32_t)max_tiles, tcur, keys), "expand");
+                                   d_key_base, (uint32_t)max_tiles, tcur, keys), "expand");
     kend(c, KMC_K_EXPAND, s);
     check(c, hipEventRecord(c->ev[3], s), "event");
 

@@ -14,6 +14,8 @@
 // Record layout (written by the split kernels): forward key of the first
 // k-mer, then the remaining symbols left aligned with the k-mer count in the
 // low 8 bits.  Keys are rolled forward and reverse-complement at once.
+#include <type_traits>
+
 #include "kmc_device.h"
 #include "kmc_internal.h"
 
@@ -301,14 +303,20 @@ template <int KW>
 __global__ void __launch_bounds__(kExpandThreads)
 k_expand_scatter(KeyCfg kc, TaskMap tm,
                  const uint64_t* __restrict__ records, const uint16_t* __restrict__ tile_of_fine,
-                 const uint64_t* __restrict__ tile_base, uint32_t mt, uint32_t n_tasks,
-                 unsigned long long* tile_cursor, uint64_t* keys) {
+                 const uint64_t* __restrict__ tile_base, const uint64_t* __restrict__ key_base,
+                 uint32_t mt, uint32_t n_tasks, unsigned long long* tile_cursor,
+                 uint64_t* keys) {
   typedef typename KeyOf<KW>::T K;
+  // a tile's reserved start: for 64-bit keys 32 bits relative to the bin's
+  // first key (a bin holds fewer than 2^32), so the per-tile arrays take 8
+  // bytes a tile and bins of thousands of tiles leave room for more
+  // workgroups; 128-bit keys keep 64 bits (measured faster there)
+  typedef typename std::conditional<KW == 1, uint32_t, uint64_t>::type Off;
   extern __shared__ __attribute__((aligned(16))) uint64_t lds64[];
   const uint32_t nf = 1u << kc.fine_bits;
-  // layout: round records | delta u64[mt] | cnt u32[mt] | tof u16[nf]
+  // layout: round records | delta Off[mt] | cnt u32[mt] | tof u16[nf]
   RoundLds<KW>& L = *reinterpret_cast<RoundLds<KW>*>(lds64);
-  uint64_t* delta = reinterpret_cast<uint64_t*>(&L + 1);
+  Off* delta = reinterpret_cast<Off*>(&L + 1);
   uint32_t* cnt = reinterpret_cast<uint32_t*>(delta + mt);
   uint16_t* tof = reinterpret_cast<uint16_t*>(cnt + mt);
 
@@ -322,6 +330,7 @@ k_expand_scatter(KeyCfg kc, TaskMap tm,
   for (uint32_t i = threadIdx.x; i < nf; i += blockDim.x) tof[i] = gt[i];
   const uint64_t tb = tile_base[tk.bin];
   const uint32_t nt = (uint32_t)(tile_base[tk.bin + 1] - tb);  // <= mt
+  const uint64_t kb = KW == 1 ? key_base[tk.bin] : 0;
   for (uint32_t i = threadIdx.x; i < nt; i += blockDim.x) cnt[i] = 0;
   const K kmask = key_mask<K>(kc.k);
   const bool canon = kc.canonical != 0;
@@ -342,7 +351,7 @@ k_expand_scatter(KeyCfg kc, TaskMap tm,
     for (uint32_t i = 0;; ++i) {
       const K key = rec.key();
       const uint32_t t = tof[top_bits(key, kc.k, kc.fine_bits)];
-      const uint64_t g = delta[t] + atomicAdd(&cnt[t], 1u);
+      const uint64_t g = kb + delta[t] + atomicAdd(&cnt[t], 1u);
       if (KW == 1) {
         keys[g] = (uint64_t)key;
       } else {
@@ -357,7 +366,7 @@ k_expand_scatter(KeyCfg kc, TaskMap tm,
   auto reserve = [&]() {
     for (uint32_t i = threadIdx.x; i < nt; i += blockDim.x) {
       const uint32_t c = cnt[i];
-      if (c) delta[i] = atomicAdd(&tile_cursor[tb + i], (unsigned long long)c);
+      if (c) delta[i] = (Off)(atomicAdd(&tile_cursor[tb + i], (unsigned long long)c) - kb);
       cnt[i] = 0;
     }
   };
@@ -397,7 +406,7 @@ static size_t round_lds(int kw) {
   return kw == 1 ? sizeof(RoundLds<1>) : sizeof(RoundLds<2>);
 }
 static size_t expand_lds(int kw, uint32_t mt, uint32_t nf) {
-  return round_lds(kw) + (size_t)mt * 12 + (size_t)nf * 2;
+  return round_lds(kw) + (size_t)mt * (kw == 1 ? 8 : 12) + (size_t)nf * 2;
 }
 
 hipError_t launch_task_bins(hipStream_t s, uint32_t n_bins, const uint64_t* pre_a,
@@ -435,7 +444,7 @@ hipError_t launch_plan_tiles(hipStream_t s, const KeyCfg& kc, const uint32_t* fi
 hipError_t launch_expand_scatter(hipStream_t s, const KeyCfg& kc, const TaskMap& tm,
                                  uint32_t n_tasks, const uint64_t* records,
                                  const uint16_t* tile_of_fine, const uint64_t* tile_base,
-                                 uint32_t max_tiles_per_bin,
+                                 const uint64_t* key_base, uint32_t max_tiles_per_bin,
                                  unsigned long long* tile_cursor, uint64_t* keys) {
   if (n_tasks == 0) return hipSuccess;
   const uint32_t nf = 1u << kc.fine_bits;
@@ -446,12 +455,12 @@ hipError_t launch_expand_scatter(hipStream_t s, const KeyCfg& kc, const TaskMap&
     (void)hipFuncSetAttribute((const void*)k_expand_scatter<1>,
                         hipFuncAttributeMaxDynamicSharedMemorySize, (int)sh);
     hipLaunchKernelGGL(k_expand_scatter<1>, dim3(grid), dim3(kExpandThreads), sh, s, kc,
-                       tm, records, tile_of_fine, tile_base, mt, n_tasks, tile_cursor, keys);
+                       tm, records, tile_of_fine, tile_base, key_base, mt, n_tasks, tile_cursor, keys);
   } else {
     (void)hipFuncSetAttribute((const void*)k_expand_scatter<2>,
                         hipFuncAttributeMaxDynamicSharedMemorySize, (int)sh);
     hipLaunchKernelGGL(k_expand_scatter<2>, dim3(grid), dim3(kExpandThreads), sh, s, kc,
-                       tm, records, tile_of_fine, tile_base, mt, n_tasks, tile_cursor, keys);
+                       tm, records, tile_of_fine, tile_base, key_base, mt, n_tasks, tile_cursor, keys);
   }
   return hipGetLastError();
 }

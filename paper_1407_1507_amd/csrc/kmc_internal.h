@@ -153,7 +153,7 @@ hipError_t launch_plan_tiles(hipStream_t s, const KeyCfg& kc, const uint32_t* fi
 hipError_t launch_expand_scatter(hipStream_t s, const KeyCfg& kc, const TaskMap& tm,
                                  uint32_t n_tasks, const uint64_t* records,
                                  const uint16_t* tile_of_fine, const uint64_t* tile_base,
-                                 uint32_t max_tiles_per_bin,
+                                 const uint64_t* key_base, uint32_t max_tiles_per_bin,
                                  unsigned long long* tile_cursor, uint64_t* keys);
 
 // Sort + count every tile that fits LDS.  Output of a tile is written over

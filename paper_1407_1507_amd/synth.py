@@ -182,8 +182,8 @@ CONFIGS = {
     "uniform-10k": dict(k=28, p=7, n_bins=512, cutoff_min=1, cutoff_max=10**9),
     "genome-5M-2Mx100": dict(k=28, p=7, n_bins=512, cutoff_min=2, cutoff_max=10**9),
     "repeats-50M-30x150-k55": dict(k=55, p=9, n_bins=1024, cutoff_min=2, cutoff_max=10**6),
-    # the served form's large job; 2048 bins keep bins near 3.5M keys, which
-    # 2^12 fine ranges split into LDS tiles (512 bins would leave 14M)
+    # the served form's large job: 3.5M keys per bin on average at 2048 bins,
+    # but the most frequent signatures alone hold up to 19M each
     "large-300M-60Mx150": dict(k=28, p=7, n_bins=2048, cutoff_min=2, cutoff_max=10**9),
 }
 
