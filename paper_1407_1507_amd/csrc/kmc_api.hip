@@ -781,17 +781,22 @@ void run_count(kmc_ctx* c, const kmc_reads* R, const kmc_params* P, kmc_table* T
     uint32_t* big = ensure<uint32_t>(c, B_BIG, n_tiles * 20 + 16);
     uint64_t* big_off = reinterpret_cast<uint64_t*>(big + ((n_tiles + 1) & ~1ull));
     uint32_t* big_order = reinterpret_cast<uint32_t*>(big_off + n_tiles);
-    uint32_t* big_fail = big_order + n_tiles;
+    // the big tiles' sizes, read once to order them; the same words then hold
+    // the list of big tiles left to the partition kernel
+    uint32_t* big_size = big_order + n_tiles;
+    uint32_t* big_fail = big_size;
     kbeg(c, KMC_K_TILE_SORT, s);
     check(c, launch_tile_sort(s, kc, tiles, n_tiles, keys, counts, tile_out, big, big_off,
-                              &misc->n_big, &misc->big_total, tile_dist), "tile_sort");
+                              &misc->n_big, &misc->big_total, tile_dist, big_size),
+          "tile_sort");
     kend(c, KMC_K_TILE_SORT, s);
     // big tiles: their number stays on the device (no round trip); scratch
     // for their partition passes is sized for every key of the group
     kbeg(c, KMC_K_BIG_TILES, s);
     {
       uint64_t* tmp = ensure<uint64_t>(c, B_TMP, std::max<uint64_t>(1, gk) * J.kw * 8);
-      check(c, launch_big_tiles(s, kc, tiles, big, big_off, big_order, big_fail, &misc->n_big,
+      check(c, launch_big_tiles(s, kc, tiles, big, big_off, big_size, big_order, big_fail,
+                                &misc->n_big,
                                 &misc->big_next, &misc->n_fail, &misc->fail_next, n_tiles,
                                 stream_big, keys, tmp, counts, tile_out, tile_dist,
                                 &misc->big_out),

@@ -159,13 +159,13 @@ hipError_t launch_expand_scatter(hipStream_t s, const KeyCfg& kc, const TaskMap&
 // Sort + count every tile that fits LDS.  Output of a tile is written over
 // its own keys (out_counts at the same indices); tile_out[t] = entries kept,
 // tile_distinct[t] = distinct keys of tile t.  Tiles larger than LDS are appended to
-// big_list (count in n_big[0]) with a private slice of the HBM scratch at
-// big_off (its size summed into big_total).
+// big_list (count in n_big[0]) with their size in big_size and a private
+// slice of the HBM scratch at big_off (its size summed into big_total).
 hipError_t launch_tile_sort(hipStream_t s, const KeyCfg& kc, const Tile* tiles,
                             uint64_t n_tiles, uint64_t* keys, uint32_t* out_counts,
                             uint32_t* tile_out, uint32_t* big_list, uint64_t* big_off,
                             uint32_t* n_big, unsigned long long* big_total,
-                            uint32_t* tile_distinct);
+                            uint32_t* tile_distinct, uint32_t* big_size);
 
 // Sort + count the big tiles: MSD partition through HBM, each tile
 // ping-ponging between its keys and its own slice tmp[big_off[i] ...]; for
@@ -179,7 +179,8 @@ hipError_t launch_tile_sort(hipStream_t s, const KeyCfg& kc, const Tile* tiles,
 // *n_big (the grids never exceed it).  *big_out accumulates the entries the
 // big tiles keep.
 hipError_t launch_big_tiles(hipStream_t s, const KeyCfg& kc, const Tile* tiles,
-                            const uint32_t* big_list, const uint64_t* big_off, uint32_t* order,
+                            const uint32_t* big_list, const uint64_t* big_off,
+                            const uint32_t* big_size, uint32_t* order,
                             uint32_t* fail_list, const uint32_t* n_big, uint32_t* next,
                             uint32_t* n_fail, uint32_t* fail_next, uint64_t max_big,
                             bool stream_first,

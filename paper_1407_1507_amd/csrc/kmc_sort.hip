@@ -849,7 +849,8 @@ template <int KW>
 __global__ void __launch_bounds__(kSortThreads, 3)  // 3 waves per SIMD: as many as LDS allows
 k_tile_sort(KeyCfg kc, const Tile* __restrict__ tiles, uint64_t n_tiles, uint64_t* keys,
             uint32_t* counts, uint32_t* tile_out, uint32_t* big_list, uint64_t* big_off,
-            uint32_t* n_big, unsigned long long* big_total, uint32_t* tile_distinct) {
+            uint32_t* n_big, unsigned long long* big_total, uint32_t* tile_distinct,
+            uint32_t* big_size) {
   typedef typename KeyOf<KW>::T K;
   constexpr uint32_t ITEMS = SortCfg<KW>::ITEMS, CAP = SortCfg<KW>::CAP;
   __shared__ SortShared<KW> S;
@@ -882,6 +883,7 @@ k_tile_sort(KeyCfg kc, const Tile* __restrict__ tiles, uint64_t n_tiles, uint64_
         tile_out[t] = tile_distinct[t] = 0;
         const uint32_t idx = atomicAdd(n_big, 1u);
         big_list[idx] = (uint32_t)t;
+        big_size[idx] = T.size;
         big_off[idx] = atomicAdd(big_total, (unsigned long long)T.size);  // own slice of tmp
       }
     } else {
@@ -902,7 +904,8 @@ k_tile_sort(KeyCfg kc, const Tile* __restrict__ tiles, uint64_t n_tiles, uint64_
 __global__ void __launch_bounds__(kSortThreads, 3)
 k_tile_hash2(KeyCfg kc, const Tile* __restrict__ tiles, uint64_t n_tiles, uint64_t* keys,
              uint32_t* counts, uint32_t* tile_out, uint32_t* big_list, uint64_t* big_off,
-             uint32_t* n_big, unsigned long long* big_total, uint32_t* tile_distinct) {
+             uint32_t* n_big, unsigned long long* big_total, uint32_t* tile_distinct,
+            uint32_t* big_size) {
   constexpr uint32_t ITEMS = SortCfg<2>::ITEMS;
   __shared__ HashShared2 S;
   for (uint32_t i = threadIdx.x; i < kHashSlots2; i += blockDim.x) S.F[i] = 0;
@@ -936,6 +939,7 @@ k_tile_hash2(KeyCfg kc, const Tile* __restrict__ tiles, uint64_t n_tiles, uint64
         tile_out[t] = tile_distinct[t] = 0;
         const uint32_t idx = atomicAdd(n_big, 1u);
         big_list[idx] = (uint32_t)t;
+        big_size[idx] = T.size;
         big_off[idx] = atomicAdd(big_total, (unsigned long long)T.size);
       } else {
         tile_out[t] = kept;
@@ -1266,19 +1270,19 @@ __device__ __forceinline__ uint32_t size_class(uint32_t size) {
   const uint32_t q = (size >> (l - 2)) & 3u;           // next two bits
   return kSizeClasses - 1u - min(4u * l + q, kSizeClasses - 1u);  // largest -> 0
 }
+// big_size[i] = size of big tile i (written beside big_list, so the reads
+// here are sequential).
 __global__ void __launch_bounds__(1024)
-k_order_big(const Tile* __restrict__ tiles, const uint32_t* __restrict__ big_list,
-            const uint32_t* n_big, uint32_t* order) {
+k_order_big(const uint32_t* __restrict__ big_size, const uint32_t* n_big, uint32_t* order) {
   __shared__ uint32_t cnt[kSizeClasses], tmp[16];
   const uint32_t nb = *n_big, tid = threadIdx.x;
   for (uint32_t i = tid; i < kSizeClasses; i += blockDim.x) cnt[i] = 0;
   __syncthreads();
-  for (uint32_t i = tid; i < nb; i += blockDim.x)
-    atomicAdd(&cnt[size_class(tiles[big_list[i]].size)], 1u);
+  for (uint32_t i = tid; i < nb; i += blockDim.x) atomicAdd(&cnt[size_class(big_size[i])], 1u);
   __syncthreads();
   block_exclusive_scan(cnt, kSizeClasses, tmp);
   for (uint32_t i = tid; i < nb; i += blockDim.x)
-    order[atomicAdd(&cnt[size_class(tiles[big_list[i]].size)], 1u)] = i;
+    order[atomicAdd(&cnt[size_class(big_size[i])], 1u)] = i;
 }
 
 // ---------------------------------------------------------------- scans
@@ -1558,7 +1562,7 @@ hipError_t launch_tile_sort(hipStream_t s, const KeyCfg& kc, const Tile* tiles,
                             uint64_t n_tiles, uint64_t* keys, uint32_t* out_counts,
                             uint32_t* tile_out, uint32_t* big_list, uint64_t* big_off,
                             uint32_t* n_big, unsigned long long* big_total,
-                            uint32_t* tile_distinct) {
+                            uint32_t* tile_distinct, uint32_t* big_size) {
   if (n_tiles == 0) return hipSuccess;
   // persistent grid: exactly the workgroups that are resident at once
   const int kw = kc.key_words == 1 ? 1 : 2;
@@ -1569,23 +1573,24 @@ hipError_t launch_tile_sort(hipStream_t s, const KeyCfg& kc, const Tile* tiles,
   if (kc.key_words == 1)
     hipLaunchKernelGGL(k_tile_sort<1>, dim3(grid), dim3(kSortThreads), 0, s, kc,
                        tiles, n_tiles, keys, out_counts, tile_out, big_list, big_off, n_big, big_total,
-                       tile_distinct);
+                       tile_distinct, big_size);
   else
     hipLaunchKernelGGL(k_tile_hash2, dim3(grid), dim3(kSortThreads), 0, s, kc,
                        tiles, n_tiles, keys, out_counts, tile_out, big_list, big_off, n_big, big_total,
-                       tile_distinct);
+                       tile_distinct, big_size);
   return hipGetLastError();
 }
 
 hipError_t launch_big_tiles(hipStream_t s, const KeyCfg& kc, const Tile* tiles,
-                            const uint32_t* big_list, const uint64_t* big_off, uint32_t* order,
+                            const uint32_t* big_list, const uint64_t* big_off,
+                            const uint32_t* big_size, uint32_t* order,
                             uint32_t* fail_list, const uint32_t* n_big, uint32_t* next,
                             uint32_t* n_fail, uint32_t* fail_next, uint64_t max_big,
                             bool stream_first, uint64_t* keys, uint64_t* tmp,
                             uint32_t* out_counts, uint32_t* tile_out, uint32_t* tile_distinct,
                             unsigned long long* big_out) {
   if (max_big == 0) return hipSuccess;
-  hipLaunchKernelGGL(k_order_big, dim3(1), dim3(1024), 0, s, tiles, big_list, n_big, order);
+  hipLaunchKernelGGL(k_order_big, dim3(1), dim3(1024), 0, s, big_size, n_big, order);
   if (kc.key_words == 1 && !stream_first) {
     const uint32_t grid = (uint32_t)std::min<uint64_t>(
         max_big, (uint64_t)resident_blocks((const void*)k_big_tiles<1, true>, 5));
