@@ -97,6 +97,21 @@ typedef struct kmc_params {
  * as two keys.  Bins are unchanged (the signature of a k-mer and of its
  * reverse complement are the same). */
 #define KMC_FLAG_NON_CANONICAL 0x8u
+/* (k,x)-mers (Methods, "(k,x)-mers" and the counting from sorted (k,x)-mers
+ * that follows Fig. 2): each super k-mer is cut into the fewest (k + x')-mers,
+ * x' <= x, whose k-mers are all canonical in the same direction (a piece grows
+ * while the next k-mer has the direction of its first and it holds at most
+ * x + 1 k-mers; a k-mer is forward when it is not larger than its reverse
+ * complement), each stored in the direction that makes its k-mers canonical.
+ * These are sorted and run-length counted per bin, and the k-mer counts are
+ * taken from the distinct (k,x)-mers, each of whose k-mers counts as many
+ * times as the (k,x)-mer occurs.  The table is the same as without the flag.
+ * x = 1..3 in bits 4-5 (KMC_FLAG_KX(x)); needs canonical k-mers and
+ * k + x <= 31; not available with a caller workspace (kmc_count_ws,
+ * kmc_count_static) or a memory budget that splits the job into bin groups
+ * (KMC_ERR_INVALID_ARG). */
+#define KMC_FLAG_KX(x) (((uint32_t)(x) & 3u) << 4)
+#define KMC_FLAG_KX_MASK 0x30u
 /* Test only.  Tiles of 128-bit keys (k > 32) are counted in an LDS hash table
  * whose slots are claimed by a 47-bit fingerprint of the key; a tile where two
  * different keys share a fingerprint is detected and counted by the exact
@@ -138,6 +153,9 @@ typedef struct kmc_stats {
                               memory budget splits the job) */
   uint64_t records_spilled; /* 1 if the super k-mer records went to pinned
                                host memory (memory budget) */
+  uint64_t n_kx_entries;   /* KMC_FLAG_KX: (k,x)-mers sorted (Table 7's sorted
+                              fraction is n_kx_entries / n_kmers); else 0 */
+  uint64_t n_kx_distinct;  /* KMC_FLAG_KX: distinct (k,x)-mers; else 0 */
   double us_map;           /* device time of each phase, microseconds */
   double us_split;
   double us_expand;

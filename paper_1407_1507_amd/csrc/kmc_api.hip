@@ -30,6 +30,7 @@ enum BufId {
   B_SEQ, B_OFF, B_HIST, B_MAP, B_BINCNT, B_CURSOR, B_REC, B_FINE, B_TOF, B_TILES, B_TCUR,
   B_BASES, B_HTASK, B_ETASK, B_KEYS, B_COUNTS, B_TILEOUT, B_BIG, B_MISC, B_TMP, B_SCANTMP,
   B_TILEOFF, B_BINOFF, B_OUTK, B_OUTC, B_DBG1, B_DBG2, B_ASCSEG, B_ASCK, B_ASCC, B_STAGE,
+  B_KXK, B_KXC, B_KXR, B_TMPW,
   B_AUX0, B_COUNT_ = B_AUX0 + kmc::kCtxAuxBuffers
 };
 
@@ -64,7 +65,7 @@ struct WsLayout {
 
 // Pinned host buffers for the small transfers between the phases (plans,
 // counters, histograms), cached like the device buffers.
-enum HostId { H_HIST, H_CNT, H_BASES, H_MISC, H_BINOFF, H_MAP, H_COUNT_ };
+enum HostId { H_HIST, H_CNT, H_BASES, H_MISC, H_BINOFF, H_MAP, H_KX, H_COUNT_ };
 
 struct kmc_ctx {
   int device = 0;
@@ -388,8 +389,10 @@ kmc_status validate(const kmc_reads* reads, const kmc_params* P) {
   if (P->n_bins < 1 || P->n_bins > 65535 || P->n_bins > n_sig) return KMC_ERR_INVALID_ARG;
   if (P->cutoff_min > P->cutoff_max) return KMC_ERR_INVALID_ARG;
   if (P->flags & ~(KMC_FLAG_DEVICE_TABLE | KMC_FLAG_PLAIN_MINIMIZERS | KMC_FLAG_ASCENDING |
-                   KMC_FLAG_NON_CANONICAL | KMC_FLAG_TEST_NARROW_FINGERPRINT))
+                   KMC_FLAG_NON_CANONICAL | KMC_FLAG_TEST_NARROW_FINGERPRINT | KMC_FLAG_KX_MASK))
     return KMC_ERR_INVALID_ARG;
+  const uint32_t kx = (P->flags & KMC_FLAG_KX_MASK) >> 4;
+  if (kx && ((P->flags & KMC_FLAG_NON_CANONICAL) || P->k + kx > 31)) return KMC_ERR_INVALID_ARG;
   if (reads->n_reads > 0 && (!reads->seq && reads->n_bases > 0)) return KMC_ERR_INVALID_ARG;
   if (reads->n_reads > 0 && !reads->offsets) return KMC_ERR_INVALID_ARG;
   if (reads->n_reads >= (1ull << 40) || reads->n_bases >= (1ull << 46)) return KMC_ERR_TOO_LARGE;
@@ -671,6 +674,12 @@ void run_count(kmc_ctx* c, const kmc_reads* R, const kmc_params* P, kmc_table* T
     groups.emplace_back(b0, J.n_bins);
   }
   const bool grouped = groups.size() > 1 || rec_on_host;
+  const uint32_t kx = (J.flags & KMC_FLAG_KX_MASK) >> 4;
+  if (kx && (grouped || c->ws_base)) {
+    c->err = "(k,x)-mers need the job in one bin group and library-managed buffers";
+    throw Fail{KMC_ERR_INVALID_ARG};
+  }
+  double kx_us[KMC_N_KERNELS] = {};
   st.n_groups = groups.size();
   st.records_spilled = rec_on_host ? 1 : 0;
   // a grouped job collects its entries in host memory (pinned staging), and
@@ -718,21 +727,6 @@ void run_count(kmc_ctx* c, const kmc_reads* R, const kmc_params* P, kmc_table* T
     tile_base[nbg] = n_tiles;  // max_tiles <= 2^fb <= kMaxTilesPerBin
     n_tiles_all += n_tiles;
     const uint64_t gk = key_base[nbg];
-    // tasks: fine-histogram tasks of up to hrec records, expansion tasks of
-    // one record per lane; only per-bin task offsets go to the device, which
-    // lists every task's bin itself
-    const uint64_t hrec = std::min<uint64_t>(65536, std::max<uint64_t>(1024, 8ull << fb));
-    const uint64_t eper = kn.expand_task ? kn.expand_task : expand_task_records(J.kw);
-    htask_pre[0] = etask_pre[0] = 0;
-    for (uint32_t i = 0; i < nbg; ++i) {
-      const uint64_t rc = rec_cnt[b0 + i];
-      rec_end[i] = rb[i] + rc;
-      htask_pre[i + 1] = htask_pre[i] + (rc + hrec - 1) / hrec;
-      etask_pre[i + 1] = etask_pre[i] + (rc + eper - 1) / eper;
-    }
-    rec_end[nbg] = rb[nbg];
-    const uint64_t n_htasks = htask_pre[nbg], n_etasks = etask_pre[nbg];
-    check(c, hipMemcpyAsync(d_bases, bases, 6 * gb1 * 8, hipMemcpyHostToDevice, s), "H2D");
     // the group's records: in place on the device, or staged from host memory
     const uint64_t* grec = records + g_rec_base[b0] * RW;
     if (rec_on_host) {
@@ -742,8 +736,39 @@ void run_count(kmc_ctx* c, const kmc_reads* R, const kmc_params* P, kmc_table* T
         check(c, hipMemcpyAsync(stage, grec, words * 8, hipMemcpyDefault, s), "H2D records");
       grec = stage;
     }
+    const std::vector<uint64_t> rs1(rb, rb + gb1);
+    const std::vector<uint64_t> rc1(rec_cnt.begin() + b0, rec_cnt.begin() + b1);
     const uint64_t* d_key_base = d_bases + gb1;
     const uint64_t* d_tile_base = d_bases + 2 * gb1;
+    // tasks: fine-histogram tasks of up to hrec records, expansion tasks of
+    // one record per lane; only per-bin task offsets go to the device, which
+    // lists every task's bin itself
+    const uint64_t hrec = std::min<uint64_t>(65536, std::max<uint64_t>(1024, 8ull << fb));
+    const uint64_t eper = kn.expand_task ? kn.expand_task : expand_task_records(J.kw);
+    Tile* tiles = nullptr;
+    uint64_t* tile_off = nullptr;
+    uint64_t* keys = nullptr;
+    uint32_t* counts = nullptr;
+    uint64_t* h_binoff = nullptr;
+    // One pass of the sorting phase over a record source (records of RW
+    // words): bin i holds rcnt[i] records from record rstart[i] on.  Fine
+    // histogram, tiles, expansion, counting, tile and bin offsets; reads
+    // back the bin offsets of the counted entries (the distinct count in
+    // h_binoff[gb1]) and the counters.  Keys are placed by the bins' k-mer
+    // counts, which bound the keys of every pass.
+    auto tile_pass = [&](const uint64_t* src, const uint64_t* rstart, const uint64_t* rcnt,
+                         const KeyCfg& kp, bool weighted) {
+    htask_pre[0] = etask_pre[0] = 0;
+    for (uint32_t i = 0; i < nbg; ++i) {
+      const uint64_t rc = rcnt[i];
+      rb[i] = rstart[i];
+      rec_end[i] = rb[i] + rc;
+      htask_pre[i + 1] = htask_pre[i] + (rc + hrec - 1) / hrec;
+      etask_pre[i + 1] = etask_pre[i] + (rc + eper - 1) / eper;
+    }
+    rb[nbg] = rec_end[nbg] = rstart[nbg];
+    const uint64_t n_htasks = htask_pre[nbg], n_etasks = etask_pre[nbg];
+    check(c, hipMemcpyAsync(d_bases, bases, 6 * gb1 * 8, hipMemcpyHostToDevice, s), "H2D");
     uint16_t* d_hbin = ensure<uint16_t>(c, B_HTASK, std::max<uint64_t>(1, n_htasks) * 2);
     ExpandTask* d_etask =
         ensure<ExpandTask>(c, B_ETASK, std::max<uint64_t>(1, n_etasks) * sizeof(ExpandTask));
@@ -758,20 +783,21 @@ void run_count(kmc_ctx* c, const kmc_reads* R, const kmc_params* P, kmc_table* T
     uint32_t* fine = ensure<uint32_t>(c, B_FINE, nfine * 4);
     check(c, hipMemsetAsync(fine, 0, nfine * 4, s), "memset");
     kbeg(c, KMC_K_FINE_HIST, s);
-    check(c, launch_fine_hist(s, kc, hmap, (uint32_t)n_htasks, grec, fine), "fine_hist");
+    check(c, launch_fine_hist(s, kp, hmap, (uint32_t)n_htasks, src, fine), "fine_hist");
     kend(c, KMC_K_FINE_HIST, s);
     uint16_t* tof = ensure<uint16_t>(c, B_TOF, nfine * 2);
-    Tile* tiles = ensure<Tile>(c, B_TILES, n_tiles * sizeof(Tile));
+    tiles = ensure<Tile>(c, B_TILES, n_tiles * sizeof(Tile));
     unsigned long long* tcur = ensure<unsigned long long>(c, B_TCUR, n_tiles * 8);
     if (n_tiles) check(c, hipMemsetAsync(tiles, 0, n_tiles * sizeof(Tile), s), "memset");
     kbeg(c, KMC_K_PLAN_TILES, s);
-    check(c, launch_plan_tiles(s, kc, fine, d_key_base, d_tile_base, tof, tiles, tcur), "plan");
+    check(c, launch_plan_tiles(s, kp, fine, d_key_base, d_tile_base, tof, tiles, tcur), "plan");
     kend(c, KMC_K_PLAN_TILES, s);
-    uint64_t* keys = ensure<uint64_t>(c, B_KEYS, gk * J.kw * 8);
-    uint32_t* counts = ensure<uint32_t>(c, B_COUNTS, gk * 4);
+    keys = ensure<uint64_t>(c, B_KEYS, gk * J.kw * 8);
+    counts = ensure<uint32_t>(c, B_COUNTS, gk * 4);
     kbeg(c, KMC_K_EXPAND, s);
-    check(c, launch_expand_scatter(s, kc, emap, (uint32_t)n_etasks, grec, tof, d_tile_base,
-                                   d_key_base, (uint32_t)max_tiles, tcur, keys), "expand");
+    check(c, launch_expand_scatter(s, kp, emap, (uint32_t)n_etasks, src, tof, d_tile_base,
+                                   d_key_base, (uint32_t)max_tiles, tcur, keys,
+                                   weighted ? counts : nullptr), "expand");
     kend(c, KMC_K_EXPAND, s);
     check(c, hipEventRecord(c->ev[3], s), "event");
 
@@ -786,8 +812,8 @@ void run_count(kmc_ctx* c, const kmc_reads* R, const kmc_params* P, kmc_table* T
     uint32_t* big_size = big_order + n_tiles;
     uint32_t* big_fail = big_size;
     kbeg(c, KMC_K_TILE_SORT, s);
-    check(c, launch_tile_sort(s, kc, tiles, n_tiles, keys, counts, tile_out, big, big_off,
-                              &misc->n_big, &misc->big_total, tile_dist, big_size),
+    check(c, launch_tile_sort(s, kp, tiles, n_tiles, keys, counts, tile_out, big, big_off,
+                              &misc->n_big, &misc->big_total, tile_dist, big_size, weighted),
           "tile_sort");
     kend(c, KMC_K_TILE_SORT, s);
     // big tiles: their number stays on the device (no round trip); scratch
@@ -795,10 +821,12 @@ void run_count(kmc_ctx* c, const kmc_reads* R, const kmc_params* P, kmc_table* T
     kbeg(c, KMC_K_BIG_TILES, s);
     {
       uint64_t* tmp = ensure<uint64_t>(c, B_TMP, std::max<uint64_t>(1, gk) * J.kw * 8);
-      check(c, launch_big_tiles(s, kc, tiles, big, big_off, big_size, big_order, big_fail,
+      uint32_t* tmpw =
+          weighted ? ensure<uint32_t>(c, B_TMPW, std::max<uint64_t>(1, gk) * 4) : nullptr;
+      check(c, launch_big_tiles(s, kp, tiles, big, big_off, big_size, big_order, big_fail,
                                 &misc->n_big,
                                 &misc->big_next, &misc->n_fail, &misc->fail_next, n_tiles,
-                                stream_big, keys, tmp, counts, tile_out, tile_dist,
+                                stream_big, keys, tmp, counts, tmpw, tile_out, tile_dist,
                                 &misc->big_out),
             "big_tiles");
     }
@@ -806,14 +834,14 @@ void run_count(kmc_ctx* c, const kmc_reads* R, const kmc_params* P, kmc_table* T
     check(c, hipEventRecord(c->ev[4], s), "event");
 
     // ---- assemble: offsets of every tile's output, bin offsets, gather
-    uint64_t* tile_off = ensure<uint64_t>(c, B_TILEOFF, (n_tiles + 1) * 8);
+    tile_off = ensure<uint64_t>(c, B_TILEOFF, (n_tiles + 1) * 8);
     uint64_t* scan_tmp = ensure<uint64_t>(c, B_SCANTMP, scan_tmp_words(n_tiles) * 8);
     kbeg(c, KMC_K_ASSEMBLE, s);
     check(c, launch_scan_u32(s, tile_out, n_tiles, tile_off, scan_tmp), "scan");
     uint64_t* bin_off = ensure<uint64_t>(c, B_BINOFF, gb1 * 8);
     check(c, launch_bin_offsets(s, tile_off, d_tile_base, nbg, bin_off), "bin_offsets");
     kend(c, KMC_K_ASSEMBLE, s);
-    uint64_t* h_binoff = ensure_host<uint64_t>(c, H_BINOFF, (gb1 + 1) * 8);
+    h_binoff = ensure_host<uint64_t>(c, H_BINOFF, (gb1 + 1) * 8);
     check(c, hipMemcpyAsync(h_binoff, bin_off, gb1 * 8, hipMemcpyDeviceToHost, s), "D2H");
     // distinct keys: sum of the per-tile counts (a scan; its last entry is the total)
     uint64_t* dist_scan = ensure<uint64_t>(c, B_DBG1, (n_tiles + 1) * 8);
@@ -822,12 +850,57 @@ void run_count(kmc_ctx* c, const kmc_reads* R, const kmc_params* P, kmc_table* T
           "D2H");
     check(c, hipMemcpyAsync(h_misc_p, misc, sizeof(Misc), hipMemcpyDeviceToHost, s), "D2H");
     check(c, hipStreamSynchronize(s), "sync");
-    const uint64_t g_out = h_binoff[nbg];
-    for (uint32_t i = 0; i <= nbg; ++i) T->bin_offsets[b0 + i] = n_out_total + h_binoff[i];
-    n_distinct += h_binoff[gb1];
     big_tiles += h_misc_p->n_big;
     big_keys += h_misc_p->big_total;
     big_out += h_misc_p->big_out;
+    };  // tile_pass
+
+    if (kx) {
+      // (k,x)-mers: the first pass sorts and counts the (k,x)-mers of the
+      // records (every one kept); the second counts the k-mers of the
+      // distinct (k,x)-mers, each weighted by its count, with the job's
+      // cutoffs
+      KeyCfg k1 = kc;
+      k1.kx = kx;
+      k1.kx_pass = 1;
+      k1.cutoff_min = 1;
+      k1.cutoff_max = 0xFFFFFFFFu;
+      k1.counter_max = 0xFFFFFFFFu;
+      tile_pass(grec, rs1.data(), rc1.data(), k1, false);
+      for (int i = KMC_K_FINE_HIST; i <= KMC_K_BIG_TILES; ++i)
+        kx_us[i] = 1e3 * ev_ms(c->ev[8 + 2 * i], c->ev[9 + 2 * i]);
+      kx_us[KMC_K_ASSEMBLE] = 1e3 * ev_ms(c->ev[8 + 2 * KMC_K_ASSEMBLE],
+                                          c->ev[9 + 2 * KMC_K_ASSEMBLE]);
+      const uint64_t n1 = h_binoff[nbg];
+      const std::vector<uint64_t> rs2(h_binoff, h_binoff + gb1);
+      std::vector<uint64_t> rc2(nbg);
+      for (uint32_t i = 0; i < nbg; ++i) rc2[i] = rs2[i + 1] - rs2[i];
+      st.n_kx_distinct += n1;
+      uint64_t* kxk = ensure<uint64_t>(c, B_KXK, std::max<uint64_t>(1, n1) * 8);
+      uint32_t* kxc = ensure<uint32_t>(c, B_KXC, std::max<uint64_t>(1, n1) * 4);
+      uint64_t* kxr = ensure<uint64_t>(c, B_KXR, std::max<uint64_t>(1, n1) * 16);
+      uint64_t* kxs = ensure<uint64_t>(c, B_DBG2, (n1 + 1) * 8);
+      uint64_t* kst = ensure<uint64_t>(c, B_SCANTMP,
+                                       scan_tmp_words(std::max<uint64_t>(n_tiles, n1)) * 8);
+      check(c, launch_gather(s, k1, tiles, n_tiles, tile_off, keys, counts, kxk, kxc),
+            "gather (k,x)-mers");
+      check(c, launch_scan_u32(s, kxc, n1, kxs, kst), "scan");
+      check(c, launch_kx_records(s, kxk, kxc, n1, kxr), "(k,x)-mer records");
+      uint64_t* h_kx = ensure_host<uint64_t>(c, H_KX, 8);
+      check(c, hipMemcpyAsync(h_kx, kxs + n1, 8, hipMemcpyDeviceToHost, s), "D2H");
+      check(c, hipMemsetAsync(misc, 0, sizeof(Misc), s), "memset");
+      check(c, hipStreamSynchronize(s), "sync");
+      st.n_kx_entries += *h_kx;
+      KeyCfg k2 = kc;
+      k2.kx = kx;
+      k2.kx_pass = 2;
+      tile_pass(kxr, rs2.data(), rc2.data(), k2, true);
+    } else {
+      tile_pass(grec, rs1.data(), rc1.data(), kc, false);
+    }
+    const uint64_t g_out = h_binoff[nbg];
+    for (uint32_t i = 0; i <= nbg; ++i) T->bin_offsets[b0 + i] = n_out_total + h_binoff[i];
+    n_distinct += h_binoff[gb1];
     if (!grouped) {
       // one group: the table is gathered straight into its final place
       n_out_total = g_out;
@@ -983,6 +1056,7 @@ void run_count(kmc_ctx* c, const kmc_reads* R, const kmc_params* P, kmc_table* T
   st.us_total = 1e3 * ev_ms(c->ev[0], c->ev[5]);
   for (int i = 0; i < KMC_N_KERNELS; ++i)
     st.us_kernel[i] = 1e3 * ev_ms(c->ev[8 + 2 * i], c->ev[9 + 2 * i]);
+  for (int i = 0; i < KMC_N_KERNELS; ++i) st.us_kernel[i] += kx_us[i];  // (k,x): first pass
   if (!grouped) {
     st.us_expand = 1e3 * ev_ms(c->ev[2], c->ev[3]);
     st.us_sort = 1e3 * ev_ms(c->ev[3], c->ev[4]);

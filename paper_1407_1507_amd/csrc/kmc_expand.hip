@@ -102,6 +102,61 @@ template <int KW> struct RecTop {
   }
 };
 
+// --------------------------------------------------------------- (k,x)-mers
+// Methods, "(k,x)-mers", and Fig. 2: a super k-mer is cut into the fewest
+// (k + x')-mers (x' <= x) whose k-mers are all canonical in the same
+// direction: walking its k-mers in order, a piece grows while the next k-mer
+// has the direction of the piece's first (forward when it is not larger than
+// its reverse complement, else reverse) and the piece holds at most x + 1
+// k-mers.  A forward piece is stored as read, a reverse piece as its reverse
+// complement, so every k-mer inside it is canonical.  Key (64 bits, k + x
+// <= 31): x' in the top two bits, the (k + x')-mer left-aligned below, the
+// rest zero; keys thus sort by x' first, then by sequence (the order of the
+// figure: the k-mers, then the (k+1)-mers).
+__device__ __forceinline__ uint64_t kx_key(uint64_t seq, uint32_t len, uint32_t xp) {
+  return ((uint64_t)xp << 62) | (seq << (62 - 2 * len));
+}
+// f(key) for every (k,x)-mer of the staged record r (64-bit k-mers)
+template <class F>
+__device__ __forceinline__ void kx_pieces(const uint64_t* r, const KeyCfg& kc, F f) {
+  Rec<1> rec;
+  rec.load(r, kc.k, true);
+  const uint64_t kmask = key_mask<uint64_t>(kc.k);
+  uint64_t E = rec.F;  // the piece's symbols as read
+  uint32_t len = 1;    // k-mers in the piece
+  bool rev = rec.R < rec.F;
+  auto emit = [&]() {
+    const uint32_t xp = len - 1, L = kc.k + xp;
+    f(kx_key(rev ? revcomp64(E, L) : E, L, xp));
+  };
+  for (uint32_t i = 1; i < rec.n; ++i) {
+    const uint32_t c = (uint32_t)(rec.T >> 62);
+    rec.step(kc.k, kmask);
+    const bool ri = rec.R < rec.F;
+    if (ri == rev && len <= kc.kx) {
+      E = (E << 2) | c;
+      ++len;
+    } else {
+      emit();
+      E = rec.F;
+      len = 1;
+      rev = ri;
+    }
+  }
+  emit();
+}
+// f(k-mer, weight) for the k-mers of a distinct (k,x)-mer record r (word 0
+// its key, word 1 its count << 8 | k-mers)
+template <class F>
+__device__ __forceinline__ void kx_kmers(const uint64_t* r, const KeyCfg& kc, F f) {
+  const uint64_t key = r[0];
+  const uint32_t xp = (uint32_t)(key >> 62), L = kc.k + xp;
+  const uint64_t E = (key & ((1ull << 62) - 1)) >> (62 - 2 * L);
+  const uint32_t w = (uint32_t)(r[1] >> 8);
+  const uint64_t kmask = key_mask<uint64_t>(kc.k);
+  for (uint32_t j = 0; j <= xp; ++j) f((E >> (2 * (xp - j))) & kmask, w);
+}
+
 // ------------------------------------------------------------ round staging
 // A super k-mer holds 1 .. w k-mers, so with one record per lane a wavefront
 // runs as long as its longest record.  Each round of up to 256 records is
@@ -183,7 +238,9 @@ k_task_bins(const uint64_t* __restrict__ pre_a, uint16_t* bin_a, const uint64_t*
   }
 }
 
-template <int KW>
+// MODE: 0 the k-mers of the records; 1 their (k,x)-mers; 2 the k-mers of
+// distinct (k,x)-mer records (KeyCfg::kx_pass; 1 and 2 with 64-bit keys).
+template <int KW, int MODE>
 __global__ void __launch_bounds__(kExpandThreads)
 k_fine_hist(KeyCfg kc, TaskMap tm, const uint64_t* __restrict__ records, uint32_t* fine_hist) {
   typedef typename KeyOf<KW>::T K;
@@ -197,7 +254,17 @@ k_fine_hist(KeyCfg kc, TaskMap tm, const uint64_t* __restrict__ records, uint32_
   for (uint32_t r0 = 0; r0 < tk.n_rec; r0 += kExpandThreads) {
     const uint32_t nr = min(tk.n_rec - r0, (uint32_t)kExpandThreads);
     stage_round<KW>(records + (tk.rec_begin + r0) * (2 * KW), nr, L);
-    if (threadIdx.x < nr && kc.fine_bits >= 2) {
+    if constexpr (MODE == 1) {
+      if (threadIdx.x < nr)
+        kx_pieces(L.w + (uint32_t)L.perm[threadIdx.x] * 2, kc, [&](uint64_t key) {
+          atomicAdd(&fh[(uint32_t)(key >> (64 - kc.fine_bits))], 1u);
+        });
+    } else if constexpr (MODE == 2) {
+      if (threadIdx.x < nr)
+        kx_kmers(L.w + (uint32_t)L.perm[threadIdx.x] * 2, kc, [&](uint64_t y, uint32_t) {
+          atomicAdd(&fh[top_bits(y, kc.k, kc.fine_bits)], 1u);
+        });
+    } else if (threadIdx.x < nr && kc.fine_bits >= 2) {
       // only the top fine_bits bits of each key: see RecTop
       const uint32_t sh = 2 * kc.k - kc.fine_bits;
       RecTop<KW> rec;
@@ -299,13 +366,15 @@ k_plan_tiles(KeyCfg kc, const uint32_t* __restrict__ fine_hist, const uint64_t* 
 // its slot, tile slot = reserved start + rank from an LDS counter.  A task's
 // keys of one tile land in one contiguous range.  No barrier inside the
 // walks.
-template <int KW>
+// MODE as for k_fine_hist; with MODE 2 each key's weight goes to weights at
+// the key's slot.
+template <int KW, int MODE>
 __global__ void __launch_bounds__(kExpandThreads)
 k_expand_scatter(KeyCfg kc, TaskMap tm,
                  const uint64_t* __restrict__ records, const uint16_t* __restrict__ tile_of_fine,
                  const uint64_t* __restrict__ tile_base, const uint64_t* __restrict__ key_base,
                  uint32_t mt, uint32_t n_tasks, unsigned long long* tile_cursor,
-                 uint64_t* keys) {
+                 uint64_t* keys, uint32_t* weights) {
   typedef typename KeyOf<KW>::T K;
   // a tile's reserved start: for 64-bit keys 32 bits relative to the bin's
   // first key (a bin holds fewer than 2^32), so the per-tile arrays take 8
@@ -336,6 +405,17 @@ k_expand_scatter(KeyCfg kc, TaskMap tm,
   const bool canon = kc.canonical != 0;
   // walk 1 over the slot's staged record: keys per tile
   auto count_walk = [&](const uint64_t* my) {
+    if constexpr (MODE == 1) {
+      kx_pieces(my, kc, [&](uint64_t key) {
+        atomicAdd(&cnt[tof[(uint32_t)(key >> (64 - kc.fine_bits))]], 1u);
+      });
+      return;
+    } else if constexpr (MODE == 2) {
+      kx_kmers(my, kc, [&](uint64_t y, uint32_t) {
+        atomicAdd(&cnt[tof[top_bits(y, kc.k, kc.fine_bits)]], 1u);
+      });
+      return;
+    }
     Rec<KW> rec;
     rec.load(my, kc.k, canon);
     for (uint32_t i = 0;; ++i) {
@@ -346,6 +426,21 @@ k_expand_scatter(KeyCfg kc, TaskMap tm,
   };
   // walk 2: the same keys again, each written to its tile
   auto write_walk = [&](const uint64_t* my) {
+    if constexpr (MODE == 1) {
+      kx_pieces(my, kc, [&](uint64_t key) {
+        const uint32_t t = tof[(uint32_t)(key >> (64 - kc.fine_bits))];
+        keys[kb + delta[t] + atomicAdd(&cnt[t], 1u)] = key;
+      });
+      return;
+    } else if constexpr (MODE == 2) {
+      kx_kmers(my, kc, [&](uint64_t y, uint32_t w) {
+        const uint32_t t = tof[top_bits(y, kc.k, kc.fine_bits)];
+        const uint64_t g = kb + delta[t] + atomicAdd(&cnt[t], 1u);
+        keys[g] = y;
+        weights[g] = w;
+      });
+      return;
+    }
     Rec<KW> rec;
     rec.load(my, kc.k, canon);
     for (uint32_t i = 0;; ++i) {
@@ -400,7 +495,27 @@ k_expand_scatter(KeyCfg kc, TaskMap tm,
   }
 }
 
+__global__ void __launch_bounds__(256)
+k_kx_records(const uint64_t* __restrict__ keys, const uint32_t* __restrict__ counts, uint64_t n,
+             uint64_t* records) {
+  const uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const uint64_t key = keys[i];
+  ulonglong2 r;
+  r.x = key;
+  r.y = ((uint64_t)counts[i] << 8) | ((key >> 62) + 1);
+  reinterpret_cast<ulonglong2*>(records)[i] = r;
+}
+
 }  // namespace
+
+hipError_t launch_kx_records(hipStream_t s, const uint64_t* keys, const uint32_t* counts,
+                             uint64_t n, uint64_t* records) {
+  if (n == 0) return hipSuccess;
+  hipLaunchKernelGGL(k_kx_records, dim3((uint32_t)((n + 255) / 256)), dim3(256), 0, s, keys,
+                     counts, n, records);
+  return hipGetLastError();
+}
 
 static size_t round_lds(int kw) {
   return kw == 1 ? sizeof(RoundLds<1>) : sizeof(RoundLds<2>);
@@ -420,13 +535,17 @@ hipError_t launch_task_bins(hipStream_t s, uint32_t n_bins, const uint64_t* pre_
 hipError_t launch_fine_hist(hipStream_t s, const KeyCfg& kc, const TaskMap& tm,
                             uint32_t n_tasks, const uint64_t* records, uint32_t* fine_hist) {
   if (n_tasks == 0) return hipSuccess;
+  if (kc.kx_pass && kc.key_words != 1) return hipErrorInvalidValue;
   const size_t sh = round_lds(kc.key_words) + ((size_t)1 << kc.fine_bits) * 4;
-  if (kc.key_words == 1)
-    hipLaunchKernelGGL(k_fine_hist<1>, dim3(n_tasks), dim3(kExpandThreads), sh, s, kc, tm,
-                       records, fine_hist);
+  const dim3 g(n_tasks), b(kExpandThreads);
+  if (kc.key_words == 2)
+    hipLaunchKernelGGL((k_fine_hist<2, 0>), g, b, sh, s, kc, tm, records, fine_hist);
+  else if (kc.kx_pass == 1)
+    hipLaunchKernelGGL((k_fine_hist<1, 1>), g, b, sh, s, kc, tm, records, fine_hist);
+  else if (kc.kx_pass == 2)
+    hipLaunchKernelGGL((k_fine_hist<1, 2>), g, b, sh, s, kc, tm, records, fine_hist);
   else
-    hipLaunchKernelGGL(k_fine_hist<2>, dim3(n_tasks), dim3(kExpandThreads), sh, s, kc, tm,
-                       records, fine_hist);
+    hipLaunchKernelGGL((k_fine_hist<1, 0>), g, b, sh, s, kc, tm, records, fine_hist);
   return hipGetLastError();
 }
 
@@ -441,27 +560,44 @@ hipError_t launch_plan_tiles(hipStream_t s, const KeyCfg& kc, const uint32_t* fi
   return hipGetLastError();
 }
 
+template <int KW, int MODE>
+static void expand_launch(hipStream_t s, uint32_t grid, size_t sh, const KeyCfg& kc,
+                          const TaskMap& tm, const uint64_t* records,
+                          const uint16_t* tile_of_fine, const uint64_t* tile_base,
+                          const uint64_t* key_base, uint32_t mt, uint32_t n_tasks,
+                          unsigned long long* tile_cursor, uint64_t* keys, uint32_t* weights) {
+  (void)hipFuncSetAttribute((const void*)k_expand_scatter<KW, MODE>,
+                            hipFuncAttributeMaxDynamicSharedMemorySize, (int)sh);
+  hipLaunchKernelGGL((k_expand_scatter<KW, MODE>), dim3(grid), dim3(kExpandThreads), sh, s, kc,
+                     tm, records, tile_of_fine, tile_base, key_base, mt, n_tasks, tile_cursor,
+                     keys, weights);
+}
+
 hipError_t launch_expand_scatter(hipStream_t s, const KeyCfg& kc, const TaskMap& tm,
                                  uint32_t n_tasks, const uint64_t* records,
                                  const uint16_t* tile_of_fine, const uint64_t* tile_base,
                                  const uint64_t* key_base, uint32_t max_tiles_per_bin,
-                                 unsigned long long* tile_cursor, uint64_t* keys) {
+                                 unsigned long long* tile_cursor, uint64_t* keys,
+                                 uint32_t* weights) {
   if (n_tasks == 0) return hipSuccess;
+  if (kc.kx_pass && kc.key_words != 1) return hipErrorInvalidValue;
+  if (kc.kx_pass == 2 && !weights) return hipErrorInvalidValue;
   const uint32_t nf = 1u << kc.fine_bits;
   const uint32_t mt = max_tiles_per_bin < 1 ? 1 : max_tiles_per_bin;
   const size_t sh = expand_lds(kc.key_words, mt, nf);
   const uint32_t grid = kc.key_words == 2 ? (n_tasks + kXcds - 1) / kXcds * kXcds : n_tasks;
-  if (kc.key_words == 1) {
-    (void)hipFuncSetAttribute((const void*)k_expand_scatter<1>,
-                        hipFuncAttributeMaxDynamicSharedMemorySize, (int)sh);
-    hipLaunchKernelGGL(k_expand_scatter<1>, dim3(grid), dim3(kExpandThreads), sh, s, kc,
-                       tm, records, tile_of_fine, tile_base, key_base, mt, n_tasks, tile_cursor, keys);
-  } else {
-    (void)hipFuncSetAttribute((const void*)k_expand_scatter<2>,
-                        hipFuncAttributeMaxDynamicSharedMemorySize, (int)sh);
-    hipLaunchKernelGGL(k_expand_scatter<2>, dim3(grid), dim3(kExpandThreads), sh, s, kc,
-                       tm, records, tile_of_fine, tile_base, key_base, mt, n_tasks, tile_cursor, keys);
-  }
+  if (kc.key_words == 2)
+    expand_launch<2, 0>(s, grid, sh, kc, tm, records, tile_of_fine, tile_base, key_base, mt,
+                        n_tasks, tile_cursor, keys, weights);
+  else if (kc.kx_pass == 1)
+    expand_launch<1, 1>(s, grid, sh, kc, tm, records, tile_of_fine, tile_base, key_base, mt,
+                        n_tasks, tile_cursor, keys, weights);
+  else if (kc.kx_pass == 2)
+    expand_launch<1, 2>(s, grid, sh, kc, tm, records, tile_of_fine, tile_base, key_base, mt,
+                        n_tasks, tile_cursor, keys, weights);
+  else
+    expand_launch<1, 0>(s, grid, sh, kc, tm, records, tile_of_fine, tile_base, key_base, mt,
+                        n_tasks, tile_cursor, keys, weights);
   return hipGetLastError();
 }
 

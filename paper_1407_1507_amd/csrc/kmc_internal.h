@@ -130,6 +130,13 @@ struct KeyCfg {
   uint32_t fp_bits;     // fingerprint bits of 128-bit hash-table claims (47; fewer in tests)
   uint32_t canonical;   // 1: keys are canonical k-mers; 0: forward k-mers as read
   uint32_t counter_max; // stored counts saturate here (0xFFFFFFFF: exact)
+  // (k,x)-mers: x (0: off) and the pass: 1 = the (k,x)-mers of the records
+  // are the keys (64-bit: x' in the top two bits, the canonical (k + x')-mer
+  // left-aligned below); 2 = the records are distinct (k,x)-mers with their
+  // counts (word 0 the key, word 1 count << 8 | k-mers) and the keys are
+  // their k-mers, each weighted by the (k,x)-mer's count
+  uint32_t kx = 0;
+  uint32_t kx_pass = 0;
 };
 
 // bin[t] for every task t of two task maps (pre arrays of n_bins + 1).
@@ -154,18 +161,27 @@ hipError_t launch_expand_scatter(hipStream_t s, const KeyCfg& kc, const TaskMap&
                                  uint32_t n_tasks, const uint64_t* records,
                                  const uint16_t* tile_of_fine, const uint64_t* tile_base,
                                  const uint64_t* key_base, uint32_t max_tiles_per_bin,
-                                 unsigned long long* tile_cursor, uint64_t* keys);
+                                 unsigned long long* tile_cursor, uint64_t* keys,
+                                 uint32_t* weights = nullptr);
+
+// (k,x)-mers, between the two passes: the distinct (k,x)-mers of the first
+// pass (keys, counts; n of them) as records of the second, two words each:
+// the key, then count << 8 | the number of its k-mers.
+hipError_t launch_kx_records(hipStream_t s, const uint64_t* keys, const uint32_t* counts,
+                             uint64_t n, uint64_t* records);
 
 // Sort + count every tile that fits LDS.  Output of a tile is written over
 // its own keys (out_counts at the same indices); tile_out[t] = entries kept,
 // tile_distinct[t] = distinct keys of tile t.  Tiles larger than LDS are appended to
 // big_list (count in n_big[0]) with their size in big_size and a private
 // slice of the HBM scratch at big_off (its size summed into big_total).
+// weighted (64-bit keys only): out_counts[i] holds the weight of key i on
+// entry, each key standing for that many equal keys.
 hipError_t launch_tile_sort(hipStream_t s, const KeyCfg& kc, const Tile* tiles,
                             uint64_t n_tiles, uint64_t* keys, uint32_t* out_counts,
                             uint32_t* tile_out, uint32_t* big_list, uint64_t* big_off,
                             uint32_t* n_big, unsigned long long* big_total,
-                            uint32_t* tile_distinct, uint32_t* big_size);
+                            uint32_t* tile_distinct, uint32_t* big_size, bool weighted);
 
 // Sort + count the big tiles: MSD partition through HBM, each tile
 // ping-ponging between its keys and its own slice tmp[big_off[i] ...]; for
@@ -177,14 +193,15 @@ hipError_t launch_tile_sort(hipStream_t s, const KeyCfg& kc, const Tile* tiles,
 // *next and *fail_next, and the failures are counted in *n_fail (all three
 // zero at launch).  order and fail_list hold max_big entries; max_big bounds
 // *n_big (the grids never exceed it).  *big_out accumulates the entries the
-// big tiles keep.
+// big tiles keep.  tmpw (64-bit keys, weighted tiles): u32 scratch beside
+// tmp for the weights, which move with their keys; null when unweighted.
 hipError_t launch_big_tiles(hipStream_t s, const KeyCfg& kc, const Tile* tiles,
                             const uint32_t* big_list, const uint64_t* big_off,
                             const uint32_t* big_size, uint32_t* order,
                             uint32_t* fail_list, const uint32_t* n_big, uint32_t* next,
                             uint32_t* n_fail, uint32_t* fail_next, uint64_t max_big,
                             bool stream_first,
-                            uint64_t* keys, uint64_t* tmp, uint32_t* out_counts,
+                            uint64_t* keys, uint64_t* tmp, uint32_t* out_counts, uint32_t* tmpw,
                             uint32_t* tile_out, uint32_t* tile_distinct,
                             unsigned long long* big_out);
 

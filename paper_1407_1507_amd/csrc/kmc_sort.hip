@@ -318,11 +318,15 @@ __device__ __forceinline__ uint32_t hash_finish(uint64_t (&key)[SortCfg<1>::ITEM
                                                 uint32_t ci, uint32_t cx, SortShared<1>& S,
                                                 uint32_t* distinct);
 
-template <bool kClean>
+//
+// kW: key m carries the weight wt[m] (a run of wt[m] equal keys); a slot's
+// counter then sums the weights of its key.
+template <bool kClean, bool kW = false>
 __device__ __forceinline__ uint32_t count_tile_hash(uint64_t (&key)[SortCfg<1>::ITEMS], uint32_t n,
                                                     uint64_t* out_keys, uint32_t* out_counts,
                                                     uint32_t ci, uint32_t cx, SortShared<1>& S,
-                                                    uint32_t* distinct) {
+                                                    uint32_t* distinct,
+                                                    const uint32_t* wt = nullptr) {
   constexpr uint32_t ITEMS = SortCfg<1>::ITEMS, T = SortCfg<1>::CAP, TB = 12;
   static_assert((1u << TB) == T, "table size");
   constexpr uint64_t EMPTY = ~0ull;
@@ -363,7 +367,7 @@ __device__ __forceinline__ uint32_t count_tile_hash(uint64_t (&key)[SortCfg<1>::
             ov = atomicCAS(reinterpret_cast<unsigned long long*>(&S.A[sl]),
                            (unsigned long long)EMPTY, (unsigned long long)key[g + u]);
           }
-          atomicAdd(&S.H[sl], 1u);
+          atomicAdd(&S.H[sl], kW ? wt[g + u] : 1u);
         }
       }
     }
@@ -629,11 +633,12 @@ __device__ __forceinline__ uint32_t count_any<1>(uint64_t (&key)[SortCfg<1>::ITE
 // The tile kernel's counting: only the hash table for 64-bit keys (tiles up
 // to DIRECT keys), so the kernel carries none of the bucket path's registers;
 // the kernel keeps the table empty between tiles.
+template <bool kW = false>
 __device__ __forceinline__ uint32_t count_direct(uint64_t (&key)[SortCfg<1>::ITEMS], uint32_t n,
                                                  uint64_t* out_keys, uint32_t* out_counts,
                                                  uint32_t ci, uint32_t cx, SortShared<1>& S,
-                                                 uint32_t* distinct) {
-  return count_tile_hash<true>(key, n, out_keys, out_counts, ci, cx, S, distinct);
+                                                 uint32_t* distinct, const uint32_t* wt = nullptr) {
+  return count_tile_hash<true, kW>(key, n, out_keys, out_counts, ci, cx, S, distinct, wt);
 }
 __device__ __forceinline__ uint32_t count_direct(u128 (&key)[SortCfg<2>::ITEMS], uint32_t n,
                                                  uint64_t* out_keys, uint32_t* out_counts,
@@ -659,13 +664,29 @@ __device__ __forceinline__ void load_tile(const uint64_t* src, uint32_t n,
   }
 }
 
-template <int KW>
-__device__ uint32_t sort_count_emit(const uint64_t* src, uint32_t n, uint64_t* out_keys,
-                                    uint32_t* out_counts, uint32_t ci, uint32_t cx,
-                                    SortShared<KW>& S, uint32_t* distinct) {
+__device__ __forceinline__ void load_weights(const uint32_t* src, uint32_t n,
+                                             uint32_t (&w)[SortCfg<1>::ITEMS]) {
+#pragma unroll
+  for (uint32_t m = 0; m < SortCfg<1>::ITEMS; ++m) {
+    const uint32_t i = m * blockDim.x + threadIdx.x;
+    if (i < n) w[m] = src[i];
+  }
+}
+
+// kW (64-bit keys): key i carries the weight wsrc[i].
+template <int KW, bool kW = false>
+__device__ uint32_t sort_count_emit(const uint64_t* src, const uint32_t* wsrc, uint32_t n,
+                                    uint64_t* out_keys, uint32_t* out_counts, uint32_t ci,
+                                    uint32_t cx, SortShared<KW>& S, uint32_t* distinct) {
   typename KeyOf<KW>::T key[SortCfg<KW>::ITEMS];
   load_tile<KW>(src, n, key);
-  return count_any<KW>(key, n, out_keys, out_counts, ci, cx, S, distinct);
+  if constexpr (KW == 1 && kW) {
+    uint32_t w[SortCfg<1>::ITEMS];
+    load_weights(wsrc, n, w);
+    return count_tile_hash<false, true>(key, n, out_keys, out_counts, ci, cx, S, distinct, w);
+  } else {
+    return count_any<KW>(key, n, out_keys, out_counts, ci, cx, S, distinct);
+  }
 }
 
 // Same as sort_count_emit, with the tile's keys already in registers
@@ -844,8 +865,10 @@ __device__ __forceinline__ uint32_t count_tile(typename KeyOf<KW>::T (&key)[Sort
 
 // Persistent: the grid is the number of workgroups resident at once, and
 // workgroup g takes tiles g, g + G, g + 2G, ... (tens of thousands of short
-// tiles would otherwise be bound by workgroup dispatch).
-template <int KW>
+// tiles would otherwise be bound by workgroup dispatch).  kW: counts[i]
+// holds the weight of key i on entry (the key stands for that many equal
+// keys), and the counters sum weights.
+template <int KW, bool kW>
 __global__ void __launch_bounds__(kSortThreads, 3)  // 3 waves per SIMD: as many as LDS allows
 k_tile_sort(KeyCfg kc, const Tile* __restrict__ tiles, uint64_t n_tiles, uint64_t* keys,
             uint32_t* counts, uint32_t* tile_out, uint32_t* big_list, uint64_t* big_off,
@@ -853,6 +876,7 @@ k_tile_sort(KeyCfg kc, const Tile* __restrict__ tiles, uint64_t n_tiles, uint64_
             uint32_t* big_size) {
   typedef typename KeyOf<KW>::T K;
   constexpr uint32_t ITEMS = SortCfg<KW>::ITEMS, CAP = SortCfg<KW>::CAP;
+  static_assert(KW == 1 || !kW, "weights with 64-bit keys only");
   __shared__ SortShared<KW> S;
   if (KW == 1) {  // the hash table starts empty; count_direct leaves it empty
     for (uint32_t i = threadIdx.x; i < CAP; i += blockDim.x) {
@@ -866,15 +890,27 @@ k_tile_sort(KeyCfg kc, const Tile* __restrict__ tiles, uint64_t n_tiles, uint64_
   auto direct = [](const Tile& x) { return x.size != 0 && x.size <= SortCfg<KW>::DIRECT; };
   Tile next = tiles[blockIdx.x];
   K nkey[ITEMS];
-  if (direct(next)) load_tile<KW>(keys + next.begin * KW, next.size, nkey);
+  uint32_t nw[kW ? ITEMS : 1];
+  if (direct(next)) {
+    load_tile<KW>(keys + next.begin * KW, next.size, nkey);
+    if constexpr (kW) load_weights(counts + next.begin, next.size, nw);
+  }
   for (uint64_t t = blockIdx.x; t < n_tiles; t += gridDim.x) {
     const Tile T = next;
     K key[ITEMS];
+    uint32_t w[kW ? ITEMS : 1];
 #pragma unroll
     for (uint32_t m = 0; m < ITEMS; ++m) key[m] = nkey[m];
+    if constexpr (kW) {
+#pragma unroll
+      for (uint32_t m = 0; m < ITEMS; ++m) w[m] = nw[m];
+    }
     if (t + gridDim.x < n_tiles) {
       next = tiles[t + gridDim.x];
-      if (direct(next)) load_tile<KW>(keys + next.begin * KW, next.size, nkey);
+      if (direct(next)) {
+        load_tile<KW>(keys + next.begin * KW, next.size, nkey);
+        if constexpr (kW) load_weights(counts + next.begin, next.size, nw);
+      }
     }
     if (T.size == 0) {
       if (threadIdx.x == 0) tile_out[t] = tile_distinct[t] = 0;
@@ -888,8 +924,13 @@ k_tile_sort(KeyCfg kc, const Tile* __restrict__ tiles, uint64_t n_tiles, uint64_
       }
     } else {
       uint32_t d;
-      const uint32_t kept = count_direct(key, T.size, keys + T.begin * KW, counts + T.begin,
-                                         kc.cutoff_min, kc.cutoff_max, S, &d);
+      uint32_t kept;
+      if constexpr (kW)
+        kept = count_direct<true>(key, T.size, keys + T.begin * KW, counts + T.begin,
+                                  kc.cutoff_min, kc.cutoff_max, S, &d, w);
+      else
+        kept = count_direct(key, T.size, keys + T.begin * KW, counts + T.begin, kc.cutoff_min,
+                            kc.cutoff_max, S, &d);
       if (threadIdx.x == 0) {
         tile_out[t] = kept;
         tile_distinct[t] = d;
@@ -955,17 +996,19 @@ k_tile_hash2(KeyCfg kc, const Tile* __restrict__ tiles, uint64_t n_tiles, uint64
 // the LDS hash table in chunks of kStreamChunk, each key read once, and the
 // table is read back as for a small tile.  The distinct keys claimed so far
 // are checked after every chunk: once more than DIRECT are claimed the attempt
-// stops (the table emptied, false returned) and the caller partitions the
-// tile instead.  A chunk holds T - DIRECT keys, so the table never fills and
-// every probe ends.
+// stops (false returned, the table left as it is: every user of the table
+// sets it up first) and the caller partitions the tile instead.  A chunk
+// holds T - DIRECT keys, so the table never fills and every probe ends.
+// kW: key i carries the weight wsrc[i].
 constexpr uint32_t kStreamItems = 4;
 constexpr uint32_t kStreamChunk = kStreamItems * kSortThreads;
 static_assert(SortCfg<1>::CAP - SortCfg<1>::DIRECT >= kStreamChunk, "a chunk never fills the table");
 
-__device__ bool stream_count_hash(const uint64_t* src, uint64_t n, uint64_t* out_keys,
-                                  uint32_t* out_counts, uint32_t ci, uint32_t cx,
-                                  SortShared<1>& S, uint32_t* claims, uint32_t* distinct,
-                                  uint32_t* kept) {
+template <bool kW = false>
+__device__ bool stream_count_hash(const uint64_t* src, const uint32_t* wsrc, uint64_t n,
+                                  uint64_t* out_keys, uint32_t* out_counts, uint32_t ci,
+                                  uint32_t cx, SortShared<1>& S, uint32_t* claims,
+                                  uint32_t* distinct, uint32_t* kept) {
   constexpr uint32_t T = SortCfg<1>::CAP, TB = 12, U = kStreamItems;
   constexpr uint64_t EMPTY = ~0ull;
   const uint32_t tid = threadIdx.x;
@@ -976,20 +1019,24 @@ __device__ bool stream_count_hash(const uint64_t* src, uint64_t n, uint64_t* out
   }
   if (tid == 0) *claims = 0;
   uint64_t cur[U];
+  uint32_t cw[kW ? U : 1];
 #pragma unroll
   for (uint32_t u = 0; u < U; ++u) {
     const uint64_t i = (uint64_t)u * nt + tid;
     cur[u] = i < n ? src[i] : EMPTY;
+    if constexpr (kW) cw[u] = i < n ? wsrc[i] : 0u;
   }
   __syncthreads();
   bool ok = true;
   for (uint64_t base = 0; base < n; base += kStreamChunk) {
     // the next chunk's loads go out before this chunk's inserts
     uint64_t nxt[U];
+    uint32_t nw[kW ? U : 1];
 #pragma unroll
     for (uint32_t u = 0; u < U; ++u) {
       const uint64_t i = base + kStreamChunk + (uint64_t)u * nt + tid;
       nxt[u] = i < n ? src[i] : EMPTY;
+      if constexpr (kW) nw[u] = i < n ? wsrc[i] : 0u;
     }
     uint64_t old[U];
     uint32_t slot[U];
@@ -1013,7 +1060,10 @@ __device__ bool stream_count_hash(const uint64_t* src, uint64_t n, uint64_t* out
                          (unsigned long long)EMPTY, (unsigned long long)cur[u]);
         }
         mine += ov == EMPTY;  // this key claimed its slot
-        atomicAdd(&S.H[sl], 1u);
+        if constexpr (kW)
+          atomicAdd(&S.H[sl], cw[u]);
+        else
+          atomicAdd(&S.H[sl], 1u);
       }
     }
     // claims of the wave, one atomic per wave
@@ -1029,6 +1079,10 @@ __device__ bool stream_count_hash(const uint64_t* src, uint64_t n, uint64_t* out
     }
 #pragma unroll
     for (uint32_t u = 0; u < U; ++u) cur[u] = nxt[u];
+    if constexpr (kW) {
+#pragma unroll
+      for (uint32_t u = 0; u < U; ++u) cw[u] = nw[u];
+    }
   }
   if (!ok) return false;
   uint64_t key[SortCfg<1>::ITEMS];
@@ -1070,11 +1124,13 @@ template <int KW> struct MaxLevels { static constexpr int N = KW == 1 ? 10 : 18;
 
 // One big tile, by the whole workgroup.  kStream (64-bit keys): the tile is
 // first streamed through the LDS hash table, and partitioned only if it holds
-// too many distinct keys.
-template <int KW, bool kStream>
+// too many distinct keys.  kW (64-bit keys): counts[i] holds the weight of
+// key i on entry; weights move with their keys through tmpw, and a run sums
+// its weights.
+template <int KW, bool kStream, bool kW>
 __device__ void big_tile(const KeyCfg& kc, const Tile* __restrict__ tiles, uint32_t t,
                          uint64_t tmp_off, uint64_t* keys, uint64_t* tmp, uint32_t* counts,
-                         uint32_t* tile_out, uint32_t* tile_distinct,
+                         uint32_t* tmpw, uint32_t* tile_out, uint32_t* tile_distinct,
                          unsigned long long* big_out) {
   typedef typename KeyOf<KW>::T K;
   __shared__ SortShared<KW> S;
@@ -1086,8 +1142,9 @@ __device__ void big_tile(const KeyCfg& kc, const Tile* __restrict__ tiles, uint3
   if constexpr (KW == 1 && kStream) {
     __shared__ uint32_t claims;
     uint32_t d, kept;
-    if (stream_count_hash(keys + T.begin, T.size, keys + T.begin, counts + T.begin,
-                          kc.cutoff_min, kc.cutoff_max, S, &claims, &d, &kept)) {
+    if (stream_count_hash<kW>(keys + T.begin, counts + T.begin, T.size, keys + T.begin,
+                              counts + T.begin, kc.cutoff_min, kc.cutoff_max, S, &claims, &d,
+                              &kept)) {
       if (tid == 0) {
         tile_out[t] = kept;
         tile_distinct[t] = d;
@@ -1098,6 +1155,8 @@ __device__ void big_tile(const KeyCfg& kc, const Tile* __restrict__ tiles, uint3
     }
   }
   uint64_t* bufs[2] = {keys + T.begin * KW, tmp + tmp_off * KW};
+  uint32_t* wbufs[2] = {counts + T.begin, kW ? tmpw + tmp_off : nullptr};
+  __shared__ unsigned long long wsum;
   if (tid == 0) {
     L[0].base = 0;
     L[0].next = 0;
@@ -1132,9 +1191,10 @@ __device__ void big_tile(const KeyCfg& kc, const Tile* __restrict__ tiles, uint3
     const unsigned long long oc = outc;
     if (n <= SortCfg<KW>::CAP) {
       uint32_t d;
-      const uint32_t kept = sort_count_emit<KW>(src, n, keys + (T.begin + oc) * KW,
-                                                counts + T.begin + oc, kc.cutoff_min,
-                                                kc.cutoff_max, S, &d);
+      const uint32_t kept = sort_count_emit<KW, kW>(src, wbufs[buf] + off, n,
+                                                    keys + (T.begin + oc) * KW,
+                                                    counts + T.begin + oc, kc.cutoff_min,
+                                                    kc.cutoff_max, S, &d);
       if (tid == 0) {
         outc = oc + kept;
         dist += d;
@@ -1151,10 +1211,25 @@ __device__ void big_tile(const KeyCfg& kc, const Tile* __restrict__ tiles, uint3
     block_and_or<K>(a, o, S.red);
     const K diff = a ^ o;
     if (diff == 0) {
+      // one key: its count is n, or the sum of its weights
+      uint64_t run = n;
+      if constexpr (kW) {
+        if (tid == 0) wsum = 0;
+        __syncthreads();
+        const uint32_t* ws = wbufs[buf] + off;
+        uint64_t v = 0;
+        for (uint32_t i = tid; i < n; i += nt) v += ws[i];
+        for (int dd = 32; dd >= 1; dd >>= 1) v += __shfl_xor(v, dd, 64);
+        if ((tid & 63u) == 0) atomicAdd(&wsum, (unsigned long long)v);
+        __syncthreads();
+        run = wsum;
+        __syncthreads();  // every thread has read wsum
+      }
+      const uint32_t rc = run > 0xFFFFFFFFull ? 0xFFFFFFFFu : (uint32_t)run;
       if (tid == 0) {
-        if (n >= kc.cutoff_min && n <= kc.cutoff_max) {
+        if (rc >= kc.cutoff_min && rc <= kc.cutoff_max) {
           store_key(keys, T.begin + oc, a);
-          counts[T.begin + oc] = n;
+          counts[T.begin + oc] = rc;
           outc = oc + 1;
         }
         dist += 1;
@@ -1184,9 +1259,35 @@ __device__ void big_tile(const KeyCfg& kc, const Tile* __restrict__ tiles, uint3
     }
     __syncthreads();
     uint64_t* dst = bufs[1 - buf] + off * KW;
-    for_each_key<K, U>(src, n, [&](const K& x) {
-      store_key(dst, atomicAdd(&cur[(uint32_t)(x >> shift) & dmask], 1u), x);
-    });
+    if constexpr (kW) {
+      // weights move with their keys
+      const uint32_t* ws = wbufs[buf] + off;
+      uint32_t* wd = wbufs[1 - buf] + off;
+      for (uint32_t base = 0; base < n; base += nt * U) {
+        K x[U];
+        uint32_t w[U];
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+          const uint32_t i = base + u * nt + tid;
+          if (i < n) {
+            x[u] = load_key(src, i, (K*)nullptr);
+            w[u] = ws[i];
+          }
+        }
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+          if (base + u * nt + tid < n) {
+            const uint32_t at = atomicAdd(&cur[(uint32_t)(x[u] >> shift) & dmask], 1u);
+            store_key(dst, at, x[u]);
+            wd[at] = w[u];
+          }
+        }
+      }
+    } else {
+      for_each_key<K, U>(src, n, [&](const K& x) {
+        store_key(dst, atomicAdd(&cur[(uint32_t)(x >> shift) & dmask], 1u), x);
+      });
+    }
     __threadfence();
     __syncthreads();
     depth = nd;
@@ -1202,12 +1303,12 @@ __device__ void big_tile(const KeyCfg& kc, const Tile* __restrict__ tiles, uint3
 // Persistent: workgroups take big tiles from a counter until none is left;
 // item it of the work is big tile list[it] (an index into big_list /
 // big_off), for it < *n_items.
-template <int KW, bool kStream>
+template <int KW, bool kStream, bool kW>
 __global__ void __launch_bounds__(kSortThreads)
 k_big_tiles(KeyCfg kc, const Tile* __restrict__ tiles, const uint32_t* __restrict__ big_list,
             const uint64_t* __restrict__ big_off, const uint32_t* __restrict__ list,
             const uint32_t* n_items, uint32_t* next, uint64_t* keys, uint64_t* tmp,
-            uint32_t* counts, uint32_t* tile_out, uint32_t* tile_distinct,
+            uint32_t* counts, uint32_t* tmpw, uint32_t* tile_out, uint32_t* tile_distinct,
             unsigned long long* big_out) {
   __shared__ uint32_t item;
   const uint32_t nb = *n_items;
@@ -1218,8 +1319,8 @@ k_big_tiles(KeyCfg kc, const Tile* __restrict__ tiles, const uint32_t* __restric
     __syncthreads();
     if (it >= nb) return;
     const uint32_t j = list[it];
-    big_tile<KW, kStream>(kc, tiles, big_list[j], big_off[j], keys, tmp, counts, tile_out,
-                          tile_distinct, big_out);
+    big_tile<KW, kStream, kW>(kc, tiles, big_list[j], big_off[j], keys, tmp, counts, tmpw,
+                              tile_out, tile_distinct, big_out);
   }
 }
 
@@ -1228,6 +1329,7 @@ k_big_tiles(KeyCfg kc, const Tile* __restrict__ tiles, const uint32_t* __restric
 // table takes are listed in fail_list for k_big_tiles.  A kernel of its own,
 // so that its registers allow two workgroups per compute unit (the kernel
 // that does both allows one).
+template <bool kW>
 __global__ void __launch_bounds__(kSortThreads)
 k_big_stream(KeyCfg kc, const Tile* __restrict__ tiles, const uint32_t* __restrict__ big_list,
              const uint32_t* __restrict__ order, const uint32_t* n_big, uint32_t* next,
@@ -1245,8 +1347,9 @@ k_big_stream(KeyCfg kc, const Tile* __restrict__ tiles, const uint32_t* __restri
     const uint32_t j = order[it], t = big_list[j];
     const Tile T = tiles[t];
     uint32_t d, kept;
-    const bool ok = stream_count_hash(keys + T.begin, T.size, keys + T.begin, counts + T.begin,
-                                      kc.cutoff_min, kc.cutoff_max, S, &claims, &d, &kept);
+    const bool ok = stream_count_hash<kW>(keys + T.begin, counts + T.begin, T.size,
+                                          keys + T.begin, counts + T.begin, kc.cutoff_min,
+                                          kc.cutoff_max, S, &claims, &d, &kept);
     if (threadIdx.x == 0) {
       if (ok) {
         tile_out[t] = kept;
@@ -1543,7 +1646,7 @@ k_group_sort(const uint64_t* __restrict__ lo, uint64_t* xk, uint32_t* xc, uint64
 // device: compute units x blocks per unit (by occupancy), cached per
 // (kernel slot, device).
 static int resident_blocks(const void* kernel, int slot) {
-  constexpr int kSlots = 6, kDevs = 16;
+  constexpr int kSlots = 10, kDevs = 16;
   static std::atomic<int> cache[kSlots][kDevs];
   int dev = 0;
   (void)hipGetDevice(&dev);
@@ -1562,23 +1665,57 @@ hipError_t launch_tile_sort(hipStream_t s, const KeyCfg& kc, const Tile* tiles,
                             uint64_t n_tiles, uint64_t* keys, uint32_t* out_counts,
                             uint32_t* tile_out, uint32_t* big_list, uint64_t* big_off,
                             uint32_t* n_big, unsigned long long* big_total,
-                            uint32_t* tile_distinct, uint32_t* big_size) {
+                            uint32_t* tile_distinct, uint32_t* big_size, bool weighted) {
   if (n_tiles == 0) return hipSuccess;
+  if (weighted && kc.key_words != 1) return hipErrorInvalidValue;
   // persistent grid: exactly the workgroups that are resident at once
-  const int kw = kc.key_words == 1 ? 1 : 2;
+  const void* kern = kc.key_words == 2 ? (const void*)k_tile_hash2
+                     : weighted        ? (const void*)k_tile_sort<1, true>
+                                       : (const void*)k_tile_sort<1, false>;
   const uint32_t grid = (uint32_t)std::min<uint64_t>(
-      n_tiles, (uint64_t)resident_blocks(kw == 1 ? (const void*)k_tile_sort<1>
-                                                 : (const void*)k_tile_hash2,
-                                         kw - 1));
-  if (kc.key_words == 1)
-    hipLaunchKernelGGL(k_tile_sort<1>, dim3(grid), dim3(kSortThreads), 0, s, kc,
-                       tiles, n_tiles, keys, out_counts, tile_out, big_list, big_off, n_big, big_total,
-                       tile_distinct, big_size);
-  else
+      n_tiles, (uint64_t)resident_blocks(kern, kc.key_words == 2 ? 1 : weighted ? 6 : 0));
+  if (kc.key_words == 2)
     hipLaunchKernelGGL(k_tile_hash2, dim3(grid), dim3(kSortThreads), 0, s, kc,
                        tiles, n_tiles, keys, out_counts, tile_out, big_list, big_off, n_big, big_total,
                        tile_distinct, big_size);
+  else if (weighted)
+    hipLaunchKernelGGL((k_tile_sort<1, true>), dim3(grid), dim3(kSortThreads), 0, s, kc,
+                       tiles, n_tiles, keys, out_counts, tile_out, big_list, big_off, n_big, big_total,
+                       tile_distinct, big_size);
+  else
+    hipLaunchKernelGGL((k_tile_sort<1, false>), dim3(grid), dim3(kSortThreads), 0, s, kc,
+                       tiles, n_tiles, keys, out_counts, tile_out, big_list, big_off, n_big, big_total,
+                       tile_distinct, big_size);
   return hipGetLastError();
+}
+
+// The big-tile kernels of 64-bit keys, with or without weights.
+template <bool kW>
+static void big_tiles_64(hipStream_t s, const KeyCfg& kc, const Tile* tiles,
+                         const uint32_t* big_list, const uint64_t* big_off, uint32_t* order,
+                         uint32_t* fail_list, const uint32_t* n_big, uint32_t* next,
+                         uint32_t* n_fail, uint32_t* fail_next, uint64_t max_big,
+                         bool stream_first, uint64_t* keys, uint64_t* tmp, uint32_t* out_counts,
+                         uint32_t* tmpw, uint32_t* tile_out, uint32_t* tile_distinct,
+                         unsigned long long* big_out) {
+  if (!stream_first) {
+    const uint32_t grid = (uint32_t)std::min<uint64_t>(
+        max_big, (uint64_t)resident_blocks((const void*)k_big_tiles<1, true, kW>, kW ? 7 : 5));
+    hipLaunchKernelGGL((k_big_tiles<1, true, kW>), dim3(grid), dim3(kSortThreads), 0, s, kc,
+                       tiles, big_list, big_off, order, n_big, next, keys, tmp, out_counts, tmpw,
+                       tile_out, tile_distinct, big_out);
+    return;
+  }
+  const uint32_t gs = (uint32_t)std::min<uint64_t>(
+      max_big, (uint64_t)resident_blocks((const void*)k_big_stream<kW>, kW ? 8 : 4));
+  hipLaunchKernelGGL(k_big_stream<kW>, dim3(gs), dim3(kSortThreads), 0, s, kc, tiles, big_list,
+                     order, n_big, next, keys, out_counts, tile_out, tile_distinct, big_out,
+                     fail_list, n_fail);
+  const uint32_t grid = (uint32_t)std::min<uint64_t>(
+      max_big, (uint64_t)resident_blocks((const void*)k_big_tiles<1, false, kW>, kW ? 9 : 2));
+  hipLaunchKernelGGL((k_big_tiles<1, false, kW>), dim3(grid), dim3(kSortThreads), 0, s, kc,
+                     tiles, big_list, big_off, fail_list, n_fail, fail_next, keys, tmp,
+                     out_counts, tmpw, tile_out, tile_distinct, big_out);
 }
 
 hipError_t launch_big_tiles(hipStream_t s, const KeyCfg& kc, const Tile* tiles,
@@ -1587,33 +1724,25 @@ hipError_t launch_big_tiles(hipStream_t s, const KeyCfg& kc, const Tile* tiles,
                             uint32_t* fail_list, const uint32_t* n_big, uint32_t* next,
                             uint32_t* n_fail, uint32_t* fail_next, uint64_t max_big,
                             bool stream_first, uint64_t* keys, uint64_t* tmp,
-                            uint32_t* out_counts, uint32_t* tile_out, uint32_t* tile_distinct,
-                            unsigned long long* big_out) {
+                            uint32_t* out_counts, uint32_t* tmpw, uint32_t* tile_out,
+                            uint32_t* tile_distinct, unsigned long long* big_out) {
   if (max_big == 0) return hipSuccess;
+  if (tmpw && kc.key_words != 1) return hipErrorInvalidValue;
   hipLaunchKernelGGL(k_order_big, dim3(1), dim3(1024), 0, s, big_size, n_big, order);
-  if (kc.key_words == 1 && !stream_first) {
-    const uint32_t grid = (uint32_t)std::min<uint64_t>(
-        max_big, (uint64_t)resident_blocks((const void*)k_big_tiles<1, true>, 5));
-    hipLaunchKernelGGL((k_big_tiles<1, true>), dim3(grid), dim3(kSortThreads), 0, s, kc, tiles,
-                       big_list, big_off, order, n_big, next, keys, tmp, out_counts, tile_out,
+  if (kc.key_words == 1 && tmpw) {
+    big_tiles_64<true>(s, kc, tiles, big_list, big_off, order, fail_list, n_big, next, n_fail,
+                       fail_next, max_big, stream_first, keys, tmp, out_counts, tmpw, tile_out,
                        tile_distinct, big_out);
   } else if (kc.key_words == 1) {
-    const uint32_t gs = (uint32_t)std::min<uint64_t>(
-        max_big, (uint64_t)resident_blocks((const void*)k_big_stream, 4));
-    hipLaunchKernelGGL(k_big_stream, dim3(gs), dim3(kSortThreads), 0, s, kc, tiles, big_list,
-                       order, n_big, next, keys, out_counts, tile_out, tile_distinct, big_out,
-                       fail_list, n_fail);
-    const uint32_t grid = (uint32_t)std::min<uint64_t>(
-        max_big, (uint64_t)resident_blocks((const void*)k_big_tiles<1, false>, 2));
-    hipLaunchKernelGGL((k_big_tiles<1, false>), dim3(grid), dim3(kSortThreads), 0, s, kc, tiles,
-                       big_list, big_off, fail_list, n_fail, fail_next, keys, tmp, out_counts,
-                       tile_out, tile_distinct, big_out);
+    big_tiles_64<false>(s, kc, tiles, big_list, big_off, order, fail_list, n_big, next, n_fail,
+                        fail_next, max_big, stream_first, keys, tmp, out_counts, nullptr,
+                        tile_out, tile_distinct, big_out);
   } else {
     const uint32_t grid = (uint32_t)std::min<uint64_t>(
-        max_big, (uint64_t)resident_blocks((const void*)k_big_tiles<2, false>, 3));
-    hipLaunchKernelGGL((k_big_tiles<2, false>), dim3(grid), dim3(kSortThreads), 0, s, kc, tiles,
-                       big_list, big_off, order, n_big, next, keys, tmp, out_counts, tile_out,
-                       tile_distinct, big_out);
+        max_big, (uint64_t)resident_blocks((const void*)k_big_tiles<2, false, false>, 3));
+    hipLaunchKernelGGL((k_big_tiles<2, false, false>), dim3(grid), dim3(kSortThreads), 0, s, kc,
+                       tiles, big_list, big_off, order, n_big, next, keys, tmp, out_counts,
+                       nullptr, tile_out, tile_distinct, big_out);
   }
   return hipGetLastError();
 }

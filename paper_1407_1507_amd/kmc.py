@@ -29,6 +29,11 @@ FLAG_DEVICE_TABLE = 0x1
 FLAG_PLAIN_MINIMIZERS = 0x2
 FLAG_ASCENDING = 0x4
 FLAG_NON_CANONICAL = 0x8
+
+
+def FLAG_KX(x: int) -> int:
+    """(k,x)-mers with x = 1..3 (include/kmc.h, KMC_FLAG_KX)."""
+    return (x & 3) << 4
 FLAG_TEST_NARROW_FINGERPRINT = 0x100  # test only: drives the exact path of 128-bit tiles
 
 EXPORTS = ["kmc_ctx_create", "kmc_ctx_destroy", "kmc_last_error", "kmc_ctx_set_budget", "kmc_count", "kmc_count_ex",
@@ -64,7 +69,7 @@ class Stats(ctypes.Structure):
     _fields_ = [(n, ctypes.c_uint64) for n in (
         "n_reads", "n_bases", "n_kmers", "n_superkmers", "n_distinct", "n_out", "sample_kmers",
         "max_bin_kmers", "n_tiles", "n_big_tiles", "bytes_alg", "split_passes", "n_big_keys",
-        "n_big_out", "n_groups", "records_spilled")] + [
+        "n_big_out", "n_groups", "records_spilled", "n_kx_entries", "n_kx_distinct")] + [
         (n, ctypes.c_double) for n in (
             "us_map", "us_split", "us_expand", "us_sort", "us_assemble", "us_total")] + [
         ("us_kernel", ctypes.c_double * 8), ("us_queue", ctypes.c_double),
