@@ -496,6 +496,51 @@ def bench_table6(args):
             "rows": rows}
 
 
+def bench_kx(args):
+    """(k,x)-mers against plain k-mers (the shape of the paper's Table 7): per
+    x = 0..3, time per job on device-resident reads, the sorted fraction
+    ((k,x)-mers sorted / k-mers) and the distinct (k,x)-mers, on a k = 28
+    workload (k + x <= 31)."""
+    import torch
+    from paper_1407_1507_amd import kmc
+    seq, off, p = load_workload(args.workload, args.input_cache)
+    if p["k"] + 3 > 31:
+        raise SystemExit("--mode kx needs a workload with k <= 28")
+    dseq = torch.from_numpy(seq).to("cuda:0")
+    doff = torch.from_numpy(off.view(np.int64)).to("cuda:0")
+    ctx = kmc.Context(0)
+    rows = []
+    for x in (0, 1, 2, 3):
+        flags = kmc.FLAG_DEVICE_TABLE | kmc.FLAG_KX(x)
+        run = lambda: ctx.count(dseq, doff, p["k"], p["p"], p["n_bins"], p["cutoff_min"],
+                                p["cutoff_max"], flags=flags)
+        for _ in range(args.warmup):
+            run().free()
+        torch.cuda.synchronize()
+        t = []
+        st = None
+        for _ in range(args.steps):
+            t0 = time.perf_counter()
+            r = run()
+            t.append(time.perf_counter() - t0)
+            st = r.stats
+            r.free()
+        ms = 1e3 * float(np.median(t))
+        rows.append({"x": x, "ms_per_job": ms, "bases_per_s": int(off[-1]) / (ms / 1e3),
+                     "sorted_fraction": (st["n_kx_entries"] / st["n_kmers"]) if x else 1.0,
+                     "distinct_kx": st["n_kx_distinct"], "n_kmers": st["n_kmers"],
+                     "n_out": st["n_out"], "n_big_tiles": st["n_big_tiles"],
+                     "kernel_us": {k: round(v, 1) for k, v in st["us_kernel"].items()}})
+        print(json.dumps(rows[-1]), file=sys.stderr, flush=True)
+    ctx.close()
+    return {"metric": "time per job and sorted fraction, (k,x)-mers against k-mers (Table 7 shape)",
+            "value": None, "unit": "ms per job", "n_gpus": 1,
+            "data": "synthetic (seeded generator)",
+            "config": {"workload": args.workload, "k": p["k"], "p": p["p"],
+                       "n_bins": p["n_bins"], "steps": args.steps, "warmup": args.warmup},
+            "rows": rows}
+
+
 def fastq_bytes(seq, off, read_len: int) -> np.ndarray:
     """FASTQ text of equal-length reads ("@r<i>" headers, constant quality),
     built with array operations."""
@@ -594,7 +639,8 @@ def bench_query(args):
 
 def main():
     ap = argparse.ArgumentParser()
-    ap.add_argument("--mode", choices=["single", "batch", "serve", "table6", "parse", "query"],
+    ap.add_argument("--mode", choices=["single", "batch", "serve", "table6", "parse", "query",
+                                       "kx"],
                     default="single")
     ap.add_argument("--query-n", type=int, default=50_000_000)
     ap.add_argument("--table6-scale", type=float, default=1.0)
@@ -635,7 +681,7 @@ def main():
     if args.mode != "single":
         line = {"batch": bench_batch, "serve": bench_serve,
                 "table6": bench_table6, "parse": bench_parse,
-                "query": bench_query}[args.mode](args)
+                "query": bench_query, "kx": bench_kx}[args.mode](args)
         print(json.dumps(line), flush=True)
         return
 
