@@ -411,14 +411,25 @@ def serve_large_mix(ctx, kmc, djobs, job, sat, args):
     import threading
     import torch
     from paper_1407_1507_amd import synth
-    seq, off, p = synth.make("large-300M-60Mx150")
+    seq, off, p = load_workload("large-300M-60Mx150", args.input_cache)
     dl = (torch.from_numpy(seq).to("cuda:0"), torch.from_numpy(off.view(np.int64)).to("cuda:0"))
     del seq, off
     largs = (dl[0], dl[1], p["k"], p["p"], p["n_bins"], p["cutoff_min"], p["cutoff_max"])
-    alone = ctx.count(*largs, flags=kmc.FLAG_DEVICE_TABLE)
-    ref = (alone.n, alone.stats["n_kmers"], alone.stats["us_total"])
+
+    def digest(r):
+        # entries, sum of counts, and the wrapped sums of keys and of
+        # key * count: equal tables give equal digests
+        k = r.keys.astype(np.uint64)
+        c = r.counts.astype(np.uint64)
+        return (int(r.n), int(c.sum()), int(k.sum(dtype=np.uint64)),
+                int((k * c).sum(dtype=np.uint64)))
+
+    alone = ctx.count(*largs)
+    ref = digest(alone)
+    alone_ms = alone.stats["us_total"] * 1e-3
     alone.free()
-    res = {"large_job": {"n_bases": int(dl[0].numel()), "alone_device_ms": ref[2] * 1e-3}}
+    res = {"large_job": {"n_bases": int(dl[0].numel()), "alone_device_ms": alone_ms,
+                         "entries": ref[0]}}
     for label, budget in (("full", 0), ("24GB", 24 << 30)):
         srv = kmc.Server(ctx, hbm_budget=budget, max_active=args.max_active)
         n = args.serve_arrivals
@@ -446,7 +457,7 @@ def serve_large_mix(ctx, kmc, djobs, job, sat, args):
             tickets.put(srv.submit(*job(i)))
         r = srv.poll(big)
         big_ms = r.stats["us_latency"] * 1e-3
-        same = r.n == ref[0] and r.stats["n_kmers"] == ref[1]
+        same = digest(r) == ref
         groups, spilled = r.stats["n_groups"], r.stats["records_spilled"]
         r.free()
         th.join()
