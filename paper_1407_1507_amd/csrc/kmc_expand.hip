@@ -416,6 +416,18 @@ k_expand_scatter(KeyCfg kc, TaskMap tm,
       });
       return;
     }
+    if (kc.fine_bits >= 2) {
+      // only the top fine_bits bits of each key: see RecTop
+      const uint32_t sh = 2 * kc.k - kc.fine_bits;
+      RecTop<KW> rec;
+      rec.load(my, kc.k, sh, canon);
+      for (uint32_t i = 0;; ++i) {
+        atomicAdd(&cnt[tof[rec.top(sh)]], 1u);
+        if (i + 1 >= rec.n) break;
+        rec.step(kmask, kc.fine_bits);
+      }
+      return;
+    }
     Rec<KW> rec;
     rec.load(my, kc.k, canon);
     for (uint32_t i = 0;; ++i) {

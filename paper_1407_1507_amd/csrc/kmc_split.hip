@@ -69,13 +69,18 @@ __device__ __forceinline__ void scan_read(const uint8_t* __restrict__ seq, uint6
   for (; xc < x1; xc += 16) {
     const uint4 next =
         xc + 16 < x1 ? load_chunk(seq, n_bases, C.seq_align, xc + 16) : make_uint4(0, 0, 0, 0);
+    // bytes q of the chunk inside [x0, x1): bits lo .. hi - 1 (one 64-bit
+    // comparison per chunk instead of two per byte)
+    const uint32_t lo = x0 > xc ? (uint32_t)min(x0 - xc, (uint64_t)16) : 0u;
+    const uint32_t hi = (uint32_t)min(x1 - xc, (uint64_t)16);
+    const uint32_t inside = ((1u << hi) - 1u) & ~((1u << lo) - 1u);
 #pragma unroll
     for (uint32_t q = 0; q < 16; ++q) {
       const uint64_t x = xc + q;
       const uint32_t word = q < 4 ? chunk.x : q < 8 ? chunk.y : q < 12 ? chunk.z : chunk.w;
       bool ok;
       const uint32_t c = decode_base((word >> (8 * (q & 3))) & 0xFFu, ok);
-      ok = ok && x >= x0 && x < x1;
+      ok = ok && ((inside >> q) & 1u);
       run = ok ? run + 1 : 0;
       fp = ((fp << 2) | c) & C.pmask;
       rp = (rp >> 2) | ((3u - c) << rcs);
