@@ -15,6 +15,8 @@ device and copied back here).
   entries carry the oracle's count; sampled windows of the input are in the
   table exactly when their oracle count passes the cutoffs; sampled keys sit
   in the bin of their signature; bins are disjoint and ascending.
+- the batched workload (256 uneven jobs, 10.3 Gbases): every table of one
+  kmc_batch_count equals the same job's table counted alone.
 """
 import ctypes
 import os
@@ -214,3 +216,43 @@ def test_large_job_full_size_properties(ctx, kmc):
     bin_of = np.searchsorted(bo, idx[:5000], side="right") - 1
     sig = oracle.key_signatures(keys[idx[:5000]], k, p["p"])
     assert np.array_equal(s2b[sig], bin_of)
+
+
+def _batch_job(j):
+    from paper_1407_1507_amd import synth as sy
+    return sy.batch_job(j, 1.0)
+
+
+@pytest.mark.timeout(900)
+def test_batch_256_full_size_equals_single_runs(ctx, kmc):
+    # the batched workload at full size (256 uneven jobs, 10.3 Gbases, k in
+    # {21, 25, 31, 47, 55}): every table of one kmc_batch_count equals the
+    # table of the same job counted alone, entry for entry
+    import multiprocessing
+    from concurrent.futures import ProcessPoolExecutor
+    import torch
+    step = lambda m: print(f"[batch 256] {m}", flush=True)  # progress of a long test
+    with ProcessPoolExecutor(THREADS, mp_context=multiprocessing.get_context("spawn")) as ex:
+        jobs = list(ex.map(_batch_job, range(256)))
+    step(f"generated {sum(s.size for s, _, _ in jobs)} bases")
+    dev = [(torch.from_numpy(s).to("cuda:0"), torch.from_numpy(o.view(np.int64)).to("cuda:0"), p)
+           for s, o, p in jobs]
+    del jobs
+    torch.cuda.synchronize()
+    c = kmc.Context(0)  # its own buffers, apart from the large job's cached ones
+    out = c.batch_count(dev)
+    step(f"batch: {sum(r.n for r in out)} entries")
+    assert len(out) == 256
+    ks = set()
+    for (dseq, doff, p), r in zip(dev, out):
+        a = c.count(dseq, doff, p["k"], p["p"], p["n_bins"], p["cutoff_min"], p["cutoff_max"])
+        ks.add(p["k"])
+        assert r.n == a.n
+        assert np.array_equal(r.keys, a.keys)
+        assert np.array_equal(r.counts, a.counts)
+        assert np.array_equal(r.bin_offsets, a.bin_offsets)
+    assert ks == {21, 25, 31, 47, 55}
+    step("all 256 tables equal their single runs")
+    c.close()
+    del dev, out
+    torch.cuda.empty_cache()
