@@ -744,7 +744,12 @@ void run_count(kmc_ctx* c, const kmc_reads* R, const kmc_params* P, kmc_table* T
     // one record per lane; only per-bin task offsets go to the device, which
     // lists every task's bin itself
     const uint64_t hrec = std::min<uint64_t>(65536, std::max<uint64_t>(1024, 8ull << fb));
-    const uint64_t eper = kn.expand_task ? kn.expand_task : expand_task_records(J.kw);
+    // expansion tasks: with heavy bins (thousands of tiles each, see above)
+    // a task of 256 records lands less than one key per tile, and 512-record
+    // tasks (two rounds) measured faster there (9-Gbase job 74.2 -> 62.7 ms)
+    const uint64_t eper = kn.expand_task             ? kn.expand_task
+                          : (stream_big && J.kw == 1) ? 2 * (uint64_t)kExpandThreads
+                                                      : expand_task_records(J.kw);
     Tile* tiles = nullptr;
     uint64_t* tile_off = nullptr;
     uint64_t* keys = nullptr;
