@@ -65,7 +65,8 @@ struct WsLayout {
 
 // Pinned host buffers for the small transfers between the phases (plans,
 // counters, histograms), cached like the device buffers.
-enum HostId { H_HIST, H_CNT, H_BASES, H_MISC, H_BINOFF, H_MAP, H_KX, H_COUNT_ };
+enum HostId { H_HIST, H_CNT, H_BASES, H_MISC, H_BINOFF, H_MAP, H_KX, H_ACCK, H_ACCC, H_COUNT_ };
+
 
 struct kmc_ctx {
   int device = 0;
@@ -133,6 +134,24 @@ T* ensure_host(kmc_ctx* c, HostId id, size_t bytes) {
     b.cap = want;
   }
   return static_cast<T*>(b.p);
+}
+
+// ensure_host that keeps the first `keep` bytes when it has to grow.
+template <class T>
+T* grow_host(kmc_ctx* c, HostId id, size_t bytes, size_t keep) {
+  if (c->pageable_host) return ensure_host<T>(c, id, bytes);  // std::vector keeps its contents
+  DevBuf& b = c->hbuf[id];
+  if (b.cap >= bytes) return static_cast<T*>(b.p);
+  const size_t want = std::max<size_t>(bytes + bytes / 4, 4096);
+  void* p = nullptr;
+  check(c, hipHostMalloc(&p, want, 0), "hipHostMalloc");
+  if (b.p) {
+    if (keep) std::memcpy(p, b.p, std::min(keep, b.cap));
+    (void)hipHostFree(b.p);
+  }
+  b.p = p;
+  b.cap = want;
+  return static_cast<T*>(p);
 }
 
 template <class T>
@@ -682,10 +701,11 @@ void run_count(kmc_ctx* c, const kmc_reads* R, const kmc_params* P, kmc_table* T
   double kx_us[KMC_N_KERNELS] = {};
   st.n_groups = groups.size();
   st.records_spilled = rec_on_host ? 1 : 0;
-  // a grouped job collects its entries in host memory (pinned staging), and
-  // builds the requested table from them at the end
-  std::vector<uint64_t> acc_keys;
-  std::vector<uint32_t> acc_counts;
+  // a grouped job collects its entries in the context's pinned host buffers
+  // (copied there straight from the device; kept between calls, so no pages
+  // to fault in), and builds the requested table from them at the end
+  uint64_t* acc_k = nullptr;
+  uint32_t* acc_c = nullptr;
   double acc_us[KMC_N_KERNELS] = {}, acc_phase[3] = {};
   uint64_t n_out_total = 0, n_distinct = 0, n_tiles_all = 0;
   uint64_t big_tiles = 0, big_keys = 0, big_out = 0;
@@ -919,13 +939,17 @@ void run_count(kmc_ctx* c, const kmc_reads* R, const kmc_params* P, kmc_table* T
     check(c, launch_gather(s, kc, tiles, n_tiles, tile_off, keys, counts, gk_out, gc_out),
           "gather");
     check(c, hipEventRecord(c->ev[29], s), "event");
-    acc_keys.resize((n_out_total + g_out) * J.kw);
-    acc_counts.resize(n_out_total + g_out);
+    // room for the whole table once the first group has shown its share
+    // (groups hold about equal numbers of k-mers)
+    const uint64_t want = std::max<uint64_t>(
+        n_out_total + g_out, gi == 0 ? (g_out * groups.size() * 5) / 4 + 1 : 0);
+    acc_k = grow_host<uint64_t>(c, H_ACCK, want * J.kw * 8, n_out_total * J.kw * 8);
+    acc_c = grow_host<uint32_t>(c, H_ACCC, want * 4, n_out_total * 4);
     if (g_out) {
-      check(c, hipMemcpyAsync(acc_keys.data() + n_out_total * J.kw, gk_out, g_out * J.kw * 8,
+      check(c, hipMemcpyAsync(acc_k + n_out_total * J.kw, gk_out, g_out * J.kw * 8,
                               hipMemcpyDeviceToHost, s), "D2H");
-      check(c, hipMemcpyAsync(acc_counts.data() + n_out_total, gc_out, g_out * 4,
-                              hipMemcpyDeviceToHost, s), "D2H");
+      check(c, hipMemcpyAsync(acc_c + n_out_total, gc_out, g_out * 4, hipMemcpyDeviceToHost,
+                              s), "D2H");
     }
     check(c, hipStreamSynchronize(s), "sync");
     n_out_total += g_out;
@@ -994,10 +1018,9 @@ void run_count(kmc_ctx* c, const kmc_reads* R, const kmc_params* P, kmc_table* T
   } else if (out_k && n_out) {
     // a grouped job's entries into the device table
     check(c, hipEventRecord(c->ev[28], s), "event");
-    check(c, hipMemcpyAsync(out_k, acc_keys.data(), n_out * J.kw * 8, hipMemcpyHostToDevice, s),
+    check(c, hipMemcpyAsync(out_k, acc_k, n_out * J.kw * 8, hipMemcpyHostToDevice, s),
           "H2D table");
-    check(c, hipMemcpyAsync(out_c, acc_counts.data(), n_out * 4, hipMemcpyHostToDevice, s),
-          "H2D table");
+    check(c, hipMemcpyAsync(out_c, acc_c, n_out * 4, hipMemcpyHostToDevice, s), "H2D table");
   } else {
     check(c, hipEventRecord(c->ev[28], s), "event");
   }
@@ -1030,8 +1053,8 @@ void run_count(kmc_ctx* c, const kmc_reads* R, const kmc_params* P, kmc_table* T
     T->on_device = 0;
     host_table(T, n_out, J.kw);
     if (n_out) {
-      std::memcpy(T->keys, acc_keys.data(), n_out * J.kw * 8);
-      std::memcpy(T->counts, acc_counts.data(), n_out * 4);
+      std::memcpy(T->keys, acc_k, n_out * J.kw * 8);
+      std::memcpy(T->counts, acc_c, n_out * 4);
     }
   } else if (want_host) {
     // a host table copied out of the device table (or the staging buffers)
