@@ -330,10 +330,10 @@ kmc_status kmc_autotune(kmc_ctx* ctx, const kmc_job* jobs, uint32_t n_jobs,
  * already admitted, and up to max_active admitted jobs run at once, each on
  * its own stream; as one finishes the next admissible job starts (continuous
  * batching).  A job larger than the whole budget runs alone, within the
- * budget: the reserved arena is released while it runs and the job's
- * buffers are bounded by the budget as under kmc_ctx_set_budget (bin
- * groups, records in pinned host memory); its device table, if requested,
- * is allocated beside the budget. */
+ * budget: its device buffers are taken from the reserved arena and bounded
+ * by the budget as under kmc_ctx_set_budget (bin groups, records in pinned
+ * host memory); its device table, if requested, is allocated beside the
+ * budget. */
 typedef struct kmc_server_cfg {
   uint64_t hbm_budget; /* bytes; 0 = 90% of the device memory free at start */
   uint32_t max_active; /* 1..16 jobs running at once; 0 = 4 */

@@ -65,7 +65,7 @@ struct WsLayout {
 
 // Pinned host buffers for the small transfers between the phases (plans,
 // counters, histograms), cached like the device buffers.
-enum HostId { H_HIST, H_CNT, H_BASES, H_MISC, H_BINOFF, H_MAP, H_KX, H_ACCK, H_ACCC, H_COUNT_ };
+enum HostId { H_HIST, H_CNT, H_BASES, H_MISC, H_BINOFF, H_MAP, H_KX, H_COUNT_ };
 
 
 struct kmc_ctx {
@@ -78,6 +78,11 @@ struct kmc_ctx {
   // workspace mode (kmc_count_ws): buffers come from ws_base + layout
   uint8_t* ws_base = nullptr;
   WsLayout ws;
+  // lent-region mode (an oversize served job): device buffers are taken from
+  // the top of [pool_base, pool_base + pool_bytes); a bin group's buffers
+  // start again at pool_mark, the top when the first group began
+  uint8_t* pool_base = nullptr;
+  size_t pool_bytes = 0, pool_top = 0, pool_mark = 0;
   bool ws_own_table = false;  // device table allocated apart from the workspace
   // allocation-free mode (kmc_count_static): host staging in pageable
   // vectors instead of pinned buffers, and the table written to the caller's
@@ -136,24 +141,6 @@ T* ensure_host(kmc_ctx* c, HostId id, size_t bytes) {
   return static_cast<T*>(b.p);
 }
 
-// ensure_host that keeps the first `keep` bytes when it has to grow.
-template <class T>
-T* grow_host(kmc_ctx* c, HostId id, size_t bytes, size_t keep) {
-  if (c->pageable_host) return ensure_host<T>(c, id, bytes);  // std::vector keeps its contents
-  DevBuf& b = c->hbuf[id];
-  if (b.cap >= bytes) return static_cast<T*>(b.p);
-  const size_t want = std::max<size_t>(bytes + bytes / 4, 4096);
-  void* p = nullptr;
-  check(c, hipHostMalloc(&p, want, 0), "hipHostMalloc");
-  if (b.p) {
-    if (keep) std::memcpy(p, b.p, std::min(keep, b.cap));
-    (void)hipHostFree(b.p);
-  }
-  b.p = p;
-  b.cap = want;
-  return static_cast<T*>(p);
-}
-
 template <class T>
 T* ensure(kmc_ctx* c, BufId id, size_t bytes) {
   if (c->ws_base) {
@@ -165,6 +152,27 @@ T* ensure(kmc_ctx* c, BufId id, size_t bytes) {
   }
   DevBuf& b = c->buf[id];
   if (bytes == 0) bytes = 16;
+  if (c->pool_base) {
+    // exact sizes from the lent region; the top block grows in place, any
+    // other block outgrown is left behind until its group ends
+    if (b.p && b.cap >= bytes) return static_cast<T*>(b.p);
+    const size_t want = (bytes + 255) & ~(size_t)255;
+    if (b.p && static_cast<uint8_t*>(b.p) + b.cap == c->pool_base + c->pool_top &&
+        static_cast<uint8_t*>(b.p) >= c->pool_base + c->pool_mark &&
+        want - b.cap <= c->pool_bytes - c->pool_top) {
+      c->pool_top += want - b.cap;
+      b.cap = want;
+      return static_cast<T*>(b.p);
+    }
+    if (want > c->pool_bytes - c->pool_top) {
+      c->err = "the job's device buffers exceed the memory budget";
+      throw Fail{KMC_ERR_OUT_OF_MEMORY};
+    }
+    b.p = c->pool_base + c->pool_top;
+    b.cap = want;
+    c->pool_top += want;
+    return static_cast<T*>(b.p);
+  }
   if (b.cap < bytes) {
     if (b.p) check(c, hipFree(b.p), "hipFree");
     b.p = nullptr;
@@ -175,6 +183,15 @@ T* ensure(kmc_ctx* c, BufId id, size_t bytes) {
     b.cap = want;
   }
   return static_cast<T*>(b.p);
+}
+
+// Lent-region mode: forget the buffers taken since pool_mark (those of the
+// bin group that ended) and take the next group's from there.
+void pool_next_group(kmc_ctx* c) {
+  if (!c->pool_base) return;
+  for (auto& b : c->buf)
+    if (b.p && static_cast<uint8_t*>(b.p) >= c->pool_base + c->pool_mark) b = DevBuf{};
+  c->pool_top = c->pool_mark;
 }
 
 // Device-accessible pinned host memory for records that do not fit the
@@ -372,6 +389,45 @@ void host_table(kmc_table* T, uint64_t n, uint32_t kw) {
   T->reserved = 0;
   if (!T->keys || !T->counts) throw Fail{KMC_ERR_OUT_OF_MEMORY};
 }
+
+// The entries of a bin-grouped job in host memory: one pinned block of the
+// table pool, keys then counts, that becomes the host table's block (a freed
+// table's block serves the next grouped job, so its pages are pinned once).
+struct HostEntries {
+  void* blk = nullptr;  // owned here until a table takes it
+  uint64_t cap = 0;     // entries
+  uint64_t* k = nullptr;
+  uint32_t* c = nullptr;
+  HostEntries() = default;
+  HostEntries(const HostEntries&) = delete;
+  HostEntries& operator=(const HostEntries&) = delete;
+  ~HostEntries() {
+    if (blk) pool_give(blk);
+  }
+  // room for n entries, the first keep of them kept; false if the block
+  // cannot be allocated
+  bool reserve(uint64_t n, uint64_t keep, uint32_t kw) {
+    if (blk && n <= cap) return true;
+    const uint64_t ncap = std::max<uint64_t>(n, cap + cap / 2);
+    const size_t kb = (std::max<uint64_t>(1, ncap * kw) * 8 + 255) & ~(size_t)255;
+    void* nb = pool_take(kHostPool, kb + std::max<uint64_t>(1, ncap) * 4);
+    if (!nb) return false;
+    uint64_t* nk = static_cast<uint64_t*>(nb);
+    uint32_t* nc = reinterpret_cast<uint32_t*>(static_cast<uint8_t*>(nb) + kb);
+    if (blk) {
+      if (keep) {
+        std::memcpy(nk, k, keep * kw * 8);
+        std::memcpy(nc, c, keep * 4);
+      }
+      pool_give(blk);
+    }
+    blk = nb;
+    cap = ncap;
+    k = nk;
+    c = nc;
+    return true;
+  }
+};
 
 kmc_table* new_table() {
   kmc_table* t = static_cast<kmc_table*>(std::calloc(1, sizeof(kmc_table)));
@@ -668,8 +724,11 @@ void run_count(kmc_ctx* c, const kmc_reads* R, const kmc_params* P, kmc_table* T
     // fine histograms, and a fixed allowance for the per-tile and per-task
     // arrays, scans and counters
     const uint64_t rec_dev = rec_on_host ? 0 : g_rec_base[J.n_bins] * RW * 8;
+    // (per bin: up to three tiles beyond two per tile_limit keys, at under
+    // 96 bytes of per-tile arrays each)
     const uint64_t fixed = (R->on_device ? 0 : J.n_bases + 8 * (J.n_reads + 1)) +
-                           ((uint64_t)J.n_bins << fb) * 6 + (16ull << 20);
+                           ((uint64_t)J.n_bins << fb) * 6 + (uint64_t)J.n_bins * 288 +
+                           (16ull << 20);
     const uint64_t room = c->budget > rec_dev + fixed ? c->budget - rec_dev - fixed : 0;
     key_cap = room / per_kmer;
     if (max_bin > key_cap) {
@@ -701,22 +760,24 @@ void run_count(kmc_ctx* c, const kmc_reads* R, const kmc_params* P, kmc_table* T
   double kx_us[KMC_N_KERNELS] = {};
   st.n_groups = groups.size();
   st.records_spilled = rec_on_host ? 1 : 0;
-  // a grouped job collects its entries in the context's pinned host buffers
-  // (copied there straight from the device; kept between calls, so no pages
-  // to fault in), and builds the requested table from them at the end
-  uint64_t* acc_k = nullptr;
-  uint32_t* acc_c = nullptr;
+  // a grouped job collects its entries in host memory, copied there straight
+  // from the device, and builds the requested table from them at the end
+  HostEntries acc;
   double acc_us[KMC_N_KERNELS] = {}, acc_phase[3] = {};
   uint64_t n_out_total = 0, n_distinct = 0, n_tiles_all = 0;
   uint64_t big_tiles = 0, big_keys = 0, big_out = 0;
   uint64_t* out_k = nullptr;
   uint32_t* out_c = nullptr;
 
+  c->pool_mark = c->pool_top;
   for (size_t gi = 0; gi < groups.size(); ++gi) {
     const uint32_t b0 = groups[gi].first, b1 = groups[gi].second, nbg = b1 - b0;
     const size_t gb1 = (size_t)nbg + 1;
     kc.n_bins = nbg;
-    if (gi > 0) check(c, hipMemsetAsync(misc, 0, sizeof(Misc), s), "memset");
+    if (gi > 0) {
+      check(c, hipMemsetAsync(misc, 0, sizeof(Misc), s), "memset");
+      pool_next_group(c);  // the previous group's entries are in host memory
+    }
     // the group's bases, relative to its first bin
     uint64_t* bases = ensure_host<uint64_t>(c, H_BASES, 6 * gb1 * 8);
     uint64_t* rb = bases;
@@ -941,14 +1002,16 @@ void run_count(kmc_ctx* c, const kmc_reads* R, const kmc_params* P, kmc_table* T
     check(c, hipEventRecord(c->ev[29], s), "event");
     // room for the whole table once the first group has shown its share
     // (groups hold about equal numbers of k-mers)
-    const uint64_t want = std::max<uint64_t>(
-        n_out_total + g_out, gi == 0 ? (g_out * groups.size() * 5) / 4 + 1 : 0);
-    acc_k = grow_host<uint64_t>(c, H_ACCK, want * J.kw * 8, n_out_total * J.kw * 8);
-    acc_c = grow_host<uint32_t>(c, H_ACCC, want * 4, n_out_total * 4);
+    if (!acc.reserve(std::max<uint64_t>(n_out_total + g_out,
+                                        gi == 0 ? (g_out * groups.size() * 5) / 4 + 1 : 0),
+                     n_out_total, J.kw)) {
+      c->err = "pinned host allocation of a grouped job's entries failed";
+      throw Fail{KMC_ERR_OUT_OF_MEMORY};
+    }
     if (g_out) {
-      check(c, hipMemcpyAsync(acc_k + n_out_total * J.kw, gk_out, g_out * J.kw * 8,
+      check(c, hipMemcpyAsync(acc.k + n_out_total * J.kw, gk_out, g_out * J.kw * 8,
                               hipMemcpyDeviceToHost, s), "D2H");
-      check(c, hipMemcpyAsync(acc_c + n_out_total, gc_out, g_out * 4, hipMemcpyDeviceToHost,
+      check(c, hipMemcpyAsync(acc.c + n_out_total, gc_out, g_out * 4, hipMemcpyDeviceToHost,
                               s), "D2H");
     }
     check(c, hipStreamSynchronize(s), "sync");
@@ -960,6 +1023,7 @@ void run_count(kmc_ctx* c, const kmc_reads* R, const kmc_params* P, kmc_table* T
     acc_phase[1] += 1e3 * ev_ms(c->ev[3], c->ev[4]);
     acc_phase[2] += 1e3 * ev_ms(c->ev[4], c->ev[29]);
   }
+  if (grouped) pool_next_group(c);  // every group's entries are in host memory
   st.n_tiles = n_tiles_all;
   st.n_big_tiles = big_tiles;
   st.n_big_keys = big_keys;
@@ -1018,9 +1082,9 @@ void run_count(kmc_ctx* c, const kmc_reads* R, const kmc_params* P, kmc_table* T
   } else if (out_k && n_out) {
     // a grouped job's entries into the device table
     check(c, hipEventRecord(c->ev[28], s), "event");
-    check(c, hipMemcpyAsync(out_k, acc_k, n_out * J.kw * 8, hipMemcpyHostToDevice, s),
+    check(c, hipMemcpyAsync(out_k, acc.k, n_out * J.kw * 8, hipMemcpyHostToDevice, s),
           "H2D table");
-    check(c, hipMemcpyAsync(out_c, acc_c, n_out * 4, hipMemcpyHostToDevice, s), "H2D table");
+    check(c, hipMemcpyAsync(out_c, acc.c, n_out * 4, hipMemcpyHostToDevice, s), "H2D table");
   } else {
     check(c, hipEventRecord(c->ev[28], s), "event");
   }
@@ -1049,13 +1113,16 @@ void run_count(kmc_ctx* c, const kmc_reads* R, const kmc_params* P, kmc_table* T
   check(c, hipEventRecord(c->ev[5], s), "event");
   const bool want_host = !(J.flags & KMC_FLAG_DEVICE_TABLE) && !c->user_keys;
   if (want_host && grouped && !(J.flags & KMC_FLAG_ASCENDING)) {
-    // a grouped job's host table: the entries collected in host memory
+    // a grouped job's host table: the block that collected the entries
     T->on_device = 0;
-    host_table(T, n_out, J.kw);
-    if (n_out) {
-      std::memcpy(T->keys, acc_k, n_out * J.kw * 8);
-      std::memcpy(T->counts, acc_c, n_out * 4);
+    if (!acc.reserve(1, 0, J.kw)) {  // (a job without entries)
+      c->err = "pinned host allocation of the table failed";
+      throw Fail{KMC_ERR_OUT_OF_MEMORY};
     }
+    T->keys = acc.k;
+    T->counts = acc.c;
+    T->reserved = 3;
+    acc.blk = nullptr;
   } else if (want_host) {
     // a host table copied out of the device table (or the staging buffers)
     uint64_t* dk = out_k;
@@ -1309,7 +1376,7 @@ void kmc::ctx_release_buffers(kmc_ctx* c) {
   (void)hipSetDevice(c->device);
   if (c->stream) (void)hipStreamSynchronize(c->stream);
   for (auto& b : c->buf) {
-    if (b.p) (void)hipFree(b.p);
+    if (b.p && !c->pool_base) (void)hipFree(b.p);
     b.p = nullptr;
     b.cap = 0;
   }
@@ -1318,6 +1385,18 @@ void kmc::ctx_release_buffers(kmc_ctx* c) {
   c->spill.cap = 0;
 }
 void kmc::ctx_set_budget(kmc_ctx* c, uint64_t bytes) { c->budget = bytes; }
+void kmc::ctx_lend_region(kmc_ctx* c, void* base, size_t bytes) {
+  kmc::ctx_release_buffers(c);
+  c->pool_base = static_cast<uint8_t*>(base);
+  c->pool_bytes = bytes;
+  c->pool_top = c->pool_mark = 0;
+}
+void kmc::ctx_end_region(kmc_ctx* c) {
+  if (c->stream) (void)hipStreamSynchronize(c->stream);
+  for (auto& b : c->buf) b = DevBuf{};  // inside the lent region: not freed here
+  c->pool_base = nullptr;
+  c->pool_bytes = c->pool_top = c->pool_mark = 0;
+}
 void kmc::ctx_copy_tuning(kmc_ctx* dst, const kmc_ctx* src) {
   dst->has_knobs = src->has_knobs;
   dst->knobs = src->knobs;

@@ -265,6 +265,14 @@ constexpr int kCtxAuxBuffers = 12;
 void* ctx_aux_buffer(kmc_ctx* c, int slot, size_t bytes);
 // Set the context's memory budget (as kmc_ctx_set_budget).
 void ctx_set_budget(kmc_ctx* c, uint64_t bytes);
+// Lend the context a device region: its buffers are released, and until
+// ctx_end_region every device buffer of its jobs is taken from the region
+// (a job that needs more fails with KMC_ERR_OUT_OF_MEMORY).  Pair it with a
+// budget no larger than the region.
+void ctx_lend_region(kmc_ctx* c, void* base, size_t bytes);
+// Give the region back (after the stream is idle); the context allocates its
+// own buffers again.
+void ctx_end_region(kmc_ctx* c);
 // Knobs: copy src's override and tuned knobs into dst; tuned knobs of the
 // class of (key_words, n_bases); the batch pool's worker count (0 = default);
 // override (k non-null) or clear it, returning whether one was set.

@@ -155,22 +155,17 @@ void serve(kmc_server* s, kmc_ctx* w) {
     lk.unlock();
     kmc_table* t = nullptr;
     kmc_status st;
-    if (j->oversize) {
-      // alone, inside the budget: the arena is handed back for the job's
-      // duration (no other job runs), and the job's own buffers are bounded
-      // by the budget (bin groups, records spilled to pinned host memory);
-      // then the arena is reserved again
+    if (j->oversize && s->arena) {
+      // alone, inside the budget: no other job runs, so the job's device
+      // buffers are taken from the arena, and the budget bounds them (bin
+      // groups, records spilled to pinned host memory)
       (void)hipSetDevice(s->device);
-      if (s->arena) (void)hipFree(s->arena);
-      s->arena = nullptr;
       kmc::ctx_set_budget(w, s->budget);
+      kmc::ctx_lend_region(w, s->arena, s->budget);
       st = kmc_count_ex(w, &j->job.reads, &j->job.params, nullptr, &t);
+      kmc::ctx_end_region(w);
       kmc::ctx_set_budget(w, 0);
-      kmc::ctx_release_buffers(w);
-      if (hipMalloc(&s->arena, s->budget) != hipSuccess) {
-        (void)hipGetLastError();
-        s->arena = nullptr;  // later jobs fail with KMC_ERR_OUT_OF_MEMORY
-      }
+      kmc::ctx_release_buffers(w);  // the spilled records' host memory
     } else if (!s->arena) {
       st = KMC_ERR_OUT_OF_MEMORY;
     } else {

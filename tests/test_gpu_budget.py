@@ -141,3 +141,55 @@ def test_server_oversize_job_within_budget(kmc):
     assert outs[1].stats["n_groups"] >= 2
     assert st["peak_admitted_bytes"] <= budget and st["completed"] == 3
     ctx.close()
+
+
+@pytest.mark.parametrize("name,scale", [("genome-5M-2Mx100", 0.05),
+                                        ("repeats-50M-30x150-k55", 0.01)])
+def test_server_oversize_job_records_on_device(kmc, name, scale):
+    # an oversize served job whose records stay on the device: its buffers
+    # come from the server's arena, group after group; host, device and
+    # ascending tables equal the job's table counted alone (and the oracle's)
+    import torch
+    seq, off, p = synth.make(name, scale)
+    s, o = dev(seq, off)
+    small = synth.make("genome-5M-2Mx100", 0.002)
+    ctx = kmc.Context(0)
+    ref = ctx.count(s, o, *args(p))
+    ref_small = ctx.count(small[0], small[1], *args(small[2]))
+    n_kmers, n_rec = ref.stats["n_kmers"], ref.stats["n_superkmers"]
+    rec_bytes = int(n_rec * (16 if p["k"] <= 32 else 32) * 1.3) + 256 * p["n_bins"] * 32
+    budget = 2 * rec_bytes + (24 << 20) + per_kmer(p["k"]) * n_kmers // 3
+    assert ctx.workspace_size(s, o, *args(p)) > budget
+    srv = kmc.Server(ctx, hbm_budget=budget, max_active=2)
+    tickets = [srv.submit(small[0], small[1], *args(small[2])), srv.submit(s, o, *args(p)),
+               srv.submit(s, o, *args(p), flags=kmc.FLAG_ASCENDING),
+               srv.submit(s, o, *args(p), flags=kmc.FLAG_DEVICE_TABLE),
+               srv.submit(small[0], small[1], *args(small[2]))]
+    outs = [srv.poll(t) for t in tickets]
+    st = srv.stats()
+    srv.stop()
+    same(outs[0], ref_small)
+    same(outs[4], ref_small)
+    same(outs[1], ref)
+    assert outs[1].stats["n_groups"] >= 2 and outs[1].stats["records_spilled"] == 0
+    ok_keys, ok_counts = oracle.count(seq, off, p["k"], p["cutoff_min"], p["cutoff_max"],
+                                      threads=8)
+    assert np.array_equal(outs[2].keys, ok_keys) and np.array_equal(outs[2].counts, ok_counts)
+    dt = outs[3]
+    assert dt.on_device and dt.n == ref.n and dt.stats["n_groups"] >= 2
+    kw = 1 if p["k"] <= 32 else 2
+    k = torch.empty(dt.n * kw, dtype=torch.int64, device="cuda:0")
+    c = torch.empty(dt.n, dtype=torch.int32, device="cuda:0")
+    import ctypes
+    hip = ctypes.CDLL("libamdhip64.so")
+    assert hip.hipMemcpy(ctypes.c_void_p(k.data_ptr()), ctypes.c_void_p(dt.keys_ptr),
+                         ctypes.c_size_t(dt.n * kw * 8), 3) == 0
+    assert hip.hipMemcpy(ctypes.c_void_p(c.data_ptr()), ctypes.c_void_p(dt.counts_ptr),
+                         ctypes.c_size_t(dt.n * 4), 3) == 0
+    dk = k.cpu().numpy().view(np.uint64)
+    assert np.array_equal(dk.reshape(-1, 2) if kw == 2 else dk, ref.keys)
+    assert np.array_equal(c.cpu().numpy().view(np.uint32), ref.counts)
+    assert st["completed"] == 5 and st["peak_admitted_bytes"] <= budget
+    for r in outs:
+        r.free()
+    ctx.close()
