@@ -43,23 +43,39 @@ template <> struct Rec<1> {
     R = (R >> 2) | ((uint64_t)(3u - c) << (2 * k - 2));
   }
 };
+// 128-bit keys (33 <= k <= 64) as high and low words: every shift by an
+// amount that depends on k stays inside one word (the reverse complement's
+// new symbol enters the high word at bit 2k - 66), where a 128-bit shift by a
+// run-time amount costs selects between the words at each step.
 template <> struct Rec<2> {
-  u128 F, R, T;
+  uint64_t Fh, Fl, Rh, Rl, Th, Tl;
   uint32_t n;
   bool canon;
   __device__ void load(const uint64_t* r, uint32_t k, bool canonical = true) {
-    F = ((u128)r[0] << 64) | r[1];
-    T = ((u128)r[2] << 64) | r[3];
-    n = (uint32_t)(r[3] & 0xFFu);
-    R = revcomp128(F, k);
+    Fh = r[0];
+    Fl = r[1];
+    Th = r[2];
+    Tl = r[3];
+    n = (uint32_t)(Tl & 0xFFu);
+    const u128 R = revcomp128(((u128)Fh << 64) | Fl, k);
+    Rh = (uint64_t)(R >> 64);
+    Rl = (uint64_t)R;
     canon = canonical;
   }
-  __device__ u128 key() const { return canon && R < F ? R : F; }
+  // the canonical key is the reverse complement
+  __device__ bool rev() const { return canon && (Rh < Fh || (Rh == Fh && Rl < Fl)); }
+  __device__ u128 key() const {
+    const bool r = rev();
+    return ((u128)(r ? Rh : Fh) << 64) | (r ? Rl : Fl);
+  }
   __device__ void step(uint32_t k, u128 kmask) {
-    const uint32_t c = (uint32_t)(T >> 126);
-    T <<= 2;
-    F = ((F << 2) | (u128)c) & kmask;
-    R = (R >> 2) | ((u128)(3u - c) << (2 * k - 2));
+    const uint64_t c = Th >> 62;
+    Th = (Th << 2) | (Tl >> 62);
+    Tl <<= 2;
+    Fh = ((Fh << 2) | (Fl >> 62)) & (uint64_t)(kmask >> 64);
+    Fl = (Fl << 2) | c;
+    Rl = (Rl >> 2) | (Rh << 62);
+    Rh = (Rh >> 2) | ((3 - c) << (2 * k - 66));
   }
 };
 
@@ -70,19 +86,23 @@ __device__ __forceinline__ uint32_t top_bits(uint64_t key, uint32_t k, uint32_t 
 __device__ __forceinline__ uint32_t top_bits(u128 key, uint32_t k, uint32_t bits) {
   return (uint32_t)(key >> (2 * k - bits));
 }
+// the same for a 128-bit key as words, sh = 2k - bits (>= 1)
+__device__ __forceinline__ uint32_t top_bits2(uint64_t h, uint64_t l, uint32_t sh) {
+  return sh >= 64 ? (uint32_t)(h >> (sh - 64)) : (uint32_t)((h << (64 - sh)) | (l >> sh));
+}
 
 // The top b bits of a canonical key, min(F, R) >> (2k - b), are min(F >> (2k
 // - b), R >> (2k - b)): a shift keeps the order.  So a walk that needs only
 // those bits keeps the forward key and just the top bits of the reverse
 // complement, which roll on their own: R' = (R >> 2) | (3 - c) << (2k - 2)
 // gives top(R') = (top(R) >> 2) | (3 - c) << (b - 2) (b >= 2).
-template <int KW> struct RecTop {
-  typedef typename KeyOf<KW>::T K;
-  K F, T;
+template <int KW> struct RecTop;
+template <> struct RecTop<1> {
+  uint64_t F, T;
   uint32_t rt, n;
   bool canon;
   __device__ void load(const uint64_t* r, uint32_t k, uint32_t sh, bool canonical) {
-    Rec<KW> full;
+    Rec<1> full;
     full.load(r, k);
     F = full.F;
     T = full.T;
@@ -94,10 +114,34 @@ template <int KW> struct RecTop {
     const uint32_t f = (uint32_t)(F >> sh);
     return canon ? min(f, rt) : f;
   }
-  __device__ void step(K kmask, uint32_t bits) {
-    const uint32_t c = (uint32_t)(T >> (8 * sizeof(K) - 2));
+  __device__ void step(uint64_t kmask, uint32_t bits) {
+    const uint32_t c = (uint32_t)(T >> 62);
     T <<= 2;
-    F = ((F << 2) | (K)c) & kmask;
+    F = ((F << 2) | c) & kmask;
+    rt = (rt >> 2) | ((3u - c) << (bits - 2));
+  }
+};
+template <> struct RecTop<2> {
+  u128 F, T;
+  uint32_t rt, n;
+  bool canon;
+  __device__ void load(const uint64_t* r, uint32_t k, uint32_t sh, bool canonical) {
+    Rec<2> full;
+    full.load(r, k);
+    F = ((u128)full.Fh << 64) | full.Fl;
+    T = ((u128)full.Th << 64) | full.Tl;
+    n = full.n;
+    rt = top_bits2(full.Rh, full.Rl, sh);
+    canon = canonical;
+  }
+  __device__ uint32_t top(uint32_t sh) const {
+    const uint32_t f = (uint32_t)(F >> sh);
+    return canon ? min(f, rt) : f;
+  }
+  __device__ void step(u128 kmask, uint32_t bits) {
+    const uint32_t c = (uint32_t)(T >> 126);
+    T <<= 2;
+    F = ((F << 2) | (u128)c) & kmask;
     rt = (rt >> 2) | ((3u - c) << (bits - 2));
   }
 };
@@ -455,18 +499,25 @@ k_expand_scatter(KeyCfg kc, TaskMap tm,
     }
     Rec<KW> rec;
     rec.load(my, kc.k, canon);
-    for (uint32_t i = 0;; ++i) {
-      const K key = rec.key();
-      const uint32_t t = tof[top_bits(key, kc.k, kc.fine_bits)];
-      const uint64_t g = kb + delta[t] + atomicAdd(&cnt[t], 1u);
-      if (KW == 1) {
-        keys[g] = (uint64_t)key;
-      } else {
-        keys[2 * g] = (uint64_t)((u128)key >> 64);
-        keys[2 * g + 1] = (uint64_t)key;
+    if constexpr (KW == 2) {
+      const uint32_t sh = 2 * kc.k - kc.fine_bits;
+      for (uint32_t i = 0;; ++i) {
+        const bool r = rec.rev();
+        const uint64_t h = r ? rec.Rh : rec.Fh, l = r ? rec.Rl : rec.Fl;
+        const uint32_t t = tof[top_bits2(h, l, sh)];
+        const uint64_t g = delta[t] + atomicAdd(&cnt[t], 1u);
+        reinterpret_cast<ulonglong2*>(keys)[g] = make_ulonglong2(h, l);
+        if (i + 1 >= rec.n) break;
+        rec.step(kc.k, kmask);
       }
-      if (i + 1 >= rec.n) break;
-      rec.step(kc.k, kmask);
+    } else {
+      for (uint32_t i = 0;; ++i) {
+        const K key = rec.key();
+        const uint32_t t = tof[top_bits(key, kc.k, kc.fine_bits)];
+        keys[kb + delta[t] + atomicAdd(&cnt[t], 1u)] = (uint64_t)key;
+        if (i + 1 >= rec.n) break;
+        rec.step(kc.k, kmask);
+      }
     }
   };
   // reserve each tile's range; cnt then becomes the running slot

@@ -477,7 +477,12 @@ struct HashShared2 {
   uint32_t C2[kRankMax];    // counts of the kept keys (keys in K[0, kept))
   uint64_t red[4 * kSortThreads / 64];
   uint32_t tmp[kSortThreads / 64];
+  // the occupied slots, in claiming order (a tile holds at most DIRECT keys)
+  uint16_t L[3 * kHashSlots2 / 4];
+  uint32_t n_claimed;
 };
+// three workgroups per compute unit
+static_assert(3 * sizeof(HashShared2) <= 160 * 1024, "LDS of the 128-bit tile kernel");
 
 __device__ __forceinline__ uint64_t mix128(u128 x) {
   uint64_t h = (uint64_t)x * 0x9E3779B97F4A7C15ull ^ (uint64_t)(x >> 64) * 0xD6E8FEB86659FD93ull;
@@ -529,36 +534,46 @@ __device__ uint32_t count_tile_hash2(u128 (&key)[SortCfg<2>::ITEMS], uint32_t n,
             ov = atomicCAS(reinterpret_cast<unsigned long long*>(&S.F[slot]), 0ull,
                            (unsigned long long)((fp[u] << 16) | 1u));
           }
-          if (ov == 0)
+          if (ov == 0) {
             S.K[slot] = key[g + u];
-          else
+            S.L[atomicAdd(&S.n_claimed, 1u)] = (uint16_t)slot;
+          } else {
             atomicAdd(reinterpret_cast<unsigned long long*>(&S.F[slot]), 1ull);
+          }
           slot_of[g + u] = slot;
         }
       }
     }
   }
   __syncthreads();
+  const uint32_t nd = S.n_claimed;  // distinct keys (slots claimed)
   bool clash = false;
 #pragma unroll
   for (uint32_t m = 0; m < ITEMS; ++m)
     if (m * nt + tid < n && S.K[slot_of[m]] != key[m]) clash = true;
-  if (__syncthreads_or(clash)) {
+  const bool any_clash = __syncthreads_or(clash);  // every thread has read nd
+  if (tid == 0) S.n_claimed = 0;  // the barriers below order this before the next tile
+  if (any_clash) {
     for (uint32_t i = tid; i < T; i += nt) S.F[i] = 0;
     __syncthreads();
     return kFingerprintClash;
   }
-  // read back (and clear) every slot; an empty slot reads 0
+  // read back (and clear) the claimed slots only (at most DIRECT: the first
+  // RB entries of each thread); the other entries count 0
+  constexpr uint32_t RB = (SortCfg<2>::DIRECT + nt - 1) / nt;
   uint32_t cnt[ITEMS];
 #pragma unroll
   for (uint32_t i = 0; i < ITEMS; ++i) {
-    const uint32_t s = i * nt + tid;
-    const uint64_t w = S.F[s];
-    key[i] = S.K[s];
-    cnt[i] = (uint32_t)(w & 0xFFFFu);
+    const uint32_t j = i * nt + tid;
+    cnt[i] = 0;
+    if (i < RB && i * nt < nd && j < nd) {
+      const uint32_t s = S.L[j];
+      const uint64_t w = S.F[s];
+      key[i] = S.K[s];
+      cnt[i] = (uint32_t)(w & 0xFFFFu);
+      S.F[s] = 0;
+    }
   }
-#pragma unroll
-  for (uint32_t i = 0; i < ITEMS; ++i) S.F[i * nt + tid] = 0;
   uint32_t nh = 0, nk = 0;
   u128 a = ~(u128)0, o = 0;
 #pragma unroll
@@ -950,6 +965,7 @@ k_tile_hash2(KeyCfg kc, const Tile* __restrict__ tiles, uint64_t n_tiles, uint64
   constexpr uint32_t ITEMS = SortCfg<2>::ITEMS;
   __shared__ HashShared2 S;
   for (uint32_t i = threadIdx.x; i < kHashSlots2; i += blockDim.x) S.F[i] = 0;
+  if (threadIdx.x == 0) S.n_claimed = 0;
   __syncthreads();
   // the next tile's keys are loaded into registers while the current tile
   // is counted (double buffering)
