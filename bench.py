@@ -404,8 +404,9 @@ def bench_serve(args):
 
 def serve_large_mix(ctx, kmc, djobs, job, sat, args):
     """The served form's large job (60M reads x 150 bp, 9 Gbases, k = 28)
-    submitted first, beside Poisson arrivals of the pool's jobs at half the
-    saturation rate, for each budget; the large job's table must equal its
+    beside Poisson arrivals of the pool's jobs at half the saturation rate,
+    for each budget: submitted first, and submitted after the 20th arrival
+    (pool jobs running and queued); the large job's table must equal its
     table counted alone."""
     import queue
     import threading
@@ -430,7 +431,8 @@ def serve_large_mix(ctx, kmc, djobs, job, sat, args):
     alone.free()
     res = {"large_job": {"n_bases": int(dl[0].numel()), "alone_device_ms": alone_ms,
                          "entries": ref[0]}}
-    for label, budget in (("full", 0), ("24GB", 24 << 30)):
+    for label, budget, at in (("full", 0, 0), ("24GB", 24 << 30, 0), ("full, mid-stream", 0, 20),
+                              ("24GB, mid-stream", 24 << 30, 20)):
         srv = kmc.Server(ctx, hbm_budget=budget, max_active=args.max_active)
         n = args.serve_arrivals
         rng = np.random.default_rng(9)
@@ -447,7 +449,7 @@ def serve_large_mix(ctx, kmc, djobs, job, sat, args):
         th = threading.Thread(target=poller)
         th.start()
         t0 = time.perf_counter()
-        big = srv.submit(*largs)
+        big = srv.submit(*largs) if at == 0 else None
         nxt = t0
         for i in range(n):
             nxt += gaps[i]
@@ -455,8 +457,11 @@ def serve_large_mix(ctx, kmc, djobs, job, sat, args):
             if d > 0:
                 time.sleep(d)
             tickets.put(srv.submit(*job(i)))
+            if i + 1 == at:
+                big = srv.submit(*largs)
         r = srv.poll(big)
         big_ms = r.stats["us_latency"] * 1e-3
+        big_queue_ms = r.stats["us_queue"] * 1e-3
         same = digest(r) == ref
         groups, spilled = r.stats["n_groups"], r.stats["records_spilled"]
         r.free()
@@ -464,7 +469,9 @@ def serve_large_mix(ctx, kmc, djobs, job, sat, args):
         span = time.perf_counter() - t0
         st = srv.stats()
         srv.stop()
-        res[label] = {"budget_bytes": st["budget"], "large_latency_ms": big_ms,
+        res[label] = {"budget_bytes": st["budget"], "large_after_arrivals": at,
+                      "large_latency_ms": big_ms, "large_queue_ms": big_queue_ms,
+                      "peak_admitted_bytes": st["peak_admitted_bytes"],
                       "large_n_groups": groups, "large_records_spilled": spilled,
                       "large_table_as_alone": same, "small_jobs": n,
                       "small_latency_ms_p50": float(np.percentile(lat, 50)),

@@ -329,11 +329,13 @@ kmc_status kmc_autotune(kmc_ctx* ctx, const kmc_job* jobs, uint32_t n_jobs,
  * its footprint (kmc_workspace_size) fits the HBM budget next to the jobs
  * already admitted, and up to max_active admitted jobs run at once, each on
  * its own stream; as one finishes the next admissible job starts (continuous
- * batching).  A job larger than the whole budget runs alone, within the
- * budget: its device buffers are taken from the reserved arena and bounded
- * by the budget as under kmc_ctx_set_budget (bin groups, records in pinned
- * host memory); its device table, if requested, is allocated beside the
- * budget. */
+ * batching).  A job larger than the whole budget runs in a region of the
+ * reserved arena: the whole arena less room for the largest other job queued
+ * or running, when that leaves at least three quarters of it (that job runs
+ * beside it), else the whole arena (the other jobs wait).  Its device
+ * buffers are taken from that region and bounded by it as under
+ * kmc_ctx_set_budget (bin groups, records in pinned host memory); its device
+ * table, if requested, is allocated beside the budget. */
 typedef struct kmc_server_cfg {
   uint64_t hbm_budget; /* bytes; 0 = 90% of the device memory free at start */
   uint32_t max_active; /* 1..16 jobs running at once; 0 = 4 */

@@ -56,7 +56,9 @@ struct SrvJob {
   uint64_t ticket = 0;
   kmc_job job{};
   size_t footprint = 0;
-  bool oversize = false;  // larger than the whole budget: runs alone, bounded by it
+  // larger than the whole budget: runs in a region of the arena (footprint
+  // = the region, chosen when it is admitted), bounded by it
+  bool oversize = false;
   uint32_t bypassed = 0;
   int state = 0;  // 0 queued, 1 running, 2 done
   kmc_status st = KMC_OK;
@@ -78,13 +80,20 @@ struct kmc_server {
   std::unordered_map<uint64_t, SrvJob*> jobs;
   uint64_t next_ticket = 1;
   bool stopping = false;
-  bool exclusive = false;  // an oversize job is running
   kmc_server_stats stats{};
   std::vector<kmc_ctx*> workers;
   std::vector<std::thread> threads;
 };
 
 namespace {
+
+// An oversize job runs in a region of the arena (bin groups and spilled
+// records keep it inside): the whole arena less room for the largest other
+// job queued or running, when that leaves at least kOversizeShare of it (so
+// such jobs run beside it), else the whole arena (they wait).  A smaller
+// region costs the job more bin groups, and records spilled to host memory
+// once they exceed half of it.
+constexpr double kOversizeShare = 0.75;
 
 // First fit in the arena.
 bool arena_take(kmc_server* s, size_t bytes, size_t* off) {
@@ -121,11 +130,24 @@ void arena_give(kmc_server* s, size_t off, size_t bytes) {
 // footprint does not fit now may be overtaken by later jobs that do, at most
 // kMaxBypass times; after that it holds back the jobs behind it until it fits.
 // Called with the lock held.
+size_t oversize_region(kmc_server* s) {
+  size_t beside = 0;
+  for (const SrvJob* q : s->queue)
+    if (!q->oversize) beside = std::max(beside, align256(q->footprint));
+  for (const auto& kv : s->jobs)
+    if (kv.second->state == 1 && !kv.second->oversize)
+      beside = std::max(beside, align256(kv.second->footprint));
+  const size_t least = (size_t)(kOversizeShare * (double)s->budget);
+  if (beside && s->budget - std::min<size_t>(beside, s->budget) >= least)
+    return (s->budget - beside) & ~(size_t)255;
+  return s->budget;
+}
+
 SrvJob* pick(kmc_server* s) {
-  if (s->exclusive) return nullptr;
   for (auto it = s->queue.begin(); it != s->queue.end(); ++it) {
     SrvJob* j = *it;
-    const bool ok = j->oversize ? s->stats.active == 0 : arena_take(s, j->footprint, &j->ws_off);
+    if (j->oversize) j->footprint = oversize_region(s);
+    const bool ok = arena_take(s, j->footprint, &j->ws_off);
     if (ok) {
       for (auto jt = s->queue.begin(); jt != it; ++jt) (*jt)->bypassed++;
       s->queue.erase(it);
@@ -146,22 +168,18 @@ void serve(kmc_server* s, kmc_ctx* w) {
     j->t_start = now_us();
     s->stats.active++;
     s->stats.queued = (uint32_t)s->queue.size();
-    if (j->oversize) {
-      s->exclusive = true;
-    } else {
-      s->stats.admitted_bytes += align256(j->footprint);
-      s->stats.peak_admitted_bytes = std::max(s->stats.peak_admitted_bytes, s->stats.admitted_bytes);
-    }
+    s->stats.admitted_bytes += align256(j->footprint);
+    s->stats.peak_admitted_bytes = std::max(s->stats.peak_admitted_bytes, s->stats.admitted_bytes);
     lk.unlock();
     kmc_table* t = nullptr;
     kmc_status st;
     if (j->oversize && s->arena) {
-      // alone, inside the budget: no other job runs, so the job's device
-      // buffers are taken from the arena, and the budget bounds them (bin
-      // groups, records spilled to pinned host memory)
+      // its region of the arena lent to the worker's context, which takes
+      // every device buffer of the job from it; the region is the job's
+      // budget (bin groups, records spilled to pinned host memory)
       (void)hipSetDevice(s->device);
-      kmc::ctx_set_budget(w, s->budget);
-      kmc::ctx_lend_region(w, s->arena, s->budget);
+      kmc::ctx_set_budget(w, j->footprint);
+      kmc::ctx_lend_region(w, s->arena + j->ws_off, j->footprint);
       st = kmc_count_ex(w, &j->job.reads, &j->job.params, nullptr, &t);
       kmc::ctx_end_region(w);
       kmc::ctx_set_budget(w, 0);
@@ -178,12 +196,8 @@ void serve(kmc_server* s, kmc_ctx* w) {
       t->stats.us_latency = t_done - j->t_submit;
     }
     lk.lock();
-    if (j->oversize) {
-      s->exclusive = false;
-    } else {
-      arena_give(s, j->ws_off, j->footprint);
-      s->stats.admitted_bytes -= align256(j->footprint);
-    }
+    arena_give(s, j->ws_off, j->footprint);
+    s->stats.admitted_bytes -= align256(j->footprint);
     s->stats.active--;
     j->st = st;
     j->table = t;

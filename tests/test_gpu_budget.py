@@ -120,9 +120,9 @@ def test_bin_above_budget_rejected(kmc):
 
 
 def test_server_oversize_job_within_budget(kmc):
-    # a job whose footprint exceeds the server's budget runs alone, grouped
-    # and spilled inside it; the same table as alone, and the jobs around it
-    # still served
+    # a job whose footprint exceeds the server's budget runs in three
+    # quarters of it, grouped and spilled; the same table as alone, and the
+    # jobs around it still served
     big = synth.make("genome-5M-2Mx100", 0.05)
     small = synth.make("genome-5M-2Mx100", 0.002)
     ctx = kmc.Context(0)
@@ -147,8 +147,9 @@ def test_server_oversize_job_within_budget(kmc):
                                         ("repeats-50M-30x150-k55", 0.01)])
 def test_server_oversize_job_records_on_device(kmc, name, scale):
     # an oversize served job whose records stay on the device: its buffers
-    # come from the server's arena, group after group; host, device and
-    # ascending tables equal the job's table counted alone (and the oracle's)
+    # come from its region of the server's arena, group after group; host,
+    # device and ascending tables equal the job's table counted alone (and
+    # the oracle's)
     import torch
     seq, off, p = synth.make(name, scale)
     s, o = dev(seq, off)
@@ -158,7 +159,8 @@ def test_server_oversize_job_records_on_device(kmc, name, scale):
     ref_small = ctx.count(small[0], small[1], *args(small[2]))
     n_kmers, n_rec = ref.stats["n_kmers"], ref.stats["n_superkmers"]
     rec_bytes = int(n_rec * (16 if p["k"] <= 32 else 32) * 1.3) + 256 * p["n_bins"] * 32
-    budget = 2 * rec_bytes + (24 << 20) + per_kmer(p["k"]) * n_kmers // 3
+    # the job runs in three quarters of the budget
+    budget = (2 * rec_bytes + (24 << 20) + per_kmer(p["k"]) * n_kmers // 3) * 4 // 3
     assert ctx.workspace_size(s, o, *args(p)) > budget
     srv = kmc.Server(ctx, hbm_budget=budget, max_active=2)
     tickets = [srv.submit(small[0], small[1], *args(small[2])), srv.submit(s, o, *args(p)),
