@@ -135,6 +135,8 @@ def test_server_oversize_job_runs_alone(ctx, kmc):
     large = synth.make("genome-5M-2Mx100", 0.02)
     fp_small = ctx.workspace_size(small[0], small[1], *args(small[2]))
     fp_large = ctx.workspace_size(large[0], large[1], *args(large[2]))
+    # room for a small job beside the large one would leave it less than
+    # three quarters of the budget, so it takes the whole arena, alone
     budget = 2 * fp_small + 4096
     assert fp_large > budget
     srv = kmc.Server(ctx, hbm_budget=budget, max_active=2)
