@@ -337,7 +337,9 @@ k_fine_hist(KeyCfg kc, TaskMap tm, const uint64_t* __restrict__ records, uint32_
 // -------------------------------------------------------------- plan tiles
 // One workgroup per bin.  Consecutive fine ranges are packed greedily into
 // tiles of at most tile_limit keys: a tile is closed when the next range would
-// take it past the limit (a range larger than the limit is a tile of its own).
+// take it past the limit (a range larger than the limit is a tile of its own,
+// a big tile, which with big_merge set also takes the following ranges while
+// it holds at most big_merge keys).
 // Two consecutive tiles then hold more than tile_limit keys together, so a bin
 // of T keys needs at most 2 * ceil(T / tile_limit) + 1 tiles; slots beyond
 // the ones used stay empty (the tile array is zeroed beforehand).
@@ -377,6 +379,18 @@ k_plan_tiles(KeyCfg kc, const uint32_t* __restrict__ fine_hist, const uint64_t* 
     uint32_t q = lo;
     // a tile still empty at q1 takes range q1 too (a range over the limit)
     if (q < nf && start[q] == s0) ++q;
+    if (kc.big_merge && start[min(q, nf)] - s0 > lim) {
+      // a big tile: the following ranges too, while it holds at most
+      // big_merge keys (q2: the smallest q2 >= q with start[q2 + 1] > s0 +
+      // big_merge, nf if none)
+      uint32_t lo2 = q, hi2 = nf;
+      while (lo2 < hi2) {
+        const uint32_t mid = (lo2 + hi2) >> 1;
+        if (start[mid + 1] > s0 + kc.big_merge) hi2 = mid;
+        else lo2 = mid + 1;
+      }
+      q = max(q, lo2);
+    }
     nxt[r] = (uint16_t)min(q, nf);
   }
   __syncthreads();

@@ -137,6 +137,9 @@ struct KeyCfg {
   // their k-mers, each weighted by the (k,x)-mer's count
   uint32_t kx = 0;
   uint32_t kx_pass = 0;
+  // a tile over tile_limit (a big tile) also takes the fine ranges after it
+  // while it holds at most big_merge keys (0: a big tile is one range)
+  uint32_t big_merge = 0;
 };
 
 // bin[t] for every task t of two task maps (pre arrays of n_bins + 1).

@@ -176,6 +176,24 @@ def test_one_huge_bin(ctx, k, p, n_reads):
     check_table(res, seq, off, k, p, 1, 2**32 - 1)
 
 
+def test_merged_big_tiles_streamed(ctx):
+    # every k-mer in one bin, reads drawn without errors from a 100 kbp
+    # reference (about 70x): each fine range holds more keys than the tile
+    # limit but few distinct keys, so big tiles take the following ranges up
+    # to four limits and are counted by streaming (mean big tile well above
+    # one range)
+    rng = np.random.default_rng(77)
+    ref = rng.choice(np.frombuffer(b"ACGT", dtype=np.uint8), size=100_000)
+    n_reads = 200_000
+    st = rng.integers(0, ref.size - 100, size=n_reads)
+    seq = ref[st[:, None] + np.arange(100)].reshape(-1)
+    off = np.arange(n_reads + 1, dtype=np.uint64) * 100
+    res = ctx.count(seq, off, 28, 7, 1, 1, 2**32 - 1)
+    big, keys = res.stats["n_big_tiles"], res.stats["n_big_keys"]
+    assert big > 0 and keys / big > 2 * 3072
+    check_table(res, seq, off, 28, 7, 1, 2**32 - 1)
+
+
 def test_skewed_ranges(ctx):
     # reads at 40x coverage in 64 bins: the k-mers that begin with their
     # signature fill fine ranges of several thousand keys (big tiles), about a
