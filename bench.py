@@ -692,8 +692,9 @@ def main():
         copy_calibration(args.copy_calibration)
         return
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
-        print("bench.py measures one GPU: the counting path runs on a single MI355X "
-              "(see DESIGN.md for how it would shard); run with --gpus 1", file=sys.stderr)
+        print("bench.py measures one GPU: every job of the counting path runs on a single "
+              "MI355X (jobs are independent; several GPUs would each take whole jobs); "
+              "run with --gpus 1", file=sys.stderr)
         sys.exit(2)
 
     if args.mode != "single":
