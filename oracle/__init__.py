@@ -55,6 +55,13 @@ def _load():
                                          ctypes.POINTER(ctypes.c_uint64),
                                          ctypes.POINTER(u64p), ctypes.POINTER(u32p)]
         lib.kmc_oracle_count.restype = ctypes.c_int
+        lib.kmc_oracle_count_slice.argtypes = [ctypes.c_void_p, ctypes.c_void_p,
+                                               ctypes.c_uint64, ctypes.c_uint32, ctypes.c_uint32,
+                                               ctypes.c_uint32, ctypes.c_int, ctypes.c_int,
+                                               ctypes.c_uint32, ctypes.c_uint64,
+                                               ctypes.POINTER(ctypes.c_uint64),
+                                               ctypes.POINTER(u64p), ctypes.POINTER(u32p)]
+        lib.kmc_oracle_count_slice.restype = ctypes.c_int
         lib.kmc_oracle_valid_windows.argtypes = [ctypes.c_void_p, ctypes.c_void_p,
                                                  ctypes.c_uint64, ctypes.c_uint32]
         lib.kmc_oracle_valid_windows.restype = ctypes.c_uint64
@@ -87,19 +94,22 @@ def _reads(seq, offsets):
 
 
 def count(seq, offsets, k: int, cutoff_min: int = 1, cutoff_max: int = 2**32 - 1,
-          threads: int = 1, canonical: bool = True, counter_max: int = 0):
+          threads: int = 1, canonical: bool = True, counter_max: int = 0,
+          slice_bits: int = 0, slice: int = 0):
     """Return (keys, counts): keys is uint64 [n] (k <= 32) or [n, 2] (hi, lo).
     canonical=False counts k-mers as read (supplement, -b); counter_max > 0
     stores min(count, counter_max), the cutoffs applying to the exact count
-    (supplement, -cs)."""
+    (supplement, -cs).  slice_bits > 0 keeps only the keys whose top
+    slice_bits bits (of the 2k-bit key) equal slice: that part of the whole
+    count, in memory proportional to it."""
     seq, offsets = _reads(seq, offsets)
     lib = _load()
     n = ctypes.c_uint64(0)
     kp = ctypes.POINTER(ctypes.c_uint64)()
     cp = ctypes.POINTER(ctypes.c_uint32)()
-    rc = lib.kmc_oracle_count(seq.ctypes.data, offsets.ctypes.data, offsets.size - 1, k,
-                              cutoff_min, cutoff_max, int(canonical), threads, ctypes.byref(n),
-                              ctypes.byref(kp), ctypes.byref(cp))
+    rc = lib.kmc_oracle_count_slice(seq.ctypes.data, offsets.ctypes.data, offsets.size - 1, k,
+                                    cutoff_min, cutoff_max, int(canonical), threads, slice_bits,
+                                    slice, ctypes.byref(n), ctypes.byref(kp), ctypes.byref(cp))
     if rc != 0:
         raise ValueError(f"oracle count failed ({rc})")
     kw = 1 if k <= 32 else 2

@@ -172,6 +172,8 @@ typedef struct {
   const uint64_t* offsets;
   uint64_t r0, r1;
   uint32_t k, shift;
+  uint32_t slice_bits;  /* 0: every key; else only keys whose top slice_bits */
+  uint64_t slice;       /* bits of the 2k-bit key equal slice */
   int canonical;
   int n_parts;
   uint64_t n_win;   /* valid windows of the share */
@@ -181,16 +183,16 @@ typedef struct {
   u128* sorted;
 } enum_t;
 
-static void* enum_count(void* arg) {
-  enum_t* E = (enum_t*)arg;
-  E->n_win = valid_windows_range(E->seq, E->offsets, E->r0, E->r1, E->k);
-  return NULL;
+/* Is key K (2k bits) in the share's slice? */
+static int in_slice(const enum_t* E, u128 K) {
+  return E->slice_bits == 0 || (uint64_t)(K >> (2 * E->k - E->slice_bits)) == E->slice;
 }
 
-/* Steps 1-2 on the share: every window whose k bytes are all valid ->
- * canonical key; and the partition histogram of the keys. */
-static void* enum_keys(void* arg) {
-  enum_t* E = (enum_t*)arg;
+/* Every window of the share whose k bytes are all valid, in read order:
+ * with keys == NULL only counted (of the slice), else its canonical key to
+ * keys[] when it is in the slice, with the partition histogram.  Returns the
+ * number of keys. */
+static uint64_t enum_windows(enum_t* E, u128* keys) {
   const uint32_t k = E->k;
   uint64_t n = 0;
   for (uint64_t r = E->r0; r < E->r1; ++r) {
@@ -200,13 +202,31 @@ static void* enum_keys(void* arg) {
       int ok = 1;
       for (uint32_t t = 0; t < k; ++t)
         if (sym_code(E->seq[j + t]) < 0) { ok = 0; break; }
-      if (ok) {
-        const u128 K = key_at(E->seq + j, k, E->canonical);
-        E->keys[n++] = K;
+      if (!ok) continue;
+      const u128 K = key_at(E->seq + j, k, E->canonical);
+      if (!in_slice(E, K)) continue;
+      if (keys) {
+        keys[n] = K;
         if (E->n_parts > 1) E->hist[(uint32_t)(K >> E->shift)]++;
       }
+      ++n;
     }
   }
+  return n;
+}
+
+static void* enum_count(void* arg) {
+  enum_t* E = (enum_t*)arg;
+  E->n_win = E->slice_bits ? enum_windows(E, NULL)
+                           : valid_windows_range(E->seq, E->offsets, E->r0, E->r1, E->k);
+  return NULL;
+}
+
+/* Steps 1-2 on the share: every window whose k bytes are all valid ->
+ * canonical key; and the partition histogram of the keys. */
+static void* enum_keys(void* arg) {
+  enum_t* E = (enum_t*)arg;
+  enum_windows(E, E->keys);
   return NULL;
 }
 
@@ -221,17 +241,22 @@ static void* enum_scatter(void* arg) {
 }
 
 /* Enumerate every canonical k-mer, sort, run-length count, apply cutoffs.
+ * With slice_bits > 0 only the keys whose top slice_bits bits (of the 2k-bit
+ * key) equal slice are kept from the enumeration on: the result is the part
+ * of the whole count in that key range, for inputs whose whole count would
+ * not fit in memory (a key's count does not depend on the other keys).
  * n_threads > 1 splits the reads into n_threads consecutive shares that are
  * enumerated in parallel, partitions the keys by their top 8 bits (so
  * partitions are key ranges in order) and sorts each partition on its own
  * thread.  Returns 0 on success, -1 on bad arguments, -2 on allocation
  * failure (nothing allocated is left behind).  *out_keys and *out_counts are
  * malloc'd; release them with kmc_oracle_free. */
-int kmc_oracle_count(const uint8_t* seq, const uint64_t* offsets, uint64_t n_reads,
-                     uint32_t k, uint32_t cutoff_min, uint32_t cutoff_max, int canonical,
-                     int n_threads, uint64_t* out_n, uint64_t** out_keys,
-                     uint32_t** out_counts) {
+int kmc_oracle_count_slice(const uint8_t* seq, const uint64_t* offsets, uint64_t n_reads,
+                           uint32_t k, uint32_t cutoff_min, uint32_t cutoff_max, int canonical,
+                           int n_threads, uint32_t slice_bits, uint64_t slice, uint64_t* out_n,
+                           uint64_t** out_keys, uint32_t** out_counts) {
   if (k < 1 || k > 64 || !out_n || !out_keys || !out_counts) return -1;
+  if (slice_bits > 2 * k || slice_bits > 32 || (slice_bits && slice >> slice_bits)) return -1;
   if (cutoff_min > cutoff_max) return -1;
   if (n_threads < 1) n_threads = 1;
   if (n_threads > 256) n_threads = 256;
@@ -263,6 +288,8 @@ int kmc_oracle_count(const uint8_t* seq, const uint64_t* offsets, uint64_t n_rea
     E[t].k = k;
     E[t].canonical = canonical;
     E[t].shift = shift;
+    E[t].slice_bits = slice_bits;
+    E[t].slice = slice;
     E[t].n_parts = n_parts;
     E[t].hist = hist + (size_t)t * n_parts;
     E[t].pos = hist + (size_t)(n_threads + t) * n_parts;
@@ -366,6 +393,15 @@ done:
   free(hist);
   free(E);
   return rc;
+}
+
+/* The whole count: every key. */
+int kmc_oracle_count(const uint8_t* seq, const uint64_t* offsets, uint64_t n_reads,
+                     uint32_t k, uint32_t cutoff_min, uint32_t cutoff_max, int canonical,
+                     int n_threads, uint64_t* out_n, uint64_t** out_keys,
+                     uint32_t** out_counts) {
+  return kmc_oracle_count_slice(seq, offsets, n_reads, k, cutoff_min, cutoff_max, canonical,
+                                n_threads, 0, 0, out_n, out_keys, out_counts);
 }
 
 void kmc_oracle_free(void* p) { free(p); }

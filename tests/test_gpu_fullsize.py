@@ -9,12 +9,13 @@ device and copied back here).
   threads).
 - large-300M-60Mx150 (the served form's large job, 60M reads x 150 bp, 9
   Gbases, k = 28, 2048 bins): exact at 2% scale (same generator and
-  parameters); at full size (7.2e9 k-mers, beyond a full oracle sort in a
-  test) by properties that hold at any size and on samples the oracle counts
-  one by one: the number of k-mers equals the closed form; sampled table
-  entries carry the oracle's count; sampled windows of the input are in the
-  table exactly when their oracle count passes the cutoffs; sampled keys sit
-  in the bin of their signature; bins are disjoint and ascending.
+  parameters); at full size (7.2e9 k-mers, beyond a whole oracle count in a
+  test's memory) every entry of one sixteenth of the key space equals the
+  oracle's count of that key range, entry for entry, and properties that
+  hold at any size cover the rest: the number of k-mers equals the closed
+  form; sampled windows of the input are in the table exactly when their
+  oracle count passes the cutoffs; sampled keys sit in the bin of their
+  signature; bins are disjoint and ascending.
 - the batched workload (256 uneven jobs, 10.3 Gbases): every table of one
   kmc_batch_count equals the same job's table counted alone.
 """
@@ -188,7 +189,7 @@ def test_large_job_scaled_exact(ctx, kmc):
 
 
 @pytest.mark.timeout(1200)
-def test_large_job_full_size_properties(ctx, kmc):
+def test_large_job_full_size_exact_slice(ctx, kmc):
     step = lambda m: print(f"[large job] {m}", flush=True)  # progress of a long test
     seq, off, p = synth.make("large-300M-60Mx150")
     step(f"generated {seq.size} bases")
@@ -201,11 +202,22 @@ def test_large_job_full_size_properties(ctx, kmc):
     assert st["n_kmers"] == oracle.valid_windows(seq, off, k)
     assert np.all((counts >= ci) & (counts <= cx))
     step("bins and k-mer total checked")
+    # every entry of one sixteenth of the key space (the keys whose top four
+    # bits are 9) against the oracle's count of that range, entry for entry
+    # (the whole count would need some 230 GB of host memory)
+    sl = (keys >> np.uint64(2 * k - 4)) == 9
+    ok_keys, ok_counts = oracle.count(seq, off, k, ci, cx, threads=THREADS, slice_bits=4,
+                                      slice=9)
+    o = np.argsort(keys[sl])
+    assert len(ok_keys) > 10_000_000
+    assert np.array_equal(keys[sl][o], ok_keys) and np.array_equal(counts[sl][o], ok_counts)
+    del ok_keys, ok_counts, o
+    step(f"key range 9/16 checked: {int(sl.sum())} entries")
     rng = np.random.default_rng(13)
-    idx = rng.choice(n, 20000, replace=False)
-    got = oracle.count_keys(seq, off, k, keys[idx], threads=THREADS)
-    assert np.array_equal(got, counts[idx].astype(np.uint64))
-    step("sampled entries checked")
+    idx = rng.choice(n, 5000, replace=False)
+    bin_of = np.searchsorted(bo, idx, side="right") - 1
+    sig = oracle.key_signatures(keys[idx], k, p["p"])
+    assert np.array_equal(s2b[sig], bin_of)
     q = window_keys(seq, off, k, rng, 4000)
     qc = oracle.count_keys(seq, off, k, q, threads=THREADS)
     order = np.argsort(keys)
@@ -213,9 +225,6 @@ def test_large_job_full_size_properties(ctx, kmc):
     want = (qc >= ci) & (qc <= cx)
     assert np.array_equal(pos >= 0, want)
     assert np.array_equal(counts[pos[pos >= 0]].astype(np.uint64), qc[pos >= 0])
-    bin_of = np.searchsorted(bo, idx[:5000], side="right") - 1
-    sig = oracle.key_signatures(keys[idx[:5000]], k, p["p"])
-    assert np.array_equal(s2b[sig], bin_of)
 
 
 def _batch_job(j):

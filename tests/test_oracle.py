@@ -235,6 +235,31 @@ def test_count_keys_brute_force(oracle_lib, k):
     assert [int(c) for c in got] == [full.get(q, 0) for q in query]
 
 
+@pytest.mark.parametrize("k,bits", [(4, 3), (21, 4), (32, 5), (33, 2), (55, 4), (64, 1)])
+def test_slices_brute_force(oracle_lib, k, bits):
+    # the count restricted to the keys whose top `bits` bits equal s: the
+    # string-level brute force's keys of that range, for every s; the slices
+    # together are the whole count
+    rng = np.random.default_rng(400 + k)
+    reads = random_reads(rng, 60, 0, k + 40, n_rate=0.03, lower=0.05)
+    reads.append("ACGT" * 30)
+    seq, off = to_reads(reads)
+    full = brute_force(reads, k, 2, 2**32 - 1)
+    union = {}
+    for sl in range(1 << bits):
+        for threads in (1, 3):
+            keys, counts = oracle_lib.count(seq, off, k, 2, 2**32 - 1, threads=threads,
+                                            slice_bits=bits, slice=sl)
+            got = table_dict(keys, counts, k)
+            assert got == {q: c for q, c in full.items() if q >> (2 * k - bits) == sl}
+        union.update(got)
+    assert union == full
+    whole = oracle_lib.count(seq, off, k, 2, 2**32 - 1, slice_bits=0)
+    assert table_dict(*whole, k) == full
+    with pytest.raises(ValueError):
+        oracle_lib.count(seq, off, k, slice_bits=bits, slice=1 << bits)
+
+
 @pytest.mark.parametrize("threads", [2, 5])
 def test_threaded_equals_single(oracle_lib, threads):
     seq, off, _ = synth.make("genome-5M-2Mx100", 0.002)
