@@ -229,9 +229,7 @@ uint32_t ilog2_ceil(uint64_t x) {
 // signatures, heaviest first (ties: smaller signature first), each into the
 // currently lightest bin (ties: lowest bin id); signatures absent from the
 // sample go to bin (signature mod n_bins).
-void build_map(const std::vector<uint32_t>& hist, uint32_t n_bins, std::vector<uint32_t>& map) {
-  const uint32_t n_sig = (uint32_t)hist.size();
-  map.resize(n_sig);
+void build_map(const uint32_t* hist, uint32_t n_sig, uint32_t n_bins, uint32_t* map) {
   std::vector<uint32_t> a, b;
   a.reserve(n_sig);
   uint32_t maxc = 0;
@@ -580,17 +578,14 @@ void run_count(kmc_ctx* c, const kmc_reads* R, const kmc_params* P, kmc_table* T
   Misc h_misc = *h_misc_p;
   if (h_misc.offsets_err) throw Fail{KMC_ERR_INVALID_ARG};
   st.sample_kmers = h_misc.sample_kmers;
-  std::vector<uint32_t> map;
-  {
-    std::vector<uint32_t> hk(h_hist, h_hist + n_sig);
-    build_map(hk, J.n_bins, map);
-  }
-  std::memcpy(T->sig_to_bin, map.data(), (size_t)n_sig * 4);
-  uint32_t* h_map = ensure_host<uint32_t>(c, H_MAP, (size_t)n_sig * 4);
-  std::memcpy(h_map, map.data(), (size_t)n_sig * 4);
+  // the map is built in its pinned upload buffer, uploaded, then copied into
+  // the table while the upload runs
+  uint32_t* map = ensure_host<uint32_t>(c, H_MAP, (size_t)n_sig * 4);
+  build_map(h_hist, n_sig, J.n_bins, map);
   uint32_t* d_map = ensure<uint32_t>(c, B_MAP, (size_t)n_sig * 4);
-  check(c, hipMemcpyAsync(d_map, h_map, (size_t)n_sig * 4, hipMemcpyHostToDevice, s), "H2D map");
+  check(c, hipMemcpyAsync(d_map, map, (size_t)n_sig * 4, hipMemcpyHostToDevice, s), "H2D map");
   check(c, hipEventRecord(c->ev[1], s), "event");
+  std::memcpy(T->sig_to_bin, map, (size_t)n_sig * 4);
 
   // ---- split: one pass writing super k-mer records into bin regions sized
   // from the sample; if a bin overflows, the pass is repeated with the exact
@@ -601,7 +596,9 @@ void run_count(kmc_ctx* c, const kmc_reads* R, const kmc_params* P, kmc_table* T
   std::vector<uint64_t> cap(J.n_bins, 0);
   {
     std::vector<double> est(J.n_bins, 0.0);
-    for (uint32_t g = 0; g < n_sig; ++g) est[map[g]] += h_hist[n_sig + g];
+    const uint32_t* h_rec = h_hist + n_sig;  // sampled super k-mers per signature
+    for (uint32_t g = 0; g < n_sig; ++g)
+      if (h_rec[g]) est[map[g]] += h_rec[g];
     const double scale = h_misc.sample_bases ? (double)J.n_bases / (double)h_misc.sample_bases : 0.0;
     for (uint32_t b = 0; b < J.n_bins; ++b)
       cap[b] = std::min<uint64_t>((uint64_t)((1.15 * est[b] + 8.0 * std::sqrt(est[b])) * scale) + 256,
