@@ -123,14 +123,46 @@ struct Lines {
 };
 
 // *last = 1 + index of the last line that holds anything (trailing empty
-// lines carry nothing and are dropped).
-__global__ void __launch_bounds__(256)
+// lines carry nothing and are dropped).  One wavefront walks back from the
+// end, 64 lines a step, for at most kLastSteps steps (trailing empty lines
+// are few); if all of those are empty it leaves ~0 and the host runs
+// k_last_line_all.
+constexpr uint32_t kLastSteps = 64;
+__global__ void __launch_bounds__(64)
 k_last_line(Lines L, unsigned long long* last) {
+  const uint32_t lane = threadIdx.x;
+  uint64_t top = L.n_lines;
+  for (uint32_t step = 0; step < kLastSteps && top > 0; ++step) {
+    bool ne = false;
+    if (lane < top) {  // lane l tests line top - 1 - l
+      uint64_t b, e;
+      L.span(top - 1 - lane, b, e);
+      ne = e > b;
+    }
+    const uint64_t m = __ballot(ne);
+    if (m) {  // the lowest such lane holds the highest non-empty line
+      if (lane == 0) *last = top - (uint64_t)(__ffsll((unsigned long long)m) - 1);
+      return;
+    }
+    top = top > 64 ? top - 64 : 0;
+  }
+  if (lane == 0) *last = top == 0 ? 0ull : ~0ull;
+}
+// The same over every line (one atomic per wavefront).
+__global__ void __launch_bounds__(256)
+k_last_line_all(Lines L, unsigned long long* last) {
   const uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= L.n_lines) return;
-  uint64_t b, e;
-  L.span(i, b, e);
-  if (e > b) atomicMax(last, (unsigned long long)(i + 1));
+  bool ne = false;
+  if (i < L.n_lines) {
+    uint64_t b, e;
+    L.span(i, b, e);
+    ne = e > b;
+  }
+  const uint64_t m = __ballot(ne);
+  if (m && (threadIdx.x & 63u) == 0) {
+    const uint64_t w0 = i;  // line of lane 0
+    atomicMax(last, (unsigned long long)(w0 + 64 - __clzll((long long)m)));
+  }
 }
 
 // Per line: its sequence length (0 for header, '+' and quality lines) and,
@@ -188,15 +220,29 @@ k_offsets(uint64_t n_lines, const uint32_t* __restrict__ starts,
 __global__ void __launch_bounds__(256)
 k_copy(Lines L, const uint32_t* __restrict__ len, const uint64_t* __restrict__ out_pos,
        uint8_t* seq) {
-  const uint64_t i = ((uint64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6;
+  // one wavefront per 64 consecutive lines: the lines that hold sequence
+  // are copied one after another, 64 bytes at a time
+  const uint64_t i0 = (((uint64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6) * 64;
   const uint32_t lane = threadIdx.x & 63u;
-  if (i >= L.n_lines) return;
-  const uint32_t n = len[i];
-  if (!n) return;
-  uint64_t b, e;
-  L.span(i, b, e);
-  const uint64_t o = out_pos[i];
-  for (uint32_t j = lane; j < n; j += 64) seq[o + j] = L.t[b + j];
+  if (i0 >= L.n_lines) return;
+  // each lane loads its own line's length, start and output position, so
+  // the copies below wait on no per-line load
+  const uint32_t my_len = i0 + lane < L.n_lines ? len[i0 + lane] : 0u;
+  unsigned long long my_b = 0, my_o = 0;
+  if (my_len) {
+    uint64_t b, e;
+    L.span(i0 + lane, b, e);
+    my_b = b;
+    my_o = out_pos[i0 + lane];
+  }
+  uint64_t m = __ballot(my_len != 0);
+  while (m) {
+    const int l = __ffsll((unsigned long long)m) - 1;
+    m &= m - 1;
+    const uint32_t n = (uint32_t)__shfl((int)my_len, l);
+    const uint64_t b = __shfl(my_b, l), o = __shfl(my_o, l);
+    for (uint32_t j = lane; j < n; j += 64) seq[o + j] = L.t[b + j];
+  }
 }
 
 uint32_t grid(uint64_t n) { return (uint32_t)((n + 255) / 256); }
@@ -295,11 +341,20 @@ kmc_status kmc_parse(kmc_ctx* ctx, const uint8_t* text, uint64_t n_bytes, int32_
     return dev_err("H2D failed");
   if (n_lines) {
     const Lines L0{t, nl, n_nl, n_bytes, n_lines};
-    hipLaunchKernelGGL(k_last_line, dim3(grid(n_lines)), dim3(256), 0, s, L0, err + 1);
+    hipLaunchKernelGGL(k_last_line, dim3(1), dim3(64), 0, s, L0, err + 1);
     unsigned long long lastne = 0;
     if (hipMemcpyAsync(&lastne, err + 1, 8, hipMemcpyDeviceToHost, s) != hipSuccess ||
         hipStreamSynchronize(s) != hipSuccess)
       return dev_err("line scan failed");
+    if (lastne == ~0ull) {  // more than kLastSteps * 64 empty lines at the end
+      const unsigned long long zero = 0;
+      if (hipMemcpyAsync(err + 1, &zero, 8, hipMemcpyHostToDevice, s) != hipSuccess)
+        return dev_err("H2D failed");
+      hipLaunchKernelGGL(k_last_line_all, dim3(grid(n_lines)), dim3(256), 0, s, L0, err + 1);
+      if (hipMemcpyAsync(&lastne, err + 1, 8, hipMemcpyDeviceToHost, s) != hipSuccess ||
+          hipStreamSynchronize(s) != hipSuccess)
+        return dev_err("line scan failed");
+    }
     n_lines = lastne;
   }
   if (fmt == KMC_FORMAT_FASTQ && n_lines % 4 != 0) {
@@ -348,7 +403,8 @@ kmc_status kmc_parse(kmc_ctx* ctx, const uint8_t* text, uint64_t n_bytes, int32_
   if (n_lines) {
     hipLaunchKernelGGL(k_offsets, dim3(grid(n_lines + 1)), dim3(256), 0, s, n_lines, starts, rank,
                        out_pos, P->offsets);
-    hipLaunchKernelGGL(k_copy, dim3(grid(n_lines * 64)), dim3(256), 0, s, L, len, out_pos, P->seq);
+    hipLaunchKernelGGL(k_copy, dim3(grid((n_lines + 63) / 64 * 64)), dim3(256), 0, s, L, len,
+                       out_pos, P->seq);
   } else if (hipMemsetAsync(P->offsets, 0, 8, s) != hipSuccess) {
     kmc_parsed_free(P);
     return dev_err("memset failed");

@@ -48,6 +48,12 @@ LITERALS = [
     (0, b"\n\n>a\nCCCC\n>b\nGG\n"),
     (0, b"@x\nAC\n+\n!!\n"),
     (2, b""),
+    # trailing empty lines beyond the backward walk's 64 x 64 lines, and
+    # texts of empty lines only
+    (1, b"@r1\nACGT\n+\nIIII\n" + b"\n" * 5000),
+    (2, b">a\nACGT\n" + b"\r\n" * 4200 + b"\r"),
+    (2, b"\n" * 70),
+    (2, b"\n" * 9000),
 ]
 
 
