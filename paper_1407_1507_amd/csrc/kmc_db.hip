@@ -82,6 +82,30 @@ __device__ __forceinline__ typename KeyOf<KW>::T read_suffix(const uint8_t* rec,
   return v;
 }
 
+// The same from aligned 8-byte words of the records (the record buffer is
+// padded by kRecPad bytes, so the words of the last record stay inside it):
+// one load per word instead of one per byte.
+constexpr size_t kRecPad = 32;
+template <int KW>
+__device__ __forceinline__ typename KeyOf<KW>::T read_suffix_words(const uint8_t* recs, uint64_t a,
+                                                                   uint32_t sb) {
+  typedef typename KeyOf<KW>::T K;
+  if (sb == 0) return 0;
+  const uint64_t* w = reinterpret_cast<const uint64_t*>(recs) + (a >> 3);
+  const uint32_t s = 8 * (uint32_t)(a & 7);
+  // bytes a .. a + 7 (and a + 8 .. a + 15), first byte lowest
+  const uint64_t w0 = w[0], w1 = w[1];
+  const uint64_t b0 = s ? (w0 >> s) | (w1 << (64 - s)) : w0;
+  if constexpr (KW == 1) {
+    return __builtin_bswap64(b0) >> (8 * (8 - sb));
+  } else {
+    const uint64_t w2 = sb + (a & 7) > 16 ? w[2] : 0;
+    const uint64_t b1 = s ? (w1 >> s) | (w2 << (64 - s)) : w1;
+    const K v = ((K)__builtin_bswap64(b0) << 64) | (K)__builtin_bswap64(b1);
+    return v >> (8 * (16 - sb));
+  }
+}
+
 __device__ __forceinline__ uint32_t read_count(const uint8_t* c, uint32_t cs) {
   uint32_t v = 0;
   for (uint32_t j = 0; j < cs; ++j) v |= (uint32_t)c[j] << (8 * j);
@@ -164,7 +188,7 @@ k_db_query(DbView D, const uint64_t* __restrict__ q, uint64_t n, uint32_t cmin, 
   uint32_t c = 0;
   while (lo < hi) {
     const uint64_t mid = (lo + hi) >> 1;
-    const K v = read_suffix<KW>(D.rec + mid * rb, D.sb);
+    const K v = read_suffix_words<KW>(D.rec, mid * rb, D.sb);
     if (v == suf) {
       c = read_count(D.rec + mid * rb + D.sb, D.cs);
       break;
@@ -356,7 +380,7 @@ kmc_status kmc_db_build(kmc_ctx* ctx, const kmc_table* table, const kmc_params* 
   };
   do {
     if (!dev_alloc(&db->map, n_sig) || !dev_alloc(&db->pre, n_pre) ||
-        !dev_alloc(&db->rec, n * db->rec_bytes) || !dev_alloc(&bo, db->n_bins + 1)) {
+        !dev_alloc(&db->rec, n * db->rec_bytes + kRecPad) || !dev_alloc(&bo, db->n_bins + 1)) {
       fail(KMC_ERR_OUT_OF_MEMORY, "device allocation of the database failed");
       break;
     }
@@ -556,7 +580,7 @@ kmc_status kmc_db_open(kmc_ctx* ctx, const char* path_prefix, kmc_db** out) {
     return KMC_ERR_DEVICE;
   }
   const uint64_t nrec = I.total_kmers * db->rec_bytes;
-  if (!dev_alloc(&db->map, n_sig) || !dev_alloc(&db->pre, n_pre) || !dev_alloc(&db->rec, nrec)) {
+  if (!dev_alloc(&db->map, n_sig) || !dev_alloc(&db->pre, n_pre) || !dev_alloc(&db->rec, nrec + kRecPad)) {
     free_parts(db);
     return KMC_ERR_OUT_OF_MEMORY;
   }

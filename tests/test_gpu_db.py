@@ -212,6 +212,35 @@ def test_db_query_matches_oracle(ctx, kmc):
         db.free()
 
 
+@pytest.mark.parametrize("k,lut,cs", [(32, 0, 1), (21, 1, 3), (33, 1, 2), (64, 0, 4),
+                                      (40, 4, 1)])
+def test_db_query_suffix_widths(ctx, kmc, k, lut, cs):
+    # suffixes of 5 to 16 bytes, records of odd lengths (every alignment of a
+    # record in the buffer), including the last record: lookups of every
+    # entry (both orientations) and of absent k-mers against the oracle
+    import torch
+    seq, off = synth.sample_reads(k, synth.random_reference(k + 1, 20_000), 4000, (80, 160),
+                                  0.01, 0.0)
+    res = ctx.count(seq, off, k, 7, 64, 1, 2**32 - 1, flags=kmc.FLAG_DEVICE_TABLE)
+    db = kmc.Db.build(ctx, res, lut, cs)
+    ok_keys, ok_counts = oracle.count(seq, off, k)
+    cap = 2 ** (8 * cs) - 1
+    table = dict(zip(as_ints(ok_keys), (min(int(c), cap) for c in ok_counts)))
+    q = [revcomp_int(v, k) if i % 2 else v for i, v in enumerate(table)]
+    rng = np.random.default_rng(k)
+    while len(q) < len(table) + 3000:
+        v = (int(rng.integers(0, 2**62)) << 62 | int(rng.integers(0, 2**62))) % (4 ** k)
+        if min(v, revcomp_int(v, k)) not in table:
+            q.append(v)
+    dq = pack_queries(q, k)
+    out = torch.zeros(len(q), dtype=torch.int32, device="cuda:0")
+    db.query(dq, out)
+    got = out.cpu().numpy().view(np.uint32)
+    assert [int(x) for x in got] == [table.get(min(v, revcomp_int(v, k)), 0) for v in q]
+    res.free()
+    db.free()
+
+
 def test_db_open_decode_roundtrip(ctx, kmc, tmp_path):
     import torch
     seq, off, p = synth.make("genome-5M-2Mx100", 0.01)
