@@ -392,34 +392,70 @@ void host_table(kmc_table* T, uint64_t n, uint32_t kw) {
 // table pool, keys then counts, that becomes the host table's block (a freed
 // table's block serves the next grouped job, so its pages are pinned once).
 struct HostEntries {
-  void* blk = nullptr;  // owned here until a table takes it
+  // above this many bytes (or when pinning fails) keys and counts are two
+  // ordinary allocations instead: pinning tens of GB would take host memory
+  // from everything else
+  static constexpr size_t kPinnedMax = size_t(16) << 30;
+  void* blk = nullptr;  // pinned pool block, owned here until a table takes it
+  bool pinned = false;
   uint64_t cap = 0;     // entries
   uint64_t* k = nullptr;
   uint32_t* c = nullptr;
   HostEntries() = default;
   HostEntries(const HostEntries&) = delete;
   HostEntries& operator=(const HostEntries&) = delete;
-  ~HostEntries() {
-    if (blk) pool_give(blk);
+  ~HostEntries() { release(); }
+  void release() {
+    if (pinned) {
+      if (blk) pool_give(blk);
+    } else {
+      std::free(k);
+      std::free(c);
+    }
+    blk = nullptr;
+    k = nullptr;
+    c = nullptr;
+    cap = 0;
   }
-  // room for n entries, the first keep of them kept; false if the block
-  // cannot be allocated
+  // hand keys and counts to a host table (reserved 3: a pinned pool block,
+  // 0: two allocations that kmc_table_free releases)
+  void give_to(kmc_table* T) {
+    T->keys = k;
+    T->counts = c;
+    T->reserved = pinned ? 3 : 0;
+    blk = nullptr;
+    k = nullptr;
+    c = nullptr;
+    cap = 0;
+  }
+  // room for n entries, the first keep of them kept; false if no memory
   bool reserve(uint64_t n, uint64_t keep, uint32_t kw) {
-    if (blk && n <= cap) return true;
+    if ((k || blk) && n <= cap) return true;
     const uint64_t ncap = std::max<uint64_t>(n, cap + cap / 2);
     const size_t kb = (std::max<uint64_t>(1, ncap * kw) * 8 + 255) & ~(size_t)255;
-    void* nb = pool_take(kHostPool, kb + std::max<uint64_t>(1, ncap) * 4);
-    if (!nb) return false;
-    uint64_t* nk = static_cast<uint64_t*>(nb);
-    uint32_t* nc = reinterpret_cast<uint32_t*>(static_cast<uint8_t*>(nb) + kb);
-    if (blk) {
-      if (keep) {
-        std::memcpy(nk, k, keep * kw * 8);
-        std::memcpy(nc, c, keep * 4);
+    const size_t total = kb + std::max<uint64_t>(1, ncap) * 4;
+    void* nb = total <= kPinnedMax ? pool_take(kHostPool, total) : nullptr;
+    uint64_t* nk;
+    uint32_t* nc;
+    if (nb) {
+      nk = static_cast<uint64_t*>(nb);
+      nc = reinterpret_cast<uint32_t*>(static_cast<uint8_t*>(nb) + kb);
+    } else {
+      nk = static_cast<uint64_t*>(std::malloc(kb));
+      nc = static_cast<uint32_t*>(std::malloc(std::max<uint64_t>(1, ncap) * 4));
+      if (!nk || !nc) {
+        std::free(nk);
+        std::free(nc);
+        return false;
       }
-      pool_give(blk);
     }
+    if (keep) {
+      std::memcpy(nk, k, keep * kw * 8);
+      std::memcpy(nc, c, keep * 4);
+    }
+    release();
     blk = nb;
+    pinned = nb != nullptr;
     cap = ncap;
     k = nk;
     c = nc;
@@ -1009,7 +1045,7 @@ void run_count(kmc_ctx* c, const kmc_reads* R, const kmc_params* P, kmc_table* T
     if (!acc.reserve(std::max<uint64_t>(n_out_total + g_out,
                                         gi == 0 ? (g_out * groups.size() * 5) / 4 + 1 : 0),
                      n_out_total, J.kw)) {
-      c->err = "pinned host allocation of a grouped job's entries failed";
+      c->err = "host allocation of a grouped job's entries failed";
       throw Fail{KMC_ERR_OUT_OF_MEMORY};
     }
     if (g_out) {
@@ -1117,16 +1153,13 @@ void run_count(kmc_ctx* c, const kmc_reads* R, const kmc_params* P, kmc_table* T
   check(c, hipEventRecord(c->ev[5], s), "event");
   const bool want_host = !(J.flags & KMC_FLAG_DEVICE_TABLE) && !c->user_keys;
   if (want_host && grouped && !(J.flags & KMC_FLAG_ASCENDING)) {
-    // a grouped job's host table: the block that collected the entries
+    // a grouped job's host table: the memory that collected the entries
     T->on_device = 0;
     if (!acc.reserve(1, 0, J.kw)) {  // (a job without entries)
-      c->err = "pinned host allocation of the table failed";
+      c->err = "host allocation of the table failed";
       throw Fail{KMC_ERR_OUT_OF_MEMORY};
     }
-    T->keys = acc.k;
-    T->counts = acc.c;
-    T->reserved = 3;
-    acc.blk = nullptr;
+    acc.give_to(T);
   } else if (want_host) {
     // a host table copied out of the device table (or the staging buffers)
     uint64_t* dk = out_k;
