@@ -1480,17 +1480,22 @@ k_scan_apply(const uint32_t* __restrict__ in, uint64_t n, const uint64_t* __rest
 // ---------------------------------------------------------------- gather
 // Counts are stored saturated at cmax (counter saturation; the cutoffs were
 // applied to the exact counts before).
+// One wavefront per tile, four tiles per workgroup (a tile keeps a few
+// dozen entries: a workgroup per tile spent the kernel dispatching them).
 template <int KW>
 __global__ void __launch_bounds__(256)
-k_gather(const Tile* __restrict__ tiles, const uint64_t* __restrict__ tile_off,
+k_gather(const Tile* __restrict__ tiles, const uint64_t* __restrict__ tile_off, uint64_t n_tiles,
          const uint64_t* __restrict__ keys, const uint32_t* __restrict__ counts,
          uint64_t* out_keys, uint32_t* out_counts, uint32_t cmax) {
-  const uint64_t t = blockIdx.x;
+  const uint64_t t = (uint64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
+  const uint32_t lane = threadIdx.x & 63u;
+  if (t >= n_tiles) return;
   const uint64_t o = tile_off[t], m = tile_off[t + 1] - o;
   if (m == 0) return;
   const uint64_t b = tiles[t].begin;
-  for (uint64_t i = threadIdx.x; i < m * KW; i += blockDim.x) out_keys[o * KW + i] = keys[b * KW + i];
-  for (uint64_t i = threadIdx.x; i < m; i += blockDim.x) out_counts[o + i] = min(counts[b + i], cmax);
+  // 8-byte words: the output may be a caller's buffer with 8-byte alignment
+  for (uint64_t i = lane; i < m * KW; i += 64) out_keys[o * KW + i] = keys[b * KW + i];
+  for (uint64_t i = lane; i < m; i += 64) out_counts[o + i] = min(counts[b + i], cmax);
 }
 
 // ------------------------------------------------- global ascending order
@@ -1782,12 +1787,13 @@ hipError_t launch_gather(hipStream_t s, const KeyCfg& kc, const Tile* tiles, uin
                          const uint64_t* tile_off, const uint64_t* keys,
                          const uint32_t* counts, uint64_t* out_keys, uint32_t* out_counts) {
   if (n_tiles == 0) return hipSuccess;
+  const dim3 g((uint32_t)((n_tiles + 3) / 4));
   if (kc.key_words == 1)
-    hipLaunchKernelGGL(k_gather<1>, dim3((uint32_t)n_tiles), dim3(256), 0, s, tiles, tile_off,
-                       keys, counts, out_keys, out_counts, kc.counter_max);
+    hipLaunchKernelGGL(k_gather<1>, g, dim3(256), 0, s, tiles, tile_off, n_tiles, keys, counts,
+                       out_keys, out_counts, kc.counter_max);
   else
-    hipLaunchKernelGGL(k_gather<2>, dim3((uint32_t)n_tiles), dim3(256), 0, s, tiles, tile_off,
-                       keys, counts, out_keys, out_counts, kc.counter_max);
+    hipLaunchKernelGGL(k_gather<2>, g, dim3(256), 0, s, tiles, tile_off, n_tiles, keys, counts,
+                       out_keys, out_counts, kc.counter_max);
   return hipGetLastError();
 }
 
