@@ -1496,7 +1496,7 @@ kmc_status kmc_count(const kmc_reads* reads, uint32_t k, uint32_t p, uint32_t n_
                      uint32_t cutoff_min, uint32_t cutoff_max, kmc_table** out) {
   if (!out) return KMC_ERR_INVALID_ARG;
   *out = nullptr;
-  kmc_params P{k, p, n_bins, cutoff_min, cutoff_max, 0};
+  kmc_params P{k, p, n_bins, cutoff_min, cutoff_max, 0, 0};
   kmc_status v = validate(reads, &P);  // before any device work
   if (v != KMC_OK) return v;
   if (!t_default_ctx) {
@@ -1634,7 +1634,7 @@ kmc_status kmc_debug_signatures(kmc_ctx* c, const kmc_reads* reads, uint32_t k, 
                                 uint32_t flags, uint32_t* sig_per_window,
                                 uint8_t* superkmer_start) {
   if (!c || !sig_per_window) return KMC_ERR_INVALID_ARG;
-  kmc_params P{k, p, 1, 1, 1, flags & KMC_FLAG_PLAIN_MINIMIZERS};
+  kmc_params P{k, p, 1, 1, 1, flags & KMC_FLAG_PLAIN_MINIMIZERS, 0};
   kmc_status v = validate(reads, &P);
   if (v != KMC_OK) return v;
   if (hipSetDevice(c->device) != hipSuccess) {
